@@ -1,0 +1,883 @@
+/*
+ * mcrt_oracle.c -- plain, slow, FP64 CPU oracle of the gCMCRT photon-transport
+ * hot path (Lee et al., "3D radiative-transfer for exoplanet atmospheres.
+ * gCMCRT: a GPU accelerated MCRT code", arXiv:2110.15640).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or helper with
+ * the HIP library.
+ *
+ * Every function follows the paper's definitions, step by step, in FP64 with
+ * no blocking, fusion or reordering:
+ *   - photon-packet Monte Carlo with peel-off (Sect. 2, Sect. 4.6 "Next event
+ *     estimation", the peel-off fraction equation);
+ *   - phase functions and their samplers (Sect. 3: isotropic, Rayleigh, HG
+ *     with its inverse-CDF equation; gas/cloud choice by P_gas);
+ *   - continuous absorption and survival biasing (Sect. 4.1, 4.4),
+ *     Russian roulette (Sect. 4.5), hybrid emission biasing (Sect. 4.3),
+ *     the vertical optical-depth cut (Sect. 4.6, tau_vert);
+ *   - observables (Sect. 5: transmission equation and its MC estimator,
+ *     geometric albedo A_g, cell luminosity L_i, L_p, I_p, F_p);
+ *   - Doppler shifted high-resolution opacity (Sect. 7: v_LOS and
+ *     lambda_eff equations) and band-centre continuum in ck mode.
+ * Where the paper is silent or garbled the reading taken is stated inline
+ * (e.g. the Rayleigh inverse CDF, the RNG, the traversal tie order).
+ *
+ * Pins (tests/test_oracle_*.py) tie it to closed forms: Philox KAT vs
+ * rocRAND, sampler CDFs/moments, brute-force geometry, Beer-Lambert,
+ * Chandrasekhar H-function reflection, single scattering, transit shell sums,
+ * isothermal emission and energy conservation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+static const double ORC_H = 6.62607015e-27;  /* erg s */
+static const double ORC_C = 2.99792458e10;   /* cm / s */
+static const double ORC_KB = 1.380649e-16;   /* erg / K */
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox4x32-10 (Salmon et al. 2011).  The paper does not
+ * name its RNG; a counter-based one keyed by (packet, event, block) makes the
+ * packet histories independent of scheduling.                              */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)prod1;
+        uint32_t n2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)prod0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 52 random bits from a word pair -> (m + 1/2) 2^-52, exactly in (0,1). */
+double orc_u01(uint32_t a, uint32_t b)
+{
+    uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+    return ((double)m + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+/* Uniform pair for (packet, event, block) under the solve key. */
+static void orc_draw(uint64_t seed, uint32_t tag, uint64_t packet, uint32_t event,
+                     uint32_t block, double *ua, double *ub)
+{
+    uint32_t ctr[4] = {(uint32_t)packet, (uint32_t)(packet >> 32), event, block};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ tag};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    *ua = orc_u01(w[0], w[1]);
+    *ub = orc_u01(w[2], w[3]);
+}
+
+void orc_draw_pair(uint64_t seed, uint32_t tag, uint64_t packet, uint32_t event,
+                   uint32_t block, double out[2])
+{
+    orc_draw(seed, tag, packet, event, block, &out[0], &out[1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase functions (Sect. 3).                                               */
+/* ------------------------------------------------------------------------ */
+double orc_phase_rayleigh(double mu) { return 0.75 * (1.0 + mu * mu); }
+
+double orc_phase_hg(double mu, double g)
+{
+    if (fabs(g) < 1e-6) return 1.0;  /* g -> 0: HG is isotropic */
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (den * sqrt(den));
+}
+
+/* Rayleigh cos(theta): exact inverse of F(mu) = (mu^3 + 3 mu + 4)/8.  The
+ * printed sampling formula is garbled (it is not a CDF inverse); Cardano's
+ * root of mu^3 + 3 mu = 2q with q = 4 zeta - 2 is used instead.             */
+double orc_sample_rayleigh(double zeta)
+{
+    double q = 4.0 * zeta - 2.0;
+    double u = cbrt(q + sqrt(q * q + 1.0));
+    double mu = u - 1.0 / u;
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    return mu;
+}
+
+/* HG cos(theta) by the paper's inverse CDF; isotropic when |g| < 1e-6. */
+double orc_sample_hg(double zeta, double g)
+{
+    double mu;
+    if (fabs(g) < 1e-6) {
+        mu = 2.0 * zeta - 1.0;
+    } else {
+        double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * zeta);
+        mu = (1.0 + g * g - t * t) / (2.0 * g);
+    }
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    return mu;
+}
+
+/* Rotate unit d by polar cos(theta)=mu about it and azimuth psi. */
+void orc_rotate(double d[3], double mu, double psi)
+{
+    double st = sqrt(fmax(1.0 - mu * mu, 0.0));
+    double cp = cos(psi), sp = sin(psi);
+    double nx, ny, nz;
+    if (fabs(d[2]) < 0.99999) {
+        double t = sqrt(1.0 - d[2] * d[2]);
+        nx = st * (d[0] * d[2] * cp - d[1] * sp) / t + d[0] * mu;
+        ny = st * (d[1] * d[2] * cp + d[0] * sp) / t + d[1] * mu;
+        nz = -st * cp * t + d[2] * mu;
+    } else {
+        double sgn = d[2] >= 0.0 ? 1.0 : -1.0;
+        nx = st * cp;
+        ny = st * sp;
+        nz = sgn * mu;
+    }
+    double n = sqrt(nx * nx + ny * ny + nz * nz);
+    d[0] = nx / n;
+    d[1] = ny / n;
+    d[2] = nz / n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid and geometry (Sect. 2: spherical lon-lat-radius cells, sub-grid     */
+/* packet motion; also the plane-parallel slab for 1D structures).          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t geom; /* 0 spherical, 1 plane-parallel slab */
+    int64_t nlon, nlat, nlay;
+    const double *r;   /* nlay+1 radii [cm] (slab: heights z [cm]) */
+    const double *lat; /* nlat+1 latitude edges [rad], -pi/2 .. pi/2 */
+    const double *lon; /* nlon+1 longitude edges [rad], -pi .. pi */
+} orc_grid;
+
+enum { F_NONE = -1, F_OUT = 0, F_IN = 1, F_LATLO = 2, F_LATHI = 3, F_LONLO = 4, F_LONHI = 5 };
+enum { T_INTERACT = 0, T_ESCAPE = 1, T_SURFACE = 2, T_LOST = 3, T_CUT = 4 };
+
+static int64_t cell_index(const orc_grid *g, int i, int j, int k)
+{
+    return ((int64_t)k * g->nlat + j) * g->nlon + i;
+}
+
+/* largest index m in [0, n-1] with e[m] <= x (clamped) */
+static int edge_find(const double *e, int64_t n, double x)
+{
+    int m = 0;
+    for (int64_t q = 1; q < n; ++q)
+        if (e[q] <= x) m = (int)q;
+    return m;
+}
+
+/* Candidate distance to a latitude cone (or the equatorial plane) of edge
+ * latitude tb.  Roots below lo are ignored; the hit must lie on the nappe
+ * whose z sign is that of tb.  Returns +inf when there is none.            */
+static double cone_distance(const double p[3], const double d[3], double tb, double lo)
+{
+    double best = INFINITY;
+    if (tb == 0.0) {
+        if (d[2] != 0.0) {
+            double s = -p[2] / d[2];
+            if (s >= lo) best = s;
+        }
+        return best;
+    }
+    double ct = cos(tb), st = sin(tb);
+    double c2 = ct * ct, s2 = st * st;
+    double a = d[2] * d[2] * c2 - (d[0] * d[0] + d[1] * d[1]) * s2;
+    double b = p[2] * d[2] * c2 - (p[0] * d[0] + p[1] * d[1]) * s2;
+    double c = p[2] * p[2] * c2 - (p[0] * p[0] + p[1] * p[1]) * s2;
+    double roots[2];
+    int nr = 0;
+    if (a == 0.0) {
+        if (b != 0.0) roots[nr++] = -c / (2.0 * b);
+    } else {
+        double disc = b * b - a * c;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -(b + (b >= 0.0 ? sq : -sq));
+            roots[nr++] = q / a;
+            if (q != 0.0) roots[nr++] = c / q;
+        }
+    }
+    for (int m = 0; m < nr; ++m) {
+        double s = roots[m];
+        if (!(s >= lo)) continue;
+        double zh = p[2] + s * d[2];
+        int ok = tb > 0.0 ? (zh > 0.0) : (zh < 0.0);
+        if (ok && s < best) best = s;
+    }
+    return best;
+}
+
+/* Distance to leave spherical cell (i,j,k) from p along d.  ef = face by
+ * which the ray entered (F_NONE at an event point).  Ties resolve in the
+ * order outer, inner, lat-low, lat-high, lon-low, lon-high.               */
+static int sph_exit(const orc_grid *g, const double p[3], const double d[3],
+                    int i, int j, int k, int ef, double *s_out)
+{
+    double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    double B = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
+    double best = INFINITY;
+    int face = F_NONE;
+
+    /* outer shell r_{k+1} */
+    {
+        double ro = g->r[k + 1];
+        double C = rr - ro * ro;
+        double D = B * B - C;
+        if (D < 0.0) D = 0.0;
+        double s = (B <= 0.0) ? (-B + sqrt(D)) : (-C / (B + sqrt(D)));
+        if (s < 0.0) s = 0.0;
+        if (s < best) { best = s; face = F_OUT; }
+    }
+    /* inner shell r_k (the planet surface when k == 0) */
+    if (B < 0.0) {
+        double ri = g->r[k];
+        double C = rr - ri * ri;
+        double D = B * B - C;
+        if (D >= 0.0) {
+            double s = C / (-B + sqrt(D));
+            if (s < 0.0) s = 0.0;
+            if (s < best) { best = s; face = F_IN; }
+        }
+    }
+    /* latitude cones; the poles are not faces */
+    double tol = 1e-9 * sqrt(rr);
+    if (j > 0) {
+        double s = cone_distance(p, d, g->lat[j], ef == F_LATLO ? tol : 0.0);
+        if (s < best) { best = s; face = F_LATLO; }
+    }
+    if (j < g->nlat - 1) {
+        double s = cone_distance(p, d, g->lat[j + 1], ef == F_LATHI ? tol : 0.0);
+        if (s < best) { best = s; face = F_LATHI; }
+    }
+    /* longitude half-planes (periodic; edge nlon is edge 0) */
+    if (g->nlon > 1) {
+        double pb = g->lon[i];
+        double nx = -sin(pb), ny = cos(pb);
+        double dn = d[0] * nx + d[1] * ny;
+        if (dn < 0.0) {
+            double s = -(p[0] * nx + p[1] * ny) / dn;
+            if (s < 0.0) s = 0.0;
+            double hx = p[0] + s * d[0], hy = p[1] + s * d[1];
+            if (cos(pb) * hx + sin(pb) * hy > 0.0 && s < best) { best = s; face = F_LONLO; }
+        }
+        int iu = (int)((i + 1) % g->nlon);
+        pb = g->lon[iu];
+        nx = -sin(pb);
+        ny = cos(pb);
+        dn = d[0] * nx + d[1] * ny;
+        if (dn > 0.0) {
+            double s = -(p[0] * nx + p[1] * ny) / dn;
+            if (s < 0.0) s = 0.0;
+            double hx = p[0] + s * d[0], hy = p[1] + s * d[1];
+            if (cos(pb) * hx + sin(pb) * hy > 0.0 && s < best) { best = s; face = F_LONHI; }
+        }
+    }
+    *s_out = best;
+    return face;
+}
+
+/* Slab: distance along d to the top or bottom of layer k from height z. */
+static int slab_exit(const orc_grid *g, double z, const double d[3], int k, double *s_out)
+{
+    if (d[2] > 0.0) {
+        double s = (g->r[k + 1] - z) / d[2];
+        *s_out = s < 0.0 ? 0.0 : s;
+        return F_OUT;
+    }
+    if (d[2] < 0.0) {
+        double s = (g->r[k] - z) / d[2];
+        *s_out = s < 0.0 ? 0.0 : s;
+        return F_IN;
+    }
+    *s_out = INFINITY;
+    return F_NONE;
+}
+
+typedef struct {
+    double p[3];
+    int i, j, k;
+    int ef;
+} orc_ray;
+
+/* Move across face f: update indices and the entry face of the new cell.
+ * In the slab the height snaps onto the crossed edge.                     */
+static void cross_face(const orc_grid *g, orc_ray *ry, int f)
+{
+    switch (f) {
+    case F_OUT: ry->k += 1; ry->ef = F_IN; if (g->geom == 1 && ry->k <= g->nlay) ry->p[2] = g->r[ry->k]; break;
+    case F_IN: ry->k -= 1; ry->ef = F_OUT; if (g->geom == 1 && ry->k >= -1) ry->p[2] = g->r[ry->k + 1]; break;
+    case F_LATLO: ry->j -= 1; ry->ef = F_LATHI; break;
+    case F_LATHI: ry->j += 1; ry->ef = F_LATLO; break;
+    case F_LONLO: ry->i = (int)((ry->i - 1 + g->nlon) % g->nlon); ry->ef = F_LONHI; break;
+    case F_LONHI: ry->i = (int)((ry->i + 1) % g->nlon); ry->ef = F_LONLO; break;
+    default: break;
+    }
+}
+
+static int exit_distance(const orc_grid *g, const orc_ray *ry, const double d[3], double *s)
+{
+    if (g->geom == 1) return slab_exit(g, ry->p[2], d, ry->k, s);
+    return sph_exit(g, ry->p, d, ry->i, ry->j, ry->k, ry->ef, s);
+}
+
+static void advance(const orc_grid *g, orc_ray *ry, const double d[3], double s)
+{
+    if (g->geom == 1) {
+        ry->p[2] = ry->p[2] + s * d[2];
+    } else {
+        ry->p[0] = ry->p[0] + s * d[0];
+        ry->p[1] = ry->p[1] + s * d[1];
+        ry->p[2] = ry->p[2] + s * d[2];
+    }
+}
+
+/* Locate the (i,j) column of a spherical position. */
+static void locate_column(const orc_grid *g, const double p[3], int *i, int *j)
+{
+    double lat = atan2(p[2], sqrt(p[0] * p[0] + p[1] * p[1]));
+    double lon = atan2(p[1], p[0]);
+    *j = edge_find(g->lat, g->nlat, lat);
+    *i = edge_find(g->lon, g->nlon, lon);
+}
+
+/* Exported for the brute-force geometry pin: trace a ray from p (in cell
+ * i,j,k, entry face ef) to the boundary, recording cells and path lengths.
+ * Returns the number of segments (<= cap) and the termination code.        */
+int64_t orc_trace_segments(const orc_grid *g, const double p0[3], const double d[3],
+                           int64_t i, int64_t j, int64_t k, int64_t ef, int64_t cap,
+                           int64_t *cells, double *lens, int64_t *term)
+{
+    orc_ray ry = {{p0[0], p0[1], p0[2]}, (int)i, (int)j, (int)k, (int)ef};
+    int64_t n = 0;
+    *term = T_LOST;
+    while (n < cap) {
+        double s;
+        int f = exit_distance(g, &ry, d, &s);
+        if (f == F_NONE) { *term = T_LOST; return n; }
+        cells[n] = cell_index(g, ry.i, ry.j, ry.k);
+        lens[n] = s;
+        ++n;
+        advance(g, &ry, d, s);
+        cross_face(g, &ry, f);
+        if (ry.k >= g->nlay) { *term = T_ESCAPE; return n; }
+        if (ry.k < 0) { *term = T_SURFACE; return n; }
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Opacity gathers.                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Bracket x on an increasing grid: clamped, lower index and weight. */
+static void bracket(const double *gx, int64_t n, double x, int *i0, int *i1, double *t)
+{
+    if (n == 1) { *i0 = 0; *i1 = 0; *t = 0.0; return; }
+    if (x <= gx[0]) { *i0 = 0; *i1 = 1; *t = 0.0; return; }
+    if (x >= gx[n - 1]) { *i0 = (int)n - 2; *i1 = (int)n - 1; *t = 1.0; return; }
+    int m = 0;
+    for (int64_t q = 0; q < n - 1; ++q)
+        if (gx[q] <= x) m = (int)q;
+    *i0 = m;
+    *i1 = m + 1;
+    *t = (x - gx[m]) / (gx[m + 1] - gx[m]);
+}
+
+/* Bilinear interpolation in (T, ln P) on ln kappa (kappa^w product form; a
+ * zero kappa at a corner with positive weight gives zero).                 */
+static double interp_tp(const float *tab, int64_t nP, int iT0, int iT1, double t,
+                        int iP0, int iP1, double u)
+{
+    double w[4] = {(1.0 - t) * (1.0 - u), (1.0 - t) * u, t * (1.0 - u), t * u};
+    int64_t idx[4] = {(int64_t)iT0 * nP + iP0, (int64_t)iT0 * nP + iP1,
+                      (int64_t)iT1 * nP + iP0, (int64_t)iT1 * nP + iP1};
+    double acc = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        if (w[q] > 0.0) {
+            double kv = (double)tab[idx[q]];
+            if (kv <= 0.0) return 0.0;
+            acc = acc + w[q] * log(kv);
+        }
+    }
+    return exp(acc);
+}
+
+/* Correlated-k gather for one (band, g): per cell alpha_ext [1/cm],
+ * alpha_abs, single-scattering albedo omega, gas scattering probability
+ * P_gas and cloud asymmetry g.  kappa_abs from the pre-mixed k-table
+ * interpolated to the cell (T, P); Rayleigh and cloud terms at the band
+ * centre (Sect. 7).  tab points at kappa[band][g][T][P].                  */
+void orc_ck_optics(int64_t ncell, const float *T, const float *P, const double *rho,
+                   const float *cld_ksca, const float *cld_kabs, const float *cld_g,
+                   int64_t nT, int64_t nP, const double *T_grid, const double *P_grid,
+                   const float *tab, double k_ray,
+                   double *a_ext, double *a_abs, double *omega, double *p_gas, double *g_cld)
+{
+    double *lnP = (double *)malloc(sizeof(double) * nP);
+    for (int64_t q = 0; q < nP; ++q) lnP[q] = log(P_grid[q]);
+    for (int64_t c = 0; c < ncell; ++c) {
+        int iT0, iT1, iP0, iP1;
+        double t, u;
+        bracket(T_grid, nT, (double)T[c], &iT0, &iT1, &t);
+        bracket(lnP, nP, log((double)P[c]), &iP0, &iP1, &u);
+        double kg = interp_tp(tab, nP, iT0, iT1, t, iP0, iP1, u);
+        double ks = cld_ksca ? (double)cld_ksca[c] : 0.0;
+        double ka = cld_kabs ? (double)cld_kabs[c] : 0.0;
+        double kab = kg + ka;
+        double ksc = k_ray + ks;
+        double kext = kab + ksc;
+        a_ext[c] = rho[c] * kext;
+        a_abs[c] = rho[c] * kab;
+        omega[c] = kext > 0.0 ? ksc / kext : 0.0;
+        p_gas[c] = ksc > 0.0 ? k_ray / ksc : 1.0;
+        g_cld[c] = cld_g ? (double)cld_g[c] : 0.0;
+    }
+    free(lnP);
+}
+
+/* Line-of-sight velocity of each cell centre toward observer direction o:
+ * v_LOS = -(v . o), with v = u e_E + v e_N + w e_r + Omega z x r (the wind and
+ * solid-body rotation of the v_LOS equation, written in vector form; positive
+ * is receding).  The result is the fractional index shift
+ * ln(1 - v_LOS/c)/dlnlam of lambda_eff = lambda_0 (1 - v_LOS/c).            */
+void orc_doppler_shift(const orc_grid *g, const float *u, const float *v, const float *w,
+                       double omega_rot, const double o[3], double dlnlam, double *shift)
+{
+    for (int64_t k = 0; k < g->nlay; ++k)
+        for (int64_t j = 0; j < g->nlat; ++j)
+            for (int64_t i = 0; i < g->nlon; ++i) {
+                int64_t c = cell_index(g, (int)i, (int)j, (int)k);
+                double rc = 0.5 * (g->r[k] + g->r[k + 1]);
+                double th = 0.5 * (g->lat[j] + g->lat[j + 1]);
+                double ph = 0.5 * (g->lon[i] + g->lon[i + 1]);
+                double eE[3] = {-sin(ph), cos(ph), 0.0};
+                double eN[3] = {-sin(th) * cos(ph), -sin(th) * sin(ph), cos(th)};
+                double eR[3] = {cos(th) * cos(ph), cos(th) * sin(ph), sin(th)};
+                double uu = u ? (double)u[c] : 0.0, vv = v ? (double)v[c] : 0.0, ww = w ? (double)w[c] : 0.0;
+                double ue = uu + omega_rot * rc * cos(th);
+                double vel[3];
+                for (int q = 0; q < 3; ++q) vel[q] = ue * eE[q] + vv * eN[q] + ww * eR[q];
+                double vlos = -(vel[0] * o[0] + vel[1] * o[1] + vel[2] * o[2]);
+                shift[c] = log1p(-vlos / ORC_C) / dlnlam;
+            }
+}
+
+/* High-resolution gather at table wavelength index n: kappa interpolated at
+ * the Doppler shifted effective wavelength (linear in kappa between the two
+ * neighbouring table wavelengths of the log-uniform grid; bilinear (T, ln P)
+ * on ln kappa at each), plus Rayleigh at the rest wavelength.  Lines are
+ * pure absorbers.  tab is kappa[lam][T][P].                               */
+void orc_hires_optics(int64_t ncell, const float *T, const float *P, const double *rho,
+                      const double *shift, int64_t nlam, int64_t nT, int64_t nP,
+                      const double *T_grid, const double *P_grid, const float *tab,
+                      int64_t n, double k_ray,
+                      double *a_ext, double *a_abs, double *omega, double *p_gas, double *g_cld)
+{
+    double *lnP = (double *)malloc(sizeof(double) * nP);
+    for (int64_t q = 0; q < nP; ++q) lnP[q] = log(P_grid[q]);
+    for (int64_t c = 0; c < ncell; ++c) {
+        int iT0, iT1, iP0, iP1;
+        double t, uu;
+        bracket(T_grid, nT, (double)T[c], &iT0, &iT1, &t);
+        bracket(lnP, nP, log((double)P[c]), &iP0, &iP1, &uu);
+        double x = (double)n + (shift ? shift[c] : 0.0);
+        int64_t n0;
+        double fr;
+        if (nlam == 1) { n0 = 0; fr = 0.0; }
+        else if (x <= 0.0) { n0 = 0; fr = 0.0; }
+        else if (x >= (double)(nlam - 1)) { n0 = nlam - 2; fr = 1.0; }
+        else { n0 = (int64_t)floor(x); fr = x - (double)n0; }
+        double k0 = interp_tp(tab + n0 * nT * nP, nP, iT0, iT1, t, iP0, iP1, uu);
+        double kl = k0;
+        if (nlam > 1) {
+            double k1 = interp_tp(tab + (n0 + 1) * nT * nP, nP, iT0, iT1, t, iP0, iP1, uu);
+            kl = (1.0 - fr) * k0 + fr * k1;
+        }
+        double kext = kl + k_ray;
+        a_ext[c] = rho[c] * kext;
+        a_abs[c] = rho[c] * kl;
+        omega[c] = kext > 0.0 ? k_ray / kext : 0.0;
+        p_gas[c] = 1.0;
+        g_cld[c] = 0.0;
+    }
+    free(lnP);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Emission sources (Sect. 5.3 L_i; Sect. 4.3 hybrid biasing; Sect. 4.6     */
+/* vertical tau cut).                                                       */
+/* ------------------------------------------------------------------------ */
+double orc_planck(double lam_cm, double T)
+{
+    double x = ORC_H * ORC_C / (lam_cm * ORC_KB * T);
+    return 2.0 * ORC_H * ORC_C * ORC_C / pow(lam_cm, 5.0) / expm1(x);
+}
+
+/* L_i = 4 pi V_i alpha_abs,i B_lambda(T_i), zero for cells whose column
+ * extinction optical depth from the top of the atmosphere down to the cell's
+ * top face exceeds tau_vert; q_i = (1 - xi) L_i / L_tot + xi / N_emit over
+ * emitting cells; cdf = running sum of q in cell order; wbirth = (L_i/L_tot)
+ * / q_i.  Returns L_tot (erg/s/cm).  info[0] = N_emit.                    */
+double orc_emission_sources(const orc_grid *g, const float *T, const double *a_ext,
+                            const double *a_abs, double lam_cm, double tau_vert, double xi,
+                            double *L, double *cdf, double *wbirth, int64_t *info)
+{
+    int64_t ncell = g->nlon * g->nlat * g->nlay;
+    for (int64_t j = 0; j < g->nlat; ++j)
+        for (int64_t i = 0; i < g->nlon; ++i) {
+            double tau = 0.0;
+            for (int64_t k = g->nlay - 1; k >= 0; --k) {
+                int64_t c = cell_index(g, (int)i, (int)j, (int)k);
+                double vol = (pow(g->r[k + 1], 3.0) - pow(g->r[k], 3.0)) / 3.0 *
+                             (sin(g->lat[j + 1]) - sin(g->lat[j])) * (g->lon[i + 1] - g->lon[i]);
+                double Li = 4.0 * ORC_PI * vol * a_abs[c] * orc_planck(lam_cm, (double)T[c]);
+                L[c] = (tau > tau_vert) ? 0.0 : Li;
+                tau = tau + a_ext[c] * (g->r[k + 1] - g->r[k]);
+            }
+        }
+    double Ltot = 0.0;
+    int64_t nemit = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        Ltot = Ltot + L[c];
+        if (L[c] > 0.0) nemit++;
+    }
+    double run = 0.0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        double q = 0.0;
+        if (L[c] > 0.0) q = (1.0 - xi) * L[c] / Ltot + xi / (double)nemit;
+        run = run + q;
+        cdf[c] = run;
+        wbirth[c] = (L[c] > 0.0) ? (L[c] / Ltot) / q : 0.0;
+    }
+    info[0] = nemit;
+    return Ltot;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport (Sect. 2, 3, 4).                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    uint64_t n_packets;
+    uint64_t packet0;     /* first packet id */
+    int64_t mode;         /* 0 albedo (spherical disk or slab), 1 emission */
+    int64_t scattering;   /* 0: no multiple scattering */
+    int64_t absorption;   /* 0 survival biasing, 1 continuous absorption */
+    int64_t tag;          /* XORed into the high key word */
+    int64_t max_events;
+    int64_t max_cross;    /* per ray segment walk */
+    int64_t n_obs;        /* slab albedo with n_obs == 0: backscatter */
+    double rr_threshold;
+    double rr_survive;
+    double tau_peel_max;
+    double mu0;           /* slab incidence cosine; <= 0: uniform over disk */
+} orc_params;
+
+typedef struct {
+    const double *a_ext, *a_abs, *omega, *p_gas, *g_cld;
+} orc_optics;
+
+/* counters per packet */
+enum { K_ESC = 0, K_SURF, K_ABS, K_RR, K_CAP, K_LOST, K_NINT, K_NCROSS, K_NCAPPED, K_NLOST, K_W0, NK };
+
+/* Walk a ray through the grid until an interaction at optical depth tau
+ * (measured in 'a'), escape, the surface or the crossing cap.  With
+ * continuous absorption the weight is reduced by exp(-alpha_abs s) on every
+ * path element and the removed weight is added to *absorbed.               */
+static int walk_flight(const orc_grid *g, const orc_optics *op, orc_ray *ry, const double d[3],
+                       double tau, int cont, double *W, double *absorbed, int64_t max_cross,
+                       int64_t *ncross)
+{
+    int64_t nc = 0;
+    for (;;) {
+        double s;
+        int f = exit_distance(g, ry, d, &s);
+        int64_t c = cell_index(g, ry->i, ry->j, ry->k);
+        double a = cont ? (op->a_ext[c] - op->a_abs[c]) : op->a_ext[c];
+        if (f == F_NONE && !(a > 0.0)) { *ncross += nc; return T_LOST; }
+        if (a > 0.0 && tau < a * s) {
+            double ds = tau / a;
+            if (cont) {
+                double wn = *W * exp(-op->a_abs[c] * ds);
+                *absorbed = *absorbed + (*W - wn);
+                *W = wn;
+            }
+            advance(g, ry, d, ds);
+            ry->ef = F_NONE;
+            *ncross += nc;
+            return T_INTERACT;
+        }
+        tau = tau - a * s;
+        if (cont) {
+            double wn = *W * exp(-op->a_abs[c] * s);
+            *absorbed = *absorbed + (*W - wn);
+            *W = wn;
+        }
+        advance(g, ry, d, s);
+        cross_face(g, ry, f);
+        nc++;
+        if (ry->k >= g->nlay) { *ncross += nc; return T_ESCAPE; }
+        if (ry->k < 0) { *ncross += nc; return T_SURFACE; }
+        if (nc >= max_cross) { *ncross += nc; return T_LOST; }
+    }
+}
+
+/* Optical depth from an event point to the top of the atmosphere along o.
+ * Returns +inf for rays that reach the surface, stall, or exceed tau_cut. */
+static double peel_tau(const orc_grid *g, const orc_optics *op, const orc_ray *start,
+                       const double o[3], double tau_cut, int64_t max_cross, int64_t *ncross)
+{
+    if (g->geom == 1 && !(o[2] > 0.0)) return INFINITY;
+    orc_ray ry = *start;
+    ry.ef = F_NONE;
+    double tau = 0.0;
+    int64_t nc = 0;
+    for (;;) {
+        double s;
+        int f = exit_distance(g, &ry, o, &s);
+        if (f == F_NONE) { *ncross += nc; return INFINITY; }
+        int64_t c = cell_index(g, ry.i, ry.j, ry.k);
+        tau = tau + op->a_ext[c] * s;
+        advance(g, &ry, o, s);
+        cross_face(g, &ry, f);
+        nc++;
+        if (tau > tau_cut) { *ncross += nc; return INFINITY; }
+        if (ry.k >= g->nlay) { *ncross += nc; return tau; }
+        if (ry.k < 0) { *ncross += nc; return INFINITY; }
+        if (nc >= max_cross) { *ncross += nc; return INFINITY; }
+    }
+}
+
+/* One packet history.  F[o] receives its peel-off sum per observer. */
+static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params *pr,
+                       const double *obs, const double *cdf, const double *wbirth, int64_t ncell,
+                       double r_toa, uint64_t pid, double *F, double *K)
+{
+    uint32_t tag = (uint32_t)pr->tag;
+    int nobs = (int)pr->n_obs;
+    int slab_back = (g->geom == 1 && nobs == 0);
+    int nout = slab_back ? 1 : nobs;
+    double oback[3] = {0.0, 0.0, 0.0};
+    for (int o = 0; o < nout; ++o) F[o] = 0.0;
+    for (int q = 0; q < NK; ++q) K[q] = 0.0;
+
+    orc_ray ry;
+    double d[3];
+    double W, W0;
+    double ua, ub;
+    int64_t ncross = 0;
+
+    if (pr->mode == 0) {
+        /* albedo: unit-weight packets enter at the top along -x (star at +x) */
+        orc_draw(pr->seed, tag, pid, 0, 0, &ua, &ub);
+        if (g->geom == 1) {
+            double mu0 = pr->mu0 > 0.0 ? pr->mu0 : sqrt(1.0 - ua);
+            d[0] = sqrt(fmax(1.0 - mu0 * mu0, 0.0));
+            d[1] = 0.0;
+            d[2] = -mu0;
+            oback[0] = -d[0]; oback[1] = 0.0; oback[2] = mu0;
+            ry.p[0] = 0.0; ry.p[1] = 0.0; ry.p[2] = g->r[g->nlay];
+            ry.i = 0; ry.j = 0; ry.k = (int)g->nlay - 1; ry.ef = F_OUT;
+        } else {
+            double rho = r_toa * sqrt(ua);
+            double a = 2.0 * ORC_PI * ub;
+            double y = rho * cos(a), z = rho * sin(a);
+            double x = sqrt(fmax(r_toa * r_toa - y * y - z * z, 0.0));
+            ry.p[0] = x; ry.p[1] = y; ry.p[2] = z;
+            d[0] = -1.0; d[1] = 0.0; d[2] = 0.0;
+            ry.k = (int)g->nlay - 1;
+            locate_column(g, ry.p, &ry.i, &ry.j);
+            ry.ef = F_OUT;
+        }
+        W = 1.0;
+    } else {
+        /* emission: cell by the biased CDF, uniform position in the cell's
+         * volume, isotropic direction, weight (L_i/L_tot)/q_i              */
+        if (!(cdf[ncell - 1] > 0.0)) return; /* nothing emits */
+        double u0a, u0b, u1a, u1b, u2a, u2b;
+        orc_draw(pr->seed, tag, pid, 0, 0, &u0a, &u0b);
+        orc_draw(pr->seed, tag, pid, 0, 1, &u1a, &u1b);
+        orc_draw(pr->seed, tag, pid, 0, 2, &u2a, &u2b);
+        double target = u0a * cdf[ncell - 1];
+        int64_t c = 0;
+        while (!(cdf[c] > target)) c++; /* smallest c with cdf[c] > target */
+        int i = (int)(c % g->nlon);
+        int j = (int)((c / g->nlon) % g->nlat);
+        int k = (int)(c / (g->nlon * g->nlat));
+        double rk3 = g->r[k] * g->r[k] * g->r[k];
+        double rk13 = g->r[k + 1] * g->r[k + 1] * g->r[k + 1];
+        double r = cbrt(rk3 + u0b * (rk13 - rk3));
+        double sl0 = sin(g->lat[j]), sl1 = sin(g->lat[j + 1]);
+        double sl = sl0 + u1a * (sl1 - sl0);
+        double cl = sqrt(fmax(1.0 - sl * sl, 0.0));
+        double lon = g->lon[i] + u1b * (g->lon[i + 1] - g->lon[i]);
+        ry.p[0] = r * cl * cos(lon);
+        ry.p[1] = r * cl * sin(lon);
+        ry.p[2] = r * sl;
+        ry.i = i; ry.j = j; ry.k = k; ry.ef = F_NONE;
+        double mu = 2.0 * u2a - 1.0;
+        double sp = sqrt(fmax(1.0 - mu * mu, 0.0));
+        double psi = 2.0 * ORC_PI * u2b;
+        d[0] = sp * cos(psi);
+        d[1] = sp * sin(psi);
+        d[2] = mu;
+        W = wbirth[c];
+        /* initial peel-off from the emission point */
+        for (int o = 0; o < nobs; ++o) {
+            double tau = peel_tau(g, op, &ry, obs + 3 * o, pr->tau_peel_max, pr->max_cross, &ncross);
+            F[o] = F[o] + W * exp(-tau) / (4.0 * ORC_PI);
+        }
+    }
+    W0 = W;
+    K[K_W0] = W0;
+
+    if (pr->mode == 1 && !pr->scattering) {
+        K[K_ESC] += W; /* weight leaves with its initial peel-off only */
+        K[K_NCROSS] = (double)ncross;
+        return;
+    }
+
+    int cont = pr->absorption == 1;
+    for (uint32_t e = 1;; ++e) {
+        double tau, usel;
+        orc_draw(pr->seed, tag, pid, e, 0, &ua, &usel);
+        tau = -log(ua);
+        int term = walk_flight(g, op, &ry, d, tau, cont, &W, &K[K_ABS], pr->max_cross, &ncross);
+        if (term == T_ESCAPE) { K[K_ESC] += W; break; }
+        if (term == T_SURFACE) { K[K_SURF] += W; break; }
+        if (term == T_LOST) { K[K_LOST] += W; K[K_NLOST] += 1.0; break; }
+        /* interaction in cell c */
+        K[K_NINT] += 1.0;
+        int64_t c = cell_index(g, ry.i, ry.j, ry.k);
+        double om = op->omega[c], pg = op->p_gas[c], gc = op->g_cld[c];
+        for (int o = 0; o < nout; ++o) {
+            const double *ov = slab_back ? oback : obs + 3 * o;
+            double mu = d[0] * ov[0] + d[1] * ov[1] + d[2] * ov[2];
+            double theta = (pg * orc_phase_rayleigh(mu) + (1.0 - pg) * orc_phase_hg(mu, gc)) / (4.0 * ORC_PI);
+            double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
+            double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
+            F[o] = F[o] + f;
+        }
+        if (!cont) {
+            K[K_ABS] += W * (1.0 - om);
+            W = W * om;
+        }
+        double u1a, u1b;
+        orc_draw(pr->seed, tag, pid, e, 1, &u1a, &u1b);
+        double mu = (usel < pg) ? orc_sample_rayleigh(u1a) : orc_sample_hg(u1a, gc);
+        orc_rotate(d, mu, 2.0 * ORC_PI * u1b);
+        if (W < pr->rr_threshold * W0) {
+            double u2a, u2b;
+            orc_draw(pr->seed, tag, pid, e, 2, &u2a, &u2b);
+            if (u2a < pr->rr_survive) {
+                double wn = W / pr->rr_survive;
+                K[K_RR] -= (wn - W);
+                W = wn;
+            } else {
+                K[K_RR] += W;
+                W = 0.0;
+                break;
+            }
+        }
+        if ((int64_t)e >= pr->max_events) { K[K_CAP] += W; K[K_NCAPPED] += 1.0; break; }
+    }
+    K[K_NCROSS] = (double)ncross;
+}
+
+/* Run n_packets histories.  F_out[n][nout], K_out[n][NK] per packet (the
+ * caller sums them in packet order).  obs: n_obs unit vectors.           */
+int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params *pr,
+                      const double *obs, const double *cdf, const double *wbirth, double r_toa,
+                      double *F_out, double *K_out, int64_t nthreads)
+{
+    int64_t ncell = g->nlon * g->nlat * g->nlay;
+    int nout = (g->geom == 1 && pr->n_obs == 0) ? 1 : (int)pr->n_obs;
+    int64_t n = (int64_t)pr->n_packets;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads((int)nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t q = 0; q < n; ++q) {
+        run_packet(g, op, pr, obs, cdf, wbirth, ncell, r_toa, pr->packet0 + (uint64_t)q,
+                   F_out + q * nout, K_out + q * NK);
+    }
+    return nout;
+}
+
+int64_t orc_num_counters(void) { return NK; }
+
+int64_t orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transmission (Sect. 5.1): chords along -x through the limb, stratified   */
+/* jittered (b, alpha) samples; per chord tau(lambda) = sum alpha s and the */
+/* estimator term (1 - exp(-tau)) b.                                        */
+/* ------------------------------------------------------------------------ */
+/* value[c][s] = (1 - exp(-tau_cs)) b_c for chord c and spectral slot s;
+ * alpha is [n_spec][ncell].  tau_out (optional) = tau_cs.                 */
+void orc_transmission(const orc_grid *g, const double *alpha, int64_t n_spec, int64_t n_b,
+                      int64_t n_alpha, uint64_t seed, int64_t tag, double r0, double r_toa,
+                      double *value, double *tau_out, int64_t nthreads)
+{
+    int64_t nch = n_b * n_alpha;
+    int64_t cap = 64 * (g->nlay + g->nlat + g->nlon) + 64;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads((int)nthreads);
+#pragma omp parallel
+#endif
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * cap);
+        double *lens = (double *)malloc(sizeof(double) * cap);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            int64_t ib = ch / n_alpha, ia = ch % n_alpha;
+            double ua, ub;
+            orc_draw(seed, (uint32_t)tag, (uint64_t)ch, 0, 0, &ua, &ub);
+            double b = r0 + ((double)ib + ua) * (r_toa - r0) / (double)n_b;
+            double al = 2.0 * ORC_PI * ((double)ia + ub) / (double)n_alpha;
+            double p[3] = {sqrt(fmax(r_toa * r_toa - b * b, 0.0)), b * cos(al), b * sin(al)};
+            double d[3] = {-1.0, 0.0, 0.0};
+            int i, j;
+            locate_column(g, p, &i, &j);
+            int64_t term;
+            int64_t nseg = orc_trace_segments(g, p, d, i, j, g->nlay - 1, F_OUT, cap, cells, lens, &term);
+            for (int64_t s = 0; s < n_spec; ++s) {
+                double tau = 0.0;
+                for (int64_t q = 0; q < nseg; ++q)
+                    tau = tau + alpha[s * (g->nlon * g->nlat * g->nlay) + cells[q]] * lens[q];
+                if (term != T_ESCAPE) tau = INFINITY;
+                value[ch * n_spec + s] = (1.0 - exp(-tau)) * b;
+                if (tau_out) tau_out[ch * n_spec + s] = tau;
+            }
+        }
+        free(cells);
+        free(lens);
+    }
+}

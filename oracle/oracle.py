@@ -1,0 +1,459 @@
+"""Python driver of the FP64 CPU oracle (mcrt_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: used by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+
+The solve drivers below follow the paper's observables (Sect. 5):
+* albedo: the escaping fraction toward the observer per unit incident flux,
+  times pi (geometric albedo at zero phase, the A_g equation);
+* emission: L_p = (L_tot/N) sum_n F_n, I_p = L_p / (pi R_TOA^2), F_p = pi I_p;
+* transmission: <I> = (R_TOA - R0)/N sum (1 - e^-tau) b and
+  (R_p/R_star)^2 = (R0^2 + 2 <I>)/R_star^2;
+band values are sum_g w_g X_g over fixed-g solves.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mcrt_oracle.c")
+_LIB = os.path.join(_HERE, "libmcrt_oracle.so")
+
+NK = 11
+K_NAMES = ["escaped", "surface", "absorbed", "roulette", "capped", "lost",
+           "n_interactions", "n_crossings", "n_capped", "n_lost", "w0"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (plain FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_int64), ("nlon", ctypes.c_int64), ("nlat", ctypes.c_int64),
+                ("nlay", ctypes.c_int64), ("r", ctypes.c_void_p), ("lat", ctypes.c_void_p),
+                ("lon", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_packets", ctypes.c_uint64),
+                ("packet0", ctypes.c_uint64), ("mode", ctypes.c_int64),
+                ("scattering", ctypes.c_int64), ("absorption", ctypes.c_int64),
+                ("tag", ctypes.c_int64), ("max_events", ctypes.c_int64),
+                ("max_cross", ctypes.c_int64), ("n_obs", ctypes.c_int64),
+                ("rr_threshold", ctypes.c_double), ("rr_survive", ctypes.c_double),
+                ("tau_peel_max", ctypes.c_double), ("mu0", ctypes.c_double)]
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("a_ext", ctypes.c_void_p), ("a_abs", ctypes.c_void_p), ("omega", ctypes.c_void_p),
+                ("p_gas", ctypes.c_void_p), ("g_cld", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        vp, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_u01.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_u01.restype = dbl
+        L.orc_draw_pair.argtypes = [u64, ctypes.c_uint32, u64, ctypes.c_uint32, ctypes.c_uint32, vp]
+        for nm in ("orc_phase_rayleigh",):
+            getattr(L, nm).argtypes = [dbl]
+            getattr(L, nm).restype = dbl
+        L.orc_phase_hg.argtypes = [dbl, dbl]
+        L.orc_phase_hg.restype = dbl
+        L.orc_sample_rayleigh.argtypes = [dbl]
+        L.orc_sample_rayleigh.restype = dbl
+        L.orc_sample_hg.argtypes = [dbl, dbl]
+        L.orc_sample_hg.restype = dbl
+        L.orc_rotate.argtypes = [vp, dbl, dbl]
+        L.orc_planck.argtypes = [dbl, dbl]
+        L.orc_planck.restype = dbl
+        L.orc_trace_segments.argtypes = [ctypes.POINTER(_Grid), vp, vp, i64, i64, i64, i64, i64, vp, vp, vp]
+        L.orc_trace_segments.restype = i64
+        L.orc_ck_optics.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, dbl,
+                                    vp, vp, vp, vp, vp]
+        L.orc_doppler_shift.argtypes = [ctypes.POINTER(_Grid), vp, vp, vp, dbl, vp, dbl, vp]
+        L.orc_hires_optics.argtypes = [i64, vp, vp, vp, vp, i64, i64, i64, vp, vp, vp, i64, dbl,
+                                       vp, vp, vp, vp, vp]
+        L.orc_emission_sources.argtypes = [ctypes.POINTER(_Grid), vp, vp, vp, dbl, dbl, dbl,
+                                           vp, vp, vp, vp]
+        L.orc_emission_sources.restype = dbl
+        L.orc_transport.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Optics),
+                                    ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp, i64]
+        L.orc_transport.restype = i64
+        L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
+                                       vp, vp, i64]
+        L.orc_max_threads.restype = i64
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def u01(a: int, b: int) -> float:
+    return lib().orc_u01(a, b)
+
+
+def draw_pair(seed, tag, packet, event, block):
+    out = np.zeros(2)
+    lib().orc_draw_pair(seed, tag, packet, event, block, out.ctypes.data)
+    return out
+
+
+def sample_rayleigh(z):
+    return lib().orc_sample_rayleigh(float(z))
+
+
+def sample_hg(z, g):
+    return lib().orc_sample_hg(float(z), float(g))
+
+
+def phase_rayleigh(mu):
+    return lib().orc_phase_rayleigh(float(mu))
+
+
+def phase_hg(mu, g):
+    return lib().orc_phase_hg(float(mu), float(g))
+
+
+def rotate(d, mu, psi):
+    v = np.ascontiguousarray(d, dtype=np.float64).copy()
+    lib().orc_rotate(v.ctypes.data, float(mu), float(psi))
+    return v
+
+
+def planck(lam_cm, T):
+    return lib().orc_planck(float(lam_cm), float(T))
+
+
+class GridView:
+    """Keeps the numpy arrays alive behind the C grid struct."""
+
+    def __init__(self, grid):
+        self.grid = grid
+        self.r = _f64(grid.r_edges)
+        self.lat = _f64(grid.lat_edges)
+        self.lon = _f64(grid.lon_edges)
+        self.c = _Grid(grid.geometry, grid.nlon, grid.nlat, grid.nlay, self.r.ctypes.data,
+                       self.lat.ctypes.data, self.lon.ctypes.data)
+
+    @property
+    def max_cross(self):
+        g = self.grid
+        return 4 * (g.nlay + g.nlat + g.nlon) + 16
+
+
+def trace_segments(grid, p, d, i, j, k, ef=-1, cap=100000):
+    gv = GridView(grid)
+    p = _f64(p)
+    d = _f64(d)
+    cells = np.zeros(cap, dtype=np.int64)
+    lens = np.zeros(cap)
+    term = np.zeros(1, dtype=np.int64)
+    n = lib().orc_trace_segments(ctypes.byref(gv.c), p.ctypes.data, d.ctypes.data, i, j, k, ef,
+                                 cap, cells.ctypes.data, lens.ctypes.data, term.ctypes.data)
+    return cells[:n], lens[:n], int(term[0])
+
+
+@dataclass
+class Optics:
+    a_ext: np.ndarray
+    a_abs: np.ndarray
+    omega: np.ndarray
+    p_gas: np.ndarray
+    g_cld: np.ndarray
+
+
+def ck_optics(grid, table, band: int, g: int) -> Optics:
+    n = grid.ncell
+    out = [np.zeros(n) for _ in range(5)]
+    T, P, rho = _f32(grid.T), _f32(grid.P), _f64(grid.rho)
+    cs, ca, cg = _f32(grid.cld_ksca), _f32(grid.cld_kabs), _f32(grid.cld_g)
+    Tg, Pg = _f64(table.T_grid), _f64(table.P_grid)
+    tab = np.ascontiguousarray(table.kappa[band, g], dtype=np.float32)
+    lib().orc_ck_optics(n, _p(T), _p(P), _p(rho), _p(cs), _p(ca), _p(cg), len(Tg), len(Pg),
+                        _p(Tg), _p(Pg), _p(tab), float(table.k_ray[band]), *[o.ctypes.data for o in out])
+    return Optics(*out)
+
+
+def doppler_shift(grid, obs_dir, dlnlam) -> np.ndarray:
+    gv = GridView(grid)
+    o = _f64(obs_dir)
+    out = np.zeros(grid.ncell)
+    u, v, w = _f32(grid.u), _f32(grid.v), _f32(grid.w)
+    lib().orc_doppler_shift(ctypes.byref(gv.c), _p(u), _p(v), _p(w), float(grid.omega_rot),
+                            o.ctypes.data, float(dlnlam), out.ctypes.data)
+    return out
+
+
+def hires_optics(grid, table, n: int, shift: Optional[np.ndarray]) -> Optics:
+    nc = grid.ncell
+    out = [np.zeros(nc) for _ in range(5)]
+    T, P, rho = _f32(grid.T), _f32(grid.P), _f64(grid.rho)
+    Tg, Pg = _f64(table.T_grid), _f64(table.P_grid)
+    tab = np.ascontiguousarray(table.kappa, dtype=np.float32)
+    sh = _f64(shift)
+    lib().orc_hires_optics(nc, _p(T), _p(P), _p(rho), _p(sh), table.nlam, len(Tg), len(Pg),
+                           _p(Tg), _p(Pg), _p(tab), int(n), float(table.k_ray[n]),
+                           *[o.ctypes.data for o in out])
+    return Optics(*out)
+
+
+@dataclass
+class Sources:
+    L: np.ndarray
+    cdf: np.ndarray
+    wbirth: np.ndarray
+    L_tot: float
+    n_emit: int
+
+
+def emission_sources(grid, optics: Optics, lam_um: float, tau_vert: float, xi: float) -> Sources:
+    gv = GridView(grid)
+    n = grid.ncell
+    L, cdf, wb = np.zeros(n), np.zeros(n), np.zeros(n)
+    info = np.zeros(1, dtype=np.int64)
+    T = _f32(grid.T)
+    Ltot = lib().orc_emission_sources(ctypes.byref(gv.c), T.ctypes.data, optics.a_ext.ctypes.data,
+                                      optics.a_abs.ctypes.data, float(lam_um) * 1e-4, float(tau_vert),
+                                      float(xi), L.ctypes.data, cdf.ctypes.data, wb.ctypes.data,
+                                      info.ctypes.data)
+    return Sources(L, cdf, wb, Ltot, int(info[0]))
+
+
+@dataclass
+class Params:
+    seed: int = 12345
+    n_packets: int = 1000
+    packet0: int = 0
+    scattering: bool = True
+    absorption: int = 0  # 0 survival, 1 continuous
+    decorrelate: bool = False
+    max_events: int = 1_000_000
+    rr_threshold: float = 1e-3
+    rr_survive: float = 0.1
+    tau_peel_max: float = 50.0
+    mu0: float = 0.0
+    emis_bias: float = 0.5
+    tau_vert_max: float = 30.0
+    obs_phase: Sequence[float] = (0.0,)
+    obs_dir: Optional[np.ndarray] = None
+    n_b: int = 256
+    n_alpha: int = 360
+    r_star: float = 6.957e10
+    threads: int = 0
+
+
+def albedo_obs_dirs(phases):
+    """Albedo phase angle a: o = (cos a, sin a, 0) (star at +x)."""
+    return np.array([[math.cos(a), math.sin(a), 0.0] for a in phases], dtype=np.float64).reshape(-1, 3)
+
+
+def emission_obs_dirs(phases):
+    """Orbital phase phi: o = (cos l, sin l, 0), l = pi (1 - 2 phi); phi = 0.5
+    views the dayside (substellar point at lon = 0)."""
+    out = []
+    for ph in phases:
+        lo = math.pi * (1.0 - 2.0 * ph)
+        out.append([math.cos(lo), math.sin(lo), 0.0])
+    return np.array(out, dtype=np.float64).reshape(-1, 3)
+
+
+def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.ndarray],
+              sources: Optional[Sources] = None, tag: int = 0):
+    """Run params.n_packets histories; returns per-packet F [n, nout] and
+    counters K [n, NK]."""
+    gv = GridView(grid)
+    nobs = 0 if obs is None else len(obs)
+    pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
+                 int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
+                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0)
+    op = _Optics(optics.a_ext.ctypes.data, optics.a_abs.ctypes.data, optics.omega.ctypes.data,
+                 optics.p_gas.ctypes.data, optics.g_cld.ctypes.data)
+    nout = 1 if (grid.geometry == 1 and nobs == 0) else nobs
+    F = np.zeros((params.n_packets, max(nout, 1)))
+    K = np.zeros((params.n_packets, NK))
+    o = None if obs is None else _f64(obs)
+    cdf = None if sources is None else sources.cdf
+    wb = None if sources is None else sources.wbirth
+    lib().orc_transport(ctypes.byref(gv.c), ctypes.byref(op), ctypes.byref(pr), _p(o), _p(cdf), _p(wb),
+                        float(grid.r_toa), F.ctypes.data, K.ctypes.data, int(params.threads))
+    return F[:, :nout], K
+
+
+def _tag(params, spec_slot_idx, g, ng):
+    return (1 + spec_slot_idx * ng + g) if params.decorrelate else 0
+
+
+@dataclass
+class Result:
+    value: np.ndarray           # [n_spec, n_obs]
+    stderr: np.ndarray          # [n_spec, n_obs]
+    per_g: np.ndarray           # [n_spec, n_g, n_obs] value per g-ordinate
+    sums: np.ndarray            # [n_spec, n_g, n_obs, 2] (sum F, sum F^2)
+    counters: np.ndarray        # [n_spec, n_g, NK]
+    extra: dict = field(default_factory=dict)
+
+
+def _spec_list(table, spec_idx):
+    if spec_idx is None:
+        return list(range(table.nband))
+    return [int(s) for s in spec_idx]
+
+
+def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False) -> Result:
+    specs = _spec_list(table, spec_idx)
+    ng = table.ng
+    if grid.geometry == 1:
+        obs = None if params.obs_dir is None else _f64(params.obs_dir)
+    else:
+        obs = _f64(params.obs_dir) if params.obs_dir is not None else albedo_obs_dirs(params.obs_phase)
+    nout = 1 if obs is None else len(obs)
+    N = params.n_packets
+    sums = np.zeros((len(specs), ng, nout, 2))
+    cnt = np.zeros((len(specs), ng, NK))
+    per_g = np.zeros((len(specs), ng, nout))
+    se_g = np.zeros_like(per_g)
+    packets = {}
+    for si, b in enumerate(specs):
+        for g in range(ng):
+            op = ck_optics(grid, table, b, g)
+            F, K = transport(grid, op, params, 0, obs, tag=_tag(params, b, g, ng))
+            if keep_packets:
+                packets[(si, g)] = (F, K)
+            sums[si, g, :, 0] = F.sum(axis=0)
+            sums[si, g, :, 1] = (F * F).sum(axis=0)
+            cnt[si, g] = K.sum(axis=0)
+            E = sums[si, g, :, 0] / N
+            var = np.maximum(sums[si, g, :, 1] / N - E * E, 0.0) / N
+            per_g[si, g] = math.pi * E
+            se_g[si, g] = math.pi * np.sqrt(var)
+    w = np.asarray(table.g_weights, dtype=np.float64)
+    value = np.einsum("g,sgo->so", w, per_g)
+    stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
+    return Result(value, stderr, per_g, sums, cnt, {"packets": packets})
+
+
+def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=False) -> Result:
+    """Correlated-k emission spectrum F_p(band, phase) [erg/s/cm^2/cm]."""
+    specs = _spec_list(table, spec_idx)
+    ng = table.ng
+    obs = _f64(params.obs_dir) if params.obs_dir is not None else emission_obs_dirs(params.obs_phase)
+    nout = len(obs)
+    N = params.n_packets
+    sums = np.zeros((len(specs), ng, nout, 2))
+    cnt = np.zeros((len(specs), ng, NK))
+    per_g = np.zeros((len(specs), ng, nout))
+    se_g = np.zeros_like(per_g)
+    ltot = np.zeros((len(specs), ng))
+    packets = {}
+    rt2 = grid.r_toa ** 2
+    for si, b in enumerate(specs):
+        for g in range(ng):
+            op = ck_optics(grid, table, b, g)
+            src = emission_sources(grid, op, table.lam_um[b], params.tau_vert_max, params.emis_bias)
+            ltot[si, g] = src.L_tot
+            if src.L_tot > 0.0:
+                F, K = transport(grid, op, params, 1, obs, sources=src, tag=_tag(params, b, g, ng))
+            else:
+                F, K = np.zeros((N, nout)), np.zeros((N, NK))
+            if keep_packets:
+                packets[(si, g)] = (F, K, src)
+            sums[si, g, :, 0] = F.sum(axis=0)
+            sums[si, g, :, 1] = (F * F).sum(axis=0)
+            cnt[si, g] = K.sum(axis=0)
+            mean = sums[si, g, :, 0] / N
+            var = np.maximum(sums[si, g, :, 1] / N - mean * mean, 0.0) / N
+            # L_p = (L_tot/N) sum F ; I_p = L_p/(pi R_TOA^2) ; F_p = pi I_p
+            per_g[si, g] = src.L_tot * mean / rt2
+            se_g[si, g] = src.L_tot * np.sqrt(var) / rt2
+    w = np.asarray(table.g_weights, dtype=np.float64)
+    value = np.einsum("g,sgo->so", w, per_g)
+    stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
+    return Result(value, stderr, per_g, sums, cnt, {"packets": packets, "L_tot": ltot})
+
+
+def transmission_alpha(grid, table, specs, hires: bool):
+    """alpha_ext per spectral point (rows) for the transmission chords."""
+    if hires:
+        sh = doppler_shift(grid, np.array([-1.0, 0.0, 0.0]), table.dlnlam) if grid.u is not None or \
+            grid.omega_rot != 0.0 else None
+        return [hires_optics(grid, table, n, sh).a_ext for n in specs], [0] * len(specs)
+    rows, gs = [], []
+    for b in specs:
+        for g in range(table.ng):
+            rows.append(ck_optics(grid, table, b, g).a_ext)
+            gs.append(g)
+    return rows, gs
+
+
+def solve_transmission(grid, table, params: Params, spec_idx=None, tau_out=False) -> Result:
+    """Raytrace transmission with jittered (b, alpha) chords along -x."""
+    hires = not hasattr(table, "g_weights")
+    if spec_idx is None:
+        specs = list(range(table.nlam if hires else table.nband))
+    else:
+        specs = [int(s) for s in spec_idx]
+    rows, _ = transmission_alpha(grid, table, specs, hires)
+    alpha = np.ascontiguousarray(np.stack(rows), dtype=np.float64)
+    gv = GridView(grid)
+    nrow = alpha.shape[0]
+    nch = params.n_b * params.n_alpha
+    val = np.zeros((nch, nrow))
+    tau = np.zeros((nch, nrow)) if tau_out else None
+    lib().orc_transmission(ctypes.byref(gv.c), alpha.ctypes.data, nrow, params.n_b, params.n_alpha,
+                           params.seed, 0, grid.r0, grid.r_toa, val.ctypes.data, _p(tau),
+                           int(params.threads))
+    s1 = val.sum(axis=0)
+    s2 = (val * val).sum(axis=0)
+    dr = grid.r_toa - grid.r0
+    I = dr * s1 / nch
+    var = np.maximum(s2 / nch - (s1 / nch) ** 2, 0.0) / nch
+    depth = (grid.r0 ** 2 + 2.0 * I) / params.r_star ** 2
+    se = 2.0 * dr * np.sqrt(var) / params.r_star ** 2
+    ng = 1 if hires else table.ng
+    depth = depth.reshape(len(specs), ng)
+    se = se.reshape(len(specs), ng)
+    w = np.ones(1) if hires else np.asarray(table.g_weights, dtype=np.float64)
+    value = (depth * w[None, :]).sum(axis=1)[:, None]
+    stderr = np.sqrt(((se * w[None, :]) ** 2).sum(axis=1))[:, None]
+    sums = np.stack([s1, s2], axis=-1).reshape(len(specs), ng, 1, 2)
+    return Result(value, stderr, depth[:, :, None], sums, np.zeros((len(specs), ng, NK)),
+                  {"tau": tau})

@@ -1,0 +1,207 @@
+"""Pins of the oracle's packet transport against closed forms: Beer-Lambert,
+exact single scattering, Chandrasekhar's H-function (isotropic, semi-infinite,
+conservative), adding-doubling (Rayleigh and HG, omega = 0.99), energy
+conservation and estimator equivalences."""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+from oracle import oracle as O
+from paper_2110_15640_amd import inputs as I
+
+
+def within(x, ref, se, k=4.0, floor=0.0):
+    assert abs(x - ref) <= k * se + floor, (x, ref, se, (x - ref) / max(se, 1e-300))
+
+
+def slab_obs(mu, dphi):
+    s = math.sqrt(1.0 - mu * mu)
+    return [s * math.cos(dphi), s * math.sin(dphi), mu]
+
+
+def run(grid, table, params, obs=None):
+    p = O.Params(**params)
+    if obs is not None:
+        p.obs_dir = np.array(obs, dtype=np.float64)
+    return O.solve_albedo(grid, table, p, keep_packets=True)
+
+
+def test_beer_lambert_continuous_is_exact():
+    g, t = I.make_homogeneous_slab(1.0, 0.0)
+    r = run(g, t, dict(n_packets=500, mu0=1.0, absorption=1, seed=3))
+    F, K = r.extra["packets"][(0, 0)]
+    np.testing.assert_allclose(K[:, 1], math.exp(-1.0), rtol=1e-14)  # weight at the surface
+    np.testing.assert_allclose(K[:, 2], 1.0 - math.exp(-1.0), rtol=1e-14)
+
+
+def test_beer_lambert_oblique_multilayer_continuous():
+    g, t = I.make_homogeneous_slab(2.0, 0.0, nlay=7)
+    mu0 = 0.3
+    r = run(g, t, dict(n_packets=50, mu0=mu0, absorption=1, seed=4))
+    F, K = r.extra["packets"][(0, 0)]
+    np.testing.assert_allclose(K[:, 1], math.exp(-2.0 / mu0), rtol=1e-12)
+
+
+def test_beer_lambert_survival_binomial():
+    g, t = I.make_homogeneous_slab(1.0, 0.0)
+    n = 40000
+    r = run(g, t, dict(n_packets=n, mu0=1.0, absorption=0, seed=5))
+    frac = r.counters[0, 0, 1] / n
+    p = math.exp(-1.0)
+    within(frac, p, math.sqrt(p * (1 - p) / n), k=3.5)
+
+
+@pytest.mark.parametrize("kind", ["iso", "hg", "ray", "mix"])
+def test_single_scattering_exact(kind):
+    tau, om, mu0 = 0.75, 0.8, 0.6
+    if kind == "ray":
+        g, t = I.make_homogeneous_slab(tau, om, rayleigh=True)
+        pg, gc = 1.0, 0.0
+    else:
+        gc = {"iso": 0.0, "hg": 0.65, "mix": -0.3}[kind]
+        g, t = I.make_homogeneous_slab(tau, om, g_cld=gc)
+        pg = 0.0
+        if kind == "mix":  # 30 % of the scattering opacity by gas
+            ks = float(g.cld_ksca[0])
+            t.k_ray = np.array([0.3 * ks])
+            g.cld_ksca = np.full(1, 0.7 * ks, np.float32)
+            pg = 0.3
+    obs = [slab_obs(0.9, math.pi), slab_obs(0.6, math.pi), slab_obs(0.35, 0.4), slab_obs(0.15, 2.2)]
+    n = 60000
+    r = run(g, t, dict(n_packets=n, mu0=mu0, max_events=1, seed=6), obs)
+    d0 = np.array([math.sqrt(1 - mu0 * mu0), 0.0, -mu0])
+    kext = float(t.kappa.ravel()[0]) + float(t.k_ray[0]) + (float(g.cld_ksca[0]) if g.cld_ksca is not None else 0.0)
+    tau_e = kext * g.r_edges[-1]
+    om_e = (kext - float(t.kappa.ravel()[0])) / kext
+    for o, ov in enumerate(obs):
+        mu = ov[2]
+        c = float(d0 @ np.array(ov))
+        P = pg * 0.75 * (1 + c * c) + (1 - pg) * ((1 - gc * gc) / (1 + gc * gc - 2 * gc * c) ** 1.5 if gc else 1.0)
+        E = om_e * P / (4 * math.pi) * mu * (1 - math.exp(-tau_e * (1 / mu0 + 1 / mu))) / (mu + mu0)
+        within(r.value[0, o] / math.pi, E, r.stderr[0, o] / math.pi)
+
+
+@pytest.fixture(scope="module")
+def iso_H():
+    return CF.isotropic_semi_infinite(1.0)
+
+
+@pytest.mark.parametrize("mu0", [1.0, 0.5, 0.2])
+def test_semi_infinite_isotropic_h_function(iso_H, mu0):
+    """omega = 1, tau = 1e4: E = S(mu0, mu0)/(4 pi mu0) = H(mu0)^2/(8 pi)."""
+    S, H = iso_H
+    g, t = I.make_homogeneous_slab(8192.0, 1.0, g_cld=0.0)
+    n = 12000
+    r = run(g, t, dict(n_packets=n, mu0=mu0, seed=7))
+    E = float(H(np.array([mu0]))[0]) ** 2 / (8 * math.pi)
+    within(r.value[0, 0] / math.pi, E, r.stderr[0, 0] / math.pi, floor=2e-4 * E)
+
+
+def test_semi_infinite_isotropic_geometric_albedo(iso_H):
+    S, H = iso_H
+    mu, w = CF.gauss01(200)
+    Ag = 0.5 * float((w * S(mu, mu)).sum())
+    assert Ag == pytest.approx(0.68967, abs=2e-5)
+    g, t = I.make_homogeneous_slab(8192.0, 1.0, g_cld=0.0)
+    r = run(g, t, dict(n_packets=30000, seed=8))
+    within(r.value[0, 0], Ag, r.stderr[0, 0], floor=2e-4)
+
+
+@pytest.fixture(scope="module")
+def dbl_ray():
+    return CF.Doubling(CF.phase_rayleigh, 0.99, 4096.0, n=32, mmax=2, n_double=42)
+
+
+@pytest.fixture(scope="module")
+def dbl_hg():
+    return CF.Doubling(CF.phase_hg(0.5), 0.99, 4096.0, n=32, mmax=48, n_double=42)
+
+
+@pytest.mark.parametrize("which", ["ray", "hg"])
+def test_semi_infinite_reflection_by_doubling(which, dbl_ray, dbl_hg):
+    D = dbl_ray if which == "ray" else dbl_hg
+    if which == "ray":
+        g, t = I.make_homogeneous_slab(4096.0, 0.99, rayleigh=True)
+    else:
+        g, t = I.make_homogeneous_slab(4096.0, 0.99, g_cld=0.5)
+    j0 = 26  # incidence on a quadrature node
+    mu0 = float(D.mu[j0])
+    sel = [(31, math.pi), (26, math.pi), (18, 0.0), (10, 1.0), (4, 2.5)]
+    obs = [slab_obs(float(D.mu[i]), dp) for i, dp in sel]
+    n = 30000
+    r = run(g, t, dict(n_packets=n, mu0=mu0, seed=9), obs)
+    for o, (i, dp) in enumerate(sel):
+        E = float(D.mu[i]) * D.rho_nodes(dp)[i, j0] / math.pi
+        within(r.value[0, o] / math.pi, E, r.stderr[0, o] / math.pi, floor=1e-4 * E)
+
+
+@pytest.mark.parametrize("which", ["ray", "hg"])
+def test_semi_infinite_geometric_albedo_by_doubling(which, dbl_ray, dbl_hg):
+    D = dbl_ray if which == "ray" else dbl_hg
+    if which == "ray":
+        g, t = I.make_homogeneous_slab(4096.0, 0.99, rayleigh=True)
+    else:
+        g, t = I.make_homogeneous_slab(4096.0, 0.99, g_cld=0.5)
+    r = run(g, t, dict(n_packets=40000, seed=10))
+    within(r.value[0, 0], D.geometric_albedo(), r.stderr[0, 0], floor=1e-4)
+
+
+def test_energy_conservation_per_packet():
+    g, t = I.make_albedo_slab(nlay=20, nlam=2)
+    p = dict(n_packets=3000, seed=11, rr_threshold=0.0)
+    r = run(g, t, p)
+    for key in r.extra["packets"]:
+        F, K = r.extra["packets"][key]
+        tot = K[:, 0] + K[:, 1] + K[:, 2] + K[:, 3] + K[:, 4] + K[:, 5]
+        np.testing.assert_allclose(tot, K[:, 10], rtol=1e-12)
+    # with roulette: conservation holds in expectation only
+    r = run(g, t, dict(n_packets=20000, seed=12, rr_threshold=0.5, rr_survive=0.3))
+    F, K = r.extra["packets"][(0, 0)]
+    dev = K[:, 0] + K[:, 1] + K[:, 2] + K[:, 3] + K[:, 4] + K[:, 5] - K[:, 10]
+    np.testing.assert_allclose(dev, 0.0, atol=1e-12)  # roulette term is book-kept
+    within(K[:, 3].mean(), 0.0, K[:, 3].std() / math.sqrt(len(K)))
+
+
+def test_max_events_cap_counts_packets():
+    g, t = I.make_homogeneous_slab(8192.0, 1.0, g_cld=0.0)
+    r = run(g, t, dict(n_packets=500, seed=13, max_events=3))
+    F, K = r.extra["packets"][(0, 0)]
+    assert K[:, 8].sum() > 0
+    assert K[:, 6].max() == 3
+
+
+def test_survival_equals_continuous_absorption():
+    g, t = I.make_albedo_slab(nlay=20, nlam=3)
+    a = run(g, t, dict(n_packets=30000, seed=14))
+    b = run(g, t, dict(n_packets=30000, seed=15, absorption=1))
+    for s in range(3):
+        within(a.value[s, 0] - b.value[s, 0], 0.0, math.hypot(a.stderr[s, 0], b.stderr[s, 0]))
+
+
+def test_packet_ranges_and_fused_observers_are_bit_identical():
+    g = I.make_sphere(8, 4, 5, seed=16)
+    _, tab, _ = I.make_emission_3d(8, 4, 5, nband=2, ng=2)
+    op = O.ck_optics(g, tab, 1, 0)
+    obs = O.albedo_obs_dirs([0.0, 0.7, 2.0])
+    p = O.Params(n_packets=600, seed=17)
+    F, K = O.transport(g, op, p, 0, obs)
+    p2 = O.Params(n_packets=300, seed=17, packet0=300)
+    F2, K2 = O.transport(g, op, p2, 0, obs)
+    assert np.array_equal(F[300:], F2) and np.array_equal(K[300:], K2)
+    for o in range(3):
+        Fo, _ = O.transport(g, op, p, 0, obs[o:o + 1])
+        assert np.array_equal(Fo[:, 0], F[:, o])
+
+
+def test_emission_bias_is_unbiased():
+    g, tab, _ = I.make_emission_3d(16, 8, 10, nband=2, ng=1)
+    base = dict(n_packets=20000, seed=18, obs_phase=(0.5, 0.0), scattering=False)
+    res = []
+    for xi in (0.0, 0.5, 1.0):
+        p = O.Params(**base, emis_bias=xi)
+        res.append(O.solve_emission(g, tab, p, spec_idx=[1]))
+    for o in range(2):
+        for r in res[1:]:
+            within(r.value[0, o] - res[0].value[0, o], 0.0, math.hypot(r.stderr[0, o], res[0].stderr[0, o]))
