@@ -1,0 +1,230 @@
+/*
+ * mcrt.h -- C ABI of the MI355X photon-transport library (libmcrt.so).
+ *
+ * The library solves the three observables of the gCMCRT method (Lee et al.
+ * 2022, arXiv:2110.15640) by Monte Carlo radiative transfer with peel-off on
+ * 3D spherical lon-lat-radius grids (Sect. 2) or 1D plane-parallel slabs:
+ *   - geometric albedo spectra and scattered-light phase curves (Sect. 5.2,
+ *     the A_g and Phi(phi) equations),
+ *   - thermal emission spectra and phase curves (Sect. 5.3, L_i, L_p, I_p,
+ *     F_p equations),
+ *   - transmission spectra (Sect. 5.1, the (R_p/R_star)^2 equation and its
+ *     Monte Carlo estimator),
+ * with correlated-k opacities or Doppler-shifted high-resolution opacities
+ * (Sect. 7, the v_LOS and lambda_eff equations).  All device work runs in
+ * hand-written HIP kernels for gfx950; no torch types cross this boundary.
+ *
+ * Conventions (CGS): star at +x, rotation axis +z, longitude east-positive in
+ * [-pi, pi], latitude in [-pi/2, pi/2].  Cell (i, j, k) = (lon, lat, radius)
+ * is stored at c = (k*nlat + j)*nlon + i, k = 0 at the bottom (r = R0).
+ *
+ * Errors: every int-returning call returns MCRT_OK (0) or a negative code
+ * below; mcrt_last_error() then gives a message (thread-local, valid until
+ * the next failing call on that thread).  No exception crosses the ABI.
+ * Thread safety: one context may be used from several threads; uploads,
+ * frees and blocking solves are serialised by the context; submit / poll /
+ * wait / cancel are safe to call concurrently.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRT_OK 0
+#define MCRT_EINVAL (-1)     /* bad argument or input data            */
+#define MCRT_ENOMEM (-2)     /* device or host allocation failed      */
+#define MCRT_EDEVICE (-3)    /* HIP runtime error; context unusable   */
+#define MCRT_ENOTFOUND (-4)  /* unknown grid / opacity / ticket id    */
+#define MCRT_EBUDGET (-5)    /* would exceed the context's HBM budget */
+#define MCRT_EBUSY (-6)      /* object in use by queued work          */
+#define MCRT_ECANCELLED (-7) /* request was cancelled                 */
+
+#define MCRT_SPHERICAL 0
+#define MCRT_PLANE_PARALLEL 1
+
+#define MCRT_SURVIVAL 0   /* survival biasing (Sect. 4.4) */
+#define MCRT_CONTINUOUS 1 /* continuous absorption (Sect. 4.1) */
+
+#define MCRT_FP64 0  /* all arithmetic in FP64 */
+#define MCRT_MIXED 1 /* FP32 opacity, phase function, direction; FP64 roots, tau, tallies */
+
+#define MCRT_OPAC_CK 0
+#define MCRT_OPAC_HIRES 1
+
+#define MCRT_MODE_ALBEDO 0
+#define MCRT_MODE_EMISSION 1
+#define MCRT_MODE_TRANSMISSION 2
+
+/* Number of per-solve counters in mcrt_result.counters, in this order:
+ * escaped weight, weight reaching the surface, absorbed weight, net weight
+ * removed by Russian roulette, weight of capped packets, weight of lost
+ * packets, interactions, cell crossings, capped packets, lost packets,
+ * total initial weight. */
+#define MCRT_NCOUNTERS 11
+
+typedef struct mcrt_ctx mcrt_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold (0 = 90 % of the free memory).  The context
+ * owns every device buffer it allocates; mcrt_destroy frees them. */
+int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out);
+void mcrt_destroy(mcrt_ctx* ctx);
+const char* mcrt_last_error(void);
+/* Device memory currently held by the context, in bytes. */
+uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx);
+
+/* Atmosphere structure (Sect. 2 "spherical geometry grid"; GCM output in
+ * lat-lon form).  All arrays are host memory and are copied before return.
+ * r_edges[nlay+1]: radii [cm], strictly increasing, r_edges[0] = R0 (slab:
+ * heights [cm]); lat_edges[nlat+1] from -pi/2 to pi/2 and lon_edges[nlon+1]
+ * from -pi to pi, strictly increasing (ignored for the slab, where nlat =
+ * nlon = 1).  Per cell: T [K] float, P [bar] float, rho [g/cm^3] double,
+ * optional winds u (east), v (north), w (up) [cm/s] float (NULL = 0) and
+ * optional grey cloud opacities cld_ksca, cld_kabs [cm^2/g] and asymmetry
+ * cld_g float (NULL = no cloud).  omega_rot: solid-body rotation [1/s].
+ * Errors: EINVAL for non-monotone or incomplete edges, non-finite values,
+ * T <= 0, P <= 0, rho < 0, |g| >= 1; EBUDGET if the copy would exceed the
+ * budget (nothing is allocated then). */
+typedef struct {
+    int32_t geometry;
+    int32_t nlon, nlat, nlay;
+    const double* r_edges;
+    const double* lat_edges;
+    const double* lon_edges;
+    const float* T;
+    const float* P;
+    const double* rho;
+    const float* u;
+    const float* v;
+    const float* w;
+    const float* cld_ksca;
+    const float* cld_kabs;
+    const float* cld_g;
+    double omega_rot;
+} mcrt_grid_desc;
+
+int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* desc, int32_t* grid_id);
+int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id);
+
+/* Opacity table (Sect. 7).  kind = MCRT_OPAC_CK: pre-mixed k-table
+ * kappa[nspec][ng][nT][nP] [cm^2/g] interpolated bilinearly in (T, ln P) on
+ * ln kappa and clamped to the table, band-centre wavelengths lam_um[nspec],
+ * g_weights[ng] (sum 1).  kind = MCRT_OPAC_HIRES: kappa[nspec][nT][nP] on
+ * the log-uniform grid lam_n = lam_min_um exp(n dlnlam), ng = 1.  k_ray
+ * [nspec]: Rayleigh opacity [cm^2/g] at each spectral point.  Host arrays,
+ * copied.  Errors: EINVAL for kappa < 0 or non-finite, a non-increasing
+ * T/P grid, P_grid <= 0, weights not summing to 1 within 1e-9. */
+typedef struct {
+    int32_t kind;
+    int32_t nspec;
+    int32_t ng;
+    int32_t nT, nP;
+    const double* lam_um;
+    double lam_min_um;
+    double dlnlam;
+    const double* g_weights;
+    const double* T_grid;
+    const double* P_grid;
+    const float* kappa;
+    const double* k_ray;
+} mcrt_opacity_desc;
+
+int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* desc, int32_t* opac_id);
+int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
+
+/* Solve parameters.  Fill with mcrt_default_params() first.
+ * seed: Philox4x32-10 key; packet n at event e draws block b from counter
+ *   (lo32 n, hi32 n, e, b) under key (lo32 seed, hi32 seed ^ tag), tag = 0,
+ *   or 1 + spec*ng + g with decorrelate != 0.
+ * n_packets: packets per (spectral point, g) solve (albedo, emission).
+ * spec_idx[n_spec]: bands (CK) or table wavelength indices (HIRES); NULL =
+ *   all.  Every g-ordinate of a band is solved and weighted by g_weights.
+ * Observers: obs_phase[n_obs] -- albedo: phase angle a, o = (cos a, sin a, 0);
+ *   emission: orbital phase p, o = (cos l, sin l, 0), l = pi (1 - 2 p), so
+ *   p = 0.5 views the dayside.  obs_dir[n_obs][3] (unit vectors) overrides.
+ *   Slab albedo with n_obs = 0 uses the backscatter direction of each packet.
+ *   Transmission always observes along -x.  n_obs <= 8.
+ * scattering: 0 = emission peel-off only / no multiple scattering.
+ * absorption: MCRT_SURVIVAL or MCRT_CONTINUOUS.
+ * rr_threshold, rr_survive: Russian roulette (Sect. 4.5) below
+ *   rr_threshold * W0, survival probability rr_survive.
+ * emis_bias: hybrid emission bias fraction xi (Sect. 4.3).
+ * tau_vert_max: cells whose column optical depth above their top face
+ *   exceeds this do not emit (Sect. 4.6).
+ * tau_peel_max: peel-off rays stop (f = 0) beyond this optical depth.
+ * max_events: interactions per packet before it is stopped and counted.
+ * mu0: slab albedo incidence cosine; <= 0 samples the uniform-disk mu0.
+ * n_b, n_alpha: transmission strata in impact parameter and limb angle.
+ * r_star: stellar radius [cm] for transmission depths.
+ * precision: MCRT_FP64 or MCRT_MIXED.
+ * stream: hipStream_t to run on (NULL = the context's own stream).
+ * packet_dump: optional DEVICE buffer of doubles receiving each packet's
+ *   peel-off sum per observer, [solve][packet][observer] with solves ordered
+ *   (spec, g); NULL = none. */
+typedef struct {
+    uint64_t seed;
+    uint64_t n_packets;
+    int32_t decorrelate;
+    int32_t precision;
+    int32_t n_spec;
+    const int32_t* spec_idx;
+    int32_t n_obs;
+    const double* obs_phase;
+    const double* obs_dir;
+    int32_t scattering;
+    int32_t absorption;
+    double rr_threshold;
+    double rr_survive;
+    double emis_bias;
+    double tau_vert_max;
+    double tau_peel_max;
+    int64_t max_events;
+    double mu0;
+    int32_t n_b;
+    int32_t n_alpha;
+    double r_star;
+    void* stream;
+    double* packet_dump;
+} mcrt_solve_params;
+
+void mcrt_default_params(mcrt_solve_params* p);
+
+/* Results, caller-owned HOST arrays (any optional pointer may be NULL):
+ * value[n_spec][n_obs]     band value: A_g(phase) = pi E for albedo, F_p
+ *                          [erg/s/cm^2/cm] for emission, (R_p/R_star)^2 for
+ *                          transmission (n_obs = 1), summed over g with w_g;
+ * stderr_[n_spec][n_obs]   its Monte Carlo standard error (g independent);
+ * per_g[n_spec][ng][n_obs] value of each g-ordinate;
+ * sums[n_spec][ng][n_obs][2] raw (sum F, sum F^2) over packets;
+ * counters[n_spec][ng][MCRT_NCOUNTERS];
+ * l_tot[n_spec][ng]        emission: L_tot [erg/s/cm].
+ * elapsed_ms receives the device time of the solve. */
+typedef struct {
+    double* value;
+    double* stderr_;
+    double* per_g;
+    double* sums;
+    double* counters;
+    double* l_tot;
+    double elapsed_ms;
+} mcrt_result;
+
+/* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /
+ * opacity, e.g. emission on a slab), ENOTFOUND (ids), EBUDGET (scratch would
+ * exceed the budget), EDEVICE (HIP failure; the context is then poisoned). */
+int mcrt_solve_albedo(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
+                      const mcrt_solve_params* params, mcrt_result* result);
+int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
+                        const mcrt_solve_params* params, mcrt_result* result);
+int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
+                            const mcrt_solve_params* params, mcrt_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCRT_H */

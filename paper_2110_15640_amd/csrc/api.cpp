@@ -1,0 +1,862 @@
+// Host runtime of libmcrt.so: context, resident grids and opacity tables,
+// input validation, solve planning and the paper's post-processing of the
+// tallies into observables (Sect. 5).  Implements include/mcrt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mcrt.h"
+#include "mcrt_internal.hpp"
+
+using namespace mcrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GridRes {
+    GridDev dev{};
+    int ncell = 0;
+    std::vector<DevBuf> bufs;
+    size_t bytes = 0;
+    double r0 = 0.0, r_toa = 0.0;
+    int refs = 0;
+};
+
+struct OpacRes {
+    int kind = 0, nspec = 0, ng = 0, nT = 0, nP = 0;
+    double lam_min = 0.0, dlnlam = 0.0;
+    std::vector<double> lam_um, g_weights, k_ray;
+    double* lnk = nullptr;     // CK: [nspec][ng][nT][nP]; HIRES: [nT][nP][nlam]
+    double* T_grid = nullptr;  // [nT]
+    double* lnP_grid = nullptr;
+    double* k_ray_dev = nullptr;
+    std::vector<DevBuf> bufs;
+    size_t bytes = 0;
+    int refs = 0;
+};
+
+}  // namespace
+
+struct mcrt_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::mutex mu;
+    std::map<int32_t, std::unique_ptr<GridRes>> grids;
+    std::map<int32_t, std::unique_ptr<OpacRes>> opacs;
+    int32_t next_grid = 1, next_opac = 1;
+    bool poisoned = false;
+    // grow-only scratch arena per role
+    std::map<std::string, DevBuf> scratch;
+};
+
+namespace {
+
+int hip_check(mcrt_ctx* ctx, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MCRT_OK;
+    if (ctx) ctx->poisoned = true;
+    return fail(MCRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPTRY(expr)                                          \
+    do {                                                      \
+        int _rc = hip_check(ctx, (expr), #expr);              \
+        if (_rc != MCRT_OK) return _rc;                       \
+    } while (0)
+
+int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out)
+{
+    if (bytes == 0) bytes = 8;
+    if (ctx->in_use + bytes > ctx->budget)
+        return fail(MCRT_EBUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu in use)", bytes,
+                    (unsigned long long)ctx->in_use, (unsigned long long)ctx->budget);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MCRT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    out.p = p;
+    out.bytes = bytes;
+    ctx->in_use += bytes;
+    return MCRT_OK;
+}
+
+void dev_free(mcrt_ctx* ctx, DevBuf& b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        ctx->in_use -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Scratch buffer of at least `bytes` under `name` (grow-only, kept by ctx).
+int scratch(mcrt_ctx* ctx, const char* name, size_t bytes, void** out)
+{
+    DevBuf& b = ctx->scratch[name];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            HIPTRY(hipDeviceSynchronize());  // the old buffer may still be read by queued work
+            dev_free(ctx, b);
+        }
+        int rc = dev_alloc(ctx, bytes, b);
+        if (rc) return rc;
+    }
+    *out = b.p;
+    return MCRT_OK;
+}
+
+template <typename T>
+int upload(mcrt_ctx* ctx, std::vector<DevBuf>& bufs, size_t& total, const T* host, size_t n, T** dev)
+{
+    DevBuf b;
+    int rc = dev_alloc(ctx, n * sizeof(T), b);
+    if (rc) return rc;
+    bufs.push_back(b);
+    total += b.bytes;
+    HIPTRY(hipMemcpy(b.p, host, n * sizeof(T), hipMemcpyHostToDevice));
+    *dev = (T*)b.p;
+    return MCRT_OK;
+}
+
+bool finite_all(const double* a, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+bool finite_all(const float* a, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+bool increasing(const double* a, size_t n)
+{
+    for (size_t i = 1; i < n; ++i)
+        if (!(a[i] > a[i - 1])) return false;
+    return true;
+}
+
+int validate_grid(const mcrt_grid_desc* d)
+{
+    if (!d) return fail(MCRT_EINVAL, "grid descriptor is NULL");
+    if (d->geometry != MCRT_SPHERICAL && d->geometry != MCRT_PLANE_PARALLEL)
+        return fail(MCRT_EINVAL, "unknown geometry %d", d->geometry);
+    if (d->nlay < 1 || d->nlon < 1 || d->nlat < 1) return fail(MCRT_EINVAL, "grid dimensions must be >= 1");
+    if ((long long)d->nlon * d->nlat * d->nlay > (1LL << 31) - 1) return fail(MCRT_EINVAL, "grid too large");
+    if (!d->r_edges || !d->T || !d->P || !d->rho) return fail(MCRT_EINVAL, "r_edges, T, P and rho are required");
+    if (!finite_all(d->r_edges, d->nlay + 1) || !increasing(d->r_edges, d->nlay + 1))
+        return fail(MCRT_EINVAL, "r_edges must be finite and strictly increasing");
+    if (d->geometry == MCRT_PLANE_PARALLEL) {
+        if (d->nlon != 1 || d->nlat != 1) return fail(MCRT_EINVAL, "a slab has nlon = nlat = 1");
+    } else {
+        if (!(d->r_edges[0] > 0.0)) return fail(MCRT_EINVAL, "r_edges[0] (R0) must be > 0");
+        if (!d->lat_edges || !d->lon_edges) return fail(MCRT_EINVAL, "lat_edges and lon_edges are required");
+        if (!finite_all(d->lat_edges, d->nlat + 1) || !increasing(d->lat_edges, d->nlat + 1) ||
+            std::fabs(d->lat_edges[0] + kPi / 2) > 1e-12 || std::fabs(d->lat_edges[d->nlat] - kPi / 2) > 1e-12)
+            return fail(MCRT_EINVAL, "lat_edges must increase from -pi/2 to pi/2");
+        if (!finite_all(d->lon_edges, d->nlon + 1) || !increasing(d->lon_edges, d->nlon + 1) ||
+            std::fabs(d->lon_edges[0] + kPi) > 1e-12 || std::fabs(d->lon_edges[d->nlon] - kPi) > 1e-12)
+            return fail(MCRT_EINVAL, "lon_edges must increase from -pi to pi");
+    }
+    size_t n = (size_t)d->nlon * d->nlat * d->nlay;
+    for (size_t c = 0; c < n; ++c) {
+        if (!(std::isfinite(d->T[c]) && d->T[c] > 0.0f)) return fail(MCRT_EINVAL, "T[%zu] must be finite and > 0", c);
+        if (!(std::isfinite(d->P[c]) && d->P[c] > 0.0f)) return fail(MCRT_EINVAL, "P[%zu] must be finite and > 0", c);
+        if (!(std::isfinite(d->rho[c]) && d->rho[c] >= 0.0)) return fail(MCRT_EINVAL, "rho[%zu] must be finite and >= 0", c);
+    }
+    const float* wind[3] = {d->u, d->v, d->w};
+    for (int q = 0; q < 3; ++q)
+        if (wind[q] && !finite_all(wind[q], n)) return fail(MCRT_EINVAL, "winds must be finite");
+    if (d->cld_ksca || d->cld_kabs || d->cld_g) {
+        if (!(d->cld_ksca && d->cld_kabs && d->cld_g))
+            return fail(MCRT_EINVAL, "cloud needs cld_ksca, cld_kabs and cld_g together");
+        for (size_t c = 0; c < n; ++c) {
+            if (!(std::isfinite(d->cld_ksca[c]) && d->cld_ksca[c] >= 0.0f && std::isfinite(d->cld_kabs[c]) &&
+                  d->cld_kabs[c] >= 0.0f))
+                return fail(MCRT_EINVAL, "cloud opacities must be finite and >= 0");
+            if (!(std::fabs(d->cld_g[c]) < 1.0f)) return fail(MCRT_EINVAL, "cloud g must satisfy |g| < 1");
+        }
+    }
+    if (!std::isfinite(d->omega_rot)) return fail(MCRT_EINVAL, "omega_rot must be finite");
+    return MCRT_OK;
+}
+
+int validate_opacity(const mcrt_opacity_desc* d)
+{
+    if (!d) return fail(MCRT_EINVAL, "opacity descriptor is NULL");
+    if (d->kind != MCRT_OPAC_CK && d->kind != MCRT_OPAC_HIRES) return fail(MCRT_EINVAL, "unknown opacity kind");
+    if (d->nspec < 1 || d->ng < 1 || d->nT < 1 || d->nP < 1) return fail(MCRT_EINVAL, "table dimensions must be >= 1");
+    if (d->kind == MCRT_OPAC_HIRES && d->ng != 1) return fail(MCRT_EINVAL, "a high-resolution table has ng = 1");
+    if (!d->T_grid || !d->P_grid || !d->kappa || !d->k_ray) return fail(MCRT_EINVAL, "missing table arrays");
+    if (!finite_all(d->T_grid, d->nT) || !increasing(d->T_grid, d->nT) || !(d->T_grid[0] > 0.0))
+        return fail(MCRT_EINVAL, "T_grid must be positive and strictly increasing");
+    if (!finite_all(d->P_grid, d->nP) || !increasing(d->P_grid, d->nP) || !(d->P_grid[0] > 0.0))
+        return fail(MCRT_EINVAL, "P_grid must be positive and strictly increasing");
+    size_t n = (size_t)d->nspec * d->ng * d->nT * d->nP;
+    for (size_t i = 0; i < n; ++i)
+        if (!(std::isfinite(d->kappa[i]) && d->kappa[i] >= 0.0f))
+            return fail(MCRT_EINVAL, "kappa[%zu] must be finite and >= 0", i);
+    for (int s = 0; s < d->nspec; ++s)
+        if (!(std::isfinite(d->k_ray[s]) && d->k_ray[s] >= 0.0)) return fail(MCRT_EINVAL, "k_ray must be >= 0");
+    if (d->kind == MCRT_OPAC_CK) {
+        if (!d->lam_um || !d->g_weights) return fail(MCRT_EINVAL, "a ck table needs lam_um and g_weights");
+        double ws = 0.0;
+        for (int g = 0; g < d->ng; ++g) {
+            if (!(d->g_weights[g] >= 0.0)) return fail(MCRT_EINVAL, "g_weights must be >= 0");
+            ws += d->g_weights[g];
+        }
+        if (std::fabs(ws - 1.0) > 1e-9) return fail(MCRT_EINVAL, "g_weights must sum to 1 (got %.12g)", ws);
+        for (int s = 0; s < d->nspec; ++s)
+            if (!(d->lam_um[s] > 0.0 && std::isfinite(d->lam_um[s]))) return fail(MCRT_EINVAL, "lam_um must be > 0");
+    } else {
+        if (!(d->lam_min_um > 0.0) || !(d->dlnlam > 0.0) || !std::isfinite(d->lam_min_um) || !std::isfinite(d->dlnlam))
+            return fail(MCRT_EINVAL, "lam_min_um and dlnlam must be > 0");
+    }
+    return MCRT_OK;
+}
+
+GridRes* find_grid(mcrt_ctx* ctx, int32_t id)
+{
+    auto it = ctx->grids.find(id);
+    return it == ctx->grids.end() ? nullptr : it->second.get();
+}
+
+OpacRes* find_opac(mcrt_ctx* ctx, int32_t id)
+{
+    auto it = ctx->opacs.find(id);
+    return it == ctx->opacs.end() ? nullptr : it->second.get();
+}
+
+struct SolvePlan {
+    std::vector<int> specs;
+    int ng = 1;
+    int n_out = 0;
+    int n_obs = 0;
+    std::vector<double> obs;  // 3 * n_obs
+    hipStream_t stream = nullptr;
+};
+
+int plan_common(mcrt_ctx* ctx, GridRes* g, OpacRes* op, const mcrt_solve_params* p, int mode, SolvePlan& pl)
+{
+    if (!p) return fail(MCRT_EINVAL, "params is NULL");
+    if (p->precision != MCRT_FP64 && p->precision != MCRT_MIXED) return fail(MCRT_EINVAL, "unknown precision");
+    if (p->precision == MCRT_MIXED) return fail(MCRT_EINVAL, "MCRT_MIXED is not available in this build");
+    if (p->n_spec < 0) return fail(MCRT_EINVAL, "n_spec < 0");
+    int nspec_tab = op->nspec;
+    if (p->spec_idx) {
+        for (int s = 0; s < p->n_spec; ++s) {
+            if (p->spec_idx[s] < 0 || p->spec_idx[s] >= nspec_tab)
+                return fail(MCRT_EINVAL, "spec_idx[%d] = %d out of range", s, p->spec_idx[s]);
+            pl.specs.push_back(p->spec_idx[s]);
+        }
+    } else {
+        for (int s = 0; s < nspec_tab; ++s) pl.specs.push_back(s);
+    }
+    if (pl.specs.empty()) return fail(MCRT_EINVAL, "no spectral points selected");
+    pl.ng = op->kind == MCRT_OPAC_CK ? op->ng : 1;
+    pl.stream = p->stream ? (hipStream_t)p->stream : ctx->stream;
+    if (mode == MCRT_MODE_TRANSMISSION) {
+        if (g->dev.geom != 0) return fail(MCRT_EINVAL, "transmission needs a spherical grid");
+        if (p->n_b < 1 || p->n_alpha < 1 || (long long)p->n_b * p->n_alpha > (1LL << 30))
+            return fail(MCRT_EINVAL, "n_b and n_alpha must be >= 1 with n_b * n_alpha <= 2^30");
+        if (!(p->r_star > 0.0)) return fail(MCRT_EINVAL, "r_star must be > 0");
+        pl.n_out = 1;
+        return MCRT_OK;
+    }
+    if (p->n_packets < 1 || p->n_packets > (1ULL << 40)) return fail(MCRT_EINVAL, "n_packets must be in [1, 2^40]");
+    if (p->n_obs < 0 || p->n_obs > kMaxObs) return fail(MCRT_EINVAL, "n_obs must be in [0, %d]", kMaxObs);
+    if (!(p->rr_survive > 0.0 && p->rr_survive <= 1.0)) return fail(MCRT_EINVAL, "rr_survive must be in (0, 1]");
+    if (!(p->rr_threshold >= 0.0) || !std::isfinite(p->rr_threshold)) return fail(MCRT_EINVAL, "rr_threshold >= 0");
+    if (!(p->emis_bias >= 0.0 && p->emis_bias <= 1.0)) return fail(MCRT_EINVAL, "emis_bias must be in [0, 1]");
+    if (!(p->tau_peel_max > 0.0)) return fail(MCRT_EINVAL, "tau_peel_max must be > 0");
+    if (!(p->tau_vert_max >= 0.0)) return fail(MCRT_EINVAL, "tau_vert_max must be >= 0");
+    if (p->max_events < 1) return fail(MCRT_EINVAL, "max_events must be >= 1");
+    if (p->absorption != MCRT_SURVIVAL && p->absorption != MCRT_CONTINUOUS) return fail(MCRT_EINVAL, "bad absorption");
+    if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
+    if (mode == MCRT_MODE_EMISSION && g->dev.geom != 0) return fail(MCRT_EINVAL, "emission needs a spherical grid");
+    if (p->n_obs == 0) {
+        if (!(mode == MCRT_MODE_ALBEDO && g->dev.geom == 1))
+            return fail(MCRT_EINVAL, "n_obs = 0 is only allowed for slab albedo (backscatter)");
+        pl.n_obs = 0;
+        pl.n_out = 1;
+        return MCRT_OK;
+    }
+    if (!p->obs_dir && !p->obs_phase) return fail(MCRT_EINVAL, "observers need obs_phase or obs_dir");
+    pl.n_obs = p->n_obs;
+    pl.n_out = p->n_obs;
+    for (int o = 0; o < p->n_obs; ++o) {
+        double v[3];
+        if (p->obs_dir) {
+            v[0] = p->obs_dir[3 * o];
+            v[1] = p->obs_dir[3 * o + 1];
+            v[2] = p->obs_dir[3 * o + 2];
+            double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(std::fabs(n - 1.0) < 1e-9)) return fail(MCRT_EINVAL, "obs_dir[%d] is not a unit vector", o);
+        } else {
+            double ph = p->obs_phase[o];
+            if (!std::isfinite(ph)) return fail(MCRT_EINVAL, "obs_phase must be finite");
+            double a = mode == MCRT_MODE_ALBEDO ? ph : kPi * (1.0 - 2.0 * ph);
+            v[0] = std::cos(a);
+            v[1] = std::sin(a);
+            v[2] = 0.0;
+        }
+        pl.obs.insert(pl.obs.end(), v, v + 3);
+    }
+    return MCRT_OK;
+}
+
+void fill_results(const SolvePlan& pl, const std::vector<double>& perg_val, const std::vector<double>& perg_se,
+                  const std::vector<double>& g_w, const std::vector<double>& sums, int row_w,
+                  const std::vector<double>& counters, const std::vector<double>& ltot, mcrt_result* r)
+{
+    int ns = (int)pl.specs.size(), ng = pl.ng, no = pl.n_out;
+    for (int s = 0; s < ns; ++s)
+        for (int o = 0; o < no; ++o) {
+            double v = 0.0, e2 = 0.0;
+            for (int g = 0; g < ng; ++g) {
+                double w = g_w[g];
+                size_t i = ((size_t)s * ng + g) * no + o;
+                v += w * perg_val[i];
+                e2 += w * w * perg_se[i] * perg_se[i];
+            }
+            if (r->value) r->value[(size_t)s * no + o] = v;
+            if (r->stderr_) r->stderr_[(size_t)s * no + o] = std::sqrt(e2);
+        }
+    if (r->per_g) std::copy(perg_val.begin(), perg_val.end(), r->per_g);
+    if (r->sums) {
+        for (size_t sg = 0; sg < (size_t)ns * ng; ++sg)
+            for (int o = 0; o < no; ++o) {
+                r->sums[(sg * no + o) * 2] = sums[sg * row_w + 2 * o];
+                r->sums[(sg * no + o) * 2 + 1] = sums[sg * row_w + 2 * o + 1];
+            }
+    }
+    if (r->counters) std::copy(counters.begin(), counters.end(), r->counters);
+    if (r->l_tot) std::copy(ltot.begin(), ltot.end(), r->l_tot);
+}
+
+int finish_timing(mcrt_ctx* ctx, hipStream_t st, mcrt_result* r)
+{
+    HIPTRY(hipEventRecord(ctx->ev1, st));
+    HIPTRY(hipEventSynchronize(ctx->ev1));
+    float ms = 0.0f;
+    HIPTRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (r) r->elapsed_ms = ms;
+    return MCRT_OK;
+}
+
+// Albedo and emission: per (spec, g) solve: optics -> [sources] -> transport
+// -> fixed-order tally reduction into one row of the device sums table.
+int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res, int mode)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    if (!res) return fail(MCRT_EINVAL, "result is NULL");
+    GridRes* g = find_grid(ctx, gid);
+    if (!g) return fail(MCRT_ENOTFOUND, "grid %d not found", gid);
+    OpacRes* op = find_opac(ctx, oid);
+    if (!op) return fail(MCRT_ENOTFOUND, "opacity %d not found", oid);
+    SolvePlan pl;
+    int rc = plan_common(ctx, g, op, p, mode, pl);
+    if (rc) return rc;
+    if (op->kind == MCRT_OPAC_HIRES && mode == MCRT_MODE_ALBEDO)
+        return fail(MCRT_EINVAL, "albedo solves take a correlated-k table");
+    if (op->kind == MCRT_OPAC_HIRES && pl.n_out != 1)
+        return fail(MCRT_EINVAL, "high-resolution emission is Doppler-shifted per observer: pass one observer per call");
+    HIPTRY(hipSetDevice(ctx->device));
+    hipStream_t st = pl.stream;
+    const int ncell = g->ncell;
+    const int ns = (int)pl.specs.size(), ng = pl.ng, nsolve = ns * ng;
+    const int row_w = 2 * pl.n_out + kNCounters + 2;  // + (L_tot, N_emit)
+    const int part_w = 2 * pl.n_out + kNCounters;
+    const uint64_t N = p->n_packets;
+    const int tb = transport_block_size();
+    const long long nblocks_ll = (long long)((N + tb - 1) / tb);
+    if (nblocks_ll > (1LL << 31) - 1) return fail(MCRT_EINVAL, "too many packets for one launch");
+    const int nblocks = (int)nblocks_ll;
+
+    void *v_opt, *v_part, *v_sums, *v_L, *v_cdf, *v_wb, *v_es, *v_shift = nullptr;
+    if ((rc = scratch(ctx, "optics", sizeof(double) * 5 * (size_t)ncell, &v_opt))) return rc;
+    if ((rc = scratch(ctx, "partials", sizeof(double) * (size_t)nblocks * part_w, &v_part))) return rc;
+    if ((rc = scratch(ctx, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if (mode == MCRT_MODE_EMISSION) {
+        if ((rc = scratch(ctx, "L", sizeof(double) * (size_t)ncell, &v_L))) return rc;
+        if ((rc = scratch(ctx, "cdf", sizeof(double) * (size_t)ncell, &v_cdf))) return rc;
+        if ((rc = scratch(ctx, "wbirth", sizeof(double) * (size_t)ncell, &v_wb))) return rc;
+        if ((rc = scratch(ctx, "em_scratch", sizeof(double) * emission_scratch_doubles(ncell), &v_es))) return rc;
+    }
+    if (op->kind == MCRT_OPAC_HIRES)
+        if ((rc = scratch(ctx, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+    double* opt = (double*)v_opt;
+    OpticsDev<double> od{opt, opt + ncell, opt + 2 * (size_t)ncell, opt + 3 * (size_t)ncell, opt + 4 * (size_t)ncell};
+    double* sums = (double*)v_sums;
+
+    TransportArgs A{};
+    A.seed = p->seed;
+    A.n_packets = N;
+    A.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
+    A.scattering = p->scattering ? 1 : 0;
+    A.absorption = p->absorption;
+    A.n_obs = pl.n_obs;
+    A.n_out = pl.n_out;
+    A.max_events = p->max_events;
+    A.rr_threshold = p->rr_threshold;
+    A.rr_survive = p->rr_survive;
+    A.tau_peel_max = p->tau_peel_max;
+    A.mu0 = p->mu0;
+    A.r_toa = g->r_toa;
+    for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[q] = pl.obs[q];
+    A.partials = (double*)v_part;
+    if (mode == MCRT_MODE_EMISSION) {
+        A.cdf = (double*)v_cdf;
+        A.wbirth = (double*)v_wb;
+    }
+
+    HIPTRY(hipEventRecord(ctx->ev0, st));
+    HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
+    if (op->kind == MCRT_OPAC_HIRES)
+        launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
+    for (int s = 0; s < ns; ++s) {
+        int b = pl.specs[s];
+        for (int gi = 0; gi < ng; ++gi) {
+            int sg = s * ng + gi;
+            if (op->kind == MCRT_OPAC_CK) {
+                const double* tab = op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP;
+                launch_ck_optics(g->dev, ncell, tab, op->nT, op->nP, op->T_grid, op->lnP_grid, op->k_ray[b], od, 1, st);
+            } else {
+                launch_hires_optics(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
+                                    op->k_ray[b], (double*)v_shift, b, od, st);
+            }
+            double* row = sums + (size_t)sg * row_w;
+            if (mode == MCRT_MODE_EMISSION) {
+                double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
+                launch_emission_sources(g->dev, od, lam * 1e-4, p->tau_vert_max, p->emis_bias, (double*)v_L,
+                                        (double*)v_cdf, (double*)v_wb, (double*)v_es, row + part_w, st);
+            }
+            A.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
+            A.packet_dump = p->packet_dump ? p->packet_dump + (size_t)sg * N * pl.n_out : nullptr;
+            launch_transport(g->dev, od, A, nblocks, st);
+            launch_reduce_partials((double*)v_part, nblocks, part_w, row, st);
+        }
+    }
+    HIPTRY(hipGetLastError());
+    std::vector<double> hs((size_t)nsolve * row_w);
+    HIPTRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    if ((rc = finish_timing(ctx, st, res))) return rc;
+
+    // Post-processing (Sect. 5.2 A_g = pi E; Sect. 5.3 F_p = L_tot/(N R_TOA^2) sum F)
+    const int no = pl.n_out;
+    std::vector<double> val((size_t)nsolve * no), se((size_t)nsolve * no), cnt((size_t)nsolve * kNCounters),
+        ltot(nsolve);
+    const double Nd = (double)N;
+    for (int sg = 0; sg < nsolve; ++sg) {
+        const double* row = hs.data() + (size_t)sg * row_w;
+        double scale;
+        if (mode == MCRT_MODE_ALBEDO) {
+            scale = kPi;
+        } else {
+            ltot[sg] = row[part_w];
+            scale = row[part_w] / (g->r_toa * g->r_toa);
+        }
+        for (int o = 0; o < no; ++o) {
+            double m = row[2 * o] / Nd;
+            double var = std::max(row[2 * o + 1] / Nd - m * m, 0.0) / Nd;
+            val[(size_t)sg * no + o] = scale * m;
+            se[(size_t)sg * no + o] = scale * std::sqrt(var);
+        }
+    }
+    // counters sit right after the 2*n_out sums
+    for (int sg = 0; sg < nsolve; ++sg)
+        for (int t = 0; t < kNCounters; ++t)
+            cnt[(size_t)sg * kNCounters + t] = hs[(size_t)sg * row_w + 2 * no + t];
+    std::vector<double> gw = op->kind == MCRT_OPAC_CK ? op->g_weights : std::vector<double>{1.0};
+    std::vector<double> sumrows(hs);
+    fill_results(pl, val, se, gw, sumrows, row_w, cnt, ltot, res);
+    return MCRT_OK;
+}
+
+// Transmission: chord geometry once, then per block of up to 64 spectral
+// rows: alpha gather -> chord optical depths -> fixed-order tally.
+int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    if (!res) return fail(MCRT_EINVAL, "result is NULL");
+    GridRes* g = find_grid(ctx, gid);
+    if (!g) return fail(MCRT_ENOTFOUND, "grid %d not found", gid);
+    OpacRes* op = find_opac(ctx, oid);
+    if (!op) return fail(MCRT_ENOTFOUND, "opacity %d not found", oid);
+    SolvePlan pl;
+    int rc = plan_common(ctx, g, op, p, MCRT_MODE_TRANSMISSION, pl);
+    if (rc) return rc;
+    HIPTRY(hipSetDevice(ctx->device));
+    hipStream_t st = pl.stream;
+    const int ncell = g->ncell;
+    const int nch = p->n_b * p->n_alpha;
+    const int ns = (int)pl.specs.size(), ng = pl.ng;
+    const int nrow = ns * ng;
+    const int kSlot = 64;
+    const int nslot_max = std::min(kSlot, nrow);
+    void *v_cnt, *v_off, *v_b, *v_ok, *v_alpha, *v_part, *v_sums, *v_shift = nullptr, *v_nl = nullptr;
+    if ((rc = scratch(ctx, "chord_cnt", sizeof(int) * (size_t)nch, &v_cnt))) return rc;
+    if ((rc = scratch(ctx, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
+    if ((rc = scratch(ctx, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
+    if ((rc = scratch(ctx, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
+    if ((rc = scratch(ctx, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
+    int tblocks = chord_tau_blocks(nch);
+    if ((rc = scratch(ctx, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
+    if ((rc = scratch(ctx, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
+    if (op->kind == MCRT_OPAC_HIRES) {
+        if ((rc = scratch(ctx, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+        if ((rc = scratch(ctx, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
+    }
+    const uint32_t tag = 0;  // chords are common to all spectral points
+    HIPTRY(hipEventRecord(ctx->ev0, st));
+    launch_chord_count(g->dev, p->n_b, p->n_alpha, p->seed, tag, (int*)v_cnt, st);
+    launch_exclusive_scan_int((int*)v_cnt, (long long*)v_off, nch, nullptr, st);
+    long long nseg = 0;
+    HIPTRY(hipMemcpyAsync(&nseg, (long long*)v_off + nch, sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    void *v_sc, *v_sl;
+    if ((rc = scratch(ctx, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
+    if ((rc = scratch(ctx, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
+    launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
+                      (double*)v_b, (int*)v_ok, st);
+    if (op->kind == MCRT_OPAC_HIRES) {
+        launch_doppler_shift(g->dev, -1.0, 0.0, 0.0, op->dlnlam, (double*)v_shift, st);
+        HIPTRY(hipMemcpyAsync(v_nl, pl.specs.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    }
+    double* alpha = (double*)v_alpha;
+    for (int r0 = 0; r0 < nrow; r0 += kSlot) {
+        int nslot = std::min(kSlot, nrow - r0);
+        if (op->kind == MCRT_OPAC_CK) {
+            for (int q = 0; q < nslot; ++q) {
+                int rr = r0 + q, b = pl.specs[rr / ng], gi = rr % ng;
+                const double* tab = op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP;
+                OpticsDev<double> od{alpha + q, nullptr, nullptr, nullptr, nullptr};
+                launch_ck_optics(g->dev, ncell, tab, op->nT, op->nP, op->T_grid, op->lnP_grid, op->k_ray[b], od, nslot,
+                                 st);
+            }
+        } else {
+            launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
+                                     op->k_ray_dev, (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
+        }
+        launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok, alpha,
+                         nslot, (double*)v_part, tblocks, st);
+        launch_reduce_partials((double*)v_part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
+    }
+    HIPTRY(hipGetLastError());
+    std::vector<double> hs((size_t)nrow * 2);
+    HIPTRY(hipMemcpyAsync(hs.data(), v_sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    if ((rc = finish_timing(ctx, st, res))) return rc;
+
+    // (R_p/R*)^2 = (R0^2 + 2 <I>)/R*^2, <I> = (R_TOA - R0)/N sum (1 - e^-tau) b  (Sect. 5.1)
+    const double dr = g->r_toa - g->r0, Nd = (double)nch, rs2 = p->r_star * p->r_star;
+    std::vector<double> val(nrow), se(nrow), cnt((size_t)nrow * kNCounters, 0.0), ltot(nrow, 0.0);
+    for (int r = 0; r < nrow; ++r) {
+        double s1 = hs[2 * r], s2 = hs[2 * r + 1];
+        double I = dr * s1 / Nd;
+        double m = s1 / Nd;
+        double var = std::max(s2 / Nd - m * m, 0.0) / Nd;
+        val[r] = (g->r0 * g->r0 + 2.0 * I) / rs2;
+        se[r] = 2.0 * dr * std::sqrt(var) / rs2;
+    }
+    std::vector<double> gw = op->kind == MCRT_OPAC_CK ? op->g_weights : std::vector<double>{1.0};
+    // sums rows are [row][2] already (n_out = 1)
+    std::vector<double> sumrows(hs);
+    fill_results(pl, val, se, gw, sumrows, 2, cnt, ltot, res);
+    return MCRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mcrt_last_error(void) { return g_err.c_str(); }
+
+int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
+{
+    if (!out) return fail(MCRT_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(MCRT_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(MCRT_EINVAL, "device %d out of range (have %d)", device, ndev);
+    std::unique_ptr<mcrt_ctx> ctx(new mcrt_ctx());
+    ctx->device = device;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    size_t fr = 0, tot = 0;
+    e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    *out = ctx.release();
+    return MCRT_OK;
+}
+
+void mcrt_destroy(mcrt_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->grids)
+        for (auto& b : kv.second->bufs) dev_free(ctx, b);
+    for (auto& kv : ctx->opacs)
+        for (auto& b : kv.second->bufs) dev_free(ctx, b);
+    for (auto& kv : ctx->scratch) dev_free(ctx, kv.second);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+
+void mcrt_default_params(mcrt_solve_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->seed = 211015640ULL;
+    p->n_packets = 100000;
+    p->precision = MCRT_FP64;
+    p->scattering = 1;
+    p->absorption = MCRT_SURVIVAL;
+    p->rr_threshold = 1e-3;
+    p->rr_survive = 0.1;
+    p->emis_bias = 0.5;
+    p->tau_vert_max = 30.0;
+    p->tau_peel_max = 50.0;
+    p->max_events = 1000000;
+    p->mu0 = 0.0;
+    p->n_b = 256;
+    p->n_alpha = 360;
+    p->r_star = 6.957e10;
+}
+
+int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, int32_t* grid_id)
+{
+    if (!ctx || !grid_id) return fail(MCRT_EINVAL, "ctx and grid_id are required");
+    int rc = validate_grid(d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    HIPTRY(hipSetDevice(ctx->device));
+    const bool slab = d->geometry == MCRT_PLANE_PARALLEL;
+    const int nlon = d->nlon, nlat = d->nlat, nlay = d->nlay;
+    const size_t n = (size_t)nlon * nlat * nlay;
+    // host-side edge tables
+    std::vector<double> lat(nlat + 1), lon(nlon + 1);
+    if (slab) {
+        lat = {-kPi / 2, kPi / 2};
+        lon = {-kPi, kPi};
+    } else {
+        std::copy(d->lat_edges, d->lat_edges + nlat + 1, lat.begin());
+        std::copy(d->lon_edges, d->lon_edges + nlon + 1, lon.begin());
+    }
+    std::vector<double> lc2(nlat + 1), ls2(nlat + 1), lsn(nlat + 1), los(nlon), loc(nlon), volr(nlay);
+    for (int e = 0; e <= nlat; ++e) {
+        double c = std::cos(lat[e]), s = std::sin(lat[e]);
+        lc2[e] = c * c;
+        ls2[e] = s * s;
+        lsn[e] = s;
+    }
+    for (int e = 0; e < nlon; ++e) {
+        los[e] = std::sin(lon[e]);
+        loc[e] = std::cos(lon[e]);
+    }
+    for (int k = 0; k < nlay; ++k)
+        volr[k] = (std::pow(d->r_edges[k + 1], 3.0) - std::pow(d->r_edges[k], 3.0)) / 3.0;
+
+    std::unique_ptr<GridRes> G(new GridRes());
+    GridDev& gd = G->dev;
+    gd.geom = slab ? 1 : 0;
+    gd.nlon = nlon;
+    gd.nlat = nlat;
+    gd.nlay = nlay;
+    gd.max_cross = 4 * (nlay + nlat + nlon) + 16;
+    gd.omega_rot = d->omega_rot;
+    auto cleanup = [&](int code) {
+        for (auto& b : G->bufs) dev_free(ctx, b);
+        return code;
+    };
+    double* dp;
+    float* fp;
+#define UP(field, host, cnt, ptr)                                            \
+    do {                                                                     \
+        int _r = upload(ctx, G->bufs, G->bytes, host, cnt, &ptr);            \
+        if (_r) return cleanup(_r);                                          \
+        gd.field = ptr;                                                      \
+    } while (0)
+    UP(r, d->r_edges, (size_t)nlay + 1, dp);
+    UP(lat, lat.data(), lat.size(), dp);
+    UP(lat_c2, lc2.data(), lc2.size(), dp);
+    UP(lat_s2, ls2.data(), ls2.size(), dp);
+    UP(lat_sin, lsn.data(), lsn.size(), dp);
+    UP(lon, lon.data(), lon.size(), dp);
+    UP(lon_s, los.data(), los.size(), dp);
+    UP(lon_c, loc.data(), loc.size(), dp);
+    UP(vol_r, volr.data(), volr.size(), dp);
+    UP(T, d->T, n, fp);
+    UP(P, d->P, n, fp);
+    UP(rho, d->rho, n, dp);
+    if (d->u) UP(u, d->u, n, fp);
+    if (d->v) UP(v, d->v, n, fp);
+    if (d->w) UP(w, d->w, n, fp);
+    if (d->cld_ksca) {
+        UP(cld_ksca, d->cld_ksca, n, fp);
+        UP(cld_kabs, d->cld_kabs, n, fp);
+        UP(cld_g, d->cld_g, n, fp);
+    }
+#undef UP
+    G->ncell = (int)n;
+    G->r0 = d->r_edges[0];
+    G->r_toa = d->r_edges[nlay];
+    int32_t id = ctx->next_grid++;
+    ctx->grids[id] = std::move(G);
+    *grid_id = id;
+    return MCRT_OK;
+}
+
+int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->grids.find(grid_id);
+    if (it == ctx->grids.end()) return fail(MCRT_ENOTFOUND, "grid %d not found", grid_id);
+    if (it->second->refs > 0) return fail(MCRT_EBUSY, "grid %d is used by queued work", grid_id);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& b : it->second->bufs) dev_free(ctx, b);
+    ctx->grids.erase(it);
+    return MCRT_OK;
+}
+
+int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, int32_t* opac_id)
+{
+    if (!ctx || !opac_id) return fail(MCRT_EINVAL, "ctx and opac_id are required");
+    int rc = validate_opacity(d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    HIPTRY(hipSetDevice(ctx->device));
+    std::unique_ptr<OpacRes> O(new OpacRes());
+    O->kind = d->kind;
+    O->nspec = d->nspec;
+    O->ng = d->ng;
+    O->nT = d->nT;
+    O->nP = d->nP;
+    O->lam_min = d->lam_min_um;
+    O->dlnlam = d->dlnlam;
+    O->k_ray.assign(d->k_ray, d->k_ray + d->nspec);
+    if (d->kind == MCRT_OPAC_CK) {
+        O->lam_um.assign(d->lam_um, d->lam_um + d->nspec);
+        O->g_weights.assign(d->g_weights, d->g_weights + d->ng);
+    } else {
+        O->g_weights = {1.0};
+    }
+    const size_t nTP = (size_t)d->nT * d->nP;
+    const size_t ntab = (size_t)d->nspec * d->ng * nTP;
+    std::vector<double> lnk(ntab);
+    if (d->kind == MCRT_OPAC_CK) {
+        for (size_t i = 0; i < ntab; ++i) lnk[i] = d->kappa[i] > 0.0f ? std::log((double)d->kappa[i]) : -INFINITY;
+    } else {
+        // [lam][T][P] -> [T][P][lam]: consecutive wavelengths are contiguous
+        const size_t nl = (size_t)d->nspec;
+        for (size_t l = 0; l < nl; ++l)
+            for (size_t tp = 0; tp < nTP; ++tp) {
+                float kv = d->kappa[l * nTP + tp];
+                lnk[tp * nl + l] = kv > 0.0f ? std::log((double)kv) : -INFINITY;
+            }
+    }
+    std::vector<double> lnP(d->nP);
+    for (int q = 0; q < d->nP; ++q) lnP[q] = std::log(d->P_grid[q]);
+    auto cleanup = [&](int code) {
+        for (auto& b : O->bufs) dev_free(ctx, b);
+        return code;
+    };
+    if ((rc = upload(ctx, O->bufs, O->bytes, lnk.data(), lnk.size(), &O->lnk))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, d->T_grid, (size_t)d->nT, &O->T_grid))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, lnP.data(), lnP.size(), &O->lnP_grid))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, d->k_ray, (size_t)d->nspec, &O->k_ray_dev))) return cleanup(rc);
+    int32_t id = ctx->next_opac++;
+    ctx->opacs[id] = std::move(O);
+    *opac_id = id;
+    return MCRT_OK;
+}
+
+int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->opacs.find(opac_id);
+    if (it == ctx->opacs.end()) return fail(MCRT_ENOTFOUND, "opacity %d not found", opac_id);
+    if (it->second->refs > 0) return fail(MCRT_EBUSY, "opacity %d is used by queued work", opac_id);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& b : it->second->bufs) dev_free(ctx, b);
+    ctx->opacs.erase(it);
+    return MCRT_OK;
+}
+
+int mcrt_solve_albedo(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
+                      mcrt_result* result)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    return solve_packets(ctx, grid_id, opac_id, params, result, MCRT_MODE_ALBEDO);
+}
+
+int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
+                        mcrt_result* result)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    return solve_packets(ctx, grid_id, opac_id, params, result, MCRT_MODE_EMISSION);
+}
+
+int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
+                            mcrt_result* result)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    return solve_chords(ctx, grid_id, opac_id, params, result);
+}
+
+}  // extern "C"

@@ -1,0 +1,1168 @@
+// HIP kernels of the photon-transport path for gfx950 (CDNA4, wave64).
+//
+// K1 ck_optics        correlated-k gather to per-cell extinction, albedo,
+//                     gas-scattering probability (Sect. 7, pre-mixed tables
+//                     interpolated to the T-p structure; continuum at the band
+//                     centre)
+// K2 doppler/hires    line-of-sight velocity and Doppler-shifted
+//                     high-resolution opacity (Sect. 7, v_LOS and lambda_eff)
+// K3 emission sources cell luminosity L_i = 4 pi V_i rho kappa_abs B(T_i)
+//                     (Sect. 5.3), tau_vert cut (Sect. 4.6), hybrid bias CDF
+//                     (Sect. 4.3)
+// K4 transport        packet histories with peel-off toward every observer
+//                     (Sect. 2-4); one lane per packet
+// K5 chords           transmission chord geometry and per-wavelength optical
+//                     depth (Sect. 5.1)
+// K6 reductions       deterministic fixed-order FP64 sums of block partials
+//
+// All FP64 arithmetic is written in the order of its definition and built
+// with -ffp-contract=off so that results equal an independent FP64 CPU
+// evaluation up to the last-bit differences of the math library.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mcrt_internal.hpp"
+
+namespace mcrt {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kH = 6.62607015e-27;
+constexpr double kC = 2.99792458e10;
+constexpr double kKB = 1.380649e-16;
+constexpr int kTB = 256;  // threads per block for the per-packet kernels
+
+// ---------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon et al. 2011): counter (packet lo, packet hi, event,
+// block), key (seed lo, seed hi ^ tag).
+struct U2 {
+    double a, b;
+};
+
+__device__ __forceinline__ U2 draw(uint64_t seed, uint32_t tag, uint64_t packet, uint32_t event,
+                                   uint32_t block)
+{
+    uint32_t c0 = (uint32_t)packet, c1 = (uint32_t)(packet >> 32), c2 = event, c3 = block;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ tag;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    U2 u;
+    uint64_t ma = ((uint64_t)c0 << 20) | (uint64_t)(c1 >> 12);
+    uint64_t mb = ((uint64_t)c2 << 20) | (uint64_t)(c3 >> 12);
+    u.a = ((double)ma + 0.5) * (1.0 / 4503599627370496.0);
+    u.b = ((double)mb + 0.5) * (1.0 / 4503599627370496.0);
+    return u;
+}
+
+// ---------------------------------------------------------------- phase functions
+__device__ __forceinline__ double p_rayleigh(double mu) { return 0.75 * (1.0 + mu * mu); }
+
+__device__ __forceinline__ double p_hg(double mu, double g)
+{
+    if (fabs(g) < 1e-6) return 1.0;
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (den * sqrt(den));
+}
+
+// Rayleigh: Cardano root of mu^3 + 3 mu = 2 (4 zeta - 2), the inverse of the
+// CDF (mu^3 + 3 mu + 4)/8 of the normalised phase function.
+__device__ __forceinline__ double sample_rayleigh(double z)
+{
+    double q = 4.0 * z - 2.0;
+    double u = cbrt(q + sqrt(q * q + 1.0));
+    double mu = u - 1.0 / u;
+    return fmin(fmax(mu, -1.0), 1.0);
+}
+
+__device__ __forceinline__ double sample_hg(double z, double g)
+{
+    double mu;
+    if (fabs(g) < 1e-6) {
+        mu = 2.0 * z - 1.0;
+    } else {
+        double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * z);
+        mu = (1.0 + g * g - t * t) / (2.0 * g);
+    }
+    return fmin(fmax(mu, -1.0), 1.0);
+}
+
+__device__ __forceinline__ void rotate_dir(double& dx, double& dy, double& dz, double mu, double psi)
+{
+    double st = sqrt(fmax(1.0 - mu * mu, 0.0));
+    double cp = cos(psi), sp = sin(psi);
+    double nx, ny, nz;
+    if (fabs(dz) < 0.99999) {
+        double t = sqrt(1.0 - dz * dz);
+        nx = st * (dx * dz * cp - dy * sp) / t + dx * mu;
+        ny = st * (dy * dz * cp + dx * sp) / t + dy * mu;
+        nz = -st * cp * t + dz * mu;
+    } else {
+        double sgn = dz >= 0.0 ? 1.0 : -1.0;
+        nx = st * cp;
+        ny = st * sp;
+        nz = sgn * mu;
+    }
+    double n = sqrt(nx * nx + ny * ny + nz * nz);
+    dx = nx / n;
+    dy = ny / n;
+    dz = nz / n;
+}
+
+// ---------------------------------------------------------------- geometry
+enum { F_NONE = -1, F_OUT = 0, F_IN = 1, F_LATLO = 2, F_LATHI = 3, F_LONLO = 4, F_LONHI = 5 };
+enum { T_INTERACT = 0, T_ESCAPE = 1, T_SURFACE = 2, T_LOST = 3 };
+
+struct Ray {
+    double x, y, z;
+    int i, j, k;
+    int ef;
+};
+
+__device__ __forceinline__ int find_edge(const double* e, int n, double x)
+{
+    // largest m in [0, n-1] with e[m] <= x, 0 if none (edges increasing)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (e[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Distance to the latitude cone (the equatorial plane when tb == 0) of an
+// edge with cos^2 = c2, sin^2 = s2; roots below lo ignored; hits must be on
+// the nappe whose z has the sign of tb.
+__device__ __forceinline__ double cone_distance(const Ray& p, double dx, double dy, double dz, double tb,
+                                                double c2, double s2, double lo)
+{
+    double best = INFINITY;
+    if (tb == 0.0) {
+        if (dz != 0.0) {
+            double s = -p.z / dz;
+            if (s >= lo) best = s;
+        }
+        return best;
+    }
+    double a = dz * dz * c2 - (dx * dx + dy * dy) * s2;
+    double b = p.z * dz * c2 - (p.x * dx + p.y * dy) * s2;
+    double c = p.z * p.z * c2 - (p.x * p.x + p.y * p.y) * s2;
+    double r0 = -1.0, r1 = -1.0;
+    bool h0 = false, h1 = false;
+    if (a == 0.0) {
+        if (b != 0.0) {
+            r0 = -c / (2.0 * b);
+            h0 = true;
+        }
+    } else {
+        double disc = b * b - a * c;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -(b + (b >= 0.0 ? sq : -sq));
+            r0 = q / a;
+            h0 = true;
+            if (q != 0.0) {
+                r1 = c / q;
+                h1 = true;
+            }
+        }
+    }
+    if (h0 && r0 >= lo) {
+        double zh = p.z + r0 * dz;
+        bool ok = tb > 0.0 ? (zh > 0.0) : (zh < 0.0);
+        if (ok && r0 < best) best = r0;
+    }
+    if (h1 && r1 >= lo) {
+        double zh = p.z + r1 * dz;
+        bool ok = tb > 0.0 ? (zh > 0.0) : (zh < 0.0);
+        if (ok && r1 < best) best = r1;
+    }
+    return best;
+}
+
+// Distance to leave the current cell along d; returns the face (ties in the
+// order outer, inner, lat-low, lat-high, lon-low, lon-high).
+__device__ __forceinline__ int exit_distance(const GridDev& g, const Ray& p, double dx, double dy,
+                                             double dz, double& s_out)
+{
+    if (g.geom == 1) {
+        if (dz > 0.0) {
+            double s = (g.r[p.k + 1] - p.z) / dz;
+            s_out = s < 0.0 ? 0.0 : s;
+            return F_OUT;
+        }
+        if (dz < 0.0) {
+            double s = (g.r[p.k] - p.z) / dz;
+            s_out = s < 0.0 ? 0.0 : s;
+            return F_IN;
+        }
+        s_out = INFINITY;
+        return F_NONE;
+    }
+    double rr = p.x * p.x + p.y * p.y + p.z * p.z;
+    double B = p.x * dx + p.y * dy + p.z * dz;
+    double best;
+    int face;
+    {
+        double ro = g.r[p.k + 1];
+        double C = rr - ro * ro;
+        double D = B * B - C;
+        if (D < 0.0) D = 0.0;
+        double s = (B <= 0.0) ? (-B + sqrt(D)) : (-C / (B + sqrt(D)));
+        if (s < 0.0) s = 0.0;
+        best = s;
+        face = F_OUT;
+    }
+    if (B < 0.0) {
+        double ri = g.r[p.k];
+        double C = rr - ri * ri;
+        double D = B * B - C;
+        if (D >= 0.0) {
+            double s = C / (-B + sqrt(D));
+            if (s < 0.0) s = 0.0;
+            if (s < best) {
+                best = s;
+                face = F_IN;
+            }
+        }
+    }
+    double tol = 1e-9 * sqrt(rr);
+    if (p.j > 0) {
+        int e = p.j;
+        double s = cone_distance(p, dx, dy, dz, g.lat[e], g.lat_c2[e], g.lat_s2[e],
+                                 p.ef == F_LATLO ? tol : 0.0);
+        if (s < best) {
+            best = s;
+            face = F_LATLO;
+        }
+    }
+    if (p.j < g.nlat - 1) {
+        int e = p.j + 1;
+        double s = cone_distance(p, dx, dy, dz, g.lat[e], g.lat_c2[e], g.lat_s2[e],
+                                 p.ef == F_LATHI ? tol : 0.0);
+        if (s < best) {
+            best = s;
+            face = F_LATHI;
+        }
+    }
+    if (g.nlon > 1) {
+        {
+            double sb = g.lon_s[p.i], cb = g.lon_c[p.i];
+            double nx = -sb, ny = cb;
+            double dn = dx * nx + dy * ny;
+            if (dn < 0.0) {
+                double s = -(p.x * nx + p.y * ny) / dn;
+                if (s < 0.0) s = 0.0;
+                double hx = p.x + s * dx, hy = p.y + s * dy;
+                if (cb * hx + sb * hy > 0.0 && s < best) {
+                    best = s;
+                    face = F_LONLO;
+                }
+            }
+        }
+        {
+            int iu = p.i + 1 == g.nlon ? 0 : p.i + 1;
+            double sb = g.lon_s[iu], cb = g.lon_c[iu];
+            double nx = -sb, ny = cb;
+            double dn = dx * nx + dy * ny;
+            if (dn > 0.0) {
+                double s = -(p.x * nx + p.y * ny) / dn;
+                if (s < 0.0) s = 0.0;
+                double hx = p.x + s * dx, hy = p.y + s * dy;
+                if (cb * hx + sb * hy > 0.0 && s < best) {
+                    best = s;
+                    face = F_LONHI;
+                }
+            }
+        }
+    }
+    s_out = best;
+    return face;
+}
+
+__device__ __forceinline__ void advance(const GridDev& g, Ray& p, double dx, double dy, double dz, double s)
+{
+    if (g.geom == 1) {
+        p.z = p.z + s * dz;
+    } else {
+        p.x = p.x + s * dx;
+        p.y = p.y + s * dy;
+        p.z = p.z + s * dz;
+    }
+}
+
+__device__ __forceinline__ void cross(const GridDev& g, Ray& p, int f)
+{
+    switch (f) {
+    case F_OUT:
+        p.k += 1;
+        p.ef = F_IN;
+        if (g.geom == 1 && p.k <= g.nlay) p.z = g.r[p.k];
+        break;
+    case F_IN:
+        p.k -= 1;
+        p.ef = F_OUT;
+        if (g.geom == 1 && p.k >= -1) p.z = g.r[p.k + 1];
+        break;
+    case F_LATLO: p.j -= 1; p.ef = F_LATHI; break;
+    case F_LATHI: p.j += 1; p.ef = F_LATLO; break;
+    case F_LONLO: p.i = p.i == 0 ? g.nlon - 1 : p.i - 1; p.ef = F_LONHI; break;
+    case F_LONHI: p.i = p.i + 1 == g.nlon ? 0 : p.i + 1; p.ef = F_LONLO; break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ int cell_of(const GridDev& g, const Ray& p)
+{
+    return (p.k * g.nlat + p.j) * g.nlon + p.i;
+}
+
+__device__ __forceinline__ void locate_column(const GridDev& g, Ray& p)
+{
+    double lat = atan2(p.z, sqrt(p.x * p.x + p.y * p.y));
+    double lon = atan2(p.y, p.x);
+    p.j = find_edge(g.lat, g.nlat, lat);
+    p.i = find_edge(g.lon, g.nlon, lon);
+}
+
+// ---------------------------------------------------------------- opacity interpolation
+struct Bracket {
+    int i0, i1;
+    double t;
+};
+
+__device__ __forceinline__ Bracket bracket(const double* gx, int n, double x)
+{
+    Bracket b;
+    if (n == 1) {
+        b.i0 = 0; b.i1 = 0; b.t = 0.0;
+        return b;
+    }
+    if (x <= gx[0]) {
+        b.i0 = 0; b.i1 = 1; b.t = 0.0;
+        return b;
+    }
+    if (x >= gx[n - 1]) {
+        b.i0 = n - 2; b.i1 = n - 1; b.t = 1.0;
+        return b;
+    }
+    int m = find_edge(gx, n - 1, x);
+    b.i0 = m;
+    b.i1 = m + 1;
+    b.t = (x - gx[m]) / (gx[m + 1] - gx[m]);
+    return b;
+}
+
+// ln-kappa bilinear in (T, ln P); a -inf (zero kappa) corner with positive
+// weight gives zero.  lnk(iT, iP) read through the accessor.
+template <typename F>
+__device__ __forceinline__ double interp_tp(F lnk, const Bracket& bt, const Bracket& bp)
+{
+    double t = bt.t, u = bp.t;
+    double w0 = (1.0 - t) * (1.0 - u), w1 = (1.0 - t) * u, w2 = t * (1.0 - u), w3 = t * u;
+    double acc = 0.0;
+    if (w0 > 0.0) { double l = lnk(bt.i0, bp.i0); if (isinf(l)) return 0.0; acc = acc + w0 * l; }
+    if (w1 > 0.0) { double l = lnk(bt.i0, bp.i1); if (isinf(l)) return 0.0; acc = acc + w1 * l; }
+    if (w2 > 0.0) { double l = lnk(bt.i1, bp.i0); if (isinf(l)) return 0.0; acc = acc + w2 * l; }
+    if (w3 > 0.0) { double l = lnk(bt.i1, bp.i1); if (isinf(l)) return 0.0; acc = acc + w3 * l; }
+    return exp(acc);
+}
+
+// ---------------------------------------------------------------- K1
+__global__ void __launch_bounds__(256) k_ck_optics(GridDev g, int ncell, const double* __restrict__ lnk_tab,
+                                                   int nT, int nP, const double* __restrict__ T_grid,
+                                                   const double* __restrict__ lnP_grid, double k_ray,
+                                                   OpticsDev<double> out, int ext_stride)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
+    Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
+    double kg = interp_tp([&](int a, int b) { return lnk_tab[a * nP + b]; }, bt, bp);
+    double ks = g.cld_ksca ? (double)g.cld_ksca[c] : 0.0;
+    double ka = g.cld_kabs ? (double)g.cld_kabs[c] : 0.0;
+    double kab = kg + ka;
+    double ksc = k_ray + ks;
+    double kext = kab + ksc;
+    double rho = g.rho[c];
+    out.a_ext[(size_t)c * ext_stride] = rho * kext;
+    if (out.a_abs) {
+        out.a_abs[c] = rho * kab;
+        out.omega[c] = kext > 0.0 ? ksc / kext : 0.0;
+        out.p_gas[c] = ksc > 0.0 ? k_ray / ksc : 1.0;
+        out.g_cld[c] = g.cld_g ? (double)g.cld_g[c] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- K2
+__global__ void __launch_bounds__(256) k_doppler_shift(GridDev g, double ox, double oy, double oz,
+                                                       double dlnlam, double* __restrict__ shift)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int ncell = g.nlon * g.nlat * g.nlay;
+    if (c >= ncell) return;
+    int i = c % g.nlon, j = (c / g.nlon) % g.nlat, k = c / (g.nlon * g.nlat);
+    double rc = 0.5 * (g.r[k] + g.r[k + 1]);
+    double th = 0.5 * (g.lat[j] + g.lat[j + 1]);
+    double ph = 0.5 * (g.lon[i] + g.lon[i + 1]);
+    double sth = sin(th), cth = cos(th), sph = sin(ph), cph = cos(ph);
+    double eE0 = -sph, eE1 = cph, eE2 = 0.0;
+    double eN0 = -sth * cph, eN1 = -sth * sph, eN2 = cth;
+    double eR0 = cth * cph, eR1 = cth * sph, eR2 = sth;
+    double uu = g.u ? (double)g.u[c] : 0.0, vv = g.v ? (double)g.v[c] : 0.0, ww = g.w ? (double)g.w[c] : 0.0;
+    double ue = uu + g.omega_rot * rc * cth;
+    double v0 = ue * eE0 + vv * eN0 + ww * eR0;
+    double v1 = ue * eE1 + vv * eN1 + ww * eR1;
+    double v2 = ue * eE2 + vv * eN2 + ww * eR2;
+    double vlos = -(v0 * ox + v1 * oy + v2 * oz);
+    shift[c] = log1p(-vlos / kC) / dlnlam;
+}
+
+__device__ __forceinline__ double hires_kappa(const double* __restrict__ lnk_tpl, int nlam, int nP,
+                                              const Bracket& bt, const Bracket& bp, int n, double shift)
+{
+    double x = (double)n + shift;
+    int n0;
+    double fr;
+    if (nlam == 1) { n0 = 0; fr = 0.0; }
+    else if (x <= 0.0) { n0 = 0; fr = 0.0; }
+    else if (x >= (double)(nlam - 1)) { n0 = nlam - 2; fr = 1.0; }
+    else { n0 = (int)floor(x); fr = x - (double)n0; }
+    double k0 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
+    if (nlam == 1) return k0;
+    double k1 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
+    return (1.0 - fr) * k0 + fr * k1;
+}
+
+// alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
+// Threads run slot-fastest so a wave reads consecutive wavelengths of the
+// [T][P][lambda] table and writes a contiguous row.
+__global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
+                                                           int nlam, int nT, int nP,
+                                                           const double* __restrict__ T_grid,
+                                                           const double* __restrict__ lnP_grid,
+                                                           const double* __restrict__ k_ray,
+                                                           const double* __restrict__ shift,
+                                                           const int* __restrict__ nlist, int nslot,
+                                                           int slot_stride, double* __restrict__ alpha)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)ncell * nslot) return;
+    int c = (int)(t / nslot), s = (int)(t % nslot);
+    int n = nlist[s];
+    Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
+    Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
+    double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
+    double kext = kl + k_ray[n];
+    alpha[(size_t)c * slot_stride + s] = g.rho[c] * kext;
+}
+
+__global__ void __launch_bounds__(256) k_hires_optics(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
+                                                      int nlam, int nT, int nP, const double* __restrict__ T_grid,
+                                                      const double* __restrict__ lnP_grid, double k_ray,
+                                                      const double* __restrict__ shift, int n, OpticsDev<double> out)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
+    Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
+    double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
+    double kext = kl + k_ray;
+    double rho = g.rho[c];
+    out.a_ext[c] = rho * kext;
+    out.a_abs[c] = rho * kl;
+    out.omega[c] = kext > 0.0 ? k_ray / kext : 0.0;
+    out.p_gas[c] = 1.0;
+    out.g_cld[c] = 0.0;
+}
+
+// ---------------------------------------------------------------- K3
+__device__ __forceinline__ double planck(double lam_cm, double T)
+{
+    double x = kH * kC / (lam_cm * kKB * T);
+    return 2.0 * kH * kC * kC / pow(lam_cm, 5.0) / expm1(x);
+}
+
+// One thread per column: walk down from the top accumulating the extinction
+// optical depth above each cell's top face.
+__global__ void __launch_bounds__(256) k_emission_L(GridDev g, OpticsDev<double> op, double lam_cm,
+                                                    double tau_vert, double* __restrict__ L)
+{
+    int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= g.nlon * g.nlat) return;
+    int i = col % g.nlon, j = col / g.nlon;
+    double tau = 0.0;
+    double dsl = g.lat_sin[j + 1] - g.lat_sin[j];
+    double dph = g.lon[i + 1] - g.lon[i];
+    for (int k = g.nlay - 1; k >= 0; --k) {
+        int c = (k * g.nlat + j) * g.nlon + i;
+        double vol = g.vol_r[k] * dsl * dph;
+        double Li = 4.0 * kPi * vol * op.a_abs[c] * planck(lam_cm, (double)g.T[c]);
+        L[c] = (tau > tau_vert) ? 0.0 : Li;
+        tau = tau + op.a_ext[c] * (g.r[k + 1] - g.r[k]);
+    }
+}
+
+// Fixed-order block reduction helpers (deterministic).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Per-block (sum L, count L > 0) -> partial[block][2].
+__global__ void __launch_bounds__(256) k_sum_L(const double* __restrict__ L, int n, double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    int c = blockIdx.x * 256 + threadIdx.x;
+    double v = c < n ? L[c] : 0.0;
+    double cnt = (c < n && v > 0.0) ? 1.0 : 0.0;
+    double s = block_sum<256>(v, sh);
+    double m = block_sum<256>(cnt, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s;
+        part[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// Serial-per-thread then tree reduction of nblk rows of `width` doubles;
+// Neumaier-compensated so the result is nearly independent of blocking.
+__global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ part, int nrow, int width,
+                                                    double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    __shared__ double shc[256];
+    int col = blockIdx.x;
+    double s = 0.0, comp = 0.0;
+    for (int r = threadIdx.x; r < nrow; r += 256) {
+        double x = part[(size_t)r * width + col];
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) comp = comp + ((s - t) + x);
+        else comp = comp + ((x - t) + s);
+        s = t;
+    }
+    sh[threadIdx.x] = s;
+    shc[threadIdx.x] = comp;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double a = sh[threadIdx.x], b = sh[threadIdx.x + st];
+            double t = a + b;
+            double e = (fabs(a) >= fabs(b)) ? ((a - t) + b) : ((b - t) + a);
+            sh[threadIdx.x] = t;
+            shc[threadIdx.x] = shc[threadIdx.x] + shc[threadIdx.x + st] + e;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[col] = sh[0] + shc[0];
+}
+
+// q_i and the per-block sums of q for the scan; stats = (L_tot, N_emit).
+__global__ void __launch_bounds__(256) k_bias_pdf(const double* __restrict__ L, int n, const double* __restrict__ stats,
+                                                  double xi, double* __restrict__ q, double* __restrict__ wbirth)
+{
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    double Ltot = stats[0], nemit = stats[1];
+    double Lc = L[c];
+    double qc = 0.0;
+    if (Lc > 0.0) qc = (1.0 - xi) * Lc / Ltot + xi / nemit;
+    q[c] = qc;
+    wbirth[c] = (Lc > 0.0) ? (Lc / Ltot) / qc : 0.0;
+}
+
+// Inclusive scan: per-block local scan (sequential within a thread's run of 8,
+// then across threads), block totals scanned by one block, then offsets added.
+constexpr int kScanPer = 8;
+constexpr int kScanBlock = 256 * kScanPer;
+
+__global__ void __launch_bounds__(256) k_scan_local(const double* __restrict__ in, int n, double* __restrict__ out,
+                                                    double* __restrict__ blocksum)
+{
+    __shared__ double sh[256];
+    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    double loc[kScanPer];
+    double run = 0.0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        double x = (base + q < n) ? in[base + q] : 0.0;
+        run = run + x;
+        loc[q] = run;
+    }
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 256 thread totals
+    for (int off = 1; off < 256; off <<= 1) {
+        double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        sh[threadIdx.x] = sh[threadIdx.x] + v;
+        __syncthreads();
+    }
+    double pre = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q)
+        if (base + q < n) out[base + q] = pre + loc[q];
+    if (threadIdx.x == 255) blocksum[blockIdx.x] = sh[255];
+}
+
+__global__ void __launch_bounds__(256) k_scan_blocksums(double* __restrict__ bs, int nb)
+{
+    // single block: sequential chunks per thread then a thread-level scan
+    __shared__ double sh[256];
+    int per = (nb + 255) / 256;
+    int b0 = threadIdx.x * per;
+    double run = 0.0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nb) run = run + bs[b0 + q];
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        sh[threadIdx.x] = sh[threadIdx.x] + v;
+        __syncthreads();
+    }
+    double pre = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+    // convert to exclusive offsets of each block
+    double acc = pre;
+    for (int q = 0; q < per; ++q) {
+        if (b0 + q < nb) {
+            double x = bs[b0 + q];
+            bs[b0 + q] = acc;
+            acc = acc + x;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(double* __restrict__ out, int n, const double* __restrict__ off)
+{
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    int b = c / kScanBlock;
+    if (b > 0) out[c] = off[b] + out[c];
+}
+
+// ---------------------------------------------------------------- K4 transport
+struct Counters {
+    double k[kNCounters];
+};
+
+// Walk until an interaction at optical depth tau, escape, surface or the
+// crossing cap; continuous absorption reduces W along the path.
+__device__ __forceinline__ int walk_flight(const GridDev& g, const OpticsDev<double>& op, Ray& p, double dx,
+                                           double dy, double dz, double tau, bool cont, double& W, Counters& K)
+{
+    int nc = 0;
+    for (;;) {
+        double s;
+        int f = exit_distance(g, p, dx, dy, dz, s);
+        int c = cell_of(g, p);
+        double ae = op.a_ext[c];
+        double a = cont ? (ae - op.a_abs[c]) : ae;
+        if (f == F_NONE && !(a > 0.0)) { K.k[K_NCROSS] += nc; return T_LOST; }
+        if (a > 0.0 && tau < a * s) {
+            double ds = tau / a;
+            if (cont) {
+                double wn = W * exp(-op.a_abs[c] * ds);
+                K.k[K_ABS] = K.k[K_ABS] + (W - wn);
+                W = wn;
+            }
+            advance(g, p, dx, dy, dz, ds);
+            p.ef = F_NONE;
+            K.k[K_NCROSS] += nc;
+            return T_INTERACT;
+        }
+        tau = tau - a * s;
+        if (cont) {
+            double wn = W * exp(-op.a_abs[c] * s);
+            K.k[K_ABS] = K.k[K_ABS] + (W - wn);
+            W = wn;
+        }
+        advance(g, p, dx, dy, dz, s);
+        cross(g, p, f);
+        nc++;
+        if (p.k >= g.nlay) { K.k[K_NCROSS] += nc; return T_ESCAPE; }
+        if (p.k < 0) { K.k[K_NCROSS] += nc; return T_SURFACE; }
+        if (nc >= g.max_cross) { K.k[K_NCROSS] += nc; return T_LOST; }
+    }
+}
+
+// Extinction optical depth from an event point to the top along o; +inf if
+// the ray meets the surface, stalls or passes tau_cut.
+__device__ __forceinline__ double peel_tau(const GridDev& g, const OpticsDev<double>& op, const Ray& start,
+                                           double ox, double oy, double oz, double tau_cut, Counters& K)
+{
+    if (g.geom == 1 && !(oz > 0.0)) return INFINITY;
+    Ray p = start;
+    p.ef = F_NONE;
+    double tau = 0.0;
+    int nc = 0;
+    for (;;) {
+        double s;
+        int f = exit_distance(g, p, ox, oy, oz, s);
+        if (f == F_NONE) { K.k[K_NCROSS] += nc; return INFINITY; }
+        int c = cell_of(g, p);
+        tau = tau + op.a_ext[c] * s;
+        advance(g, p, ox, oy, oz, s);
+        cross(g, p, f);
+        nc++;
+        if (tau > tau_cut) { K.k[K_NCROSS] += nc; return INFINITY; }
+        if (p.k >= g.nlay) { K.k[K_NCROSS] += nc; return tau; }
+        if (p.k < 0) { K.k[K_NCROSS] += nc; return INFINITY; }
+        if (nc >= g.max_cross) { K.k[K_NCROSS] += nc; return INFINITY; }
+    }
+}
+
+__device__ void run_packet(const GridDev& g, const OpticsDev<double>& op, const TransportArgs& A, uint64_t pid,
+                           double* F, Counters& K)
+{
+    const int nobs = A.n_obs;
+    const bool slab_back = (g.geom == 1 && nobs == 0);
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) F[o] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNCounters; ++q) K.k[q] = 0.0;
+    double obx = 0.0, oby = 0.0, obz = 0.0;
+    Ray p;
+    double dx, dy, dz, W;
+    if (A.mode == 0) {
+        U2 u = draw(A.seed, A.tag, pid, 0, 0);
+        if (g.geom == 1) {
+            double mu0 = A.mu0 > 0.0 ? A.mu0 : sqrt(1.0 - u.a);
+            dx = sqrt(fmax(1.0 - mu0 * mu0, 0.0));
+            dy = 0.0;
+            dz = -mu0;
+            obx = -dx;
+            oby = 0.0;
+            obz = mu0;
+            p.x = 0.0; p.y = 0.0; p.z = g.r[g.nlay];
+            p.i = 0; p.j = 0; p.k = g.nlay - 1; p.ef = F_OUT;
+        } else {
+            double rho = A.r_toa * sqrt(u.a);
+            double a = 2.0 * kPi * u.b;
+            double y = rho * cos(a), z = rho * sin(a);
+            double x = sqrt(fmax(A.r_toa * A.r_toa - y * y - z * z, 0.0));
+            p.x = x; p.y = y; p.z = z;
+            dx = -1.0; dy = 0.0; dz = 0.0;
+            p.k = g.nlay - 1;
+            locate_column(g, p);
+            p.ef = F_OUT;
+        }
+        W = 1.0;
+    } else {
+        int ncell = g.nlon * g.nlat * g.nlay;
+        double tot = A.cdf[ncell - 1];
+        if (!(tot > 0.0)) return;
+        U2 u0 = draw(A.seed, A.tag, pid, 0, 0);
+        U2 u1 = draw(A.seed, A.tag, pid, 0, 1);
+        U2 u2 = draw(A.seed, A.tag, pid, 0, 2);
+        double target = u0.a * tot;
+        int lo = 0, hi = ncell - 1;  // smallest c with cdf[c] > target
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (A.cdf[mid] > target) hi = mid;
+            else lo = mid + 1;
+        }
+        int c = lo;
+        int i = c % g.nlon, j = (c / g.nlon) % g.nlat, k = c / (g.nlon * g.nlat);
+        double rk = g.r[k], rk1 = g.r[k + 1];
+        double rk3 = rk * rk * rk;
+        double rk13 = rk1 * rk1 * rk1;
+        double r = cbrt(rk3 + u0.b * (rk13 - rk3));
+        double sl0 = g.lat_sin[j], sl1 = g.lat_sin[j + 1];
+        double sl = sl0 + u1.a * (sl1 - sl0);
+        double cl = sqrt(fmax(1.0 - sl * sl, 0.0));
+        double lon = g.lon[i] + u1.b * (g.lon[i + 1] - g.lon[i]);
+        p.x = r * cl * cos(lon);
+        p.y = r * cl * sin(lon);
+        p.z = r * sl;
+        p.i = i; p.j = j; p.k = k; p.ef = F_NONE;
+        double mu = 2.0 * u2.a - 1.0;
+        double sp = sqrt(fmax(1.0 - mu * mu, 0.0));
+        double psi = 2.0 * kPi * u2.b;
+        dx = sp * cos(psi);
+        dy = sp * sin(psi);
+        dz = mu;
+        W = A.wbirth[c];
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o) {
+            if (o < nobs) {
+                double t = peel_tau(g, op, p, A.obs[3 * o], A.obs[3 * o + 1], A.obs[3 * o + 2], A.tau_peel_max, K);
+                F[o] = F[o] + W * exp(-t) / (4.0 * kPi);
+            }
+        }
+    }
+    const double W0 = W;
+    K.k[K_W0] = W0;
+    if (A.mode == 1 && !A.scattering) {
+        K.k[K_ESC] += W;
+        return;
+    }
+    const bool cont = A.absorption == 1;
+    for (uint32_t e = 1;; ++e) {
+        U2 u = draw(A.seed, A.tag, pid, e, 0);
+        double tau = -log(u.a);
+        double usel = u.b;
+        int term = walk_flight(g, op, p, dx, dy, dz, tau, cont, W, K);
+        if (term == T_ESCAPE) { K.k[K_ESC] += W; break; }
+        if (term == T_SURFACE) { K.k[K_SURF] += W; break; }
+        if (term == T_LOST) { K.k[K_LOST] += W; K.k[K_NLOST] += 1.0; break; }
+        K.k[K_NINT] += 1.0;
+        int c = cell_of(g, p);
+        double om = op.omega[c], pg = op.p_gas[c], gc = op.g_cld[c];
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o) {
+            if (o < (slab_back ? 1 : nobs)) {
+                double ox = slab_back ? obx : A.obs[3 * o];
+                double oy = slab_back ? oby : A.obs[3 * o + 1];
+                double oz = slab_back ? obz : A.obs[3 * o + 2];
+                double mu = dx * ox + dy * oy + dz * oz;
+                double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * p_hg(mu, gc)) / (4.0 * kPi);
+                double t = peel_tau(g, op, p, ox, oy, oz, A.tau_peel_max, K);
+                double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
+                F[o] = F[o] + f;
+            }
+        }
+        if (!cont) {
+            K.k[K_ABS] += W * (1.0 - om);
+            W = W * om;
+        }
+        U2 u1 = draw(A.seed, A.tag, pid, e, 1);
+        double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, gc);
+        rotate_dir(dx, dy, dz, mu, 2.0 * kPi * u1.b);
+        if (W < A.rr_threshold * W0) {
+            U2 u2 = draw(A.seed, A.tag, pid, e, 2);
+            if (u2.a < A.rr_survive) {
+                double wn = W / A.rr_survive;
+                K.k[K_RR] -= (wn - W);
+                W = wn;
+            } else {
+                K.k[K_RR] += W;
+                W = 0.0;
+                break;
+            }
+        }
+        if ((long long)e >= A.max_events) { K.k[K_CAP] += W; K.k[K_NCAPPED] += 1.0; break; }
+    }
+}
+
+// One packet per lane; each block writes (sum F, sum F^2) per observer and
+// its counters to its partial row in a fixed reduction order.
+__global__ void __launch_bounds__(kTB) k_transport(GridDev g, OpticsDev<double> op, TransportArgs A)
+{
+    __shared__ double sh[kTB];
+    uint64_t q = (uint64_t)blockIdx.x * kTB + threadIdx.x;
+    double F[kMaxObs];
+    Counters K;
+    bool live = q < A.n_packets;
+    if (live) {
+        run_packet(g, op, A, q, F, K);
+    } else {
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o) F[o] = 0.0;
+#pragma unroll
+        for (int t = 0; t < kNCounters; ++t) K.k[t] = 0.0;
+    }
+    if (live && A.packet_dump) {
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o)
+            if (o < A.n_out) A.packet_dump[q * A.n_out + o] = F[o];
+    }
+    int width = 2 * A.n_out + kNCounters;
+    double* row = A.partials + (size_t)blockIdx.x * width;
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) {
+        if (o < A.n_out) {
+            double s1 = block_sum<kTB>(F[o], sh);
+            double s2 = block_sum<kTB>(F[o] * F[o], sh);
+            if (threadIdx.x == 0) {
+                row[2 * o] = s1;
+                row[2 * o + 1] = s2;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kNCounters; ++t) {
+        double s = block_sum<kTB>(K.k[t], sh);
+        if (threadIdx.x == 0) row[2 * A.n_out + t] = s;
+    }
+}
+
+// ---------------------------------------------------------------- K5 chords
+__device__ __forceinline__ void chord_start(const GridDev& g, int ch, int n_b, int n_alpha, uint64_t seed,
+                                            uint32_t tag, Ray& p, double& b)
+{
+    int ib = ch / n_alpha, ia = ch % n_alpha;
+    U2 u = draw(seed, tag, (uint64_t)ch, 0, 0);
+    double r0 = g.r[0], rt = g.r[g.nlay];
+    b = r0 + ((double)ib + u.a) * (rt - r0) / (double)n_b;
+    double al = 2.0 * kPi * ((double)ia + u.b) / (double)n_alpha;
+    p.x = sqrt(fmax(rt * rt - b * b, 0.0));
+    p.y = b * cos(al);
+    p.z = b * sin(al);
+    p.k = g.nlay - 1;
+    locate_column(g, p);
+    p.ef = F_OUT;
+}
+
+__global__ void __launch_bounds__(256) k_chord_count(GridDev g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
+                                                     int* __restrict__ counts)
+{
+    int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_b * n_alpha) return;
+    Ray p;
+    double b;
+    chord_start(g, ch, n_b, n_alpha, seed, tag, p, b);
+    int n = 0;
+    int cap = 64 * (g.nlay + g.nlat + g.nlon) + 64;
+    while (n < cap) {
+        double s;
+        int f = exit_distance(g, p, -1.0, 0.0, 0.0, s);
+        if (f == F_NONE) break;
+        ++n;
+        advance(g, p, -1.0, 0.0, 0.0, s);
+        cross(g, p, f);
+        if (p.k >= g.nlay || p.k < 0) break;
+    }
+    counts[ch] = n;
+}
+
+__global__ void __launch_bounds__(256) k_chord_fill(GridDev g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
+                                                    const long long* __restrict__ offsets,
+                                                    uint32_t* __restrict__ seg_cell, double* __restrict__ seg_len,
+                                                    double* __restrict__ chord_b, int* __restrict__ chord_ok)
+{
+    int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_b * n_alpha) return;
+    Ray p;
+    double b;
+    chord_start(g, ch, n_b, n_alpha, seed, tag, p, b);
+    long long o = offsets[ch], end = offsets[ch + 1];
+    int ok = 0;
+    while (o < end) {
+        double s;
+        int f = exit_distance(g, p, -1.0, 0.0, 0.0, s);
+        if (f == F_NONE) break;
+        seg_cell[o] = (uint32_t)cell_of(g, p);
+        seg_len[o] = s;
+        ++o;
+        advance(g, p, -1.0, 0.0, 0.0, s);
+        cross(g, p, f);
+        if (p.k >= g.nlay) { ok = 1; break; }
+        if (p.k < 0) break;
+    }
+    chord_b[ch] = b;
+    chord_ok[ch] = ok;
+}
+
+__global__ void __launch_bounds__(256) k_scan_int(const int* __restrict__ in, long long* __restrict__ out, int n)
+{
+    // single block exclusive scan of ints into 64-bit offsets; out[n] = total
+    __shared__ long long sh[256];
+    int per = (n + 255) / 256;
+    int b0 = threadIdx.x * per;
+    long long run = 0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < n) run += in[b0 + q];
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        long long v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    long long acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0;
+    for (int q = 0; q < per; ++q) {
+        if (b0 + q < n) {
+            out[b0 + q] = acc;
+            acc += in[b0 + q];
+        }
+    }
+    if (threadIdx.x == 255) out[n] = sh[255];
+}
+
+// tau per (chord, slot) = sum over the chord's segments of alpha[cell][slot]
+// * length, in segment order; one wave per chord, lanes over slots.
+// Each block sums (1 - e^-tau) b and its square over its chords in a fixed
+// order into partials[block][slot][2].
+constexpr int kChordWaves = 4;
+constexpr int kChordsPerWave = 8;
+
+__global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ seg_cell,
+                                                   const double* __restrict__ seg_len,
+                                                   const double* __restrict__ chord_b,
+                                                   const int* __restrict__ chord_ok,
+                                                   const double* __restrict__ alpha, int nslot,
+                                                   double* __restrict__ partials)
+{
+    __shared__ double sh1[kChordWaves][64];
+    __shared__ double sh2[kChordWaves][64];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int s0 = 0; s0 < nslot; s0 += 64) {
+        int s = s0 + lane;
+        double a1 = 0.0, a2 = 0.0;
+        for (int m = 0; m < kChordsPerWave; ++m) {
+            int ch = (blockIdx.x * kChordWaves + wave) * kChordsPerWave + m;
+            if (ch >= nch) break;
+            long long o0 = offsets[ch], o1 = offsets[ch + 1];
+            double tau = 0.0;
+            if (s < nslot) {
+                for (long long o = o0; o < o1; ++o)
+                    tau = tau + alpha[(size_t)seg_cell[o] * nslot + s] * seg_len[o];
+            }
+            if (!chord_ok[ch]) tau = INFINITY;
+            double v = (1.0 - exp(-tau)) * chord_b[ch];
+            a1 = a1 + v;
+            a2 = a2 + v * v;
+        }
+        sh1[wave][lane] = a1;
+        sh2[wave][lane] = a2;
+        __syncthreads();
+        if (wave == 0 && s < nslot) {
+            double t1 = sh1[0][lane], t2 = sh2[0][lane];
+            for (int w = 1; w < kChordWaves; ++w) {
+                t1 = t1 + sh1[w][lane];
+                t2 = t2 + sh2[w][lane];
+            }
+            double* row = partials + (size_t)blockIdx.x * (2 * nslot);
+            row[2 * s] = t1;
+            row[2 * s + 1] = t2;
+        }
+        __syncthreads();
+    }
+}
+
+inline int nblk(long long n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP, const double* T_grid,
+                      const double* lnP_grid, double k_ray, OpticsDev<double> out, int ext_stride,
+                      hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_ck_optics, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, lnk_tab, nT, nP, T_grid,
+                       lnP_grid, k_ray, out, ext_stride);
+}
+
+void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, double dlnlam, double* shift,
+                          hipStream_t stream)
+{
+    int ncell = g.nlon * g.nlat * g.nlay;
+    hipLaunchKernelGGL(k_doppler_shift, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ox, oy, oz, dlnlam, shift);
+}
+
+void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
+                              const double* T_grid, const double* lnP_grid, const double* k_ray,
+                              const double* shift, const int* nlist, int nslot, int slot_stride, double* alpha,
+                              hipStream_t stream)
+{
+    long long n = (long long)ncell * nslot;
+    hipLaunchKernelGGL(k_hires_alpha_block, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nT,
+                       nP, T_grid, lnP_grid, k_ray, shift, nlist, nslot, slot_stride, alpha);
+}
+
+void launch_hires_optics(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
+                         const double* T_grid, const double* lnP_grid, double k_ray, const double* shift, int n,
+                         OpticsDev<double> out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_hires_optics, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nT, nP,
+                       T_grid, lnP_grid, k_ray, shift, n, out);
+}
+
+size_t emission_scratch_doubles(int ncell)
+{
+    // q (ncell) + L-sum partials (2 per 256) + scan block sums
+    return (size_t)ncell + 2 * (size_t)nblk(ncell, 256) + (size_t)nblk(ncell, kScanBlock) + 16;
+}
+
+void launch_emission_sources(const GridDev& g, const OpticsDev<double>& op, double lam_cm, double tau_vert,
+                             double xi, double* L, double* cdf, double* wbirth, double* scratch, double* stats_out,
+                             hipStream_t stream)
+{
+    int ncell = g.nlon * g.nlat * g.nlay;
+    int ncol = g.nlon * g.nlat;
+    double* q = scratch;
+    double* lpart = q + ncell;
+    int nb = nblk(ncell, 256);
+    double* bsum = lpart + 2 * nb;
+    hipLaunchKernelGGL(k_emission_L, dim3(nblk(ncol, 256)), dim3(256), 0, stream, g, op, lam_cm, tau_vert, L);
+    hipLaunchKernelGGL(k_sum_L, dim3(nb), dim3(256), 0, stream, L, ncell, lpart);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(2), dim3(256), 0, stream, lpart, nb, 2, stats_out);
+    hipLaunchKernelGGL(k_bias_pdf, dim3(nb), dim3(256), 0, stream, L, ncell, stats_out, xi, q, wbirth);
+    int ns = nblk(ncell, kScanBlock);
+    hipLaunchKernelGGL(k_scan_local, dim3(ns), dim3(256), 0, stream, q, ncell, cdf, bsum);
+    if (ns > 1) {
+        hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(256), 0, stream, bsum, ns);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, cdf, ncell, bsum);
+    }
+}
+
+int transport_block_size() { return kTB; }
+
+void launch_transport(const GridDev& g, const OpticsDev<double>& op, const TransportArgs& a, int blocks,
+                      hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_transport, dim3(blocks), dim3(kTB), 0, stream, g, op, a);
+}
+
+void launch_reduce_partials(const double* partials, int nblocks, int width, double* out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reduce_rows, dim3(width), dim3(256), 0, stream, partials, nblocks, width, out);
+}
+
+void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag, int* counts,
+                        hipStream_t stream)
+{
+    int nch = n_b * n_alpha;
+    hipLaunchKernelGGL(k_chord_count, dim3(nblk(nch, 256)), dim3(256), 0, stream, g, n_b, n_alpha, seed, tag, counts);
+}
+
+void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* /*total_dev*/, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(256), 0, stream, in, out, n);
+}
+
+void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag, const long long* offsets,
+                       uint32_t* seg_cell, double* seg_len, double* chord_b, int* chord_ok, hipStream_t stream)
+{
+    int nch = n_b * n_alpha;
+    hipLaunchKernelGGL(k_chord_fill, dim3(nblk(nch, 256)), dim3(256), 0, stream, g, n_b, n_alpha, seed, tag, offsets,
+                       seg_cell, seg_len, chord_b, chord_ok);
+}
+
+int chord_tau_blocks(int nch) { return nblk(nch, kChordWaves * kChordsPerWave); }
+
+void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell, const double* seg_len,
+                      const double* chord_b, const int* chord_ok, const double* alpha, int nslot, double* partials,
+                      int nblocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_chord_tau, dim3(nblocks), dim3(256), 0, stream, nch, offsets, seg_cell, seg_len, chord_b,
+                       chord_ok, alpha, nslot, partials);
+}
+
+}  // namespace mcrt

@@ -1,0 +1,107 @@
+// Internal structures shared by the host runtime (api.cpp) and the HIP
+// kernels (kernels.hip).  Device pointers only; plain data.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcrt {
+
+constexpr int kMaxObs = 8;
+constexpr int kNCounters = 11;
+enum Counter { K_ESC = 0, K_SURF, K_ABS, K_RR, K_CAP, K_LOST, K_NINT, K_NCROSS, K_NCAPPED, K_NLOST, K_W0 };
+
+// Geometry of one resident grid.  The trigonometric edge tables are computed
+// once at upload on the host.
+struct GridDev {
+    int geom;  // 0 spherical, 1 slab
+    int nlon, nlat, nlay;
+    int max_cross;
+    const double* r;       // [nlay+1]
+    const double* lat;     // [nlat+1]
+    const double* lat_c2;  // cos^2(lat edge)
+    const double* lat_s2;  // sin^2(lat edge)
+    const double* lat_sin; // sin(lat edge)
+    const double* lon;     // [nlon+1]
+    const double* lon_s;   // sin(lon edge) [nlon]
+    const double* lon_c;   // cos(lon edge) [nlon]
+    const double* vol_r;   // (r_{k+1}^3 - r_k^3)/3 [nlay]
+    const float* T;
+    const float* P;
+    const double* rho;
+    const float* u;
+    const float* v;
+    const float* w;
+    const float* cld_ksca;
+    const float* cld_kabs;
+    const float* cld_g;
+    double omega_rot;
+};
+
+// Per-cell optical properties of one (spectral point, g) solve.
+template <typename R>
+struct OpticsDev {
+    R* a_ext;   // extinction coefficient [1/cm]
+    R* a_abs;   // absorption coefficient [1/cm]
+    R* omega;   // single-scattering albedo
+    R* p_gas;   // probability that a scattering is by gas (Rayleigh)
+    R* g_cld;   // cloud HG asymmetry
+};
+
+struct TransportArgs {
+    uint64_t seed;
+    uint64_t n_packets;
+    uint32_t tag;
+    int mode;        // 0 albedo, 1 emission
+    int scattering;
+    int absorption;  // 0 survival, 1 continuous
+    int n_obs;       // observers in obs[]; 0 = slab backscatter
+    int n_out;
+    long long max_events;
+    double rr_threshold;
+    double rr_survive;
+    double tau_peel_max;
+    double mu0;
+    double r_toa;
+    double obs[3 * kMaxObs];
+    const double* cdf;     // emission: inclusive CDF of the biased source pdf
+    const double* wbirth;  // emission: (L_i/L_tot)/q_i
+    double* partials;      // [blocks][2*n_out + kNCounters]
+    double* packet_dump;   // optional [n_packets][n_out]
+};
+
+// Launchers (kernels.hip).  All run on `stream`; none synchronises.
+void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP,
+                      const double* T_grid, const double* lnP_grid, double k_ray,
+                      OpticsDev<double> out, int ext_stride, hipStream_t stream);
+void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, double dlnlam,
+                          double* shift, hipStream_t stream);
+void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT,
+                              int nP, const double* T_grid, const double* lnP_grid,
+                              const double* k_ray, const double* shift, const int* nlist, int nslot,
+                              int slot_stride, double* alpha, hipStream_t stream);
+void launch_hires_optics(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
+                         const double* T_grid, const double* lnP_grid, double k_ray,
+                         const double* shift, int n, OpticsDev<double> out, hipStream_t stream);
+void launch_emission_sources(const GridDev& g, const OpticsDev<double>& op, double lam_cm,
+                             double tau_vert, double xi, double* L, double* cdf, double* wbirth,
+                             double* scratch, double* stats_out, hipStream_t stream);
+size_t emission_scratch_doubles(int ncell);
+void launch_transport(const GridDev& g, const OpticsDev<double>& op, const TransportArgs& a,
+                      int blocks, hipStream_t stream);
+int transport_block_size();
+void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,
+                            hipStream_t stream);
+void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
+                        int* counts, hipStream_t stream);
+void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* total_dev,
+                               hipStream_t stream);
+void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
+                       const long long* offsets, uint32_t* seg_cell, double* seg_len,
+                       double* chord_b, int* chord_ok, hipStream_t stream);
+void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell,
+                      const double* seg_len, const double* chord_b, const int* chord_ok,
+                      const double* alpha, int nslot, double* partials, int nblocks,
+                      hipStream_t stream);
+int chord_tau_blocks(int nch);
+
+}  // namespace mcrt

@@ -1,0 +1,250 @@
+"""Python binding of libmcrt.so (ctypes; argument marshalling only).
+
+Every step of the transport runs in the library's HIP kernels.  The binding
+fails loudly when the library has not been built; there is no fallback.
+Names follow include/mcrt.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcrt.so")
+
+MCRT_SPHERICAL, MCRT_PLANE_PARALLEL = 0, 1
+MCRT_SURVIVAL, MCRT_CONTINUOUS = 0, 1
+MCRT_FP64, MCRT_MIXED = 0, 1
+MCRT_OPAC_CK, MCRT_OPAC_HIRES = 0, 1
+NCOUNTERS = 11
+COUNTER_NAMES = ["escaped", "surface", "absorbed", "roulette", "capped", "lost",
+                 "n_interactions", "n_crossings", "n_capped", "n_lost", "w0"]
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTFOUND", -5: "EBUDGET",
+          -6: "EBUSY", -7: "ECANCELLED"}
+
+EXPORTED = ["mcrt_create", "mcrt_destroy", "mcrt_last_error", "mcrt_memory_in_use",
+            "mcrt_grid_upload", "mcrt_grid_free", "mcrt_opacity_upload", "mcrt_opacity_free",
+            "mcrt_default_params", "mcrt_solve_albedo", "mcrt_solve_emission",
+            "mcrt_solve_transmission"]
+
+
+class McrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+_vp, _i32, _u64, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("geometry", _i32), ("nlon", _i32), ("nlat", _i32), ("nlay", _i32),
+                ("r_edges", _vp), ("lat_edges", _vp), ("lon_edges", _vp),
+                ("T", _vp), ("P", _vp), ("rho", _vp), ("u", _vp), ("v", _vp), ("w", _vp),
+                ("cld_ksca", _vp), ("cld_kabs", _vp), ("cld_g", _vp), ("omega_rot", _dbl)]
+
+
+class OpacityDesc(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("nspec", _i32), ("ng", _i32), ("nT", _i32), ("nP", _i32),
+                ("lam_um", _vp), ("lam_min_um", _dbl), ("dlnlam", _dbl), ("g_weights", _vp),
+                ("T_grid", _vp), ("P_grid", _vp), ("kappa", _vp), ("k_ray", _vp)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("seed", _u64), ("n_packets", _u64), ("decorrelate", _i32), ("precision", _i32),
+                ("n_spec", _i32), ("spec_idx", _vp), ("n_obs", _i32), ("obs_phase", _vp),
+                ("obs_dir", _vp), ("scattering", _i32), ("absorption", _i32),
+                ("rr_threshold", _dbl), ("rr_survive", _dbl), ("emis_bias", _dbl),
+                ("tau_vert_max", _dbl), ("tau_peel_max", _dbl), ("max_events", _i64), ("mu0", _dbl),
+                ("n_b", _i32), ("n_alpha", _i32), ("r_star", _dbl), ("stream", _vp),
+                ("packet_dump", _vp)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
+                ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libmcrt.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    L.mcrt_create.argtypes = [ctypes.c_int, _u64, ctypes.POINTER(_vp)]
+    L.mcrt_destroy.argtypes = [_vp]
+    L.mcrt_destroy.restype = None
+    L.mcrt_last_error.restype = ctypes.c_char_p
+    L.mcrt_memory_in_use.argtypes = [_vp]
+    L.mcrt_memory_in_use.restype = _u64
+    L.mcrt_grid_upload.argtypes = [_vp, ctypes.POINTER(GridDesc), ctypes.POINTER(_i32)]
+    L.mcrt_grid_free.argtypes = [_vp, _i32]
+    L.mcrt_opacity_upload.argtypes = [_vp, ctypes.POINTER(OpacityDesc), ctypes.POINTER(_i32)]
+    L.mcrt_opacity_free.argtypes = [_vp, _i32]
+    L.mcrt_default_params.argtypes = [ctypes.POINTER(SolveParams)]
+    L.mcrt_default_params.restype = None
+    for nm in ("mcrt_solve_albedo", "mcrt_solve_emission", "mcrt_solve_transmission"):
+        getattr(L, nm).argtypes = [_vp, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise McrtError(rc, load().mcrt_last_error().decode())
+
+
+def _arr(a, dtype):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def default_params() -> SolveParams:
+    p = SolveParams()
+    load().mcrt_default_params(ctypes.byref(p))
+    return p
+
+
+class Context:
+    """A library context on one HIP device (owns resident grids and tables)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        L = load()
+        h = _vp()
+        _check(L.mcrt_create(device, hbm_budget_bytes, ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mcrt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def memory_in_use(self) -> int:
+        return int(load().mcrt_memory_in_use(self._h))
+
+    # ---------------------------------------------------------- uploads
+    def upload_grid(self, g) -> int:
+        """g: paper_2110_15640_amd.inputs.Grid (host numpy arrays)."""
+        arrs = dict(r=_arr(g.r_edges, np.float64), lat=_arr(g.lat_edges, np.float64),
+                    lon=_arr(g.lon_edges, np.float64), T=_arr(g.T, np.float32),
+                    P=_arr(g.P, np.float32), rho=_arr(g.rho, np.float64),
+                    u=_arr(g.u, np.float32), v=_arr(g.v, np.float32), w=_arr(g.w, np.float32),
+                    cs=_arr(g.cld_ksca, np.float32), ca=_arr(g.cld_kabs, np.float32),
+                    cg=_arr(g.cld_g, np.float32))
+        d = GridDesc(g.geometry, g.nlon, g.nlat, g.nlay, _ptr(arrs["r"]), _ptr(arrs["lat"]),
+                     _ptr(arrs["lon"]), _ptr(arrs["T"]), _ptr(arrs["P"]), _ptr(arrs["rho"]),
+                     _ptr(arrs["u"]), _ptr(arrs["v"]), _ptr(arrs["w"]), _ptr(arrs["cs"]),
+                     _ptr(arrs["ca"]), _ptr(arrs["cg"]), float(g.omega_rot))
+        gid = _i32()
+        _check(load().mcrt_grid_upload(self._h, ctypes.byref(d), ctypes.byref(gid)))
+        return gid.value
+
+    def upload_opacity(self, t) -> int:
+        """t: inputs.CKTable or inputs.HiresTable."""
+        hires = not hasattr(t, "g_weights")
+        kap = _arr(t.kappa, np.float32)
+        Tg, Pg, kr = _arr(t.T_grid, np.float64), _arr(t.P_grid, np.float64), _arr(t.k_ray, np.float64)
+        if hires:
+            d = OpacityDesc(MCRT_OPAC_HIRES, t.nlam, 1, len(Tg), len(Pg), None, float(t.lam_min_um),
+                            float(t.dlnlam), None, _ptr(Tg), _ptr(Pg), _ptr(kap), _ptr(kr))
+        else:
+            lam, gw = _arr(t.lam_um, np.float64), _arr(t.g_weights, np.float64)
+            d = OpacityDesc(MCRT_OPAC_CK, t.nband, t.ng, len(Tg), len(Pg), _ptr(lam), 0.0, 0.0, _ptr(gw),
+                            _ptr(Tg), _ptr(Pg), _ptr(kap), _ptr(kr))
+        oid = _i32()
+        _check(load().mcrt_opacity_upload(self._h, ctypes.byref(d), ctypes.byref(oid)))
+        return oid.value
+
+    def free_grid(self, gid: int):
+        _check(load().mcrt_grid_free(self._h, gid))
+
+    def free_opacity(self, oid: int):
+        _check(load().mcrt_opacity_free(self._h, oid))
+
+    # ---------------------------------------------------------- solves
+    def _params(self, kw):
+        p = default_params()
+        keep = []
+        spec_idx = kw.pop("spec_idx", None)
+        if spec_idx is not None:
+            a = _arr(spec_idx, np.int32)
+            keep.append(a)
+            p.n_spec, p.spec_idx = len(a), a.ctypes.data
+        obs_phase = kw.pop("obs_phase", None)
+        obs_dir = kw.pop("obs_dir", None)
+        if obs_dir is not None:
+            a = _arr(obs_dir, np.float64).reshape(-1, 3)
+            keep.append(a)
+            p.n_obs, p.obs_dir = len(a), a.ctypes.data
+        elif obs_phase is not None:
+            a = _arr(obs_phase, np.float64).reshape(-1)
+            keep.append(a)
+            p.n_obs, p.obs_phase = len(a), a.ctypes.data
+        stream = kw.pop("stream", None)
+        if stream is not None:
+            p.stream = getattr(stream, "cuda_stream", stream)
+        dump = kw.pop("packet_dump", None)
+        if dump is not None:
+            p.packet_dump = dump.data_ptr() if hasattr(dump, "data_ptr") else int(dump)
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown solve parameter {k!r}")
+            setattr(p, k, v)
+        return p, keep
+
+    def _solve(self, fn, gid, oid, n_spec, n_out, ng, kw):
+        p, keep = self._params(dict(kw))
+        ns = p.n_spec if p.spec_idx else n_spec
+        no = n_out(p)
+        out = dict(value=np.zeros((ns, no)), stderr=np.zeros((ns, no)), per_g=np.zeros((ns, ng, no)),
+                   sums=np.zeros((ns, ng, no, 2)), counters=np.zeros((ns, ng, NCOUNTERS)),
+                   l_tot=np.zeros((ns, ng)))
+        r = Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
+                   out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data, 0.0)
+        _check(fn(self._h, gid, oid, ctypes.byref(p), ctypes.byref(r)))
+        out["elapsed_ms"] = r.elapsed_ms
+        del keep
+        return out
+
+    def solve_albedo(self, gid, oid, table, **kw):
+        return self._solve(load().mcrt_solve_albedo, gid, oid, table.nband,
+                           lambda p: max(p.n_obs, 1), table.ng, kw)
+
+    def solve_emission(self, gid, oid, table, **kw):
+        ns = table.nband if hasattr(table, "g_weights") else table.nlam
+        ng = table.ng if hasattr(table, "g_weights") else 1
+        return self._solve(load().mcrt_solve_emission, gid, oid, ns, lambda p: p.n_obs, ng, kw)
+
+    def solve_transmission(self, gid, oid, table, **kw):
+        ns = table.nband if hasattr(table, "g_weights") else table.nlam
+        ng = table.ng if hasattr(table, "g_weights") else 1
+        return self._solve(load().mcrt_solve_transmission, gid, oid, ns, lambda p: 1, ng, kw)

@@ -1,0 +1,60 @@
+"""CPU checks of the C ABI library: it loads and exports every declared
+symbol; no compute calls (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcrt.h")
+LIB = os.path.join(ROOT, "paper_2110_15640_amd", "libmcrt.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcrt_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["mcrt_grid_upload", "mcrt_opacity_upload", "mcrt_solve_albedo", "mcrt_solve_emission",
+              "mcrt_solve_transmission", "mcrt_create", "mcrt_destroy", "mcrt_last_error"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcrt.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcrt.so not built")
+def test_binding_struct_layouts_match_header():
+    """The ctypes structs must mirror the C structs field by field."""
+    from paper_2110_15640_amd import mcrt as M
+    txt = open(HEADER).read()
+    for cname, py in [("mcrt_grid_desc", M.GridDesc), ("mcrt_opacity_desc", M.OpacityDesc),
+                      ("mcrt_solve_params", M.SolveParams), ("mcrt_result", M.Result)]:
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = [x.strip() for x in decl.split(",")]
+            fields.append(parts[0].split()[-1].lstrip("*"))
+            fields.extend(x.lstrip("*") for x in parts[1:])
+        assert [f[0] for f in py._fields_] == fields, cname
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcrt.so not built")
+def test_default_params_and_error_string_need_no_device():
+    from paper_2110_15640_amd import mcrt as M
+    p = M.default_params()
+    assert p.rr_threshold == 1e-3 and p.rr_survive == 0.1 and p.emis_bias == 0.5
+    assert p.tau_vert_max == 30.0 and p.max_events == 1000000 and p.n_b == 256 and p.n_alpha == 360
+    assert isinstance(M.load().mcrt_last_error(), bytes)

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs and the same Philox stream.
+
+FP64 per-packet peel-off sums must agree to 1e-9 relative (absolute floor
+1e-12 of the largest packet value); solve values and counters to 1e-9.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2110_15640_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2110_15640_amd import mcrt as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def dump_buffer(torch, nsolve, n, nout):
+    return torch.zeros(nsolve * n * nout, dtype=torch.float64, device="cuda:0")
+
+
+def check_packets(dump, ref, shape):
+    d = dump.cpu().numpy().reshape(shape)
+    ns, ng, n, no = shape
+    for s in range(ns):
+        for g in range(ng):
+            F = ref.extra["packets"][(s, g)][0]
+            scale = max(float(np.abs(F).max()), 1e-300)
+            bad = np.abs(d[s, g] - F) > RTOL * np.abs(F) + 1e-12 * scale
+            assert not bad.any(), (s, g, np.argwhere(bad)[:5].tolist(), d[s, g][bad][:3], F[bad][:3])
+
+
+def check_solve(got, ref, counters=True):
+    np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(got["per_g"], ref.per_g, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL, atol=1e-300)
+    if counters:
+        c_ref = ref.counters
+        np.testing.assert_allclose(got["counters"], c_ref, rtol=RTOL, atol=1e-12 * max(c_ref.max(), 1.0))
+
+
+def test_albedo_slab_parity(ctx, torch_dev):
+    _log("albedo slab parity: 10 wavelengths x 3000 packets, uniform-disk incidence")
+    grid, table = I.make_albedo_slab()
+    n = 3000  # ragged: not a multiple of the 256-lane block
+    dump = dump_buffer(torch_dev, 10, n, 1)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_albedo(gid, oid, table, n_packets=n, seed=101, packet_dump=dump)
+    ref = O.solve_albedo(grid, table, O.Params(n_packets=n, seed=101), keep_packets=True)
+    check_packets(dump, ref, (10, 1, n, 1))
+    check_solve(got, ref)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_albedo_slab_fixed_incidence_and_observers(ctx, torch_dev):
+    _log("albedo slab parity: mu0 = 0.42, 3 explicit observers, continuous absorption, clouds")
+    grid, table = I.make_albedo_slab(nlay=12, nlam=3)
+    grid.cld_ksca = np.linspace(0.0, 2e-3, 12).astype(np.float32)
+    grid.cld_kabs = np.full(12, 1e-4, np.float32)
+    grid.cld_g = np.linspace(-0.3, 0.8, 12).astype(np.float32)
+    obs = np.array([[-0.6, 0.0, 0.8], [0.28, 0.96 * 0.6, 0.96 * 0.8], [0.0, 0.6, 0.8]])
+    obs /= np.linalg.norm(obs, axis=1)[:, None]
+    n = 2000
+    for absorption in (0, 1):
+        dump = dump_buffer(torch_dev, 3, n, 3)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+        got = ctx.solve_albedo(gid, oid, table, n_packets=n, seed=7, mu0=0.42, obs_dir=obs,
+                               absorption=absorption, packet_dump=dump)
+        p = O.Params(n_packets=n, seed=7, mu0=0.42, obs_dir=obs, absorption=absorption)
+        ref = O.solve_albedo(grid, table, p, keep_packets=True)
+        check_packets(dump, ref, (3, 1, n, 3))
+        check_solve(got, ref)
+        ctx.free_grid(gid)
+        ctx.free_opacity(oid)
+
+
+def test_albedo_sphere_parity(ctx, torch_dev):
+    _log("albedo 3D sphere parity: 16x8x6 grid, 3 bands x 2 g, 3 phases")
+    grid = I.make_sphere(16, 8, 6, seed=31)
+    _, table, _ = I.make_emission_3d(16, 8, 6, nband=3, ng=2)
+    table.k_ray = table.k_ray * 1e3  # make scattering matter
+    n = 1500
+    dump = dump_buffer(torch_dev, 6, n, 3)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    phases = [0.0, 0.8, 2.2]
+    got = ctx.solve_albedo(gid, oid, table, n_packets=n, seed=33, obs_phase=phases, packet_dump=dump,
+                           decorrelate=1)
+    ref = O.solve_albedo(grid, table, O.Params(n_packets=n, seed=33, obs_phase=phases, decorrelate=True),
+                         keep_packets=True)
+    check_packets(dump, ref, (3, 2, n, 3))
+    check_solve(got, ref)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_emission_parity_with_clouds(ctx, torch_dev):
+    _log("emission 3D parity: 16x8x10 grid with HG clouds, 2 bands x 2 g, 4 phases, roulette")
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2)
+    rng = np.random.default_rng(3)
+    grid.cld_ksca = rng.uniform(0, 5e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 1e-2, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.5, 0.9, grid.ncell).astype(np.float32)
+    n = 1200
+    dump = dump_buffer(torch_dev, 4, n, 4)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=41, obs_phase=phases, packet_dump=dump,
+                             rr_threshold=0.05, rr_survive=0.3)
+    p = O.Params(n_packets=n, seed=41, obs_phase=tuple(phases), rr_threshold=0.05, rr_survive=0.3)
+    ref = O.solve_emission(grid, table, p, keep_packets=True)
+    check_packets(dump, ref, (2, 2, n, 4))
+    check_solve(got, ref)
+    np.testing.assert_allclose(got["l_tot"], ref.extra["L_tot"], rtol=1e-12)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_emission_no_scattering_and_tau_cut(ctx, torch_dev):
+    _log("emission parity: scattering off, tau_vert = 3, bias xi = 0.8")
+    grid, table, phases = I.make_emission_3d(12, 6, 8, nband=3, ng=1)
+    n = 2500
+    dump = dump_buffer(torch_dev, 3, n, 2)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=43, obs_phase=[0.5, 0.25], packet_dump=dump,
+                             scattering=0, tau_vert_max=3.0, emis_bias=0.8)
+    p = O.Params(n_packets=n, seed=43, obs_phase=(0.5, 0.25), scattering=False, tau_vert_max=3.0, emis_bias=0.8)
+    ref = O.solve_emission(grid, table, p, keep_packets=True)
+    check_packets(dump, ref, (3, 1, n, 2))
+    check_solve(got, ref)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_emission_hires_doppler_parity(ctx, torch_dev):
+    _log("hi-res emission parity: Doppler-shifted lines, 1 observer, 4 wavelengths")
+    grid, table = I.make_transmission_hires(12, 6, 8, nlam=300, nT=6, nP=5)
+    n = 1500
+    spec = [0, 7, 150, 299]
+    dump = dump_buffer(torch_dev, 4, n, 1)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=45, obs_phase=[0.4], spec_idx=spec,
+                             scattering=0, packet_dump=dump)
+    # oracle: per-wavelength Doppler optics for the observer, emission sources, transport
+    o = O.emission_obs_dirs([0.4])
+    sh = O.doppler_shift(grid, o[0], table.dlnlam)
+    d = dump.cpu().numpy().reshape(4, n)
+    for q, lam in enumerate(spec):
+        op = O.hires_optics(grid, table, lam, sh)
+        src = O.emission_sources(grid, op, table.lam_um()[lam], 30.0, 0.5)
+        F, K = O.transport(grid, op, O.Params(n_packets=n, seed=45, scattering=False), 1, o, sources=src)
+        scale = F.max()
+        assert np.all(np.abs(d[q] - F[:, 0]) <= RTOL * np.abs(F[:, 0]) + 1e-12 * scale)
+        want = src.L_tot * F[:, 0].sum() / n / grid.r_toa ** 2
+        assert got["value"][q, 0] == pytest.approx(want, rel=RTOL)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_transmission_ck_parity(ctx, torch_dev):
+    _log("transmission ck parity: 16x8x9 grid, 3 bands x 2 g, 24 x 30 chords")
+    grid, table, _ = I.make_emission_3d(16, 8, 9, nband=3, ng=2)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    kw = dict(n_b=24, n_alpha=30, seed=47, r_star=I.R_SUN)
+    got = ctx.solve_transmission(gid, oid, table, **kw)
+    ref = O.solve_transmission(grid, table, O.Params(**kw))
+    np.testing.assert_allclose(got["value"], ref.value, rtol=1e-12)
+    np.testing.assert_allclose(got["per_g"], ref.per_g, rtol=1e-12)
+    np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_transmission_hires_parity_multi_block(ctx, torch_dev):
+    _log("transmission hi-res parity: winds + rotation, 150 wavelengths (3 slot blocks), 32 x 20 chords")
+    grid, table = I.make_transmission_hires(16, 8, 10, nlam=400, nT=5, nP=6)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    spec = list(range(100, 250))
+    kw = dict(n_b=32, n_alpha=20, seed=49, r_star=I.R_SUN)
+    got = ctx.solve_transmission(gid, oid, table, spec_idx=spec, **kw)
+    ref = O.solve_transmission(grid, table, O.Params(**kw), spec_idx=spec)
+    np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL)
+    np.testing.assert_allclose(got["value"], ref.value, rtol=1e-12)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+def test_edge_cases(ctx, torch_dev):
+    _log("edge cases: one packet, no emitting cells, error codes")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, _ = I.make_emission_3d(8, 4, 5, nband=2, ng=1)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_emission(gid, oid, table, n_packets=1, seed=3, obs_phase=[0.5])
+    ref = O.solve_emission(grid, table, O.Params(n_packets=1, seed=3, obs_phase=(0.5,)))
+    np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL)
+    dark = I.CKTable(table.lam_um, table.g_weights, table.T_grid, table.P_grid,
+                     np.zeros_like(table.kappa), np.zeros_like(table.k_ray))
+    did = ctx.upload_opacity(dark)
+    got = ctx.solve_emission(gid, did, dark, n_packets=100, seed=3, obs_phase=[0.5])
+    assert np.all(got["value"] == 0.0) and np.all(got["l_tot"] == 0.0)
+    with pytest.raises(M.McrtError) as e:
+        ctx.solve_emission(gid, oid, table, n_packets=0, obs_phase=[0.5])
+    assert e.value.name == "EINVAL"
+    with pytest.raises(M.McrtError) as e:
+        ctx.solve_emission(gid + 1000, oid, table, n_packets=10, obs_phase=[0.5])
+    assert e.value.name == "ENOTFOUND"
+    slab, st = I.make_albedo_slab(nlay=4, nlam=1)
+    sid = ctx.upload_grid(slab)
+    with pytest.raises(M.McrtError) as e:
+        ctx.solve_emission(sid, oid, table, n_packets=10, obs_phase=[0.5])
+    assert e.value.name == "EINVAL"
+    bad = I.make_sphere(4, 2, 3, seed=1)
+    bad.rho = bad.rho.copy()
+    bad.rho[3] = -1.0
+    with pytest.raises(M.McrtError) as e:
+        ctx.upload_grid(bad)
+    assert e.value.name == "EINVAL"
+    bad_t = I.CKTable(table.lam_um, np.array([0.7]), table.T_grid, table.P_grid, table.kappa, table.k_ray)
+    with pytest.raises(M.McrtError) as e:
+        ctx.upload_opacity(bad_t)
+    assert e.value.name == "EINVAL"
+    with pytest.raises(M.McrtError) as e:
+        M.Context(0, hbm_budget_bytes=1024).upload_grid(grid)
+    assert e.value.name == "EBUDGET"
+    for x in (gid, sid):
+        ctx.free_grid(x)
+    for x in (oid, did):
+        ctx.free_opacity(x)
