@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Benchmark: 3D emission phase curve on one MI355X.
+
+Workload (one step = one pass of the whole hot path): a 128 x 64 x 50
+lon-lat-radius grid with a day-night temperature contrast, a 100 band x 8 g
+correlated-k table, 4 orbital phases and 1e6 packets per (band, g) solve:
+for every (band, g) the ck gather, emission sources + CDF, the transport with
+peel-off toward all 4 observers and the tally reduction, then the spectra
+F_p(band, phase).  Inputs are uploaded (resident in HBM) before timing.
+
+Prints one JSON line with packets/s, the achieved Monte Carlo error (and the
+packets needed for 1e-3 relative standard error), the transport kernel's
+roofline figure measured live with HIP events, and the FP64 oracle timed on a
+bounded sample on this host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "packets/s at 1e-3 rel. spectral error, plain vs batched; p50/p99 solve latency"
+# FP64 operations the traversal performs per cell crossing on the spherical
+# grid (exit distances to 2 shells, 2 latitude cones, 2 longitude half-planes,
+# the move and the optical-depth update); see the design doc for the breakdown.
+FLOP_PER_CROSSING = 110.0
+PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X
+PEAK_HBM = 8000.0  # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--bands", type=int, default=100, help="bands solved per step (workload: 100)")
+    ap.add_argument("--packets", type=float, default=1e6, help="packets per (band, g) (workload: 1e6)")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-packets", type=int, default=3000)
+    return ap.parse_args()
+
+
+def cpu_baseline(grid, table, phases, n_per):
+    from oracle import oracle as O  # test infrastructure: the CPU baseline leg only
+    bands = list(range(0, table.nband, max(table.nband // 10, 1)))[:10]
+    p = O.Params(n_packets=n_per, seed=211015641, obs_phase=tuple(phases))
+    t0 = time.perf_counter()
+    O.solve_emission(grid, table, p, spec_idx=bands)
+    dt = time.perf_counter() - t0
+    npk = len(bands) * table.ng * n_per
+    return {"value": npk / dt, "unit": "packets/s", "cores": int(O.lib().orc_max_threads()), "kind": "oracle",
+            "sample": f"{len(bands)} evenly spaced bands x {table.ng} g x {n_per} packets on the full "
+                      f"{grid.nlon}x{grid.nlat}x{grid.nlay} grid, 4 phases ({npk} packets, {dt:.1f} s)"}
+
+
+def run_form(ctx, M, gid, oid, table, bands, npk, phases, precision, max_batch, steps, warmup, tune):
+    kw = dict(n_packets=npk, obs_phase=list(phases), spec_idx=bands, precision=precision, profile=1,
+              seed=211015642, max_batch=max_batch, **tune)
+    for _ in range(warmup):
+        ctx.solve_emission(gid, oid, table, **kw)
+    import torch
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        res.append(ctx.solve_emission(gid, oid, table, **kw))
+        print(f"[bench]   step {s + 1}/{steps}: {res[-1]['elapsed_ms']:.1f} ms device", flush=True)
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0
+
+
+def summarize(res, wall, steps, pk_step, npk, ng):
+    value = pk_step * steps / wall
+    r = res[-1]
+    rel = (r["stderr"] / np.maximum(r["value"], 1e-300)).ravel()
+    need = npk * ng * (rel / 1e-3) ** 2  # packets per band for 1e-3 relative error
+    cross = float(sum(x["counters"][:, :, 7].sum() for x in res))
+    kms = float(sum(x["kernel_ms"] for x in res))
+    launches = int(sum(x["kernel_launches"] for x in res))
+    return value, rel, need, cross, kms, launches
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path shards by whole "
+              "(band, g) solves, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2110_15640_amd import inputs as I
+    from paper_2110_15640_amd import mcrt as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    grid, table, phases = I.make_emission_3d()
+    bands = list(range(a.bands))
+    npk = int(a.packets)
+    ctx = M.Context(0)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    pk_step = len(bands) * table.ng * npk
+    tune = {}
+    print(f"[bench] workload: {len(bands)} bands x {table.ng} g x {npk} packets, 4 phases", flush=True)
+    # warm the library's kernels and scratch once on a single band
+    ctx.solve_emission(gid, oid, table, n_packets=npk, obs_phase=list(phases), spec_idx=[0], precision=M.MCRT_MIXED)
+    print("[bench] plain form: FP64, one transport launch per (band, g)", flush=True)
+    pres, pwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_FP64, 1, a.plain_steps, 0, tune)
+    pval, prel, _, pcross, pkms, plaunch = summarize(pres, pwall, a.plain_steps, pk_step, npk, table.ng)
+    print("[bench] batched form: FP32-mixed, all (band, g) solves in persistent launches", flush=True)
+    bres, bwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_MIXED, 0, a.steps, a.warmup, tune)
+    value, rel, need, cross, kms, launches = summarize(bres, bwall, a.steps, pk_step, npk, table.ng)
+    # spectrum error of the mixed form against the FP64 form on the same random stream
+    dmix = np.abs(bres[-1]["value"] - pres[-1]["value"]) / np.abs(pres[-1]["value"])
+    ach = cross * FLOP_PER_CROSSING / (kms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "packets/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": bwall / a.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"3D emission phase curve: {grid.nlon}x{grid.nlat}x{grid.nlay} lon-lat-radius grid, "
+                               f"{len(bands)} bands x {table.ng} g correlated-k (log-normal k), 4 phases, "
+                               f"{npk} packets per (band, g)",
+                   "form": "batched FP32-mixed persistent", "packets_per_step": pk_step,
+                   "crossings_per_step": cross / a.steps},
+        "plain": {"value": pval, "unit": "packets/s", "dtype": "f64", "steps": a.plain_steps,
+                  "ms_per_step": pwall / a.plain_steps * 1e3, "launches_per_step": plaunch // a.plain_steps,
+                  "kernel_ms_per_step": pkms / a.plain_steps},
+        "batched_over_plain": value / pval,
+        "error": {"rel_se_median": float(np.median(rel)), "rel_se_max": float(rel.max()),
+                  "packets_per_band_for_1e-3_median": float(np.median(need)),
+                  "seconds_per_band_for_1e-3_median_batched": float(np.median(need)) / value,
+                  "seconds_per_band_for_1e-3_median_plain": float(np.median(need)) / pval,
+                  "mixed_vs_fp64_rel_max": float(dmix.max()), "mixed_vs_fp64_rel_median": float(np.median(dmix))},
+        "roofline": {"bound": "alu", "kernel": "k_transport_persistent<MIXED>", "achieved": ach,
+                     "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR, "traffic": None,
+                     "avg_launch_ms": kms / max(launches, 1), "launches": launches,
+                     "flop_per_crossing": FLOP_PER_CROSSING},
+    }
+    if a.cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", flush=True)
+        out["cpu_baseline"] = cpu_baseline(grid, table, phases, a.cpu_packets)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

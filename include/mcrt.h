@@ -165,7 +165,15 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  * stream: hipStream_t to run on (NULL = the context's own stream).
  * packet_dump: optional DEVICE buffer of doubles receiving each packet's
  *   peel-off sum per observer, [solve][packet][observer] with solves ordered
- *   (spec, g); NULL = none. */
+ *   (spec, g); NULL = none.
+ * profile: non-zero times every launch of the dominant kernel (transport for
+ *   albedo/emission, chord optical depth for transmission) with HIP events on
+ *   the solve's stream; see mcrt_result.kernel_ms.
+ * max_batch: (spectral point, g) solves per persistent transport launch;
+ *   1 = one launch per solve, 0 = as many as the HBM budget allows.
+ * tune_ev_threshold, tune_blocks_per_cu, tune_wave_batch: launch shape of the
+ *   persistent transport (lanes waiting before events are handled, 256-lane
+ *   blocks per compute unit, packets a wave takes at once); 0 = default. */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -190,6 +198,11 @@ typedef struct {
     double r_star;
     void* stream;
     double* packet_dump;
+    int32_t profile;
+    int32_t max_batch;
+    int32_t tune_ev_threshold;
+    int32_t tune_blocks_per_cu;
+    int32_t tune_wave_batch;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);
@@ -203,7 +216,9 @@ void mcrt_default_params(mcrt_solve_params* p);
  * sums[n_spec][ng][n_obs][2] raw (sum F, sum F^2) over packets;
  * counters[n_spec][ng][MCRT_NCOUNTERS];
  * l_tot[n_spec][ng]        emission: L_tot [erg/s/cm].
- * elapsed_ms receives the device time of the solve. */
+ * elapsed_ms receives the device time of the solve; with params.profile,
+ * kernel_ms and kernel_launches the summed duration and count of the
+ * dominant kernel's launches. */
 typedef struct {
     double* value;
     double* stderr_;
@@ -212,6 +227,8 @@ typedef struct {
     double* counters;
     double* l_tot;
     double elapsed_ms;
+    double kernel_ms;
+    int64_t kernel_launches;
 } mcrt_result;
 
 /* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /

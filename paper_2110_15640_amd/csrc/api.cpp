@@ -67,6 +67,7 @@ struct OpacRes {
 
 struct mcrt_ctx {
     int device = 0;
+    int n_cu = 256;
     uint64_t budget = 0;
     uint64_t in_use = 0;
     hipStream_t stream = nullptr;
@@ -76,6 +77,7 @@ struct mcrt_ctx {
     std::map<int32_t, std::unique_ptr<OpacRes>> opacs;
     int32_t next_grid = 1, next_opac = 1;
     bool poisoned = false;
+    std::vector<hipEvent_t> prof_ev;  // pairs around timed launches
     // grow-only scratch arena per role
     std::map<std::string, DevBuf> scratch;
 };
@@ -371,6 +373,30 @@ void fill_results(const SolvePlan& pl, const std::vector<double>& perg_val, cons
     if (r->l_tot) std::copy(ltot.begin(), ltot.end(), r->l_tot);
 }
 
+// Timed-launch bracket: events 2i and 2i+1 around the i-th launch.
+int prof_events(mcrt_ctx* ctx, size_t n_launch)
+{
+    while (ctx->prof_ev.size() < 2 * n_launch) {
+        hipEvent_t e;
+        HIPTRY(hipEventCreate(&e));
+        ctx->prof_ev.push_back(e);
+    }
+    return MCRT_OK;
+}
+
+int prof_collect(mcrt_ctx* ctx, size_t n_launch, mcrt_result* r)
+{
+    double tot = 0.0;
+    for (size_t i = 0; i < n_launch; ++i) {
+        float ms = 0.0f;
+        HIPTRY(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+        tot += ms;
+    }
+    r->kernel_ms = tot;
+    r->kernel_launches = (int64_t)n_launch;
+    return MCRT_OK;
+}
+
 int finish_timing(mcrt_ctx* ctx, hipStream_t st, mcrt_result* r)
 {
     HIPTRY(hipEventRecord(ctx->ev1, st));
@@ -381,8 +407,10 @@ int finish_timing(mcrt_ctx* ctx, hipStream_t st, mcrt_result* r)
     return MCRT_OK;
 }
 
-// Albedo and emission: per (spec, g) solve: optics -> [sources] -> transport
-// -> fixed-order tally reduction into one row of the device sums table.
+// Albedo and emission.  The (spec, g) solves are grouped into batches; per
+// batch every solve gets its own optics (and emission CDF) slot, then one
+// persistent transport launch runs all their packets and a fixed-order
+// reduction turns the packet rows into one tally row per solve.
 int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res, int mode)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -399,42 +427,60 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
         return fail(MCRT_EINVAL, "albedo solves take a correlated-k table");
     if (op->kind == MCRT_OPAC_HIRES && pl.n_out != 1)
         return fail(MCRT_EINVAL, "high-resolution emission is Doppler-shifted per observer: pass one observer per call");
+    if (p->max_batch < 0 || p->tune_ev_threshold < 0 || p->tune_ev_threshold > 64 || p->tune_blocks_per_cu < 0 ||
+        p->tune_blocks_per_cu > 16 || p->tune_wave_batch < 0)
+        return fail(MCRT_EINVAL, "bad batching / tuning parameters");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
+    const bool mixed = p->precision == MCRT_MIXED;
     const int ncell = g->ncell;
     const int ns = (int)pl.specs.size(), ng = pl.ng, nsolve = ns * ng;
-    const int row_w = 2 * pl.n_out + kNCounters + 2;  // + (L_tot, N_emit)
-    const int part_w = 2 * pl.n_out + kNCounters;
+    const int no = pl.n_out;
+    const int pw = 2 * no + kNCounters;  // tally columns
+    const int row_w = pw + 2;           // + (L_tot, N_emit)
+    const int prow = no + kNCounters;   // packet row
     const uint64_t N = p->n_packets;
-    const int tb = transport_block_size();
-    const long long nblocks_ll = (long long)((N + tb - 1) / tb);
-    if (nblocks_ll > (1LL << 31) - 1) return fail(MCRT_EINVAL, "too many packets for one launch");
-    const int nblocks = (int)nblocks_ll;
 
-    void *v_opt, *v_part, *v_sums, *v_L, *v_cdf, *v_wb, *v_es, *v_shift = nullptr;
-    if ((rc = scratch(ctx, "optics", sizeof(double) * 5 * (size_t)ncell, &v_opt))) return rc;
-    if ((rc = scratch(ctx, "partials", sizeof(double) * (size_t)nblocks * part_w, &v_part))) return rc;
+    // per-solve device footprint and the batch size the budget allows
+    const size_t opt_b = (size_t)ncell * 5 * (mixed ? sizeof(float) : sizeof(double));
+    const size_t src_b = mode == MCRT_MODE_EMISSION ? (size_t)ncell * 2 * sizeof(double) : 0;
+    const size_t row_b = (size_t)N * prow * sizeof(double);
+    const size_t per_solve = opt_b + src_b + row_b;
+    int batch = p->max_batch > 0 ? p->max_batch : nsolve;
+    {
+        uint64_t room = ctx->budget > ctx->in_use ? ctx->budget - ctx->in_use : 0;
+        uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
+        int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
+        batch = std::max(1, std::min(std::min(batch, fit), nsolve));
+    }
+    const int chunks = reduce_rows_chunks(N);
+    void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_L = nullptr, *v_es = nullptr,
+                 *v_shift = nullptr, *v_solves, *v_ctr;
+    if ((rc = scratch(ctx, "optics", sizeof(double) * 5 * (size_t)ncell * (mixed ? 1 : batch), &v_opt))) return rc;
+    if (mixed && (rc = scratch(ctx, "optics_f32", opt_b * batch, &v_optf))) return rc;
+    if ((rc = scratch(ctx, "rows", row_b * batch, &v_rows))) return rc;
     if ((rc = scratch(ctx, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if ((rc = scratch(ctx, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
+    if ((rc = scratch(ctx, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
+    if ((rc = scratch(ctx, "dispenser", 64, &v_ctr))) return rc;
     if (mode == MCRT_MODE_EMISSION) {
+        if ((rc = scratch(ctx, "sources", src_b * batch, &v_src))) return rc;
         if ((rc = scratch(ctx, "L", sizeof(double) * (size_t)ncell, &v_L))) return rc;
-        if ((rc = scratch(ctx, "cdf", sizeof(double) * (size_t)ncell, &v_cdf))) return rc;
-        if ((rc = scratch(ctx, "wbirth", sizeof(double) * (size_t)ncell, &v_wb))) return rc;
         if ((rc = scratch(ctx, "em_scratch", sizeof(double) * emission_scratch_doubles(ncell), &v_es))) return rc;
     }
     if (op->kind == MCRT_OPAC_HIRES)
         if ((rc = scratch(ctx, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
-    double* opt = (double*)v_opt;
-    OpticsDev<double> od{opt, opt + ncell, opt + 2 * (size_t)ncell, opt + 3 * (size_t)ncell, opt + 4 * (size_t)ncell};
     double* sums = (double*)v_sums;
 
-    TransportArgs A{};
+    BatchArgs A{};
+    A.counter = (unsigned long long*)v_ctr;
+    A.rows = (double*)v_rows;
+    A.row_w = prow;
     A.seed = p->seed;
-    A.n_packets = N;
-    A.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
     A.scattering = p->scattering ? 1 : 0;
     A.absorption = p->absorption;
     A.n_obs = pl.n_obs;
-    A.n_out = pl.n_out;
+    A.n_out = no;
     A.max_events = p->max_events;
     A.rr_threshold = p->rr_threshold;
     A.rr_survive = p->rr_survive;
@@ -442,20 +488,31 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
     A.mu0 = p->mu0;
     A.r_toa = g->r_toa;
     for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[q] = pl.obs[q];
-    A.partials = (double*)v_part;
-    if (mode == MCRT_MODE_EMISSION) {
-        A.cdf = (double*)v_cdf;
-        A.wbirth = (double*)v_wb;
-    }
+    A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
+    A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
+    const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 2;
+    const int pblocks = ctx->n_cu * bpc;
 
+    const bool prof = p->profile != 0;
+    const int nbatches = (nsolve + batch - 1) / batch;
+    if (prof && (rc = prof_events(ctx, (size_t)nbatches))) return rc;
+    res->kernel_ms = 0.0;
+    res->kernel_launches = 0;
+    std::vector<std::vector<SolveDev>> host_solves(nbatches);
     HIPTRY(hipEventRecord(ctx->ev0, st));
     HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
     if (op->kind == MCRT_OPAC_HIRES)
         launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
-    for (int s = 0; s < ns; ++s) {
-        int b = pl.specs[s];
-        for (int gi = 0; gi < ng; ++gi) {
-            int sg = s * ng + gi;
+    for (int bt = 0; bt < nbatches; ++bt) {
+        const int s0 = bt * batch, s1 = std::min(nsolve, s0 + batch);
+        std::vector<SolveDev>& hsv = host_solves[bt];
+        hsv.resize(s1 - s0);
+        for (int sg = s0; sg < s1; ++sg) {
+            const int slot = sg - s0;
+            const int b = pl.specs[sg / ng], gi = sg % ng;
+            double* o64 = (double*)v_opt + (mixed ? 0 : (size_t)slot * 5 * ncell);
+            OpticsDev<double> od{o64, o64 + ncell, o64 + 2 * (size_t)ncell, o64 + 3 * (size_t)ncell,
+                                 o64 + 4 * (size_t)ncell};
             if (op->kind == MCRT_OPAC_CK) {
                 const double* tab = op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP;
                 launch_ck_optics(g->dev, ncell, tab, op->nT, op->nP, op->T_grid, op->lnP_grid, op->k_ray[b], od, 1, st);
@@ -463,25 +520,51 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
                 launch_hires_optics(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
                                     op->k_ray[b], (double*)v_shift, b, od, st);
             }
-            double* row = sums + (size_t)sg * row_w;
+            SolveDev& S = hsv[slot];
+            S.begin = (unsigned long long)slot * N;
+            S.n = N;
+            S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
+            S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
+            S.cdf = nullptr;
+            S.wbirth = nullptr;
             if (mode == MCRT_MODE_EMISSION) {
+                double* cdf = (double*)v_src + (size_t)slot * 2 * ncell;
+                double* wb = cdf + ncell;
                 double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
-                launch_emission_sources(g->dev, od, lam * 1e-4, p->tau_vert_max, p->emis_bias, (double*)v_L,
-                                        (double*)v_cdf, (double*)v_wb, (double*)v_es, row + part_w, st);
+                launch_emission_sources(g->dev, od, lam * 1e-4, p->tau_vert_max, p->emis_bias, (double*)v_L, cdf, wb,
+                                        (double*)v_es, sums + (size_t)sg * row_w + pw, st);
+                S.cdf = cdf;
+                S.wbirth = wb;
             }
-            A.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
-            A.packet_dump = p->packet_dump ? p->packet_dump + (size_t)sg * N * pl.n_out : nullptr;
-            launch_transport(g->dev, od, A, nblocks, st);
-            launch_reduce_partials((double*)v_part, nblocks, part_w, row, st);
+            if (mixed) {
+                float* o32 = (float*)v_optf + (size_t)slot * 5 * ncell;
+                OpticsDev<float> of{o32, o32 + ncell, o32 + 2 * (size_t)ncell, o32 + 3 * (size_t)ncell,
+                                    o32 + 4 * (size_t)ncell};
+                launch_mixed_optics(od, of, ncell, st);
+                S.a_ext = of.a_ext; S.a_abs = of.a_abs; S.omega = of.omega; S.p_gas = of.p_gas; S.g_cld = of.g_cld;
+            } else {
+                S.a_ext = od.a_ext; S.a_abs = od.a_abs; S.omega = od.omega; S.p_gas = od.p_gas; S.g_cld = od.g_cld;
+            }
         }
+        HIPTRY(hipMemcpyAsync(v_solves, hsv.data(), sizeof(SolveDev) * hsv.size(), hipMemcpyHostToDevice, st));
+        A.solves = (const SolveDev*)v_solves;
+        A.n_solves = s1 - s0;
+        A.total = (unsigned long long)(s1 - s0) * N;
+        launch_fill_u64(A.counter, 0ULL, st);
+        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * bt], st));
+        launch_transport_persistent(g->dev, A, mixed, pblocks, st);
+        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * bt + 1], st));
+        double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
+        launch_reduce_rows(A, nullptr, s1 - s0, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
+        if (bt + 1 < nbatches) HIPTRY(hipStreamSynchronize(st));  // slots are reused by the next batch
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nsolve * row_w);
     HIPTRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     if ((rc = finish_timing(ctx, st, res))) return rc;
+    if (prof && (rc = prof_collect(ctx, (size_t)nbatches, res))) return rc;
 
     // Post-processing (Sect. 5.2 A_g = pi E; Sect. 5.3 F_p = L_tot/(N R_TOA^2) sum F)
-    const int no = pl.n_out;
     std::vector<double> val((size_t)nsolve * no), se((size_t)nsolve * no), cnt((size_t)nsolve * kNCounters),
         ltot(nsolve);
     const double Nd = (double)N;
@@ -491,8 +574,8 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
         if (mode == MCRT_MODE_ALBEDO) {
             scale = kPi;
         } else {
-            ltot[sg] = row[part_w];
-            scale = row[part_w] / (g->r_toa * g->r_toa);
+            ltot[sg] = row[pw];
+            scale = row[pw] / (g->r_toa * g->r_toa);
         }
         for (int o = 0; o < no; ++o) {
             double m = row[2 * o] / Nd;
@@ -500,14 +583,10 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
             val[(size_t)sg * no + o] = scale * m;
             se[(size_t)sg * no + o] = scale * std::sqrt(var);
         }
+        for (int t = 0; t < kNCounters; ++t) cnt[(size_t)sg * kNCounters + t] = row[2 * no + t];
     }
-    // counters sit right after the 2*n_out sums
-    for (int sg = 0; sg < nsolve; ++sg)
-        for (int t = 0; t < kNCounters; ++t)
-            cnt[(size_t)sg * kNCounters + t] = hs[(size_t)sg * row_w + 2 * no + t];
     std::vector<double> gw = op->kind == MCRT_OPAC_CK ? op->g_weights : std::vector<double>{1.0};
-    std::vector<double> sumrows(hs);
-    fill_results(pl, val, se, gw, sumrows, row_w, cnt, ltot, res);
+    fill_results(pl, val, se, gw, hs, row_w, cnt, ltot, res);
     return MCRT_OK;
 }
 
@@ -547,6 +626,11 @@ int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_param
         if ((rc = scratch(ctx, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
     }
     const uint32_t tag = 0;  // chords are common to all spectral points
+    const bool prof = p->profile != 0;
+    const int nblk_rows = (nrow + kSlot - 1) / kSlot;
+    if (prof && (rc = prof_events(ctx, (size_t)nblk_rows))) return rc;
+    res->kernel_ms = 0.0;
+    res->kernel_launches = 0;
     HIPTRY(hipEventRecord(ctx->ev0, st));
     launch_chord_count(g->dev, p->n_b, p->n_alpha, p->seed, tag, (int*)v_cnt, st);
     launch_exclusive_scan_int((int*)v_cnt, (long long*)v_off, nch, nullptr, st);
@@ -577,14 +661,17 @@ int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_param
             launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
                                      op->k_ray_dev, (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
+        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * (r0 / kSlot)], st));
         launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok, alpha,
                          nslot, (double*)v_part, tblocks, st);
+        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * (r0 / kSlot) + 1], st));
         launch_reduce_partials((double*)v_part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nrow * 2);
     HIPTRY(hipMemcpyAsync(hs.data(), v_sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     if ((rc = finish_timing(ctx, st, res))) return rc;
+    if (prof && (rc = prof_collect(ctx, (size_t)nblk_rows, res))) return rc;
 
     // (R_p/R*)^2 = (R0^2 + 2 <I>)/R*^2, <I> = (R_TOA - R0)/N sum (1 - e^-tau) b  (Sect. 5.1)
     const double dr = g->r_toa - g->r0, Nd = (double)nch, rs2 = p->r_star * p->r_star;
@@ -626,6 +713,9 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
     e = hipMemGetInfo(&fr, &tot);
     if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
     ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->n_cu = prop.multiProcessorCount;
     if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
         return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
@@ -644,6 +734,7 @@ void mcrt_destroy(mcrt_ctx* ctx)
     for (auto& kv : ctx->opacs)
         for (auto& b : kv.second->bufs) dev_free(ctx, b);
     for (auto& kv : ctx->scratch) dev_free(ctx, kv.second);
+    for (auto e : ctx->prof_ev) (void)hipEventDestroy(e);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);

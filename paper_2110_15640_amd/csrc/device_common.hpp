@@ -1,0 +1,370 @@
+// Device building blocks shared by the HIP kernels: the Philox4x32-10 draw
+// keyed by (packet, event, block), phase functions and their samplers
+// (Sect. 3), direction rotation, the spherical / slab cell traversal
+// (Sect. 2) and the opacity-table interpolation (Sect. 7).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mcrt_internal.hpp"
+
+namespace mcrt {
+namespace dev {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kH = 6.62607015e-27;
+constexpr double kC = 2.99792458e10;
+constexpr double kKB = 1.380649e-16;
+
+// ---------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon et al. 2011): counter (packet lo, packet hi, event,
+// block), key (seed lo, seed hi ^ tag).
+struct U2 {
+    double a, b;
+};
+
+__device__ __forceinline__ U2 draw(uint64_t seed, uint32_t tag, uint64_t packet, uint32_t event,
+                                   uint32_t block)
+{
+    uint32_t c0 = (uint32_t)packet, c1 = (uint32_t)(packet >> 32), c2 = event, c3 = block;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ tag;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    U2 u;
+    uint64_t ma = ((uint64_t)c0 << 20) | (uint64_t)(c1 >> 12);
+    uint64_t mb = ((uint64_t)c2 << 20) | (uint64_t)(c3 >> 12);
+    u.a = ((double)ma + 0.5) * (1.0 / 4503599627370496.0);
+    u.b = ((double)mb + 0.5) * (1.0 / 4503599627370496.0);
+    return u;
+}
+
+// ---------------------------------------------------------------- phase functions
+__device__ __forceinline__ double p_rayleigh(double mu) { return 0.75 * (1.0 + mu * mu); }
+
+__device__ __forceinline__ double p_hg(double mu, double g)
+{
+    if (fabs(g) < 1e-6) return 1.0;
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (den * sqrt(den));
+}
+
+// Rayleigh: Cardano root of mu^3 + 3 mu = 2 (4 zeta - 2), the inverse of the
+// CDF (mu^3 + 3 mu + 4)/8 of the normalised phase function.
+__device__ __forceinline__ double sample_rayleigh(double z)
+{
+    double q = 4.0 * z - 2.0;
+    double u = cbrt(q + sqrt(q * q + 1.0));
+    double mu = u - 1.0 / u;
+    return fmin(fmax(mu, -1.0), 1.0);
+}
+
+__device__ __forceinline__ double sample_hg(double z, double g)
+{
+    double mu;
+    if (fabs(g) < 1e-6) {
+        mu = 2.0 * z - 1.0;
+    } else {
+        double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * z);
+        mu = (1.0 + g * g - t * t) / (2.0 * g);
+    }
+    return fmin(fmax(mu, -1.0), 1.0);
+}
+
+__device__ __forceinline__ void rotate_dir(double& dx, double& dy, double& dz, double mu, double psi)
+{
+    double st = sqrt(fmax(1.0 - mu * mu, 0.0));
+    double cp = cos(psi), sp = sin(psi);
+    double nx, ny, nz;
+    if (fabs(dz) < 0.99999) {
+        double t = sqrt(1.0 - dz * dz);
+        nx = st * (dx * dz * cp - dy * sp) / t + dx * mu;
+        ny = st * (dy * dz * cp + dx * sp) / t + dy * mu;
+        nz = -st * cp * t + dz * mu;
+    } else {
+        double sgn = dz >= 0.0 ? 1.0 : -1.0;
+        nx = st * cp;
+        ny = st * sp;
+        nz = sgn * mu;
+    }
+    double n = sqrt(nx * nx + ny * ny + nz * nz);
+    dx = nx / n;
+    dy = ny / n;
+    dz = nz / n;
+}
+
+// ---------------------------------------------------------------- geometry
+enum { F_NONE = -1, F_OUT = 0, F_IN = 1, F_LATLO = 2, F_LATHI = 3, F_LONLO = 4, F_LONHI = 5 };
+enum { T_INTERACT = 0, T_ESCAPE = 1, T_SURFACE = 2, T_LOST = 3 };
+
+struct Ray {
+    double x, y, z;
+    int i, j, k;
+    int ef;
+};
+
+__device__ __forceinline__ int find_edge(const double* e, int n, double x)
+{
+    // largest m in [0, n-1] with e[m] <= x, 0 if none (edges increasing)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (e[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Distance to the latitude cone (the equatorial plane when tb == 0) of an
+// edge with cos^2 = c2, sin^2 = s2; roots below lo ignored; hits must be on
+// the nappe whose z has the sign of tb.
+__device__ __forceinline__ double cone_distance(const Ray& p, double dx, double dy, double dz, double tb,
+                                                double c2, double s2, double lo)
+{
+    double best = INFINITY;
+    if (tb == 0.0) {
+        if (dz != 0.0) {
+            double s = -p.z / dz;
+            if (s >= lo) best = s;
+        }
+        return best;
+    }
+    double a = dz * dz * c2 - (dx * dx + dy * dy) * s2;
+    double b = p.z * dz * c2 - (p.x * dx + p.y * dy) * s2;
+    double c = p.z * p.z * c2 - (p.x * p.x + p.y * p.y) * s2;
+    double r0 = -1.0, r1 = -1.0;
+    bool h0 = false, h1 = false;
+    if (a == 0.0) {
+        if (b != 0.0) {
+            r0 = -c / (2.0 * b);
+            h0 = true;
+        }
+    } else {
+        double disc = b * b - a * c;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -(b + (b >= 0.0 ? sq : -sq));
+            r0 = q / a;
+            h0 = true;
+            if (q != 0.0) {
+                r1 = c / q;
+                h1 = true;
+            }
+        }
+    }
+    if (h0 && r0 >= lo) {
+        double zh = p.z + r0 * dz;
+        bool ok = tb > 0.0 ? (zh > 0.0) : (zh < 0.0);
+        if (ok && r0 < best) best = r0;
+    }
+    if (h1 && r1 >= lo) {
+        double zh = p.z + r1 * dz;
+        bool ok = tb > 0.0 ? (zh > 0.0) : (zh < 0.0);
+        if (ok && r1 < best) best = r1;
+    }
+    return best;
+}
+
+// Distance to leave the current cell along d; returns the face (ties in the
+// order outer, inner, lat-low, lat-high, lon-low, lon-high).
+__device__ __forceinline__ int exit_distance(const GridDev& g, const Ray& p, double dx, double dy,
+                                             double dz, double& s_out)
+{
+    if (g.geom == 1) {
+        if (dz > 0.0) {
+            double s = (g.r[p.k + 1] - p.z) / dz;
+            s_out = s < 0.0 ? 0.0 : s;
+            return F_OUT;
+        }
+        if (dz < 0.0) {
+            double s = (g.r[p.k] - p.z) / dz;
+            s_out = s < 0.0 ? 0.0 : s;
+            return F_IN;
+        }
+        s_out = INFINITY;
+        return F_NONE;
+    }
+    double rr = p.x * p.x + p.y * p.y + p.z * p.z;
+    double B = p.x * dx + p.y * dy + p.z * dz;
+    double best;
+    int face;
+    {
+        double ro = g.r[p.k + 1];
+        double C = rr - ro * ro;
+        double D = B * B - C;
+        if (D < 0.0) D = 0.0;
+        double s = (B <= 0.0) ? (-B + sqrt(D)) : (-C / (B + sqrt(D)));
+        if (s < 0.0) s = 0.0;
+        best = s;
+        face = F_OUT;
+    }
+    if (B < 0.0) {
+        double ri = g.r[p.k];
+        double C = rr - ri * ri;
+        double D = B * B - C;
+        if (D >= 0.0) {
+            double s = C / (-B + sqrt(D));
+            if (s < 0.0) s = 0.0;
+            if (s < best) {
+                best = s;
+                face = F_IN;
+            }
+        }
+    }
+    double tol = 1e-9 * sqrt(rr);
+    if (p.j > 0) {
+        int e = p.j;
+        double s = cone_distance(p, dx, dy, dz, g.lat[e], g.lat_c2[e], g.lat_s2[e],
+                                 p.ef == F_LATLO ? tol : 0.0);
+        if (s < best) {
+            best = s;
+            face = F_LATLO;
+        }
+    }
+    if (p.j < g.nlat - 1) {
+        int e = p.j + 1;
+        double s = cone_distance(p, dx, dy, dz, g.lat[e], g.lat_c2[e], g.lat_s2[e],
+                                 p.ef == F_LATHI ? tol : 0.0);
+        if (s < best) {
+            best = s;
+            face = F_LATHI;
+        }
+    }
+    if (g.nlon > 1) {
+        {
+            double sb = g.lon_s[p.i], cb = g.lon_c[p.i];
+            double nx = -sb, ny = cb;
+            double dn = dx * nx + dy * ny;
+            if (dn < 0.0) {
+                double s = -(p.x * nx + p.y * ny) / dn;
+                if (s < 0.0) s = 0.0;
+                double hx = p.x + s * dx, hy = p.y + s * dy;
+                if (cb * hx + sb * hy > 0.0 && s < best) {
+                    best = s;
+                    face = F_LONLO;
+                }
+            }
+        }
+        {
+            int iu = p.i + 1 == g.nlon ? 0 : p.i + 1;
+            double sb = g.lon_s[iu], cb = g.lon_c[iu];
+            double nx = -sb, ny = cb;
+            double dn = dx * nx + dy * ny;
+            if (dn > 0.0) {
+                double s = -(p.x * nx + p.y * ny) / dn;
+                if (s < 0.0) s = 0.0;
+                double hx = p.x + s * dx, hy = p.y + s * dy;
+                if (cb * hx + sb * hy > 0.0 && s < best) {
+                    best = s;
+                    face = F_LONHI;
+                }
+            }
+        }
+    }
+    s_out = best;
+    return face;
+}
+
+__device__ __forceinline__ void advance(const GridDev& g, Ray& p, double dx, double dy, double dz, double s)
+{
+    if (g.geom == 1) {
+        p.z = p.z + s * dz;
+    } else {
+        p.x = p.x + s * dx;
+        p.y = p.y + s * dy;
+        p.z = p.z + s * dz;
+    }
+}
+
+__device__ __forceinline__ void cross(const GridDev& g, Ray& p, int f)
+{
+    switch (f) {
+    case F_OUT:
+        p.k += 1;
+        p.ef = F_IN;
+        if (g.geom == 1 && p.k <= g.nlay) p.z = g.r[p.k];
+        break;
+    case F_IN:
+        p.k -= 1;
+        p.ef = F_OUT;
+        if (g.geom == 1 && p.k >= -1) p.z = g.r[p.k + 1];
+        break;
+    case F_LATLO: p.j -= 1; p.ef = F_LATHI; break;
+    case F_LATHI: p.j += 1; p.ef = F_LATLO; break;
+    case F_LONLO: p.i = p.i == 0 ? g.nlon - 1 : p.i - 1; p.ef = F_LONHI; break;
+    case F_LONHI: p.i = p.i + 1 == g.nlon ? 0 : p.i + 1; p.ef = F_LONLO; break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ int cell_of(const GridDev& g, const Ray& p)
+{
+    return (p.k * g.nlat + p.j) * g.nlon + p.i;
+}
+
+__device__ __forceinline__ void locate_column(const GridDev& g, Ray& p)
+{
+    double lat = atan2(p.z, sqrt(p.x * p.x + p.y * p.y));
+    double lon = atan2(p.y, p.x);
+    p.j = find_edge(g.lat, g.nlat, lat);
+    p.i = find_edge(g.lon, g.nlon, lon);
+}
+
+// ---------------------------------------------------------------- opacity interpolation
+struct Bracket {
+    int i0, i1;
+    double t;
+};
+
+__device__ __forceinline__ Bracket bracket(const double* gx, int n, double x)
+{
+    Bracket b;
+    if (n == 1) {
+        b.i0 = 0; b.i1 = 0; b.t = 0.0;
+        return b;
+    }
+    if (x <= gx[0]) {
+        b.i0 = 0; b.i1 = 1; b.t = 0.0;
+        return b;
+    }
+    if (x >= gx[n - 1]) {
+        b.i0 = n - 2; b.i1 = n - 1; b.t = 1.0;
+        return b;
+    }
+    int m = find_edge(gx, n - 1, x);
+    b.i0 = m;
+    b.i1 = m + 1;
+    b.t = (x - gx[m]) / (gx[m + 1] - gx[m]);
+    return b;
+}
+
+// ln-kappa bilinear in (T, ln P); a -inf (zero kappa) corner with positive
+// weight gives zero.  lnk(iT, iP) read through the accessor.
+template <typename F>
+__device__ __forceinline__ double interp_tp(F lnk, const Bracket& bt, const Bracket& bp)
+{
+    double t = bt.t, u = bp.t;
+    double w0 = (1.0 - t) * (1.0 - u), w1 = (1.0 - t) * u, w2 = t * (1.0 - u), w3 = t * u;
+    double acc = 0.0;
+    if (w0 > 0.0) { double l = lnk(bt.i0, bp.i0); if (isinf(l)) return 0.0; acc = acc + w0 * l; }
+    if (w1 > 0.0) { double l = lnk(bt.i0, bp.i1); if (isinf(l)) return 0.0; acc = acc + w1 * l; }
+    if (w2 > 0.0) { double l = lnk(bt.i1, bp.i0); if (isinf(l)) return 0.0; acc = acc + w2 * l; }
+    if (w3 > 0.0) { double l = lnk(bt.i1, bp.i1); if (isinf(l)) return 0.0; acc = acc + w3 * l; }
+    return exp(acc);
+}
+
+
+}  // namespace dev
+}  // namespace mcrt

@@ -47,14 +47,33 @@ struct OpticsDev {
     R* g_cld;   // cloud HG asymmetry
 };
 
-struct TransportArgs {
-    uint64_t seed;
-    uint64_t n_packets;
+// One (spectral point, g) solve inside a persistent transport launch.
+// Optical-property arrays are double (FP64) or float (MIXED).
+struct SolveDev {
+    const void* a_ext;
+    const void* a_abs;
+    const void* omega;
+    const void* p_gas;
+    const void* g_cld;
+    const double* cdf;     // emission only
+    const double* wbirth;  // emission only
+    unsigned long long begin;  // global index of the solve's first packet
+    unsigned long long n;      // packets of the solve
     uint32_t tag;
-    int mode;        // 0 albedo, 1 emission
+    int mode;  // 0 albedo, 1 emission
+};
+
+struct BatchArgs {
+    const SolveDev* solves;
+    int n_solves;
+    unsigned long long total;     // packets over all solves
+    unsigned long long* counter;  // packet dispenser
+    double* rows;                 // [total][row_w]: F per observer, then counters
+    int row_w;
+    uint64_t seed;
     int scattering;
-    int absorption;  // 0 survival, 1 continuous
-    int n_obs;       // observers in obs[]; 0 = slab backscatter
+    int absorption;
+    int n_obs;
     int n_out;
     long long max_events;
     double rr_threshold;
@@ -63,11 +82,18 @@ struct TransportArgs {
     double mu0;
     double r_toa;
     double obs[3 * kMaxObs];
-    const double* cdf;     // emission: inclusive CDF of the biased source pdf
-    const double* wbirth;  // emission: (L_i/L_tot)/q_i
-    double* partials;      // [blocks][2*n_out + kNCounters]
-    double* packet_dump;   // optional [n_packets][n_out]
+    int batch;         // packets a wave takes from the dispenser at once
+    int ev_threshold;  // waiting lanes that trigger event handling
 };
+
+void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks,
+                                 hipStream_t stream);
+void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_solves,
+                        double* partials, int chunks, double* sums, int sums_w, double* dump,
+                        hipStream_t stream);
+int reduce_rows_chunks(unsigned long long max_n);
+void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream);
+void launch_mixed_optics(const OpticsDev<double>& in, OpticsDev<float> out, int ncell, hipStream_t stream);
 
 // Launchers (kernels.hip).  All run on `stream`; none synchronises.
 void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP,
@@ -86,9 +112,6 @@ void launch_emission_sources(const GridDev& g, const OpticsDev<double>& op, doub
                              double tau_vert, double xi, double* L, double* cdf, double* wbirth,
                              double* scratch, double* stats_out, hipStream_t stream);
 size_t emission_scratch_doubles(int ncell);
-void launch_transport(const GridDev& g, const OpticsDev<double>& op, const TransportArgs& a,
-                      int blocks, hipStream_t stream);
-int transport_block_size();
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,
                             hipStream_t stream);
 void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,

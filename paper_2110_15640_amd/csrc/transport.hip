@@ -1,0 +1,631 @@
+// K4: persistent packet transport with wavefront-level regeneration.
+//
+// Every lane of a wave64 carries one photon packet (Sect. 2: packets are
+// emitted or injected, sample an optical depth, move sub-grid through the
+// spherical cells, interact, scatter or are absorbed, and are peeled off
+// toward every observer at each emission and interaction, Sect. 4.6).
+// Flights and peel-off rays are both walks through the grid, so the
+// cell-exit computation runs for all walking lanes together; the rarer
+// events (interaction, end of a peel-off, death, birth) are handled only
+// when at least ev_threshold lanes wait on one, or when no lane walks.
+// Lanes whose packet has terminated take the next packet index from the
+// wave's reservoir, refilled from a global dispenser, so the grid drains
+// without tail imbalance and many (spectral point, g) solves share a launch.
+//
+// Per packet the kernel writes one row: the peel-off sums F_o toward each
+// observer, then the bookkeeping counters.  A fixed-order reduction over the
+// rows forms the tallies, so results are deterministic and identical whether
+// a solve runs alone or inside a batch.
+//
+// Precision: FP64 keeps everything in double.  MIXED gathers float optical
+// properties and evaluates phase functions, scattering angles, the direction
+// rotation and the peel-off attenuation in float; positions, the directions
+// the traversal uses, exit distances, optical depths and tallies stay double.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "mcrt_internal.hpp"
+
+namespace mcrt {
+namespace {
+using namespace dev;
+
+enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 5 };
+enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
+
+struct Lane {
+    Ray r;                 // walking ray: position, cell, entry face
+    double dx, dy, dz;     // walking direction
+    double tau;            // flight: optical depth left; peel-off: accumulated
+    Ray s;                 // saved event point
+    double sdx, sdy, sdz;  // packet direction
+    double W, W0;
+    double mu0;            // slab backscatter observer (-sqrt(1-mu0^2), 0, mu0)
+    double w_abs, w_rr;
+    unsigned long long gid;  // global packet index
+    uint32_t e;              // event counter (flight e, then interaction e)
+    int ncw;                 // crossings of the current walk
+    int o;                   // observer of the current peel-off
+    int birth;               // 1 while peeling from the emission point
+    int mode, ev;
+    int solve;
+    int nint, ncross, ncapped, nlost;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ double ld(const void* p, int c)
+{
+    if (MIXED) return (double)((const float*)p)[c];
+    return ((const double*)p)[c];
+}
+
+// Write the packet's counters; `kind` says where its remaining weight went.
+__device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int kind)
+{
+    double* row = A.rows + L.gid * (unsigned long long)A.row_w + A.n_out;
+    row[K_ESC] = kind == K_ESC ? L.W : 0.0;
+    row[K_SURF] = kind == K_SURF ? L.W : 0.0;
+    row[K_ABS] = L.w_abs;
+    row[K_RR] = L.w_rr;
+    row[K_CAP] = kind == K_CAP ? L.W : 0.0;
+    row[K_LOST] = kind == K_LOST ? L.W : 0.0;
+    row[K_NINT] = (double)L.nint;
+    row[K_NCROSS] = (double)L.ncross;
+    row[K_NCAPPED] = (double)L.ncapped;
+    row[K_NLOST] = (double)L.nlost;
+    row[K_W0] = L.W0;
+    L.mode = M_DEAD;
+}
+
+__device__ __forceinline__ void observer(const Lane& L, const BatchArgs& A, const double* sobs, double& ox, double& oy,
+                                         double& oz)
+{
+    if (A.n_obs == 0) {
+        ox = -sqrt(fmax(1.0 - L.mu0 * L.mu0, 0.0));
+        oy = 0.0;
+        oz = L.mu0;
+    } else {
+        ox = sobs[3 * L.o];
+        oy = sobs[3 * L.o + 1];
+        oz = sobs[3 * L.o + 2];
+    }
+}
+
+__device__ __forceinline__ void start_peel(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs)
+{
+    L.r = L.s;
+    L.r.ef = -1;
+    L.tau = 0.0;
+    L.ncw = 0;
+    observer(L, A, sobs, L.dx, L.dy, L.dz);
+    if (g.geom == 1 && !(L.dz > 0.0)) {  // a slab ray that never reaches the top
+        L.tau = INFINITY;
+        L.mode = M_EVENT;
+        L.ev = E_PEEL_DONE;
+        return;
+    }
+    L.mode = M_PEEL;
+}
+
+__device__ __forceinline__ void start_flight(Lane& L, const BatchArgs& A, const SolveDev& S)
+{
+    U2 u = draw(A.seed, S.tag, L.gid - S.begin, L.e, 0);
+    L.tau = -log(u.a);
+    L.r = L.s;
+    L.dx = L.sdx; L.dy = L.sdy; L.dz = L.sdz;
+    L.ncw = 0;
+    L.mode = M_FLIGHT;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
+                                          const BatchArgs& A)
+{
+    double s;
+    int f = exit_distance(g, L.r, L.dx, L.dy, L.dz, s);
+    if (L.mode == M_FLIGHT) {
+        int c = cell_of(g, L.r);
+        const bool cont = A.absorption == 1;
+        double ae = ld<MIXED>(aext, c);
+        double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
+        double a = cont ? (ae - aa) : ae;
+        if (f == F_NONE && !(a > 0.0)) {
+            L.ncross += L.ncw;
+            L.mode = M_EVENT;
+            L.ev = E_LOST;
+            return;
+        }
+        if (a > 0.0 && L.tau < a * s) {
+            double ds = L.tau / a;
+            if (cont) {
+                double wn = L.W * exp(-aa * ds);
+                L.w_abs = L.w_abs + (L.W - wn);
+                L.W = wn;
+            }
+            advance(g, L.r, L.dx, L.dy, L.dz, ds);
+            L.r.ef = F_NONE;
+            L.ncross += L.ncw;
+            L.mode = M_EVENT;
+            L.ev = E_INTERACT;
+            return;
+        }
+        L.tau = L.tau - a * s;
+        if (cont) {
+            double wn = L.W * exp(-aa * s);
+            L.w_abs = L.w_abs + (L.W - wn);
+            L.W = wn;
+        }
+        advance(g, L.r, L.dx, L.dy, L.dz, s);
+        cross(g, L.r, f);
+        L.ncw++;
+        if (L.r.k >= g.nlay) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_ESCAPE; }
+        else if (L.r.k < 0) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_SURFACE; }
+        else if (L.ncw >= g.max_cross) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_LOST; }
+    } else {
+        if (f == F_NONE) {
+            L.ncross += L.ncw;
+            L.tau = INFINITY;
+            L.mode = M_EVENT;
+            L.ev = E_PEEL_DONE;
+            return;
+        }
+        int c = cell_of(g, L.r);
+        L.tau = L.tau + ld<MIXED>(aext, c) * s;
+        advance(g, L.r, L.dx, L.dy, L.dz, s);
+        cross(g, L.r, f);
+        L.ncw++;
+        bool done = true;
+        if (L.tau > A.tau_peel_max) L.tau = INFINITY;
+        else if (L.r.k >= g.nlay) {}
+        else if (L.r.k < 0) L.tau = INFINITY;
+        else if (L.ncw >= g.max_cross) L.tau = INFINITY;
+        else done = false;
+        if (done) {
+            L.ncross += L.ncw;
+            L.mode = M_EVENT;
+            L.ev = E_PEEL_DONE;
+        }
+    }
+}
+
+// Pending actions of a lane after an event; each is executed at exactly one
+// place in the kernel loop so its code (and register demand) appears once.
+enum { A_NONE = 0, A_PEEL = 1, A_FLIGHT = 2, A_SCATTER = 3, A_FINISH = 4 };
+
+// Survival weight update, scattering angle, rotation, roulette, event cap.
+template <bool MIXED>
+__device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
+{
+    const int c = cell_of(g, L.s);
+    const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
+    const unsigned long long q = L.gid - S.begin;
+    if (A.absorption != 1) {
+        L.w_abs += L.W * (1.0 - om);
+        L.W = L.W * om;
+    }
+    const double usel = draw(A.seed, S.tag, q, L.e, 0).b;  // scatterer choice of this event
+    U2 u1 = draw(A.seed, S.tag, q, L.e, 1);
+    if (MIXED) {
+        float z = fminf((float)u1.a, 0.99999994f);
+        float mu;
+        float g32 = (float)gc;
+        if ((float)usel < (float)pg) {
+            float qq = 4.0f * z - 2.0f;
+            float u = cbrtf(qq + sqrtf(qq * qq + 1.0f));
+            mu = u - 1.0f / u;
+        } else if (fabsf(g32) < 1e-6f) {
+            mu = 2.0f * z - 1.0f;
+        } else {
+            float t = (1.0f - g32 * g32) / (1.0f - g32 + 2.0f * g32 * z);
+            mu = (1.0f + g32 * g32 - t * t) / (2.0f * g32);
+        }
+        mu = fminf(fmaxf(mu, -1.0f), 1.0f);
+        float st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
+        float sp, cp;
+        __sincosf((float)(2.0 * kPi) * (float)u1.b, &sp, &cp);
+        float dx = (float)L.sdx, dy = (float)L.sdy, dz = (float)L.sdz;
+        float nx, ny, nz;
+        if (fabsf(dz) < 0.99999f) {
+            float t = sqrtf(1.0f - dz * dz);
+            float it = 1.0f / t;
+            nx = st * (dx * dz * cp - dy * sp) * it + dx * mu;
+            ny = st * (dy * dz * cp + dx * sp) * it + dy * mu;
+            nz = -st * cp * t + dz * mu;
+        } else {
+            float sgn = dz >= 0.0f ? 1.0f : -1.0f;
+            nx = st * cp;
+            ny = st * sp;
+            nz = sgn * mu;
+        }
+        double ddx = nx, ddy = ny, ddz = nz;
+        double n = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+        L.sdx = ddx / n;
+        L.sdy = ddy / n;
+        L.sdz = ddz / n;
+    } else {
+        double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, gc);
+        rotate_dir(L.sdx, L.sdy, L.sdz, mu, 2.0 * kPi * u1.b);
+    }
+    if (L.W < A.rr_threshold * L.W0) {
+        U2 u2 = draw(A.seed, S.tag, q, L.e, 2);
+        if (u2.a < A.rr_survive) {
+            double wn = L.W / A.rr_survive;
+            L.w_rr -= (wn - L.W);
+            L.W = wn;
+        } else {
+            L.w_rr += L.W;
+            L.W = 0.0;
+            L.ev = -1;
+            return A_FINISH;
+        }
+    }
+    if ((long long)L.e >= A.max_events) {
+        L.ncapped += 1;
+        L.ev = K_CAP;
+        return A_FINISH;
+    }
+    L.e += 1;
+    return A_FLIGHT;
+}
+
+// Bookkeeping of one event; returns the action that follows.  L.ev carries
+// the counter that receives the final weight when the action is A_FINISH.
+template <bool MIXED>
+__device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const BatchArgs& A)
+{
+    const SolveDev& S = A.solves[L.solve];
+    if (L.ev == E_PEEL_DONE) {
+        double f;
+        if (L.birth) {
+            f = L.W * exp(-L.tau) / (4.0 * kPi);
+        } else {
+            // normalised mixture of the Rayleigh and cloud phase functions
+            // toward the observer, weighted by the gas scattering probability
+            const int c = cell_of(g, L.s);
+            const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
+            if (MIXED) {
+                float mu = (float)(L.sdx * L.dx + L.sdy * L.dy + L.sdz * L.dz);
+                float pgf = (float)pg, gcf = (float)gc;
+                float pr = 0.75f * (1.0f + mu * mu);
+                float ph = 1.0f;
+                if (fabsf(gcf) >= 1e-6f) {
+                    float den = 1.0f + gcf * gcf - 2.0f * gcf * mu;
+                    ph = (1.0f - gcf * gcf) / (den * sqrtf(den));
+                }
+                float theta = (pgf * pr + (1.0f - pgf) * ph) * (float)(0.25 / kPi);
+                float att = L.tau < INFINITY ? __expf(-(float)L.tau) : 0.0f;
+                float w = A.absorption == 1 ? (float)L.W : (float)(L.W * om);
+                f = (double)(w * theta * att);
+            } else {
+                double mu = L.sdx * L.dx + L.sdy * L.dy + L.sdz * L.dz;
+                double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * p_hg(mu, gc)) / (4.0 * kPi);
+                double att = exp(-L.tau);
+                f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
+            }
+        }
+        double* row = A.rows + L.gid * (unsigned long long)A.row_w;
+        row[L.o] = row[L.o] + f;
+        L.o += 1;
+        if (L.o < A.n_out) return A_PEEL;
+        if (L.birth) {
+            L.birth = 0;
+            if (!A.scattering) {
+                L.ev = K_ESC;
+                return A_FINISH;
+            }
+            L.e = 1;
+            return A_FLIGHT;
+        }
+        return A_SCATTER;
+    }
+    if (L.ev == E_INTERACT) {
+        L.nint += 1;
+        L.s = L.r;
+        L.o = 0;
+        L.birth = 0;
+        return A_PEEL;
+    }
+    if (L.ev == E_LOST) L.nlost += 1;
+    L.ev = L.ev == E_ESCAPE ? K_ESC : (L.ev == E_SURFACE ? K_SURF : K_LOST);
+    return A_FINISH;
+}
+
+// New packet L.gid: find its solve, zero its row, place it and return the
+// first action (a flight for albedo, the emission-point peel-off otherwise).
+template <bool MIXED>
+__device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
+{
+    int lo = 0, hi = A.n_solves - 1;  // last solve with begin <= gid
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (A.solves[mid].begin <= L.gid) lo = mid;
+        else hi = mid - 1;
+    }
+    L.solve = lo;
+    const SolveDev& S = A.solves[lo];
+    const unsigned long long q = L.gid - S.begin;
+    double* row = A.rows + L.gid * (unsigned long long)A.row_w;
+    for (int o = 0; o < A.n_out; ++o) row[o] = 0.0;
+    L.w_abs = L.w_rr = 0.0;
+    L.nint = L.ncross = L.ncapped = L.nlost = 0;
+    L.birth = 0;
+    L.o = 0;
+    L.mu0 = 0.0;
+    L.e = 1;
+    const uint32_t tag = S.tag;
+    if (S.mode == 0) {
+        U2 u = draw(A.seed, tag, q, 0, 0);
+        if (g.geom == 1) {
+            double mu0 = A.mu0 > 0.0 ? A.mu0 : sqrt(1.0 - u.a);
+            L.sdx = sqrt(fmax(1.0 - mu0 * mu0, 0.0));
+            L.sdy = 0.0;
+            L.sdz = -mu0;
+            L.mu0 = mu0;
+            L.s.x = 0.0; L.s.y = 0.0; L.s.z = g.r[g.nlay];
+            L.s.i = 0; L.s.j = 0; L.s.k = g.nlay - 1; L.s.ef = F_OUT;
+        } else {
+            double rho = A.r_toa * sqrt(u.a);
+            double a = 2.0 * kPi * u.b;
+            double sa, ca;
+            sincos(a, &sa, &ca);
+            double y = rho * ca, z = rho * sa;
+            double x = sqrt(fmax(A.r_toa * A.r_toa - y * y - z * z, 0.0));
+            L.s.x = x; L.s.y = y; L.s.z = z;
+            L.sdx = -1.0; L.sdy = 0.0; L.sdz = 0.0;
+            L.s.k = g.nlay - 1;
+            locate_column(g, L.s);
+            L.s.ef = F_OUT;
+        }
+        L.W = 1.0;
+        L.W0 = 1.0;
+        return A_FLIGHT;
+    }
+    const int ncell = g.nlon * g.nlat * g.nlay;
+    const double tot = S.cdf[ncell - 1];
+    if (!(tot > 0.0)) {  // nothing emits
+        L.W = 0.0;
+        L.W0 = 0.0;
+        L.ev = -1;
+        return A_FINISH;
+    }
+    U2 u0 = draw(A.seed, tag, q, 0, 0);
+    U2 u1 = draw(A.seed, tag, q, 0, 1);
+    U2 u2 = draw(A.seed, tag, q, 0, 2);
+    double target = u0.a * tot;
+    int lo2 = 0, hi2 = ncell - 1;
+    while (lo2 < hi2) {
+        int mid = (lo2 + hi2) >> 1;
+        if (S.cdf[mid] > target) hi2 = mid;
+        else lo2 = mid + 1;
+    }
+    int c = lo2;
+    int i = c % g.nlon, j = (c / g.nlon) % g.nlat, k = c / (g.nlon * g.nlat);
+    double rk = g.r[k], rk1 = g.r[k + 1];
+    double rk3 = rk * rk * rk;
+    double rk13 = rk1 * rk1 * rk1;
+    double r = cbrt(rk3 + u0.b * (rk13 - rk3));
+    double sl0 = g.lat_sin[j], sl1 = g.lat_sin[j + 1];
+    double sl = sl0 + u1.a * (sl1 - sl0);
+    double cl = sqrt(fmax(1.0 - sl * sl, 0.0));
+    double lon = g.lon[i] + u1.b * (g.lon[i + 1] - g.lon[i]);
+    double slo, clo;
+    sincos(lon, &slo, &clo);
+    L.s.x = r * cl * clo;
+    L.s.y = r * cl * slo;
+    L.s.z = r * sl;
+    L.s.i = i; L.s.j = j; L.s.k = k; L.s.ef = F_NONE;
+    double mu = 2.0 * u2.a - 1.0;
+    double sp = sqrt(fmax(1.0 - mu * mu, 0.0));
+    double psi = 2.0 * kPi * u2.b;
+    double sps, cps;
+    sincos(psi, &sps, &cps);
+    L.sdx = sp * cps;
+    L.sdy = sp * sps;
+    L.sdz = mu;
+    L.W = S.wbirth[c];
+    L.W0 = L.W;
+    L.birth = 1;
+    return A_PEEL;
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchArgs A)
+{
+    __shared__ double sobs[3 * kMaxObs];
+    if (threadIdx.x < 3 * kMaxObs) sobs[threadIdx.x] = A.obs[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long res_next = 0, res_end = 0;
+    bool exhausted = false;
+    Lane L;
+    L.mode = M_DEAD;
+    L.solve = 0;
+    const void* aext = nullptr;
+    const void* aabs = nullptr;
+    for (;;) {
+        if (L.mode <= M_PEEL) walk_step<MIXED>(L, g, aext, aabs, A);
+        unsigned long long evm = __ballot(L.mode == M_EVENT);
+        unsigned long long walking = __ballot(L.mode <= M_PEEL);
+        if (__popcll(evm) < A.ev_threshold && walking != 0) continue;
+        int act = A_NONE;
+        if (L.mode == M_EVENT) act = handle_event<MIXED>(L, g, A);
+        if (act == A_SCATTER) act = scatter<MIXED>(L, g, A, A.solves[L.solve]);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (act == A_FINISH) {
+                finish_packet(L, A, L.ev);
+                act = A_NONE;
+            }
+            if (pass == 1) break;
+            // regeneration: dead lanes take the next packets of the reservoir
+            unsigned long long dead = __ballot(L.mode == M_DEAD);
+            while (dead != 0) {
+                if (res_next >= res_end) {
+                    if (exhausted) break;
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(A.counter, (unsigned long long)A.batch);
+                    base = __shfl(base, 0);
+                    if (base >= A.total) {
+                        exhausted = true;
+                        break;
+                    }
+                    res_next = base;
+                    res_end = base + (unsigned long long)A.batch < A.total ? base + A.batch : A.total;
+                }
+                unsigned long long avail = res_end - res_next;
+                int cnt = __popcll(dead);
+                int take = (unsigned long long)cnt < avail ? cnt : (int)avail;
+                int rank = __popcll(dead & below);
+                if (L.mode == M_DEAD && rank < take) {
+                    L.gid = res_next + (unsigned long long)rank;
+                    L.mode = M_BIRTH;
+                }
+                res_next += (unsigned long long)take;
+                dead = __ballot(L.mode == M_DEAD);
+            }
+            if (L.mode == M_DEAD && exhausted) L.mode = M_IDLE;
+            if (L.mode == M_BIRTH) {
+                act = birth<MIXED>(L, g, A);
+                const SolveDev& S = A.solves[L.solve];
+                aext = S.a_ext;
+                aabs = S.a_abs;
+            }
+        }
+        if (act == A_FLIGHT) start_flight(L, A, A.solves[L.solve]);
+        else if (act == A_PEEL) start_peel(L, g, A, sobs);
+        if (__ballot(L.mode != M_IDLE) == 0) break;
+    }
+}
+
+// Fixed-order reduction of the packet rows of every solve: block (chunk, s)
+// sums rows [chunk*kChunk, (chunk+1)*kChunk) of solve s into
+// partials[s][chunk][2*n_out + kNCounters]; then one block per (s, column)
+// sums the chunks.  Optional copy of F to a packet dump.
+constexpr int kChunk = 4096;
+constexpr int kRT = 256;
+
+__global__ void __launch_bounds__(kRT) k_rows_partial(BatchArgs A, double* __restrict__ partials, int chunks,
+                                                      double* __restrict__ dump)
+{
+    __shared__ double sh[kRT];
+    const int s = blockIdx.y;
+    const SolveDev S = A.solves[s];
+    const unsigned long long q0 = (unsigned long long)blockIdx.x * kChunk;
+    const int pw = 2 * A.n_out + kNCounters;
+    double* out = partials + ((size_t)s * chunks + blockIdx.x) * pw;
+    for (int col = 0; col < A.n_out + kNCounters; ++col) {
+        double acc = 0.0, acc2 = 0.0;
+        for (int t = threadIdx.x; t < kChunk; t += kRT) {
+            unsigned long long q = q0 + (unsigned long long)t;
+            if (q < S.n) {
+                double v = A.rows[(S.begin + q) * (unsigned long long)A.row_w + col];
+                acc = acc + v;
+                acc2 = acc2 + v * v;
+                if (dump && col < A.n_out) dump[(S.begin + q) * (unsigned long long)A.n_out + col] = v;
+            }
+        }
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int st = kRT / 2; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
+            __syncthreads();
+        }
+        double tot = sh[0];
+        __syncthreads();
+        if (col < A.n_out) {
+            sh[threadIdx.x] = acc2;
+            __syncthreads();
+            for (int st = kRT / 2; st > 0; st >>= 1) {
+                if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
+                __syncthreads();
+            }
+            double tot2 = sh[0];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                out[2 * col] = tot;
+                out[2 * col + 1] = tot2;
+            }
+        } else if (threadIdx.x == 0) {
+            out[2 * A.n_out + (col - A.n_out)] = tot;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kRT) k_rows_final(const double* __restrict__ partials, int chunks, int pw,
+                                                    double* __restrict__ sums, int sums_w)
+{
+    __shared__ double sh[kRT];
+    __shared__ double shc[kRT];
+    const int s = blockIdx.y, col = blockIdx.x;
+    double acc = 0.0, comp = 0.0;
+    for (int c = threadIdx.x; c < chunks; c += kRT) {
+        double x = partials[((size_t)s * chunks + c) * pw + col];
+        double t = acc + x;
+        comp = comp + (fabs(acc) >= fabs(x) ? ((acc - t) + x) : ((x - t) + acc));
+        acc = t;
+    }
+    sh[threadIdx.x] = acc;
+    shc[threadIdx.x] = comp;
+    __syncthreads();
+    for (int st = kRT / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double a = sh[threadIdx.x], b = sh[threadIdx.x + st];
+            double t = a + b;
+            double e = fabs(a) >= fabs(b) ? ((a - t) + b) : ((b - t) + a);
+            sh[threadIdx.x] = t;
+            shc[threadIdx.x] = shc[threadIdx.x] + shc[threadIdx.x + st] + e;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[(size_t)s * sums_w + col] = sh[0] + shc[0];
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void __launch_bounds__(256) k_to_float(const double* __restrict__ in, float* __restrict__ out, int n)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = (float)in[c];
+}
+
+}  // namespace
+
+void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks, hipStream_t stream)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_transport_persistent<true>, dim3(blocks), dim3(256), 0, stream, g, a);
+    else
+        hipLaunchKernelGGL(k_transport_persistent<false>, dim3(blocks), dim3(256), 0, stream, g, a);
+}
+
+int reduce_rows_chunks(unsigned long long max_n) { return (int)((max_n + kChunk - 1) / kChunk); }
+
+void launch_reduce_rows(const BatchArgs& a, const SolveDev* /*solves_host*/, int n_solves, double* partials,
+                        int chunks, double* sums, int sums_w, double* dump, hipStream_t stream)
+{
+    const int pw = 2 * a.n_out + kNCounters;
+    hipLaunchKernelGGL(k_rows_partial, dim3(chunks, n_solves), dim3(kRT), 0, stream, a, partials, chunks, dump);
+    hipLaunchKernelGGL(k_rows_final, dim3(pw, n_solves), dim3(kRT), 0, stream, partials, chunks, pw, sums, sums_w);
+}
+
+void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, stream, p, v);
+}
+
+void launch_mixed_optics(const OpticsDev<double>& in, OpticsDev<float> out, int ncell, hipStream_t stream)
+{
+    int b = (ncell + 255) / 256;
+    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.a_ext, out.a_ext, ncell);
+    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.a_abs, out.a_abs, ncell);
+    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.omega, out.omega, ncell);
+    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.p_gas, out.p_gas, ncell);
+    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.g_cld, out.g_cld, ncell);
+}
+
+}  // namespace mcrt

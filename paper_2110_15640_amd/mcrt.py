@@ -61,12 +61,14 @@ class SolveParams(ctypes.Structure):
                 ("rr_threshold", _dbl), ("rr_survive", _dbl), ("emis_bias", _dbl),
                 ("tau_vert_max", _dbl), ("tau_peel_max", _dbl), ("max_events", _i64), ("mu0", _dbl),
                 ("n_b", _i32), ("n_alpha", _i32), ("r_star", _dbl), ("stream", _vp),
-                ("packet_dump", _vp)]
+                ("packet_dump", _vp), ("profile", _i32), ("max_batch", _i32),
+                ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
-                ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl)]
+                ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
+                ("kernel_launches", _i64)]
 
 
 _lib = None
@@ -229,9 +231,11 @@ class Context:
                    sums=np.zeros((ns, ng, no, 2)), counters=np.zeros((ns, ng, NCOUNTERS)),
                    l_tot=np.zeros((ns, ng)))
         r = Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
-                   out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data, 0.0)
+                   out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data, 0.0, 0.0, 0)
         _check(fn(self._h, gid, oid, ctypes.byref(p), ctypes.byref(r)))
         out["elapsed_ms"] = r.elapsed_ms
+        out["kernel_ms"] = r.kernel_ms
+        out["kernel_launches"] = r.kernel_launches
         del keep
         return out
 

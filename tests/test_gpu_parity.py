@@ -249,3 +249,40 @@ def test_edge_cases(ctx, torch_dev):
         ctx.free_grid(x)
     for x in (oid, did):
         ctx.free_opacity(x)
+
+
+def test_batched_and_launch_shapes_are_bit_identical(ctx, torch_dev):
+    _log("determinism: one launch per solve vs one batched launch vs other launch shapes")
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=3, ng=2)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    base = dict(n_packets=3000, seed=61, obs_phase=phases)
+    ref = ctx.solve_emission(gid, oid, table, max_batch=1, **base)
+    for kw in (dict(max_batch=0), dict(max_batch=4), dict(tune_ev_threshold=1, tune_blocks_per_cu=1, tune_wave_batch=7),
+               dict(tune_ev_threshold=64, tune_wave_batch=1000)):
+        got = ctx.solve_emission(gid, oid, table, **base, **kw)
+        assert np.array_equal(got["sums"], ref["sums"]), kw
+        assert np.array_equal(got["value"], ref["value"]), kw
+        assert np.array_equal(got["counters"], ref["counters"]), kw
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+@pytest.mark.parametrize("mode", ["albedo", "emission"])
+def test_mixed_precision_agrees_with_fp64(ctx, torch_dev, mode):
+    """FP32 opacity / phase-function / direction math on the same random
+    stream: spectra within 1e-3 relative and 3 sigma of the FP64 ones."""
+    _log(f"mixed vs fp64: {mode}")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(24, 12, 20, nband=4, ng=2)
+    table.k_ray = table.k_ray * 30.0
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    fn = ctx.solve_albedo if mode == "albedo" else ctx.solve_emission
+    ph = [0.0, 0.5] if mode == "albedo" else list(phases)
+    kw = dict(n_packets=40000, seed=63, obs_phase=ph)
+    a = fn(gid, oid, table, precision=M.MCRT_FP64, **kw)
+    b = fn(gid, oid, table, precision=M.MCRT_MIXED, **kw)
+    rel = np.abs(b["value"] - a["value"]) / np.abs(a["value"])
+    assert rel.max() < 1e-3, rel
+    assert np.all(np.abs(b["value"] - a["value"]) <= 3.0 * a["stderr"])
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
