@@ -218,7 +218,8 @@ void mcrt_default_params(mcrt_solve_params* p);
  * l_tot[n_spec][ng]        emission: L_tot [erg/s/cm].
  * elapsed_ms receives the device time of the solve; with params.profile,
  * kernel_ms and kernel_launches the summed duration and count of the
- * dominant kernel's launches. */
+ * dominant kernel's launches.  queued_ms and latency_ms are set by
+ * mcrt_wait: time from submit to start, and from submit to completion. */
 typedef struct {
     double* value;
     double* stderr_;
@@ -229,6 +230,8 @@ typedef struct {
     double elapsed_ms;
     double kernel_ms;
     int64_t kernel_launches;
+    double queued_ms;
+    double latency_ms;
 } mcrt_result;
 
 /* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /
@@ -240,6 +243,30 @@ int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
                         const mcrt_solve_params* params, mcrt_result* result);
 int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
                             const mcrt_solve_params* params, mcrt_result* result);
+
+/* Serving: asynchronous solves with continuous admission.
+ * mcrt_submit copies params (and the arrays they point to; stream and
+ * packet_dump are ignored) and queues the request; mode is MCRT_MODE_*.
+ * Worker threads, each with its own HIP stream, admit queued requests in
+ * arrival order whenever the context's HBM budget covers the request's
+ * device scratch (estimated at submit), so requests run concurrently on the
+ * device while grids and tables stay resident.  A request whose scratch
+ * alone exceeds the budget is rejected at submit with MCRT_EBUDGET.
+ * mcrt_poll sets *done to 1 once the request finished, failed or was
+ * cancelled.  mcrt_wait blocks until then, copies the results into the
+ * caller's arrays (shaped as for the blocking solve), forgets the ticket and
+ * returns the request's own status (MCRT_ECANCELLED if cancelled).
+ * mcrt_cancel removes a queued request (MCRT_EBUSY once it runs).
+ * mcrt_serve_config sets the number of workers (1..16, default 3) before the
+ * first submit.  Requests on one context are independent: a result is the
+ * same alone and in a mix (the RNG is keyed per request and tallies are
+ * reduced in a fixed order). */
+int mcrt_serve_config(mcrt_ctx* ctx, int32_t n_workers);
+int mcrt_submit(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
+                const mcrt_solve_params* params, uint64_t* ticket);
+int mcrt_poll(mcrt_ctx* ctx, uint64_t ticket, int32_t* done);
+int mcrt_wait(mcrt_ctx* ctx, uint64_t ticket, mcrt_result* result);
+int mcrt_cancel(mcrt_ctx* ctx, uint64_t ticket);
 
 #ifdef __cplusplus
 }

@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -63,6 +67,18 @@ struct OpacRes {
     int refs = 0;
 };
 
+// An execution slot: a stream, its timing events and its scratch arena.
+// Blocking solves use the context's main slot; each serving worker owns one.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> prof_ev;  // pairs around timed launches
+    std::map<std::string, DevBuf> scratch;  // grow-only, by role
+    bool stream_ordered = false;  // serving slots allocate with hipMallocAsync
+};
+
+struct Request;
+
 }  // namespace
 
 struct mcrt_ctx {
@@ -70,16 +86,25 @@ struct mcrt_ctx {
     int n_cu = 256;
     uint64_t budget = 0;
     uint64_t in_use = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::mutex mu;
+    std::mutex mem_mu;  // in_use
+    std::mutex mu;      // grids, opacs, refs
+    std::mutex main_mu; // blocking solves on the main slot
+    Slot main;
     std::map<int32_t, std::unique_ptr<GridRes>> grids;
     std::map<int32_t, std::unique_ptr<OpacRes>> opacs;
     int32_t next_grid = 1, next_opac = 1;
     bool poisoned = false;
-    std::vector<hipEvent_t> prof_ev;  // pairs around timed launches
-    // grow-only scratch arena per role
-    std::map<std::string, DevBuf> scratch;
+    // serving
+    std::mutex q_mu;
+    std::condition_variable q_cv;
+    std::deque<Request*> queue;
+    std::map<uint64_t, std::unique_ptr<Request>> requests;
+    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Slot>> wslots;
+    uint64_t reserved = 0;  // bytes admitted to running requests
+    uint64_t next_ticket = 1;
+    int n_workers = 3;
+    bool stopping = false;
 };
 
 namespace {
@@ -97,48 +122,91 @@ int hip_check(mcrt_ctx* ctx, hipError_t e, const char* what)
         if (_rc != MCRT_OK) return _rc;                       \
     } while (0)
 
-int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out)
+// Device allocation charged to the context's budget.  A stream-ordered
+// allocation (serving slots) was admitted against the budget beforehand.
+int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out, hipStream_t ordered = nullptr)
 {
     if (bytes == 0) bytes = 8;
-    if (ctx->in_use + bytes > ctx->budget)
-        return fail(MCRT_EBUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu in use)", bytes,
-                    (unsigned long long)ctx->in_use, (unsigned long long)ctx->budget);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        if (!ordered && ctx->in_use + ctx->reserved + bytes > ctx->budget)
+            return fail(MCRT_EBUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu in use, %llu reserved, "
+                        "budget %llu)", bytes, (unsigned long long)ctx->in_use, (unsigned long long)ctx->reserved,
+                        (unsigned long long)ctx->budget);
+        ctx->in_use += bytes;
+    }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = ordered ? hipMallocAsync(&p, bytes, ordered) : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        return fail(MCRT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        ctx->in_use -= bytes;
+        return fail(MCRT_ENOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
     }
     out.p = p;
     out.bytes = bytes;
-    ctx->in_use += bytes;
     return MCRT_OK;
 }
 
-void dev_free(mcrt_ctx* ctx, DevBuf& b)
+void dev_free(mcrt_ctx* ctx, DevBuf& b, hipStream_t ordered = nullptr)
 {
     if (b.p) {
-        (void)hipFree(b.p);
+        if (ordered) (void)hipFreeAsync(b.p, ordered);
+        else (void)hipFree(b.p);
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
         ctx->in_use -= b.bytes;
     }
     b.p = nullptr;
     b.bytes = 0;
 }
 
-// Scratch buffer of at least `bytes` under `name` (grow-only, kept by ctx).
-int scratch(mcrt_ctx* ctx, const char* name, size_t bytes, void** out)
+// Scratch buffer of at least `bytes` under `name` in slot `sl` (grow-only).
+int scratch(mcrt_ctx* ctx, Slot& sl, hipStream_t st, const char* name, size_t bytes, void** out)
 {
-    DevBuf& b = ctx->scratch[name];
+    DevBuf& b = sl.scratch[name];
     if (b.bytes < bytes) {
         if (b.p) {
-            HIPTRY(hipDeviceSynchronize());  // the old buffer may still be read by queued work
-            dev_free(ctx, b);
+            if (!sl.stream_ordered) {  // the old buffer may still be read by queued work
+                HIPTRY(hipStreamSynchronize(st));
+                HIPTRY(hipStreamSynchronize(sl.stream));
+            }
+            dev_free(ctx, b, sl.stream_ordered ? st : nullptr);
         }
-        int rc = dev_alloc(ctx, bytes, b);
+        int rc = dev_alloc(ctx, bytes, b, sl.stream_ordered ? st : nullptr);
         if (rc) return rc;
     }
     *out = b.p;
     return MCRT_OK;
+}
+
+void release_scratch(mcrt_ctx* ctx, Slot& sl)
+{
+    for (auto& kv : sl.scratch) dev_free(ctx, kv.second, sl.stream_ordered ? sl.stream : nullptr);
+    sl.scratch.clear();
+}
+
+int slot_init(Slot& sl)
+{
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    if ((e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    return MCRT_OK;
+}
+
+void slot_destroy(mcrt_ctx* ctx, Slot& sl)
+{
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    release_scratch(ctx, sl);
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    for (auto e : sl.prof_ev) (void)hipEventDestroy(e);
+    sl.prof_ev.clear();
+    if (sl.ev0) (void)hipEventDestroy(sl.ev0);
+    if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    sl.stream = nullptr;
+    sl.ev0 = sl.ev1 = nullptr;
 }
 
 template <typename T>
@@ -275,11 +343,10 @@ struct SolvePlan {
     hipStream_t stream = nullptr;
 };
 
-int plan_common(mcrt_ctx* ctx, GridRes* g, OpacRes* op, const mcrt_solve_params* p, int mode, SolvePlan& pl)
+int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solve_params* p, int mode, SolvePlan& pl)
 {
     if (!p) return fail(MCRT_EINVAL, "params is NULL");
     if (p->precision != MCRT_FP64 && p->precision != MCRT_MIXED) return fail(MCRT_EINVAL, "unknown precision");
-    if (p->precision == MCRT_MIXED) return fail(MCRT_EINVAL, "MCRT_MIXED is not available in this build");
     if (p->n_spec < 0) return fail(MCRT_EINVAL, "n_spec < 0");
     int nspec_tab = op->nspec;
     if (p->spec_idx) {
@@ -293,7 +360,7 @@ int plan_common(mcrt_ctx* ctx, GridRes* g, OpacRes* op, const mcrt_solve_params*
     }
     if (pl.specs.empty()) return fail(MCRT_EINVAL, "no spectral points selected");
     pl.ng = op->kind == MCRT_OPAC_CK ? op->ng : 1;
-    pl.stream = p->stream ? (hipStream_t)p->stream : ctx->stream;
+    pl.stream = p->stream ? (hipStream_t)p->stream : def_stream;
     if (mode == MCRT_MODE_TRANSMISSION) {
         if (g->dev.geom != 0) return fail(MCRT_EINVAL, "transmission needs a spherical grid");
         if (p->n_b < 1 || p->n_alpha < 1 || (long long)p->n_b * p->n_alpha > (1LL << 30))
@@ -374,22 +441,22 @@ void fill_results(const SolvePlan& pl, const std::vector<double>& perg_val, cons
 }
 
 // Timed-launch bracket: events 2i and 2i+1 around the i-th launch.
-int prof_events(mcrt_ctx* ctx, size_t n_launch)
+int prof_events(mcrt_ctx* ctx, Slot& sl, size_t n_launch)
 {
-    while (ctx->prof_ev.size() < 2 * n_launch) {
+    while (sl.prof_ev.size() < 2 * n_launch) {
         hipEvent_t e;
         HIPTRY(hipEventCreate(&e));
-        ctx->prof_ev.push_back(e);
+        sl.prof_ev.push_back(e);
     }
     return MCRT_OK;
 }
 
-int prof_collect(mcrt_ctx* ctx, size_t n_launch, mcrt_result* r)
+int prof_collect(mcrt_ctx* ctx, Slot& sl, size_t n_launch, mcrt_result* r)
 {
     double tot = 0.0;
     for (size_t i = 0; i < n_launch; ++i) {
         float ms = 0.0f;
-        HIPTRY(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+        HIPTRY(hipEventElapsedTime(&ms, sl.prof_ev[2 * i], sl.prof_ev[2 * i + 1]));
         tot += ms;
     }
     r->kernel_ms = tot;
@@ -397,31 +464,72 @@ int prof_collect(mcrt_ctx* ctx, size_t n_launch, mcrt_result* r)
     return MCRT_OK;
 }
 
-int finish_timing(mcrt_ctx* ctx, hipStream_t st, mcrt_result* r)
+int finish_timing(mcrt_ctx* ctx, Slot& sl, hipStream_t st, mcrt_result* r)
 {
-    HIPTRY(hipEventRecord(ctx->ev1, st));
-    HIPTRY(hipEventSynchronize(ctx->ev1));
+    HIPTRY(hipEventRecord(sl.ev1, st));
+    HIPTRY(hipEventSynchronize(sl.ev1));
     float ms = 0.0f;
-    HIPTRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    HIPTRY(hipEventElapsedTime(&ms, sl.ev0, sl.ev1));
     if (r) r->elapsed_ms = ms;
     return MCRT_OK;
+}
+
+// Looks up a grid and an opacity table and holds a reference on both for
+// the duration of a solve (mcrt_*_free return EBUSY meanwhile).
+struct Lease {
+    mcrt_ctx* ctx = nullptr;
+    GridRes* g = nullptr;
+    OpacRes* op = nullptr;
+    ~Lease()
+    {
+        if (!ctx) return;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (g) g->refs--;
+        if (op) op->refs--;
+    }
+};
+
+int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    auto gi = ctx->grids.find(gid);
+    if (gi == ctx->grids.end()) return fail(MCRT_ENOTFOUND, "grid %d not found", gid);
+    auto oi = ctx->opacs.find(oid);
+    if (oi == ctx->opacs.end()) return fail(MCRT_ENOTFOUND, "opacity %d not found", oid);
+    L.ctx = ctx;
+    L.g = gi->second.get();
+    L.op = oi->second.get();
+    L.g->refs++;
+    L.op->refs++;
+    return MCRT_OK;
+}
+
+// Solves per persistent launch for a serving request: a fixed share of the
+// budget, so that the admission estimate and the allocation agree.
+int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve)
+{
+    uint64_t cap = std::min<uint64_t>(ctx->budget / 8, 24ULL << 30);
+    int batch = max_batch > 0 ? max_batch : nsolve;
+    int fit = (int)std::max<uint64_t>(1, cap / std::max<uint64_t>(per_solve, 1));
+    return std::max(1, std::min(std::min(batch, fit), nsolve));
 }
 
 // Albedo and emission.  The (spec, g) solves are grouped into batches; per
 // batch every solve gets its own optics (and emission CDF) slot, then one
 // persistent transport launch runs all their packets and a fixed-order
 // reduction turns the packet rows into one tally row per solve.
-int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res, int mode)
+int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, int32_t oid,
+                  const mcrt_solve_params* p, mcrt_result* res, int mode)
 {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
     if (!res) return fail(MCRT_EINVAL, "result is NULL");
-    GridRes* g = find_grid(ctx, gid);
-    if (!g) return fail(MCRT_ENOTFOUND, "grid %d not found", gid);
-    OpacRes* op = find_opac(ctx, oid);
-    if (!op) return fail(MCRT_ENOTFOUND, "opacity %d not found", oid);
+    Lease ls;
+    int rc = lease(ctx, gid, oid, ls);
+    if (rc) return rc;
+    GridRes* g = ls.g;
+    OpacRes* op = ls.op;
     SolvePlan pl;
-    int rc = plan_common(ctx, g, op, p, mode, pl);
+    rc = plan_common(def_stream, g, op, p, mode, pl);
     if (rc) return rc;
     if (op->kind == MCRT_OPAC_HIRES && mode == MCRT_MODE_ALBEDO)
         return fail(MCRT_EINVAL, "albedo solves take a correlated-k table");
@@ -446,9 +554,16 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
     const size_t src_b = mode == MCRT_MODE_EMISSION ? (size_t)ncell * 2 * sizeof(double) : 0;
     const size_t row_b = (size_t)N * prow * sizeof(double);
     const size_t per_solve = opt_b + src_b + row_b;
-    int batch = p->max_batch > 0 ? p->max_batch : nsolve;
-    {
-        uint64_t room = ctx->budget > ctx->in_use ? ctx->budget - ctx->in_use : 0;
+    int batch;
+    if (sl.stream_ordered) {
+        batch = serving_batch(ctx, p->max_batch, nsolve, per_solve);  // as admitted
+    } else {
+        batch = p->max_batch > 0 ? p->max_batch : nsolve;
+        uint64_t room;
+        {
+            std::lock_guard<std::mutex> mk(ctx->mem_mu);
+            room = ctx->budget > ctx->in_use + ctx->reserved ? ctx->budget - ctx->in_use - ctx->reserved : 0;
+        }
         uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
         int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
         batch = std::max(1, std::min(std::min(batch, fit), nsolve));
@@ -456,20 +571,20 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
     const int chunks = reduce_rows_chunks(N);
     void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_L = nullptr, *v_es = nullptr,
                  *v_shift = nullptr, *v_solves, *v_ctr;
-    if ((rc = scratch(ctx, "optics", sizeof(double) * 5 * (size_t)ncell * (mixed ? 1 : batch), &v_opt))) return rc;
-    if (mixed && (rc = scratch(ctx, "optics_f32", opt_b * batch, &v_optf))) return rc;
-    if ((rc = scratch(ctx, "rows", row_b * batch, &v_rows))) return rc;
-    if ((rc = scratch(ctx, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
-    if ((rc = scratch(ctx, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
-    if ((rc = scratch(ctx, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
-    if ((rc = scratch(ctx, "dispenser", 64, &v_ctr))) return rc;
+    if ((rc = scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * (mixed ? 1 : batch), &v_opt))) return rc;
+    if (mixed && (rc = scratch(ctx, sl, st, "optics_f32", opt_b * batch, &v_optf))) return rc;
+    if ((rc = scratch(ctx, sl, st, "rows", row_b * batch, &v_rows))) return rc;
+    if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
+    if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
+    if ((rc = scratch(ctx, sl, st, "dispenser", 64, &v_ctr))) return rc;
     if (mode == MCRT_MODE_EMISSION) {
-        if ((rc = scratch(ctx, "sources", src_b * batch, &v_src))) return rc;
-        if ((rc = scratch(ctx, "L", sizeof(double) * (size_t)ncell, &v_L))) return rc;
-        if ((rc = scratch(ctx, "em_scratch", sizeof(double) * emission_scratch_doubles(ncell), &v_es))) return rc;
+        if ((rc = scratch(ctx, sl, st, "sources", src_b * batch, &v_src))) return rc;
+        if ((rc = scratch(ctx, sl, st, "L", sizeof(double) * (size_t)ncell, &v_L))) return rc;
+        if ((rc = scratch(ctx, sl, st, "em_scratch", sizeof(double) * emission_scratch_doubles(ncell), &v_es))) return rc;
     }
     if (op->kind == MCRT_OPAC_HIRES)
-        if ((rc = scratch(ctx, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+        if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
     double* sums = (double*)v_sums;
 
     BatchArgs A{};
@@ -495,11 +610,11 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
 
     const bool prof = p->profile != 0;
     const int nbatches = (nsolve + batch - 1) / batch;
-    if (prof && (rc = prof_events(ctx, (size_t)nbatches))) return rc;
+    if (prof && (rc = prof_events(ctx, sl, (size_t)nbatches))) return rc;
     res->kernel_ms = 0.0;
     res->kernel_launches = 0;
     std::vector<std::vector<SolveDev>> host_solves(nbatches);
-    HIPTRY(hipEventRecord(ctx->ev0, st));
+    HIPTRY(hipEventRecord(sl.ev0, st));
     HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
     if (op->kind == MCRT_OPAC_HIRES)
         launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
@@ -551,9 +666,9 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
         A.n_solves = s1 - s0;
         A.total = (unsigned long long)(s1 - s0) * N;
         launch_fill_u64(A.counter, 0ULL, st);
-        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * bt], st));
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
         launch_transport_persistent(g->dev, A, mixed, pblocks, st);
-        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * bt + 1], st));
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
         double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
         launch_reduce_rows(A, nullptr, s1 - s0, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
         if (bt + 1 < nbatches) HIPTRY(hipStreamSynchronize(st));  // slots are reused by the next batch
@@ -561,8 +676,8 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nsolve * row_w);
     HIPTRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
-    if ((rc = finish_timing(ctx, st, res))) return rc;
-    if (prof && (rc = prof_collect(ctx, (size_t)nbatches, res))) return rc;
+    if ((rc = finish_timing(ctx, sl, st, res))) return rc;
+    if (prof && (rc = prof_collect(ctx, sl, (size_t)nbatches, res))) return rc;
 
     // Post-processing (Sect. 5.2 A_g = pi E; Sect. 5.3 F_p = L_tot/(N R_TOA^2) sum F)
     std::vector<double> val((size_t)nsolve * no), se((size_t)nsolve * no), cnt((size_t)nsolve * kNCounters),
@@ -592,17 +707,17 @@ int solve_packets(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_para
 
 // Transmission: chord geometry once, then per block of up to 64 spectral
 // rows: alpha gather -> chord optical depths -> fixed-order tally.
-int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res)
+int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, int32_t oid,
+                 const mcrt_solve_params* p, mcrt_result* res)
 {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
     if (!res) return fail(MCRT_EINVAL, "result is NULL");
-    GridRes* g = find_grid(ctx, gid);
-    if (!g) return fail(MCRT_ENOTFOUND, "grid %d not found", gid);
-    OpacRes* op = find_opac(ctx, oid);
-    if (!op) return fail(MCRT_ENOTFOUND, "opacity %d not found", oid);
+    Lease ls;
+    int rc = lease(ctx, gid, oid, ls);
+    if (rc) return rc;
+    GridRes* g = ls.g;
+    OpacRes* op = ls.op;
     SolvePlan pl;
-    int rc = plan_common(ctx, g, op, p, MCRT_MODE_TRANSMISSION, pl);
+    rc = plan_common(def_stream, g, op, p, MCRT_MODE_TRANSMISSION, pl);
     if (rc) return rc;
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
@@ -613,33 +728,33 @@ int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_param
     const int kSlot = 64;
     const int nslot_max = std::min(kSlot, nrow);
     void *v_cnt, *v_off, *v_b, *v_ok, *v_alpha, *v_part, *v_sums, *v_shift = nullptr, *v_nl = nullptr;
-    if ((rc = scratch(ctx, "chord_cnt", sizeof(int) * (size_t)nch, &v_cnt))) return rc;
-    if ((rc = scratch(ctx, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
-    if ((rc = scratch(ctx, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
-    if ((rc = scratch(ctx, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
-    if ((rc = scratch(ctx, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_cnt", sizeof(int) * (size_t)nch, &v_cnt))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
+    if ((rc = scratch(ctx, sl, st, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
     int tblocks = chord_tau_blocks(nch);
-    if ((rc = scratch(ctx, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
-    if ((rc = scratch(ctx, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
+    if ((rc = scratch(ctx, sl, st, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
     if (op->kind == MCRT_OPAC_HIRES) {
-        if ((rc = scratch(ctx, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
-        if ((rc = scratch(ctx, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
+        if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+        if ((rc = scratch(ctx, sl, st, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
     }
     const uint32_t tag = 0;  // chords are common to all spectral points
     const bool prof = p->profile != 0;
     const int nblk_rows = (nrow + kSlot - 1) / kSlot;
-    if (prof && (rc = prof_events(ctx, (size_t)nblk_rows))) return rc;
+    if (prof && (rc = prof_events(ctx, sl, (size_t)nblk_rows))) return rc;
     res->kernel_ms = 0.0;
     res->kernel_launches = 0;
-    HIPTRY(hipEventRecord(ctx->ev0, st));
+    HIPTRY(hipEventRecord(sl.ev0, st));
     launch_chord_count(g->dev, p->n_b, p->n_alpha, p->seed, tag, (int*)v_cnt, st);
     launch_exclusive_scan_int((int*)v_cnt, (long long*)v_off, nch, nullptr, st);
     long long nseg = 0;
     HIPTRY(hipMemcpyAsync(&nseg, (long long*)v_off + nch, sizeof(long long), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
     void *v_sc, *v_sl;
-    if ((rc = scratch(ctx, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
-    if ((rc = scratch(ctx, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
+    if ((rc = scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
+    if ((rc = scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
     launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
                       (double*)v_b, (int*)v_ok, st);
     if (op->kind == MCRT_OPAC_HIRES) {
@@ -661,17 +776,17 @@ int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_param
             launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
                                      op->k_ray_dev, (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
-        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * (r0 / kSlot)], st));
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st));
         launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok, alpha,
                          nslot, (double*)v_part, tblocks, st);
-        if (prof) HIPTRY(hipEventRecord(ctx->prof_ev[2 * (r0 / kSlot) + 1], st));
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * (r0 / kSlot) + 1], st));
         launch_reduce_partials((double*)v_part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nrow * 2);
     HIPTRY(hipMemcpyAsync(hs.data(), v_sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
-    if ((rc = finish_timing(ctx, st, res))) return rc;
-    if (prof && (rc = prof_collect(ctx, (size_t)nblk_rows, res))) return rc;
+    if ((rc = finish_timing(ctx, sl, st, res))) return rc;
+    if (prof && (rc = prof_collect(ctx, sl, (size_t)nblk_rows, res))) return rc;
 
     // (R_p/R*)^2 = (R0^2 + 2 <I>)/R*^2, <I> = (R_TOA - R0)/N sum (1 - e^-tau) b  (Sect. 5.1)
     const double dr = g->r_toa - g->r0, Nd = (double)nch, rs2 = p->r_star * p->r_star;
@@ -689,6 +804,231 @@ int solve_chords(mcrt_ctx* ctx, int32_t gid, int32_t oid, const mcrt_solve_param
     std::vector<double> sumrows(hs);
     fill_results(pl, val, se, gw, sumrows, 2, cnt, ltot, res);
     return MCRT_OK;
+}
+
+// ------------------------------------------------------------------ serving
+enum { R_QUEUED = 0, R_RUNNING = 1, R_DONE = 2, R_FAILED = 3, R_CANCELLED = 4 };
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    int mode = 0;
+    int32_t gid = 0, oid = 0;
+    mcrt_solve_params p{};
+    std::vector<int32_t> spec;
+    std::vector<double> phase, dir;
+    int status = R_QUEUED;
+    int rc = MCRT_OK;
+    std::string err;
+    int ns = 0, ng = 1, no = 1;
+    uint64_t est = 0;
+    std::vector<double> value, se, per_g, sums, counters, l_tot;
+    double elapsed_ms = 0.0, kernel_ms = 0.0;
+    int64_t launches = 0;
+    Clock::time_point t_sub, t_start, t_done;
+};
+
+int run_solve(mcrt_ctx* ctx, Slot& sl, hipStream_t st, int mode, int32_t gid, int32_t oid,
+              const mcrt_solve_params* p, mcrt_result* res)
+{
+    if (mode == MCRT_MODE_TRANSMISSION) return solve_chords(ctx, sl, st, gid, oid, p, res);
+    if (mode == MCRT_MODE_ALBEDO || mode == MCRT_MODE_EMISSION) return solve_packets(ctx, sl, st, gid, oid, p, res, mode);
+    return fail(MCRT_EINVAL, "unknown mode %d", mode);
+}
+
+int blocking_solve(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_params* p, mcrt_result* res)
+{
+    std::lock_guard<std::mutex> lk(ctx->main_mu);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    return run_solve(ctx, ctx->main, ctx->main.stream, mode, gid, oid, p, res);
+}
+
+// Device bytes a request allocates (its scratch), for admission.
+uint64_t estimate_bytes(mcrt_ctx* ctx, const Request& r, GridRes* g, OpacRes* op)
+{
+    const uint64_t ncell = (uint64_t)g->ncell;
+    const uint64_t nsolve = (uint64_t)r.ns * r.ng;
+    if (r.mode == MCRT_MODE_TRANSMISSION) {
+        const uint64_t nch = (uint64_t)r.p.n_b * r.p.n_alpha;
+        const uint64_t nrow = nsolve, nslot = std::min<uint64_t>(64, nrow);
+        const uint64_t tblocks = (uint64_t)chord_tau_blocks((int)nch);
+        const uint64_t segs = nch * (2ULL * g->dev.nlay + 2ULL * g->dev.nlat + g->dev.nlon + 8ULL);
+        return nch * (4 + 8 + 8 + 4) + 8 + ncell * nslot * 8 + tblocks * 2 * nslot * 8 + nrow * 16 + ncell * 8 +
+               nrow * 4 + segs * 12 + (1ULL << 20);
+    }
+    const bool mixed = r.p.precision == MCRT_MIXED;
+    const uint64_t N = r.p.n_packets;
+    const uint64_t no = (uint64_t)r.no;
+    const uint64_t pw = 2 * no + kNCounters, row_w = pw + 2, prow = no + kNCounters;
+    const uint64_t opt_b = ncell * 5 * (mixed ? 4 : 8);
+    const uint64_t src_b = r.mode == MCRT_MODE_EMISSION ? ncell * 16 : 0;
+    const uint64_t row_b = N * prow * 8;
+    const uint64_t batch = (uint64_t)serving_batch(ctx, r.p.max_batch, (int)nsolve, opt_b + src_b + row_b);
+    const uint64_t chunks = (uint64_t)reduce_rows_chunks(N);
+    uint64_t b = 8 * 5 * ncell * (mixed ? 1 : batch) + (mixed ? opt_b * batch : 0) + row_b * batch + nsolve * row_w * 8 +
+                 batch * chunks * pw * 8 + batch * sizeof(SolveDev) + 64;
+    if (r.mode == MCRT_MODE_EMISSION) b += src_b * batch + ncell * 8 + emission_scratch_doubles((int)ncell) * 8;
+    if (op->kind == MCRT_OPAC_HIRES) b += ncell * 8;
+    return b + (1ULL << 20);
+}
+
+void worker_main(mcrt_ctx* ctx, Slot* sl)
+{
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    for (;;) {
+        ctx->q_cv.wait(lk, [&] {
+            if (ctx->stopping) return true;
+            if (ctx->queue.empty()) return false;
+            std::lock_guard<std::mutex> mk(ctx->mem_mu);
+            return ctx->in_use + ctx->reserved + ctx->queue.front()->est <= ctx->budget;
+        });
+        if (ctx->stopping) return;
+        Request* r = ctx->queue.front();
+        ctx->queue.pop_front();
+        {
+            std::lock_guard<std::mutex> mk(ctx->mem_mu);
+            ctx->reserved += r->est;
+        }
+        r->status = R_RUNNING;
+        r->t_start = Clock::now();
+        lk.unlock();
+        mcrt_result res{};
+        res.value = r->value.data();
+        res.stderr_ = r->se.data();
+        res.per_g = r->per_g.data();
+        res.sums = r->sums.data();
+        res.counters = r->counters.data();
+        res.l_tot = r->l_tot.data();
+        int rc = run_solve(ctx, *sl, sl->stream, r->mode, r->gid, r->oid, &r->p, &res);
+        std::string err = rc ? std::string(mcrt_last_error()) : std::string();
+        release_scratch(ctx, *sl);
+        (void)hipStreamSynchronize(sl->stream);
+        lk.lock();
+        {
+            std::lock_guard<std::mutex> mk(ctx->mem_mu);
+            ctx->reserved -= r->est;
+        }
+        r->rc = rc;
+        r->err = err;
+        r->elapsed_ms = res.elapsed_ms;
+        r->kernel_ms = res.kernel_ms;
+        r->launches = res.kernel_launches;
+        r->t_done = Clock::now();
+        r->status = rc ? R_FAILED : R_DONE;
+        ctx->q_cv.notify_all();
+    }
+}
+
+void stop_workers(mcrt_ctx* ctx)
+{
+    {
+        std::lock_guard<std::mutex> lk(ctx->q_mu);
+        ctx->stopping = true;
+        for (Request* r : ctx->queue) {
+            r->status = R_CANCELLED;
+            r->rc = MCRT_ECANCELLED;
+        }
+        ctx->queue.clear();
+        ctx->q_cv.notify_all();
+    }
+    for (auto& t : ctx->workers) t.join();
+    ctx->workers.clear();
+    for (auto& sl : ctx->wslots) slot_destroy(ctx, *sl);
+    ctx->wslots.clear();
+}
+
+int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_params* p, uint64_t* ticket)
+{
+    if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION && mode != MCRT_MODE_TRANSMISSION)
+        return fail(MCRT_EINVAL, "unknown mode %d", mode);
+    std::unique_ptr<Request> r(new Request());
+    r->mode = mode;
+    r->gid = gid;
+    r->oid = oid;
+    r->p = *p;
+    r->p.stream = nullptr;
+    r->p.packet_dump = nullptr;
+    Lease ls;
+    int rc = lease(ctx, gid, oid, ls);
+    if (rc) return rc;
+    SolvePlan pl;
+    if ((rc = plan_common(nullptr, ls.g, ls.op, p, mode, pl))) return rc;
+    if (p->spec_idx) {
+        r->spec.assign(p->spec_idx, p->spec_idx + p->n_spec);
+        r->p.spec_idx = r->spec.data();
+    }
+    if (p->obs_phase && p->n_obs > 0) {
+        r->phase.assign(p->obs_phase, p->obs_phase + p->n_obs);
+        r->p.obs_phase = r->phase.data();
+    }
+    if (p->obs_dir && p->n_obs > 0) {
+        r->dir.assign(p->obs_dir, p->obs_dir + 3 * p->n_obs);
+        r->p.obs_dir = r->dir.data();
+    }
+    r->ns = (int)pl.specs.size();
+    r->ng = pl.ng;
+    r->no = pl.n_out;
+    const size_t nv = (size_t)r->ns * r->no, ng = (size_t)r->ns * r->ng;
+    r->value.assign(nv, 0.0);
+    r->se.assign(nv, 0.0);
+    r->per_g.assign(ng * r->no, 0.0);
+    r->sums.assign(ng * r->no * 2, 0.0);
+    r->counters.assign(ng * kNCounters, 0.0);
+    r->l_tot.assign(ng, 0.0);
+    r->est = estimate_bytes(ctx, *r, ls.g, ls.op);
+    {
+        std::lock_guard<std::mutex> mk(ctx->mem_mu);
+        if (r->est + ctx->in_use > ctx->budget)
+            return fail(MCRT_EBUDGET, "request needs %llu bytes of scratch; the budget leaves %llu",
+                        (unsigned long long)r->est, (unsigned long long)(ctx->budget - std::min(ctx->budget, ctx->in_use)));
+    }
+    std::lock_guard<std::mutex> lk(ctx->q_mu);
+    if (ctx->stopping) return fail(MCRT_EINVAL, "context is shutting down");
+    if (ctx->workers.empty()) {
+        for (int w = 0; w < ctx->n_workers; ++w) {
+            std::unique_ptr<Slot> sl(new Slot());
+            if ((rc = slot_init(*sl))) return rc;
+            sl->stream_ordered = true;
+            ctx->wslots.push_back(std::move(sl));
+        }
+        for (int w = 0; w < ctx->n_workers; ++w) ctx->workers.emplace_back(worker_main, ctx, ctx->wslots[w].get());
+    }
+    r->ticket = ctx->next_ticket++;
+    r->t_sub = Clock::now();
+    *ticket = r->ticket;
+    ctx->queue.push_back(r.get());
+    ctx->requests[r->ticket] = std::move(r);
+    ctx->q_cv.notify_all();
+    return MCRT_OK;
+}
+
+int wait_request(mcrt_ctx* ctx, uint64_t ticket, mcrt_result* out)
+{
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) return fail(MCRT_ENOTFOUND, "ticket %llu not found", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    ctx->q_cv.wait(lk, [&] { return r->status >= R_DONE; });
+    int rc = r->rc;
+    if (rc == MCRT_OK && out) {
+        if (out->value) std::copy(r->value.begin(), r->value.end(), out->value);
+        if (out->stderr_) std::copy(r->se.begin(), r->se.end(), out->stderr_);
+        if (out->per_g) std::copy(r->per_g.begin(), r->per_g.end(), out->per_g);
+        if (out->sums) std::copy(r->sums.begin(), r->sums.end(), out->sums);
+        if (out->counters) std::copy(r->counters.begin(), r->counters.end(), out->counters);
+        if (out->l_tot) std::copy(r->l_tot.begin(), r->l_tot.end(), out->l_tot);
+        out->elapsed_ms = r->elapsed_ms;
+        out->kernel_ms = r->kernel_ms;
+        out->kernel_launches = r->launches;
+        out->queued_ms = std::chrono::duration<double, std::milli>(r->t_start - r->t_sub).count();
+        out->latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_sub).count();
+    }
+    std::string err = r->err;
+    ctx->requests.erase(it);
+    if (rc) g_err = err;
+    return rc;
 }
 
 }  // namespace
@@ -716,10 +1056,8 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->n_cu = prop.multiProcessorCount;
-    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
-        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
-    if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
-        return fail(MCRT_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    int rc = slot_init(ctx->main);
+    if (rc) return rc;
     *out = ctx.release();
     return MCRT_OK;
 }
@@ -728,20 +1066,72 @@ void mcrt_destroy(mcrt_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    stop_workers(ctx);
+    slot_destroy(ctx, ctx->main);
     for (auto& kv : ctx->grids)
         for (auto& b : kv.second->bufs) dev_free(ctx, b);
     for (auto& kv : ctx->opacs)
         for (auto& b : kv.second->bufs) dev_free(ctx, b);
-    for (auto& kv : ctx->scratch) dev_free(ctx, kv.second);
-    for (auto e : ctx->prof_ev) (void)hipEventDestroy(e);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
 uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+
+int mcrt_serve_config(mcrt_ctx* ctx, int32_t n_workers)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    if (n_workers < 1 || n_workers > 16) return fail(MCRT_EINVAL, "n_workers must be in [1, 16]");
+    std::lock_guard<std::mutex> lk(ctx->q_mu);
+    if (!ctx->workers.empty()) return fail(MCRT_EBUSY, "workers already started");
+    ctx->n_workers = n_workers;
+    return MCRT_OK;
+}
+
+int mcrt_submit(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
+                uint64_t* ticket)
+{
+    if (!ctx || !params || !ticket) return fail(MCRT_EINVAL, "ctx, params and ticket are required");
+    return submit(ctx, mode, grid_id, opac_id, params, ticket);
+}
+
+int mcrt_poll(mcrt_ctx* ctx, uint64_t ticket, int32_t* done)
+{
+    if (!ctx || !done) return fail(MCRT_EINVAL, "ctx and done are required");
+    std::lock_guard<std::mutex> lk(ctx->q_mu);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) return fail(MCRT_ENOTFOUND, "ticket %llu not found", (unsigned long long)ticket);
+    *done = it->second->status >= R_DONE ? 1 : 0;
+    return MCRT_OK;
+}
+
+int mcrt_wait(mcrt_ctx* ctx, uint64_t ticket, mcrt_result* result)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    return wait_request(ctx, ticket, result);
+}
+
+int mcrt_cancel(mcrt_ctx* ctx, uint64_t ticket)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->q_mu);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) return fail(MCRT_ENOTFOUND, "ticket %llu not found", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    if (r->status == R_QUEUED) {
+        for (auto q = ctx->queue.begin(); q != ctx->queue.end(); ++q)
+            if (*q == r) {
+                ctx->queue.erase(q);
+                break;
+            }
+        r->status = R_CANCELLED;
+        r->rc = MCRT_ECANCELLED;
+        r->err = "request was cancelled";
+        ctx->q_cv.notify_all();
+        return MCRT_OK;
+    }
+    if (r->status == R_RUNNING) return fail(MCRT_EBUSY, "request %llu is already running", (unsigned long long)ticket);
+    return MCRT_OK;  // already finished: nothing to cancel
+}
 
 void mcrt_default_params(mcrt_solve_params* p)
 {
@@ -856,7 +1246,7 @@ int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
     if (it == ctx->grids.end()) return fail(MCRT_ENOTFOUND, "grid %d not found", grid_id);
     if (it->second->refs > 0) return fail(MCRT_EBUSY, "grid %d is used by queued work", grid_id);
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->main.stream);
     for (auto& b : it->second->bufs) dev_free(ctx, b);
     ctx->grids.erase(it);
     return MCRT_OK;
@@ -923,7 +1313,7 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)
     if (it == ctx->opacs.end()) return fail(MCRT_ENOTFOUND, "opacity %d not found", opac_id);
     if (it->second->refs > 0) return fail(MCRT_EBUSY, "opacity %d is used by queued work", opac_id);
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->main.stream);
     for (auto& b : it->second->bufs) dev_free(ctx, b);
     ctx->opacs.erase(it);
     return MCRT_OK;
@@ -933,21 +1323,21 @@ int mcrt_solve_albedo(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcr
                       mcrt_result* result)
 {
     if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
-    return solve_packets(ctx, grid_id, opac_id, params, result, MCRT_MODE_ALBEDO);
+    return blocking_solve(ctx, MCRT_MODE_ALBEDO, grid_id, opac_id, params, result);
 }
 
 int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
                         mcrt_result* result)
 {
     if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
-    return solve_packets(ctx, grid_id, opac_id, params, result, MCRT_MODE_EMISSION);
+    return blocking_solve(ctx, MCRT_MODE_EMISSION, grid_id, opac_id, params, result);
 }
 
 int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,
                             mcrt_result* result)
 {
     if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
-    return solve_chords(ctx, grid_id, opac_id, params, result);
+    return blocking_solve(ctx, MCRT_MODE_TRANSMISSION, grid_id, opac_id, params, result);
 }
 
 }  // extern "C"

@@ -25,10 +25,7 @@ COUNTER_NAMES = ["escaped", "surface", "absorbed", "roulette", "capped", "lost",
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTFOUND", -5: "EBUDGET",
           -6: "EBUSY", -7: "ECANCELLED"}
 
-EXPORTED = ["mcrt_create", "mcrt_destroy", "mcrt_last_error", "mcrt_memory_in_use",
-            "mcrt_grid_upload", "mcrt_grid_free", "mcrt_opacity_upload", "mcrt_opacity_free",
-            "mcrt_default_params", "mcrt_solve_albedo", "mcrt_solve_emission",
-            "mcrt_solve_transmission"]
+MODES = {"albedo": 0, "emission": 1, "transmission": 2}
 
 
 class McrtError(RuntimeError):
@@ -68,7 +65,7 @@ class SolveParams(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
                 ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
-                ("kernel_launches", _i64)]
+                ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl)]
 
 
 _lib = None
@@ -97,6 +94,11 @@ def load() -> ctypes.CDLL:
     L.mcrt_default_params.restype = None
     for nm in ("mcrt_solve_albedo", "mcrt_solve_emission", "mcrt_solve_transmission"):
         getattr(L, nm).argtypes = [_vp, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
+    L.mcrt_serve_config.argtypes = [_vp, _i32]
+    L.mcrt_submit.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_u64)]
+    L.mcrt_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i32)]
+    L.mcrt_wait.argtypes = [_vp, _u64, ctypes.POINTER(Result)]
+    L.mcrt_cancel.argtypes = [_vp, _u64]
     _lib = L
     return L
 
@@ -227,17 +229,70 @@ class Context:
         p, keep = self._params(dict(kw))
         ns = p.n_spec if p.spec_idx else n_spec
         no = n_out(p)
-        out = dict(value=np.zeros((ns, no)), stderr=np.zeros((ns, no)), per_g=np.zeros((ns, ng, no)),
-                   sums=np.zeros((ns, ng, no, 2)), counters=np.zeros((ns, ng, NCOUNTERS)),
-                   l_tot=np.zeros((ns, ng)))
-        r = Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
-                   out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data, 0.0, 0.0, 0)
+        out = self._alloc(ns, ng, no)
+        r = self._result(out)
         _check(fn(self._h, gid, oid, ctypes.byref(p), ctypes.byref(r)))
+        self._finish(out, r)
+        del keep
+        return out
+
+    @staticmethod
+    def _shapes(table, mode, p):
+        ck = hasattr(table, "g_weights")
+        ns_tab = table.nband if ck else table.nlam
+        ns = p.n_spec if p.spec_idx else ns_tab
+        ng = table.ng if ck else 1
+        no = 1 if mode == "transmission" else max(p.n_obs, 1)
+        return ns, ng, no
+
+    @staticmethod
+    def _alloc(ns, ng, no):
+        return dict(value=np.zeros((ns, no)), stderr=np.zeros((ns, no)), per_g=np.zeros((ns, ng, no)),
+                    sums=np.zeros((ns, ng, no, 2)), counters=np.zeros((ns, ng, NCOUNTERS)),
+                    l_tot=np.zeros((ns, ng)))
+
+    @staticmethod
+    def _result(out):
+        return Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
+                      out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data,
+                      0.0, 0.0, 0, 0.0, 0.0)
+
+    @staticmethod
+    def _finish(out, r):
         out["elapsed_ms"] = r.elapsed_ms
         out["kernel_ms"] = r.kernel_ms
         out["kernel_launches"] = r.kernel_launches
-        del keep
+        out["queued_ms"] = r.queued_ms
+        out["latency_ms"] = r.latency_ms
+
+    # ---------------------------------------------------------- serving
+    def serve_config(self, n_workers: int):
+        _check(load().mcrt_serve_config(self._h, n_workers))
+
+    def submit(self, mode: str, gid: int, oid: int, table, **kw) -> int:
+        """Queue a solve; returns a ticket.  The result shape is kept with it."""
+        p, keep = self._params(dict(kw))
+        t = _u64()
+        _check(load().mcrt_submit(self._h, MODES[mode], gid, oid, ctypes.byref(p), ctypes.byref(t)))
+        self._pending = getattr(self, "_pending", {})
+        self._pending[t.value] = self._shapes(table, mode, p)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = _i32()
+        _check(load().mcrt_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> dict:
+        ns, ng, no = self._pending.pop(ticket)
+        out = self._alloc(ns, ng, no)
+        r = self._result(out)
+        _check(load().mcrt_wait(self._h, ticket, ctypes.byref(r)))
+        self._finish(out, r)
         return out
+
+    def cancel(self, ticket: int):
+        _check(load().mcrt_cancel(self._h, ticket))
 
     def solve_albedo(self, gid, oid, table, **kw):
         return self._solve(load().mcrt_solve_albedo, gid, oid, table.nband,

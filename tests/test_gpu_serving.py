@@ -1,0 +1,85 @@
+"""Serving: asynchronous requests admitted by HBM budget and run concurrently
+on worker streams give the same results as the blocking solves, alone or in
+a mix; cancellation and budget rejection."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_15640_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_mixed_requests_equal_their_blocking_solves(torch_dev):
+    print("serving: 12 mixed requests on 3 workers vs blocking solves", flush=True)
+    from paper_2110_15640_amd import mcrt as M
+    slab, ck1 = I.make_albedo_slab(nlay=20, nlam=4)
+    grid, ck, phases = I.make_emission_3d(16, 8, 10, nband=3, ng=2)
+    hg, hr = I.make_transmission_hires(16, 8, 10, nlam=200, nT=5, nP=5)
+    with M.Context(0) as ctx:
+        ctx.serve_config(3)
+        ids = dict(slab=(ctx.upload_grid(slab), ctx.upload_opacity(ck1), ck1),
+                   em=(ctx.upload_grid(grid), ctx.upload_opacity(ck), ck),
+                   tr=(ctx.upload_grid(hg), ctx.upload_opacity(hr), hr))
+        reqs = []
+        for q in range(12):
+            kind = ["slab", "em", "tr"][q % 3]
+            gid, oid, tab = ids[kind]
+            if kind == "slab":
+                reqs.append(("albedo", kind, dict(n_packets=2000 + 100 * q, seed=q)))
+            elif kind == "em":
+                reqs.append(("emission", kind, dict(n_packets=1500 + 10 * q, seed=q, obs_phase=list(phases),
+                                                    precision=q % 2)))
+            else:
+                reqs.append(("transmission", kind, dict(n_b=16, n_alpha=20, seed=q, spec_idx=list(range(q, q + 70)))))
+        tickets = []
+        for mode, kind, kw in reqs:
+            gid, oid, tab = ids[kind]
+            tickets.append(ctx.submit(mode, gid, oid, tab, **kw))
+        got = [ctx.wait(t) for t in tickets]
+        for (mode, kind, kw), g in zip(reqs, got):
+            gid, oid, tab = ids[kind]
+            ref = getattr(ctx, "solve_" + mode)(gid, oid, tab, **kw)
+            assert np.array_equal(g["sums"], ref["sums"]), (mode, kw)
+            assert np.array_equal(g["value"], ref["value"]), (mode, kw)
+            assert g["latency_ms"] >= g["queued_ms"] >= 0.0
+
+
+def test_cancel_poll_and_budget(torch_dev):
+    print("serving: cancel, poll and budget rejection", flush=True)
+    from paper_2110_15640_amd import mcrt as M
+    grid, ck, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2)
+    with M.Context(0) as ctx:
+        ctx.serve_config(1)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(ck)
+        t1 = ctx.submit("emission", gid, oid, ck, n_packets=200000, obs_phase=[0.5])
+        t2 = ctx.submit("emission", gid, oid, ck, n_packets=1000, obs_phase=[0.5])
+        ctx.cancel(t2)  # queued behind t1 on the single worker
+        with pytest.raises(M.McrtError) as e:
+            ctx.wait(t2)
+        assert e.value.name == "ECANCELLED"
+        r1 = ctx.wait(t1)
+        assert np.all(r1["value"] > 0)
+        with pytest.raises(M.McrtError) as e:
+            ctx.submit("emission", gid, oid, ck, n_packets=1 << 40, obs_phase=[0.5])
+        assert e.value.name == "EBUDGET"
+        t3 = ctx.submit("emission", gid, oid, ck, n_packets=500, obs_phase=[0.5])
+        import time
+        for _ in range(2000):
+            if ctx.poll(t3):
+                break
+            time.sleep(0.005)
+        assert ctx.poll(t3)
+        ctx.wait(t3)
+        with pytest.raises(M.McrtError) as e:
+            ctx.poll(t3)
+        assert e.value.name == "ENOTFOUND"
