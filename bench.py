@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-packets", type=int, default=3000)
+    ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="run one 1 GiB device copy first (reference kernel for HBM counter scaling)")
     return ap.parse_args()
 
 
@@ -58,6 +61,31 @@ def cpu_baseline(grid, table, phases, n_per):
     return {"value": npk / dt, "unit": "packets/s", "cores": int(O.lib().orc_max_threads()), "kind": "oracle",
             "sample": f"{len(bands)} evenly spaced bands x {table.ng} g x {n_per} packets on the full "
                       f"{grid.nlon}x{grid.nlat}x{grid.nlay} grid, 4 phases ({npk} packets, {dt:.1f} s)"}
+
+
+def transmission_leg(M, I):
+    """3D high-resolution transmission: 128x64x60 grid with winds, 20,000
+    wavelengths (1.0-1.1 um), 256 x 360 jittered chords; the Doppler-shifted
+    alpha gather and the chord optical depths for every wavelength."""
+    import torch
+    grid, table = I.make_transmission_hires()
+    with M.Context(0) as ctx:
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+        kw = dict(n_b=256, n_alpha=360, seed=211015643, r_star=I.R_SUN, profile=1)
+        ctx.solve_transmission(gid, oid, table, spec_idx=list(range(64)), **kw)  # scratch and chords warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.solve_transmission(gid, oid, table, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        depth = r["value"][:, 0]
+        nch = 256 * 360
+        return {"workload": f"3D hi-res transmission: {grid.nlon}x{grid.nlat}x{grid.nlay} grid, {table.nlam} wavelengths "
+                            "1.0-1.1 um, 256 x 360 chords, winds + rotation Doppler",
+                "ms": wall * 1e3, "chord_wavelengths_per_s": nch * table.nlam / wall,
+                "chord_tau_kernel_ms": r["kernel_ms"], "chord_tau_launches": r["kernel_launches"],
+                "depth_min": float(depth.min()), "depth_max": float(depth.max()),
+                "rel_se_median": float(np.median(r["stderr"][:, 0] / depth))}
 
 
 def run_form(ctx, M, gid, oid, table, bands, npk, phases, precision, max_batch, steps, warmup, tune):
@@ -105,12 +133,23 @@ def main():
     gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
     pk_step = len(bands) * table.ng * npk
     tune = {}
+    if a.copy_calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] workload: {len(bands)} bands x {table.ng} g x {npk} packets, 4 phases", flush=True)
     # warm the library's kernels and scratch once on a single band
     ctx.solve_emission(gid, oid, table, n_packets=npk, obs_phase=list(phases), spec_idx=[0], precision=M.MCRT_MIXED)
     print("[bench] plain form: FP64, one transport launch per (band, g)", flush=True)
     pres, pwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_FP64, 1, a.plain_steps, 0, tune)
     pval, prel, _, pcross, pkms, plaunch = summarize(pres, pwall, a.plain_steps, pk_step, npk, table.ng)
+    print("[bench] autotuning the persistent launch shape (untimed)", flush=True)
+    tuned = ctx.autotune("emission", gid, oid, n_packets=npk, obs_phase=list(phases), spec_idx=bands,
+                         precision=M.MCRT_MIXED)
+    tune = {k: v for k, v in tuned.items() if k.startswith("tune_")}
+    print(f"[bench] tuned: {tune}", flush=True)
     print("[bench] batched form: FP32-mixed, all (band, g) solves in persistent launches", flush=True)
     bres, bwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_MIXED, 0, a.steps, a.warmup, tune)
     value, rel, need, cross, kms, launches = summarize(bres, bwall, a.steps, pk_step, npk, table.ng)
@@ -130,6 +169,7 @@ def main():
                   "ms_per_step": pwall / a.plain_steps * 1e3, "launches_per_step": plaunch // a.plain_steps,
                   "kernel_ms_per_step": pkms / a.plain_steps},
         "batched_over_plain": value / pval,
+        "tuned_launch": tune,
         "error": {"rel_se_median": float(np.median(rel)), "rel_se_max": float(rel.max()),
                   "packets_per_band_for_1e-3_median": float(np.median(need)),
                   "seconds_per_band_for_1e-3_median_batched": float(np.median(need)) / value,
@@ -140,6 +180,8 @@ def main():
                      "avg_launch_ms": kms / max(launches, 1), "launches": launches,
                      "flop_per_crossing": FLOP_PER_CROSSING},
     }
+    if a.transmission:
+        out["transmission"] = transmission_leg(M, I)
     if a.cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, table, phases, a.cpu_packets)

@@ -244,6 +244,16 @@ int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
 int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
                             const mcrt_solve_params* params, mcrt_result* result);
 
+/* Autotuner for the persistent transport launch shape: runs short trial
+ * solves of this request (up to 3 of its spectral points, at most 2e5
+ * packets each) over event thresholds {8, 16, 32}, blocks per compute unit
+ * {2, 4} and wave batches {32, 128}, and writes the fastest into
+ * params->tune_* (best_packets_per_s, if not NULL, receives its trial rate).
+ * Results of a solve do not depend on these settings.  mode: MCRT_MODE_ALBEDO
+ * or MCRT_MODE_EMISSION.  Errors as for the blocking solves. */
+int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
+                  mcrt_solve_params* params, double* best_packets_per_s);
+
 /* Serving: asynchronous solves with continuous admission.
  * mcrt_submit copies params (and the arrays they point to; stream and
  * packet_dump are ignored) and queues the request; mode is MCRT_MODE_*.

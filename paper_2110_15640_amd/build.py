@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcrt.so")
-SOURCES = ["kernels.hip", "transport.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "prep.hip", "transport.hip", "api.cpp"]
 
 # -ffp-contract=off keeps every FP64 expression in the order it is written
 # (no fused multiply-add), so the FP64 path agrees with an independent FP64

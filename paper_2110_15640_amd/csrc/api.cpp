@@ -550,7 +550,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     const uint64_t N = p->n_packets;
 
     // per-solve device footprint and the batch size the budget allows
-    const size_t opt_b = (size_t)ncell * 5 * (mixed ? sizeof(float) : sizeof(double));
+    const size_t opt_b = (size_t)ncell * 5 * (sizeof(double) + (mixed ? sizeof(float) : 0));
     const size_t src_b = mode == MCRT_MODE_EMISSION ? (size_t)ncell * 2 * sizeof(double) : 0;
     const size_t row_b = (size_t)N * prow * sizeof(double);
     const size_t per_solve = opt_b + src_b + row_b;
@@ -569,19 +569,21 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         batch = std::max(1, std::min(std::min(batch, fit), nsolve));
     }
     const int chunks = reduce_rows_chunks(N);
-    void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_L = nullptr, *v_es = nullptr,
-                 *v_shift = nullptr, *v_solves, *v_ctr;
-    if ((rc = scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * (mixed ? 1 : batch), &v_opt))) return rc;
-    if (mixed && (rc = scratch(ctx, sl, st, "optics_f32", opt_b * batch, &v_optf))) return rc;
+    void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_ps = nullptr,
+                 *v_shift = nullptr, *v_solves, *v_slots, *v_ctr;
+    if ((rc = scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * batch, &v_opt))) return rc;
+    if (mixed && (rc = scratch(ctx, sl, st, "optics_f32", sizeof(float) * 5 * (size_t)ncell * batch, &v_optf)))
+        return rc;
     if ((rc = scratch(ctx, sl, st, "rows", row_b * batch, &v_rows))) return rc;
     if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
     if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
     if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
+    if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * (size_t)batch, &v_slots))) return rc;
     if ((rc = scratch(ctx, sl, st, "dispenser", 64, &v_ctr))) return rc;
     if (mode == MCRT_MODE_EMISSION) {
         if ((rc = scratch(ctx, sl, st, "sources", src_b * batch, &v_src))) return rc;
-        if ((rc = scratch(ctx, sl, st, "L", sizeof(double) * (size_t)ncell, &v_L))) return rc;
-        if ((rc = scratch(ctx, sl, st, "em_scratch", sizeof(double) * emission_scratch_doubles(ncell), &v_es))) return rc;
+        if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * prep_scratch_doubles(ncell, batch), &v_ps)))
+            return rc;
     }
     if (op->kind == MCRT_OPAC_HIRES)
         if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
@@ -605,7 +607,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[q] = pl.obs[q];
     A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
-    const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 2;
+    const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
 
     const bool prof = p->profile != 0;
@@ -614,63 +616,65 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     res->kernel_ms = 0.0;
     res->kernel_launches = 0;
     std::vector<std::vector<SolveDev>> host_solves(nbatches);
+    std::vector<std::vector<PrepSlot>> host_slots(nbatches);
     HIPTRY(hipEventRecord(sl.ev0, st));
     HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
     if (op->kind == MCRT_OPAC_HIRES)
         launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
     for (int bt = 0; bt < nbatches; ++bt) {
-        const int s0 = bt * batch, s1 = std::min(nsolve, s0 + batch);
+        const int s0 = bt * batch, s1 = std::min(nsolve, s0 + batch), nb = s1 - s0;
         std::vector<SolveDev>& hsv = host_solves[bt];
-        hsv.resize(s1 - s0);
+        std::vector<PrepSlot>& hps = host_slots[bt];
+        hsv.resize(nb);
+        hps.resize(nb);
         for (int sg = s0; sg < s1; ++sg) {
             const int slot = sg - s0;
             const int b = pl.specs[sg / ng], gi = sg % ng;
-            double* o64 = (double*)v_opt + (mixed ? 0 : (size_t)slot * 5 * ncell);
-            OpticsDev<double> od{o64, o64 + ncell, o64 + 2 * (size_t)ncell, o64 + 3 * (size_t)ncell,
-                                 o64 + 4 * (size_t)ncell};
-            if (op->kind == MCRT_OPAC_CK) {
-                const double* tab = op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP;
-                launch_ck_optics(g->dev, ncell, tab, op->nT, op->nP, op->T_grid, op->lnP_grid, op->k_ray[b], od, 1, st);
-            } else {
-                launch_hires_optics(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
-                                    op->k_ray[b], (double*)v_shift, b, od, st);
-            }
+            PrepSlot& P = hps[slot];
+            P.lnk = op->kind == MCRT_OPAC_CK ? op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP : nullptr;
+            P.k_ray = op->k_ray[b];
+            P.n = b;
+            const double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
+            P.lam_cm = lam * 1e-4;
+            P.opt = (double*)v_opt + (size_t)slot * 5 * ncell;
+            P.optf = mixed ? (float*)v_optf + (size_t)slot * 5 * ncell : nullptr;
+            P.cdf = mode == MCRT_MODE_EMISSION ? (double*)v_src + (size_t)slot * 2 * ncell : nullptr;
+            P.wbirth = P.cdf ? P.cdf + ncell : nullptr;
+            P.stats = sums + (size_t)sg * row_w + pw;
             SolveDev& S = hsv[slot];
             S.begin = (unsigned long long)slot * N;
             S.n = N;
             S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
             S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
-            S.cdf = nullptr;
-            S.wbirth = nullptr;
-            if (mode == MCRT_MODE_EMISSION) {
-                double* cdf = (double*)v_src + (size_t)slot * 2 * ncell;
-                double* wb = cdf + ncell;
-                double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
-                launch_emission_sources(g->dev, od, lam * 1e-4, p->tau_vert_max, p->emis_bias, (double*)v_L, cdf, wb,
-                                        (double*)v_es, sums + (size_t)sg * row_w + pw, st);
-                S.cdf = cdf;
-                S.wbirth = wb;
-            }
+            S.cdf = P.cdf;
+            S.wbirth = P.wbirth;
             if (mixed) {
-                float* o32 = (float*)v_optf + (size_t)slot * 5 * ncell;
-                OpticsDev<float> of{o32, o32 + ncell, o32 + 2 * (size_t)ncell, o32 + 3 * (size_t)ncell,
-                                    o32 + 4 * (size_t)ncell};
-                launch_mixed_optics(od, of, ncell, st);
-                S.a_ext = of.a_ext; S.a_abs = of.a_abs; S.omega = of.omega; S.p_gas = of.p_gas; S.g_cld = of.g_cld;
+                const float* f = P.optf;
+                S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
+                S.g_cld = f + 4 * (size_t)ncell;
             } else {
-                S.a_ext = od.a_ext; S.a_abs = od.a_abs; S.omega = od.omega; S.p_gas = od.p_gas; S.g_cld = od.g_cld;
+                const double* d = P.opt;
+                S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
+                S.g_cld = d + 4 * (size_t)ncell;
             }
         }
-        HIPTRY(hipMemcpyAsync(v_solves, hsv.data(), sizeof(SolveDev) * hsv.size(), hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(v_slots, hps.data(), sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(v_solves, hsv.data(), sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
+        launch_prep_optics(g->dev, ncell, (const PrepSlot*)v_slots, nb, op->kind == MCRT_OPAC_HIRES ? 1 : 0, op->nT,
+                           op->nP, op->T_grid, op->lnP_grid, op->lnk, op->nspec, (const double*)v_shift, st);
+        if (mode == MCRT_MODE_EMISSION)
+            launch_prep_sources(g->dev, ncell, (const PrepSlot*)v_slots, nb, p->tau_vert_max, p->emis_bias,
+                                (double*)v_ps, st);
         A.solves = (const SolveDev*)v_solves;
-        A.n_solves = s1 - s0;
-        A.total = (unsigned long long)(s1 - s0) * N;
+        A.n_solves = nb;
+        A.total = (unsigned long long)nb * N;
         launch_fill_u64(A.counter, 0ULL, st);
+        launch_births(g->dev, A, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
         launch_transport_persistent(g->dev, A, mixed, pblocks, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
         double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
-        launch_reduce_rows(A, nullptr, s1 - s0, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
+        launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
         if (bt + 1 < nbatches) HIPTRY(hipStreamSynchronize(st));  // slots are reused by the next batch
     }
     HIPTRY(hipGetLastError());
@@ -861,14 +865,14 @@ uint64_t estimate_bytes(mcrt_ctx* ctx, const Request& r, GridRes* g, OpacRes* op
     const uint64_t N = r.p.n_packets;
     const uint64_t no = (uint64_t)r.no;
     const uint64_t pw = 2 * no + kNCounters, row_w = pw + 2, prow = no + kNCounters;
-    const uint64_t opt_b = ncell * 5 * (mixed ? 4 : 8);
+    const uint64_t opt_b = ncell * 5 * (8 + (mixed ? 4 : 0));
     const uint64_t src_b = r.mode == MCRT_MODE_EMISSION ? ncell * 16 : 0;
     const uint64_t row_b = N * prow * 8;
     const uint64_t batch = (uint64_t)serving_batch(ctx, r.p.max_batch, (int)nsolve, opt_b + src_b + row_b);
     const uint64_t chunks = (uint64_t)reduce_rows_chunks(N);
-    uint64_t b = 8 * 5 * ncell * (mixed ? 1 : batch) + (mixed ? opt_b * batch : 0) + row_b * batch + nsolve * row_w * 8 +
-                 batch * chunks * pw * 8 + batch * sizeof(SolveDev) + 64;
-    if (r.mode == MCRT_MODE_EMISSION) b += src_b * batch + ncell * 8 + emission_scratch_doubles((int)ncell) * 8;
+    uint64_t b = opt_b * batch + row_b * batch + nsolve * row_w * 8 + batch * chunks * pw * 8 +
+                 batch * (sizeof(SolveDev) + sizeof(PrepSlot)) + 64;
+    if (r.mode == MCRT_MODE_EMISSION) b += src_b * batch + prep_scratch_doubles((int)ncell, (int)batch) * 8;
     if (op->kind == MCRT_OPAC_HIRES) b += ncell * 8;
     return b + (1ULL << 20);
 }
@@ -1316,6 +1320,71 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)
     (void)hipStreamSynchronize(ctx->main.stream);
     for (auto& b : it->second->bufs) dev_free(ctx, b);
     ctx->opacs.erase(it);
+    return MCRT_OK;
+}
+
+int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id, mcrt_solve_params* params,
+                  double* best_packets_per_s)
+{
+    if (!ctx || !params) return fail(MCRT_EINVAL, "ctx and params are required");
+    if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION)
+        return fail(MCRT_EINVAL, "autotuning applies to the packet transport (albedo, emission)");
+    // trial: up to 3 spectral points of the request (first, middle, last), at
+    // most 2e5 packets each, all in one batch
+    std::vector<int32_t> spec;
+    if (params->spec_idx && params->n_spec > 0) {
+        spec.push_back(params->spec_idx[0]);
+        if (params->n_spec > 2) spec.push_back(params->spec_idx[params->n_spec / 2]);
+        if (params->n_spec > 1) spec.push_back(params->spec_idx[params->n_spec - 1]);
+    } else {
+        Lease ls;
+        int rc = lease(ctx, grid_id, opac_id, ls);
+        if (rc) return rc;
+        int ns = ls.op->nspec;
+        spec.push_back(0);
+        if (ns > 2) spec.push_back(ns / 2);
+        if (ns > 1) spec.push_back(ns - 1);
+    }
+    mcrt_solve_params t = *params;
+    t.spec_idx = spec.data();
+    t.n_spec = (int32_t)spec.size();
+    t.n_packets = std::min<uint64_t>(params->n_packets, 200000);
+    t.max_batch = 0;
+    t.packet_dump = nullptr;
+    t.profile = 0;
+    const int evs[3] = {8, 16, 32}, bpcs[2] = {2, 4}, wbs[2] = {32, 128};
+    double best = -1.0;
+    int be = 16, bb = 4, bw = 64;
+    std::vector<double> v(64 * 8), e(64 * 8);
+    mcrt_result r{};
+    r.value = v.data();
+    r.stderr_ = e.data();
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                t.tune_ev_threshold = evs[a];
+                t.tune_blocks_per_cu = bpcs[b];
+                t.tune_wave_batch = wbs[c];
+                if (v.size() < (size_t)t.n_spec * std::max(1, t.n_obs)) {
+                    v.resize((size_t)t.n_spec * std::max(1, t.n_obs));
+                    e.resize(v.size());
+                    r.value = v.data();
+                    r.stderr_ = e.data();
+                }
+                int rc = blocking_solve(ctx, mode, grid_id, opac_id, &t, &r);
+                if (rc) return rc;
+                double rate = (double)t.n_packets * t.n_spec / std::max(r.elapsed_ms, 1e-3) * 1e3;
+                if (rate > best) {
+                    best = rate;
+                    be = evs[a];
+                    bb = bpcs[b];
+                    bw = wbs[c];
+                }
+            }
+    params->tune_ev_threshold = be;
+    params->tune_blocks_per_cu = bb;
+    params->tune_wave_batch = bw;
+    if (best_packets_per_s) *best_packets_per_s = best;
     return MCRT_OK;
 }
 

@@ -366,5 +366,216 @@ __device__ __forceinline__ double interp_tp(F lnk, const Bracket& bt, const Brac
 }
 
 
+// ---------------------------------------------------------------- walker
+// Straight-line walk through the cells from an origin p0 along unit d.  Along
+// a straight line every face surface is met at fixed ray parameters t (a
+// shell or a cone at most twice, a longitude plane once), so the walk keeps
+// the parameters of the current cell's faces and, after a crossing, computes
+// only the faces that are new to the cell: one shell, one cone or one plane.
+// Positions are never advanced step by step (p(t) = p0 + t d), so there is no
+// drift; tie order and entry-face rules are those of exit_distance.
+struct Walker {
+    double px, py, pz;      // origin
+    double dx, dy, dz;      // unit direction
+    double t;               // distance walked from the origin
+    double B0, C0;          // p0 . d, |p0|^2 (spherical) ; unused for the slab
+    double tout, tin;       // outer-face exit / inner-face hit (INFINITY = none)
+    double lo1, lo2;        // lower latitude cone roots on its nappe, ascending
+    double hi1, hi2;        // upper latitude cone roots
+    double tlo, thi;        // lower / upper longitude half-plane hits
+    int i, j, k;
+    int ef;                 // face by which the current cell was entered
+};
+
+__device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, bool need_out, bool need_in)
+{
+    if (g.geom == 1) {
+        if (need_out) w.tout = w.dz > 0.0 ? fmax((g.r[w.k + 1] - w.pz) / w.dz, w.t) : INFINITY;
+        if (need_in) w.tin = w.dz < 0.0 ? fmax((g.r[w.k] - w.pz) / w.dz, w.t) : INFINITY;
+        return;
+    }
+    if (need_out) {
+        double R = g.r[w.k + 1];
+        double C = w.C0 - R * R;
+        double D = w.B0 * w.B0 - C;
+        if (D < 0.0) D = 0.0;
+        double sq = sqrt(D);
+        double far = (w.B0 <= 0.0) ? (-w.B0 + sq) : (-C / (w.B0 + sq));
+        w.tout = fmax(far, w.t);
+    }
+    if (need_in) {
+        w.tin = INFINITY;
+        if (w.B0 < 0.0) {
+            double R = g.r[w.k];
+            double C = w.C0 - R * R;
+            double D = w.B0 * w.B0 - C;
+            if (D >= 0.0) {
+                double nr = C / (-w.B0 + sqrt(D));
+                if (nr >= w.t || C < 0.0) w.tin = fmax(nr, w.t);
+            }
+        }
+    }
+}
+
+// Roots of the latitude cone of edge e on the nappe of its sign (or the
+// equatorial plane), ascending, INFINITY where absent.
+__device__ __forceinline__ void wk_cone(const GridDev& g, const Walker& w, int e, double& r1, double& r2)
+{
+    r1 = INFINITY;
+    r2 = INFINITY;
+    double tb = g.lat[e];
+    if (tb == 0.0) {
+        if (w.dz != 0.0) r1 = -w.pz / w.dz;
+        return;
+    }
+    double c2 = g.lat_c2[e], s2 = g.lat_s2[e];
+    double a = w.dz * w.dz * c2 - (w.dx * w.dx + w.dy * w.dy) * s2;
+    double b = w.pz * w.dz * c2 - (w.px * w.dx + w.py * w.dy) * s2;
+    double c = w.pz * w.pz * c2 - (w.px * w.px + w.py * w.py) * s2;
+    double x0 = INFINITY, x1 = INFINITY;
+    if (a == 0.0) {
+        if (b != 0.0) x0 = -c / (2.0 * b);
+    } else {
+        double disc = b * b - a * c;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -(b + (b >= 0.0 ? sq : -sq));
+            x0 = q / a;
+            if (q != 0.0) x1 = c / q;
+        }
+    }
+    bool ok0 = x0 < INFINITY && (tb > 0.0 ? (w.pz + x0 * w.dz > 0.0) : (w.pz + x0 * w.dz < 0.0));
+    bool ok1 = x1 < INFINITY && (tb > 0.0 ? (w.pz + x1 * w.dz > 0.0) : (w.pz + x1 * w.dz < 0.0));
+    if (!ok0) x0 = INFINITY;
+    if (!ok1) x1 = INFINITY;
+    r1 = fmin(x0, x1);
+    r2 = fmax(x0, x1);
+    if (!(r1 < INFINITY)) r2 = INFINITY;
+}
+
+// Hit of the longitude half-plane of edge e (upper = the cell's upper face).
+__device__ __forceinline__ double wk_plane(const GridDev& g, const Walker& w, int e, bool upper)
+{
+    double sb = g.lon_s[e], cb = g.lon_c[e];
+    double nx = -sb, ny = cb;
+    double dn = w.dx * nx + w.dy * ny;
+    if (upper ? !(dn > 0.0) : !(dn < 0.0)) return INFINITY;
+    double th = fmax(-(w.px * nx + w.py * ny) / dn, w.t);
+    double hx = w.px + th * w.dx, hy = w.py + th * w.dy;
+    return (cb * hx + sb * hy > 0.0) ? th : INFINITY;
+}
+
+__device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, double px, double py, double pz, double dx,
+                                         double dy, double dz, int i, int j, int k, int ef)
+{
+    w.px = px; w.py = py; w.pz = pz;
+    w.dx = dx; w.dy = dy; w.dz = dz;
+    w.t = 0.0;
+    w.i = i; w.j = j; w.k = k;
+    w.ef = ef;
+    w.B0 = px * dx + py * dy + pz * dz;
+    w.C0 = px * px + py * py + pz * pz;
+    wk_shells(g, w, true, true);
+    w.lo1 = w.lo2 = w.hi1 = w.hi2 = INFINITY;
+    w.tlo = w.thi = INFINITY;
+    if (g.geom == 1) return;
+    if (j > 0) wk_cone(g, w, j, w.lo1, w.lo2);
+    if (j < g.nlat - 1) wk_cone(g, w, j + 1, w.hi1, w.hi2);
+    if (g.nlon > 1) {
+        w.tlo = wk_plane(g, w, i, false);
+        w.thi = wk_plane(g, w, i + 1 == g.nlon ? 0 : i + 1, true);
+    }
+}
+
+// Next cone root at or after t; roots of the cone just crossed must lie more
+// than 1e-9 |p| ahead (the same entry-face tolerance as exit_distance).
+__device__ __forceinline__ double wk_next_root(double r1, double r2, double t, double lo)
+{
+    if (r1 >= lo) return r1;
+    if (r2 >= lo) return r2;
+    return INFINITY;
+}
+
+// Parameter and face of the next crossing (ties: outer, inner, lat-low,
+// lat-high, lon-low, lon-high).
+__device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double& tf)
+{
+    double best = w.tout;
+    int face = w.tout < INFINITY ? F_OUT : F_NONE;
+    if (w.tin < best) { best = w.tin; face = F_IN; }
+    if (g.geom == 1) {
+        tf = best;
+        return face;
+    }
+    double lo = w.t;
+    if (w.ef == F_LATLO || w.ef == F_LATHI) lo = w.t + 1e-9 * sqrt(w.C0 + w.t * (2.0 * w.B0 + w.t));
+    double a = wk_next_root(w.lo1, w.lo2, w.t, w.ef == F_LATLO ? lo : w.t);
+    if (a < best) { best = a; face = F_LATLO; }
+    double b = wk_next_root(w.hi1, w.hi2, w.t, w.ef == F_LATHI ? lo : w.t);
+    if (b < best) { best = b; face = F_LATHI; }
+    if (w.tlo < best) { best = w.tlo; face = F_LONLO; }
+    if (w.thi < best) { best = w.thi; face = F_LONHI; }
+    tf = best;
+    return face;
+}
+
+// Move to parameter tf on face f, enter the neighbour cell and compute the
+// faces that are new to it.  Returns false when the walk left the grid
+// (k == nlay: top; k < 0: surface).
+__device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
+{
+    w.t = tf;
+    switch (f) {
+    case F_OUT:
+        w.k += 1;
+        w.ef = F_IN;
+        if (w.k >= g.nlay) return false;
+        w.tin = INFINITY;
+        wk_shells(g, w, true, false);
+        return true;
+    case F_IN:
+        w.k -= 1;
+        w.ef = F_OUT;
+        if (w.k < 0) return false;
+        wk_shells(g, w, true, true);
+        return true;
+    case F_LATLO:
+        w.j -= 1;
+        w.ef = F_LATHI;
+        w.hi1 = w.lo1;
+        w.hi2 = w.lo2;
+        if (w.j > 0) wk_cone(g, w, w.j, w.lo1, w.lo2);
+        else w.lo1 = w.lo2 = INFINITY;
+        return true;
+    case F_LATHI:
+        w.j += 1;
+        w.ef = F_LATLO;
+        w.lo1 = w.hi1;
+        w.lo2 = w.hi2;
+        if (w.j < g.nlat - 1) wk_cone(g, w, w.j + 1, w.hi1, w.hi2);
+        else w.hi1 = w.hi2 = INFINITY;
+        return true;
+    case F_LONLO:
+        w.i = w.i == 0 ? g.nlon - 1 : w.i - 1;
+        w.ef = F_LONHI;
+        w.thi = INFINITY;
+        w.tlo = wk_plane(g, w, w.i, false);
+        return true;
+    case F_LONHI:
+        w.i = w.i + 1 == g.nlon ? 0 : w.i + 1;
+        w.ef = F_LONLO;
+        w.tlo = INFINITY;
+        w.thi = wk_plane(g, w, w.i + 1 == g.nlon ? 0 : w.i + 1, true);
+        return true;
+    default:
+        return false;
+    }
+}
+
+__device__ __forceinline__ int wk_cell(const GridDev& g, const Walker& w)
+{
+    return (w.k * g.nlat + w.j) * g.nlon + w.i;
+}
+
 }  // namespace dev
 }  // namespace mcrt

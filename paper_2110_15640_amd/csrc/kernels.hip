@@ -6,9 +6,7 @@
 //                     centre)
 // K2 doppler/hires    line-of-sight velocity and Doppler-shifted
 //                     high-resolution opacity (Sect. 7, v_LOS and lambda_eff)
-// K3 emission sources cell luminosity L_i = 4 pi V_i rho kappa_abs B(T_i)
-//                     (Sect. 5.3), tau_vert cut (Sect. 4.6), hybrid bias CDF
-//                     (Sect. 4.3)
+// (K3 emission sources and the batched K1/K2 of the transport: prep.hip)
 // (K4 transport lives in transport.hip)
 // K5 chords           transmission chord geometry and per-wavelength optical
 //                     depth (Sect. 5.1)
@@ -117,82 +115,7 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
     alpha[(size_t)c * slot_stride + s] = g.rho[c] * kext;
 }
 
-__global__ void __launch_bounds__(256) k_hires_optics(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
-                                                      int nlam, int nT, int nP, const double* __restrict__ T_grid,
-                                                      const double* __restrict__ lnP_grid, double k_ray,
-                                                      const double* __restrict__ shift, int n, OpticsDev<double> out)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
-    Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
-    double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
-    double kext = kl + k_ray;
-    double rho = g.rho[c];
-    out.a_ext[c] = rho * kext;
-    out.a_abs[c] = rho * kl;
-    out.omega[c] = kext > 0.0 ? k_ray / kext : 0.0;
-    out.p_gas[c] = 1.0;
-    out.g_cld[c] = 0.0;
-}
-
-// ---------------------------------------------------------------- K3
-__device__ __forceinline__ double planck(double lam_cm, double T)
-{
-    double x = kH * kC / (lam_cm * kKB * T);
-    return 2.0 * kH * kC * kC / pow(lam_cm, 5.0) / expm1(x);
-}
-
-// One thread per column: walk down from the top accumulating the extinction
-// optical depth above each cell's top face.
-__global__ void __launch_bounds__(256) k_emission_L(GridDev g, OpticsDev<double> op, double lam_cm,
-                                                    double tau_vert, double* __restrict__ L)
-{
-    int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= g.nlon * g.nlat) return;
-    int i = col % g.nlon, j = col / g.nlon;
-    double tau = 0.0;
-    double dsl = g.lat_sin[j + 1] - g.lat_sin[j];
-    double dph = g.lon[i + 1] - g.lon[i];
-    for (int k = g.nlay - 1; k >= 0; --k) {
-        int c = (k * g.nlat + j) * g.nlon + i;
-        double vol = g.vol_r[k] * dsl * dph;
-        double Li = 4.0 * kPi * vol * op.a_abs[c] * planck(lam_cm, (double)g.T[c]);
-        L[c] = (tau > tau_vert) ? 0.0 : Li;
-        tau = tau + op.a_ext[c] * (g.r[k + 1] - g.r[k]);
-    }
-}
-
-// Fixed-order block reduction helpers (deterministic).
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh)
-{
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-// Per-block (sum L, count L > 0) -> partial[block][2].
-__global__ void __launch_bounds__(256) k_sum_L(const double* __restrict__ L, int n, double* __restrict__ part)
-{
-    __shared__ double sh[256];
-    int c = blockIdx.x * 256 + threadIdx.x;
-    double v = c < n ? L[c] : 0.0;
-    double cnt = (c < n && v > 0.0) ? 1.0 : 0.0;
-    double s = block_sum<256>(v, sh);
-    double m = block_sum<256>(cnt, sh);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s;
-        part[2 * blockIdx.x + 1] = m;
-    }
-}
+// (emission sources for the transport live in prep.hip)
 
 // Serial-per-thread then tree reduction of nblk rows of `width` doubles;
 // Neumaier-compensated so the result is nearly independent of blocking.
@@ -224,91 +147,6 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) out[col] = sh[0] + shc[0];
-}
-
-// q_i and the per-block sums of q for the scan; stats = (L_tot, N_emit).
-__global__ void __launch_bounds__(256) k_bias_pdf(const double* __restrict__ L, int n, const double* __restrict__ stats,
-                                                  double xi, double* __restrict__ q, double* __restrict__ wbirth)
-{
-    int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    double Ltot = stats[0], nemit = stats[1];
-    double Lc = L[c];
-    double qc = 0.0;
-    if (Lc > 0.0) qc = (1.0 - xi) * Lc / Ltot + xi / nemit;
-    q[c] = qc;
-    wbirth[c] = (Lc > 0.0) ? (Lc / Ltot) / qc : 0.0;
-}
-
-// Inclusive scan: per-block local scan (sequential within a thread's run of 8,
-// then across threads), block totals scanned by one block, then offsets added.
-constexpr int kScanPer = 8;
-constexpr int kScanBlock = 256 * kScanPer;
-
-__global__ void __launch_bounds__(256) k_scan_local(const double* __restrict__ in, int n, double* __restrict__ out,
-                                                    double* __restrict__ blocksum)
-{
-    __shared__ double sh[256];
-    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
-    double loc[kScanPer];
-    double run = 0.0;
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q) {
-        double x = (base + q < n) ? in[base + q] : 0.0;
-        run = run + x;
-        loc[q] = run;
-    }
-    sh[threadIdx.x] = run;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 256 thread totals
-    for (int off = 1; off < 256; off <<= 1) {
-        double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
-        __syncthreads();
-        sh[threadIdx.x] = sh[threadIdx.x] + v;
-        __syncthreads();
-    }
-    double pre = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q)
-        if (base + q < n) out[base + q] = pre + loc[q];
-    if (threadIdx.x == 255) blocksum[blockIdx.x] = sh[255];
-}
-
-__global__ void __launch_bounds__(256) k_scan_blocksums(double* __restrict__ bs, int nb)
-{
-    // single block: sequential chunks per thread then a thread-level scan
-    __shared__ double sh[256];
-    int per = (nb + 255) / 256;
-    int b0 = threadIdx.x * per;
-    double run = 0.0;
-    for (int q = 0; q < per; ++q)
-        if (b0 + q < nb) run = run + bs[b0 + q];
-    sh[threadIdx.x] = run;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
-        __syncthreads();
-        sh[threadIdx.x] = sh[threadIdx.x] + v;
-        __syncthreads();
-    }
-    double pre = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
-    // convert to exclusive offsets of each block
-    double acc = pre;
-    for (int q = 0; q < per; ++q) {
-        if (b0 + q < nb) {
-            double x = bs[b0 + q];
-            bs[b0 + q] = acc;
-            acc = acc + x;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_scan_add(double* __restrict__ out, int n, const double* __restrict__ off)
-{
-    int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    int b = c / kScanBlock;
-    if (b > 0) out[c] = off[b] + out[c];
 }
 
 // ---------------------------------------------------------------- K5 chords
@@ -485,42 +323,6 @@ void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl
     long long n = (long long)ncell * nslot;
     hipLaunchKernelGGL(k_hires_alpha_block, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nT,
                        nP, T_grid, lnP_grid, k_ray, shift, nlist, nslot, slot_stride, alpha);
-}
-
-void launch_hires_optics(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
-                         const double* T_grid, const double* lnP_grid, double k_ray, const double* shift, int n,
-                         OpticsDev<double> out, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_hires_optics, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nT, nP,
-                       T_grid, lnP_grid, k_ray, shift, n, out);
-}
-
-size_t emission_scratch_doubles(int ncell)
-{
-    // q (ncell) + L-sum partials (2 per 256) + scan block sums
-    return (size_t)ncell + 2 * (size_t)nblk(ncell, 256) + (size_t)nblk(ncell, kScanBlock) + 16;
-}
-
-void launch_emission_sources(const GridDev& g, const OpticsDev<double>& op, double lam_cm, double tau_vert,
-                             double xi, double* L, double* cdf, double* wbirth, double* scratch, double* stats_out,
-                             hipStream_t stream)
-{
-    int ncell = g.nlon * g.nlat * g.nlay;
-    int ncol = g.nlon * g.nlat;
-    double* q = scratch;
-    double* lpart = q + ncell;
-    int nb = nblk(ncell, 256);
-    double* bsum = lpart + 2 * nb;
-    hipLaunchKernelGGL(k_emission_L, dim3(nblk(ncol, 256)), dim3(256), 0, stream, g, op, lam_cm, tau_vert, L);
-    hipLaunchKernelGGL(k_sum_L, dim3(nb), dim3(256), 0, stream, L, ncell, lpart);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(2), dim3(256), 0, stream, lpart, nb, 2, stats_out);
-    hipLaunchKernelGGL(k_bias_pdf, dim3(nb), dim3(256), 0, stream, L, ncell, stats_out, xi, q, wbirth);
-    int ns = nblk(ncell, kScanBlock);
-    hipLaunchKernelGGL(k_scan_local, dim3(ns), dim3(256), 0, stream, q, ncell, cdf, bsum);
-    if (ns > 1) {
-        hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(256), 0, stream, bsum, ns);
-        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, cdf, ncell, bsum);
-    }
 }
 
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out, hipStream_t stream)

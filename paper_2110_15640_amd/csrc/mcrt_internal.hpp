@@ -86,6 +86,26 @@ struct BatchArgs {
     int ev_threshold;  // waiting lanes that trigger event handling
 };
 
+// One solve slot of a batched preparation.
+struct PrepSlot {
+    const double* lnk;  // ck: ln kappa slice [T][P] of (band, g)
+    double k_ray;       // Rayleigh opacity at the spectral point
+    int n;              // hi-res: table wavelength index
+    double lam_cm;      // emission: wavelength of B_lambda
+    double* opt;        // FP64 optics: alpha_ext, alpha_abs, omega, P_gas, g (ncell each)
+    float* optf;        // FP32 copies (mixed form) or null
+    double* cdf;        // emission: L, then q, then the inclusive CDF
+    double* wbirth;     // emission: (L_i/L_tot)/q_i
+    double* stats;      // emission: (L_tot, N_emit)
+};
+
+void launch_prep_optics(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, int hires, int nT,
+                        int nP, const double* T_grid, const double* lnP_grid, const double* lnk_tpl, int nlam,
+                        const double* shift, hipStream_t stream);
+void launch_prep_sources(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, double tau_vert,
+                         double xi, double* scratch, hipStream_t stream);
+size_t prep_scratch_doubles(int ncell, int nslots);
+
 void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks,
                                  hipStream_t stream);
 void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_solves,
@@ -93,7 +113,7 @@ void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_s
                         hipStream_t stream);
 int reduce_rows_chunks(unsigned long long max_n);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream);
-void launch_mixed_optics(const OpticsDev<double>& in, OpticsDev<float> out, int ncell, hipStream_t stream);
+void launch_births(const GridDev& g, const BatchArgs& a, hipStream_t stream);
 
 // Launchers (kernels.hip).  All run on `stream`; none synchronises.
 void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP,
@@ -105,13 +125,6 @@ void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl
                               int nP, const double* T_grid, const double* lnP_grid,
                               const double* k_ray, const double* shift, const int* nlist, int nslot,
                               int slot_stride, double* alpha, hipStream_t stream);
-void launch_hires_optics(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
-                         const double* T_grid, const double* lnP_grid, double k_ray,
-                         const double* shift, int n, OpticsDev<double> out, hipStream_t stream);
-void launch_emission_sources(const GridDev& g, const OpticsDev<double>& op, double lam_cm,
-                             double tau_vert, double xi, double* L, double* cdf, double* wbirth,
-                             double* scratch, double* stats_out, hipStream_t stream);
-size_t emission_scratch_doubles(int ncell);
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,
                             hipStream_t stream);
 void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,

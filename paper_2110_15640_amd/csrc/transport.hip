@@ -35,23 +35,50 @@ using namespace dev;
 enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 5 };
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
 
+// Per-lane state that the cell walk does not touch lives in LDS (one slot
+// per lane, structure of arrays) so the registers hold only the walking ray.
+constexpr int kTPB = 256;
+struct ColdLDS {
+    double sx[kTPB], sy[kTPB], sz[kTPB];      // event point
+    double sdx[kTPB], sdy[kTPB], sdz[kTPB];   // packet direction
+    double W0[kTPB], mu0[kTPB], w_rr[kTPB];
+    unsigned long long gid[kTPB];
+    int si[kTPB], sj[kTPB], sk[kTPB], sef[kTPB];
+    uint32_t e[kTPB];
+    int o[kTPB], birth[kTPB], solve[kTPB], nint[kTPB], ncapped[kTPB], nlost[kTPB];
+};
+
 struct Lane {
-    Ray r;                 // walking ray: position, cell, entry face
-    double dx, dy, dz;     // walking direction
-    double tau;            // flight: optical depth left; peel-off: accumulated
-    Ray s;                 // saved event point
-    double sdx, sdy, sdz;  // packet direction
-    double W, W0;
-    double mu0;            // slab backscatter observer (-sqrt(1-mu0^2), 0, mu0)
-    double w_abs, w_rr;
-    unsigned long long gid;  // global packet index
-    uint32_t e;              // event counter (flight e, then interaction e)
-    int ncw;                 // crossings of the current walk
-    int o;                   // observer of the current peel-off
-    int birth;               // 1 while peeling from the emission point
+    Walker w;      // the walking ray (flight or peel-off)
+    double tau;    // flight: optical depth left; peel-off: accumulated
+    double W, w_abs;
+    int ncw;       // crossings of the current walk
+    int ncross;
     int mode, ev;
-    int solve;
-    int nint, ncross, ncapped, nlost;
+    // cold state in LDS, accessed through these references
+    ColdLDS* C;
+    int t;
+    __device__ double& sx() { return C->sx[t]; }
+    __device__ double& sy() { return C->sy[t]; }
+    __device__ double& sz() { return C->sz[t]; }
+    __device__ double& sdx() { return C->sdx[t]; }
+    __device__ double& sdy() { return C->sdy[t]; }
+    __device__ double& sdz() { return C->sdz[t]; }
+    __device__ double& W0() { return C->W0[t]; }
+    __device__ double& mu0() { return C->mu0[t]; }
+    __device__ double& w_rr() { return C->w_rr[t]; }
+    __device__ unsigned long long& gid() { return C->gid[t]; }
+    __device__ int& si() { return C->si[t]; }
+    __device__ int& sj() { return C->sj[t]; }
+    __device__ int& sk() { return C->sk[t]; }
+    __device__ int& sef() { return C->sef[t]; }
+    __device__ uint32_t& e() { return C->e[t]; }
+    __device__ int& o() { return C->o[t]; }
+    __device__ int& birth() { return C->birth[t]; }
+    __device__ int& solve() { return C->solve[t]; }
+    __device__ int& nint() { return C->nint[t]; }
+    __device__ int& ncapped() { return C->ncapped[t]; }
+    __device__ int& nlost() { return C->nlost[t]; }
 };
 
 template <bool MIXED>
@@ -64,43 +91,43 @@ __device__ __forceinline__ double ld(const void* p, int c)
 // Write the packet's counters; `kind` says where its remaining weight went.
 __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int kind)
 {
-    double* row = A.rows + L.gid * (unsigned long long)A.row_w + A.n_out;
+    double* row = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
     row[K_ESC] = kind == K_ESC ? L.W : 0.0;
     row[K_SURF] = kind == K_SURF ? L.W : 0.0;
     row[K_ABS] = L.w_abs;
-    row[K_RR] = L.w_rr;
+    row[K_RR] = L.w_rr();
     row[K_CAP] = kind == K_CAP ? L.W : 0.0;
     row[K_LOST] = kind == K_LOST ? L.W : 0.0;
-    row[K_NINT] = (double)L.nint;
+    row[K_NINT] = (double)L.nint();
     row[K_NCROSS] = (double)L.ncross;
-    row[K_NCAPPED] = (double)L.ncapped;
-    row[K_NLOST] = (double)L.nlost;
-    row[K_W0] = L.W0;
+    row[K_NCAPPED] = (double)L.ncapped();
+    row[K_NLOST] = (double)L.nlost();
+    row[K_W0] = L.W0();
     L.mode = M_DEAD;
 }
 
-__device__ __forceinline__ void observer(const Lane& L, const BatchArgs& A, const double* sobs, double& ox, double& oy,
+__device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const double* sobs, double& ox, double& oy,
                                          double& oz)
 {
     if (A.n_obs == 0) {
-        ox = -sqrt(fmax(1.0 - L.mu0 * L.mu0, 0.0));
+        ox = -sqrt(fmax(1.0 - L.mu0() * L.mu0(), 0.0));
         oy = 0.0;
-        oz = L.mu0;
+        oz = L.mu0();
     } else {
-        ox = sobs[3 * L.o];
-        oy = sobs[3 * L.o + 1];
-        oz = sobs[3 * L.o + 2];
+        ox = sobs[3 * L.o()];
+        oy = sobs[3 * L.o() + 1];
+        oz = sobs[3 * L.o() + 2];
     }
 }
 
 __device__ __forceinline__ void start_peel(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs)
 {
-    L.r = L.s;
-    L.r.ef = -1;
+    double ox, oy, oz;
+    observer(L, A, sobs, ox, oy, oz);
+    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), ox, oy, oz, L.si(), L.sj(), L.sk(), F_NONE);
     L.tau = 0.0;
     L.ncw = 0;
-    observer(L, A, sobs, L.dx, L.dy, L.dz);
-    if (g.geom == 1 && !(L.dz > 0.0)) {  // a slab ray that never reaches the top
+    if (g.geom == 1 && !(oz > 0.0)) {  // a slab ray that never reaches the top
         L.tau = INFINITY;
         L.mode = M_EVENT;
         L.ev = E_PEEL_DONE;
@@ -109,12 +136,11 @@ __device__ __forceinline__ void start_peel(Lane& L, const GridDev& g, const Batc
     L.mode = M_PEEL;
 }
 
-__device__ __forceinline__ void start_flight(Lane& L, const BatchArgs& A, const SolveDev& S)
+__device__ __forceinline__ void start_flight(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
-    U2 u = draw(A.seed, S.tag, L.gid - S.begin, L.e, 0);
+    U2 u = draw(A.seed, S.tag, L.gid() - S.begin, L.e(), 0);
     L.tau = -log(u.a);
-    L.r = L.s;
-    L.dx = L.sdx; L.dy = L.sdy; L.dz = L.sdz;
+    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), L.sdx(), L.sdy(), L.sdz(), L.si(), L.sj(), L.sk(), L.sef());
     L.ncw = 0;
     L.mode = M_FLIGHT;
 }
@@ -123,10 +149,11 @@ template <bool MIXED>
 __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
                                           const BatchArgs& A)
 {
-    double s;
-    int f = exit_distance(g, L.r, L.dx, L.dy, L.dz, s);
+    double tf;
+    const int f = wk_next(g, L.w, tf);
+    const double s = tf - L.w.t;
+    const int c = wk_cell(g, L.w);
     if (L.mode == M_FLIGHT) {
-        int c = cell_of(g, L.r);
         const bool cont = A.absorption == 1;
         double ae = ld<MIXED>(aext, c);
         double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
@@ -144,8 +171,12 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
                 L.w_abs = L.w_abs + (L.W - wn);
                 L.W = wn;
             }
-            advance(g, L.r, L.dx, L.dy, L.dz, ds);
-            L.r.ef = F_NONE;
+            const double ti = L.w.t + ds;
+            L.sx() = L.w.px + ti * L.w.dx;
+            L.sy() = L.w.py + ti * L.w.dy;
+            L.sz() = L.w.pz + ti * L.w.dz;
+            L.si() = L.w.i; L.sj() = L.w.j; L.sk() = L.w.k;
+            L.sef() = F_NONE;
             L.ncross += L.ncw;
             L.mode = M_EVENT;
             L.ev = E_INTERACT;
@@ -157,11 +188,9 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
             L.w_abs = L.w_abs + (L.W - wn);
             L.W = wn;
         }
-        advance(g, L.r, L.dx, L.dy, L.dz, s);
-        cross(g, L.r, f);
+        const bool inside = wk_cross(g, L.w, f, tf);
         L.ncw++;
-        if (L.r.k >= g.nlay) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_ESCAPE; }
-        else if (L.r.k < 0) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_SURFACE; }
+        if (!inside) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = L.w.k >= g.nlay ? E_ESCAPE : E_SURFACE; }
         else if (L.ncw >= g.max_cross) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_LOST; }
     } else {
         if (f == F_NONE) {
@@ -171,15 +200,12 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
             L.ev = E_PEEL_DONE;
             return;
         }
-        int c = cell_of(g, L.r);
         L.tau = L.tau + ld<MIXED>(aext, c) * s;
-        advance(g, L.r, L.dx, L.dy, L.dz, s);
-        cross(g, L.r, f);
+        const bool inside = wk_cross(g, L.w, f, tf);
         L.ncw++;
         bool done = true;
         if (L.tau > A.tau_peel_max) L.tau = INFINITY;
-        else if (L.r.k >= g.nlay) {}
-        else if (L.r.k < 0) L.tau = INFINITY;
+        else if (!inside) { if (L.w.k < 0) L.tau = INFINITY; }
         else if (L.ncw >= g.max_cross) L.tau = INFINITY;
         else done = false;
         if (done) {
@@ -198,15 +224,15 @@ enum { A_NONE = 0, A_PEEL = 1, A_FLIGHT = 2, A_SCATTER = 3, A_FINISH = 4 };
 template <bool MIXED>
 __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
-    const int c = cell_of(g, L.s);
+    const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
     const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
-    const unsigned long long q = L.gid - S.begin;
+    const unsigned long long q = L.gid() - S.begin;
     if (A.absorption != 1) {
         L.w_abs += L.W * (1.0 - om);
         L.W = L.W * om;
     }
-    const double usel = draw(A.seed, S.tag, q, L.e, 0).b;  // scatterer choice of this event
-    U2 u1 = draw(A.seed, S.tag, q, L.e, 1);
+    const double usel = draw(A.seed, S.tag, q, L.e(), 0).b;  // scatterer choice of this event
+    U2 u1 = draw(A.seed, S.tag, q, L.e(), 1);
     if (MIXED) {
         float z = fminf((float)u1.a, 0.99999994f);
         float mu;
@@ -225,7 +251,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         float st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
         float sp, cp;
         __sincosf((float)(2.0 * kPi) * (float)u1.b, &sp, &cp);
-        float dx = (float)L.sdx, dy = (float)L.sdy, dz = (float)L.sdz;
+        float dx = (float)L.sdx(), dy = (float)L.sdy(), dz = (float)L.sdz();
         float nx, ny, nz;
         if (fabsf(dz) < 0.99999f) {
             float t = sqrtf(1.0f - dz * dz);
@@ -241,32 +267,32 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         }
         double ddx = nx, ddy = ny, ddz = nz;
         double n = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-        L.sdx = ddx / n;
-        L.sdy = ddy / n;
-        L.sdz = ddz / n;
+        L.sdx() = ddx / n;
+        L.sdy() = ddy / n;
+        L.sdz() = ddz / n;
     } else {
         double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, gc);
-        rotate_dir(L.sdx, L.sdy, L.sdz, mu, 2.0 * kPi * u1.b);
+        rotate_dir(L.sdx(), L.sdy(), L.sdz(), mu, 2.0 * kPi * u1.b);
     }
-    if (L.W < A.rr_threshold * L.W0) {
-        U2 u2 = draw(A.seed, S.tag, q, L.e, 2);
+    if (L.W < A.rr_threshold * L.W0()) {
+        U2 u2 = draw(A.seed, S.tag, q, L.e(), 2);
         if (u2.a < A.rr_survive) {
             double wn = L.W / A.rr_survive;
-            L.w_rr -= (wn - L.W);
+            L.w_rr() -= (wn - L.W);
             L.W = wn;
         } else {
-            L.w_rr += L.W;
+            L.w_rr() += L.W;
             L.W = 0.0;
             L.ev = -1;
             return A_FINISH;
         }
     }
-    if ((long long)L.e >= A.max_events) {
-        L.ncapped += 1;
+    if ((long long)L.e() >= A.max_events) {
+        L.ncapped() += 1;
         L.ev = K_CAP;
         return A_FINISH;
     }
-    L.e += 1;
+    L.e() += 1;
     return A_FLIGHT;
 }
 
@@ -275,18 +301,18 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
 template <bool MIXED>
 __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const BatchArgs& A)
 {
-    const SolveDev& S = A.solves[L.solve];
+    const SolveDev& S = A.solves[L.solve()];
     if (L.ev == E_PEEL_DONE) {
         double f;
-        if (L.birth) {
+        if (L.birth()) {
             f = L.W * exp(-L.tau) / (4.0 * kPi);
         } else {
             // normalised mixture of the Rayleigh and cloud phase functions
             // toward the observer, weighted by the gas scattering probability
-            const int c = cell_of(g, L.s);
+            const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
             const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
             if (MIXED) {
-                float mu = (float)(L.sdx * L.dx + L.sdy * L.dy + L.sdz * L.dz);
+                float mu = (float)(L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz);
                 float pgf = (float)pg, gcf = (float)gc;
                 float pr = 0.75f * (1.0f + mu * mu);
                 float ph = 1.0f;
@@ -299,108 +325,109 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 float w = A.absorption == 1 ? (float)L.W : (float)(L.W * om);
                 f = (double)(w * theta * att);
             } else {
-                double mu = L.sdx * L.dx + L.sdy * L.dy + L.sdz * L.dz;
+                double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
                 double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * p_hg(mu, gc)) / (4.0 * kPi);
                 double att = exp(-L.tau);
                 f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
             }
         }
-        double* row = A.rows + L.gid * (unsigned long long)A.row_w;
-        row[L.o] = row[L.o] + f;
-        L.o += 1;
-        if (L.o < A.n_out) return A_PEEL;
-        if (L.birth) {
-            L.birth = 0;
+        double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
+        row[L.o()] = row[L.o()] + f;
+        L.o() += 1;
+        if (L.o() < A.n_out) return A_PEEL;
+        if (L.birth()) {
+            L.birth() = 0;
             if (!A.scattering) {
                 L.ev = K_ESC;
                 return A_FINISH;
             }
-            L.e = 1;
+            L.e() = 1;
             return A_FLIGHT;
         }
         return A_SCATTER;
     }
     if (L.ev == E_INTERACT) {
-        L.nint += 1;
-        L.s = L.r;
-        L.o = 0;
-        L.birth = 0;
+        L.nint() += 1;
+        L.o() = 0;
+        L.birth() = 0;
         return A_PEEL;
     }
-    if (L.ev == E_LOST) L.nlost += 1;
+    if (L.ev == E_LOST) L.nlost() += 1;
     L.ev = L.ev == E_ESCAPE ? K_ESC : (L.ev == E_SURFACE ? K_SURF : K_LOST);
     return A_FINISH;
 }
 
-// New packet L.gid: find its solve, zero its row, place it and return the
-// first action (a flight for albedo, the emission-point peel-off otherwise).
-template <bool MIXED>
-__device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
+// Index of the solve that owns global packet gid (last solve with begin <= gid).
+__device__ __forceinline__ int solve_of(const BatchArgs& A, unsigned long long gid)
 {
-    int lo = 0, hi = A.n_solves - 1;  // last solve with begin <= gid
+    int lo = 0, hi = A.n_solves - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (A.solves[mid].begin <= L.gid) lo = mid;
+        if (A.solves[mid].begin <= gid) lo = mid;
         else hi = mid - 1;
     }
-    L.solve = lo;
-    const SolveDev& S = A.solves[lo];
-    const unsigned long long q = L.gid - S.begin;
-    double* row = A.rows + L.gid * (unsigned long long)A.row_w;
+    return lo;
+}
+
+// Birth record of a packet, kept in the counter columns of its row until the
+// packet dies: position, direction, weight, then cell * 8 + (entry face + 1)
+// (-1: nothing emits).
+enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL };
+
+// K4a: births of every packet of a batch (albedo: uniform on the top disk or
+// the slab's incidence; emission: cell from the biased CDF, uniform position in
+// its volume, isotropic direction, weight (L_i/L_tot)/q_i), one thread each.
+__global__ void __launch_bounds__(256) k_births(GridDev g, BatchArgs A)
+{
+    const unsigned long long gid = (unsigned long long)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= A.total) return;
+    const SolveDev& S = A.solves[solve_of(A, gid)];
+    const unsigned long long q = gid - S.begin;
+    double* row = A.rows + gid * (unsigned long long)A.row_w;
     for (int o = 0; o < A.n_out; ++o) row[o] = 0.0;
-    L.w_abs = L.w_rr = 0.0;
-    L.nint = L.ncross = L.ncapped = L.nlost = 0;
-    L.birth = 0;
-    L.o = 0;
-    L.mu0 = 0.0;
-    L.e = 1;
+    double* b = row + A.n_out;
     const uint32_t tag = S.tag;
     if (S.mode == 0) {
         U2 u = draw(A.seed, tag, q, 0, 0);
         if (g.geom == 1) {
             double mu0 = A.mu0 > 0.0 ? A.mu0 : sqrt(1.0 - u.a);
-            L.sdx = sqrt(fmax(1.0 - mu0 * mu0, 0.0));
-            L.sdy = 0.0;
-            L.sdz = -mu0;
-            L.mu0 = mu0;
-            L.s.x = 0.0; L.s.y = 0.0; L.s.z = g.r[g.nlay];
-            L.s.i = 0; L.s.j = 0; L.s.k = g.nlay - 1; L.s.ef = F_OUT;
+            b[B_X] = 0.0; b[B_Y] = 0.0; b[B_Z] = g.r[g.nlay];
+            b[B_DX] = sqrt(fmax(1.0 - mu0 * mu0, 0.0)); b[B_DY] = 0.0; b[B_DZ] = -mu0;
+            b[B_CELL] = (double)((g.nlay - 1) * 8 + (F_OUT + 1));
         } else {
             double rho = A.r_toa * sqrt(u.a);
             double a = 2.0 * kPi * u.b;
-            double sa, ca;
-            sincos(a, &sa, &ca);
-            double y = rho * ca, z = rho * sa;
+            double y = rho * cos(a), z = rho * sin(a);
             double x = sqrt(fmax(A.r_toa * A.r_toa - y * y - z * z, 0.0));
-            L.s.x = x; L.s.y = y; L.s.z = z;
-            L.sdx = -1.0; L.sdy = 0.0; L.sdz = 0.0;
-            L.s.k = g.nlay - 1;
-            locate_column(g, L.s);
-            L.s.ef = F_OUT;
+            Ray rs;
+            rs.x = x; rs.y = y; rs.z = z;
+            locate_column(g, rs);
+            b[B_X] = x; b[B_Y] = y; b[B_Z] = z;
+            b[B_DX] = -1.0; b[B_DY] = 0.0; b[B_DZ] = 0.0;
+            int c = ((g.nlay - 1) * g.nlat + rs.j) * g.nlon + rs.i;
+            b[B_CELL] = (double)c * 8.0 + (double)(F_OUT + 1);
         }
-        L.W = 1.0;
-        L.W0 = 1.0;
-        return A_FLIGHT;
+        b[B_W] = 1.0;
+        return;
     }
     const int ncell = g.nlon * g.nlat * g.nlay;
     const double tot = S.cdf[ncell - 1];
     if (!(tot > 0.0)) {  // nothing emits
-        L.W = 0.0;
-        L.W0 = 0.0;
-        L.ev = -1;
-        return A_FINISH;
+        b[B_W] = 0.0;
+        b[B_CELL] = -1.0;
+        return;
     }
     U2 u0 = draw(A.seed, tag, q, 0, 0);
     U2 u1 = draw(A.seed, tag, q, 0, 1);
     U2 u2 = draw(A.seed, tag, q, 0, 2);
     double target = u0.a * tot;
-    int lo2 = 0, hi2 = ncell - 1;
-    while (lo2 < hi2) {
-        int mid = (lo2 + hi2) >> 1;
-        if (S.cdf[mid] > target) hi2 = mid;
-        else lo2 = mid + 1;
+    int lo = 0, hi = ncell - 1;  // smallest c with cdf[c] > target
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (S.cdf[mid] > target) hi = mid;
+        else lo = mid + 1;
     }
-    int c = lo2;
+    int c = lo;
     int i = c % g.nlon, j = (c / g.nlon) % g.nlat, k = c / (g.nlon * g.nlat);
     double rk = g.r[k], rk1 = g.r[k + 1];
     double rk3 = rk * rk * rk;
@@ -410,30 +437,61 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
     double sl = sl0 + u1.a * (sl1 - sl0);
     double cl = sqrt(fmax(1.0 - sl * sl, 0.0));
     double lon = g.lon[i] + u1.b * (g.lon[i + 1] - g.lon[i]);
-    double slo, clo;
-    sincos(lon, &slo, &clo);
-    L.s.x = r * cl * clo;
-    L.s.y = r * cl * slo;
-    L.s.z = r * sl;
-    L.s.i = i; L.s.j = j; L.s.k = k; L.s.ef = F_NONE;
+    b[B_X] = r * cl * cos(lon);
+    b[B_Y] = r * cl * sin(lon);
+    b[B_Z] = r * sl;
     double mu = 2.0 * u2.a - 1.0;
     double sp = sqrt(fmax(1.0 - mu * mu, 0.0));
     double psi = 2.0 * kPi * u2.b;
-    double sps, cps;
-    sincos(psi, &sps, &cps);
-    L.sdx = sp * cps;
-    L.sdy = sp * sps;
-    L.sdz = mu;
-    L.W = S.wbirth[c];
-    L.W0 = L.W;
-    L.birth = 1;
+    b[B_DX] = sp * cos(psi);
+    b[B_DY] = sp * sin(psi);
+    b[B_DZ] = mu;
+    b[B_W] = S.wbirth[c];
+    b[B_CELL] = (double)c * 8.0 + (double)(F_NONE + 1);
+}
+
+// New packet L.gid: load its birth record and return the first action (a
+// flight for albedo, the emission-point peel-off, or finish if none emits).
+__device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
+{
+    L.solve() = solve_of(A, L.gid());
+    const SolveDev& S = A.solves[L.solve()];
+    const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    L.w_abs = 0.0;
+    L.w_rr() = 0.0;
+    L.ncross = 0;
+    L.nint() = 0;
+    L.ncapped() = 0;
+    L.nlost() = 0;
+    L.birth() = 0;
+    L.o() = 0;
+    L.e() = 1;
+    const double cw = b[B_CELL];
+    L.W = b[B_W];
+    L.W0() = L.W;
+    if (cw < 0.0) {
+        L.ev = -1;
+        return A_FINISH;
+    }
+    const long long cc = (long long)cw;
+    const int c = (int)(cc >> 3);
+    L.sef() = (int)(cc & 7) - 1;
+    L.si() = c % g.nlon;
+    L.sj() = (c / g.nlon) % g.nlat;
+    L.sk() = c / (g.nlon * g.nlat);
+    L.sx() = b[B_X]; L.sy() = b[B_Y]; L.sz() = b[B_Z];
+    L.sdx() = b[B_DX]; L.sdy() = b[B_DY]; L.sdz() = b[B_DZ];
+    L.mu0() = -L.sdz();  // slab incidence cosine (its backscatter observer)
+    if (S.mode == 0) return A_FLIGHT;
+    L.birth() = 1;
     return A_PEEL;
 }
 
 template <bool MIXED>
-__global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchArgs A)
+__global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g, BatchArgs A)
 {
     __shared__ double sobs[3 * kMaxObs];
+    __shared__ ColdLDS cold;
     if (threadIdx.x < 3 * kMaxObs) sobs[threadIdx.x] = A.obs[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -441,8 +499,10 @@ __global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchAr
     unsigned long long res_next = 0, res_end = 0;
     bool exhausted = false;
     Lane L;
+    L.C = &cold;
+    L.t = threadIdx.x;
     L.mode = M_DEAD;
-    L.solve = 0;
+    L.solve() = 0;
     const void* aext = nullptr;
     const void* aabs = nullptr;
     for (;;) {
@@ -452,7 +512,7 @@ __global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchAr
         if (__popcll(evm) < A.ev_threshold && walking != 0) continue;
         int act = A_NONE;
         if (L.mode == M_EVENT) act = handle_event<MIXED>(L, g, A);
-        if (act == A_SCATTER) act = scatter<MIXED>(L, g, A, A.solves[L.solve]);
+        if (act == A_SCATTER) act = scatter<MIXED>(L, g, A, A.solves[L.solve()]);
         for (int pass = 0; pass < 2; ++pass) {
             if (act == A_FINISH) {
                 finish_packet(L, A, L.ev);
@@ -479,7 +539,7 @@ __global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchAr
                 int take = (unsigned long long)cnt < avail ? cnt : (int)avail;
                 int rank = __popcll(dead & below);
                 if (L.mode == M_DEAD && rank < take) {
-                    L.gid = res_next + (unsigned long long)rank;
+                    L.gid() = res_next + (unsigned long long)rank;
                     L.mode = M_BIRTH;
                 }
                 res_next += (unsigned long long)take;
@@ -487,13 +547,13 @@ __global__ void __launch_bounds__(256) k_transport_persistent(GridDev g, BatchAr
             }
             if (L.mode == M_DEAD && exhausted) L.mode = M_IDLE;
             if (L.mode == M_BIRTH) {
-                act = birth<MIXED>(L, g, A);
-                const SolveDev& S = A.solves[L.solve];
+                act = birth(L, g, A);
+                const SolveDev& S = A.solves[L.solve()];
                 aext = S.a_ext;
                 aabs = S.a_abs;
             }
         }
-        if (act == A_FLIGHT) start_flight(L, A, A.solves[L.solve]);
+        if (act == A_FLIGHT) start_flight(L, g, A, A.solves[L.solve()]);
         else if (act == A_PEEL) start_peel(L, g, A, sobs);
         if (__ballot(L.mode != M_IDLE) == 0) break;
     }
@@ -587,13 +647,12 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-__global__ void __launch_bounds__(256) k_to_float(const double* __restrict__ in, float* __restrict__ out, int n)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) out[c] = (float)in[c];
-}
-
 }  // namespace
+
+void launch_births(const GridDev& g, const BatchArgs& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_births, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, stream, g, a);
+}
 
 void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks, hipStream_t stream)
 {
@@ -616,16 +675,6 @@ void launch_reduce_rows(const BatchArgs& a, const SolveDev* /*solves_host*/, int
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, stream, p, v);
-}
-
-void launch_mixed_optics(const OpticsDev<double>& in, OpticsDev<float> out, int ncell, hipStream_t stream)
-{
-    int b = (ncell + 255) / 256;
-    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.a_ext, out.a_ext, ncell);
-    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.a_abs, out.a_abs, ncell);
-    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.omega, out.omega, ncell);
-    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.p_gas, out.p_gas, ncell);
-    hipLaunchKernelGGL(k_to_float, dim3(b), dim3(256), 0, stream, in.g_cld, out.g_cld, ncell);
 }
 
 }  // namespace mcrt

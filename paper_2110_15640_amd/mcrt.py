@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
     L.mcrt_default_params.restype = None
     for nm in ("mcrt_solve_albedo", "mcrt_solve_emission", "mcrt_solve_transmission"):
         getattr(L, nm).argtypes = [_vp, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
+    L.mcrt_autotune.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_dbl)]
     L.mcrt_serve_config.argtypes = [_vp, _i32]
     L.mcrt_submit.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_u64)]
     L.mcrt_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i32)]
@@ -264,6 +265,16 @@ class Context:
         out["kernel_launches"] = r.kernel_launches
         out["queued_ms"] = r.queued_ms
         out["latency_ms"] = r.latency_ms
+
+    def autotune(self, mode: str, gid: int, oid: int, **kw) -> dict:
+        """Pick the persistent launch shape for this request; returns the
+        tune_* settings (pass them to the solve) and the trial rate."""
+        p, keep = self._params(dict(kw))
+        rate = _dbl()
+        _check(load().mcrt_autotune(self._h, MODES[mode], gid, oid, ctypes.byref(p), ctypes.byref(rate)))
+        del keep
+        return dict(tune_ev_threshold=p.tune_ev_threshold, tune_blocks_per_cu=p.tune_blocks_per_cu,
+                    tune_wave_batch=p.tune_wave_batch, trial_packets_per_s=rate.value)
 
     # ---------------------------------------------------------- serving
     def serve_config(self, n_workers: int):
