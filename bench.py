@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-packets", type=int, default=3000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="duration of the Poisson serving leg (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="run one 1 GiB device copy first (reference kernel for HBM counter scaling)")
     return ap.parse_args()
@@ -182,6 +184,13 @@ def main():
     }
     if a.transmission:
         out["transmission"] = transmission_leg(M, I)
+    if a.serve_seconds > 0:
+        print(f"[bench] serving leg: Poisson 20 req/s for {a.serve_seconds:.0f} s", flush=True)
+        from paper_2110_15640_amd import serve as SV
+        with M.Context(0) as sctx:
+            rep = SV.run_poisson(sctx, rate=20.0, duration=a.serve_seconds, load=0.7,
+                                 log=lambda m: print(m, flush=True))
+        out["serving"] = rep.summary()
     if a.cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, table, phases, a.cpu_packets)

@@ -244,6 +244,27 @@ int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
 int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
                             const mcrt_solve_params* params, mcrt_result* result);
 
+/* Batched solves on grids of uneven size: n_items albedo / emission requests,
+ * each with its own (spherical) grid, correlated-k table, spectral points and
+ * packet count, share the common params (observers, scattering, absorption,
+ * roulette, precision, tuning; params' spec_idx, n_packets and packet_dump
+ * are ignored) and must have the same number of observers.  All their
+ * (spectral point, g) solves run in as few multi-grid persistent launches as
+ * the HBM budget allows.  results[q] is filled as for the single-request solve
+ * of item q (elapsed_ms / kernel_ms are those of the whole batch); each result
+ * equals the one item q gets alone.  Errors as for the blocking solves. */
+typedef struct {
+    int32_t mode;
+    int32_t grid_id;
+    int32_t opac_id;
+    int32_t n_spec;
+    const int32_t* spec_idx;
+    uint64_t n_packets;
+} mcrt_batch_item;
+
+int mcrt_solve_batch(mcrt_ctx* ctx, int32_t n_items, const mcrt_batch_item* items,
+                     const mcrt_solve_params* params, mcrt_result* results);
+
 /* Autotuner for the persistent transport launch shape: runs short trial
  * solves of this request (up to 3 of its spectral points, at most 2e5
  * packets each) over event thresholds {8, 16, 32}, blocks per compute unit

@@ -604,7 +604,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.tau_peel_max = p->tau_peel_max;
     A.mu0 = p->mu0;
     A.r_toa = g->r_toa;
-    for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[q] = pl.obs[q];
+    for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[0][q] = A.obs[1][q] = pl.obs[q];
     A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
@@ -646,6 +646,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             S.n = N;
             S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
             S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
+            S.grid = 0;
             S.cdf = P.cdf;
             S.wbirth = P.wbirth;
             if (mixed) {
@@ -669,9 +670,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         A.n_solves = nb;
         A.total = (unsigned long long)nb * N;
         launch_fill_u64(A.counter, 0ULL, st);
-        launch_births(g->dev, A, st);
+        launch_births(g->dev, A, false, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
-        launch_transport_persistent(g->dev, A, mixed, pblocks, st);
+        launch_transport_persistent(g->dev, A, mixed, false, pblocks, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
         double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
         launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
@@ -807,6 +808,264 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     // sums rows are [row][2] already (n_out = 1)
     std::vector<double> sumrows(hs);
     fill_results(pl, val, se, gw, sumrows, 2, cnt, ltot, res);
+    return MCRT_OK;
+}
+
+// ------------------------------------------------------------------ batch
+// Many albedo / emission requests on grids of uneven size: every item's
+// (spectral point, g) solves are flattened into one list and packed, as far
+// as the budget allows, into multi-grid persistent launches; preparation runs
+// per item, the transport per launch, the tally reduction per solve.
+int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, const mcrt_batch_item* items,
+                const mcrt_solve_params* common, mcrt_result* results)
+{
+    if (n_items < 1 || !items || !common || !results) return fail(MCRT_EINVAL, "batch needs items, params, results");
+    struct Item {
+        Lease ls;
+        SolvePlan pl;
+        mcrt_solve_params p;
+        int mode;
+        int gslot;  // index into the batch grid table
+        int first;  // first flattened solve
+    };
+    std::vector<std::unique_ptr<Item>> it(n_items);
+    std::vector<GridRes*> grids;
+    int rc;
+    int no = -1;
+    for (int q = 0; q < n_items; ++q) {
+        it[q].reset(new Item());
+        Item& I = *it[q];
+        const mcrt_batch_item& b = items[q];
+        if (b.mode != MCRT_MODE_ALBEDO && b.mode != MCRT_MODE_EMISSION)
+            return fail(MCRT_EINVAL, "batch item %d: mode must be albedo or emission", q);
+        if ((rc = lease(ctx, b.grid_id, b.opac_id, I.ls))) return rc;
+        if (I.ls.g->dev.geom != 0) return fail(MCRT_EINVAL, "batch item %d: batched solves take spherical grids", q);
+        if (I.ls.op->kind != MCRT_OPAC_CK) return fail(MCRT_EINVAL, "batch item %d: batched solves take ck tables", q);
+        I.p = *common;
+        I.p.spec_idx = b.spec_idx;
+        I.p.n_spec = b.n_spec;
+        I.p.n_packets = b.n_packets;
+        I.p.packet_dump = nullptr;
+        I.mode = b.mode;
+        if ((rc = plan_common(def_stream, I.ls.g, I.ls.op, &I.p, I.mode, I.pl))) return rc;
+        if (no >= 0 && I.pl.n_out != no) return fail(MCRT_EINVAL, "batch items must have the same number of observers");
+        no = I.pl.n_out;
+        auto f = std::find(grids.begin(), grids.end(), I.ls.g);
+        I.gslot = (int)(f - grids.begin());
+        if (f == grids.end()) grids.push_back(I.ls.g);
+    }
+    if (common->max_batch < 0 || common->tune_ev_threshold < 0 || common->tune_ev_threshold > 64 ||
+        common->tune_blocks_per_cu < 0 || common->tune_blocks_per_cu > 16 || common->tune_wave_batch < 0)
+        return fail(MCRT_EINVAL, "bad batching / tuning parameters");
+    hipStream_t st = common->stream ? (hipStream_t)common->stream : def_stream;
+    const bool mixed = common->precision == MCRT_MIXED;
+    const int pw = 2 * no + kNCounters, row_w = pw + 2, prow = no + kNCounters;
+    // flattened solves
+    struct Flat {
+        int item, spec, g;
+        uint64_t bytes;
+    };
+    std::vector<Flat> fl;
+    for (int q = 0; q < n_items; ++q) {
+        Item& I = *it[q];
+        I.first = (int)fl.size();
+        const uint64_t nc = (uint64_t)I.ls.g->ncell;
+        const uint64_t by = nc * 5 * (8 + (mixed ? 4 : 0)) + (I.mode == MCRT_MODE_EMISSION ? nc * 16 : 0) +
+                            (uint64_t)I.p.n_packets * prow * 8 + 4 * 256;  // + alignment
+        for (size_t s = 0; s < I.pl.specs.size(); ++s)
+            for (int g = 0; g < I.pl.ng; ++g) fl.push_back(Flat{q, (int)s, g, by});
+    }
+    const int nsolve = (int)fl.size();
+    uint64_t room;
+    {
+        std::lock_guard<std::mutex> mk(ctx->mem_mu);
+        room = ctx->budget > ctx->in_use + ctx->reserved ? ctx->budget - ctx->in_use - ctx->reserved : 0;
+    }
+    const uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
+    // launches: consecutive solves while the footprint fits (and <= max_batch)
+    std::vector<std::pair<int, int>> launches;
+    for (int s0 = 0; s0 < nsolve;) {
+        uint64_t acc = 0;
+        int s1 = s0;
+        while (s1 < nsolve && (s1 == s0 || acc + fl[s1].bytes <= cap) &&
+               (common->max_batch <= 0 || s1 - s0 < common->max_batch)) {
+            acc += fl[s1].bytes;
+            ++s1;
+        }
+        launches.push_back({s0, s1});
+        s0 = s1;
+    }
+    uint64_t max_bytes = 0, max_n = 1, max_slots = 1, max_prep = 16;
+    int max_ncell = 1;
+    for (auto& L : launches) {
+        uint64_t acc = 0, mx = 1;
+        for (int s = L.first; s < L.second; ++s) {
+            acc += fl[s].bytes;
+            mx = std::max<uint64_t>(mx, it[fl[s].item]->p.n_packets);
+        }
+        max_bytes = std::max(max_bytes, acc);
+        max_n = std::max(max_n, mx);
+        max_slots = std::max<uint64_t>(max_slots, (uint64_t)(L.second - L.first));
+    }
+    for (GridRes* g : grids) max_ncell = std::max(max_ncell, g->ncell);
+    for (auto& L : launches) max_prep = std::max<uint64_t>(max_prep, prep_scratch_doubles(max_ncell, L.second - L.first));
+    const int chunks = reduce_rows_chunks(max_n);
+    void *v_arena, *v_sums, *v_part, *v_solves, *v_slots, *v_ctr, *v_grids, *v_ps;
+    if ((rc = scratch(ctx, sl, st, "batch_arena", max_bytes, &v_arena))) return rc;
+    if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * max_slots * chunks * pw, &v_part))) return rc;
+    if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * max_slots, &v_solves))) return rc;
+    if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * max_slots, &v_slots))) return rc;
+    if ((rc = scratch(ctx, sl, st, "dispenser", 64, &v_ctr))) return rc;
+    if ((rc = scratch(ctx, sl, st, "grid_table", sizeof(GridDev) * grids.size(), &v_grids))) return rc;
+    if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * max_prep, &v_ps))) return rc;
+    double* sums = (double*)v_sums;
+    std::vector<GridDev> hgrids;
+    for (GridRes* g : grids) hgrids.push_back(g->dev);
+
+    BatchArgs A{};
+    A.counter = (unsigned long long*)v_ctr;
+    A.row_w = prow;
+    A.grids = (const GridDev*)v_grids;
+    A.seed = common->seed;
+    A.scattering = common->scattering ? 1 : 0;
+    A.absorption = common->absorption;
+    A.n_obs = no;
+    A.n_out = no;
+    A.max_events = common->max_events;
+    A.rr_threshold = common->rr_threshold;
+    A.rr_survive = common->rr_survive;
+    A.tau_peel_max = common->tau_peel_max;
+    A.mu0 = common->mu0;
+    A.r_toa = 0.0;  // per grid in multi-grid launches
+    for (int q = 0; q < n_items; ++q) {
+        const int m = it[q]->mode == MCRT_MODE_EMISSION ? 1 : 0;
+        for (int k = 0; k < 3 * no; ++k) A.obs[m][k] = it[q]->pl.obs[k];
+    }
+    A.batch = common->tune_wave_batch > 0 ? common->tune_wave_batch : 64;
+    A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
+    const int pblocks = ctx->n_cu * (common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4);
+    const bool prof = common->profile != 0;
+    if (prof && (rc = prof_events(ctx, sl, launches.size()))) return rc;
+    std::vector<std::vector<SolveDev>> hsv(launches.size());
+    std::vector<std::vector<PrepSlot>> hps(launches.size());
+    HIPTRY(hipEventRecord(sl.ev0, st));
+    HIPTRY(hipMemcpyAsync(v_grids, hgrids.data(), sizeof(GridDev) * hgrids.size(), hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
+    for (size_t li = 0; li < launches.size(); ++li) {
+        const int s0 = launches[li].first, s1 = launches[li].second, nb = s1 - s0;
+        hsv[li].resize(nb);
+        hps[li].resize(nb);
+        char* arena = (char*)v_arena;
+        uint64_t begin = 0;
+        for (int sg = s0; sg < s1; ++sg) {
+            const Flat& F = fl[sg];
+            Item& I = *it[F.item];
+            const int ncell = I.ls.g->ncell;
+            const int b = I.pl.specs[F.spec];
+            OpacRes* op = I.ls.op;
+            PrepSlot& P = hps[li][sg - s0];
+            P.lnk = op->lnk + ((size_t)b * op->ng + F.g) * op->nT * op->nP;
+            P.k_ray = op->k_ray[b];
+            P.n = b;
+            P.lam_cm = op->lam_um[b] * 1e-4;
+            auto take = [&](size_t bytes) {
+                char* r = arena;
+                arena += (bytes + 255) & ~(size_t)255;
+                return r;
+            };
+            P.opt = (double*)take(sizeof(double) * 5 * (size_t)ncell);
+            P.optf = mixed ? (float*)take(sizeof(float) * 5 * (size_t)ncell) : nullptr;
+            P.cdf = P.wbirth = nullptr;
+            if (I.mode == MCRT_MODE_EMISSION) {
+                P.cdf = (double*)take(sizeof(double) * 2 * (size_t)ncell);
+                P.wbirth = P.cdf + ncell;
+            }
+            P.stats = sums + (size_t)sg * row_w + pw;
+            SolveDev& S = hsv[li][sg - s0];
+            S.begin = begin;
+            S.n = I.p.n_packets;
+            begin += S.n;
+            S.tag = common->decorrelate ? (uint32_t)(1 + b * I.pl.ng + F.g) : 0u;
+            S.mode = I.mode == MCRT_MODE_EMISSION ? 1 : 0;
+            S.grid = I.gslot;
+            S.cdf = P.cdf;
+            S.wbirth = P.wbirth;
+            if (mixed) {
+                const float* f = P.optf;
+                S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
+                S.g_cld = f + 4 * (size_t)ncell;
+            } else {
+                const double* d = P.opt;
+                S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
+                S.g_cld = d + 4 * (size_t)ncell;
+            }
+        }
+        double* rows = (double*)arena;  // rows after the optics of the launch
+        HIPTRY(hipMemcpyAsync(v_slots, hps[li].data(), sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(v_solves, hsv[li].data(), sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
+        // preparation per run of consecutive solves of one item (one grid, one table)
+        for (int a = s0; a < s1;) {
+            int e = a;
+            while (e < s1 && fl[e].item == fl[a].item) ++e;
+            Item& I = *it[fl[a].item];
+            OpacRes* op = I.ls.op;
+            const PrepSlot* ps = (const PrepSlot*)v_slots + (a - s0);
+            launch_prep_optics(I.ls.g->dev, I.ls.g->ncell, ps, e - a, 0, op->nT, op->nP, op->T_grid, op->lnP_grid,
+                               op->lnk, op->nspec, nullptr, st);
+            if (I.mode == MCRT_MODE_EMISSION)
+                launch_prep_sources(I.ls.g->dev, I.ls.g->ncell, ps, e - a, I.p.tau_vert_max, I.p.emis_bias,
+                                    (double*)v_ps, st);
+            a = e;
+        }
+        A.rows = rows;
+        A.solves = (const SolveDev*)v_solves;
+        A.n_solves = nb;
+        A.total = begin;
+        launch_fill_u64(A.counter, 0ULL, st);
+        launch_births(hgrids[0], A, true, st);
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li], st));
+        launch_transport_persistent(hgrids[0], A, mixed, true, pblocks, st);
+        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li + 1], st));
+        int chunks_l = 1;
+        for (int sg = s0; sg < s1; ++sg) chunks_l = std::max(chunks_l, reduce_rows_chunks(it[fl[sg].item]->p.n_packets));
+        launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks_l, sums + (size_t)s0 * row_w, row_w, nullptr, st);
+        if (li + 1 < launches.size()) HIPTRY(hipStreamSynchronize(st));  // the arena is reused
+    }
+    HIPTRY(hipGetLastError());
+    std::vector<double> hs((size_t)nsolve * row_w);
+    HIPTRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    mcrt_result tr{};
+    if ((rc = finish_timing(ctx, sl, st, &tr))) return rc;
+    if (prof && (rc = prof_collect(ctx, sl, launches.size(), &tr))) return rc;
+    // per item post-processing, as for the single-request solves
+    for (int q = 0; q < n_items; ++q) {
+        Item& I = *it[q];
+        const int ns = (int)I.pl.specs.size(), ng = I.pl.ng, nsq = ns * ng;
+        const double Nd = (double)I.p.n_packets;
+        std::vector<double> val((size_t)nsq * no), se((size_t)nsq * no), cnt((size_t)nsq * kNCounters), ltot(nsq),
+            rows((size_t)nsq * row_w);
+        for (int k = 0; k < nsq; ++k) {
+            const double* row = hs.data() + (size_t)(I.first + k) * row_w;
+            std::copy(row, row + row_w, rows.begin() + (size_t)k * row_w);
+            double scale = kPi;
+            if (I.mode == MCRT_MODE_EMISSION) {
+                ltot[k] = row[pw];
+                scale = row[pw] / (I.ls.g->r_toa * I.ls.g->r_toa);
+            }
+            for (int o = 0; o < no; ++o) {
+                double m = row[2 * o] / Nd;
+                double var = std::max(row[2 * o + 1] / Nd - m * m, 0.0) / Nd;
+                val[(size_t)k * no + o] = scale * m;
+                se[(size_t)k * no + o] = scale * std::sqrt(var);
+            }
+            for (int t = 0; t < kNCounters; ++t) cnt[(size_t)k * kNCounters + t] = row[2 * no + t];
+        }
+        fill_results(I.pl, val, se, I.ls.op->g_weights, rows, row_w, cnt, ltot, &results[q]);
+        results[q].elapsed_ms = tr.elapsed_ms;
+        results[q].kernel_ms = tr.kernel_ms;
+        results[q].kernel_launches = tr.kernel_launches;
+    }
     return MCRT_OK;
 }
 
@@ -1386,6 +1645,16 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     params->tune_wave_batch = bw;
     if (best_packets_per_s) *best_packets_per_s = best;
     return MCRT_OK;
+}
+
+int mcrt_solve_batch(mcrt_ctx* ctx, int32_t n_items, const mcrt_batch_item* items, const mcrt_solve_params* params,
+                     mcrt_result* results)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->main_mu);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    return solve_batch(ctx, ctx->main, ctx->main.stream, n_items, items, params, results);
 }
 
 int mcrt_solve_albedo(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, const mcrt_solve_params* params,

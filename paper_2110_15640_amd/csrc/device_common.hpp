@@ -115,7 +115,7 @@ struct Ray {
     int ef;
 };
 
-__device__ __forceinline__ int find_edge(const double* e, int n, double x)
+__host__ __device__ __forceinline__ int find_edge(const double* e, int n, double x)
 {
     // largest m in [0, n-1] with e[m] <= x, 0 if none (edges increasing)
     int lo = 0, hi = n - 1;
@@ -130,7 +130,7 @@ __device__ __forceinline__ int find_edge(const double* e, int n, double x)
 // Distance to the latitude cone (the equatorial plane when tb == 0) of an
 // edge with cos^2 = c2, sin^2 = s2; roots below lo ignored; hits must be on
 // the nappe whose z has the sign of tb.
-__device__ __forceinline__ double cone_distance(const Ray& p, double dx, double dy, double dz, double tb,
+__host__ __device__ __forceinline__ double cone_distance(const Ray& p, double dx, double dy, double dz, double tb,
                                                 double c2, double s2, double lo)
 {
     double best = INFINITY;
@@ -179,7 +179,7 @@ __device__ __forceinline__ double cone_distance(const Ray& p, double dx, double 
 
 // Distance to leave the current cell along d; returns the face (ties in the
 // order outer, inner, lat-low, lat-high, lon-low, lon-high).
-__device__ __forceinline__ int exit_distance(const GridDev& g, const Ray& p, double dx, double dy,
+__host__ __device__ __forceinline__ int exit_distance(const GridDev& g, const Ray& p, double dx, double dy,
                                              double dz, double& s_out)
 {
     if (g.geom == 1) {
@@ -277,7 +277,7 @@ __device__ __forceinline__ int exit_distance(const GridDev& g, const Ray& p, dou
     return face;
 }
 
-__device__ __forceinline__ void advance(const GridDev& g, Ray& p, double dx, double dy, double dz, double s)
+__host__ __device__ __forceinline__ void advance(const GridDev& g, Ray& p, double dx, double dy, double dz, double s)
 {
     if (g.geom == 1) {
         p.z = p.z + s * dz;
@@ -288,7 +288,7 @@ __device__ __forceinline__ void advance(const GridDev& g, Ray& p, double dx, dou
     }
 }
 
-__device__ __forceinline__ void cross(const GridDev& g, Ray& p, int f)
+__host__ __device__ __forceinline__ void cross(const GridDev& g, Ray& p, int f)
 {
     switch (f) {
     case F_OUT:
@@ -309,12 +309,12 @@ __device__ __forceinline__ void cross(const GridDev& g, Ray& p, int f)
     }
 }
 
-__device__ __forceinline__ int cell_of(const GridDev& g, const Ray& p)
+__host__ __device__ __forceinline__ int cell_of(const GridDev& g, const Ray& p)
 {
     return (p.k * g.nlat + p.j) * g.nlon + p.i;
 }
 
-__device__ __forceinline__ void locate_column(const GridDev& g, Ray& p)
+__host__ __device__ __forceinline__ void locate_column(const GridDev& g, Ray& p)
 {
     double lat = atan2(p.z, sqrt(p.x * p.x + p.y * p.y));
     double lon = atan2(p.y, p.x);
@@ -387,7 +387,7 @@ struct Walker {
     int ef;                 // face by which the current cell was entered
 };
 
-__device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, bool need_out, bool need_in)
+__host__ __device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, bool need_out, bool need_in)
 {
     if (g.geom == 1) {
         if (need_out) w.tout = w.dz > 0.0 ? fmax((g.r[w.k + 1] - w.pz) / w.dz, w.t) : INFINITY;
@@ -419,7 +419,7 @@ __device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, bool need
 
 // Roots of the latitude cone of edge e on the nappe of its sign (or the
 // equatorial plane), ascending, INFINITY where absent.
-__device__ __forceinline__ void wk_cone(const GridDev& g, const Walker& w, int e, double& r1, double& r2)
+__host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker& w, int e, double& r1, double& r2)
 {
     r1 = INFINITY;
     r2 = INFINITY;
@@ -454,7 +454,7 @@ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker& w, int e
 }
 
 // Hit of the longitude half-plane of edge e (upper = the cell's upper face).
-__device__ __forceinline__ double wk_plane(const GridDev& g, const Walker& w, int e, bool upper)
+__host__ __device__ __forceinline__ double wk_plane(const GridDev& g, const Walker& w, int e, bool upper)
 {
     double sb = g.lon_s[e], cb = g.lon_c[e];
     double nx = -sb, ny = cb;
@@ -465,7 +465,7 @@ __device__ __forceinline__ double wk_plane(const GridDev& g, const Walker& w, in
     return (cb * hx + sb * hy > 0.0) ? th : INFINITY;
 }
 
-__device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, double px, double py, double pz, double dx,
+__host__ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, double px, double py, double pz, double dx,
                                          double dy, double dz, int i, int j, int k, int ef)
 {
     w.px = px; w.py = py; w.pz = pz;
@@ -489,7 +489,7 @@ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, double px,
 
 // Next cone root at or after t; roots of the cone just crossed must lie more
 // than 1e-9 |p| ahead (the same entry-face tolerance as exit_distance).
-__device__ __forceinline__ double wk_next_root(double r1, double r2, double t, double lo)
+__host__ __device__ __forceinline__ double wk_next_root(double r1, double r2, double t, double lo)
 {
     if (r1 >= lo) return r1;
     if (r2 >= lo) return r2;
@@ -498,7 +498,7 @@ __device__ __forceinline__ double wk_next_root(double r1, double r2, double t, d
 
 // Parameter and face of the next crossing (ties: outer, inner, lat-low,
 // lat-high, lon-low, lon-high).
-__device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double& tf)
+__host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double& tf)
 {
     double best = w.tout;
     int face = w.tout < INFINITY ? F_OUT : F_NONE;
@@ -522,7 +522,7 @@ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double
 // Move to parameter tf on face f, enter the neighbour cell and compute the
 // faces that are new to it.  Returns false when the walk left the grid
 // (k == nlay: top; k < 0: surface).
-__device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
+__host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
 {
     w.t = tf;
     switch (f) {
@@ -572,7 +572,7 @@ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, dou
     }
 }
 
-__device__ __forceinline__ int wk_cell(const GridDev& g, const Walker& w)
+__host__ __device__ __forceinline__ int wk_cell(const GridDev& g, const Walker& w)
 {
     return (w.k * g.nlat + w.j) * g.nlon + w.i;
 }

@@ -61,11 +61,13 @@ struct SolveDev {
     unsigned long long n;      // packets of the solve
     uint32_t tag;
     int mode;  // 0 albedo, 1 emission
+    int grid;  // index into BatchArgs.grids (multi-grid launches)
 };
 
 struct BatchArgs {
     const SolveDev* solves;
     int n_solves;
+    const GridDev* grids;  // per-solve grids of a multi-grid launch (else unused)
     unsigned long long total;     // packets over all solves
     unsigned long long* counter;  // packet dispenser
     double* rows;                 // [total][row_w]: F per observer, then counters
@@ -81,7 +83,7 @@ struct BatchArgs {
     double tau_peel_max;
     double mu0;
     double r_toa;
-    double obs[3 * kMaxObs];
+    double obs[2][3 * kMaxObs];  // observer directions for albedo [0] and emission [1] solves
     int batch;         // packets a wave takes from the dispenser at once
     int ev_threshold;  // waiting lanes that trigger event handling
 };
@@ -106,14 +108,14 @@ void launch_prep_sources(const GridDev& g, int ncell, const PrepSlot* slots, int
                          double xi, double* scratch, hipStream_t stream);
 size_t prep_scratch_doubles(int ncell, int nslots);
 
-void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks,
+void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, bool multi, int blocks,
                                  hipStream_t stream);
 void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_solves,
                         double* partials, int chunks, double* sums, int sums_w, double* dump,
                         hipStream_t stream);
 int reduce_rows_chunks(unsigned long long max_n);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream);
-void launch_births(const GridDev& g, const BatchArgs& a, hipStream_t stream);
+void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream);
 
 // Launchers (kernels.hip).  All run on `stream`; none synchronises.
 void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP,

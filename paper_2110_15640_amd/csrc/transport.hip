@@ -45,7 +45,7 @@ struct ColdLDS {
     unsigned long long gid[kTPB];
     int si[kTPB], sj[kTPB], sk[kTPB], sef[kTPB];
     uint32_t e[kTPB];
-    int o[kTPB], birth[kTPB], solve[kTPB], nint[kTPB], ncapped[kTPB], nlost[kTPB];
+    int o[kTPB], birth[kTPB], solve[kTPB], smode[kTPB], nint[kTPB], ncapped[kTPB], nlost[kTPB];
 };
 
 struct Lane {
@@ -76,6 +76,7 @@ struct Lane {
     __device__ int& o() { return C->o[t]; }
     __device__ int& birth() { return C->birth[t]; }
     __device__ int& solve() { return C->solve[t]; }
+    __device__ int& smode() { return C->smode[t]; }
     __device__ int& nint() { return C->nint[t]; }
     __device__ int& ncapped() { return C->ncapped[t]; }
     __device__ int& nlost() { return C->nlost[t]; }
@@ -114,9 +115,10 @@ __device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const doub
         oy = 0.0;
         oz = L.mu0();
     } else {
-        ox = sobs[3 * L.o()];
-        oy = sobs[3 * L.o() + 1];
-        oz = sobs[3 * L.o() + 2];
+        const double* ob = sobs + L.smode() * (3 * kMaxObs);
+        ox = ob[3 * L.o()];
+        oy = ob[3 * L.o() + 1];
+        oz = ob[3 * L.o() + 2];
     }
 }
 
@@ -377,11 +379,14 @@ enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL };
 // K4a: births of every packet of a batch (albedo: uniform on the top disk or
 // the slab's incidence; emission: cell from the biased CDF, uniform position in
 // its volume, isotropic direction, weight (L_i/L_tot)/q_i), one thread each.
-__global__ void __launch_bounds__(256) k_births(GridDev g, BatchArgs A)
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 {
     const unsigned long long gid = (unsigned long long)blockIdx.x * 256 + threadIdx.x;
     if (gid >= A.total) return;
     const SolveDev& S = A.solves[solve_of(A, gid)];
+    const GridDev& g = MULTI ? A.grids[S.grid] : g1;
+    const double r_toa = g.r[g.nlay];
     const unsigned long long q = gid - S.begin;
     double* row = A.rows + gid * (unsigned long long)A.row_w;
     for (int o = 0; o < A.n_out; ++o) row[o] = 0.0;
@@ -395,10 +400,10 @@ __global__ void __launch_bounds__(256) k_births(GridDev g, BatchArgs A)
             b[B_DX] = sqrt(fmax(1.0 - mu0 * mu0, 0.0)); b[B_DY] = 0.0; b[B_DZ] = -mu0;
             b[B_CELL] = (double)((g.nlay - 1) * 8 + (F_OUT + 1));
         } else {
-            double rho = A.r_toa * sqrt(u.a);
+            double rho = r_toa * sqrt(u.a);
             double a = 2.0 * kPi * u.b;
             double y = rho * cos(a), z = rho * sin(a);
-            double x = sqrt(fmax(A.r_toa * A.r_toa - y * y - z * z, 0.0));
+            double x = sqrt(fmax(r_toa * r_toa - y * y - z * z, 0.0));
             Ray rs;
             rs.x = x; rs.y = y; rs.z = z;
             locate_column(g, rs);
@@ -456,6 +461,7 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
 {
     L.solve() = solve_of(A, L.gid());
     const SolveDev& S = A.solves[L.solve()];
+    L.smode() = S.mode;
     const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
     L.w_abs = 0.0;
     L.w_rr() = 0.0;
@@ -487,13 +493,14 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
     return A_PEEL;
 }
 
-template <bool MIXED>
-__global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g, BatchArgs A)
+template <bool MIXED, bool MULTI>
+__global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g1, BatchArgs A)
 {
-    __shared__ double sobs[3 * kMaxObs];
+    __shared__ double sobs[2 * 3 * kMaxObs];
     __shared__ ColdLDS cold;
-    if (threadIdx.x < 3 * kMaxObs) sobs[threadIdx.x] = A.obs[threadIdx.x];
+    if (threadIdx.x < 2 * 3 * kMaxObs) sobs[threadIdx.x] = A.obs[threadIdx.x / (3 * kMaxObs)][threadIdx.x % (3 * kMaxObs)];
     __syncthreads();
+    int lgrid = 0;  // grid of the lane's packet (multi-grid launches)
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned long long res_next = 0, res_end = 0;
@@ -506,6 +513,7 @@ __global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g, Bat
     const void* aext = nullptr;
     const void* aabs = nullptr;
     for (;;) {
+        const GridDev& g = MULTI ? A.grids[lgrid] : g1;
         if (L.mode <= M_PEEL) walk_step<MIXED>(L, g, aext, aabs, A);
         unsigned long long evm = __ballot(L.mode == M_EVENT);
         unsigned long long walking = __ballot(L.mode <= M_PEEL);
@@ -547,14 +555,18 @@ __global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g, Bat
             }
             if (L.mode == M_DEAD && exhausted) L.mode = M_IDLE;
             if (L.mode == M_BIRTH) {
-                act = birth(L, g, A);
-                const SolveDev& S = A.solves[L.solve()];
+                const int sv = solve_of(A, L.gid());
+                const SolveDev& S = A.solves[sv];
+                if (MULTI) lgrid = S.grid;
+                const GridDev& gb = MULTI ? A.grids[lgrid] : g1;
+                act = birth(L, gb, A);
                 aext = S.a_ext;
                 aabs = S.a_abs;
             }
         }
-        if (act == A_FLIGHT) start_flight(L, g, A, A.solves[L.solve()]);
-        else if (act == A_PEEL) start_peel(L, g, A, sobs);
+        const GridDev& ga = MULTI ? A.grids[lgrid] : g1;
+        if (act == A_FLIGHT) start_flight(L, ga, A, A.solves[L.solve()]);
+        else if (act == A_PEEL) start_peel(L, ga, A, sobs);
         if (__ballot(L.mode != M_IDLE) == 0) break;
     }
 }
@@ -649,17 +661,24 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
 
 }  // namespace
 
-void launch_births(const GridDev& g, const BatchArgs& a, hipStream_t stream)
+void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_births, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, stream, g, a);
+    dim3 grid((unsigned)((a.total + 255) / 256));
+    if (multi) hipLaunchKernelGGL(k_births<true>, grid, dim3(256), 0, stream, g, a);
+    else hipLaunchKernelGGL(k_births<false>, grid, dim3(256), 0, stream, g, a);
 }
 
-void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, int blocks, hipStream_t stream)
+void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, bool multi, int blocks,
+                                 hipStream_t stream)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_transport_persistent<true>, dim3(blocks), dim3(256), 0, stream, g, a);
+    if (mixed && multi)
+        hipLaunchKernelGGL((k_transport_persistent<true, true>), dim3(blocks), dim3(256), 0, stream, g, a);
+    else if (mixed)
+        hipLaunchKernelGGL((k_transport_persistent<true, false>), dim3(blocks), dim3(256), 0, stream, g, a);
+    else if (multi)
+        hipLaunchKernelGGL((k_transport_persistent<false, true>), dim3(blocks), dim3(256), 0, stream, g, a);
     else
-        hipLaunchKernelGGL(k_transport_persistent<false>, dim3(blocks), dim3(256), 0, stream, g, a);
+        hipLaunchKernelGGL((k_transport_persistent<false, false>), dim3(blocks), dim3(256), 0, stream, g, a);
 }
 
 int reduce_rows_chunks(unsigned long long max_n) { return (int)((max_n + kChunk - 1) / kChunk); }

@@ -62,6 +62,11 @@ class SolveParams(ctypes.Structure):
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("grid_id", _i32), ("opac_id", _i32), ("n_spec", _i32), ("spec_idx", _vp),
+                ("n_packets", _u64)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
                 ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
@@ -94,6 +99,8 @@ def load() -> ctypes.CDLL:
     L.mcrt_default_params.restype = None
     for nm in ("mcrt_solve_albedo", "mcrt_solve_emission", "mcrt_solve_transmission"):
         getattr(L, nm).argtypes = [_vp, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
+    L.mcrt_solve_batch.argtypes = [_vp, _i32, ctypes.POINTER(BatchItem), ctypes.POINTER(SolveParams),
+                                   ctypes.POINTER(Result)]
     L.mcrt_autotune.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_dbl)]
     L.mcrt_serve_config.argtypes = [_vp, _i32]
     L.mcrt_submit.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_u64)]
@@ -265,6 +272,29 @@ class Context:
         out["kernel_launches"] = r.kernel_launches
         out["queued_ms"] = r.queued_ms
         out["latency_ms"] = r.latency_ms
+
+    def solve_batch(self, items, **kw):
+        """items: list of dicts (mode, gid, oid, table, spec_idx, n_packets);
+        kw: common parameters.  Returns one result dict per item."""
+        p, keep = self._params(dict(kw))
+        arr = (BatchItem * len(items))()
+        outs, res = [], (Result * len(items))()
+        for q, it in enumerate(items):
+            t = it["table"]
+            spec = it.get("spec_idx")
+            sa = None if spec is None else _arr(spec, np.int32)
+            keep.append(sa)
+            ns = len(sa) if sa is not None else t.nband
+            arr[q] = BatchItem(MODES[it["mode"]], it["gid"], it["oid"], 0 if sa is None else len(sa),
+                               None if sa is None else sa.ctypes.data, int(it["n_packets"]))
+            out = self._alloc(ns, t.ng, max(p.n_obs, 1))
+            outs.append(out)
+            res[q] = self._result(out)
+        _check(load().mcrt_solve_batch(self._h, len(items), arr, ctypes.byref(p), res))
+        for q in range(len(items)):
+            self._finish(outs[q], res[q])
+        del keep
+        return outs
 
     def autotune(self, mode: str, gid: int, oid: int, **kw) -> dict:
         """Pick the persistent launch shape for this request; returns the

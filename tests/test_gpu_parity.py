@@ -286,3 +286,33 @@ def test_mixed_precision_agrees_with_fp64(ctx, torch_dev, mode):
     assert np.all(np.abs(b["value"] - a["value"]) <= 3.0 * a["stderr"])
     ctx.free_grid(gid)
     ctx.free_opacity(oid)
+
+
+def test_multi_grid_batch_equals_single_solves(ctx, torch_dev):
+    """Albedo and emission items on grids of uneven size in multi-grid
+    persistent launches: every item's result equals its own single solve."""
+    _log("multi-grid batch: 5 items on 3 uneven grids vs single solves")
+    specs = [(16, 8, 10), (24, 12, 6), (8, 4, 12)]
+    gids, tabs = [], []
+    for q, (a, b, c) in enumerate(specs):
+        grid, table, _ = I.make_emission_3d(a, b, c, nband=4, ng=2, config_no=10 + q)
+        table.k_ray = table.k_ray * 50.0
+        gids.append(ctx.upload_grid(grid))
+        tabs.append((ctx.upload_opacity(table), table))
+    items = [dict(mode="emission", gid=gids[0], oid=tabs[0][0], table=tabs[0][1], spec_idx=[0, 3], n_packets=1700),
+             dict(mode="albedo", gid=gids[1], oid=tabs[1][0], table=tabs[1][1], spec_idx=[1], n_packets=900),
+             dict(mode="emission", gid=gids[2], oid=tabs[2][0], table=tabs[2][1], spec_idx=[2, 1, 0], n_packets=2500),
+             dict(mode="albedo", gid=gids[0], oid=tabs[0][0], table=tabs[0][1], spec_idx=[2], n_packets=300),
+             dict(mode="emission", gid=gids[1], oid=tabs[1][0], table=tabs[1][1], spec_idx=[3], n_packets=64)]
+    common = dict(obs_phase=[0.0, 0.5], seed=71, decorrelate=1)
+    for mb in (0, 3):  # one launch, and launches of at most 3 solves
+        outs = ctx.solve_batch(items, max_batch=mb, **common)
+        for it, got in zip(items, outs):
+            fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
+            ref = fn(it["gid"], it["oid"], it["table"], spec_idx=it["spec_idx"], n_packets=it["n_packets"], **common)
+            assert np.array_equal(got["sums"], ref["sums"]), (mb, it["mode"])
+            assert np.array_equal(got["value"], ref["value"]), (mb, it["mode"])
+    for g in gids:
+        ctx.free_grid(g)
+    for o, _ in tabs:
+        ctx.free_opacity(o)
