@@ -38,13 +38,20 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=1, help="untimed full steps of the batched form first")
     ap.add_argument("--bands", type=int, default=100, help="bands solved per step (workload: 100)")
     ap.add_argument("--packets", type=float, default=1e6, help="packets per (band, g) (workload: 1e6)")
-    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain FP64 form (0 = skip)")
+    ap.add_argument("--autotune", type=int, default=1, help="pick the persistent launch shape by trial solves")
+    ap.add_argument("--ev-threshold", type=int, default=0, help="launch shape when --autotune 0 (0 = library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--wave-batch", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-packets", type=int, default=3000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
+    ap.add_argument("--batch-scale", type=float, default=0.01,
+                    help="packet scale of the 256-request multi-grid batch leg (0 = skip)")
+    ap.add_argument("--batch-plain", type=int, default=1, help="also time that batch in the plain FP64 form")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="duration of the Poisson serving leg (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -90,11 +97,92 @@ def transmission_leg(M, I):
                 "rel_se_median": float(np.median(r["stderr"][:, 0] / depth))}
 
 
+def albedo_leg(M, I, reps=10):
+    """1D plane-parallel albedo spectrum (50 layers, 10 wavelengths x 1e5
+    packets, uniform-disk incidence): plain FP64 launches per solve, the
+    batched FP32-mixed form, and the same batched solve recorded once as a
+    hipGraph and replayed."""
+    import torch
+    grid, table = I.make_albedo_slab()
+    npk = 100_000
+    out = {"workload": f"1D albedo: {grid.nlay} layers, {table.nband} wavelengths x {npk} packets"}
+    with M.Context(0) as ctx:
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+        forms = (("plain_fp64", dict(precision=M.MCRT_FP64, max_batch=1)),
+                 ("batched_mixed", dict(precision=M.MCRT_MIXED, max_batch=0)),
+                 ("batched_mixed_graph", dict(precision=M.MCRT_MIXED, max_batch=0, graph=1)))
+        vals = {}
+        for name, kw in forms:
+            r = ctx.solve_albedo(gid, oid, table, n_packets=npk, seed=211015641, **kw)  # warm / record
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = ctx.solve_albedo(gid, oid, table, n_packets=npk, seed=211015641, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            vals[name] = r
+            out[name] = {"ms": dt * 1e3, "packets_per_s": table.nband * npk / dt}
+        a, b, c = vals["plain_fp64"], vals["batched_mixed"], vals["batched_mixed_graph"]
+        out["graph_equals_eager"] = bool(np.array_equal(b["sums"], c["sums"]))
+        out["mixed_vs_fp64_rel_max"] = float((np.abs(b["value"] - a["value"]) / np.abs(a["value"])).max())
+        out["A_g_rel_se_median"] = float(np.median(a["stderr"] / a["value"]))
+    return out
+
+
+def batch_leg(M, I, scale, plain, log):
+    """256 albedo / emission requests on grids from 32x16x30 to 128x64x60,
+    10-500 bands x 8 g each, packets per (band, g) log-uniform 1e4-1e6 times
+    `scale`: all of them in one mcrt_solve_batch call (FP32-mixed, multi-grid
+    persistent launches) against one FP64 launch per (band, g) solve."""
+    import torch
+    grids, table, reqs = I.make_batch_mix(packet_scale=scale)
+    common = dict(obs_phase=[0.0, 0.5], seed=211015644, profile=1)
+    out = {"workload": f"{len(reqs)} albedo/emission requests on grids 32x16x30..128x64x60, 10-500 bands x 8 g, "
+                       f"packets per (band, g) log-uniform 1e4-1e6 x {scale:g}, 2 observers"}
+    with M.Context(0) as ctx:
+        oid = ctx.upload_opacity(table)
+        gids = [ctx.upload_grid(g) for g in grids]
+        items = [dict(mode=r.mode, gid=gids[r.grid_index], oid=oid, table=table, spec_idx=r.bands,
+                      n_packets=r.n_packets) for r in reqs]
+        packets = sum(len(r.bands) * table.ng * r.n_packets for r in reqs)
+        solves = sum(len(r.bands) * table.ng for r in reqs)
+        ctx.solve_batch(items[:2], precision=M.MCRT_MIXED, **common)  # warm kernels and scratch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bo = ctx.solve_batch(items, precision=M.MCRT_MIXED, **common)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        log(f"[bench]   batch: {solves} solves, {packets} packets in {tb:.2f} s")
+        out.update({"solves": solves, "packets": packets, "batched_s": tb, "batched_packets_per_s": packets / tb,
+                    "batched_transport_launches": int(sum(o["kernel_launches"] for o in bo[:1]))})
+        if plain:
+            t0 = time.perf_counter()
+            po = []
+            for it in items:
+                fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
+                po.append(fn(it["gid"], oid, table, spec_idx=it["spec_idx"], n_packets=it["n_packets"],
+                             precision=M.MCRT_FP64, max_batch=1, **common))
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t0
+            log(f"[bench]   plain: {tp:.2f} s")
+            d = np.concatenate([(np.abs(b["value"] - a["value"]) / np.maximum(np.abs(a["value"]), 1e-300)).ravel()
+                                for a, b in zip(po, bo)])
+            z = np.concatenate([(np.abs(b["value"] - a["value"]) / np.maximum(a["stderr"], 1e-300)).ravel()
+                                for a, b in zip(po, bo)])
+            out.update({"plain_s": tp, "plain_packets_per_s": packets / tp, "batched_over_plain": tp / tb,
+                        "mixed_vs_fp64_rel_median": float(np.median(d)), "mixed_vs_fp64_rel_p99": float(np.quantile(d, 0.99)),
+                        "mixed_vs_fp64_sigma_max": float(z.max())})
+        rel = np.concatenate([(o["stderr"] / np.maximum(np.abs(o["value"]), 1e-300)).ravel() for o in bo])
+        out["rel_se_median"] = float(np.median(rel))
+    return out
+
+
 def run_form(ctx, M, gid, oid, table, bands, npk, phases, precision, max_batch, steps, warmup, tune):
     kw = dict(n_packets=npk, obs_phase=list(phases), spec_idx=bands, precision=precision, profile=1,
               seed=211015642, max_batch=max_batch, **tune)
-    for _ in range(warmup):
-        ctx.solve_emission(gid, oid, table, **kw)
+    for w in range(warmup):
+        r = ctx.solve_emission(gid, oid, table, **kw)
+        print(f"[bench]   warmup {w + 1}/{warmup}: {r['elapsed_ms']:.1f} ms device", flush=True)
     import torch
     torch.cuda.synchronize()
     res = []
@@ -142,21 +230,26 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print(f"[bench] workload: {len(bands)} bands x {table.ng} g x {npk} packets, 4 phases", flush=True)
-    # warm the library's kernels and scratch once on a single band
-    ctx.solve_emission(gid, oid, table, n_packets=npk, obs_phase=list(phases), spec_idx=[0], precision=M.MCRT_MIXED)
-    print("[bench] plain form: FP64, one transport launch per (band, g)", flush=True)
-    pres, pwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_FP64, 1, a.plain_steps, 0, tune)
-    pval, prel, _, pcross, pkms, plaunch = summarize(pres, pwall, a.plain_steps, pk_step, npk, table.ng)
-    print("[bench] autotuning the persistent launch shape (untimed)", flush=True)
-    tuned = ctx.autotune("emission", gid, oid, n_packets=npk, obs_phase=list(phases), spec_idx=bands,
-                         precision=M.MCRT_MIXED)
-    tune = {k: v for k, v in tuned.items() if k.startswith("tune_")}
-    print(f"[bench] tuned: {tune}", flush=True)
+    pres = None
+    if a.plain_steps > 0:
+        print("[bench] plain form: FP64, one transport launch per (band, g)", flush=True)
+        # one untimed band warms the FP64 kernels and the scratch
+        ctx.solve_emission(gid, oid, table, n_packets=npk, obs_phase=list(phases), spec_idx=[0],
+                           precision=M.MCRT_FP64, max_batch=1)
+        pres, pwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_FP64, 1, a.plain_steps, 0, tune)
+        pval, prel, _, pcross, pkms, plaunch = summarize(pres, pwall, a.plain_steps, pk_step, npk, table.ng)
+    if a.autotune:
+        print("[bench] autotuning the persistent launch shape (untimed)", flush=True)
+        tuned = ctx.autotune("emission", gid, oid, n_packets=npk, obs_phase=list(phases), spec_idx=bands,
+                             precision=M.MCRT_MIXED)
+        tune = {k: v for k, v in tuned.items() if k.startswith("tune_")}
+    else:
+        tune = {"tune_ev_threshold": a.ev_threshold, "tune_blocks_per_cu": a.blocks_per_cu,
+                "tune_wave_batch": a.wave_batch}
+    print(f"[bench] launch shape: {tune}", flush=True)
     print("[bench] batched form: FP32-mixed, all (band, g) solves in persistent launches", flush=True)
     bres, bwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_MIXED, 0, a.steps, a.warmup, tune)
     value, rel, need, cross, kms, launches = summarize(bres, bwall, a.steps, pk_step, npk, table.ng)
-    # spectrum error of the mixed form against the FP64 form on the same random stream
-    dmix = np.abs(bres[-1]["value"] - pres[-1]["value"]) / np.abs(pres[-1]["value"])
     ach = cross * FLOP_PER_CROSSING / (kms * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "packets/s", "n_gpus": 1, "steps": a.steps,
@@ -167,23 +260,32 @@ def main():
                                f"{npk} packets per (band, g)",
                    "form": "batched FP32-mixed persistent", "packets_per_step": pk_step,
                    "crossings_per_step": cross / a.steps},
-        "plain": {"value": pval, "unit": "packets/s", "dtype": "f64", "steps": a.plain_steps,
-                  "ms_per_step": pwall / a.plain_steps * 1e3, "launches_per_step": plaunch // a.plain_steps,
-                  "kernel_ms_per_step": pkms / a.plain_steps},
-        "batched_over_plain": value / pval,
         "tuned_launch": tune,
         "error": {"rel_se_median": float(np.median(rel)), "rel_se_max": float(rel.max()),
                   "packets_per_band_for_1e-3_median": float(np.median(need)),
-                  "seconds_per_band_for_1e-3_median_batched": float(np.median(need)) / value,
-                  "seconds_per_band_for_1e-3_median_plain": float(np.median(need)) / pval,
-                  "mixed_vs_fp64_rel_max": float(dmix.max()), "mixed_vs_fp64_rel_median": float(np.median(dmix))},
+                  "seconds_per_band_for_1e-3_median_batched": float(np.median(need)) / value},
         "roofline": {"bound": "alu", "kernel": "k_transport_persistent<MIXED>", "achieved": ach,
                      "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR, "traffic": None,
                      "avg_launch_ms": kms / max(launches, 1), "launches": launches,
                      "flop_per_crossing": FLOP_PER_CROSSING},
     }
+    if pres is not None:
+        # spectrum difference of the mixed form from the FP64 form on the same random stream
+        dmix = np.abs(bres[-1]["value"] - pres[-1]["value"]) / np.abs(pres[-1]["value"])
+        out["plain"] = {"value": pval, "unit": "packets/s", "dtype": "f64", "steps": a.plain_steps,
+                        "ms_per_step": pwall / a.plain_steps * 1e3, "launches_per_step": plaunch // a.plain_steps,
+                        "kernel_ms_per_step": pkms / a.plain_steps}
+        out["batched_over_plain"] = value / pval
+        out["error"].update({"seconds_per_band_for_1e-3_median_plain": float(np.median(need)) / pval,
+                             "mixed_vs_fp64_rel_max": float(dmix.max()),
+                             "mixed_vs_fp64_rel_median": float(np.median(dmix))})
     if a.transmission:
         out["transmission"] = transmission_leg(M, I)
+    print("[bench] 1D albedo leg: plain vs batched vs graph replay", flush=True)
+    out["albedo_1d"] = albedo_leg(M, I)
+    if a.batch_scale > 0:
+        print(f"[bench] batch leg: 256 multi-grid requests, packet scale {a.batch_scale:g}", flush=True)
+        out["batch"] = batch_leg(M, I, a.batch_scale, a.batch_plain, lambda m: print(m, flush=True))
     if a.serve_seconds > 0:
         print(f"[bench] serving leg: Poisson 20 req/s for {a.serve_seconds:.0f} s", flush=True)
         from paper_2110_15640_amd import serve as SV

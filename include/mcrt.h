@@ -173,7 +173,16 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   1 = one launch per solve, 0 = as many as the HBM budget allows.
  * tune_ev_threshold, tune_blocks_per_cu, tune_wave_batch: launch shape of the
  *   persistent transport (lanes waiting before events are handled, 256-lane
- *   blocks per compute unit, packets a wave takes at once); 0 = default. */
+ *   blocks per compute unit, packets a wave takes at once); 0 = default.
+ * graph: albedo and emission blocking solves: non-zero records the solve's
+ *   device work (preparation, transport and reduction launches and their
+ *   host-to-device parameter copies) as a hipGraph on the first call and
+ *   replays it on later calls with identical arguments (same ids, parameters,
+ *   packet_dump and stream, and the same library scratch buffers).  Results are
+ *   identical to the eager path; profile is ignored (kernel_ms then holds the
+ *   whole replay).  The library keeps at most 16 graphs and drops those of a
+ *   grid or table when it is freed.  Ignored by transmission and served
+ *   requests. */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -203,6 +212,7 @@ typedef struct {
     int32_t tune_ev_threshold;
     int32_t tune_blocks_per_cu;
     int32_t tune_wave_batch;
+    int32_t graph;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -79,6 +79,23 @@ struct Slot {
 
 struct Request;
 
+// A recorded solve (params.graph): the instantiated graph and the pinned host
+// copies of the per-batch solve tables that its copy nodes read.
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* pinned = nullptr;
+    int32_t gid = 0, oid = 0;
+    uint64_t used = 0;
+    ~GraphEntry()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+constexpr size_t kMaxGraphs = 16;
+
 }  // namespace
 
 struct mcrt_ctx {
@@ -94,6 +111,10 @@ struct mcrt_ctx {
     std::map<int32_t, std::unique_ptr<OpacRes>> opacs;
     int32_t next_grid = 1, next_opac = 1;
     bool poisoned = false;
+    // recorded blocking solves (params.graph), keyed by their arguments
+    std::mutex graph_mu;
+    std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
+    uint64_t graph_clock = 0;
     // serving
     std::mutex q_mu;
     std::condition_variable q_cv;
@@ -489,6 +510,17 @@ struct Lease {
     }
 };
 
+// Forget recorded solves of a grid (gid != 0), a table (oid != 0), or all.
+void drop_graphs(mcrt_ctx* ctx, int32_t gid, int32_t oid)
+{
+    std::lock_guard<std::mutex> gk(ctx->graph_mu);
+    for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
+        const bool hit = (gid == 0 && oid == 0) || (gid != 0 && it->second->gid == gid) ||
+                         (oid != 0 && it->second->oid == oid);
+        it = hit ? ctx->graphs.erase(it) : std::next(it);
+    }
+}
+
 int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -610,79 +642,164 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
 
-    const bool prof = p->profile != 0;
+    const bool use_graph = p->graph != 0 && !sl.stream_ordered;
+    const bool prof = p->profile != 0 && !use_graph;
     const int nbatches = (nsolve + batch - 1) / batch;
     if (prof && (rc = prof_events(ctx, sl, (size_t)nbatches))) return rc;
     res->kernel_ms = 0.0;
     res->kernel_launches = 0;
-    std::vector<std::vector<SolveDev>> host_solves(nbatches);
-    std::vector<std::vector<PrepSlot>> host_slots(nbatches);
-    HIPTRY(hipEventRecord(sl.ev0, st));
-    HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
-    if (op->kind == MCRT_OPAC_HIRES)
-        launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
-    for (int bt = 0; bt < nbatches; ++bt) {
-        const int s0 = bt * batch, s1 = std::min(nsolve, s0 + batch), nb = s1 - s0;
-        std::vector<SolveDev>& hsv = host_solves[bt];
-        std::vector<PrepSlot>& hps = host_slots[bt];
-        hsv.resize(nb);
-        hps.resize(nb);
-        for (int sg = s0; sg < s1; ++sg) {
-            const int slot = sg - s0;
-            const int b = pl.specs[sg / ng], gi = sg % ng;
-            PrepSlot& P = hps[slot];
-            P.lnk = op->kind == MCRT_OPAC_CK ? op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP : nullptr;
-            P.k_ray = op->k_ray[b];
-            P.n = b;
-            const double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
-            P.lam_cm = lam * 1e-4;
-            P.opt = (double*)v_opt + (size_t)slot * 5 * ncell;
-            P.optf = mixed ? (float*)v_optf + (size_t)slot * 5 * ncell : nullptr;
-            P.cdf = mode == MCRT_MODE_EMISSION ? (double*)v_src + (size_t)slot * 2 * ncell : nullptr;
-            P.wbirth = P.cdf ? P.cdf + ncell : nullptr;
-            P.stats = sums + (size_t)sg * row_w + pw;
-            SolveDev& S = hsv[slot];
-            S.begin = (unsigned long long)slot * N;
-            S.n = N;
-            S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
-            S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
-            S.grid = 0;
-            S.cdf = P.cdf;
-            S.wbirth = P.wbirth;
-            if (mixed) {
-                const float* f = P.optf;
-                S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
-                S.g_cld = f + 4 * (size_t)ncell;
+
+    // Replayable form: the whole device chain below is recorded once per set
+    // of arguments (ids, parameters, launch shape, stream and the scratch
+    // addresses it bakes in) and replayed afterwards.
+    GraphEntry* ge = nullptr;
+    bool capture = false;
+    std::string gkey;
+    if (use_graph) {
+        auto add = [&gkey](const void* v, size_t n) { gkey.append((const char*)v, n); };
+        const int32_t ids[3] = {mode, gid, oid};
+        add(ids, sizeof ids);
+        const double dpar[7] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
+                                p->mu0, (double)p->max_events};
+        add(dpar, sizeof dpar);
+        const int64_t ipar[10] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+                                  p->absorption, batch, A.ev_threshold, bpc, A.batch};
+        add(ipar, sizeof ipar);
+        add(pl.obs.data(), sizeof(double) * pl.obs.size());
+        add(pl.specs.data(), sizeof(int) * pl.specs.size());
+        const void* ptrs[14] = {p->packet_dump, st, v_opt, v_optf, v_src, v_rows, v_sums, v_part,
+                                v_solves, v_slots, v_ctr, v_ps, v_shift, (const void*)(uintptr_t)pl.n_obs};
+        add(ptrs, sizeof ptrs);
+        std::lock_guard<std::mutex> gk(ctx->graph_mu);
+        auto it = ctx->graphs.find(gkey);
+        if (it != ctx->graphs.end()) {
+            ge = it->second.get();
+        } else {
+            if (ctx->graphs.size() >= kMaxGraphs) {  // drop the least recently used
+                auto lru = ctx->graphs.begin();
+                for (auto q = ctx->graphs.begin(); q != ctx->graphs.end(); ++q)
+                    if (q->second->used < lru->second->used) lru = q;
+                ctx->graphs.erase(lru);
+            }
+            std::unique_ptr<GraphEntry> e(new GraphEntry());
+            e->gid = gid;
+            e->oid = oid;
+            HIPTRY(hipHostMalloc(&e->pinned, (sizeof(SolveDev) + sizeof(PrepSlot)) * (size_t)nbatches * batch));
+            ge = e.get();
+            ctx->graphs[gkey] = std::move(e);
+            capture = true;
+        }
+        ge->used = ++ctx->graph_clock;
+    }
+    SolveDev* pin_solves = ge ? (SolveDev*)ge->pinned : nullptr;
+    PrepSlot* pin_slots = ge ? (PrepSlot*)(pin_solves + (size_t)nbatches * batch) : nullptr;
+    std::vector<std::vector<SolveDev>> host_solves(use_graph ? 0 : nbatches);
+    std::vector<std::vector<PrepSlot>> host_slots(use_graph ? 0 : nbatches);
+
+    // The device chain: tally clear, Doppler shifts, then per batch the solve
+    // tables, preparation, births, transport and reduction.
+    auto enqueue = [&]() -> int {
+        launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
+        if (op->kind == MCRT_OPAC_HIRES)
+            launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
+        for (int bt = 0; bt < nbatches; ++bt) {
+            const int s0 = bt * batch, s1 = std::min(nsolve, s0 + batch), nb = s1 - s0;
+            SolveDev* hsv;
+            PrepSlot* hps;
+            if (use_graph) {
+                hsv = pin_solves + (size_t)bt * batch;
+                hps = pin_slots + (size_t)bt * batch;
             } else {
-                const double* d = P.opt;
-                S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
-                S.g_cld = d + 4 * (size_t)ncell;
+                host_solves[bt].resize(nb);
+                host_slots[bt].resize(nb);
+                hsv = host_solves[bt].data();
+                hps = host_slots[bt].data();
+            }
+            for (int sg = s0; sg < s1; ++sg) {
+                const int slot = sg - s0;
+                const int b = pl.specs[sg / ng], gi = sg % ng;
+                PrepSlot& P = hps[slot];
+                P = PrepSlot{};
+                P.lnk = op->kind == MCRT_OPAC_CK ? op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP : nullptr;
+                P.k_ray = op->k_ray[b];
+                P.n = b;
+                const double lam = op->kind == MCRT_OPAC_CK ? op->lam_um[b] : op->lam_min * std::exp(b * op->dlnlam);
+                P.lam_cm = lam * 1e-4;
+                P.opt = (double*)v_opt + (size_t)slot * 5 * ncell;
+                P.optf = mixed ? (float*)v_optf + (size_t)slot * 5 * ncell : nullptr;
+                P.cdf = mode == MCRT_MODE_EMISSION ? (double*)v_src + (size_t)slot * 2 * ncell : nullptr;
+                P.wbirth = P.cdf ? P.cdf + ncell : nullptr;
+                P.stats = sums + (size_t)sg * row_w + pw;
+                SolveDev& S = hsv[slot];
+                S = SolveDev{};
+                S.begin = (unsigned long long)slot * N;
+                S.n = N;
+                S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
+                S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
+                S.grid = 0;
+                S.cdf = P.cdf;
+                S.wbirth = P.wbirth;
+                if (mixed) {
+                    const float* f = P.optf;
+                    S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
+                    S.g_cld = f + 4 * (size_t)ncell;
+                } else {
+                    const double* d = P.opt;
+                    S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
+                    S.g_cld = d + 4 * (size_t)ncell;
+                }
+            }
+            HIPTRY(hipMemcpyAsync(v_slots, hps, sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
+            HIPTRY(hipMemcpyAsync(v_solves, hsv, sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
+            launch_prep_optics(g->dev, ncell, (const PrepSlot*)v_slots, nb, op->kind == MCRT_OPAC_HIRES ? 1 : 0, op->nT,
+                               op->nP, op->T_grid, op->lnP_grid, op->lnk, op->nspec, (const double*)v_shift, st);
+            if (mode == MCRT_MODE_EMISSION)
+                launch_prep_sources(g->dev, ncell, (const PrepSlot*)v_slots, nb, p->tau_vert_max, p->emis_bias,
+                                    (double*)v_ps, st);
+            A.solves = (const SolveDev*)v_solves;
+            A.n_solves = nb;
+            A.total = (unsigned long long)nb * N;
+            launch_fill_u64(A.counter, 0ULL, st);
+            launch_births(g->dev, A, false, st);
+            if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
+            launch_transport_persistent(g->dev, A, mixed, false, pblocks, st);
+            if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
+            double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
+            launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
+            // the next batch reuses the slots: in eager form its pageable host tables are
+            // copied only after this batch ran
+            if (!use_graph && bt + 1 < nbatches) HIPTRY(hipStreamSynchronize(st));
+        }
+        return MCRT_OK;
+    };
+    if (use_graph) {
+        if (capture) {
+            HIPTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int crc = enqueue();
+            hipGraph_t gr = nullptr;
+            hipError_t ee = hipStreamEndCapture(st, &gr);
+            if (crc == MCRT_OK && ee == hipSuccess)
+                ee = hipGraphInstantiate(&ge->exec, gr, nullptr, nullptr, 0);
+            ge->graph = gr;
+            if (crc != MCRT_OK || ee != hipSuccess) {
+                std::lock_guard<std::mutex> gk(ctx->graph_mu);
+                ctx->graphs.erase(gkey);
+                if (crc != MCRT_OK) return crc;
+                HIPTRY(ee);
             }
         }
-        HIPTRY(hipMemcpyAsync(v_slots, hps.data(), sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
-        HIPTRY(hipMemcpyAsync(v_solves, hsv.data(), sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
-        launch_prep_optics(g->dev, ncell, (const PrepSlot*)v_slots, nb, op->kind == MCRT_OPAC_HIRES ? 1 : 0, op->nT,
-                           op->nP, op->T_grid, op->lnP_grid, op->lnk, op->nspec, (const double*)v_shift, st);
-        if (mode == MCRT_MODE_EMISSION)
-            launch_prep_sources(g->dev, ncell, (const PrepSlot*)v_slots, nb, p->tau_vert_max, p->emis_bias,
-                                (double*)v_ps, st);
-        A.solves = (const SolveDev*)v_solves;
-        A.n_solves = nb;
-        A.total = (unsigned long long)nb * N;
-        launch_fill_u64(A.counter, 0ULL, st);
-        launch_births(g->dev, A, false, st);
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
-        launch_transport_persistent(g->dev, A, mixed, false, pblocks, st);
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
-        double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
-        launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
-        if (bt + 1 < nbatches) HIPTRY(hipStreamSynchronize(st));  // slots are reused by the next batch
+        HIPTRY(hipEventRecord(sl.ev0, st));
+        HIPTRY(hipGraphLaunch(ge->exec, st));
+    } else {
+        HIPTRY(hipEventRecord(sl.ev0, st));
+        if ((rc = enqueue())) return rc;
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nsolve * row_w);
     HIPTRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     if ((rc = finish_timing(ctx, sl, st, res))) return rc;
     if (prof && (rc = prof_collect(ctx, sl, (size_t)nbatches, res))) return rc;
+    if (use_graph) res->kernel_ms = res->elapsed_ms;  // the whole replay
 
     // Post-processing (Sect. 5.2 A_g = pi E; Sect. 5.3 F_p = L_tot/(N R_TOA^2) sum F)
     std::vector<double> val((size_t)nsolve * no), se((size_t)nsolve * no), cnt((size_t)nsolve * kNCounters),
@@ -951,7 +1068,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     std::vector<std::vector<PrepSlot>> hps(launches.size());
     HIPTRY(hipEventRecord(sl.ev0, st));
     HIPTRY(hipMemcpyAsync(v_grids, hgrids.data(), sizeof(GridDev) * hgrids.size(), hipMemcpyHostToDevice, st));
-    HIPTRY(hipMemsetAsync(sums, 0, sizeof(double) * (size_t)nsolve * row_w, st));
+    launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
     for (size_t li = 0; li < launches.size(); ++li) {
         const int s0 = launches[li].first, s1 = launches[li].second, nb = s1 - s0;
         hsv[li].resize(nb);
@@ -1330,6 +1447,7 @@ void mcrt_destroy(mcrt_ctx* ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     stop_workers(ctx);
+    drop_graphs(ctx, 0, 0);
     slot_destroy(ctx, ctx->main);
     for (auto& kv : ctx->grids)
         for (auto& b : kv.second->bufs) dev_free(ctx, b);
@@ -1510,6 +1628,7 @@ int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
     if (it->second->refs > 0) return fail(MCRT_EBUSY, "grid %d is used by queued work", grid_id);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->main.stream);
+    drop_graphs(ctx, grid_id, 0);
     for (auto& b : it->second->bufs) dev_free(ctx, b);
     ctx->grids.erase(it);
     return MCRT_OK;
@@ -1577,6 +1696,7 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)
     if (it->second->refs > 0) return fail(MCRT_EBUSY, "opacity %d is used by queued work", opac_id);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->main.stream);
+    drop_graphs(ctx, 0, opac_id);
     for (auto& b : it->second->bufs) dev_free(ctx, b);
     ctx->opacs.erase(it);
     return MCRT_OK;
@@ -1611,6 +1731,7 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     t.max_batch = 0;
     t.packet_dump = nullptr;
     t.profile = 0;
+    t.graph = 0;
     const int evs[3] = {8, 16, 32}, bpcs[2] = {2, 4}, wbs[2] = {32, 128};
     double best = -1.0;
     int be = 16, bb = 4, bw = 64;

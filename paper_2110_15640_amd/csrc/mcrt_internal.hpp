@@ -115,6 +115,7 @@ void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_s
                         hipStream_t stream);
 int reduce_rows_chunks(unsigned long long max_n);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream);
+void launch_fill_f64(double* p, size_t n, double v, hipStream_t stream);
 void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream);
 
 // Launchers (kernels.hip).  All run on `stream`; none synchronises.

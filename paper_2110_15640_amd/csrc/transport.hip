@@ -22,6 +22,8 @@
 // rotation and the peel-off attenuation in float; positions, the directions
 // the traversal uses, exit distances, optical depths and tallies stay double.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -659,6 +661,12 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Fill n doubles (a kernel, so that recorded graphs hold no memset nodes).
+__global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, size_t n, double v)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
 }  // namespace
 
 void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream)
@@ -694,6 +702,13 @@ void launch_reduce_rows(const BatchArgs& a, const SolveDev* /*solves_host*/, int
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, stream, p, v);
+}
+
+void launch_fill_f64(double* p, size_t n, double v, hipStream_t stream)
+{
+    if (n == 0) return;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
 }
 
 }  // namespace mcrt

@@ -316,3 +316,41 @@ def test_multi_grid_batch_equals_single_solves(ctx, torch_dev):
         ctx.free_grid(g)
     for o, _ in tabs:
         ctx.free_opacity(o)
+
+
+def test_graph_replays_equal_eager(ctx, torch_dev):
+    """Recorded solves (params.graph): the first call records the device chain,
+    later identical calls replay it; with other eager work and synchronisations
+    between the replays, every replay equals the eager solve bit for bit."""
+    _log("hipGraph: record + 4 replays (3 batches each) vs the eager solve, eager work in between")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=3, ng=2)
+    slab, st = I.make_albedo_slab(nlay=8, nlam=2)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    sid, soid = ctx.upload_grid(slab), ctx.upload_opacity(st)
+    for prec in (M.MCRT_FP64, M.MCRT_MIXED):
+        base = dict(n_packets=2100, seed=65, obs_phase=phases, max_batch=2, precision=prec)
+        ref = ctx.solve_emission(gid, oid, table, **base)
+        other = ctx.solve_albedo(sid, soid, st, n_packets=500, seed=3)
+        for rep in range(5):
+            got = ctx.solve_emission(gid, oid, table, graph=1, **base)
+            assert np.array_equal(got["sums"], ref["sums"]), (prec, rep)
+            assert np.array_equal(got["value"], ref["value"]), (prec, rep)
+            assert np.array_equal(got["counters"], ref["counters"]), (prec, rep)
+            # eager work on the same stream and scratch between the replays
+            o2 = ctx.solve_albedo(sid, soid, st, n_packets=500, seed=3)
+            assert np.array_equal(o2["sums"], other["sums"])
+            torch_dev.cuda.synchronize()
+    # albedo with a packet dump recorded into the graph
+    dump = dump_buffer(torch_dev, 2, 900, 1)
+    ref = ctx.solve_albedo(sid, soid, st, n_packets=900, seed=5, packet_dump=dump)
+    d0 = dump.clone()
+    for rep in range(3):
+        dump.zero_()
+        got = ctx.solve_albedo(sid, soid, st, n_packets=900, seed=5, packet_dump=dump, graph=1)
+        assert np.array_equal(got["sums"], ref["sums"]), rep
+        assert torch_dev.equal(dump, d0), rep
+    for x in (gid, sid):
+        ctx.free_grid(x)
+    for x in (oid, soid):
+        ctx.free_opacity(x)
