@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-packets", type=int, default=3000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
+    ap.add_argument("--albedo", type=int, default=1, help="also time the 1D albedo workload (plain / batched / graph)")
     ap.add_argument("--batch-scale", type=float, default=0.01,
                     help="packet scale of the 256-request multi-grid batch leg (0 = skip)")
     ap.add_argument("--batch-plain", type=int, default=1, help="also time that batch in the plain FP64 form")
@@ -281,8 +282,9 @@ def main():
                              "mixed_vs_fp64_rel_median": float(np.median(dmix))})
     if a.transmission:
         out["transmission"] = transmission_leg(M, I)
-    print("[bench] 1D albedo leg: plain vs batched vs graph replay", flush=True)
-    out["albedo_1d"] = albedo_leg(M, I)
+    if a.albedo:
+        print("[bench] 1D albedo leg: plain vs batched vs graph replay", flush=True)
+        out["albedo_1d"] = albedo_leg(M, I)
     if a.batch_scale > 0:
         print(f"[bench] batch leg: 256 multi-grid requests, packet scale {a.batch_scale:g}", flush=True)
         out["batch"] = batch_leg(M, I, a.batch_scale, a.batch_plain, lambda m: print(m, flush=True))

@@ -666,10 +666,23 @@ static double peel_tau(const orc_grid *g, const orc_optics *op, const orc_ray *s
     }
 }
 
+/* Contribution-function tally (Sect. "Albedo and emission contribution
+ * functions"): every peel-off f is also added to the cell of the event that
+ * produced it, split into the thermal part (emission points) and the
+ * scattered part (interactions): cf[(o * 2 + part) * ncell + cell].        */
+static void cf_add(double *cf, int64_t ncell, int o, int part, int64_t cell, double f)
+{
+    if (!cf) return;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+    cf[((int64_t)o * 2 + part) * ncell + cell] += f;
+}
+
 /* One packet history.  F[o] receives its peel-off sum per observer. */
 static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params *pr,
                        const double *obs, const double *cdf, const double *wbirth, int64_t ncell,
-                       double r_toa, uint64_t pid, double *F, double *K)
+                       double r_toa, uint64_t pid, double *F, double *K, double *cf)
 {
     uint32_t tag = (uint32_t)pr->tag;
     int nobs = (int)pr->n_obs;
@@ -743,7 +756,9 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         /* initial peel-off from the emission point */
         for (int o = 0; o < nobs; ++o) {
             double tau = peel_tau(g, op, &ry, obs + 3 * o, pr->tau_peel_max, pr->max_cross, &ncross);
-            F[o] = F[o] + W * exp(-tau) / (4.0 * ORC_PI);
+            double f = W * exp(-tau) / (4.0 * ORC_PI);
+            F[o] = F[o] + f;
+            cf_add(cf, ncell, o, 0, c, f);
         }
     }
     W0 = W;
@@ -775,6 +790,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
             F[o] = F[o] + f;
+            cf_add(cf, ncell, o, 1, c, f);
         }
         if (!cont) {
             K[K_ABS] += W * (1.0 - om);
@@ -803,10 +819,11 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
 }
 
 /* Run n_packets histories.  F_out[n][nout], K_out[n][NK] per packet (the
- * caller sums them in packet order).  obs: n_obs unit vectors.           */
+ * caller sums them in packet order).  obs: n_obs unit vectors.  cf (may be
+ * NULL): per-cell peel-off tallies [nout][2][ncell], added to.            */
 int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params *pr,
                       const double *obs, const double *cdf, const double *wbirth, double r_toa,
-                      double *F_out, double *K_out, int64_t nthreads)
+                      double *F_out, double *K_out, double *cf, int64_t nthreads)
 {
     int64_t ncell = g->nlon * g->nlat * g->nlay;
     int nout = (g->geom == 1 && pr->n_obs == 0) ? 1 : (int)pr->n_obs;
@@ -817,7 +834,7 @@ int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params 
 #endif
     for (int64_t q = 0; q < n; ++q) {
         run_packet(g, op, pr, obs, cdf, wbirth, ncell, r_toa, pr->packet0 + (uint64_t)q,
-                   F_out + q * nout, K_out + q * NK);
+                   F_out + q * nout, K_out + q * NK, cf);
     }
     return nout;
 }

@@ -97,7 +97,7 @@ def lib():
                                            vp, vp, vp, vp]
         L.orc_emission_sources.restype = dbl
         L.orc_transport.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Optics),
-                                    ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp, i64]
+                                    ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp, vp, i64]
         L.orc_transport.restype = i64
         L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
                                        vp, vp, i64]
@@ -297,9 +297,11 @@ def emission_obs_dirs(phases):
 
 
 def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.ndarray],
-              sources: Optional[Sources] = None, tag: int = 0):
+              sources: Optional[Sources] = None, tag: int = 0, cf: Optional[np.ndarray] = None):
     """Run params.n_packets histories; returns per-packet F [n, nout] and
-    counters K [n, NK]."""
+    counters K [n, NK].  cf: optional float64 array [nout, 2, ncell] to which
+    every peel-off f is added at the cell of its event, thermal (emission
+    point, index 0) or scattered (interaction, index 1)."""
     gv = GridView(grid)
     nobs = 0 if obs is None else len(obs)
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
@@ -313,8 +315,10 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     o = None if obs is None else _f64(obs)
     cdf = None if sources is None else sources.cdf
     wb = None if sources is None else sources.wbirth
+    if cf is not None:
+        assert cf.dtype == np.float64 and cf.flags.c_contiguous and cf.shape == (max(nout, 1), 2, grid.ncell)
     lib().orc_transport(ctypes.byref(gv.c), ctypes.byref(op), ctypes.byref(pr), _p(o), _p(cdf), _p(wb),
-                        float(grid.r_toa), F.ctypes.data, K.ctypes.data, int(params.threads))
+                        float(grid.r_toa), F.ctypes.data, K.ctypes.data, _p(cf), int(params.threads))
     return F[:, :nout], K
 
 
@@ -338,7 +342,24 @@ def _spec_list(table, spec_idx):
     return [int(s) for s in spec_idx]
 
 
-def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False) -> Result:
+def contribution_function(cf_g, scale_g, w_g):
+    """Band contribution function (Sect. "Albedo and emission contribution
+    functions"): the per-cell peel-off tallies of every g-ordinate, scaled as
+    their spectrum values are and weighted by w_g, divided per observer by
+    their sum over cells and both parts (thermal, scattered), so that they
+    add up to 1.  cf_g: [ng, nout, 2, ncell]."""
+    acc = np.zeros(cf_g.shape[1:])
+    for g in range(cf_g.shape[0]):
+        acc += w_g[g] * scale_g[g] * cf_g[g]
+    tot = acc.sum(axis=(1, 2))
+    out = np.zeros_like(acc)
+    for o in range(acc.shape[0]):
+        if tot[o] > 0.0:
+            out[o] = acc[o] / tot[o]
+    return out
+
+
+def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False) -> Result:
     specs = _spec_list(table, spec_idx)
     ng = table.ng
     if grid.geometry == 1:
@@ -352,10 +373,14 @@ def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False)
     per_g = np.zeros((len(specs), ng, nout))
     se_g = np.zeros_like(per_g)
     packets = {}
+    w = np.asarray(table.g_weights, dtype=np.float64)
+    cfs = []
     for si, b in enumerate(specs):
+        cf_g = np.zeros((ng, nout, 2, grid.ncell)) if contrib else None
         for g in range(ng):
             op = ck_optics(grid, table, b, g)
-            F, K = transport(grid, op, params, 0, obs, tag=_tag(params, b, g, ng))
+            F, K = transport(grid, op, params, 0, obs, tag=_tag(params, b, g, ng),
+                             cf=cf_g[g] if contrib else None)
             if keep_packets:
                 packets[(si, g)] = (F, K)
             sums[si, g, :, 0] = F.sum(axis=0)
@@ -365,13 +390,17 @@ def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False)
             var = np.maximum(sums[si, g, :, 1] / N - E * E, 0.0) / N
             per_g[si, g] = math.pi * E
             se_g[si, g] = math.pi * np.sqrt(var)
-    w = np.asarray(table.g_weights, dtype=np.float64)
+        if contrib:
+            cfs.append(contribution_function(cf_g, np.full(ng, math.pi / N), w))
     value = np.einsum("g,sgo->so", w, per_g)
     stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
-    return Result(value, stderr, per_g, sums, cnt, {"packets": packets})
+    extra = {"packets": packets}
+    if contrib:
+        extra["cf"] = np.array(cfs)
+    return Result(value, stderr, per_g, sums, cnt, extra)
 
 
-def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=False) -> Result:
+def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False) -> Result:
     """Correlated-k emission spectrum F_p(band, phase) [erg/s/cm^2/cm]."""
     specs = _spec_list(table, spec_idx)
     ng = table.ng
@@ -385,13 +414,17 @@ def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=Fals
     ltot = np.zeros((len(specs), ng))
     packets = {}
     rt2 = grid.r_toa ** 2
+    w = np.asarray(table.g_weights, dtype=np.float64)
+    cfs = []
     for si, b in enumerate(specs):
+        cf_g = np.zeros((ng, nout, 2, grid.ncell)) if contrib else None
         for g in range(ng):
             op = ck_optics(grid, table, b, g)
             src = emission_sources(grid, op, table.lam_um[b], params.tau_vert_max, params.emis_bias)
             ltot[si, g] = src.L_tot
             if src.L_tot > 0.0:
-                F, K = transport(grid, op, params, 1, obs, sources=src, tag=_tag(params, b, g, ng))
+                F, K = transport(grid, op, params, 1, obs, sources=src, tag=_tag(params, b, g, ng),
+                                 cf=cf_g[g] if contrib else None)
             else:
                 F, K = np.zeros((N, nout)), np.zeros((N, NK))
             if keep_packets:
@@ -404,10 +437,14 @@ def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=Fals
             # L_p = (L_tot/N) sum F ; I_p = L_p/(pi R_TOA^2) ; F_p = pi I_p
             per_g[si, g] = src.L_tot * mean / rt2
             se_g[si, g] = src.L_tot * np.sqrt(var) / rt2
-    w = np.asarray(table.g_weights, dtype=np.float64)
+        if contrib:
+            cfs.append(contribution_function(cf_g, ltot[si] / (N * rt2), w))
     value = np.einsum("g,sgo->so", w, per_g)
     stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
-    return Result(value, stderr, per_g, sums, cnt, {"packets": packets, "L_tot": ltot})
+    extra = {"packets": packets, "L_tot": ltot}
+    if contrib:
+        extra["cf"] = np.array(cfs)
+    return Result(value, stderr, per_g, sums, cnt, extra)
 
 
 def transmission_alpha(grid, table, specs, hires: bool):
