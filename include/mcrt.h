@@ -182,7 +182,9 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   identical to the eager path; profile is ignored (kernel_ms then holds the
  *   whole replay).  The library keeps at most 16 graphs and drops those of a
  *   grid or table when it is freed.  Ignored by transmission and served
- *   requests. */
+ *   requests.
+ * contrib: mcrt_solve_albedo / mcrt_solve_emission only (EINVAL elsewhere):
+ *   non-zero also fills mcrt_result.cf with the contribution functions. */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -213,6 +215,7 @@ typedef struct {
     int32_t tune_blocks_per_cu;
     int32_t tune_wave_batch;
     int32_t graph;
+    int32_t contrib;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);
@@ -229,7 +232,14 @@ void mcrt_default_params(mcrt_solve_params* p);
  * elapsed_ms receives the device time of the solve; with params.profile,
  * kernel_ms and kernel_launches the summed duration and count of the
  * dominant kernel's launches.  queued_ms and latency_ms are set by
- * mcrt_wait: time from submit to start, and from submit to completion. */
+ * mcrt_wait: time from submit to start, and from submit to completion.
+ * cf[n_spec][n_obs][2][ncell] (with params.contrib; the contribution
+ *   functions of the section on albedo and emission contribution functions):
+ *   per band and observer, the share of the band value produced by
+ *   peel-offs from events in each cell, [0] thermal (emission points) and
+ *   [1] scattered (interactions); each (band, observer) block sums to 1, or is
+ *   0 where the value is 0.  Cells are ordered as the grid's.  Tallied with
+ *   FP64 atomics, so the last bits vary from run to run. */
 typedef struct {
     double* value;
     double* stderr_;
@@ -242,6 +252,7 @@ typedef struct {
     int64_t kernel_launches;
     double queued_ms;
     double latency_ms;
+    double* cf;
 } mcrt_result;
 
 /* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /

@@ -570,6 +570,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     if (p->max_batch < 0 || p->tune_ev_threshold < 0 || p->tune_ev_threshold > 64 || p->tune_blocks_per_cu < 0 ||
         p->tune_blocks_per_cu > 16 || p->tune_wave_batch < 0)
         return fail(MCRT_EINVAL, "bad batching / tuning parameters");
+    if (p->contrib && sl.stream_ordered)
+        return fail(MCRT_EINVAL, "contribution functions are computed by blocking solves only");
+    if (p->contrib && !res->cf) return fail(MCRT_EINVAL, "contrib needs result.cf");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const bool mixed = p->precision == MCRT_MIXED;
@@ -619,6 +622,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     }
     if (op->kind == MCRT_OPAC_HIRES)
         if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+    void* v_cf = nullptr;  // contribution functions [spec][observer][2][cell]
+    const size_t cf_n = p->contrib ? (size_t)ns * no * 2 * ncell : 0;
+    if (p->contrib && (rc = scratch(ctx, sl, st, "contrib", sizeof(double) * cf_n, &v_cf))) return rc;
     double* sums = (double*)v_sums;
 
     BatchArgs A{};
@@ -667,8 +673,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
-        const void* ptrs[14] = {p->packet_dump, st, v_opt, v_optf, v_src, v_rows, v_sums, v_part,
-                                v_solves, v_slots, v_ctr, v_ps, v_shift, (const void*)(uintptr_t)pl.n_obs};
+        const void* ptrs[15] = {p->packet_dump, st, v_opt, v_optf, v_src, v_rows, v_sums, v_part,
+                                v_solves, v_slots, v_ctr, v_ps, v_shift, v_cf, (const void*)(uintptr_t)pl.n_obs};
         add(ptrs, sizeof ptrs);
         std::lock_guard<std::mutex> gk(ctx->graph_mu);
         auto it = ctx->graphs.find(gkey);
@@ -700,6 +706,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     // tables, preparation, births, transport and reduction.
     auto enqueue = [&]() -> int {
         launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
+        if (v_cf) launch_fill_f64((double*)v_cf, cf_n, 0.0, st);
         if (op->kind == MCRT_OPAC_HIRES)
             launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
         for (int bt = 0; bt < nbatches; ++bt) {
@@ -739,6 +746,13 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                 S.grid = 0;
                 S.cdf = P.cdf;
                 S.wbirth = P.wbirth;
+                if (v_cf) {  // scaled as the band value: w_g pi / N, or w_g L_tot / (N R_TOA^2)
+                    const double wg = op->kind == MCRT_OPAC_CK ? op->g_weights[gi] : 1.0;
+                    S.cf = (double*)v_cf + (size_t)(sg / ng) * no * 2 * ncell;
+                    S.cf_w = mode == MCRT_MODE_ALBEDO ? wg * kPi / (double)N
+                                                      : wg / ((double)N * g->r_toa * g->r_toa);
+                    S.cf_ltot = mode == MCRT_MODE_EMISSION ? P.stats : nullptr;
+                }
                 if (mixed) {
                     const float* f = P.optf;
                     S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
@@ -824,6 +838,15 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     }
     std::vector<double> gw = op->kind == MCRT_OPAC_CK ? op->g_weights : std::vector<double>{1.0};
     fill_results(pl, val, se, gw, hs, row_w, cnt, ltot, res);
+    if (v_cf) {  // contribution functions, normalised per (band, observer)
+        HIPTRY(hipMemcpy(res->cf, v_cf, sizeof(double) * cf_n, hipMemcpyDeviceToHost));
+        for (size_t b = 0; b < (size_t)ns * no; ++b) {
+            double* blk = res->cf + b * 2 * ncell;
+            double tot = 0.0;
+            for (size_t c = 0; c < 2 * (size_t)ncell; ++c) tot += blk[c];
+            for (size_t c = 0; c < 2 * (size_t)ncell; ++c) blk[c] = tot > 0.0 ? blk[c] / tot : 0.0;
+        }
+    }
     return MCRT_OK;
 }
 
@@ -841,6 +864,7 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     SolvePlan pl;
     rc = plan_common(def_stream, g, op, p, MCRT_MODE_TRANSMISSION, pl);
     if (rc) return rc;
+    if (p->contrib) return fail(MCRT_EINVAL, "contribution functions are defined for albedo and emission");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const int ncell = g->ncell;
@@ -937,6 +961,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
                 const mcrt_solve_params* common, mcrt_result* results)
 {
     if (n_items < 1 || !items || !common || !results) return fail(MCRT_EINVAL, "batch needs items, params, results");
+    if (common->contrib) return fail(MCRT_EINVAL, "contribution functions are computed by single solves only");
     struct Item {
         Lease ls;
         SolvePlan pl;
@@ -1323,6 +1348,7 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
 {
     if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION && mode != MCRT_MODE_TRANSMISSION)
         return fail(MCRT_EINVAL, "unknown mode %d", mode);
+    if (p->contrib) return fail(MCRT_EINVAL, "contribution functions are computed by blocking solves only");
     std::unique_ptr<Request> r(new Request());
     r->mode = mode;
     r->gid = gid;

@@ -62,6 +62,11 @@ struct SolveDev {
     uint32_t tag;
     int mode;  // 0 albedo, 1 emission
     int grid;  // index into BatchArgs.grids (multi-grid launches)
+    // contribution functions (or null): every peel-off f also adds
+    // f * cf_w * (*cf_ltot if set) to cf[(observer * 2 + part) * ncell + cell]
+    double* cf;
+    double cf_w;
+    const double* cf_ltot;
 };
 
 struct BatchArgs {

@@ -337,6 +337,12 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         }
         double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
         row[L.o()] = row[L.o()] + f;
+        if (S.cf && f > 0.0) {  // contribution function: the event's cell, thermal or scattered part
+            const int ncell = g.nlon * g.nlat * g.nlay;
+            const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
+            const double sc = S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w;
+            unsafeAtomicAdd(S.cf + ((size_t)L.o() * 2 + (L.birth() ? 0 : 1)) * ncell + c, f * sc);
+        }
         L.o() += 1;
         if (L.o() < A.n_out) return A_PEEL;
         if (L.birth()) {

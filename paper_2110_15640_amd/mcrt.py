@@ -60,7 +60,7 @@ class SolveParams(ctypes.Structure):
                 ("n_b", _i32), ("n_alpha", _i32), ("r_star", _dbl), ("stream", _vp),
                 ("packet_dump", _vp), ("profile", _i32), ("max_batch", _i32),
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32),
-                ("graph", _i32)]
+                ("graph", _i32), ("contrib", _i32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -71,7 +71,7 @@ class BatchItem(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
                 ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
-                ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl)]
+                ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl), ("cf", _vp)]
 
 
 _lib = None
@@ -142,6 +142,7 @@ class Context:
         _check(L.mcrt_create(device, hbm_budget_bytes, ctypes.byref(h)))
         self._h = h
         self._keep = []
+        self._ncell = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -179,6 +180,7 @@ class Context:
                      _ptr(arrs["ca"]), _ptr(arrs["cg"]), float(g.omega_rot))
         gid = _i32()
         _check(load().mcrt_grid_upload(self._h, ctypes.byref(d), ctypes.byref(gid)))
+        self._ncell[gid.value] = g.nlon * g.nlat * g.nlay
         return gid.value
 
     def upload_opacity(self, t) -> int:
@@ -239,6 +241,8 @@ class Context:
         ns = p.n_spec if p.spec_idx else n_spec
         no = n_out(p)
         out = self._alloc(ns, ng, no)
+        if p.contrib:
+            out["cf"] = np.zeros((ns, no, 2, self._ncell[gid]))
         r = self._result(out)
         _check(fn(self._h, gid, oid, ctypes.byref(p), ctypes.byref(r)))
         self._finish(out, r)
@@ -262,9 +266,10 @@ class Context:
 
     @staticmethod
     def _result(out):
+        cf = out.get("cf")
         return Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
                       out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data,
-                      0.0, 0.0, 0, 0.0, 0.0)
+                      0.0, 0.0, 0, 0.0, 0.0, None if cf is None else cf.ctypes.data)
 
     @staticmethod
     def _finish(out, r):

@@ -354,3 +354,48 @@ def test_graph_replays_equal_eager(ctx, torch_dev):
         ctx.free_grid(x)
     for x in (oid, soid):
         ctx.free_opacity(x)
+
+
+def test_contribution_functions_parity(ctx, torch_dev):
+    """Per-cell contribution functions (thermal and scattered parts, per band
+    and observer) against the oracle on the same stream; albedo and emission."""
+    _log("contribution functions: emission with clouds (16x8x10, 2 bands x 2 g, 3 phases), albedo sphere")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2)
+    rng = np.random.default_rng(5)
+    grid.cld_ksca = rng.uniform(0, 5e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 1e-2, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.5, 0.9, grid.ncell).astype(np.float32)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    ph = list(phases[:3])
+    for graph in (0, 1, 1):
+        got = ctx.solve_emission(gid, oid, table, n_packets=2500, seed=81, obs_phase=ph, contrib=1, graph=graph)
+        ref = O.solve_emission(grid, table, O.Params(n_packets=2500, seed=81, obs_phase=tuple(ph)), contrib=True)
+        np.testing.assert_allclose(got["cf"], ref.extra["cf"], rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL)
+    assert got["cf"][:, :, 1].sum() > 0.0 and got["cf"][:, :, 0].sum() > 0.0
+    sph = I.make_sphere(12, 6, 8, seed=33)
+    _, t2, _ = I.make_emission_3d(12, 6, 8, nband=2, ng=2)
+    t2.k_ray = t2.k_ray * 1e3
+    sid, soid = ctx.upload_grid(sph), ctx.upload_opacity(t2)
+    got = ctx.solve_albedo(sid, soid, t2, n_packets=3000, seed=83, obs_phase=[0.0, 1.2], contrib=1,
+                           precision=M.MCRT_FP64)
+    ref = O.solve_albedo(sph, t2, O.Params(n_packets=3000, seed=83, obs_phase=(0.0, 1.2)), contrib=True)
+    np.testing.assert_allclose(got["cf"], ref.extra["cf"], rtol=1e-9, atol=1e-13)
+    assert np.all(got["cf"][:, :, 0] == 0.0)
+    # mixed precision: still a normalised function close to the FP64 one
+    mix = ctx.solve_albedo(sid, soid, t2, n_packets=3000, seed=83, obs_phase=[0.0, 1.2], contrib=1,
+                           precision=M.MCRT_MIXED)
+    np.testing.assert_allclose(mix["cf"].sum(axis=(2, 3)), 1.0, rtol=1e-12)
+    assert np.abs(mix["cf"] - got["cf"]).max() < 1e-3
+    # not available for transmission, served requests or multi-grid batches
+    with pytest.raises(M.McrtError) as e:
+        ctx.solve_transmission(gid, oid, table, n_b=8, n_alpha=8, contrib=1)
+    assert e.value.name == "EINVAL"
+    with pytest.raises(M.McrtError) as e:
+        ctx.submit("emission", gid, oid, table, n_packets=100, obs_phase=[0.5], contrib=1)
+    assert e.value.name == "EINVAL"
+    for x in (gid, sid):
+        ctx.free_grid(x)
+    for x in (oid, soid):
+        ctx.free_opacity(x)
