@@ -666,23 +666,55 @@ static double peel_tau(const orc_grid *g, const orc_optics *op, const orc_ray *s
     }
 }
 
-/* Contribution-function tally (Sect. "Albedo and emission contribution
- * functions"): every peel-off f is also added to the cell of the event that
- * produced it, split into the thermal part (emission points) and the
- * scattered part (interactions): cf[(o * 2 + part) * ncell + cell].        */
-static void cf_add(double *cf, int64_t ncell, int o, int part, int64_t cell, double f)
+/* Per-event tallies besides the packet's peel-off sums (NULL members are
+ * skipped):
+ * - contribution functions (Sect. "Albedo and emission contribution
+ *   functions"): every peel-off f is also added to the cell of the event that
+ *   produced it, split into the thermal part (emission points) and the
+ *   scattered part (interactions): cf[(o * 2 + part) * ncell + cell];
+ * - images (Sect. 2, images from the peel-offs): f is added to the pixel of
+ *   the event point projected on the sky plane of observer o, whose
+ *   horizontal and vertical unit vectors are axes[o][0], axes[o][1]; pixels
+ *   cover [-half, half]^2: img[(o * npix + row) * npix + column].          */
+typedef struct {
+    double *cf;
+    double *img;
+    int64_t npix;
+    double half;
+    const double *axes;
+} orc_tally;
+
+static int64_t pixel_of(double x, double half, int64_t npix)
 {
-    if (!cf) return;
+    int64_t q = (int64_t)floor((x + half) / (2.0 * half) * (double)npix);
+    return q < 0 ? 0 : (q >= npix ? npix - 1 : q);
+}
+
+static void tally_add(const orc_tally *tl, int64_t ncell, int o, int part, int64_t cell, const double p[3],
+                      double f)
+{
+    if (!tl) return;
+    if (tl->cf) {
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
-    cf[((int64_t)o * 2 + part) * ncell + cell] += f;
+        tl->cf[((int64_t)o * 2 + part) * ncell + cell] += f;
+    }
+    if (tl->img) {
+        const double *eh = tl->axes + 6 * o, *ev = eh + 3;
+        int64_t col = pixel_of(p[0] * eh[0] + p[1] * eh[1] + p[2] * eh[2], tl->half, tl->npix);
+        int64_t row = pixel_of(p[0] * ev[0] + p[1] * ev[1] + p[2] * ev[2], tl->half, tl->npix);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+        tl->img[((int64_t)o * tl->npix + row) * tl->npix + col] += f;
+    }
 }
 
 /* One packet history.  F[o] receives its peel-off sum per observer. */
 static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params *pr,
                        const double *obs, const double *cdf, const double *wbirth, int64_t ncell,
-                       double r_toa, uint64_t pid, double *F, double *K, double *cf)
+                       double r_toa, uint64_t pid, double *F, double *K, const orc_tally *tl)
 {
     uint32_t tag = (uint32_t)pr->tag;
     int nobs = (int)pr->n_obs;
@@ -758,7 +790,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             double tau = peel_tau(g, op, &ry, obs + 3 * o, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = W * exp(-tau) / (4.0 * ORC_PI);
             F[o] = F[o] + f;
-            cf_add(cf, ncell, o, 0, c, f);
+            tally_add(tl, ncell, o, 0, c, ry.p, f);
         }
     }
     W0 = W;
@@ -790,7 +822,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
             F[o] = F[o] + f;
-            cf_add(cf, ncell, o, 1, c, f);
+            tally_add(tl, ncell, o, 1, c, ry.p, f);
         }
         if (!cont) {
             K[K_ABS] += W * (1.0 - om);
@@ -819,11 +851,11 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
 }
 
 /* Run n_packets histories.  F_out[n][nout], K_out[n][NK] per packet (the
- * caller sums them in packet order).  obs: n_obs unit vectors.  cf (may be
- * NULL): per-cell peel-off tallies [nout][2][ncell], added to.            */
+ * caller sums them in packet order).  obs: n_obs unit vectors.  tl (may be
+ * NULL): per-event tallies, added to.                                      */
 int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params *pr,
                       const double *obs, const double *cdf, const double *wbirth, double r_toa,
-                      double *F_out, double *K_out, double *cf, int64_t nthreads)
+                      double *F_out, double *K_out, const orc_tally *tl, int64_t nthreads)
 {
     int64_t ncell = g->nlon * g->nlat * g->nlay;
     int nout = (g->geom == 1 && pr->n_obs == 0) ? 1 : (int)pr->n_obs;
@@ -834,7 +866,7 @@ int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params 
 #endif
     for (int64_t q = 0; q < n; ++q) {
         run_packet(g, op, pr, obs, cdf, wbirth, ncell, r_toa, pr->packet0 + (uint64_t)q,
-                   F_out + q * nout, K_out + q * NK, cf);
+                   F_out + q * nout, K_out + q * NK, tl);
     }
     return nout;
 }

@@ -62,6 +62,11 @@ class _Optics(ctypes.Structure):
                 ("p_gas", ctypes.c_void_p), ("g_cld", ctypes.c_void_p)]
 
 
+class _Tally(ctypes.Structure):
+    _fields_ = [("cf", ctypes.c_void_p), ("img", ctypes.c_void_p), ("npix", ctypes.c_int64),
+                ("half", ctypes.c_double), ("axes", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -97,7 +102,8 @@ def lib():
                                            vp, vp, vp, vp]
         L.orc_emission_sources.restype = dbl
         L.orc_transport.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Optics),
-                                    ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp, vp, i64]
+                                    ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp,
+                                    ctypes.POINTER(_Tally), i64]
         L.orc_transport.restype = i64
         L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
                                        vp, vp, i64]
@@ -296,12 +302,33 @@ def emission_obs_dirs(phases):
     return np.array(out, dtype=np.float64).reshape(-1, 3)
 
 
+def image_axes(obs) -> np.ndarray:
+    """Sky-plane axes per observer o: vertical e_v = the projection of the
+    rotation axis z (x if o is along z), horizontal e_h = e_v x o, so that
+    (e_h, e_v, o) is right-handed.  Returns [n_obs, 2, 3]."""
+    out = []
+    for o in np.asarray(obs, dtype=np.float64).reshape(-1, 3):
+        ref = np.array([0.0, 0.0, 1.0])
+        v = ref - (ref @ o) * o
+        if np.linalg.norm(v) < 1e-12:
+            ref = np.array([1.0, 0.0, 0.0])
+            v = ref - (ref @ o) * o
+        v = v / np.linalg.norm(v)
+        h = np.cross(v, o)
+        out.append([h, v])
+    return np.array(out)
+
+
 def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.ndarray],
-              sources: Optional[Sources] = None, tag: int = 0, cf: Optional[np.ndarray] = None):
+              sources: Optional[Sources] = None, tag: int = 0, cf: Optional[np.ndarray] = None,
+              img: Optional[np.ndarray] = None):
     """Run params.n_packets histories; returns per-packet F [n, nout] and
     counters K [n, NK].  cf: optional float64 array [nout, 2, ncell] to which
     every peel-off f is added at the cell of its event, thermal (emission
-    point, index 0) or scattered (interaction, index 1)."""
+    point, index 0) or scattered (interaction, index 1).  img: optional
+    float64 array [nout, npix, npix] to which f is added at the pixel of the
+    event point on the observer's sky plane (image_axes), rows along e_v and
+    columns along e_h, covering [-R_TOA, R_TOA]^2."""
     gv = GridView(grid)
     nobs = 0 if obs is None else len(obs)
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
@@ -315,10 +342,21 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     o = None if obs is None else _f64(obs)
     cdf = None if sources is None else sources.cdf
     wb = None if sources is None else sources.wbirth
-    if cf is not None:
-        assert cf.dtype == np.float64 and cf.flags.c_contiguous and cf.shape == (max(nout, 1), 2, grid.ncell)
+    tl = None
+    axes = None
+    if cf is not None or img is not None:
+        npix = 0
+        if cf is not None:
+            assert cf.dtype == np.float64 and cf.flags.c_contiguous and cf.shape == (max(nout, 1), 2, grid.ncell)
+        if img is not None:
+            assert grid.geometry == 0 and obs is not None
+            npix = img.shape[1]
+            assert img.dtype == np.float64 and img.flags.c_contiguous and img.shape == (nout, npix, npix)
+            axes = np.ascontiguousarray(image_axes(obs))
+        tl = _Tally(_p(cf), _p(img), npix, float(grid.r_toa), _p(axes))
     lib().orc_transport(ctypes.byref(gv.c), ctypes.byref(op), ctypes.byref(pr), _p(o), _p(cdf), _p(wb),
-                        float(grid.r_toa), F.ctypes.data, K.ctypes.data, _p(cf), int(params.threads))
+                        float(grid.r_toa), F.ctypes.data, K.ctypes.data,
+                        None if tl is None else ctypes.byref(tl), int(params.threads))
     return F[:, :nout], K
 
 
@@ -359,7 +397,18 @@ def contribution_function(cf_g, scale_g, w_g):
     return out
 
 
-def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False) -> Result:
+def band_image(img_g, scale_g, w_g):
+    """Band image: the per-pixel peel-off tallies of every g-ordinate, scaled
+    as their spectrum values are and weighted by w_g; its pixels add up to the
+    band value.  img_g: [ng, nout, npix, npix]."""
+    acc = np.zeros(img_g.shape[1:])
+    for g in range(img_g.shape[0]):
+        acc += w_g[g] * scale_g[g] * img_g[g]
+    return acc
+
+
+def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False,
+                 image_npix=0) -> Result:
     specs = _spec_list(table, spec_idx)
     ng = table.ng
     if grid.geometry == 1:
@@ -374,13 +423,14 @@ def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False,
     se_g = np.zeros_like(per_g)
     packets = {}
     w = np.asarray(table.g_weights, dtype=np.float64)
-    cfs = []
+    cfs, imgs = [], []
     for si, b in enumerate(specs):
         cf_g = np.zeros((ng, nout, 2, grid.ncell)) if contrib else None
+        im_g = np.zeros((ng, nout, image_npix, image_npix)) if image_npix else None
         for g in range(ng):
             op = ck_optics(grid, table, b, g)
             F, K = transport(grid, op, params, 0, obs, tag=_tag(params, b, g, ng),
-                             cf=cf_g[g] if contrib else None)
+                             cf=cf_g[g] if contrib else None, img=im_g[g] if image_npix else None)
             if keep_packets:
                 packets[(si, g)] = (F, K)
             sums[si, g, :, 0] = F.sum(axis=0)
@@ -392,15 +442,20 @@ def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False,
             se_g[si, g] = math.pi * np.sqrt(var)
         if contrib:
             cfs.append(contribution_function(cf_g, np.full(ng, math.pi / N), w))
+        if image_npix:
+            imgs.append(band_image(im_g, np.full(ng, math.pi / N), w))
     value = np.einsum("g,sgo->so", w, per_g)
     stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
     extra = {"packets": packets}
     if contrib:
         extra["cf"] = np.array(cfs)
+    if image_npix:
+        extra["image"] = np.array(imgs)
     return Result(value, stderr, per_g, sums, cnt, extra)
 
 
-def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False) -> Result:
+def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False,
+                   image_npix=0) -> Result:
     """Correlated-k emission spectrum F_p(band, phase) [erg/s/cm^2/cm]."""
     specs = _spec_list(table, spec_idx)
     ng = table.ng
@@ -415,16 +470,17 @@ def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=Fals
     packets = {}
     rt2 = grid.r_toa ** 2
     w = np.asarray(table.g_weights, dtype=np.float64)
-    cfs = []
+    cfs, imgs = [], []
     for si, b in enumerate(specs):
         cf_g = np.zeros((ng, nout, 2, grid.ncell)) if contrib else None
+        im_g = np.zeros((ng, nout, image_npix, image_npix)) if image_npix else None
         for g in range(ng):
             op = ck_optics(grid, table, b, g)
             src = emission_sources(grid, op, table.lam_um[b], params.tau_vert_max, params.emis_bias)
             ltot[si, g] = src.L_tot
             if src.L_tot > 0.0:
                 F, K = transport(grid, op, params, 1, obs, sources=src, tag=_tag(params, b, g, ng),
-                                 cf=cf_g[g] if contrib else None)
+                                 cf=cf_g[g] if contrib else None, img=im_g[g] if image_npix else None)
             else:
                 F, K = np.zeros((N, nout)), np.zeros((N, NK))
             if keep_packets:
@@ -439,11 +495,15 @@ def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=Fals
             se_g[si, g] = src.L_tot * np.sqrt(var) / rt2
         if contrib:
             cfs.append(contribution_function(cf_g, ltot[si] / (N * rt2), w))
+        if image_npix:
+            imgs.append(band_image(im_g, ltot[si] / (N * rt2), w))
     value = np.einsum("g,sgo->so", w, per_g)
     stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
     extra = {"packets": packets, "L_tot": ltot}
     if contrib:
         extra["cf"] = np.array(cfs)
+    if image_npix:
+        extra["image"] = np.array(imgs)
     return Result(value, stderr, per_g, sums, cnt, extra)
 
 

@@ -9,7 +9,10 @@ functions"):
   every cell that the planet's shadow does not cut against a deterministic
   volume quadrature of (L_c/L_tot) <e^{-tau(r -> observer)}> / 4 pi, with the
   expected Monte Carlo spread from the same quadrature;
-- the band functions add up to 1 per observer and reproduce the spectrum.
+- the band functions add up to 1 per observer and reproduce the spectrum;
+- images: an isothermal pure-absorption planet against pixel integrals of
+  the closed-form B (1 - e^{-tau(b)}), and the orientation of the sky-plane
+  axes with a single warm cell.
 """
 import math
 
@@ -141,3 +144,102 @@ def test_band_function_sums_and_reproduces_the_spectrum():
     ra = O.solve_albedo(grid, table, O.Params(n_packets=3000, seed=26, obs_phase=(0.0, 1.0)), contrib=True)
     assert np.all(ra.extra["cf"][:, :, 0] == 0.0)
     np.testing.assert_allclose(ra.extra["cf"].sum(axis=(2, 3)), 1.0, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ images
+def _iso_grid():
+    import closed_forms as CF  # noqa: F401  (shell sums below)
+    g = I.make_sphere(16, 8, 10, seed=27)
+    g.T = np.full(g.ncell, 1300.0, np.float32)
+    alpha = 2e-8 * np.exp(-np.arange(10) / 2.0)
+    g.rho = np.repeat(alpha, g.nlon * g.nlat)
+    tab = I.CKTable(np.array([2.0]), np.ones(1), np.array([1000.0]), np.array([1.0]),
+                    np.ones((1, 1, 1, 1), np.float32), np.zeros(1))
+    return g, tab, alpha
+
+
+def test_isothermal_image_against_pixel_integrals():
+    """Pure absorption, isothermal, spherically symmetric extinction: pixel
+    (row, col) of the image holds (1/R_TOA^2) int_pixel B (1 - e^{-tau(b)}) dA,
+    tau the optical depth of the ray at impact distance b in front of the
+    absorbing surface (closed-form shell sums), integrated by sub-sampling."""
+    import closed_forms as CF
+    g, tab, alpha = _iso_grid()
+    npix, nb, nper = 10, 8, 40_000
+    B = O.planck(2.0e-4, 1300.0)
+    imgs = []
+    for q in range(nb):  # independent packet ranges give the pixel spread
+        p = O.Params(n_packets=nper, packet0=q * nper, seed=29, scattering=False, tau_vert_max=1e300,
+                     obs_phase=(0.13,))
+        imgs.append(O.solve_emission(g, tab, p, image_npix=npix).extra["image"][0, 0])
+    imgs = np.array(imgs)
+    got, se = imgs.mean(axis=0), imgs.std(axis=0, ddof=1) / math.sqrt(nb)
+    R, r0 = g.r_toa, g.r_edges[0]
+    m = 24
+    want = np.zeros((npix, npix))
+    w = 2.0 * R / npix
+    for row in range(npix):
+        for col in range(npix):
+            us = -R + (col + (np.arange(m) + 0.5) / m) * w
+            vs = -R + (row + (np.arange(m) + 0.5) / m) * w
+            acc = 0.0
+            for u in us:
+                for v in vs:
+                    b = math.hypot(u, v)
+                    if b >= R:
+                        continue
+                    t = CF.chord_tau(b, g.r_edges, alpha) if b >= r0 else CF.surface_ray_tau(b, g.r_edges, alpha)
+                    acc += 1.0 - math.exp(-t)
+            want[row, col] = B * acc / (m * m) * w * w / R ** 2
+    # the disk edge cuts some pixels: allow the sub-sampling error there
+    edge = np.zeros_like(want, dtype=bool)
+    for row in range(npix):
+        for col in range(npix):
+            cu = np.array([-R + col * w, -R + (col + 1) * w])
+            cv = np.array([-R + row * w, -R + (row + 1) * w])
+            bmin = math.hypot(max(0.0, abs(cu).min()) if cu[0] * cu[1] > 0 else 0.0,
+                              max(0.0, abs(cv).min()) if cv[0] * cv[1] > 0 else 0.0)
+            bmax = math.hypot(abs(cu).max(), abs(cv).max())
+            edge[row, col] = bmin < R < bmax
+    tol = 4.5 * se + np.where(edge, 0.02, 2e-3) * want + 1e-12 * want.max()
+    bad = np.abs(got - want) > tol
+    assert not bad.any(), (np.argwhere(bad)[:4].tolist(), got[bad][:4], want[bad][:4], se[bad][:4])
+    np.testing.assert_allclose(got.sum(), want.sum(), rtol=5e-3)
+
+
+def test_image_orientation_single_emitting_cell():
+    """Only one cell is warm and the atmosphere is optically thin: the image
+    falls inside the bounding box of that cell's corners projected on the
+    observer's sky-plane axes (rows along e_v, columns along e_h)."""
+    g = I.make_sphere(16, 8, 6, seed=41)
+    hot = (3 * g.nlat + 6) * g.nlon + 5  # k = 3, j = 6 (northern), i = 5
+    g.T = np.full(g.ncell, 30.0, np.float32)
+    g.T[hot] = 1500.0
+    g.rho = np.full(g.ncell, 1e-12)
+    tab = I.CKTable(np.array([2.0]), np.ones(1), np.array([1000.0]), np.array([1.0]),
+                    np.ones((1, 1, 1, 1), np.float32), np.zeros(1))
+    npix = 32
+    phases = (0.37, 0.81)
+    p = O.Params(n_packets=20_000, seed=31, scattering=False, tau_vert_max=1e300, obs_phase=phases)
+    r = O.solve_emission(g, tab, p, image_npix=npix)
+    img = r.extra["image"][0]
+    axes = O.image_axes(O.emission_obs_dirs(phases))
+    k, j, i = 3, 6, 5
+    corners = []
+    for rr in g.r_edges[k:k + 2]:
+        for la in np.linspace(g.lat_edges[j], g.lat_edges[j + 1], 5):
+            for lo in np.linspace(g.lon_edges[i], g.lon_edges[i + 1], 5):
+                corners.append([rr * math.cos(la) * math.cos(lo), rr * math.cos(la) * math.sin(lo), rr * math.sin(la)])
+    corners = np.array(corners)
+    R = g.r_toa
+    for o in range(len(phases)):
+        eh, ev = axes[o]
+        u, v = corners @ eh, corners @ ev
+        c0 = int(math.floor((u.min() + R) / (2 * R) * npix)) - 1
+        c1 = int(math.floor((u.max() + R) / (2 * R) * npix)) + 1
+        r0_ = int(math.floor((v.min() + R) / (2 * R) * npix)) - 1
+        r1_ = int(math.floor((v.max() + R) / (2 * R) * npix)) + 1
+        inside = img[o, max(r0_, 0):r1_ + 1, max(c0, 0):c1 + 1].sum()
+        assert img[o].sum() > 0.0
+        assert inside >= (1.0 - 1e-12) * img[o].sum(), (o, inside / img[o].sum())
+        np.testing.assert_allclose(img[o].sum(), r.value[0, o], rtol=1e-12)
