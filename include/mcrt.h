@@ -184,7 +184,10 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   grid or table when it is freed.  Ignored by transmission and served
  *   requests.
  * contrib: mcrt_solve_albedo / mcrt_solve_emission only (EINVAL elsewhere):
- *   non-zero also fills mcrt_result.cf with the contribution functions. */
+ *   non-zero also fills mcrt_result.cf with the contribution functions.
+ * image_npix: the same solves on a spherical grid: > 0 also fills
+ *   mcrt_result.image with npix x npix images per band and observer
+ *   (at most 4096). */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -216,6 +219,7 @@ typedef struct {
     int32_t tune_wave_batch;
     int32_t graph;
     int32_t contrib;
+    int32_t image_npix;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);
@@ -239,7 +243,14 @@ void mcrt_default_params(mcrt_solve_params* p);
  *   peel-offs from events in each cell, [0] thermal (emission points) and
  *   [1] scattered (interactions); each (band, observer) block sums to 1, or is
  *   0 where the value is 0.  Cells are ordered as the grid's.  Tallied with
- *   FP64 atomics, so the last bits vary from run to run. */
+ *   FP64 atomics, so the last bits vary from run to run.
+ * image[n_spec][n_obs][npix][npix] (with params.image_npix = npix): every
+ *   peel-off added, scaled as the band value, to the pixel of its event point
+ *   on the observer's sky plane; the pixels of a (band, observer) add up to
+ *   its value.  Row index along the vertical axis e_v = the rotation axis z
+ *   projected on the sky plane (x when the observer looks along z), column
+ *   index along e_h = e_v x o; pixels cover [-R_TOA, R_TOA]^2 from the
+ *   negative end.  FP64 atomics, as cf. */
 typedef struct {
     double* value;
     double* stderr_;
@@ -253,6 +264,7 @@ typedef struct {
     double queued_ms;
     double latency_ms;
     double* cf;
+    double* image;
 } mcrt_result;
 
 /* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /

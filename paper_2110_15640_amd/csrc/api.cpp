@@ -547,6 +547,26 @@ int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve)
     return std::max(1, std::min(std::min(batch, fit), nsolve));
 }
 
+// Sky-plane axes of observer o for images: vertical e_v = z projected on the
+// plane normal to o (x when o is along z), horizontal e_h = e_v x o.
+void sky_axes(const double* o, double* out)
+{
+    double ref[3] = {0.0, 0.0, 1.0};
+    double v[3];
+    for (int pass = 0; pass < 2; ++pass) {
+        const double d = ref[0] * o[0] + ref[1] * o[1] + ref[2] * o[2];
+        for (int q = 0; q < 3; ++q) v[q] = ref[q] - d * o[q];
+        if (std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) >= 1e-12) break;
+        ref[0] = 1.0; ref[1] = 0.0; ref[2] = 0.0;
+    }
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int q = 0; q < 3; ++q) v[q] /= n;
+    out[0] = v[1] * o[2] - v[2] * o[1];
+    out[1] = v[2] * o[0] - v[0] * o[2];
+    out[2] = v[0] * o[1] - v[1] * o[0];
+    out[3] = v[0]; out[4] = v[1]; out[5] = v[2];
+}
+
 // Albedo and emission.  The (spec, g) solves are grouped into batches; per
 // batch every solve gets its own optics (and emission CDF) slot, then one
 // persistent transport launch runs all their packets and a fixed-order
@@ -570,9 +590,12 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     if (p->max_batch < 0 || p->tune_ev_threshold < 0 || p->tune_ev_threshold > 64 || p->tune_blocks_per_cu < 0 ||
         p->tune_blocks_per_cu > 16 || p->tune_wave_batch < 0)
         return fail(MCRT_EINVAL, "bad batching / tuning parameters");
-    if (p->contrib && sl.stream_ordered)
-        return fail(MCRT_EINVAL, "contribution functions are computed by blocking solves only");
+    if ((p->contrib || p->image_npix) && sl.stream_ordered)
+        return fail(MCRT_EINVAL, "contribution functions and images are computed by blocking solves only");
     if (p->contrib && !res->cf) return fail(MCRT_EINVAL, "contrib needs result.cf");
+    if (p->image_npix < 0 || p->image_npix > 4096) return fail(MCRT_EINVAL, "image_npix must be in [0, 4096]");
+    if (p->image_npix && (!res->image || g->dev.geom != 0))
+        return fail(MCRT_EINVAL, "images need result.image and a spherical grid");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const bool mixed = p->precision == MCRT_MIXED;
@@ -625,6 +648,10 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     void* v_cf = nullptr;  // contribution functions [spec][observer][2][cell]
     const size_t cf_n = p->contrib ? (size_t)ns * no * 2 * ncell : 0;
     if (p->contrib && (rc = scratch(ctx, sl, st, "contrib", sizeof(double) * cf_n, &v_cf))) return rc;
+    void* v_img = nullptr;  // images [spec][observer][row][column]
+    const int npix = p->image_npix;
+    const size_t img_n = (size_t)ns * no * npix * npix;
+    if (npix && (rc = scratch(ctx, sl, st, "image", sizeof(double) * img_n, &v_img))) return rc;
     double* sums = (double*)v_sums;
 
     BatchArgs A{};
@@ -647,6 +674,11 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
+    if (npix) {
+        A.npix = npix;
+        A.img_half = g->r_toa;
+        for (int o = 0; o < pl.n_obs; ++o) sky_axes(&pl.obs[3 * o], &A.img_axes[6 * o]);
+    }
 
     const bool use_graph = p->graph != 0 && !sl.stream_ordered;
     const bool prof = p->profile != 0 && !use_graph;
@@ -668,13 +700,14 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         const double dpar[7] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
                                 p->mu0, (double)p->max_events};
         add(dpar, sizeof dpar);
-        const int64_t ipar[10] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
-                                  p->absorption, batch, A.ev_threshold, bpc, A.batch};
+        const int64_t ipar[11] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+                                  p->absorption, batch, A.ev_threshold, bpc, A.batch, npix};
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
-        const void* ptrs[15] = {p->packet_dump, st, v_opt, v_optf, v_src, v_rows, v_sums, v_part,
-                                v_solves, v_slots, v_ctr, v_ps, v_shift, v_cf, (const void*)(uintptr_t)pl.n_obs};
+        const void* ptrs[16] = {p->packet_dump, st, v_opt, v_optf, v_src, v_rows, v_sums, v_part,
+                                v_solves, v_slots, v_ctr, v_ps, v_shift, v_cf, v_img,
+                                (const void*)(uintptr_t)pl.n_obs};
         add(ptrs, sizeof ptrs);
         std::lock_guard<std::mutex> gk(ctx->graph_mu);
         auto it = ctx->graphs.find(gkey);
@@ -707,6 +740,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     auto enqueue = [&]() -> int {
         launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
         if (v_cf) launch_fill_f64((double*)v_cf, cf_n, 0.0, st);
+        if (v_img) launch_fill_f64((double*)v_img, img_n, 0.0, st);
         if (op->kind == MCRT_OPAC_HIRES)
             launch_doppler_shift(g->dev, pl.obs[0], pl.obs[1], pl.obs[2], op->dlnlam, (double*)v_shift, st);
         for (int bt = 0; bt < nbatches; ++bt) {
@@ -746,9 +780,10 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                 S.grid = 0;
                 S.cdf = P.cdf;
                 S.wbirth = P.wbirth;
-                if (v_cf) {  // scaled as the band value: w_g pi / N, or w_g L_tot / (N R_TOA^2)
+                if (v_cf || v_img) {  // scaled as the band value: w_g pi / N, or w_g L_tot / (N R_TOA^2)
                     const double wg = op->kind == MCRT_OPAC_CK ? op->g_weights[gi] : 1.0;
-                    S.cf = (double*)v_cf + (size_t)(sg / ng) * no * 2 * ncell;
+                    S.cf = v_cf ? (double*)v_cf + (size_t)(sg / ng) * no * 2 * ncell : nullptr;
+                    S.img = v_img ? (double*)v_img + (size_t)(sg / ng) * no * npix * npix : nullptr;
                     S.cf_w = mode == MCRT_MODE_ALBEDO ? wg * kPi / (double)N
                                                       : wg / ((double)N * g->r_toa * g->r_toa);
                     S.cf_ltot = mode == MCRT_MODE_EMISSION ? P.stats : nullptr;
@@ -847,6 +882,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             for (size_t c = 0; c < 2 * (size_t)ncell; ++c) blk[c] = tot > 0.0 ? blk[c] / tot : 0.0;
         }
     }
+    if (v_img) HIPTRY(hipMemcpy(res->image, v_img, sizeof(double) * img_n, hipMemcpyDeviceToHost));
     return MCRT_OK;
 }
 
@@ -864,7 +900,8 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     SolvePlan pl;
     rc = plan_common(def_stream, g, op, p, MCRT_MODE_TRANSMISSION, pl);
     if (rc) return rc;
-    if (p->contrib) return fail(MCRT_EINVAL, "contribution functions are defined for albedo and emission");
+    if (p->contrib || p->image_npix)
+        return fail(MCRT_EINVAL, "contribution functions and images are defined for albedo and emission");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const int ncell = g->ncell;
@@ -961,7 +998,8 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
                 const mcrt_solve_params* common, mcrt_result* results)
 {
     if (n_items < 1 || !items || !common || !results) return fail(MCRT_EINVAL, "batch needs items, params, results");
-    if (common->contrib) return fail(MCRT_EINVAL, "contribution functions are computed by single solves only");
+    if (common->contrib || common->image_npix)
+        return fail(MCRT_EINVAL, "contribution functions and images are computed by single solves only");
     struct Item {
         Lease ls;
         SolvePlan pl;
@@ -1348,7 +1386,8 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
 {
     if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION && mode != MCRT_MODE_TRANSMISSION)
         return fail(MCRT_EINVAL, "unknown mode %d", mode);
-    if (p->contrib) return fail(MCRT_EINVAL, "contribution functions are computed by blocking solves only");
+    if (p->contrib || p->image_npix)
+        return fail(MCRT_EINVAL, "contribution functions and images are computed by blocking solves only");
     std::unique_ptr<Request> r(new Request());
     r->mode = mode;
     r->gid = gid;
@@ -1758,6 +1797,8 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     t.packet_dump = nullptr;
     t.profile = 0;
     t.graph = 0;
+    t.contrib = 0;
+    t.image_npix = 0;
     const int evs[3] = {8, 16, 32}, bpcs[2] = {2, 4}, wbs[2] = {32, 128};
     double best = -1.0;
     int be = 16, bb = 4, bw = 64;

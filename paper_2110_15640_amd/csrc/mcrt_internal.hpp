@@ -62,9 +62,11 @@ struct SolveDev {
     uint32_t tag;
     int mode;  // 0 albedo, 1 emission
     int grid;  // index into BatchArgs.grids (multi-grid launches)
-    // contribution functions (or null): every peel-off f also adds
-    // f * cf_w * (*cf_ltot if set) to cf[(observer * 2 + part) * ncell + cell]
+    // per-event tallies, each scaled by cf_w * (*cf_ltot if set):
+    // contribution functions cf[(observer * 2 + part) * ncell + cell] and
+    // images img[(observer * npix + row) * npix + column] (null = off)
     double* cf;
+    double* img;
     double cf_w;
     const double* cf_ltot;
 };
@@ -91,6 +93,11 @@ struct BatchArgs {
     double obs[2][3 * kMaxObs];  // observer directions for albedo [0] and emission [1] solves
     int batch;         // packets a wave takes from the dispenser at once
     int ev_threshold;  // waiting lanes that trigger event handling
+    // images: npix x npix pixels over [-img_half, img_half]^2 of each
+    // observer's sky plane, horizontal / vertical unit vectors per observer
+    int npix;
+    double img_half;
+    double img_axes[6 * kMaxObs];
 };
 
 // One solve slot of a batched preparation.

@@ -300,6 +300,13 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
     return A_FLIGHT;
 }
 
+// Pixel of a sky-plane coordinate x on npix pixels over [-half, half].
+__device__ __forceinline__ int pixel_of(double x, double half, int npix)
+{
+    const int q = (int)floor((x + half) / (2.0 * half) * (double)npix);
+    return q < 0 ? 0 : (q >= npix ? npix - 1 : q);
+}
+
 // Bookkeeping of one event; returns the action that follows.  L.ev carries
 // the counter that receives the final weight when the action is A_FINISH.
 template <bool MIXED>
@@ -337,11 +344,20 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         }
         double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
         row[L.o()] = row[L.o()] + f;
-        if (S.cf && f > 0.0) {  // contribution function: the event's cell, thermal or scattered part
-            const int ncell = g.nlon * g.nlat * g.nlay;
-            const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
-            const double sc = S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w;
-            unsafeAtomicAdd(S.cf + ((size_t)L.o() * 2 + (L.birth() ? 0 : 1)) * ncell + c, f * sc);
+        if ((S.cf || S.img) && f > 0.0) {
+            const double sc = f * (S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w);
+            if (S.cf) {  // contribution function: the event's cell, thermal or scattered part
+                const int ncell = g.nlon * g.nlat * g.nlay;
+                const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
+                unsafeAtomicAdd(S.cf + ((size_t)L.o() * 2 + (L.birth() ? 0 : 1)) * ncell + c, sc);
+            }
+            if (S.img) {  // image: the event point on the observer's sky plane
+                const double* eh = A.img_axes + 6 * L.o();
+                const double u = L.sx() * eh[0] + L.sy() * eh[1] + L.sz() * eh[2];
+                const double v = L.sx() * eh[3] + L.sy() * eh[4] + L.sz() * eh[5];
+                const int col = pixel_of(u, A.img_half, A.npix), row = pixel_of(v, A.img_half, A.npix);
+                unsafeAtomicAdd(S.img + ((size_t)L.o() * A.npix + row) * A.npix + col, sc);
+            }
         }
         L.o() += 1;
         if (L.o() < A.n_out) return A_PEEL;

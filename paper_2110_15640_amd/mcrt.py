@@ -60,7 +60,7 @@ class SolveParams(ctypes.Structure):
                 ("n_b", _i32), ("n_alpha", _i32), ("r_star", _dbl), ("stream", _vp),
                 ("packet_dump", _vp), ("profile", _i32), ("max_batch", _i32),
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32),
-                ("graph", _i32), ("contrib", _i32)]
+                ("graph", _i32), ("contrib", _i32), ("image_npix", _i32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -71,7 +71,8 @@ class BatchItem(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
                 ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
-                ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl), ("cf", _vp)]
+                ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl), ("cf", _vp),
+                ("image", _vp)]
 
 
 _lib = None
@@ -242,7 +243,9 @@ class Context:
         no = n_out(p)
         out = self._alloc(ns, ng, no)
         if p.contrib:
-            out["cf"] = np.zeros((ns, no, 2, self._ncell[gid]))
+            out["cf"] = np.zeros((ns, no, 2, self._ncell.get(gid, 0)))
+        if p.image_npix > 0:
+            out["image"] = np.zeros((ns, no, p.image_npix, p.image_npix))
         r = self._result(out)
         _check(fn(self._h, gid, oid, ctypes.byref(p), ctypes.byref(r)))
         self._finish(out, r)
@@ -266,10 +269,11 @@ class Context:
 
     @staticmethod
     def _result(out):
-        cf = out.get("cf")
+        cf, im = out.get("cf"), out.get("image")
         return Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
                       out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data,
-                      0.0, 0.0, 0, 0.0, 0.0, None if cf is None else cf.ctypes.data)
+                      0.0, 0.0, 0, 0.0, 0.0, None if cf is None else cf.ctypes.data,
+                      None if im is None else im.ctypes.data)
 
     @staticmethod
     def _finish(out, r):

@@ -356,9 +356,10 @@ def test_graph_replays_equal_eager(ctx, torch_dev):
         ctx.free_opacity(x)
 
 
-def test_contribution_functions_parity(ctx, torch_dev):
+def test_contribution_functions_and_images_parity(ctx, torch_dev):
     """Per-cell contribution functions (thermal and scattered parts, per band
-    and observer) against the oracle on the same stream; albedo and emission."""
+    and observer) and sky-plane images against the oracle on the same stream;
+    albedo and emission, eager and graph-replayed."""
     _log("contribution functions: emission with clouds (16x8x10, 2 bands x 2 g, 3 phases), albedo sphere")
     from paper_2110_15640_amd import mcrt as M
     grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2)
@@ -368,10 +369,14 @@ def test_contribution_functions_parity(ctx, torch_dev):
     grid.cld_g = rng.uniform(-0.5, 0.9, grid.ncell).astype(np.float32)
     gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
     ph = list(phases[:3])
+    ref = O.solve_emission(grid, table, O.Params(n_packets=2500, seed=81, obs_phase=tuple(ph)), contrib=True,
+                           image_npix=24)
     for graph in (0, 1, 1):
-        got = ctx.solve_emission(gid, oid, table, n_packets=2500, seed=81, obs_phase=ph, contrib=1, graph=graph)
-        ref = O.solve_emission(grid, table, O.Params(n_packets=2500, seed=81, obs_phase=tuple(ph)), contrib=True)
+        got = ctx.solve_emission(gid, oid, table, n_packets=2500, seed=81, obs_phase=ph, contrib=1, graph=graph,
+                                 image_npix=24)
         np.testing.assert_allclose(got["cf"], ref.extra["cf"], rtol=1e-9, atol=1e-13)
+        im = ref.extra["image"]
+        np.testing.assert_allclose(got["image"], im, rtol=1e-9, atol=1e-12 * im.max())
         np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL)
     assert got["cf"][:, :, 1].sum() > 0.0 and got["cf"][:, :, 0].sum() > 0.0
     sph = I.make_sphere(12, 6, 8, seed=33)
@@ -379,9 +384,13 @@ def test_contribution_functions_parity(ctx, torch_dev):
     t2.k_ray = t2.k_ray * 1e3
     sid, soid = ctx.upload_grid(sph), ctx.upload_opacity(t2)
     got = ctx.solve_albedo(sid, soid, t2, n_packets=3000, seed=83, obs_phase=[0.0, 1.2], contrib=1,
-                           precision=M.MCRT_FP64)
-    ref = O.solve_albedo(sph, t2, O.Params(n_packets=3000, seed=83, obs_phase=(0.0, 1.2)), contrib=True)
+                           precision=M.MCRT_FP64, image_npix=17)
+    ref = O.solve_albedo(sph, t2, O.Params(n_packets=3000, seed=83, obs_phase=(0.0, 1.2)), contrib=True,
+                         image_npix=17)
     np.testing.assert_allclose(got["cf"], ref.extra["cf"], rtol=1e-9, atol=1e-13)
+    im = ref.extra["image"]
+    np.testing.assert_allclose(got["image"], im, rtol=1e-9, atol=1e-12 * im.max())
+    np.testing.assert_allclose(got["image"].sum(axis=(2, 3)), got["value"], rtol=1e-12)
     assert np.all(got["cf"][:, :, 0] == 0.0)
     # mixed precision: still a normalised function close to the FP64 one
     mix = ctx.solve_albedo(sid, soid, t2, n_packets=3000, seed=83, obs_phase=[0.0, 1.2], contrib=1,
