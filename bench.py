@@ -32,6 +32,12 @@ METRIC = "packets/s at 1e-3 rel. spectral error, plain vs batched; p50/p99 solve
 FLOP_PER_CROSSING = 110.0
 PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X
 PEAK_HBM = 8000.0  # GB/s
+# HBM traffic of the transport kernel from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
+# (band, g) solve of this workload; valid only for the kernel sources it was
+# measured on (hash below), else reported as null.
+TRAFFIC_KERNEL_SHA = "8dc5fba2b92e25af9d76c4db2f4ac668c4719aec70ec4e38ad5a9d9870d1ef2d"
+TRAFFIC_BYTES_PER_SOLVE = (396446717 * (1048576 / 524304) + 113689069 * 1.0) * 1024 / 168
 
 
 def parse():
@@ -47,17 +53,28 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--wave-batch", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-packets", type=int, default=3000)
+    ap.add_argument("--cpu-packets", type=int, default=10000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
     ap.add_argument("--albedo", type=int, default=1, help="also time the 1D albedo workload (plain / batched / graph)")
     ap.add_argument("--batch-scale", type=float, default=0.01,
                     help="packet scale of the 256-request multi-grid batch leg (0 = skip)")
-    ap.add_argument("--batch-plain", type=int, default=1, help="also time that batch in the plain FP64 form")
+    ap.add_argument("--batch-plain", type=int, default=16,
+                    help="time the first N requests of that batch in the plain FP64 form too (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="duration of the Poisson serving leg (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="run one 1 GiB device copy first (reference kernel for HBM counter scaling)")
     return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    """sha256 of the transport kernel's sources, concatenated in this order."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2110_15640_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("transport.hip", "device_common.hpp", "mcrt_internal.hpp"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
 
 
 def cpu_baseline(grid, table, phases, n_per):
@@ -157,22 +174,37 @@ def batch_leg(M, I, scale, plain, log):
         out.update({"solves": solves, "packets": packets, "batched_s": tb, "batched_packets_per_s": packets / tb,
                     "batched_transport_launches": int(sum(o["kernel_launches"] for o in bo[:1]))})
         if plain:
+            # plain FP64 (one launch per solve) against the batched form on the
+            # same subset of requests (the whole set would take minutes)
+            sub = items[:plain]
+            psolves = sum(len(it["spec_idx"]) * table.ng for it in sub)
+            ppk = sum(len(it["spec_idx"]) * table.ng * it["n_packets"] for it in sub)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bs = ctx.solve_batch(sub, precision=M.MCRT_MIXED, **common)
+            torch.cuda.synchronize()
+            tbs = time.perf_counter() - t0
             t0 = time.perf_counter()
             po = []
-            for it in items:
+            for q, it in enumerate(sub):
                 fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
                 po.append(fn(it["gid"], oid, table, spec_idx=it["spec_idx"], n_packets=it["n_packets"],
                              precision=M.MCRT_FP64, max_batch=1, **common))
+                if q % 4 == 3:
+                    log(f"[bench]   plain: {q + 1}/{len(sub)} requests")
             torch.cuda.synchronize()
             tp = time.perf_counter() - t0
-            log(f"[bench]   plain: {tp:.2f} s")
+            log(f"[bench]   subset of {len(sub)} requests ({psolves} solves): plain {tp:.2f} s, batched {tbs:.2f} s")
             d = np.concatenate([(np.abs(b["value"] - a["value"]) / np.maximum(np.abs(a["value"]), 1e-300)).ravel()
-                                for a, b in zip(po, bo)])
+                                for a, b in zip(po, bs)])
             z = np.concatenate([(np.abs(b["value"] - a["value"]) / np.maximum(a["stderr"], 1e-300)).ravel()
-                                for a, b in zip(po, bo)])
-            out.update({"plain_s": tp, "plain_packets_per_s": packets / tp, "batched_over_plain": tp / tb,
-                        "mixed_vs_fp64_rel_median": float(np.median(d)), "mixed_vs_fp64_rel_p99": float(np.quantile(d, 0.99)),
-                        "mixed_vs_fp64_sigma_max": float(z.max())})
+                                for a, b in zip(po, bs)])
+            out["subset"] = {"requests": len(sub), "solves": psolves, "packets": ppk,
+                             "plain_s": tp, "plain_packets_per_s": ppk / tp,
+                             "batched_s": tbs, "batched_packets_per_s": ppk / tbs, "batched_over_plain": tp / tbs,
+                             "mixed_vs_fp64_rel_median": float(np.median(d)),
+                             "mixed_vs_fp64_rel_p99": float(np.quantile(d, 0.99)),
+                             "mixed_vs_fp64_sigma_max": float(z.max())}
         rel = np.concatenate([(o["stderr"] / np.maximum(np.abs(o["value"]), 1e-300)).ravel() for o in bo])
         out["rel_se_median"] = float(np.median(rel))
     return out
@@ -252,6 +284,8 @@ def main():
     bres, bwall = run_form(ctx, M, gid, oid, table, bands, npk, phases, M.MCRT_MIXED, 0, a.steps, a.warmup, tune)
     value, rel, need, cross, kms, launches = summarize(bres, bwall, a.steps, pk_step, npk, table.ng)
     ach = cross * FLOP_PER_CROSSING / (kms * 1e-3) / 1e12
+    solves_per_launch = len(bands) * table.ng * a.steps / max(launches, 1)
+    traffic = TRAFFIC_BYTES_PER_SOLVE * solves_per_launch if kernel_sha() == TRAFFIC_KERNEL_SHA else None
     out = {
         "metric": METRIC, "value": value, "unit": "packets/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": bwall / a.steps * 1e3, "higher_is_better": True,
@@ -266,9 +300,10 @@ def main():
                   "packets_per_band_for_1e-3_median": float(np.median(need)),
                   "seconds_per_band_for_1e-3_median_batched": float(np.median(need)) / value},
         "roofline": {"bound": "alu", "kernel": "k_transport_persistent<MIXED>", "achieved": ach,
-                     "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR, "traffic": None,
-                     "avg_launch_ms": kms / max(launches, 1), "launches": launches,
-                     "flop_per_crossing": FLOP_PER_CROSSING},
+                     "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "avg_launch_ms": kms / max(launches, 1), "launches": launches,
+                     "solves_per_launch": solves_per_launch, "flop_per_crossing": FLOP_PER_CROSSING,
+                     "traffic_GBps": None if traffic is None else traffic / (kms / max(launches, 1) * 1e-3) / 1e9},
     }
     if pres is not None:
         # spectrum difference of the mixed form from the FP64 form on the same random stream

@@ -75,9 +75,10 @@ def test_emission_3d_full_size_sampled(ctx, torch_dev):
     _log(f"full size: 3D emission {grid.nlon}x{grid.nlat}x{grid.nlay}, {ns} solves x 1e6 packets, FP64 batched")
     dump = torch_dev.zeros(ns * n * 4, dtype=torch_dev.float64, device="cuda:0")
     gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
-    kw = dict(n_packets=n, seed=BENCH_SEED, obs_phase=list(phases), spec_idx=bands, max_batch=0)
+    kw = dict(n_packets=n, seed=BENCH_SEED, obs_phase=list(phases), spec_idx=bands, max_batch=0, profile=1)
     got = ctx.solve_emission(gid, oid, table, precision=M.MCRT_FP64, packet_dump=dump, **kw)
     assert got["kernel_launches"] >= 1
+    _log(f"  FP64: {got['elapsed_ms']:.0f} ms, {got['kernel_launches']} transport launch(es)")
     d = dump.view(ns, n, 4)
     rng = np.random.default_rng(11)
     solves = rng.choice(ns, size=10, replace=False)
