@@ -271,6 +271,8 @@ int validate_grid(const mcrt_grid_desc* d)
         return fail(MCRT_EINVAL, "unknown geometry %d", d->geometry);
     if (d->nlay < 1 || d->nlon < 1 || d->nlat < 1) return fail(MCRT_EINVAL, "grid dimensions must be >= 1");
     if ((long long)d->nlon * d->nlat * d->nlay > (1LL << 31) - 1) return fail(MCRT_EINVAL, "grid too large");
+    if (d->nlon > 2048 || d->nlat > 1024 || d->nlay > 2048)
+        return fail(MCRT_EINVAL, "grid dimensions are limited to 2048 x 1024 x 2048 (lon x lat x layers)");
     if (!d->r_edges || !d->T || !d->P || !d->rho) return fail(MCRT_EINVAL, "r_edges, T, P and rho are required");
     if (!finite_all(d->r_edges, d->nlay + 1) || !increasing(d->r_edges, d->nlay + 1))
         return fail(MCRT_EINVAL, "r_edges must be finite and strictly increasing");
@@ -626,6 +628,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
         batch = std::max(1, std::min(std::min(batch, fit), nsolve));
     }
+    batch = std::min(batch, kMaxSolvesPerLaunch);
     const int chunks = reduce_rows_chunks(N);
     void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_ps = nullptr,
                  *v_shift = nullptr, *v_solves, *v_slots, *v_ctr;
@@ -1067,7 +1070,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     for (int s0 = 0; s0 < nsolve;) {
         uint64_t acc = 0;
         int s1 = s0;
-        while (s1 < nsolve && (s1 == s0 || acc + fl[s1].bytes <= cap) &&
+        while (s1 < nsolve && (s1 == s0 || acc + fl[s1].bytes <= cap) && s1 - s0 < kMaxSolvesPerLaunch &&
                (common->max_batch <= 0 || s1 - s0 < common->max_batch)) {
             acc += fl[s1].bytes;
             ++s1;

@@ -521,55 +521,48 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
 
 // Move to parameter tf on face f, enter the neighbour cell and compute the
 // faces that are new to it.  Returns false when the walk left the grid
-// (k == nlay: top; k < 0: surface).
+// (k == nlay: top; k < 0: surface).  Each kind of face (shell, cone, plane)
+// is computed by one inlined body whatever the direction of the crossing,
+// so lanes of a wave that cross faces of one kind share its instructions.
 __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
 {
     w.t = tf;
-    switch (f) {
-    case F_OUT:
-        w.k += 1;
-        w.ef = F_IN;
-        if (w.k >= g.nlay) return false;
-        w.tin = INFINITY;
-        wk_shells(g, w, true, false);
+    if (f < 0) return false;
+    if (f <= F_IN) {  // shells: out -> k + 1 (new outer face), in -> k - 1 (new outer and inner faces)
+        const bool outward = f == F_OUT;
+        w.k += outward ? 1 : -1;
+        w.ef = outward ? F_IN : F_OUT;
+        if (w.k >= g.nlay || w.k < 0) return false;
+        if (outward) w.tin = INFINITY;
+        wk_shells(g, w, true, !outward);
         return true;
-    case F_IN:
-        w.k -= 1;
-        w.ef = F_OUT;
-        if (w.k < 0) return false;
-        wk_shells(g, w, true, true);
-        return true;
-    case F_LATLO:
-        w.j -= 1;
-        w.ef = F_LATHI;
-        w.hi1 = w.lo1;
-        w.hi2 = w.lo2;
-        if (w.j > 0) wk_cone(g, w, w.j, w.lo1, w.lo2);
-        else w.lo1 = w.lo2 = INFINITY;
-        return true;
-    case F_LATHI:
-        w.j += 1;
-        w.ef = F_LATLO;
-        w.lo1 = w.hi1;
-        w.lo2 = w.hi2;
-        if (w.j < g.nlat - 1) wk_cone(g, w, w.j + 1, w.hi1, w.hi2);
-        else w.hi1 = w.hi2 = INFINITY;
-        return true;
-    case F_LONLO:
-        w.i = w.i == 0 ? g.nlon - 1 : w.i - 1;
-        w.ef = F_LONHI;
-        w.thi = INFINITY;
-        w.tlo = wk_plane(g, w, w.i, false);
-        return true;
-    case F_LONHI:
-        w.i = w.i + 1 == g.nlon ? 0 : w.i + 1;
-        w.ef = F_LONLO;
-        w.tlo = INFINITY;
-        w.thi = wk_plane(g, w, w.i + 1 == g.nlon ? 0 : w.i + 1, true);
-        return true;
-    default:
-        return false;
     }
+    if (f <= F_LATHI) {  // cones: the face crossed becomes the opposite face of the new cell
+        const bool down = f == F_LATLO;
+        w.j += down ? -1 : 1;
+        w.ef = down ? F_LATHI : F_LATLO;
+        double k1 = down ? w.lo1 : w.hi1, k2 = down ? w.lo2 : w.hi2;  // roots of the cone crossed
+        const int e = down ? w.j : w.j + 1;                         // edge of the new face
+        double r1 = INFINITY, r2 = INFINITY;
+        if (down ? w.j > 0 : w.j < g.nlat - 1) wk_cone(g, w, e, r1, r2);
+        if (down) {
+            w.hi1 = k1; w.hi2 = k2;
+            w.lo1 = r1; w.lo2 = r2;
+        } else {
+            w.lo1 = k1; w.lo2 = k2;
+            w.hi1 = r1; w.hi2 = r2;
+        }
+        return true;
+    }
+    // longitude half-planes (the face crossed is behind the ray: never met again)
+    const bool west = f == F_LONLO;
+    w.i = west ? (w.i == 0 ? g.nlon - 1 : w.i - 1) : (w.i + 1 == g.nlon ? 0 : w.i + 1);
+    w.ef = west ? F_LONHI : F_LONLO;
+    const int e = west ? w.i : (w.i + 1 == g.nlon ? 0 : w.i + 1);
+    const double th = wk_plane(g, w, e, !west);
+    w.tlo = west ? th : INFINITY;
+    w.thi = west ? INFINITY : th;
+    return true;
 }
 
 __host__ __device__ __forceinline__ int wk_cell(const GridDev& g, const Walker& w)

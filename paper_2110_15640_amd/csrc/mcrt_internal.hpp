@@ -7,6 +7,7 @@
 namespace mcrt {
 
 constexpr int kMaxObs = 8;
+constexpr int kMaxSolvesPerLaunch = 1 << 21;  // solve index field of the transport's packed lane state
 constexpr int kNCounters = 11;
 enum Counter { K_ESC = 0, K_SURF, K_ABS, K_RR, K_CAP, K_LOST, K_NINT, K_NCROSS, K_NCAPPED, K_NLOST, K_W0 };
 

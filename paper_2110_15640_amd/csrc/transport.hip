@@ -36,18 +36,39 @@ using namespace dev;
 
 enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 5 };
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
+// Birth record of a packet, kept in the counter columns of its row until the
+// packet dies: position, direction, weight, then cell * 8 + (entry face + 1)
+// (-1: nothing emits).
+enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL };
 
 // Per-lane state that the cell walk does not touch lives in LDS (one slot
-// per lane, structure of arrays) so the registers hold only the walking ray.
+// per lane, structure of arrays) so the registers hold only the walking ray;
+// small fields are packed into 32-bit words.  The packet's peel-off sums
+// accumulate in LDS too and reach memory once, with its whole row.
 constexpr int kTPB = 256;
 struct ColdLDS {
     double sx[kTPB], sy[kTPB], sz[kTPB];      // event point
     double sdx[kTPB], sdy[kTPB], sdz[kTPB];   // packet direction
-    double W0[kTPB], mu0[kTPB], w_rr[kTPB];
+    double W0[kTPB], w_rr[kTPB];
     unsigned long long gid[kTPB];
-    int si[kTPB], sj[kTPB], sk[kTPB], sef[kTPB];
+    uint32_t ijk[kTPB];   // event cell: i | j << 11 | k << 21
+    uint32_t st[kTPB];    // observer:4 | birth:1 | smode:1 | entry face + 1:3 | capped:1 | lost:1 | solve:21
     uint32_t e[kTPB];
-    int o[kTPB], birth[kTPB], solve[kTPB], smode[kTPB], nint[kTPB], ncapped[kTPB], nlost[kTPB];
+    int nint[kTPB];
+};
+
+// A bit field [sh, sh + w) of a packed LDS word, used like an int.
+struct Bits {
+    uint32_t* p;
+    int sh;
+    uint32_t m;
+    __device__ operator int() const { return (int)((*p >> sh) & m); }
+    __device__ Bits& operator=(int v)
+    {
+        *p = (*p & ~(m << sh)) | (((uint32_t)v & m) << sh);
+        return *this;
+    }
+    __device__ Bits& operator+=(int v) { return *this = (int)*this + v; }
 };
 
 struct Lane {
@@ -59,6 +80,7 @@ struct Lane {
     int mode, ev;
     // cold state in LDS, accessed through these references
     ColdLDS* C;
+    double* F;     // peel-off sums, F[o * kTPB + t]
     int t;
     __device__ double& sx() { return C->sx[t]; }
     __device__ double& sy() { return C->sy[t]; }
@@ -67,21 +89,25 @@ struct Lane {
     __device__ double& sdy() { return C->sdy[t]; }
     __device__ double& sdz() { return C->sdz[t]; }
     __device__ double& W0() { return C->W0[t]; }
-    __device__ double& mu0() { return C->mu0[t]; }
     __device__ double& w_rr() { return C->w_rr[t]; }
     __device__ unsigned long long& gid() { return C->gid[t]; }
-    __device__ int& si() { return C->si[t]; }
-    __device__ int& sj() { return C->sj[t]; }
-    __device__ int& sk() { return C->sk[t]; }
-    __device__ int& sef() { return C->sef[t]; }
     __device__ uint32_t& e() { return C->e[t]; }
-    __device__ int& o() { return C->o[t]; }
-    __device__ int& birth() { return C->birth[t]; }
-    __device__ int& solve() { return C->solve[t]; }
-    __device__ int& smode() { return C->smode[t]; }
     __device__ int& nint() { return C->nint[t]; }
-    __device__ int& ncapped() { return C->ncapped[t]; }
-    __device__ int& nlost() { return C->nlost[t]; }
+    __device__ double& Fo(int o) { return F[o * kTPB + t]; }
+    __device__ Bits o() { return Bits{&C->st[t], 0, 0xFu}; }
+    __device__ Bits birth() { return Bits{&C->st[t], 4, 0x1u}; }
+    __device__ Bits smode() { return Bits{&C->st[t], 5, 0x1u}; }
+    __device__ int sef() { return (int)((C->st[t] >> 6) & 0x7u) - 1; }
+    __device__ void set_sef(int ef) { Bits{&C->st[t], 6, 0x7u} = ef + 1; }
+    __device__ Bits ncapped() { return Bits{&C->st[t], 9, 0x1u}; }
+    __device__ Bits nlost() { return Bits{&C->st[t], 10, 0x1u}; }
+    __device__ int solve() { return (int)(C->st[t] >> 11); }
+    __device__ void set_solve(int s) { Bits{&C->st[t], 11, 0x1FFFFFu} = s; }
+    __device__ int si() { return (int)(C->ijk[t] & 0x7FFu); }
+    __device__ int sj() { return (int)((C->ijk[t] >> 11) & 0x3FFu); }
+    __device__ int sk() { return (int)(C->ijk[t] >> 21); }
+    __device__ void set_cell(int i, int j, int k) { C->ijk[t] = (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 21); }
+    __device__ int cell(const GridDev& g) { return (sk() * g.nlat + sj()) * g.nlon + si(); }
 };
 
 template <bool MIXED>
@@ -91,10 +117,13 @@ __device__ __forceinline__ double ld(const void* p, int c)
     return ((const double*)p)[c];
 }
 
-// Write the packet's counters; `kind` says where its remaining weight went.
+// Write the packet's row: its peel-off sums, then the counters; `kind` says
+// where its remaining weight went.
 __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int kind)
 {
-    double* row = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
+    for (int o = 0; o < A.n_out; ++o) row[o] = L.Fo(o);
+    row += A.n_out;
     row[K_ESC] = kind == K_ESC ? L.W : 0.0;
     row[K_SURF] = kind == K_SURF ? L.W : 0.0;
     row[K_ABS] = L.w_abs;
@@ -112,10 +141,11 @@ __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int k
 __device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const double* sobs, double& ox, double& oy,
                                          double& oz)
 {
-    if (A.n_obs == 0) {
-        ox = -sqrt(fmax(1.0 - L.mu0() * L.mu0(), 0.0));
+    if (A.n_obs == 0) {  // slab backscatter: minus the incidence direction of the birth record
+        const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+        ox = -b[B_DX];
         oy = 0.0;
-        oz = L.mu0();
+        oz = -b[B_DZ];
     } else {
         const double* ob = sobs + L.smode() * (3 * kMaxObs);
         ox = ob[3 * L.o()];
@@ -149,6 +179,10 @@ __device__ __forceinline__ void start_flight(Lane& L, const GridDev& g, const Ba
     L.mode = M_FLIGHT;
 }
 
+// One cell of a walk.  Flights and peel-off rays share the exit search, the
+// extinction gather and the crossing (a single inlined copy of each, so that
+// a wave holding both kinds executes them once); they differ only in how the
+// optical depth is used and in when the walk stops.
 template <bool MIXED>
 __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
                                           const BatchArgs& A)
@@ -157,11 +191,12 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     const int f = wk_next(g, L.w, tf);
     const double s = tf - L.w.t;
     const int c = wk_cell(g, L.w);
-    if (L.mode == M_FLIGHT) {
-        const bool cont = A.absorption == 1;
-        double ae = ld<MIXED>(aext, c);
-        double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
-        double a = cont ? (ae - aa) : ae;
+    const bool flight = L.mode == M_FLIGHT;
+    const bool cont = flight && A.absorption == 1;
+    const double ae = ld<MIXED>(aext, c);
+    if (flight) {
+        const double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
+        const double a = cont ? (ae - aa) : ae;
         if (f == F_NONE && !(a > 0.0)) {
             L.ncross += L.ncw;
             L.mode = M_EVENT;
@@ -179,8 +214,8 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
             L.sx() = L.w.px + ti * L.w.dx;
             L.sy() = L.w.py + ti * L.w.dy;
             L.sz() = L.w.pz + ti * L.w.dz;
-            L.si() = L.w.i; L.sj() = L.w.j; L.sk() = L.w.k;
-            L.sef() = F_NONE;
+            L.set_cell(L.w.i, L.w.j, L.w.k);
+            L.set_sef(F_NONE);
             L.ncross += L.ncw;
             L.mode = M_EVENT;
             L.ev = E_INTERACT;
@@ -192,10 +227,6 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
             L.w_abs = L.w_abs + (L.W - wn);
             L.W = wn;
         }
-        const bool inside = wk_cross(g, L.w, f, tf);
-        L.ncw++;
-        if (!inside) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = L.w.k >= g.nlay ? E_ESCAPE : E_SURFACE; }
-        else if (L.ncw >= g.max_cross) { L.ncross += L.ncw; L.mode = M_EVENT; L.ev = E_LOST; }
     } else {
         if (f == F_NONE) {
             L.ncross += L.ncw;
@@ -204,19 +235,25 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
             L.ev = E_PEEL_DONE;
             return;
         }
-        L.tau = L.tau + ld<MIXED>(aext, c) * s;
-        const bool inside = wk_cross(g, L.w, f, tf);
-        L.ncw++;
-        bool done = true;
+        L.tau = L.tau + ae * s;
+    }
+    const bool inside = wk_cross(g, L.w, f, tf);
+    L.ncw++;
+    bool done;
+    if (flight) {
+        done = !inside || L.ncw >= g.max_cross;
+        if (done) L.ev = !inside ? (L.w.k >= g.nlay ? E_ESCAPE : E_SURFACE) : E_LOST;
+    } else {
+        done = true;
         if (L.tau > A.tau_peel_max) L.tau = INFINITY;
         else if (!inside) { if (L.w.k < 0) L.tau = INFINITY; }
         else if (L.ncw >= g.max_cross) L.tau = INFINITY;
         else done = false;
-        if (done) {
-            L.ncross += L.ncw;
-            L.mode = M_EVENT;
-            L.ev = E_PEEL_DONE;
-        }
+        if (done) L.ev = E_PEEL_DONE;
+    }
+    if (done) {
+        L.ncross += L.ncw;
+        L.mode = M_EVENT;
     }
 }
 
@@ -228,7 +265,7 @@ enum { A_NONE = 0, A_PEEL = 1, A_FLIGHT = 2, A_SCATTER = 3, A_FINISH = 4 };
 template <bool MIXED>
 __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
-    const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
+    const int c = L.cell(g);
     const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
     const unsigned long long q = L.gid() - S.begin;
     if (A.absorption != 1) {
@@ -320,7 +357,7 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         } else {
             // normalised mixture of the Rayleigh and cloud phase functions
             // toward the observer, weighted by the gas scattering probability
-            const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
+            const int c = L.cell(g);
             const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
             if (MIXED) {
                 float mu = (float)(L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz);
@@ -342,13 +379,12 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
             }
         }
-        double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
-        row[L.o()] = row[L.o()] + f;
+        L.Fo(L.o()) += f;
         if ((S.cf || S.img) && f > 0.0) {
             const double sc = f * (S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w);
             if (S.cf) {  // contribution function: the event's cell, thermal or scattered part
                 const int ncell = g.nlon * g.nlat * g.nlay;
-                const int c = (L.sk() * g.nlat + L.sj()) * g.nlon + L.si();
+                const int c = L.cell(g);
                 unsafeAtomicAdd(S.cf + ((size_t)L.o() * 2 + (L.birth() ? 0 : 1)) * ncell + c, sc);
             }
             if (S.img) {  // image: the event point on the observer's sky plane
@@ -395,10 +431,6 @@ __device__ __forceinline__ int solve_of(const BatchArgs& A, unsigned long long g
     return lo;
 }
 
-// Birth record of a packet, kept in the counter columns of its row until the
-// packet dies: position, direction, weight, then cell * 8 + (entry face + 1)
-// (-1: nothing emits).
-enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL };
 
 // K4a: births of every packet of a batch (albedo: uniform on the top disk or
 // the slab's incidence; emission: cell from the biased CDF, uniform position in
@@ -412,9 +444,7 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
     const GridDev& g = MULTI ? A.grids[S.grid] : g1;
     const double r_toa = g.r[g.nlay];
     const unsigned long long q = gid - S.begin;
-    double* row = A.rows + gid * (unsigned long long)A.row_w;
-    for (int o = 0; o < A.n_out; ++o) row[o] = 0.0;
-    double* b = row + A.n_out;
+    double* b = A.rows + gid * (unsigned long long)A.row_w + A.n_out;
     const uint32_t tag = S.tag;
     if (S.mode == 0) {
         U2 u = draw(A.seed, tag, q, 0, 0);
@@ -483,18 +513,17 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 // flight for albedo, the emission-point peel-off, or finish if none emits).
 __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
 {
-    L.solve() = solve_of(A, L.gid());
-    const SolveDev& S = A.solves[L.solve()];
+    const int sv = solve_of(A, L.gid());
+    const SolveDev& S = A.solves[sv];
+    L.C->st[L.t] = 0u;
+    L.set_solve(sv);
     L.smode() = S.mode;
+    for (int o = 0; o < A.n_out; ++o) L.Fo(o) = 0.0;
     const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
     L.w_abs = 0.0;
     L.w_rr() = 0.0;
     L.ncross = 0;
     L.nint() = 0;
-    L.ncapped() = 0;
-    L.nlost() = 0;
-    L.birth() = 0;
-    L.o() = 0;
     L.e() = 1;
     const double cw = b[B_CELL];
     L.W = b[B_W];
@@ -505,13 +534,10 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
     }
     const long long cc = (long long)cw;
     const int c = (int)(cc >> 3);
-    L.sef() = (int)(cc & 7) - 1;
-    L.si() = c % g.nlon;
-    L.sj() = (c / g.nlon) % g.nlat;
-    L.sk() = c / (g.nlon * g.nlat);
+    L.set_sef((int)(cc & 7) - 1);
+    L.set_cell(c % g.nlon, (c / g.nlon) % g.nlat, c / (g.nlon * g.nlat));
     L.sx() = b[B_X]; L.sy() = b[B_Y]; L.sz() = b[B_Z];
     L.sdx() = b[B_DX]; L.sdy() = b[B_DY]; L.sdz() = b[B_DZ];
-    L.mu0() = -L.sdz();  // slab incidence cosine (its backscatter observer)
     if (S.mode == 0) return A_FLIGHT;
     L.birth() = 1;
     return A_PEEL;
@@ -522,6 +548,7 @@ __global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g1, Ba
 {
     __shared__ double sobs[2 * 3 * kMaxObs];
     __shared__ ColdLDS cold;
+    __shared__ double Fsh[kMaxObs * kTPB];
     if (threadIdx.x < 2 * 3 * kMaxObs) sobs[threadIdx.x] = A.obs[threadIdx.x / (3 * kMaxObs)][threadIdx.x % (3 * kMaxObs)];
     __syncthreads();
     int lgrid = 0;  // grid of the lane's packet (multi-grid launches)
@@ -531,9 +558,10 @@ __global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g1, Ba
     bool exhausted = false;
     Lane L;
     L.C = &cold;
+    L.F = Fsh;
     L.t = threadIdx.x;
     L.mode = M_DEAD;
-    L.solve() = 0;
+    cold.st[threadIdx.x] = 0u;
     const void* aext = nullptr;
     const void* aabs = nullptr;
     for (;;) {
