@@ -36,8 +36,11 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "8dc5fba2b92e25af9d76c4db2f4ac668c4719aec70ec4e38ad5a9d9870d1ef2d"
-TRAFFIC_BYTES_PER_SOLVE = (396446717 * (1048576 / 524304) + 113689069 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "b563fd4dcf10b1b46e0c6b56b945de5a7cd28ed785a4325e04a2cce58569d25b"
+TRAFFIC_BYTES_PER_SOLVE = (351497454 * (1048576 / 524304) + 23571070 * 1.0) * 1024 / 168
+# SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
+# SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
+VALU_BUSY = 0.912
 
 
 def parse():
@@ -53,7 +56,7 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--wave-batch", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-packets", type=int, default=10000)
+    ap.add_argument("--cpu-packets", type=int, default=30000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
     ap.add_argument("--albedo", type=int, default=1, help="also time the 1D albedo workload (plain / batched / graph)")
     ap.add_argument("--batch-scale", type=float, default=0.01,
@@ -303,7 +306,8 @@ def main():
                      "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "avg_launch_ms": kms / max(launches, 1), "launches": launches,
                      "solves_per_launch": solves_per_launch, "flop_per_crossing": FLOP_PER_CROSSING,
-                     "traffic_GBps": None if traffic is None else traffic / (kms / max(launches, 1) * 1e-3) / 1e9},
+                     "traffic_GBps": None if traffic is None else traffic / (kms / max(launches, 1) * 1e-3) / 1e9,
+                     "valu_busy": VALU_BUSY if traffic is not None else None},
     }
     if pres is not None:
         # spectrum difference of the mixed form from the FP64 form on the same random stream

@@ -173,7 +173,9 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   1 = one launch per solve, 0 = as many as the HBM budget allows.
  * tune_ev_threshold, tune_blocks_per_cu, tune_wave_batch: launch shape of the
  *   persistent transport (lanes waiting before events are handled, 256-lane
- *   blocks per compute unit, packets a wave takes at once); 0 = default.
+ *   blocks per compute unit -- 1 to 3 select the spill-free register form, 4
+ *   or more the 128-register form --, packets a wave takes at once);
+ *   0 = default.
  * graph: albedo and emission blocking solves: non-zero records the solve's
  *   device work (preparation, transport and reduction launches and their
  *   host-to-device parameter copies) as a hipGraph on the first call and
@@ -299,9 +301,9 @@ int mcrt_solve_batch(mcrt_ctx* ctx, int32_t n_items, const mcrt_batch_item* item
                      const mcrt_solve_params* params, mcrt_result* results);
 
 /* Autotuner for the persistent transport launch shape: runs short trial
- * solves of this request (up to 3 of its spectral points, at most 2e5
- * packets each) over event thresholds {8, 16, 32}, blocks per compute unit
- * {2, 4} and wave batches {32, 128}, and writes the fastest into
+ * solves of this request (up to 4 of its spectral points with its packet
+ * count, at most 1e6 each) over event thresholds {16, 32}, blocks per
+ * compute unit {3, 4} and wave batches {32, 128}, and writes the fastest into
  * params->tune_* (best_packets_per_s, if not NULL, receives its trial rate).
  * Results of a solve do not depend on these settings.  mode: MCRT_MODE_ALBEDO
  * or MCRT_MODE_EMISSION.  Errors as for the blocking solves. */

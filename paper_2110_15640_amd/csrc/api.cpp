@@ -640,7 +640,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
     if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
     if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * (size_t)batch, &v_slots))) return rc;
-    if ((rc = scratch(ctx, sl, st, "dispenser", 64, &v_ctr))) return rc;
+    if ((rc = scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
     if (mode == MCRT_MODE_EMISSION) {
         if ((rc = scratch(ctx, sl, st, "sources", src_b * batch, &v_src))) return rc;
         if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * prep_scratch_doubles(ncell, batch), &v_ps)))
@@ -811,10 +811,10 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             A.solves = (const SolveDev*)v_solves;
             A.n_solves = nb;
             A.total = (unsigned long long)nb * N;
-            launch_fill_u64(A.counter, 0ULL, st);
+            launch_init_dispensers(A.counter, A.total, st);
             launch_births(g->dev, A, false, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
-            launch_transport_persistent(g->dev, A, mixed, false, pblocks, st);
+            launch_transport_persistent(g->dev, A, mixed, false, pblocks, bpc, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
             double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
             launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
@@ -1099,7 +1099,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * max_slots * chunks * pw, &v_part))) return rc;
     if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * max_slots, &v_solves))) return rc;
     if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * max_slots, &v_slots))) return rc;
-    if ((rc = scratch(ctx, sl, st, "dispenser", 64, &v_ctr))) return rc;
+    if ((rc = scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
     if ((rc = scratch(ctx, sl, st, "grid_table", sizeof(GridDev) * grids.size(), &v_grids))) return rc;
     if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * max_prep, &v_ps))) return rc;
     double* sums = (double*)v_sums;
@@ -1127,7 +1127,8 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     }
     A.batch = common->tune_wave_batch > 0 ? common->tune_wave_batch : 64;
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
-    const int pblocks = ctx->n_cu * (common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4);
+    const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
+    const int pblocks = ctx->n_cu * bpc;
     const bool prof = common->profile != 0;
     if (prof && (rc = prof_events(ctx, sl, launches.size()))) return rc;
     std::vector<std::vector<SolveDev>> hsv(launches.size());
@@ -1205,10 +1206,10 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
         A.solves = (const SolveDev*)v_solves;
         A.n_solves = nb;
         A.total = begin;
-        launch_fill_u64(A.counter, 0ULL, st);
+        launch_init_dispensers(A.counter, A.total, st);
         launch_births(hgrids[0], A, true, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li], st));
-        launch_transport_persistent(hgrids[0], A, mixed, true, pblocks, st);
+        launch_transport_persistent(hgrids[0], A, mixed, true, pblocks, bpc, st);
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li + 1], st));
         int chunks_l = 1;
         for (int sg = s0; sg < s1; ++sg) chunks_l = std::max(chunks_l, reduce_rows_chunks(it[fl[sg].item]->p.n_packets));
@@ -1776,40 +1777,39 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     if (!ctx || !params) return fail(MCRT_EINVAL, "ctx and params are required");
     if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION)
         return fail(MCRT_EINVAL, "autotuning applies to the packet transport (albedo, emission)");
-    // trial: up to 3 spectral points of the request (first, middle, last), at
-    // most 2e5 packets each, all in one batch
-    std::vector<int32_t> spec;
+    // trial: up to 4 spectral points spread over the request with the
+    // request's packet count (at most 1e6) each, all in one batch, so that
+    // the end-of-launch tail weighs about as much as in the real launches
+    std::vector<int32_t> all;
     if (params->spec_idx && params->n_spec > 0) {
-        spec.push_back(params->spec_idx[0]);
-        if (params->n_spec > 2) spec.push_back(params->spec_idx[params->n_spec / 2]);
-        if (params->n_spec > 1) spec.push_back(params->spec_idx[params->n_spec - 1]);
+        all.assign(params->spec_idx, params->spec_idx + params->n_spec);
     } else {
         Lease ls;
         int rc = lease(ctx, grid_id, opac_id, ls);
         if (rc) return rc;
-        int ns = ls.op->nspec;
-        spec.push_back(0);
-        if (ns > 2) spec.push_back(ns / 2);
-        if (ns > 1) spec.push_back(ns - 1);
+        for (int q = 0; q < ls.op->nspec; ++q) all.push_back(q);
     }
+    std::vector<int32_t> spec;
+    const int nt = std::min<int>(4, (int)all.size());
+    for (int q = 0; q < nt; ++q) spec.push_back(all[(size_t)q * all.size() / nt]);
     mcrt_solve_params t = *params;
     t.spec_idx = spec.data();
     t.n_spec = (int32_t)spec.size();
-    t.n_packets = std::min<uint64_t>(params->n_packets, 200000);
+    t.n_packets = std::min<uint64_t>(params->n_packets, 1000000);
     t.max_batch = 0;
     t.packet_dump = nullptr;
     t.profile = 0;
     t.graph = 0;
     t.contrib = 0;
     t.image_npix = 0;
-    const int evs[3] = {8, 16, 32}, bpcs[2] = {2, 4}, wbs[2] = {32, 128};
+    const int evs[2] = {16, 32}, bpcs[2] = {3, 4}, wbs[2] = {32, 128};
     double best = -1.0;
     int be = 16, bb = 4, bw = 64;
     std::vector<double> v(64 * 8), e(64 * 8);
     mcrt_result r{};
     r.value = v.data();
     r.stderr_ = e.data();
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 2; ++c) {
                 t.tune_ev_threshold = evs[a];

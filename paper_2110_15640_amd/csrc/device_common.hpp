@@ -380,6 +380,8 @@ struct Walker {
     double t;               // distance walked from the origin
     double B0, C0;          // p0 . d, |p0|^2 (spherical) ; unused for the slab
     double tout, tin;       // outer-face exit / inner-face hit (INFINITY = none)
+    double tin_far;         // far root of the inner sphere when tin is set: the
+                            // outer face's exit once that sphere is crossed
     double lo1, lo2;        // lower latitude cone roots on its nappe, ascending
     double hi1, hi2;        // upper latitude cone roots
     double tlo, thi;        // lower / upper longitude half-plane hits
@@ -410,8 +412,12 @@ __host__ __device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, 
             double C = w.C0 - R * R;
             double D = w.B0 * w.B0 - C;
             if (D >= 0.0) {
-                double nr = C / (-w.B0 + sqrt(D));
-                if (nr >= w.t || C < 0.0) w.tin = fmax(nr, w.t);
+                const double q = -w.B0 + sqrt(D);
+                double nr = C / q;
+                if (nr >= w.t || C < 0.0) {
+                    w.tin = fmax(nr, w.t);
+                    w.tin_far = q;
+                }
             }
         }
     }
@@ -507,8 +513,11 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
         tf = best;
         return face;
     }
+    // entry-face tolerance 1e-9 |p|, with |p| bounded by the cell's outer
+    // radius (it only separates a re-found root of the cone just crossed,
+    // ~1e-16 |p| away, from genuine ones)
     double lo = w.t;
-    if (w.ef == F_LATLO || w.ef == F_LATHI) lo = w.t + 1e-9 * sqrt(w.C0 + w.t * (2.0 * w.B0 + w.t));
+    if (w.ef == F_LATLO || w.ef == F_LATHI) lo = w.t + 1e-9 * g.r[w.k + 1];
     double a = wk_next_root(w.lo1, w.lo2, w.t, w.ef == F_LATLO ? lo : w.t);
     if (a < best) { best = a; face = F_LATLO; }
     double b = wk_next_root(w.hi1, w.hi2, w.t, w.ef == F_LATHI ? lo : w.t);
@@ -521,30 +530,135 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
 
 // Move to parameter tf on face f, enter the neighbour cell and compute the
 // faces that are new to it.  Returns false when the walk left the grid
-// (k == nlay: top; k < 0: surface).  Each kind of face (shell, cone, plane)
-// is computed by one inlined body whatever the direction of the crossing,
-// so lanes of a wave that cross faces of one kind share its instructions.
+// (k == nlay: top; k < 0: surface).
+//
+// Every crossing needs exactly one new surface: the next outer sphere
+// (outward), the next inner sphere (inward; the new outer face is the sphere
+// just crossed, whose far root was kept with tin), the next cone, or the next
+// longitude plane.  All of them are met where A t^2 + 2 B t + C = 0 (planes
+// and the equator: the linear B2 t + C = 0), so one branch-free body solves
+// that equation for every lane of a wave, whatever face kind it crosses, and
+// per-kind selects pick the roots.  The arithmetic of each kind is the same,
+// operation for operation, as in wk_shells, wk_cone and wk_plane.
 __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
 {
     w.t = tf;
     if (f < 0) return false;
-    if (f <= F_IN) {  // shells: out -> k + 1 (new outer face), in -> k - 1 (new outer and inner faces)
-        const bool outward = f == F_OUT;
+    const bool shell = f <= F_IN, cone = f == F_LATLO || f == F_LATHI;
+    const bool outward = f == F_OUT, down = f == F_LATLO, west = f == F_LONLO;
+    const bool slab = g.geom == 1;
+    // indices of the new cell
+    if (shell) {
         w.k += outward ? 1 : -1;
         w.ef = outward ? F_IN : F_OUT;
         if (w.k >= g.nlay || w.k < 0) return false;
-        if (outward) w.tin = INFINITY;
-        wk_shells(g, w, true, !outward);
-        return true;
-    }
-    if (f <= F_LATHI) {  // cones: the face crossed becomes the opposite face of the new cell
-        const bool down = f == F_LATLO;
+    } else if (cone) {
         w.j += down ? -1 : 1;
         w.ef = down ? F_LATHI : F_LATLO;
-        double k1 = down ? w.lo1 : w.hi1, k2 = down ? w.lo2 : w.hi2;  // roots of the cone crossed
-        const int e = down ? w.j : w.j + 1;                         // edge of the new face
+    } else {
+        w.i = west ? (w.i == 0 ? g.nlon - 1 : w.i - 1) : (w.i + 1 == g.nlon ? 0 : w.i + 1);
+        w.ef = west ? F_LONHI : F_LONLO;
+    }
+    // the new surface: coefficients of A t^2 + 2 B t + C (A = 0: B2 t + C)
+    double A = 0.0, B = 0.0, C = 0.0, B2 = 0.0;
+    bool has = true;     // a surface to intersect at all
+    bool equator = false;
+    double tb = 0.0, sb = 0.0, cb = 0.0;
+    if (shell) {
+        const double R = g.r[outward ? w.k + 1 : w.k];
+        has = outward || slab || w.B0 < 0.0;
+        if (slab) {
+            B2 = w.dz;
+            C = w.pz - R;
+        } else {
+            A = 1.0;
+            B = w.B0;
+            C = w.C0 - R * R;
+        }
+    } else if (cone) {
+        const int e = down ? w.j : w.j + 1;
+        has = down ? w.j > 0 : w.j < g.nlat - 1;
+        const int ee = has ? e : 0;
+        tb = g.lat[ee];
+        const double c2 = g.lat_c2[ee], s2 = g.lat_s2[ee];
+        equator = tb == 0.0;
+        if (equator) {
+            B2 = w.dz;
+            C = w.pz;
+        } else {
+            A = w.dz * w.dz * c2 - (w.dx * w.dx + w.dy * w.dy) * s2;
+            B = w.pz * w.dz * c2 - (w.px * w.dx + w.py * w.dy) * s2;
+            C = w.pz * w.pz * c2 - (w.px * w.px + w.py * w.py) * s2;
+            B2 = 2.0 * B;
+        }
+    } else {
+        const int e = west ? w.i : (w.i + 1 == g.nlon ? 0 : w.i + 1);
+        sb = g.lon_s[e];
+        cb = g.lon_c[e];
+        const double nx = -sb, ny = cb;
+        const double dn = w.dx * nx + w.dy * ny;
+        has = west ? dn < 0.0 : dn > 0.0;
+        B2 = dn;
+        C = w.px * nx + w.py * ny;
+    }
+    // one solve for every lane
+    const bool quad = A != 0.0;
+    const double D = B * B - A * C;
+    const double sq = sqrt(fmax(D, 0.0));
+    const bool neg = cone ? B >= 0.0 : B > 0.0;  // the sign rule of each kind at B = 0
+    const double q = neg ? -(B + sq) : (-B + sq);
+    const double x0q = q / (quad ? A : 1.0);
+    const double x1q = (quad && q != 0.0) ? C / q : INFINITY;
+    const double xl = (!quad && B2 != 0.0) ? -C / B2 : INFINITY;
+    if (shell) {
+        if (slab) {
+            const double x = fmax(-C / B2, w.t);  // (R - pz) / dz
+            if (outward) {
+                w.tout = w.dz > 0.0 ? x : INFINITY;
+                w.tin = INFINITY;
+            } else {
+                w.tout = INFINITY;
+                w.tin = w.dz < 0.0 ? x : INFINITY;
+            }
+            return true;
+        }
+        if (outward) {  // far root of the next outer sphere; the sphere crossed is behind
+            w.tout = fmax(B > 0.0 ? x1q : x0q, w.t);
+            w.tin = INFINITY;
+        } else {        // outer face: the sphere just crossed; inner face: the next sphere, if hit
+            w.tout = fmax(w.tin_far, w.t);
+            w.tin = INFINITY;
+            if (has && D >= 0.0 && (x1q >= w.t || C < 0.0)) {
+                w.tin = fmax(x1q, w.t);
+                w.tin_far = q;
+            }
+        }
+        return true;
+    }
+    if (cone) {
         double r1 = INFINITY, r2 = INFINITY;
-        if (down ? w.j > 0 : w.j < g.nlat - 1) wk_cone(g, w, e, r1, r2);
+        if (has) {
+            if (equator) {
+                r1 = w.dz != 0.0 ? xl : INFINITY;
+            } else {
+                double x0 = INFINITY, x1 = INFINITY;
+                if (!quad) {
+                    x0 = B != 0.0 ? -C / B2 : INFINITY;
+                } else if (D >= 0.0) {
+                    x0 = x0q;
+                    x1 = x1q;
+                }
+                const bool ok0 = x0 < INFINITY && (tb > 0.0 ? (w.pz + x0 * w.dz > 0.0) : (w.pz + x0 * w.dz < 0.0));
+                const bool ok1 = x1 < INFINITY && (tb > 0.0 ? (w.pz + x1 * w.dz > 0.0) : (w.pz + x1 * w.dz < 0.0));
+                if (!ok0) x0 = INFINITY;
+                if (!ok1) x1 = INFINITY;
+                r1 = fmin(x0, x1);
+                r2 = fmax(x0, x1);
+                if (!(r1 < INFINITY)) r2 = INFINITY;
+            }
+        }
+        // the cone crossed becomes the opposite face of the new cell
+        const double k1 = down ? w.lo1 : w.hi1, k2 = down ? w.lo2 : w.hi2;
         if (down) {
             w.hi1 = k1; w.hi2 = k2;
             w.lo1 = r1; w.lo2 = r2;
@@ -554,12 +668,13 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
         }
         return true;
     }
-    // longitude half-planes (the face crossed is behind the ray: never met again)
-    const bool west = f == F_LONLO;
-    w.i = west ? (w.i == 0 ? g.nlon - 1 : w.i - 1) : (w.i + 1 == g.nlon ? 0 : w.i + 1);
-    w.ef = west ? F_LONHI : F_LONLO;
-    const int e = west ? w.i : (w.i + 1 == g.nlon ? 0 : w.i + 1);
-    const double th = wk_plane(g, w, e, !west);
+    // longitude half-plane (the one crossed is behind the ray: never met again)
+    double th = INFINITY;
+    if (has) {
+        th = fmax(xl, w.t);
+        const double hx = w.px + th * w.dx, hy = w.py + th * w.dy;
+        if (!(cb * hx + sb * hy > 0.0)) th = INFINITY;
+    }
     w.tlo = west ? th : INFINITY;
     w.thi = west ? INFINITY : th;
     return true;

@@ -8,6 +8,7 @@ namespace mcrt {
 
 constexpr int kMaxObs = 8;
 constexpr int kMaxSolvesPerLaunch = 1 << 21;  // solve index field of the transport's packed lane state
+constexpr int kXcds = 8;                      // packet dispensers per launch, one per XCD
 constexpr int kNCounters = 11;
 enum Counter { K_ESC = 0, K_SURF, K_ABS, K_RR, K_CAP, K_LOST, K_NINT, K_NCROSS, K_NCAPPED, K_NLOST, K_W0 };
 
@@ -77,7 +78,7 @@ struct BatchArgs {
     int n_solves;
     const GridDev* grids;  // per-solve grids of a multi-grid launch (else unused)
     unsigned long long total;     // packets over all solves
-    unsigned long long* counter;  // packet dispenser
+    unsigned long long* counter;  // kXcds packet dispensers (one chunk of the packets each)
     double* rows;                 // [total][row_w]: F per observer, then counters
     int row_w;
     uint64_t seed;
@@ -122,12 +123,13 @@ void launch_prep_sources(const GridDev& g, int ncell, const PrepSlot* slots, int
 size_t prep_scratch_doubles(int ncell, int nslots);
 
 void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, bool multi, int blocks,
-                                 hipStream_t stream);
+                                 int blocks_per_cu, hipStream_t stream);
 void launch_reduce_rows(const BatchArgs& a, const SolveDev* solves_host, int n_solves,
                         double* partials, int chunks, double* sums, int sums_w, double* dump,
                         hipStream_t stream);
 int reduce_rows_chunks(unsigned long long max_n);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream);
+void launch_init_dispensers(unsigned long long* counters, unsigned long long total, hipStream_t stream);
 void launch_fill_f64(double* p, size_t n, double v, hipStream_t stream);
 void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream);
 

@@ -110,11 +110,21 @@ struct Lane {
     __device__ int cell(const GridDev& g) { return (sk() * g.nlat + sj()) * g.nlon + si(); }
 };
 
+// floor(total * x / kXcds) without overflow.
+__device__ __forceinline__ unsigned long long chunk_edge(unsigned long long total, int x)
+{
+    return (total / kXcds) * (unsigned long long)x + (total % kXcds) * (unsigned long long)x / kXcds;
+}
+
 template <bool MIXED>
 __device__ __forceinline__ double ld(const void* p, int c)
 {
-    if (MIXED) return (double)((const float*)p)[c];
-    return ((const double*)p)[c];
+    // per-cell optical properties live in global memory: load through the
+    // global address space (a global, not a flat, load)
+    typedef const __attribute__((address_space(1))) float gfloat;
+    typedef const __attribute__((address_space(1))) double gdouble;
+    if (MIXED) return (double)((gfloat*)p)[c];
+    return ((gdouble*)p)[c];
 }
 
 // Write the packet's row: its peel-off sums, then the counters; `kind` says
@@ -543,8 +553,12 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
     return A_PEEL;
 }
 
-template <bool MIXED, bool MULTI>
-__global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g1, BatchArgs A)
+// MINB: blocks per CU the register allocation is sized for (4: at most 128
+// VGPRs per lane, 16 waves per CU, with some spills; 2: no spills, ~170 VGPRs,
+// so up to 3 waves per SIMD = 3 blocks per CU), chosen at launch from the
+// requested blocks per CU.
+template <bool MIXED, bool MULTI, int MINB>
+__global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1, BatchArgs A)
 {
     __shared__ double sobs[2 * 3 * kMaxObs];
     __shared__ ColdLDS cold;
@@ -584,15 +598,31 @@ __global__ void __launch_bounds__(kTPB, 4) k_transport_persistent(GridDev g1, Ba
             while (dead != 0) {
                 if (res_next >= res_end) {
                     if (exhausted) break;
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(A.counter, (unsigned long long)A.batch);
+                    // the packet range is split into one contiguous chunk per XCD (blocks are
+                    // dealt to the XCDs round-robin), so each XCD's L2 holds the optics of
+                    // its own solves; a wave whose chunk is drained helps the next ones
+                    unsigned long long base = 0, end = 0;
+                    if (lane == 0) {
+                        const int x0 = (int)(blockIdx.x % kXcds);
+                        for (int q = 0; q < kXcds; ++q) {
+                            const int x = (x0 + q) % kXcds;
+                            const unsigned long long lim = chunk_edge(A.total, x + 1);
+                            const unsigned long long b = atomicAdd(A.counter + x, (unsigned long long)A.batch);
+                            if (b < lim) {
+                                base = b;
+                                end = b + (unsigned long long)A.batch < lim ? b + A.batch : lim;
+                                break;
+                            }
+                        }
+                    }
                     base = __shfl(base, 0);
-                    if (base >= A.total) {
+                    end = __shfl(end, 0);
+                    if (end == 0) {
                         exhausted = true;
                         break;
                     }
                     res_next = base;
-                    res_end = base + (unsigned long long)A.batch < A.total ? base + A.batch : A.total;
+                    res_end = end;
                 }
                 unsigned long long avail = res_end - res_next;
                 int cnt = __popcll(dead);
@@ -711,6 +741,13 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Packet dispensers of a launch: counter x starts at the first packet of
+// chunk x = [edge(x), edge(x + 1)), edge(x) = floor(total * x / kXcds).
+__global__ void k_init_dispensers(unsigned long long* c, unsigned long long total)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kXcds) c[threadIdx.x] = chunk_edge(total, (int)threadIdx.x);
+}
+
 // Fill n doubles (a kernel, so that recorded graphs hold no memset nodes).
 __global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, size_t n, double v)
 {
@@ -727,16 +764,19 @@ void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t
 }
 
 void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, bool multi, int blocks,
-                                 hipStream_t stream)
+                                 int blocks_per_cu, hipStream_t stream)
 {
-    if (mixed && multi)
-        hipLaunchKernelGGL((k_transport_persistent<true, true>), dim3(blocks), dim3(256), 0, stream, g, a);
-    else if (mixed)
-        hipLaunchKernelGGL((k_transport_persistent<true, false>), dim3(blocks), dim3(256), 0, stream, g, a);
-    else if (multi)
-        hipLaunchKernelGGL((k_transport_persistent<false, true>), dim3(blocks), dim3(256), 0, stream, g, a);
-    else
-        hipLaunchKernelGGL((k_transport_persistent<false, false>), dim3(blocks), dim3(256), 0, stream, g, a);
+    const bool wide = blocks_per_cu <= 3;  // up to 256 VGPRs: at most 3 waves per SIMD
+#define MCRT_K4(MX, MU)                                                                                       \
+    if (wide)                                                                                                 \
+        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 2>), dim3(blocks), dim3(kTPB), 0, stream, g, a);  \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 4>), dim3(blocks), dim3(kTPB), 0, stream, g, a);
+    if (mixed && multi) { MCRT_K4(true, true) }
+    else if (mixed) { MCRT_K4(true, false) }
+    else if (multi) { MCRT_K4(false, true) }
+    else { MCRT_K4(false, false) }
+#undef MCRT_K4
 }
 
 int reduce_rows_chunks(unsigned long long max_n) { return (int)((max_n + kChunk - 1) / kChunk); }
@@ -752,6 +792,11 @@ void launch_reduce_rows(const BatchArgs& a, const SolveDev* /*solves_host*/, int
 void launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, stream, p, v);
+}
+
+void launch_init_dispensers(unsigned long long* counters, unsigned long long total, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_init_dispensers, dim3(1), dim3(64), 0, stream, counters, total);
 }
 
 void launch_fill_f64(double* p, size_t n, double v, hipStream_t stream)
