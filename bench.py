@@ -110,10 +110,19 @@ def transmission_leg(M, I):
         wall = time.perf_counter() - t0
         depth = r["value"][:, 0]
         nch = 256 * 360
+        # K5 roofline: per (segment, wavelength) the 8 B FP64 alpha gather, plus the
+        # 12 B segment record (cell, length) once per 64-wavelength block launch
+        nseg, nl, nblk = r["n_segments"], table.nlam, r["kernel_launches"]
+        k5_bytes = nseg * nl * 8.0 + nseg * nblk * 12.0 + nch * nblk * 12.0
+        k5_gbps = k5_bytes / (r["kernel_ms"] * 1e-3) / 1e9
         return {"workload": f"3D hi-res transmission: {grid.nlon}x{grid.nlat}x{grid.nlay} grid, {table.nlam} wavelengths "
                             "1.0-1.1 um, 256 x 360 chords, winds + rotation Doppler",
                 "ms": wall * 1e3, "chord_wavelengths_per_s": nch * table.nlam / wall,
                 "chord_tau_kernel_ms": r["kernel_ms"], "chord_tau_launches": r["kernel_launches"],
+                "segments": nseg,
+                "roofline": {"bound": "hbm", "kernel": "k_chord_tau", "achieved": k5_gbps, "peak": PEAK_HBM,
+                             "unit": "GB/s", "frac": k5_gbps / PEAK_HBM, "traffic": None,
+                             "bytes_per_segment_wavelength": 8.0},
                 "depth_min": float(depth.min()), "depth_max": float(depth.max()),
                 "rel_se_median": float(np.median(r["stderr"][:, 0] / depth))}
 

@@ -252,7 +252,9 @@ void mcrt_default_params(mcrt_solve_params* p);
  *   its value.  Row index along the vertical axis e_v = the rotation axis z
  *   projected on the sky plane (x when the observer looks along z), column
  *   index along e_h = e_v x o; pixels cover [-R_TOA, R_TOA]^2 from the
- *   negative end.  FP64 atomics, as cf. */
+ *   negative end.  FP64 atomics, as cf.
+ * n_segments: transmission: the number of (chord, cell) segments of the
+ *   chord geometry (each is read once per spectral row); 0 otherwise. */
 typedef struct {
     double* value;
     double* stderr_;
@@ -267,6 +269,7 @@ typedef struct {
     double latency_ms;
     double* cf;
     double* image;
+    int64_t n_segments;
 } mcrt_result;
 
 /* Blocking solves.  Errors: EINVAL (bad parameters, incompatible grid /

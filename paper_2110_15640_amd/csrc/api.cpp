@@ -938,6 +938,7 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     long long nseg = 0;
     HIPTRY(hipMemcpyAsync(&nseg, (long long*)v_off + nch, sizeof(long long), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
+    res->n_segments = nseg;
     void *v_sc, *v_sl;
     if ((rc = scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
     if ((rc = scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
@@ -1272,6 +1273,7 @@ struct Request {
     std::vector<double> value, se, per_g, sums, counters, l_tot;
     double elapsed_ms = 0.0, kernel_ms = 0.0;
     int64_t launches = 0;
+    int64_t n_segments = 0;
     Clock::time_point t_sub, t_start, t_done;
 };
 
@@ -1362,6 +1364,7 @@ void worker_main(mcrt_ctx* ctx, Slot* sl)
         r->elapsed_ms = res.elapsed_ms;
         r->kernel_ms = res.kernel_ms;
         r->launches = res.kernel_launches;
+        r->n_segments = res.n_segments;
         r->t_done = Clock::now();
         r->status = rc ? R_FAILED : R_DONE;
         ctx->q_cv.notify_all();
@@ -1471,6 +1474,7 @@ int wait_request(mcrt_ctx* ctx, uint64_t ticket, mcrt_result* out)
         out->elapsed_ms = r->elapsed_ms;
         out->kernel_ms = r->kernel_ms;
         out->kernel_launches = r->launches;
+        out->n_segments = r->n_segments;
         out->queued_ms = std::chrono::duration<double, std::milli>(r->t_start - r->t_sub).count();
         out->latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_sub).count();
     }

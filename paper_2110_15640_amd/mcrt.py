@@ -72,7 +72,7 @@ class Result(ctypes.Structure):
     _fields_ = [("value", _vp), ("stderr_", _vp), ("per_g", _vp), ("sums", _vp),
                 ("counters", _vp), ("l_tot", _vp), ("elapsed_ms", _dbl), ("kernel_ms", _dbl),
                 ("kernel_launches", _i64), ("queued_ms", _dbl), ("latency_ms", _dbl), ("cf", _vp),
-                ("image", _vp)]
+                ("image", _vp), ("n_segments", _i64)]
 
 
 _lib = None
@@ -273,7 +273,7 @@ class Context:
         return Result(out["value"].ctypes.data, out["stderr"].ctypes.data, out["per_g"].ctypes.data,
                       out["sums"].ctypes.data, out["counters"].ctypes.data, out["l_tot"].ctypes.data,
                       0.0, 0.0, 0, 0.0, 0.0, None if cf is None else cf.ctypes.data,
-                      None if im is None else im.ctypes.data)
+                      None if im is None else im.ctypes.data, 0)
 
     @staticmethod
     def _finish(out, r):
@@ -282,6 +282,7 @@ class Context:
         out["kernel_launches"] = r.kernel_launches
         out["queued_ms"] = r.queued_ms
         out["latency_ms"] = r.latency_ms
+        out["n_segments"] = r.n_segments
 
     def solve_batch(self, items, **kw):
         """items: list of dicts (mode, gid, oid, table, spec_idx, n_packets);
