@@ -714,7 +714,7 @@ static void tally_add(const orc_tally *tl, int64_t ncell, int o, int part, int64
 /* One packet history.  F[o] receives its peel-off sum per observer. */
 static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params *pr,
                        const double *obs, const double *cdf, const double *wbirth, int64_t ncell,
-                       double r_toa, uint64_t pid, double *F, double *K, const orc_tally *tl)
+                       double r_toa, uint64_t pid, double wmul, double *F, double *K, const orc_tally *tl)
 {
     uint32_t tag = (uint32_t)pr->tag;
     int nobs = (int)pr->n_obs;
@@ -752,7 +752,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             locate_column(g, ry.p, &ry.i, &ry.j);
             ry.ef = F_OUT;
         }
-        W = 1.0;
+        W = wmul;
     } else {
         /* emission: cell by the biased CDF, uniform position in the cell's
          * volume, isotropic direction, weight (L_i/L_tot)/q_i              */
@@ -784,7 +784,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         d[0] = sp * cos(psi);
         d[1] = sp * sin(psi);
         d[2] = mu;
-        W = wbirth[c];
+        W = wbirth[c] * wmul;
         /* initial peel-off from the emission point */
         for (int o = 0; o < nobs; ++o) {
             double tau = peel_tau(g, op, &ry, obs + 3 * o, pr->tau_peel_max, pr->max_cross, &ncross);
@@ -865,8 +865,46 @@ int64_t orc_transport(const orc_grid *g, const orc_optics *op, const orc_params 
 #pragma omp parallel for schedule(dynamic, 64)
 #endif
     for (int64_t q = 0; q < n; ++q) {
-        run_packet(g, op, pr, obs, cdf, wbirth, ncell, r_toa, pr->packet0 + (uint64_t)q,
+        run_packet(g, op, pr, obs, cdf, wbirth, ncell, r_toa, pr->packet0 + (uint64_t)q, 1.0,
                    F_out + q * nout, K_out + q * NK, tl);
+    }
+    return nout;
+}
+
+/* Per-packet g-ordinate sampling (Sect. "G-ordinance biasing"): one band,
+ * ng g-ordinates with their own optics (and emission sources).  Packet pid
+ * draws u from block 3, slot a of its birth event and takes the smallest g
+ * whose cumulative sampling weight q exceeds u times the total; its history
+ * then runs with that g's optics and sources, all weights multiplied by
+ * wfac[g] = p(g)/q(g).  q: unnormalised sampling weights [ng]; optics,
+ * cdf, wbirth: arrays of ng pointers (cdf/wbirth NULL for albedo).        */
+int64_t orc_transport_gsampled(const orc_grid *g, const orc_optics *ops, int64_t ng, const orc_params *pr,
+                               const double *obs, const double *const *cdfs, const double *const *wbirths,
+                               const double *q, const double *wfac, double r_toa, double *F_out,
+                               double *K_out, int64_t *g_out, int64_t nthreads)
+{
+    int64_t ncell = g->nlon * g->nlat * g->nlay;
+    int nout = (g->geom == 1 && pr->n_obs == 0) ? 1 : (int)pr->n_obs;
+    int64_t n = (int64_t)pr->n_packets;
+    double qtot = 0.0;
+    for (int64_t h = 0; h < ng; ++h) qtot = qtot + q[h];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads((int)nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t pid = pr->packet0 + (uint64_t)i;
+        double ua, ub;
+        orc_draw(pr->seed, (uint32_t)pr->tag, pid, 0, 3, &ua, &ub);
+        double target = ua * qtot, cum = 0.0;
+        int64_t gi = ng - 1;
+        for (int64_t h = 0; h < ng; ++h) {
+            cum = cum + q[h];
+            if (cum > target) { gi = h; break; }
+        }
+        if (g_out) g_out[i] = gi;
+        run_packet(g, &ops[gi], pr, obs, cdfs ? cdfs[gi] : NULL, wbirths ? wbirths[gi] : NULL, ncell, r_toa, pid,
+                   wfac[gi], F_out + i * nout, K_out + i * NK, NULL);
     }
     return nout;
 }

@@ -105,6 +105,9 @@ def lib():
                                     ctypes.POINTER(_Params), vp, vp, vp, dbl, vp, vp,
                                     ctypes.POINTER(_Tally), i64]
         L.orc_transport.restype = i64
+        L.orc_transport_gsampled.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Optics), i64,
+                                             ctypes.POINTER(_Params), vp, vp, vp, vp, vp, dbl, vp, vp, vp, i64]
+        L.orc_transport_gsampled.restype = i64
         L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
                                        vp, vp, i64]
         L.orc_max_threads.restype = i64
@@ -284,6 +287,7 @@ class Params:
     n_b: int = 256
     n_alpha: int = 360
     r_star: float = 6.957e10
+    g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
     threads: int = 0
 
 
@@ -360,6 +364,56 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     return F[:, :nout], K
 
 
+def g_sampling_weights(scheme: int, w, L=None):
+    """Sampling weights q(g) (unnormalised) and weight factors p(g)/q(g) of
+    per-packet g-ordinate sampling (Sect. "G-ordinance biasing"): p(g) = w_g
+    (albedo) or w_g L_g / sum(w L) (emission); scheme 1 samples p itself
+    (factor 1), 2 the uniform q = 1/N_g (factor N_g p), 3 the composite
+    q = (p + 1/N_g) / 2."""
+    w = np.asarray(w, dtype=np.float64)
+    ng = len(w)
+    raw = w if L is None else w * np.asarray(L, dtype=np.float64)
+    tot = float(raw.sum())
+    p = raw / tot if tot > 0 else np.zeros(ng)
+    if scheme == 1:
+        return raw.copy(), np.ones(ng)
+    if scheme == 2:
+        return np.ones(ng), p * ng
+    if scheme == 3:
+        q = 0.5 * p + 0.5 / ng
+        return q, p / q
+    raise ValueError(f"unknown g-sampling scheme {scheme}")
+
+
+def transport_gsampled(grid, optics_list, params: Params, mode: int, obs, q, wfac, sources_list=None, tag=0):
+    """Per-packet g sampling over the g-ordinates of one band; returns F, K
+    and the g each packet drew."""
+    gv = GridView(grid)
+    ng = len(optics_list)
+    nobs = 0 if obs is None else len(obs)
+    pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
+                 int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
+                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0)
+    ops = (_Optics * ng)()
+    for h, op in enumerate(optics_list):
+        ops[h] = _Optics(op.a_ext.ctypes.data, op.a_abs.ctypes.data, op.omega.ctypes.data,
+                         op.p_gas.ctypes.data, op.g_cld.ctypes.data)
+    nout = 1 if (grid.geometry == 1 and nobs == 0) else nobs
+    F = np.zeros((params.n_packets, max(nout, 1)))
+    K = np.zeros((params.n_packets, NK))
+    G = np.zeros(params.n_packets, dtype=np.int64)
+    o = None if obs is None else _f64(obs)
+    qa, wa = _f64(q), _f64(wfac)
+    cdfs = wbs = None
+    if sources_list is not None:
+        cdfs = (ctypes.c_void_p * ng)(*[sv.cdf.ctypes.data for sv in sources_list])
+        wbs = (ctypes.c_void_p * ng)(*[sv.wbirth.ctypes.data for sv in sources_list])
+    lib().orc_transport_gsampled(ctypes.byref(gv.c), ops, ng, ctypes.byref(pr), _p(o), cdfs, wbs,
+                                 qa.ctypes.data, wa.ctypes.data, float(grid.r_toa), F.ctypes.data, K.ctypes.data,
+                                 G.ctypes.data, int(params.threads))
+    return F[:, :nout], K, G
+
+
 def _tag(params, spec_slot_idx, g, ng):
     return (1 + spec_slot_idx * ng + g) if params.decorrelate else 0
 
@@ -407,9 +461,58 @@ def band_image(img_g, scale_g, w_g):
     return acc
 
 
+def _solve_gsampled(grid, table, params: Params, mode: int, obs, specs, keep_packets):
+    """Band values with per-packet g-ordinate sampling: albedo A = pi sum F / N,
+    emission F_p = sum_g(w_g L_g) sum F / (N R_TOA^2); the band's sums and
+    counters are reported in its g = 0 slot (other slots and per_g stay 0)."""
+    ng = table.ng
+    nout = 1 if obs is None else len(obs)
+    N = params.n_packets
+    w = np.asarray(table.g_weights, dtype=np.float64)
+    value = np.zeros((len(specs), nout))
+    stderr = np.zeros_like(value)
+    sums = np.zeros((len(specs), ng, nout, 2))
+    cnt = np.zeros((len(specs), ng, NK))
+    ltot = np.zeros((len(specs), ng))
+    packets = {}
+    for si, b in enumerate(specs):
+        ops = [ck_optics(grid, table, b, g) for g in range(ng)]
+        srcs = None
+        if mode == 1:
+            srcs = [emission_sources(grid, op, table.lam_um[b], params.tau_vert_max, params.emis_bias) for op in ops]
+            ltot[si] = [sv.L_tot for sv in srcs]
+            q, wf = g_sampling_weights(params.g_sampling, w, ltot[si])
+            scale = float(np.dot(w, ltot[si])) / grid.r_toa ** 2
+        else:
+            q, wf = g_sampling_weights(params.g_sampling, w)
+            scale = math.pi
+        tag = (1 + b * ng) if params.decorrelate else 0
+        if q.sum() > 0.0:
+            F, K, G = transport_gsampled(grid, ops, params, mode, obs, q, wf, sources_list=srcs, tag=tag)
+        else:  # nothing emits
+            F, K, G = np.zeros((N, nout)), np.zeros((N, NK)), np.zeros(N, dtype=np.int64)
+        if keep_packets:
+            packets[(si, 0)] = (F, K, G)
+        sums[si, 0, :, 0] = F.sum(axis=0)
+        sums[si, 0, :, 1] = (F * F).sum(axis=0)
+        cnt[si, 0] = K.sum(axis=0)
+        mean = sums[si, 0, :, 0] / N
+        var = np.maximum(sums[si, 0, :, 1] / N - mean * mean, 0.0) / N
+        value[si] = scale * mean
+        stderr[si] = scale * np.sqrt(var)
+    extra = {"packets": packets}
+    if mode == 1:
+        extra["L_tot"] = ltot
+    return Result(value, stderr, np.zeros((len(specs), ng, nout)), sums, cnt, extra)
+
+
 def solve_albedo(grid, table, params: Params, spec_idx=None, keep_packets=False, contrib=False,
                  image_npix=0) -> Result:
     specs = _spec_list(table, spec_idx)
+    if params.g_sampling:
+        obs = None if (grid.geometry == 1 and params.obs_dir is None) else (
+            _f64(params.obs_dir) if params.obs_dir is not None else albedo_obs_dirs(params.obs_phase))
+        return _solve_gsampled(grid, table, params, 0, obs, specs, keep_packets)
     ng = table.ng
     if grid.geometry == 1:
         obs = None if params.obs_dir is None else _f64(params.obs_dir)
@@ -458,6 +561,9 @@ def solve_emission(grid, table, params: Params, spec_idx=None, keep_packets=Fals
                    image_npix=0) -> Result:
     """Correlated-k emission spectrum F_p(band, phase) [erg/s/cm^2/cm]."""
     specs = _spec_list(table, spec_idx)
+    if params.g_sampling:
+        obs = _f64(params.obs_dir) if params.obs_dir is not None else emission_obs_dirs(params.obs_phase)
+        return _solve_gsampled(grid, table, params, 1, obs, specs, keep_packets)
     ng = table.ng
     obs = _f64(params.obs_dir) if params.obs_dir is not None else emission_obs_dirs(params.obs_phase)
     nout = len(obs)
