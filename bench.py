@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-packets", type=int, default=30000)
     ap.add_argument("--transmission", type=int, default=1, help="also time the hi-res transmission workload")
+    ap.add_argument("--gsample", type=int, default=1,
+                    help="also run the workload with per-packet g sampling (composite), same packets per band")
     ap.add_argument("--albedo", type=int, default=1, help="also time the 1D albedo workload (plain / batched / graph)")
     ap.add_argument("--batch-scale", type=float, default=0.01,
                     help="packet scale of the 256-request multi-grid batch leg (0 = skip)")
@@ -318,6 +320,24 @@ def main():
                      "traffic_GBps": None if traffic is None else traffic / (kms / max(launches, 1) * 1e-3) / 1e9,
                      "valu_busy": VALU_BUSY if traffic is not None else None},
     }
+    if a.gsample:
+        print("[bench] per-packet g sampling (composite), same packets per band", flush=True)
+        kw = dict(n_packets=npk * table.ng, obs_phase=list(phases), spec_idx=bands, precision=M.MCRT_MIXED,
+                  seed=211015642, g_sampling=3, **tune)
+        ctx.solve_emission(gid, oid, table, **{**kw, "spec_idx": bands[:1]})  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gr = ctx.solve_emission(gid, oid, table, **kw)
+        torch.cuda.synchronize()
+        gt = time.perf_counter() - t0
+        grel = (gr["stderr"] / np.maximum(gr["value"], 1e-300)).ravel()
+        gneed = npk * table.ng * (grel / 1e-3) ** 2
+        gdiff = np.abs(gr["value"] - bres[-1]["value"]) / np.sqrt(gr["stderr"] ** 2 + bres[-1]["stderr"] ** 2)
+        out["g_sampled"] = {"scheme": "composite", "packets_per_band": npk * table.ng, "ms": gt * 1e3,
+                            "packets_per_s": pk_step / gt, "rel_se_median": float(np.median(grel)),
+                            "packets_per_band_for_1e-3_median": float(np.median(gneed)),
+                            "seconds_per_band_for_1e-3_median": float(np.median(gneed)) / (pk_step / gt),
+                            "vs_fixed_g_sigma_max": float(gdiff.max())}
     if pres is not None:
         # spectrum difference of the mixed form from the FP64 form on the same random stream
         dmix = np.abs(bres[-1]["value"] - pres[-1]["value"]) / np.abs(pres[-1]["value"])

@@ -189,7 +189,17 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   non-zero also fills mcrt_result.cf with the contribution functions.
  * image_npix: the same solves on a spherical grid: > 0 also fills
  *   mcrt_result.image with npix x npix images per band and observer
- *   (at most 4096). */
+ *   (at most 4096).
+ * g_sampling: albedo and emission with a correlated-k table: 0 = one solve
+ *   per (band, g) weighted by w_g; 1, 2, 3 = n_packets packets per BAND, each
+ *   drawing its g-ordinate (birth event, Philox block 3, slot a) from q(g)
+ *   and weighted by p(g)/q(g), p(g) = w_g (albedo) or w_g L_g / sum(w L)
+ *   (emission) (Sect. "G-ordinance biasing"): 1 unbiased (q = p), 2 uniform
+ *   (q = 1/N_g), 3 composite (q = (p + 1/N_g)/2).  The band's sums, counters
+ *   and value appear in its g = 0 slots of sums, counters and per_g; the
+ *   packet dump is [band][packet][observer]; the random key's tag with
+ *   decorrelate is 1 + band * ng.  Not with contrib, image_npix or
+ *   mcrt_solve_batch (EINVAL). */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -222,6 +232,7 @@ typedef struct {
     int32_t graph;
     int32_t contrib;
     int32_t image_npix;
+    int32_t g_sampling;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -62,6 +62,7 @@ struct OpacRes {
     double* T_grid = nullptr;  // [nT]
     double* lnP_grid = nullptr;
     double* k_ray_dev = nullptr;
+    double* gw_dev = nullptr;  // g-ordinate weights
     std::vector<DevBuf> bufs;
     size_t bytes = 0;
     int refs = 0;
@@ -598,6 +599,11 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     if (p->image_npix < 0 || p->image_npix > 4096) return fail(MCRT_EINVAL, "image_npix must be in [0, 4096]");
     if (p->image_npix && (!res->image || g->dev.geom != 0))
         return fail(MCRT_EINVAL, "images need result.image and a spherical grid");
+    const bool gs = p->g_sampling != 0;
+    if (p->g_sampling < 0 || p->g_sampling > 3) return fail(MCRT_EINVAL, "g_sampling must be 0 to 3");
+    if (gs && op->kind != MCRT_OPAC_CK) return fail(MCRT_EINVAL, "g-ordinate sampling needs a correlated-k table");
+    if (gs && (p->contrib || p->image_npix))
+        return fail(MCRT_EINVAL, "g-ordinate sampling does not combine with contribution functions or images");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const bool mixed = p->precision == MCRT_MIXED;
@@ -613,7 +619,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     const size_t opt_b = (size_t)ncell * 5 * (sizeof(double) + (mixed ? sizeof(float) : 0));
     const size_t src_b = mode == MCRT_MODE_EMISSION ? (size_t)ncell * 2 * sizeof(double) : 0;
     const size_t row_b = (size_t)N * prow * sizeof(double);
-    const size_t per_solve = opt_b + src_b + row_b;
+    // with g-ordinate sampling a band's packets (one range) serve its ng solves
+    const size_t per_solve = opt_b + src_b + (gs ? row_b / ng : row_b);
     int batch;
     if (sl.stream_ordered) {
         batch = serving_batch(ctx, p->max_batch, nsolve, per_solve);  // as admitted
@@ -629,13 +636,14 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         batch = std::max(1, std::min(std::min(batch, fit), nsolve));
     }
     batch = std::min(batch, kMaxSolvesPerLaunch);
+    if (gs) batch = std::max(ng, batch / ng * ng);  // whole bands per launch
     const int chunks = reduce_rows_chunks(N);
     void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_ps = nullptr,
                  *v_shift = nullptr, *v_solves, *v_slots, *v_ctr;
     if ((rc = scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * batch, &v_opt))) return rc;
     if (mixed && (rc = scratch(ctx, sl, st, "optics_f32", sizeof(float) * 5 * (size_t)ncell * batch, &v_optf)))
         return rc;
-    if ((rc = scratch(ctx, sl, st, "rows", row_b * batch, &v_rows))) return rc;
+    if ((rc = scratch(ctx, sl, st, "rows", row_b * (gs ? batch / ng : batch), &v_rows))) return rc;
     if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
     if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
     if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
@@ -703,8 +711,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         const double dpar[7] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
                                 p->mu0, (double)p->max_events};
         add(dpar, sizeof dpar);
-        const int64_t ipar[11] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
-                                  p->absorption, batch, A.ev_threshold, bpc, A.batch, npix};
+        const int64_t ipar[12] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+                                  p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling};
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
@@ -776,9 +784,22 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                 P.stats = sums + (size_t)sg * row_w + pw;
                 SolveDev& S = hsv[slot];
                 S = SolveDev{};
-                S.begin = (unsigned long long)slot * N;
-                S.n = N;
-                S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
+                if (gs) {  // the band's packets belong to its g = 0 solve; the others are empty ranges after it
+                    const unsigned long long band0 = (unsigned long long)(slot / ng) * N;
+                    S.begin = gi == 0 ? band0 : band0 + N;
+                    S.n = gi == 0 ? N : 0;
+                    S.pbase = band0;
+                    S.tag = p->decorrelate ? (uint32_t)(1 + b * ng) : 0u;
+                    S.gs_n = gi == 0 ? ng : 0;
+                    S.gs_scheme = p->g_sampling;
+                    S.gs_w = op->gw_dev;
+                } else {
+                    S.begin = (unsigned long long)slot * N;
+                    S.n = N;
+                    S.pbase = S.begin;
+                    S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
+                }
+                S.ltot = mode == MCRT_MODE_EMISSION ? P.stats : nullptr;
                 S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
                 S.grid = 0;
                 S.cdf = P.cdf;
@@ -810,13 +831,13 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                                     (double*)v_ps, st);
             A.solves = (const SolveDev*)v_solves;
             A.n_solves = nb;
-            A.total = (unsigned long long)nb * N;
+            A.total = (unsigned long long)(gs ? nb / ng : nb) * N;
             launch_init_dispensers(A.counter, A.total, st);
             launch_births(g->dev, A, false, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
             launch_transport_persistent(g->dev, A, mixed, false, pblocks, bpc, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
-            double* dump = p->packet_dump ? p->packet_dump + (size_t)s0 * N * no : nullptr;
+            double* dump = p->packet_dump ? p->packet_dump + (size_t)(gs ? s0 / ng : s0) * N * no : nullptr;
             launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
             // the next batch reuses the slots: in eager form its pageable host tables are
             // copied only after this batch ran
@@ -875,6 +896,32 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         for (int t = 0; t < kNCounters; ++t) cnt[(size_t)sg * kNCounters + t] = row[2 * no + t];
     }
     std::vector<double> gw = op->kind == MCRT_OPAC_CK ? op->g_weights : std::vector<double>{1.0};
+    if (gs) {  // band values from the band's packets (in its g = 0 row): pi sum F / N,
+               // or sum_g(w_g L_g) sum F / (N R_TOA^2); reported in the g = 0 slot
+        for (int sb = 0; sb < ns; ++sb) {
+            const double* row = hs.data() + (size_t)sb * ng * row_w;
+            double scale = kPi;
+            if (mode == MCRT_MODE_EMISSION) {
+                double lb = 0.0;
+                for (int gi = 0; gi < ng; ++gi) lb += op->g_weights[gi] * ltot[(size_t)sb * ng + gi];
+                scale = lb / (g->r_toa * g->r_toa);
+            }
+            for (int gi = 0; gi < ng; ++gi)
+                for (int o = 0; o < no; ++o) {
+                    const size_t at = ((size_t)sb * ng + gi) * no + o;
+                    if (gi > 0) {
+                        val[at] = se[at] = 0.0;
+                        continue;
+                    }
+                    const double m = row[2 * o] / Nd;
+                    const double var = std::max(row[2 * o + 1] / Nd - m * m, 0.0) / Nd;
+                    val[at] = scale * m;
+                    se[at] = scale * std::sqrt(var);
+                }
+        }
+        gw.assign(ng, 0.0);
+        gw[0] = 1.0;
+    }
     fill_results(pl, val, se, gw, hs, row_w, cnt, ltot, res);
     if (v_cf) {  // contribution functions, normalised per (band, observer)
         HIPTRY(hipMemcpy(res->cf, v_cf, sizeof(double) * cf_n, hipMemcpyDeviceToHost));
@@ -903,8 +950,9 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     SolvePlan pl;
     rc = plan_common(def_stream, g, op, p, MCRT_MODE_TRANSMISSION, pl);
     if (rc) return rc;
-    if (p->contrib || p->image_npix)
-        return fail(MCRT_EINVAL, "contribution functions and images are defined for albedo and emission");
+    if (p->contrib || p->image_npix || p->g_sampling)
+        return fail(MCRT_EINVAL, "contribution functions, images and g-ordinate sampling are defined for "
+                                 "albedo and emission");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = pl.stream;
     const int ncell = g->ncell;
@@ -1002,8 +1050,8 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
                 const mcrt_solve_params* common, mcrt_result* results)
 {
     if (n_items < 1 || !items || !common || !results) return fail(MCRT_EINVAL, "batch needs items, params, results");
-    if (common->contrib || common->image_npix)
-        return fail(MCRT_EINVAL, "contribution functions and images are computed by single solves only");
+    if (common->contrib || common->image_npix || common->g_sampling)
+        return fail(MCRT_EINVAL, "contribution functions, images and g-ordinate sampling are single-solve options");
     struct Item {
         Lease ls;
         SolvePlan pl;
@@ -1169,6 +1217,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
             P.stats = sums + (size_t)sg * row_w + pw;
             SolveDev& S = hsv[li][sg - s0];
             S.begin = begin;
+            S.pbase = begin;
             S.n = I.p.n_packets;
             begin += S.n;
             S.tag = common->decorrelate ? (uint32_t)(1 + b * I.pl.ng + F.g) : 0u;
@@ -1754,6 +1803,8 @@ int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, int32_t* opac
     if ((rc = upload(ctx, O->bufs, O->bytes, d->T_grid, (size_t)d->nT, &O->T_grid))) return cleanup(rc);
     if ((rc = upload(ctx, O->bufs, O->bytes, lnP.data(), lnP.size(), &O->lnP_grid))) return cleanup(rc);
     if ((rc = upload(ctx, O->bufs, O->bytes, d->k_ray, (size_t)d->nspec, &O->k_ray_dev))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, O->g_weights.data(), O->g_weights.size(), &O->gw_dev)))
+        return cleanup(rc);
     int32_t id = ctx->next_opac++;
     ctx->opacs[id] = std::move(O);
     *opac_id = id;

@@ -61,6 +61,7 @@ struct SolveDev {
     const double* wbirth;  // emission only
     unsigned long long begin;  // global index of the solve's first packet
     unsigned long long n;      // packets of the solve
+    unsigned long long pbase;  // packet id 0 of the random stream (begin, or the band's first packet)
     uint32_t tag;
     int mode;  // 0 albedo, 1 emission
     int grid;  // index into BatchArgs.grids (multi-grid launches)
@@ -71,6 +72,13 @@ struct SolveDev {
     double* img;
     double cf_w;
     const double* cf_ltot;
+    // per-packet g-ordinate sampling: on the first solve of a band, the number
+    // of g-ordinates (the band's solves follow it) and the scheme
+    // (1 unbiased, 2 uniform, 3 composite); 0 = fixed-g solve
+    int gs_n;
+    int gs_scheme;
+    const double* gs_w;    // g-ordinate weights of the table
+    const double* ltot;    // emission: L_tot of this solve (written by the preparation)
 };
 
 struct BatchArgs {

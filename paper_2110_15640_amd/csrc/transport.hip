@@ -37,9 +37,9 @@ using namespace dev;
 enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 5 };
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
 // Birth record of a packet, kept in the counter columns of its row until the
-// packet dies: position, direction, weight, then cell * 8 + (entry face + 1)
-// (-1: nothing emits).
-enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL };
+// packet dies: position, direction, weight, cell * 8 + (entry face + 1)
+// (-1: nothing emits), then the index of the solve whose optics it uses.
+enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE };
 
 // Per-lane state that the cell walk does not touch lives in LDS (one slot
 // per lane, structure of arrays) so the registers hold only the walking ray;
@@ -182,7 +182,7 @@ __device__ __forceinline__ void start_peel(Lane& L, const GridDev& g, const Batc
 
 __device__ __forceinline__ void start_flight(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
-    U2 u = draw(A.seed, S.tag, L.gid() - S.begin, L.e(), 0);
+    U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
     L.tau = -log(u.a);
     wk_start(g, L.w, L.sx(), L.sy(), L.sz(), L.sdx(), L.sdy(), L.sdz(), L.si(), L.sj(), L.sk(), L.sef());
     L.ncw = 0;
@@ -277,7 +277,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
 {
     const int c = L.cell(g);
     const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
-    const unsigned long long q = L.gid() - S.begin;
+    const unsigned long long q = L.gid() - S.pbase;
     if (A.absorption != 1) {
         L.w_abs += L.W * (1.0 - om);
         L.W = L.W * om;
@@ -450,12 +450,56 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 {
     const unsigned long long gid = (unsigned long long)blockIdx.x * 256 + threadIdx.x;
     if (gid >= A.total) return;
-    const SolveDev& S = A.solves[solve_of(A, gid)];
-    const GridDev& g = MULTI ? A.grids[S.grid] : g1;
+    int sv = solve_of(A, gid);
+    const GridDev& g = MULTI ? A.grids[A.solves[sv].grid] : g1;
     const double r_toa = g.r[g.nlay];
-    const unsigned long long q = gid - S.begin;
     double* b = A.rows + gid * (unsigned long long)A.row_w + A.n_out;
-    const uint32_t tag = S.tag;
+    const unsigned long long q = gid - A.solves[sv].pbase;
+    const uint32_t tag = A.solves[sv].tag;
+    double wmul = 1.0;
+    if (A.solves[sv].gs_n > 0) {
+        // per-packet g-ordinate: p(g) = w_g (albedo) or w_g L_g / sum(w L)
+        // (emission); sampled from q(g) (1: p, 2: uniform, 3: (p + 1/N_g)/2)
+        // with the smallest g whose cumulative weight exceeds u times the total
+        const SolveDev& H = A.solves[sv];
+        const int ng = H.gs_n, scheme = H.gs_scheme;
+        double ptot = 0.0;
+        for (int h = 0; h < ng; ++h) ptot += H.ltot ? H.gs_w[h] * *A.solves[sv + h].ltot : H.gs_w[h];
+        if (!(ptot > 0.0)) {  // nothing emits in any g-ordinate
+            b[B_W] = 0.0;
+            b[B_CELL] = -1.0;
+            b[B_SOLVE] = (double)sv;
+            return;
+        }
+        double qtot = 0.0;
+        for (int h = 0; h < ng; ++h) {
+            const double raw = H.ltot ? H.gs_w[h] * *A.solves[sv + h].ltot : H.gs_w[h];
+            qtot += scheme == 1 ? raw : (scheme == 2 ? 1.0 : 0.5 * (raw / ptot) + 0.5 / ng);
+        }
+        const double target = draw(A.seed, tag, q, 0, 3).a * qtot;
+        double cum = 0.0;
+        int gi = ng - 1;
+        double pg = 0.0, qg = 0.0;
+        for (int h = 0; h < ng; ++h) {
+            const double raw = H.ltot ? H.gs_w[h] * *A.solves[sv + h].ltot : H.gs_w[h];
+            const double qh = scheme == 1 ? raw : (scheme == 2 ? 1.0 : 0.5 * (raw / ptot) + 0.5 / ng);
+            cum += qh;
+            if (cum > target) {
+                gi = h;
+                pg = raw / ptot;
+                qg = qh;
+                break;
+            }
+            if (h == ng - 1) {
+                pg = raw / ptot;
+                qg = qh;
+            }
+        }
+        wmul = scheme == 1 ? 1.0 : (scheme == 2 ? pg * ng : pg / qg);
+        sv += gi;
+    }
+    const SolveDev& S = A.solves[sv];
+    b[B_SOLVE] = (double)sv;
     if (S.mode == 0) {
         U2 u = draw(A.seed, tag, q, 0, 0);
         if (g.geom == 1) {
@@ -476,7 +520,7 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
             int c = ((g.nlay - 1) * g.nlat + rs.j) * g.nlon + rs.i;
             b[B_CELL] = (double)c * 8.0 + (double)(F_OUT + 1);
         }
-        b[B_W] = 1.0;
+        b[B_W] = wmul;
         return;
     }
     const int ncell = g.nlon * g.nlat * g.nlay;
@@ -515,7 +559,7 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
     b[B_DX] = sp * cos(psi);
     b[B_DY] = sp * sin(psi);
     b[B_DZ] = mu;
-    b[B_W] = S.wbirth[c];
+    b[B_W] = S.wbirth[c] * wmul;
     b[B_CELL] = (double)c * 8.0 + (double)(F_NONE + 1);
 }
 
@@ -523,13 +567,13 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 // flight for albedo, the emission-point peel-off, or finish if none emits).
 __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
 {
-    const int sv = solve_of(A, L.gid());
+    const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    const int sv = (int)b[B_SOLVE];
     const SolveDev& S = A.solves[sv];
     L.C->st[L.t] = 0u;
     L.set_solve(sv);
     L.smode() = S.mode;
     for (int o = 0; o < A.n_out; ++o) L.Fo(o) = 0.0;
-    const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
     L.w_abs = 0.0;
     L.w_rr() = 0.0;
     L.ncross = 0;
@@ -637,11 +681,10 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
             }
             if (L.mode == M_DEAD && exhausted) L.mode = M_IDLE;
             if (L.mode == M_BIRTH) {
-                const int sv = solve_of(A, L.gid());
-                const SolveDev& S = A.solves[sv];
-                if (MULTI) lgrid = S.grid;
+                if (MULTI) lgrid = A.solves[solve_of(A, L.gid())].grid;
                 const GridDev& gb = MULTI ? A.grids[lgrid] : g1;
                 act = birth(L, gb, A);
+                const SolveDev& S = A.solves[L.solve()];  // the solve the birth record chose
                 aext = S.a_ext;
                 aabs = S.a_abs;
             }

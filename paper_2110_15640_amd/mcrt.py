@@ -60,7 +60,8 @@ class SolveParams(ctypes.Structure):
                 ("n_b", _i32), ("n_alpha", _i32), ("r_star", _dbl), ("stream", _vp),
                 ("packet_dump", _vp), ("profile", _i32), ("max_batch", _i32),
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32),
-                ("graph", _i32), ("contrib", _i32), ("image_npix", _i32)]
+                ("graph", _i32), ("contrib", _i32), ("image_npix", _i32),
+                ("g_sampling", _i32)]
 
 
 class BatchItem(ctypes.Structure):

@@ -408,3 +408,51 @@ def test_contribution_functions_and_images_parity(ctx, torch_dev):
         ctx.free_grid(x)
     for x in (oid, soid):
         ctx.free_opacity(x)
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+def test_g_sampling_parity(ctx, torch_dev, scheme):
+    """Per-packet g-ordinate sampling (unbiased, uniform, composite): every
+    packet's peel-off sums and the band values against the oracle, albedo and
+    emission; one band per launch equals all bands in one launch bit for bit."""
+    _log(f"g-ordinate sampling parity, scheme {scheme}: emission 12x6x8 (2 bands x 4 g), albedo sphere")
+    grid, table, phases = I.make_emission_3d(12, 6, 8, nband=2, ng=4, config_no=50)
+    rng = np.random.default_rng(9)
+    grid.cld_ksca = rng.uniform(0, 3e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 1e-2, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.4, 0.8, grid.ncell).astype(np.float32)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 2500
+    ph = list(phases[:3])
+    dump = dump_buffer(torch_dev, 2, n, 3)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=91, obs_phase=ph, g_sampling=scheme,
+                             packet_dump=dump, decorrelate=1)
+    ref = O.solve_emission(grid, table, O.Params(n_packets=n, seed=91, obs_phase=tuple(ph), g_sampling=scheme,
+                                                 decorrelate=True), keep_packets=True)
+    d = dump.cpu().numpy().reshape(2, n, 3)
+    for s in range(2):
+        F = ref.extra["packets"][(s, 0)][0]
+        scale = max(float(np.abs(F).max()), 1e-300)
+        bad = np.abs(d[s] - F) > RTOL * np.abs(F) + 1e-12 * scale
+        assert not bad.any(), (s, np.argwhere(bad)[:5].tolist())
+    np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL)
+    np.testing.assert_allclose(got["stderr"], ref.stderr, rtol=1e-7)
+    np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL, atol=1e-300)
+    one = ctx.solve_emission(gid, oid, table, n_packets=n, seed=91, obs_phase=ph, g_sampling=scheme,
+                             decorrelate=1, max_batch=4)
+    assert np.array_equal(one["sums"], got["sums"]) and np.array_equal(one["value"], got["value"])
+    _, t2, _ = I.make_emission_3d(12, 6, 8, nband=2, ng=4, config_no=51)
+    t2.k_ray = t2.k_ray * 1e3
+    sph = I.make_sphere(12, 6, 8, seed=53)
+    sid, soid = ctx.upload_grid(sph), ctx.upload_opacity(t2)
+    got = ctx.solve_albedo(sid, soid, t2, n_packets=3000, seed=93, obs_phase=[0.0, 0.9], g_sampling=scheme)
+    ref = O.solve_albedo(sph, t2, O.Params(n_packets=3000, seed=93, obs_phase=(0.0, 0.9), g_sampling=scheme))
+    np.testing.assert_allclose(got["value"], ref.value, rtol=RTOL)
+    np.testing.assert_allclose(got["counters"][:, 0], ref.counters[:, 0], rtol=RTOL,
+                               atol=1e-12 * max(ref.counters.max(), 1.0))
+    with pytest.raises(Exception):
+        ctx.solve_transmission(gid, oid, table, n_b=8, n_alpha=8, g_sampling=scheme)
+    for x in (gid, sid):
+        ctx.free_grid(x)
+    for x in (oid, soid):
+        ctx.free_opacity(x)
