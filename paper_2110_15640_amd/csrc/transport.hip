@@ -192,7 +192,10 @@ __device__ __forceinline__ void start_flight(Lane& L, const GridDev& g, const Ba
 // One cell of a walk.  Flights and peel-off rays share the exit search, the
 // extinction gather and the crossing (a single inlined copy of each, so that
 // a wave holding both kinds executes them once); they differ only in how the
-// optical depth is used and in when the walk stops.
+// optical depth is used and in when the walk stops.  Every walking lane runs
+// the crossing: a lane whose walk ends in this cell (interaction, surface
+// hit, end of a peel-off) discards its walker afterwards, so the walker is
+// never kept in two versions.
 template <bool MIXED>
 __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
                                           const BatchArgs& A)
@@ -204,50 +207,41 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     const bool flight = L.mode == M_FLIGHT;
     const bool cont = flight && A.absorption == 1;
     const double ae = ld<MIXED>(aext, c);
+    const double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
+    const double a = cont ? (ae - aa) : ae;
+    const bool lost = flight && f == F_NONE && !(a > 0.0);
+    const bool hit = flight && !lost && a > 0.0 && L.tau < a * s;
+    const bool pend = !flight && f == F_NONE;
+    const double ds = hit ? L.tau / a : s;
+    // the interaction point, from the walker before it moves
+    const double ti = L.w.t + ds;
+    const double ex = L.w.px + ti * L.w.dx, ey = L.w.py + ti * L.w.dy, ez = L.w.pz + ti * L.w.dz;
+    const int ei = L.w.i, ej = L.w.j, ek = L.w.k;
     if (flight) {
-        const double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
-        const double a = cont ? (ae - aa) : ae;
-        if (f == F_NONE && !(a > 0.0)) {
-            L.ncross += L.ncw;
-            L.mode = M_EVENT;
-            L.ev = E_LOST;
-            return;
-        }
-        if (a > 0.0 && L.tau < a * s) {
-            double ds = L.tau / a;
-            if (cont) {
-                double wn = L.W * exp(-aa * ds);
-                L.w_abs = L.w_abs + (L.W - wn);
-                L.W = wn;
-            }
-            const double ti = L.w.t + ds;
-            L.sx() = L.w.px + ti * L.w.dx;
-            L.sy() = L.w.py + ti * L.w.dy;
-            L.sz() = L.w.pz + ti * L.w.dz;
-            L.set_cell(L.w.i, L.w.j, L.w.k);
-            L.set_sef(F_NONE);
-            L.ncross += L.ncw;
-            L.mode = M_EVENT;
-            L.ev = E_INTERACT;
-            return;
-        }
-        L.tau = L.tau - a * s;
-        if (cont) {
-            double wn = L.W * exp(-aa * s);
+        if (!lost && !hit) L.tau = L.tau - a * s;
+        if (cont && !lost) {
+            double wn = L.W * exp(-aa * ds);
             L.w_abs = L.w_abs + (L.W - wn);
             L.W = wn;
         }
-    } else {
-        if (f == F_NONE) {
-            L.ncross += L.ncw;
-            L.tau = INFINITY;
-            L.mode = M_EVENT;
-            L.ev = E_PEEL_DONE;
-            return;
-        }
+    } else if (!pend) {
         L.tau = L.tau + ae * s;
     }
     const bool inside = wk_cross(g, L.w, f, tf);
+    if (lost || hit || pend) {
+        L.ncross += L.ncw;
+        L.mode = M_EVENT;
+        if (hit) {
+            L.sx() = ex;
+            L.sy() = ey;
+            L.sz() = ez;
+            L.set_cell(ei, ej, ek);
+            L.set_sef(F_NONE);
+        }
+        if (pend) L.tau = INFINITY;
+        L.ev = lost ? E_LOST : (hit ? E_INTERACT : E_PEEL_DONE);
+        return;
+    }
     L.ncw++;
     bool done;
     if (flight) {
