@@ -164,29 +164,36 @@ __device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const doub
     }
 }
 
-__device__ __forceinline__ void start_peel(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs)
+// Start the lane's next walk from its event point: a flight along the
+// packet direction (optical depth drawn from the event's block 0, slot a) or
+// a peel-off ray toward the current observer.  Both use one inlined walker
+// start, so a wave starting both kinds runs it once.
+__device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs,
+                                           bool flight)
 {
-    double ox, oy, oz;
-    observer(L, A, sobs, ox, oy, oz);
-    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), ox, oy, oz, L.si(), L.sj(), L.sk(), F_NONE);
-    L.tau = 0.0;
+    double dx, dy, dz;
+    int ef;
+    if (flight) {
+        const SolveDev& S = A.solves[L.solve()];
+        U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
+        L.tau = -log(u.a);
+        dx = L.sdx();
+        dy = L.sdy();
+        dz = L.sdz();
+        ef = L.sef();
+    } else {
+        observer(L, A, sobs, dx, dy, dz);
+        L.tau = 0.0;
+        ef = F_NONE;
+    }
+    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
     L.ncw = 0;
-    if (g.geom == 1 && !(oz > 0.0)) {  // a slab ray that never reaches the top
+    L.mode = flight ? M_FLIGHT : M_PEEL;
+    if (!flight && g.geom == 1 && !(dz > 0.0)) {  // a slab peel-off ray that never reaches the top
         L.tau = INFINITY;
         L.mode = M_EVENT;
         L.ev = E_PEEL_DONE;
-        return;
     }
-    L.mode = M_PEEL;
-}
-
-__device__ __forceinline__ void start_flight(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
-{
-    U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
-    L.tau = -log(u.a);
-    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), L.sdx(), L.sdy(), L.sdz(), L.si(), L.sj(), L.sk(), L.sef());
-    L.ncw = 0;
-    L.mode = M_FLIGHT;
 }
 
 // One cell of a walk.  Flights and peel-off rays share the exit search, the
@@ -684,8 +691,7 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
             }
         }
         const GridDev& ga = MULTI ? A.grids[lgrid] : g1;
-        if (act == A_FLIGHT) start_flight(L, ga, A, A.solves[L.solve()]);
-        else if (act == A_PEEL) start_peel(L, ga, A, sobs);
+        if (act == A_FLIGHT || act == A_PEEL) start_walk(L, ga, A, sobs, act == A_FLIGHT);
         if (__ballot(L.mode != M_IDLE) == 0) break;
     }
 }
