@@ -36,11 +36,11 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "b563fd4dcf10b1b46e0c6b56b945de5a7cd28ed785a4325e04a2cce58569d25b"
-TRAFFIC_BYTES_PER_SOLVE = (351497454 * (1048576 / 524304) + 23571070 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "db914ba0580ae7ff284760697ed0294615094b5b07326239a2d210434e2d923a"
+TRAFFIC_BYTES_PER_SOLVE = (126606277 * (1048576 / 524305) + 24204059 * 1.0) * 1024 / 168
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
-VALU_BUSY = 0.912
+VALU_BUSY = 0.914
 
 
 def parse():
