@@ -118,6 +118,34 @@ double orc_sample_rayleigh(double zeta)
 }
 
 /* HG cos(theta) by the paper's inverse CDF; isotropic when |g| < 1e-6. */
+double orc_sample_hg(double zeta, double g);
+
+/* Two-term HG (Sect. 3, aerosol scattering): a forward lobe g1 = g with
+ * weight a = 1 - g2^2 and a backward lobe g2 = -g/2 (the paper's default
+ * relation between the lobes and the asymmetry factor). */
+static void tthg_lobes(double g, double *g1, double *g2, double *a)
+{
+    *g1 = g;
+    *g2 = -0.5 * g;
+    *a = 1.0 - (*g2) * (*g2);
+}
+
+double orc_phase_tthg(double mu, double g)
+{
+    double g1, g2, a;
+    tthg_lobes(g, &g1, &g2, &a);
+    return a * orc_phase_hg(mu, g1) + (1.0 - a) * orc_phase_hg(mu, g2);
+}
+
+/* A lobe is chosen with zeta_lobe < a (forward) and cos(theta) is sampled
+ * from that lobe's HG function with zeta. */
+double orc_sample_tthg(double zeta_lobe, double zeta, double g)
+{
+    double g1, g2, a;
+    tthg_lobes(g, &g1, &g2, &a);
+    return orc_sample_hg(zeta, zeta_lobe < a ? g1 : g2);
+}
+
 double orc_sample_hg(double zeta, double g)
 {
     double mu;
@@ -589,6 +617,7 @@ typedef struct {
     double rr_survive;
     double tau_peel_max;
     double mu0;           /* slab incidence cosine; <= 0: uniform over disk */
+    int64_t cloud_phase;  /* 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein */
 } orc_params;
 
 typedef struct {
@@ -818,7 +847,8 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         for (int o = 0; o < nout; ++o) {
             const double *ov = slab_back ? oback : obs + 3 * o;
             double mu = d[0] * ov[0] + d[1] * ov[1] + d[2] * ov[2];
-            double theta = (pg * orc_phase_rayleigh(mu) + (1.0 - pg) * orc_phase_hg(mu, gc)) / (4.0 * ORC_PI);
+            double pc = pr->cloud_phase == 1 ? orc_phase_tthg(mu, gc) : orc_phase_hg(mu, gc);
+            double theta = (pg * orc_phase_rayleigh(mu) + (1.0 - pg) * pc) / (4.0 * ORC_PI);
             double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
             F[o] = F[o] + f;
@@ -830,7 +860,16 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         }
         double u1a, u1b;
         orc_draw(pr->seed, tag, pid, e, 1, &u1a, &u1b);
-        double mu = (usel < pg) ? orc_sample_rayleigh(u1a) : orc_sample_hg(u1a, gc);
+        double mu;
+        if (usel < pg) {
+            mu = orc_sample_rayleigh(u1a);
+        } else if (pr->cloud_phase == 1) {
+            double u2a, u2b;  /* the lobe: block 2, slot b */
+            orc_draw(pr->seed, tag, pid, e, 2, &u2a, &u2b);
+            mu = orc_sample_tthg(u2b, u1a, gc);
+        } else {
+            mu = orc_sample_hg(u1a, gc);
+        }
         orc_rotate(d, mu, 2.0 * ORC_PI * u1b);
         if (W < pr->rr_threshold * W0) {
             double u2a, u2b;

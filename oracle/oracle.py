@@ -54,7 +54,8 @@ class _Params(ctypes.Structure):
                 ("tag", ctypes.c_int64), ("max_events", ctypes.c_int64),
                 ("max_cross", ctypes.c_int64), ("n_obs", ctypes.c_int64),
                 ("rr_threshold", ctypes.c_double), ("rr_survive", ctypes.c_double),
-                ("tau_peel_max", ctypes.c_double), ("mu0", ctypes.c_double)]
+                ("tau_peel_max", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("cloud_phase", ctypes.c_int64)]
 
 
 class _Optics(ctypes.Structure):
@@ -88,6 +89,10 @@ def lib():
         L.orc_sample_rayleigh.restype = dbl
         L.orc_sample_hg.argtypes = [dbl, dbl]
         L.orc_sample_hg.restype = dbl
+        L.orc_phase_tthg.argtypes = [dbl, dbl]
+        L.orc_phase_tthg.restype = dbl
+        L.orc_sample_tthg.argtypes = [dbl, dbl, dbl]
+        L.orc_sample_tthg.restype = dbl
         L.orc_rotate.argtypes = [vp, dbl, dbl]
         L.orc_planck.argtypes = [dbl, dbl]
         L.orc_planck.restype = dbl
@@ -160,6 +165,14 @@ def phase_rayleigh(mu):
 
 def phase_hg(mu, g):
     return lib().orc_phase_hg(float(mu), float(g))
+
+
+def phase_tthg(mu, g):
+    return lib().orc_phase_tthg(float(mu), float(g))
+
+
+def sample_tthg(z_lobe, z, g):
+    return lib().orc_sample_tthg(float(z_lobe), float(z), float(g))
 
 
 def rotate(d, mu, psi):
@@ -288,6 +301,7 @@ class Params:
     n_alpha: int = 360
     r_star: float = 6.957e10
     g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
+    cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
     threads: int = 0
 
 
@@ -337,7 +351,8 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     nobs = 0 if obs is None else len(obs)
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
                  int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
-                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0)
+                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
+                 int(params.cloud_phase))
     op = _Optics(optics.a_ext.ctypes.data, optics.a_abs.ctypes.data, optics.omega.ctypes.data,
                  optics.p_gas.ctypes.data, optics.g_cld.ctypes.data)
     nout = 1 if (grid.geometry == 1 and nobs == 0) else nobs
@@ -393,7 +408,8 @@ def transport_gsampled(grid, optics_list, params: Params, mode: int, obs, q, wfa
     nobs = 0 if obs is None else len(obs)
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
                  int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
-                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0)
+                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
+                 int(params.cloud_phase))
     ops = (_Optics * ng)()
     for h, op in enumerate(optics_list):
         ops[h] = _Optics(op.a_ext.ctypes.data, op.a_abs.ctypes.data, op.omega.ctypes.data,
