@@ -199,7 +199,12 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   and value appear in its g = 0 slots of sums, counters and per_g; the
  *   packet dump is [band][packet][observer]; the random key's tag with
  *   decorrelate is 1 + band * ng.  Not with contrib, image_npix or
- *   mcrt_solve_batch (EINVAL). */
+ *   mcrt_solve_batch (EINVAL).
+ * cloud_phase: 0 = Henyey-Greenstein clouds; 1 = two-term HG (Sect. 3,
+ *   aerosol scattering): forward lobe g1 = g with weight a = 1 - g2^2 and
+ *   backward lobe g2 = -g/2, the lobe of a cloud scattering chosen by Philox
+ *   block 2, slot b of the event (zeta < a: forward); the peel-off uses the
+ *   mixture a P_HG(g1) + (1 - a) P_HG(g2). */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -233,6 +238,7 @@ typedef struct {
     int32_t contrib;
     int32_t image_npix;
     int32_t g_sampling;
+    int32_t cloud_phase;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

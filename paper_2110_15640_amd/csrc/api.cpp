@@ -402,6 +402,7 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
     if (!(p->tau_vert_max >= 0.0)) return fail(MCRT_EINVAL, "tau_vert_max must be >= 0");
     if (p->max_events < 1) return fail(MCRT_EINVAL, "max_events must be >= 1");
     if (p->absorption != MCRT_SURVIVAL && p->absorption != MCRT_CONTINUOUS) return fail(MCRT_EINVAL, "bad absorption");
+    if (p->cloud_phase != 0 && p->cloud_phase != 1) return fail(MCRT_EINVAL, "cloud_phase must be 0 (HG) or 1 (TTHG)");
     if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
     if (mode == MCRT_MODE_EMISSION && g->dev.geom != 0) return fail(MCRT_EINVAL, "emission needs a spherical grid");
     if (p->n_obs == 0) {
@@ -683,6 +684,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     for (int q = 0; q < 3 * pl.n_obs; ++q) A.obs[0][q] = A.obs[1][q] = pl.obs[q];
     A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
+    A.cloud_phase = p->cloud_phase;
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     if (npix) {
@@ -711,8 +713,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         const double dpar[7] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
                                 p->mu0, (double)p->max_events};
         add(dpar, sizeof dpar);
-        const int64_t ipar[12] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
-                                  p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling};
+        const int64_t ipar[13] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+                                  p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling,
+                                  p->cloud_phase};
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
@@ -1176,6 +1179,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     }
     A.batch = common->tune_wave_batch > 0 ? common->tune_wave_batch : 64;
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
+    A.cloud_phase = common->cloud_phase;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     const bool prof = common->profile != 0;

@@ -103,6 +103,7 @@ struct BatchArgs {
     double obs[2][3 * kMaxObs];  // observer directions for albedo [0] and emission [1] solves
     int batch;         // packets a wave takes from the dispenser at once
     int ev_threshold;  // waiting lanes that trigger event handling
+    int cloud_phase;   // 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
     // images: npix x npix pixels over [-img_half, img_half]^2 of each
     // observer's sky plane, horizontal / vertical unit vectors per observer
     int npix;

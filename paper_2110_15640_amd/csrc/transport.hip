@@ -285,10 +285,17 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
     }
     const double usel = draw(A.seed, S.tag, q, L.e(), 0).b;  // scatterer choice of this event
     U2 u1 = draw(A.seed, S.tag, q, L.e(), 1);
+    // two-term HG clouds: the forward lobe g with weight 1 - (g/2)^2 or the
+    // backward lobe -g/2, chosen by block 2, slot b of the event
+    double globe = gc;
+    if (A.cloud_phase == 1 && !(usel < pg)) {
+        const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
+        globe = draw(A.seed, S.tag, q, L.e(), 2).b < a ? gc : g2;
+    }
     if (MIXED) {
         float z = fminf((float)u1.a, 0.99999994f);
         float mu;
-        float g32 = (float)gc;
+        float g32 = (float)globe;
         if ((float)usel < (float)pg) {
             float qq = 4.0f * z - 2.0f;
             float u = cbrtf(qq + sqrtf(qq * qq + 1.0f));
@@ -323,7 +330,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         L.sdy() = ddy / n;
         L.sdz() = ddz / n;
     } else {
-        double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, gc);
+        double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, globe);
         rotate_dir(L.sdx(), L.sdy(), L.sdz(), mu, 2.0 * kPi * u1.b);
     }
     if (L.W < A.rr_threshold * L.W0()) {
@@ -374,10 +381,17 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 float mu = (float)(L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz);
                 float pgf = (float)pg, gcf = (float)gc;
                 float pr = 0.75f * (1.0f + mu * mu);
-                float ph = 1.0f;
-                if (fabsf(gcf) >= 1e-6f) {
-                    float den = 1.0f + gcf * gcf - 2.0f * gcf * mu;
-                    ph = (1.0f - gcf * gcf) / (den * sqrtf(den));
+                auto hgf = [mu](float gg) {
+                    if (!(fabsf(gg) >= 1e-6f)) return 1.0f;
+                    const float den = 1.0f + gg * gg - 2.0f * gg * mu;
+                    return (1.0f - gg * gg) / (den * sqrtf(den));
+                };
+                float ph;
+                if (A.cloud_phase == 1) {
+                    const float g2 = -0.5f * gcf, af = 1.0f - g2 * g2;
+                    ph = af * hgf(gcf) + (1.0f - af) * hgf(g2);
+                } else {
+                    ph = hgf(gcf);
                 }
                 float theta = (pgf * pr + (1.0f - pgf) * ph) * (float)(0.25 / kPi);
                 float att = L.tau < INFINITY ? __expf(-(float)L.tau) : 0.0f;
@@ -385,7 +399,14 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 f = (double)(w * theta * att);
             } else {
                 double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
-                double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * p_hg(mu, gc)) / (4.0 * kPi);
+                double pc;
+                if (A.cloud_phase == 1) {
+                    const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
+                    pc = a * p_hg(mu, gc) + (1.0 - a) * p_hg(mu, g2);
+                } else {
+                    pc = p_hg(mu, gc);
+                }
+                double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * pc) / (4.0 * kPi);
                 double att = exp(-L.tau);
                 f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
             }

@@ -456,3 +456,31 @@ def test_g_sampling_parity(ctx, torch_dev, scheme):
         ctx.free_grid(x)
     for x in (oid, soid):
         ctx.free_opacity(x)
+
+
+def test_tthg_clouds_parity(ctx, torch_dev):
+    """Two-term HG clouds: every packet against the oracle (emission with
+    clouds, FP64), the albedo spectrum, and the mixed form within 1e-3 / 3 sigma."""
+    _log("two-term HG clouds: emission 16x8x10 with clouds, albedo sphere, mixed vs fp64")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2, config_no=60)
+    rng = np.random.default_rng(13)
+    grid.cld_ksca = rng.uniform(0, 6e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 5e-3, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.3, 0.9, grid.ncell).astype(np.float32)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 1500
+    dump = dump_buffer(torch_dev, 4, n, 4)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=95, obs_phase=phases, packet_dump=dump, cloud_phase=1)
+    ref = O.solve_emission(grid, table, O.Params(n_packets=n, seed=95, obs_phase=tuple(phases), cloud_phase=1),
+                           keep_packets=True)
+    check_packets(dump, ref, (2, 2, n, 4))
+    check_solve(got, ref)
+    alb = ctx.solve_albedo(gid, oid, table, n_packets=4000, seed=97, obs_phase=[0.0, 1.1], cloud_phase=1)
+    aref = O.solve_albedo(grid, table, O.Params(n_packets=4000, seed=97, obs_phase=(0.0, 1.1), cloud_phase=1))
+    np.testing.assert_allclose(alb["value"], aref.value, rtol=RTOL)
+    mix = ctx.solve_albedo(gid, oid, table, n_packets=4000, seed=97, obs_phase=[0.0, 1.1], cloud_phase=1,
+                           precision=M.MCRT_MIXED)
+    assert np.all(np.abs(mix["value"] - alb["value"]) <= np.maximum(3.0 * alb["stderr"], 1e-3 * np.abs(alb["value"])))
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
