@@ -618,6 +618,7 @@ typedef struct {
     double tau_peel_max;
     double mu0;           /* slab incidence cosine; <= 0: uniform over disk */
     int64_t cloud_phase;  /* 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein */
+    double surface_albedo; /* 0: absorbing lower boundary; > 0: Lambert surface */
 } orc_params;
 
 typedef struct {
@@ -838,10 +839,43 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         tau = -log(ua);
         int term = walk_flight(g, op, &ry, d, tau, cont, &W, &K[K_ABS], pr->max_cross, &ncross);
         if (term == T_ESCAPE) { K[K_ESC] += W; break; }
-        if (term == T_SURFACE) { K[K_SURF] += W; break; }
+        if (term == T_SURFACE && !(pr->surface_albedo > 0.0)) { K[K_SURF] += W; break; }
         if (term == T_LOST) { K[K_LOST] += W; K[K_NLOST] += 1.0; break; }
-        /* interaction in cell c */
         K[K_NINT] += 1.0;
+        if (term == T_SURFACE) {
+            /* Lambert surface (Sect. 3, Lambertian surface scattering): a
+             * peel-off f = W A_s max(n.o, 0)/pi e^{-tau} toward every observer,
+             * then W <- W A_s and a new direction at cos(theta) = sqrt(zeta)
+             * (block 1, slot a) from the outward normal n, azimuth 2 pi zeta'
+             * (block 1, slot b).  The packet stays in the lowest layer,
+             * entered through its inner face. */
+            ry.k = 0;
+            ry.ef = F_IN;
+            double nrm[3] = {0.0, 0.0, 1.0};
+            if (g->geom != 1) {
+                double rr = sqrt(ry.p[0] * ry.p[0] + ry.p[1] * ry.p[1] + ry.p[2] * ry.p[2]);
+                nrm[0] = ry.p[0] / rr; nrm[1] = ry.p[1] / rr; nrm[2] = ry.p[2] / rr;
+            }
+            int64_t c = cell_index(g, ry.i, ry.j, 0);
+            for (int o = 0; o < nout; ++o) {
+                const double *ov = slab_back ? oback : obs + 3 * o;
+                double mu = nrm[0] * ov[0] + nrm[1] * ov[1] + nrm[2] * ov[2];
+                double f = 0.0;
+                if (mu > 0.0) {
+                    double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
+                    f = W * pr->surface_albedo * (mu / ORC_PI) * exp(-t);
+                }
+                F[o] = F[o] + f;
+                tally_add(tl, ncell, o, 1, c, ry.p, f);
+            }
+            K[K_SURF] += W * (1.0 - pr->surface_albedo);
+            W = W * pr->surface_albedo;
+            double u1a, u1b;
+            orc_draw(pr->seed, tag, pid, e, 1, &u1a, &u1b);
+            d[0] = nrm[0]; d[1] = nrm[1]; d[2] = nrm[2];
+            orc_rotate(d, sqrt(u1a), 2.0 * ORC_PI * u1b);
+        } else {
+        /* interaction in cell c */
         int64_t c = cell_index(g, ry.i, ry.j, ry.k);
         double om = op->omega[c], pg = op->p_gas[c], gc = op->g_cld[c];
         for (int o = 0; o < nout; ++o) {
@@ -871,6 +905,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             mu = orc_sample_hg(u1a, gc);
         }
         orc_rotate(d, mu, 2.0 * ORC_PI * u1b);
+        }
         if (W < pr->rr_threshold * W0) {
             double u2a, u2b;
             orc_draw(pr->seed, tag, pid, e, 2, &u2a, &u2b);

@@ -55,7 +55,7 @@ class _Params(ctypes.Structure):
                 ("max_cross", ctypes.c_int64), ("n_obs", ctypes.c_int64),
                 ("rr_threshold", ctypes.c_double), ("rr_survive", ctypes.c_double),
                 ("tau_peel_max", ctypes.c_double), ("mu0", ctypes.c_double),
-                ("cloud_phase", ctypes.c_int64)]
+                ("cloud_phase", ctypes.c_int64), ("surface_albedo", ctypes.c_double)]
 
 
 class _Optics(ctypes.Structure):
@@ -302,6 +302,7 @@ class Params:
     r_star: float = 6.957e10
     g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
     cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
+    surface_albedo: float = 0.0  # 0 absorbing lower boundary; > 0 Lambert surface
     threads: int = 0
 
 
@@ -352,7 +353,7 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
                  int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
                  params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
-                 int(params.cloud_phase))
+                 int(params.cloud_phase), float(params.surface_albedo))
     op = _Optics(optics.a_ext.ctypes.data, optics.a_abs.ctypes.data, optics.omega.ctypes.data,
                  optics.p_gas.ctypes.data, optics.g_cld.ctypes.data)
     nout = 1 if (grid.geometry == 1 and nobs == 0) else nobs
@@ -409,7 +410,7 @@ def transport_gsampled(grid, optics_list, params: Params, mode: int, obs, q, wfa
     pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
                  int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
                  params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
-                 int(params.cloud_phase))
+                 int(params.cloud_phase), float(params.surface_albedo))
     ops = (_Optics * ng)()
     for h, op in enumerate(optics_list):
         ops[h] = _Optics(op.a_ext.ctypes.data, op.a_abs.ctypes.data, op.omega.ctypes.data,

@@ -107,9 +107,10 @@ class Doubling:
     thick limit loses digits to the near-singular (1 - R R) and is pinned by
     the H-function instead).  Convention: reflected intensity for a
     collimated beam of flux pi F at mu0 is I = F mu0 rho; Chandrasekhar's
-    S = 4 mu mu0 rho; dphi = pi is the backscatter azimuth."""
+    S = 4 mu mu0 rho; dphi = pi is the backscatter azimuth.  surface_albedo > 0
+    puts a Lambert reflector of that albedo under the layer (adding method)."""
 
-    def __init__(self, P, omega, tau, n=48, mmax=0, nphi=512, n_double=None):
+    def __init__(self, P, omega, tau, n=48, mmax=0, nphi=512, n_double=None, surface_albedo=0.0):
         self.mu, self.w = gauss01(n)
         mu, w = self.mu, self.w
         self.mmax = mmax
@@ -135,6 +136,13 @@ class Doubling:
                 Rn = R + T @ X @ R @ T
                 Tn = T @ X @ T
                 R, T = Rn, Tn
+            if m == 0 and surface_albedo > 0.0:
+                # add a Lambert floor below the layer: its reflection operator
+                # is A_s 2 mu_j w_j in the azimuth-mean mode and zero above;
+                # the layer is homogeneous, so it transmits and reflects alike
+                # from either side
+                Rs = surface_albedo * np.repeat(Wq, n, axis=0)
+                R = R + T @ np.linalg.solve(np.eye(n) - Rs @ R, Rs @ T)
             self.rho.append(R / Wq)
 
     def rho_nodes(self, dphi):
