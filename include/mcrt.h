@@ -204,7 +204,15 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   aerosol scattering): forward lobe g1 = g with weight a = 1 - g2^2 and
  *   backward lobe g2 = -g/2, the lobe of a cloud scattering chosen by Philox
  *   block 2, slot b of the event (zeta < a: forward); the peel-off uses the
- *   mixture a P_HG(g1) + (1 - a) P_HG(g2). */
+ *   mixture a P_HG(g1) + (1 - a) P_HG(g2).
+ * surface_albedo: 0 = the lower boundary absorbs every packet that reaches
+ *   it; A_s in (0, 1] = a Lambert floor (Sect. 3, surface scattering): a
+ *   packet reaching it peels off W A_s max(n.o, 0)/pi e^{-tau} toward each
+ *   observer (n: outward normal, the radial direction on a sphere, +z in a
+ *   slab), leaves W (1 - A_s) in the SURF counter, keeps W A_s and leaves
+ *   at cos(theta) = sqrt(zeta) from n, azimuth 2 pi zeta' (Philox block 1
+ *   of the event); it counts as an interaction (NINT) and is subject to the
+ *   roulette and the event cap.  Outside [0, 1]: EINVAL. */
 typedef struct {
     uint64_t seed;
     uint64_t n_packets;
@@ -239,6 +247,7 @@ typedef struct {
     int32_t image_npix;
     int32_t g_sampling;
     int32_t cloud_phase;
+    double surface_albedo;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -403,6 +403,8 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
     if (p->max_events < 1) return fail(MCRT_EINVAL, "max_events must be >= 1");
     if (p->absorption != MCRT_SURVIVAL && p->absorption != MCRT_CONTINUOUS) return fail(MCRT_EINVAL, "bad absorption");
     if (p->cloud_phase != 0 && p->cloud_phase != 1) return fail(MCRT_EINVAL, "cloud_phase must be 0 (HG) or 1 (TTHG)");
+    if (!(p->surface_albedo >= 0.0 && p->surface_albedo <= 1.0))
+        return fail(MCRT_EINVAL, "surface_albedo must be in [0, 1]");
     if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
     if (mode == MCRT_MODE_EMISSION && g->dev.geom != 0) return fail(MCRT_EINVAL, "emission needs a spherical grid");
     if (p->n_obs == 0) {
@@ -685,6 +687,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     A.cloud_phase = p->cloud_phase;
+    A.surface_albedo = p->surface_albedo;
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     if (npix) {
@@ -710,8 +713,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         auto add = [&gkey](const void* v, size_t n) { gkey.append((const char*)v, n); };
         const int32_t ids[3] = {mode, gid, oid};
         add(ids, sizeof ids);
-        const double dpar[7] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
-                                p->mu0, (double)p->max_events};
+        const double dpar[8] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
+                                p->mu0, (double)p->max_events, p->surface_albedo};
         add(dpar, sizeof dpar);
         const int64_t ipar[13] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
                                   p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling,
@@ -1180,6 +1183,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     A.batch = common->tune_wave_batch > 0 ? common->tune_wave_batch : 64;
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
     A.cloud_phase = common->cloud_phase;
+    A.surface_albedo = common->surface_albedo;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     const bool prof = common->profile != 0;

@@ -7,7 +7,7 @@
 namespace mcrt {
 
 constexpr int kMaxObs = 8;
-constexpr int kMaxSolvesPerLaunch = 1 << 21;  // solve index field of the transport's packed lane state
+constexpr int kMaxSolvesPerLaunch = 1 << 20;  // solve index field of the transport's packed lane state
 constexpr int kXcds = 8;                      // packet dispensers per launch, one per XCD
 constexpr int kNCounters = 11;
 enum Counter { K_ESC = 0, K_SURF, K_ABS, K_RR, K_CAP, K_LOST, K_NINT, K_NCROSS, K_NCAPPED, K_NLOST, K_W0 };
@@ -104,6 +104,7 @@ struct BatchArgs {
     int batch;         // packets a wave takes from the dispenser at once
     int ev_threshold;  // waiting lanes that trigger event handling
     int cloud_phase;   // 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
+    double surface_albedo;  // 0: the lower boundary absorbs; > 0: Lambert albedo of the floor
     // images: npix x npix pixels over [-img_half, img_half]^2 of each
     // observer's sky plane, horizontal / vertical unit vectors per observer
     int npix;

@@ -38,8 +38,9 @@ enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
 // Birth record of a packet, kept in the counter columns of its row until the
 // packet dies: position, direction, weight, cell * 8 + (entry face + 1)
-// (-1: nothing emits), then the index of the solve whose optics it uses.
-enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE };
+// (-1: nothing emits), then the index of the solve whose optics it uses;
+// with a Lambert floor, the weight the floor has absorbed so far.
+enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE, B_SURF };
 
 // Per-lane state that the cell walk does not touch lives in LDS (one slot
 // per lane, structure of arrays) so the registers hold only the walking ray;
@@ -52,7 +53,7 @@ struct ColdLDS {
     double W0[kTPB], w_rr[kTPB];
     unsigned long long gid[kTPB];
     uint32_t ijk[kTPB];   // event cell: i | j << 11 | k << 21
-    uint32_t st[kTPB];    // observer:4 | birth:1 | smode:1 | entry face + 1:3 | capped:1 | lost:1 | solve:21
+    uint32_t st[kTPB];    // observer:4 | birth:1 | smode:1 | entry face + 1:3 | capped:1 | lost:1 | surface:1 | solve:20
     uint32_t e[kTPB];
     int nint[kTPB];
 };
@@ -101,8 +102,9 @@ struct Lane {
     __device__ void set_sef(int ef) { Bits{&C->st[t], 6, 0x7u} = ef + 1; }
     __device__ Bits ncapped() { return Bits{&C->st[t], 9, 0x1u}; }
     __device__ Bits nlost() { return Bits{&C->st[t], 10, 0x1u}; }
-    __device__ int solve() { return (int)(C->st[t] >> 11); }
-    __device__ void set_solve(int s) { Bits{&C->st[t], 11, 0x1FFFFFu} = s; }
+    __device__ Bits surf() { return Bits{&C->st[t], 11, 0x1u}; }  // the event is a reflection by the floor
+    __device__ int solve() { return (int)(C->st[t] >> 12); }
+    __device__ void set_solve(int s) { Bits{&C->st[t], 12, 0xFFFFFu} = s; }
     __device__ int si() { return (int)(C->ijk[t] & 0x7FFu); }
     __device__ int sj() { return (int)((C->ijk[t] >> 11) & 0x3FFu); }
     __device__ int sk() { return (int)(C->ijk[t] >> 21); }
@@ -134,8 +136,10 @@ __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int k
     double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
     for (int o = 0; o < A.n_out; ++o) row[o] = L.Fo(o);
     row += A.n_out;
+    // a Lambert floor never ends a packet; it has kept its absorbed share
+    const double wsurf = A.surface_albedo > 0.0 ? row[B_SURF] : 0.0;
     row[K_ESC] = kind == K_ESC ? L.W : 0.0;
-    row[K_SURF] = kind == K_SURF ? L.W : 0.0;
+    row[K_SURF] = kind == K_SURF ? L.W : wsurf;
     row[K_ABS] = L.w_abs;
     row[K_RR] = L.w_rr();
     row[K_CAP] = kind == K_CAP ? L.W : 0.0;
@@ -189,7 +193,11 @@ __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const Batc
     wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
     L.ncw = 0;
     L.mode = flight ? M_FLIGHT : M_PEEL;
-    if (!flight && g.geom == 1 && !(dz > 0.0)) {  // a slab peel-off ray that never reaches the top
+    // a slab peel-off ray that never reaches the top, or a floor peel-off
+    // ray below the horizon (the floor's normal is the packet direction then)
+    const bool dark = !flight && ((g.geom == 1 && !(dz > 0.0)) ||
+                                  (L.surf() && !(L.sdx() * dx + L.sdy() * dy + L.sdz() * dz > 0.0)));
+    if (dark) {
         L.tau = INFINITY;
         L.mode = M_EVENT;
         L.ev = E_PEEL_DONE;
@@ -273,13 +281,22 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
 enum { A_NONE = 0, A_PEEL = 1, A_FLIGHT = 2, A_SCATTER = 3, A_FINISH = 4 };
 
 // Survival weight update, scattering angle, rotation, roulette, event cap.
+// A reflection by the Lambert floor takes the same steps: its albedo is A_s,
+// its absorbed share goes to the floor, and its polar cosine about the
+// normal (held as the packet direction) is sqrt(zeta), block 1, slot a.
 template <bool MIXED>
 __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
-    const int c = L.cell(g);
-    const double om = ld<MIXED>(S.omega, c), pg = ld<MIXED>(S.p_gas, c), gc = ld<MIXED>(S.g_cld, c);
     const unsigned long long q = L.gid() - S.pbase;
-    if (A.absorption != 1) {
+    const bool sf = L.surf();
+    const int c = L.cell(g);
+    const double om = sf ? A.surface_albedo : ld<MIXED>(S.omega, c);
+    const double pg = sf ? 0.0 : ld<MIXED>(S.p_gas, c), gc = sf ? 0.0 : ld<MIXED>(S.g_cld, c);
+    if (sf) {
+        double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+        b[B_SURF] = b[B_SURF] + L.W * (1.0 - om);
+        L.W = L.W * om;
+    } else if (A.absorption != 1) {
         L.w_abs += L.W * (1.0 - om);
         L.W = L.W * om;
     }
@@ -288,7 +305,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
     // two-term HG clouds: the forward lobe g with weight 1 - (g/2)^2 or the
     // backward lobe -g/2, chosen by block 2, slot b of the event
     double globe = gc;
-    if (A.cloud_phase == 1 && !(usel < pg)) {
+    if (A.cloud_phase == 1 && !sf && !(usel < pg)) {
         const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
         globe = draw(A.seed, S.tag, q, L.e(), 2).b < a ? gc : g2;
     }
@@ -296,7 +313,9 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         float z = fminf((float)u1.a, 0.99999994f);
         float mu;
         float g32 = (float)globe;
-        if ((float)usel < (float)pg) {
+        if (sf) {
+            mu = sqrtf(z);
+        } else if ((float)usel < (float)pg) {
             float qq = 4.0f * z - 2.0f;
             float u = cbrtf(qq + sqrtf(qq * qq + 1.0f));
             mu = u - 1.0f / u;
@@ -330,7 +349,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         L.sdy() = ddy / n;
         L.sdz() = ddz / n;
     } else {
-        double mu = (usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, globe);
+        double mu = sf ? sqrt(u1.a) : ((usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, globe));
         rotate_dir(L.sdx(), L.sdy(), L.sdz(), mu, 2.0 * kPi * u1.b);
     }
     if (L.W < A.rr_threshold * L.W0()) {
@@ -372,6 +391,9 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         double f;
         if (L.birth()) {
             f = L.W * exp(-L.tau) / (4.0 * kPi);
+        } else if (L.surf()) {  // Lambert floor: W A_s max(n.o, 0)/pi e^{-tau}, n held as the direction
+            const double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
+            f = mu > 0.0 ? L.W * A.surface_albedo * (mu / kPi) * exp(-L.tau) : 0.0;
         } else {
             // normalised mixture of the Rayleigh and cloud phase functions
             // toward the observer, weighted by the gas scattering probability
@@ -444,6 +466,35 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         L.nint() += 1;
         L.o() = 0;
         L.birth() = 0;
+        L.surf() = 0;
+        return A_PEEL;
+    }
+    if (L.ev == E_SURFACE && A.surface_albedo > 0.0) {
+        // the floor reflects: an event on the surface of the lowest cell,
+        // entered through its inner face; until the reflection the packet
+        // direction holds the floor's outward normal (radial on a sphere, +z
+        // in a slab)
+        L.nint() += 1;
+        const double x = L.w.px + L.w.t * L.w.dx, y = L.w.py + L.w.t * L.w.dy;
+        const double z = g.geom == 1 ? g.r[0] : L.w.pz + L.w.t * L.w.dz;
+        L.sx() = x;
+        L.sy() = y;
+        L.sz() = z;
+        if (g.geom == 1) {
+            L.sdx() = 0.0;
+            L.sdy() = 0.0;
+            L.sdz() = 1.0;
+        } else {
+            const double rr = sqrt(x * x + y * y + z * z);
+            L.sdx() = x / rr;
+            L.sdy() = y / rr;
+            L.sdz() = z / rr;
+        }
+        L.set_cell(L.w.i, L.w.j, 0);
+        L.set_sef(F_IN);
+        L.o() = 0;
+        L.birth() = 0;
+        L.surf() = 1;
         return A_PEEL;
     }
     if (L.ev == E_LOST) L.nlost() += 1;
@@ -589,7 +640,8 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 // flight for albedo, the emission-point peel-off, or finish if none emits).
 __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
 {
-    const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    if (A.surface_albedo > 0.0) b[B_SURF] = 0.0;
     const int sv = (int)b[B_SOLVE];
     const SolveDev& S = A.solves[sv];
     L.C->st[L.t] = 0u;

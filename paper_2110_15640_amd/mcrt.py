@@ -61,7 +61,8 @@ class SolveParams(ctypes.Structure):
                 ("packet_dump", _vp), ("profile", _i32), ("max_batch", _i32),
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32),
                 ("graph", _i32), ("contrib", _i32), ("image_npix", _i32),
-                ("g_sampling", _i32), ("cloud_phase", _i32)]
+                ("g_sampling", _i32), ("cloud_phase", _i32),
+                ("surface_albedo", ctypes.c_double)]
 
 
 class BatchItem(ctypes.Structure):

@@ -484,3 +484,75 @@ def test_tthg_clouds_parity(ctx, torch_dev):
     assert np.all(np.abs(mix["value"] - alb["value"]) <= np.maximum(3.0 * alb["stderr"], 1e-3 * np.abs(alb["value"])))
     ctx.free_grid(gid)
     ctx.free_opacity(oid)
+
+
+def test_lambert_floor_parity(ctx, torch_dev):
+    """Lambert floor (A_s > 0): every packet against the oracle for a
+    scattering slab (three observers and the backscatter form) and for
+    emission from a cloudy sphere; counters, contribution functions and
+    images of an albedo sphere; a multi-grid batch equals its single solves;
+    the mixed form within 1e-3 / 3 sigma."""
+    _log("Lambert floor: slab (Rayleigh + HG cloud), emission sphere 16x8x10, albedo sphere CF/images, batch")
+    from paper_2110_15640_amd import mcrt as M
+    n = 2500
+    obs = [[0.6, 0.0, 0.8], [-0.28, 0.4, math.sqrt(1 - 0.28 ** 2 - 0.16)], [0.0, 0.99, math.sqrt(1 - 0.99 ** 2)]]
+    for ray in (True, False):
+        if ray:
+            grid, table = I.make_homogeneous_slab(1.0, 0.875, rayleigh=True, nlay=4)
+        else:
+            grid, table = I.make_homogeneous_slab(1.0, 0.875, g_cld=0.5, nlay=4)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+        for o in (obs, None):
+            kw = dict(n_packets=n, seed=111, mu0=0.55, surface_albedo=0.6)
+            no = 3 if o is not None else 1
+            dump = dump_buffer(torch_dev, 1, n, no)
+            if o is not None:
+                got = ctx.solve_albedo(gid, oid, table, obs_dir=o, packet_dump=dump, **kw)
+                ref = O.solve_albedo(grid, table, O.Params(obs_dir=np.array(o), **kw), keep_packets=True)
+            else:
+                got = ctx.solve_albedo(gid, oid, table, packet_dump=dump, **kw)
+                ref = O.solve_albedo(grid, table, O.Params(**kw), keep_packets=True)
+            check_packets(dump, ref, (1, 1, n, no))
+            check_solve(got, ref)
+            assert ref.counters[0, 0, 1] > 0.0  # the floor absorbed some weight
+        ctx.free_grid(gid)
+        ctx.free_opacity(oid)
+    # a thin atmosphere (opacities / 1000), so that packets of every kind
+    # reach the floor
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2, config_no=70)
+    rng = np.random.default_rng(17)
+    grid.cld_ksca = rng.uniform(0, 3e-5, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 5e-6, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.3, 0.9, grid.ncell).astype(np.float32)
+    table.kappa = (table.kappa * 1e-3).astype(np.float32)
+    table.k_ray = table.k_ray * 0.02
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 1500
+    dump = dump_buffer(torch_dev, 4, n, 4)
+    kw = dict(n_packets=n, seed=113, surface_albedo=0.45)
+    got = ctx.solve_emission(gid, oid, table, obs_phase=phases, packet_dump=dump, cloud_phase=1, **kw)
+    ref = O.solve_emission(grid, table, O.Params(obs_phase=tuple(phases), cloud_phase=1, **kw), keep_packets=True)
+    check_packets(dump, ref, (2, 2, n, 4))
+    check_solve(got, ref)
+    assert ref.counters[:, :, 1].min() > 0.0  # every solve has floor events
+    kw = dict(n_packets=3000, seed=115, surface_albedo=0.7)
+    alb = ctx.solve_albedo(gid, oid, table, obs_phase=[0.0, 1.3], contrib=1, image_npix=15, **kw)
+    aref = O.solve_albedo(grid, table, O.Params(obs_phase=(0.0, 1.3), **kw), contrib=True, image_npix=15)
+    check_solve(alb, aref)
+    np.testing.assert_allclose(alb["cf"], aref.extra["cf"], rtol=1e-9, atol=1e-13)
+    im = aref.extra["image"]
+    np.testing.assert_allclose(alb["image"], im, rtol=1e-9, atol=1e-12 * im.max())
+    # the floor cells (k = 0) carry scattered contribution
+    assert alb["cf"][:, :, 1, :grid.nlon * grid.nlat].sum() > 0.0
+    mix = ctx.solve_albedo(gid, oid, table, obs_phase=[0.0, 1.3], precision=M.MCRT_MIXED, **kw)
+    assert np.all(np.abs(mix["value"] - alb["value"]) <= np.maximum(3.0 * alb["stderr"], 1e-3 * np.abs(alb["value"])))
+    items = [dict(mode="emission", gid=gid, oid=oid, table=table, spec_idx=[1], n_packets=900),
+             dict(mode="albedo", gid=gid, oid=oid, table=table, spec_idx=[0], n_packets=700)]
+    common = dict(obs_phase=[0.25, 0.5], seed=117, decorrelate=1, surface_albedo=0.3)
+    outs = ctx.solve_batch(items, **common)
+    for it, b in zip(items, outs):
+        fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
+        one = fn(it["gid"], it["oid"], it["table"], spec_idx=it["spec_idx"], n_packets=it["n_packets"], **common)
+        assert np.array_equal(b["sums"], one["sums"]) and np.array_equal(b["counters"], one["counters"])
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
