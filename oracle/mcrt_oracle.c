@@ -600,6 +600,39 @@ double orc_emission_sources(const orc_grid *g, const float *T, const double *a_e
 }
 
 /* ------------------------------------------------------------------------ */
+/* Stellar limb darkening (Sect. 5.1.1): I(mu)/I(1) on the stellar disk,    */
+/* mu the cosine of the zenith angle on the stellar surface.  Laws:         */
+/* 0 none, 1 linear, 2 quadratic (Kopal), 3 square-root, 4 logarithmic,     */
+/* 5 exponential, 6 power-2.                                                */
+/* ------------------------------------------------------------------------ */
+double orc_limb_darkening(int64_t law, double c1, double c2, double mu)
+{
+    double x = 1.0 - mu;
+    switch (law) {
+    case 1: return 1.0 - c1 * x;
+    case 2: return 1.0 - c1 * x - c2 * x * x;
+    case 3: return 1.0 - c1 * x - c2 * (1.0 - sqrt(mu));
+    case 4: return 1.0 - c1 * x - c2 * (mu > 0.0 ? mu * log(mu) : 0.0);
+    case 5: return 1.0 - c1 * x - c2 / (1.0 - exp(mu));
+    case 6: return 1.0 - c1 * (1.0 - pow(mu, c2));
+    default: return 1.0;
+    }
+}
+
+/* Weight of the stellar light behind sky-plane point (y, z) of the planet's
+ * frame: the point lies at (transit_y + y, transit_z + z) on the stellar
+ * disk; off the disk there is no light.                                    */
+double orc_chord_limb_weight(int64_t law, double c1, double c2, double ty, double tz, double r_star,
+                             double y, double z)
+{
+    if (law == 0) return 1.0;
+    double sy = ty + y, sz = tz + z;
+    double q = (sy * sy + sz * sz) / (r_star * r_star);
+    if (!(q < 1.0)) return 0.0;
+    return orc_limb_darkening(law, c1, c2, sqrt(1.0 - q));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Transport (Sect. 2, 3, 4).                                               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -619,6 +652,12 @@ typedef struct {
     double mu0;           /* slab incidence cosine; <= 0: uniform over disk */
     int64_t cloud_phase;  /* 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein */
     double surface_albedo; /* 0: absorbing lower boundary; > 0: Lambert surface */
+    /* transmission with multiple scattering (mode 2) */
+    double omega_star;    /* solid angle pi (R_star / a)^2 of the stellar beam at the planet */
+    int64_t ld_law;       /* stellar limb darkening, see orc_limb_darkening */
+    double ld_c1, ld_c2;
+    double transit_y, transit_z; /* planet centre on the stellar disk (sky plane), cm */
+    double r_star;
 } orc_params;
 
 typedef struct {
@@ -783,6 +822,31 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             ry.ef = F_OUT;
         }
         W = wmul;
+    } else if (pr->mode == 2) {
+        /* transmission with multiple scattering (Sect. 5.1): the packet
+         * enters at a random point of the annulus R0 <= b <= R_TOA (block 0 of
+         * the birth event: slot a gives b uniformly, slot b the angle) with
+         * the stellar beam along -x; its weight is b (the factor of the
+         * estimator) times the limb-darkening fraction of the stellar light
+         * behind its chord.  The first peel-off, along the chord toward the
+         * observer, is the directly transmitted light.                     */
+        orc_draw(pr->seed, tag, pid, 0, 0, &ua, &ub);
+        double r0 = g->r[0];
+        double b = r0 + ua * (r_toa - r0);
+        double al = 2.0 * ORC_PI * ub;
+        ry.p[0] = sqrt(fmax(r_toa * r_toa - b * b, 0.0));
+        ry.p[1] = b * cos(al);
+        ry.p[2] = b * sin(al);
+        d[0] = -1.0; d[1] = 0.0; d[2] = 0.0;
+        ry.k = (int)g->nlay - 1;
+        locate_column(g, ry.p, &ry.i, &ry.j);
+        ry.ef = F_OUT;
+        W = b * orc_chord_limb_weight(pr->ld_law, pr->ld_c1, pr->ld_c2, pr->transit_y, pr->transit_z,
+                                      pr->r_star, ry.p[1], ry.p[2]);
+        for (int o = 0; o < nobs; ++o) {
+            double tau = peel_tau(g, op, &ry, obs + 3 * o, pr->tau_peel_max, pr->max_cross, &ncross);
+            F[o] = F[o] + W * exp(-tau);
+        }
     } else {
         /* emission: cell by the biased CDF, uniform position in the cell's
          * volume, isotropic direction, weight (L_i/L_tot)/q_i              */
@@ -826,7 +890,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
     W0 = W;
     K[K_W0] = W0;
 
-    if (pr->mode == 1 && !pr->scattering) {
+    if (pr->mode >= 1 && !pr->scattering) {
         K[K_ESC] += W; /* weight leaves with its initial peel-off only */
         K[K_NCROSS] = (double)ncross;
         return;
@@ -864,6 +928,7 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
                 if (mu > 0.0) {
                     double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
                     f = W * pr->surface_albedo * (mu / ORC_PI) * exp(-t);
+                    if (pr->mode == 2) f = f * pr->omega_star;
                 }
                 F[o] = F[o] + f;
                 tally_add(tl, ncell, o, 1, c, ry.p, f);
@@ -885,6 +950,8 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             double theta = (pg * orc_phase_rayleigh(mu) + (1.0 - pg) * pc) / (4.0 * ORC_PI);
             double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
+            /* transmission: scattered light per steradian, over the beam's solid angle */
+            if (pr->mode == 2) f = f * pr->omega_star;
             F[o] = F[o] + f;
             tally_add(tl, ncell, o, 1, c, ry.p, f);
         }
@@ -1003,7 +1070,7 @@ int64_t orc_max_threads(void)
  * alpha is [n_spec][ncell].  tau_out (optional) = tau_cs.                 */
 void orc_transmission(const orc_grid *g, const double *alpha, int64_t n_spec, int64_t n_b,
                       int64_t n_alpha, uint64_t seed, int64_t tag, double r0, double r_toa,
-                      double *value, double *tau_out, int64_t nthreads)
+                      const orc_params *ld, double *value, double *tau_out, int64_t nthreads)
 {
     int64_t nch = n_b * n_alpha;
     int64_t cap = 64 * (g->nlay + g->nlat + g->nlon) + 64;
@@ -1029,12 +1096,14 @@ void orc_transmission(const orc_grid *g, const double *alpha, int64_t n_spec, in
             locate_column(g, p, &i, &j);
             int64_t term;
             int64_t nseg = orc_trace_segments(g, p, d, i, j, g->nlay - 1, F_OUT, cap, cells, lens, &term);
+            double wb = b * orc_chord_limb_weight(ld->ld_law, ld->ld_c1, ld->ld_c2, ld->transit_y,
+                                                  ld->transit_z, ld->r_star, p[1], p[2]);
             for (int64_t s = 0; s < n_spec; ++s) {
                 double tau = 0.0;
                 for (int64_t q = 0; q < nseg; ++q)
                     tau = tau + alpha[s * (g->nlon * g->nlat * g->nlay) + cells[q]] * lens[q];
                 if (term != T_ESCAPE) tau = INFINITY;
-                value[ch * n_spec + s] = (1.0 - exp(-tau)) * b;
+                value[ch * n_spec + s] = (1.0 - exp(-tau)) * wb;
                 if (tau_out) tau_out[ch * n_spec + s] = tau;
             }
         }

@@ -55,7 +55,10 @@ class _Params(ctypes.Structure):
                 ("max_cross", ctypes.c_int64), ("n_obs", ctypes.c_int64),
                 ("rr_threshold", ctypes.c_double), ("rr_survive", ctypes.c_double),
                 ("tau_peel_max", ctypes.c_double), ("mu0", ctypes.c_double),
-                ("cloud_phase", ctypes.c_int64), ("surface_albedo", ctypes.c_double)]
+                ("cloud_phase", ctypes.c_int64), ("surface_albedo", ctypes.c_double),
+                ("omega_star", ctypes.c_double), ("ld_law", ctypes.c_int64), ("ld_c1", ctypes.c_double),
+                ("ld_c2", ctypes.c_double), ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double),
+                ("r_star", ctypes.c_double)]
 
 
 class _Optics(ctypes.Structure):
@@ -114,7 +117,11 @@ def lib():
                                              ctypes.POINTER(_Params), vp, vp, vp, vp, vp, dbl, vp, vp, vp, i64]
         L.orc_transport_gsampled.restype = i64
         L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
-                                       vp, vp, i64]
+                                       ctypes.POINTER(_Params), vp, vp, i64]
+        L.orc_limb_darkening.argtypes = [i64, dbl, dbl, dbl]
+        L.orc_limb_darkening.restype = dbl
+        L.orc_chord_limb_weight.argtypes = [i64, dbl, dbl, dbl, dbl, dbl, dbl, dbl]
+        L.orc_chord_limb_weight.restype = dbl
         L.orc_max_threads.restype = i64
         _lib = L
     return _lib
@@ -303,6 +310,12 @@ class Params:
     g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
     cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
     surface_albedo: float = 0.0  # 0 absorbing lower boundary; > 0 Lambert surface
+    a_orbit: float = 0.0  # star-planet distance [cm] (transmission with scattering)
+    ld_law: int = 0  # stellar limb darkening: 0 none, 1 linear, 2 quadratic, 3 sqrt, 4 log, 5 exp, 6 power-2
+    ld_c1: float = 0.0
+    ld_c2: float = 0.0
+    transit_y: float = 0.0  # planet centre on the stellar disk (sky plane) [cm]
+    transit_z: float = 0.0
     threads: int = 0
 
 
@@ -338,6 +351,30 @@ def image_axes(obs) -> np.ndarray:
     return np.array(out)
 
 
+def omega_star(params: Params) -> float:
+    """Solid angle pi (R*/a)^2 of the stellar beam at the planet (0 without a_orbit)."""
+    return math.pi * (params.r_star / params.a_orbit) ** 2 if params.a_orbit > 0.0 else 0.0
+
+
+def _params(params: Params, mode: int, tag: int, max_cross: int, nobs: int) -> _Params:
+    return _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
+                   int(params.absorption), tag, params.max_events, max_cross, nobs,
+                   params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
+                   int(params.cloud_phase), float(params.surface_albedo), omega_star(params),
+                   int(params.ld_law), float(params.ld_c1), float(params.ld_c2), float(params.transit_y),
+                   float(params.transit_z), float(params.r_star))
+
+
+def limb_darkening(law: int, c1: float, c2: float, mu: float) -> float:
+    return lib().orc_limb_darkening(int(law), float(c1), float(c2), float(mu))
+
+
+def chord_limb_weight(params: Params, y: float, z: float) -> float:
+    return lib().orc_chord_limb_weight(int(params.ld_law), float(params.ld_c1), float(params.ld_c2),
+                                       float(params.transit_y), float(params.transit_z), float(params.r_star),
+                                       float(y), float(z))
+
+
 def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.ndarray],
               sources: Optional[Sources] = None, tag: int = 0, cf: Optional[np.ndarray] = None,
               img: Optional[np.ndarray] = None):
@@ -350,10 +387,7 @@ def transport(grid, optics: Optics, params: Params, mode: int, obs: Optional[np.
     columns along e_h, covering [-R_TOA, R_TOA]^2."""
     gv = GridView(grid)
     nobs = 0 if obs is None else len(obs)
-    pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
-                 int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
-                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
-                 int(params.cloud_phase), float(params.surface_albedo))
+    pr = _params(params, mode, tag, gv.max_cross, nobs)
     op = _Optics(optics.a_ext.ctypes.data, optics.a_abs.ctypes.data, optics.omega.ctypes.data,
                  optics.p_gas.ctypes.data, optics.g_cld.ctypes.data)
     nout = 1 if (grid.geometry == 1 and nobs == 0) else nobs
@@ -407,10 +441,7 @@ def transport_gsampled(grid, optics_list, params: Params, mode: int, obs, q, wfa
     gv = GridView(grid)
     ng = len(optics_list)
     nobs = 0 if obs is None else len(obs)
-    pr = _Params(params.seed, params.n_packets, params.packet0, mode, int(bool(params.scattering)),
-                 int(params.absorption), tag, params.max_events, gv.max_cross, nobs,
-                 params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
-                 int(params.cloud_phase), float(params.surface_albedo))
+    pr = _params(params, mode, tag, gv.max_cross, nobs)
     ops = (_Optics * ng)()
     for h, op in enumerate(optics_list):
         ops[h] = _Optics(op.a_ext.ctypes.data, op.a_abs.ctypes.data, op.omega.ctypes.data,
@@ -658,8 +689,9 @@ def solve_transmission(grid, table, params: Params, spec_idx=None, tau_out=False
     nch = params.n_b * params.n_alpha
     val = np.zeros((nch, nrow))
     tau = np.zeros((nch, nrow)) if tau_out else None
+    ld = _params(params, 0, 0, gv.max_cross, 0)
     lib().orc_transmission(ctypes.byref(gv.c), alpha.ctypes.data, nrow, params.n_b, params.n_alpha,
-                           params.seed, 0, grid.r0, grid.r_toa, val.ctypes.data, _p(tau),
+                           params.seed, 0, grid.r0, grid.r_toa, ctypes.byref(ld), val.ctypes.data, _p(tau),
                            int(params.threads))
     s1 = val.sum(axis=0)
     s2 = (val * val).sum(axis=0)
@@ -677,3 +709,50 @@ def solve_transmission(grid, table, params: Params, spec_idx=None, tau_out=False
     sums = np.stack([s1, s2], axis=-1).reshape(len(specs), ng, 1, 2)
     return Result(value, stderr, depth[:, :, None], sums, np.zeros((len(specs), ng, NK)),
                   {"tau": tau})
+
+
+def solve_transmission_ms(grid, table, params: Params, spec_idx=None, keep_packets=False) -> Result:
+    """Transmission with multiple scattering (Sect. 5.1).  Packets enter at
+    random points of the annulus R0 <= b <= R_TOA with weight W0 = b times
+    the stellar limb-darkening fraction of their chord; the first peel-off,
+    along the chord, is the directly transmitted light and every later
+    peel-off toward the observer (-x), taken over the stellar beam's solid
+    angle pi (R*/a)^2, light scattered into the line of sight.  Per packet
+    v = W0 - F is the light taken out of the beam, and per g-ordinate
+    (R_p/R*)^2 = (R0^2 + 2 (R_TOA - R0) <v>) / R*^2, summed over g with w_g."""
+    hires = not hasattr(table, "g_weights")
+    if spec_idx is None:
+        specs = list(range(table.nlam if hires else table.nband))
+    else:
+        specs = [int(s) for s in spec_idx]
+    ng = 1 if hires else table.ng
+    obs = np.array([[-1.0, 0.0, 0.0]])
+    sh = None
+    if hires and (grid.u is not None or grid.omega_rot != 0.0):
+        sh = doppler_shift(grid, obs[0], table.dlnlam)
+    N = params.n_packets
+    dr = grid.r_toa - grid.r0
+    rs2 = params.r_star ** 2
+    sums = np.zeros((len(specs), ng, 1, 2))
+    cnt = np.zeros((len(specs), ng, NK))
+    per_g = np.zeros((len(specs), ng, 1))
+    se_g = np.zeros_like(per_g)
+    packets = {}
+    for si, s in enumerate(specs):
+        for g in range(ng):
+            op = hires_optics(grid, table, s, sh) if hires else ck_optics(grid, table, s, g)
+            F, K = transport(grid, op, params, 2, obs, tag=_tag(params, s, g, ng))
+            v = K[:, 10] - F[:, 0]
+            if keep_packets:
+                packets[(si, g)] = (v, K)
+            sums[si, g, 0, 0] = v.sum()
+            sums[si, g, 0, 1] = (v * v).sum()
+            cnt[si, g] = K.sum(axis=0)
+            m = sums[si, g, 0, 0] / N
+            var = max(sums[si, g, 0, 1] / N - m * m, 0.0) / N
+            per_g[si, g, 0] = (grid.r0 ** 2 + 2.0 * dr * m) / rs2
+            se_g[si, g, 0] = 2.0 * dr * math.sqrt(var) / rs2
+    w = np.ones(1) if hires else np.asarray(table.g_weights, dtype=np.float64)
+    value = np.einsum("g,sgo->so", w, per_g)
+    stderr = np.sqrt(np.einsum("g,sgo->so", w * w, se_g * se_g))
+    return Result(value, stderr, per_g, sums, cnt, {"packets": packets})
