@@ -161,6 +161,32 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  * mu0: slab albedo incidence cosine; <= 0 samples the uniform-disk mu0.
  * n_b, n_alpha: transmission strata in impact parameter and limb angle.
  * r_star: stellar radius [cm] for transmission depths.
+ * ms_transmission: mcrt_solve_transmission only.  0 = raytrace chords (the
+ *   n_b x n_alpha jittered strata, no scattering).  1 = multiple scattering
+ *   (Sect. 5.1): n_packets packets per (spectral point, g) enter at random
+ *   points of the annulus R0 <= b <= R_TOA (birth event, Philox block 0:
+ *   slot a gives b uniformly, slot b the angle) with the stellar beam along
+ *   -x and weight W0 = b times the limb-darkening fraction; the first
+ *   peel-off, along the chord, is the directly transmitted light, and every
+ *   interaction (and Lambert-floor reflection) peels off toward -x the light
+ *   it scatters into the line of sight, W omega Theta e^{-tau} per steradian
+ *   over the stellar beam's solid angle pi (r_star / a_orbit)^2.  Per packet
+ *   the light taken out of the beam, v = W0 - F, is the tallied value (and
+ *   the packet dump); per g-ordinate (R_p/R*)^2 = (R0^2 + 2 (R_TOA - R0)
+ *   <v>) / R*^2, weighted by w_g.  Needs a_orbit > r_star; obs_*, contrib,
+ *   image_npix and g_sampling do not apply (EINVAL for the last three).
+ * a_orbit: star-planet distance [cm] (ms_transmission).
+ * ld_law, ld_c1, ld_c2: stellar limb darkening of transmission packets and
+ *   chords (Sect. 5.1.1): the chord at sky-plane offset (y, z) from the
+ *   planet centre lies at (transit_y + y, transit_z + z) on the stellar
+ *   disk, mu = sqrt(1 - r^2 / r_star^2), and its weight is multiplied by
+ *   I(mu)/I(1): 0 none; 1 linear 1 - c1 (1 - mu); 2 quadratic
+ *   1 - c1 (1 - mu) - c2 (1 - mu)^2; 3 square-root 1 - c1 (1 - mu)
+ *   - c2 (1 - sqrt(mu)); 4 logarithmic 1 - c1 (1 - mu) - c2 mu ln mu;
+ *   5 exponential 1 - c1 (1 - mu) - c2 / (1 - e^mu); 6 power-2
+ *   1 - c1 (1 - mu^c2).  Off the stellar disk the weight is 0.  The bulk
+ *   disk term R0^2 is not weighted.  Other laws: EINVAL.
+ * transit_y, transit_z: planet centre on the stellar disk [cm] (sky plane). 
  * precision: MCRT_FP64 or MCRT_MIXED.
  * stream: hipStream_t to run on (NULL = the context's own stream).
  * packet_dump: optional DEVICE buffer of doubles receiving each packet's
@@ -248,6 +274,13 @@ typedef struct {
     int32_t g_sampling;
     int32_t cloud_phase;
     double surface_albedo;
+    int32_t ms_transmission;
+    int32_t ld_law;
+    double a_orbit;
+    double ld_c1;
+    double ld_c2;
+    double transit_y;
+    double transit_z;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -387,11 +387,20 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
     pl.stream = p->stream ? (hipStream_t)p->stream : def_stream;
     if (mode == MCRT_MODE_TRANSMISSION) {
         if (g->dev.geom != 0) return fail(MCRT_EINVAL, "transmission needs a spherical grid");
-        if (p->n_b < 1 || p->n_alpha < 1 || (long long)p->n_b * p->n_alpha > (1LL << 30))
-            return fail(MCRT_EINVAL, "n_b and n_alpha must be >= 1 with n_b * n_alpha <= 2^30");
-        if (!(p->r_star > 0.0)) return fail(MCRT_EINVAL, "r_star must be > 0");
+        if (!(p->r_star > 0.0) || !std::isfinite(p->r_star)) return fail(MCRT_EINVAL, "r_star must be > 0");
+        if (p->ld_law < 0 || p->ld_law > 6) return fail(MCRT_EINVAL, "ld_law must be 0 to 6");
+        if (!std::isfinite(p->ld_c1) || !std::isfinite(p->ld_c2) || !std::isfinite(p->transit_y) ||
+            !std::isfinite(p->transit_z))
+            return fail(MCRT_EINVAL, "limb-darkening coefficients and the transit position must be finite");
+        if (p->ms_transmission != 0 && p->ms_transmission != 1) return fail(MCRT_EINVAL, "ms_transmission must be 0 or 1");
         pl.n_out = 1;
-        return MCRT_OK;
+        if (!p->ms_transmission) {
+            if (p->n_b < 1 || p->n_alpha < 1 || (long long)p->n_b * p->n_alpha > (1LL << 30))
+                return fail(MCRT_EINVAL, "n_b and n_alpha must be >= 1 with n_b * n_alpha <= 2^30");
+            return MCRT_OK;
+        }
+        if (!(p->a_orbit > p->r_star) || !std::isfinite(p->a_orbit))
+            return fail(MCRT_EINVAL, "transmission with multiple scattering needs a_orbit > r_star");
     }
     if (p->n_packets < 1 || p->n_packets > (1ULL << 40)) return fail(MCRT_EINVAL, "n_packets must be in [1, 2^40]");
     if (p->n_obs < 0 || p->n_obs > kMaxObs) return fail(MCRT_EINVAL, "n_obs must be in [0, %d]", kMaxObs);
@@ -407,6 +416,11 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
         return fail(MCRT_EINVAL, "surface_albedo must be in [0, 1]");
     if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
     if (mode == MCRT_MODE_EMISSION && g->dev.geom != 0) return fail(MCRT_EINVAL, "emission needs a spherical grid");
+    if (mode == MCRT_MODE_TRANSMISSION) {  // one observer, along -x
+        pl.n_obs = 1;
+        pl.obs = {-1.0, 0.0, 0.0};
+        return MCRT_OK;
+    }
     if (p->n_obs == 0) {
         if (!(mode == MCRT_MODE_ALBEDO && g->dev.geom == 1))
             return fail(MCRT_EINVAL, "n_obs = 0 is only allowed for slab albedo (backscatter)");
@@ -602,6 +616,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     if (p->image_npix < 0 || p->image_npix > 4096) return fail(MCRT_EINVAL, "image_npix must be in [0, 4096]");
     if (p->image_npix && (!res->image || g->dev.geom != 0))
         return fail(MCRT_EINVAL, "images need result.image and a spherical grid");
+    if (mode == MCRT_MODE_TRANSMISSION && (p->contrib || p->image_npix || p->g_sampling))
+        return fail(MCRT_EINVAL, "contribution functions, images and g-ordinate sampling are defined for "
+                                 "albedo and emission");
     const bool gs = p->g_sampling != 0;
     if (p->g_sampling < 0 || p->g_sampling > 3) return fail(MCRT_EINVAL, "g_sampling must be 0 to 3");
     if (gs && op->kind != MCRT_OPAC_CK) return fail(MCRT_EINVAL, "g-ordinate sampling needs a correlated-k table");
@@ -688,6 +705,14 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     A.cloud_phase = p->cloud_phase;
     A.surface_albedo = p->surface_albedo;
+    A.trans_ms = mode == MCRT_MODE_TRANSMISSION ? 1 : 0;
+    if (A.trans_ms) {
+        const double q = p->r_star / p->a_orbit;
+        A.peel_w = kPi * (q * q);
+        A.ld = LimbDark{p->ld_law, p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->r_star};
+    } else {
+        A.peel_w = 1.0;
+    }
     const int bpc = p->tune_blocks_per_cu > 0 ? p->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     if (npix) {
@@ -713,12 +738,13 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         auto add = [&gkey](const void* v, size_t n) { gkey.append((const char*)v, n); };
         const int32_t ids[3] = {mode, gid, oid};
         add(ids, sizeof ids);
-        const double dpar[8] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
-                                p->mu0, (double)p->max_events, p->surface_albedo};
+        const double dpar[14] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
+                                 p->mu0, (double)p->max_events, p->surface_albedo, p->r_star, p->a_orbit,
+                                 p->ld_c1, p->ld_c2, p->transit_y, p->transit_z};
         add(dpar, sizeof dpar);
-        const int64_t ipar[13] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+        const int64_t ipar[14] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
                                   p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling,
-                                  p->cloud_phase};
+                                  p->cloud_phase, p->ld_law};
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
@@ -806,7 +832,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                     S.tag = p->decorrelate ? (uint32_t)(1 + b * ng + gi) : 0u;
                 }
                 S.ltot = mode == MCRT_MODE_EMISSION ? P.stats : nullptr;
-                S.mode = mode == MCRT_MODE_EMISSION ? 1 : 0;
+                S.mode = mode == MCRT_MODE_EMISSION ? 1 : (mode == MCRT_MODE_TRANSMISSION ? 2 : 0);
                 S.grid = 0;
                 S.cdf = P.cdf;
                 S.wbirth = P.wbirth;
@@ -886,6 +912,16 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     const double Nd = (double)N;
     for (int sg = 0; sg < nsolve; ++sg) {
         const double* row = hs.data() + (size_t)sg * row_w;
+        if (mode == MCRT_MODE_TRANSMISSION) {
+            // (R_p/R*)^2 = (R0^2 + 2 (R_TOA - R0) <W0 - F>) / R*^2  (Sect. 5.1)
+            const double dr = g->r_toa - g->r0, rs2 = p->r_star * p->r_star;
+            const double m = row[0] / Nd;
+            const double var = std::max(row[1] / Nd - m * m, 0.0) / Nd;
+            val[sg] = (g->r0 * g->r0 + 2.0 * dr * m) / rs2;
+            se[sg] = 2.0 * dr * std::sqrt(var) / rs2;
+            for (int t = 0; t < kNCounters; ++t) cnt[(size_t)sg * kNCounters + t] = row[2 * no + t];
+            continue;
+        }
         double scale;
         if (mode == MCRT_MODE_ALBEDO) {
             scale = kPi;
@@ -996,8 +1032,9 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     void *v_sc, *v_sl;
     if ((rc = scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
     if ((rc = scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
+    const LimbDark ld{p->ld_law, p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->r_star};
     launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
-                      (double*)v_b, (int*)v_ok, st);
+                      (double*)v_b, (int*)v_ok, ld, st);
     if (op->kind == MCRT_OPAC_HIRES) {
         launch_doppler_shift(g->dev, -1.0, 0.0, 0.0, op->dlnlam, (double*)v_shift, st);
         HIPTRY(hipMemcpyAsync(v_nl, pl.specs.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
@@ -1184,6 +1221,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
     A.cloud_phase = common->cloud_phase;
     A.surface_albedo = common->surface_albedo;
+    A.peel_w = 1.0;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
     const bool prof = common->profile != 0;
@@ -1337,8 +1375,9 @@ struct Request {
 int run_solve(mcrt_ctx* ctx, Slot& sl, hipStream_t st, int mode, int32_t gid, int32_t oid,
               const mcrt_solve_params* p, mcrt_result* res)
 {
-    if (mode == MCRT_MODE_TRANSMISSION) return solve_chords(ctx, sl, st, gid, oid, p, res);
-    if (mode == MCRT_MODE_ALBEDO || mode == MCRT_MODE_EMISSION) return solve_packets(ctx, sl, st, gid, oid, p, res, mode);
+    if (mode == MCRT_MODE_TRANSMISSION && !p->ms_transmission) return solve_chords(ctx, sl, st, gid, oid, p, res);
+    if (mode == MCRT_MODE_ALBEDO || mode == MCRT_MODE_EMISSION || mode == MCRT_MODE_TRANSMISSION)
+        return solve_packets(ctx, sl, st, gid, oid, p, res, mode);
     return fail(MCRT_EINVAL, "unknown mode %d", mode);
 }
 
@@ -1355,7 +1394,7 @@ uint64_t estimate_bytes(mcrt_ctx* ctx, const Request& r, GridRes* g, OpacRes* op
 {
     const uint64_t ncell = (uint64_t)g->ncell;
     const uint64_t nsolve = (uint64_t)r.ns * r.ng;
-    if (r.mode == MCRT_MODE_TRANSMISSION) {
+    if (r.mode == MCRT_MODE_TRANSMISSION && !r.p.ms_transmission) {
         const uint64_t nch = (uint64_t)r.p.n_b * r.p.n_alpha;
         const uint64_t nrow = nsolve, nslot = std::min<uint64_t>(64, nrow);
         const uint64_t tblocks = (uint64_t)chord_tau_blocks((int)nch);

@@ -105,6 +105,32 @@ __device__ __forceinline__ void rotate_dir(double& dx, double& dy, double& dz, d
     dz = nz / n;
 }
 
+// ------------------------------------------------- stellar limb darkening
+// I(mu)/I(1) of the stellar disk at zenith cosine mu (Sect. 5.1.1): laws
+// 0 none, 1 linear, 2 quadratic, 3 square-root, 4 logarithmic,
+// 5 exponential, 6 power-2; and the weight of the stellar light behind the
+// sky-plane point (y, z) of the planet's frame, which lies at (ty + y,
+// tz + z) on the stellar disk (zero off the disk).
+__host__ __device__ inline double limb_law(int law, double c1, double c2, double mu)
+{
+    const double x = 1.0 - mu;
+    if (law == 1) return 1.0 - c1 * x;
+    if (law == 2) return 1.0 - c1 * x - c2 * x * x;
+    if (law == 3) return 1.0 - c1 * x - c2 * (1.0 - sqrt(mu));
+    if (law == 4) return 1.0 - c1 * x - c2 * (mu > 0.0 ? mu * log(mu) : 0.0);
+    if (law == 5) return 1.0 - c1 * x - c2 / (1.0 - exp(mu));
+    if (law == 6) return 1.0 - c1 * (1.0 - pow(mu, c2));
+    return 1.0;
+}
+
+__host__ __device__ inline double limb_weight(const LimbDark& ld, double y, double z)
+{
+    if (ld.law == 0) return 1.0;
+    const double sy = ld.ty + y, sz = ld.tz + z;
+    const double q = (sy * sy + sz * sz) / (ld.r_star * ld.r_star);
+    return q < 1.0 ? limb_law(ld.law, ld.c1, ld.c2, sqrt(1.0 - q)) : 0.0;
+}
+
 // ---------------------------------------------------------------- geometry
 enum { F_NONE = -1, F_OUT = 0, F_IN = 1, F_LATLO = 2, F_LATHI = 3, F_LONLO = 4, F_LONHI = 5 };
 enum { T_INTERACT = 0, T_ESCAPE = 1, T_SURFACE = 2, T_LOST = 3 };

@@ -191,13 +191,17 @@ __global__ void __launch_bounds__(256) k_chord_count(GridDev g, int n_b, int n_a
 __global__ void __launch_bounds__(256) k_chord_fill(GridDev g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
                                                     const long long* __restrict__ offsets,
                                                     uint32_t* __restrict__ seg_cell, double* __restrict__ seg_len,
-                                                    double* __restrict__ chord_b, int* __restrict__ chord_ok)
+                                                    double* __restrict__ chord_b, int* __restrict__ chord_ok,
+                                                    LimbDark ld)
 {
     int ch = blockIdx.x * blockDim.x + threadIdx.x;
     if (ch >= n_b * n_alpha) return;
     Ray p;
     double b;
     chord_start(g, ch, n_b, n_alpha, seed, tag, p, b);
+    // the chord's weight: b times the limb-darkening fraction of the stellar
+    // light behind it
+    const double wb = b * limb_weight(ld, p.y, p.z);
     long long o = offsets[ch], end = offsets[ch + 1];
     int ok = 0;
     while (o < end) {
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(256) k_chord_fill(GridDev g, int n_b, int n_al
         if (p.k >= g.nlay) { ok = 1; break; }
         if (p.k < 0) break;
     }
-    chord_b[ch] = b;
+    chord_b[ch] = wb;
     chord_ok[ch] = ok;
 }
 
@@ -343,11 +347,12 @@ void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* 
 }
 
 void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag, const long long* offsets,
-                       uint32_t* seg_cell, double* seg_len, double* chord_b, int* chord_ok, hipStream_t stream)
+                       uint32_t* seg_cell, double* seg_len, double* chord_b, int* chord_ok, const LimbDark& ld,
+                       hipStream_t stream)
 {
     int nch = n_b * n_alpha;
     hipLaunchKernelGGL(k_chord_fill, dim3(nblk(nch, 256)), dim3(256), 0, stream, g, n_b, n_alpha, seed, tag, offsets,
-                       seg_cell, seg_len, chord_b, chord_ok);
+                       seg_cell, seg_len, chord_b, chord_ok, ld);
 }
 
 int chord_tau_blocks(int nch) { return nblk(nch, kChordWaves * kChordsPerWave); }

@@ -81,6 +81,17 @@ struct SolveDev {
     const double* ltot;    // emission: L_tot of this solve (written by the preparation)
 };
 
+// Stellar limb darkening of transmission chords and packets: law (0 none,
+// 1 linear, 2 quadratic, 3 square-root, 4 logarithmic, 5 exponential,
+// 6 power-2), its coefficients, the planet centre on the stellar disk (sky
+// plane, cm) and the stellar radius.
+struct LimbDark {
+    int law;
+    double c1, c2;
+    double ty, tz;
+    double r_star;
+};
+
 struct BatchArgs {
     const SolveDev* solves;
     int n_solves;
@@ -105,6 +116,13 @@ struct BatchArgs {
     int ev_threshold;  // waiting lanes that trigger event handling
     int cloud_phase;   // 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
     double surface_albedo;  // 0: the lower boundary absorbs; > 0: Lambert albedo of the floor
+    // transmission with multiple scattering: births on the annulus, the birth
+    // peel-off is the direct light (no 1/4pi), later peel-offs are scaled by
+    // peel_w (the stellar beam's solid angle; 1 otherwise), and a packet's
+    // row holds W0 - F
+    int trans_ms;
+    double peel_w;
+    LimbDark ld;
     // images: npix x npix pixels over [-img_half, img_half]^2 of each
     // observer's sky plane, horizontal / vertical unit vectors per observer
     int npix;
@@ -161,7 +179,7 @@ void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* 
                                hipStream_t stream);
 void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
                        const long long* offsets, uint32_t* seg_cell, double* seg_len,
-                       double* chord_b, int* chord_ok, hipStream_t stream);
+                       double* chord_b, int* chord_ok, const LimbDark& ld, hipStream_t stream);
 void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell,
                       const double* seg_len, const double* chord_b, const int* chord_ok,
                       const double* alpha, int nslot, double* partials, int nblocks,

@@ -134,7 +134,7 @@ __device__ __forceinline__ double ld(const void* p, int c)
 __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int kind)
 {
     double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
-    for (int o = 0; o < A.n_out; ++o) row[o] = L.Fo(o);
+    for (int o = 0; o < A.n_out; ++o) row[o] = A.trans_ms ? L.W0() - L.Fo(o) : L.Fo(o);
     row += A.n_out;
     // a Lambert floor never ends a packet; it has kept its absorbed share
     const double wsurf = A.surface_albedo > 0.0 ? row[B_SURF] : 0.0;
@@ -389,8 +389,8 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
     const SolveDev& S = A.solves[L.solve()];
     if (L.ev == E_PEEL_DONE) {
         double f;
-        if (L.birth()) {
-            f = L.W * exp(-L.tau) / (4.0 * kPi);
+        if (L.birth()) {  // emission point (isotropic), or a transmission chord's direct light
+            f = A.trans_ms ? L.W * exp(-L.tau) : L.W * exp(-L.tau) / (4.0 * kPi);
         } else if (L.surf()) {  // Lambert floor: W A_s max(n.o, 0)/pi e^{-tau}, n held as the direction
             const double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
             f = mu > 0.0 ? L.W * A.surface_albedo * (mu / kPi) * exp(-L.tau) : 0.0;
@@ -433,6 +433,9 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
             }
         }
+        // scattered light of a transmission packet: per steradian, over the
+        // stellar beam's solid angle (peel_w = 1 otherwise)
+        if (!L.birth()) f = f * A.peel_w;
         L.Fo(L.o()) += f;
         if ((S.cf || S.img) && f > 0.0) {
             const double sc = f * (S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w);
@@ -596,6 +599,25 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
         b[B_W] = wmul;
         return;
     }
+    if (S.mode == 2) {
+        // transmission: a random point of the annulus R0 <= bi <= R_TOA, the
+        // stellar beam along -x, weight bi times the limb-darkening fraction
+        U2 u = draw(A.seed, tag, q, 0, 0);
+        const double r0 = g.r[0];
+        const double bi = r0 + u.a * (r_toa - r0);
+        const double al = 2.0 * kPi * u.b;
+        Ray rs;
+        rs.x = sqrt(fmax(r_toa * r_toa - bi * bi, 0.0));
+        rs.y = bi * cos(al);
+        rs.z = bi * sin(al);
+        locate_column(g, rs);
+        b[B_X] = rs.x; b[B_Y] = rs.y; b[B_Z] = rs.z;
+        b[B_DX] = -1.0; b[B_DY] = 0.0; b[B_DZ] = 0.0;
+        const int c = ((g.nlay - 1) * g.nlat + rs.j) * g.nlon + rs.i;
+        b[B_CELL] = (double)c * 8.0 + (double)(F_OUT + 1);
+        b[B_W] = bi * limb_weight(A.ld, rs.y, rs.z) * wmul;
+        return;
+    }
     const int ncell = g.nlon * g.nlat * g.nlay;
     const double tot = S.cdf[ncell - 1];
     if (!(tot > 0.0)) {  // nothing emits
@@ -646,7 +668,7 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
     const SolveDev& S = A.solves[sv];
     L.C->st[L.t] = 0u;
     L.set_solve(sv);
-    L.smode() = S.mode;
+    L.smode() = S.mode == 1;  // the emission observer set; albedo and transmission use the other
     for (int o = 0; o < A.n_out; ++o) L.Fo(o) = 0.0;
     L.w_abs = 0.0;
     L.w_rr() = 0.0;

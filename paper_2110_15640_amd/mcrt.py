@@ -62,7 +62,9 @@ class SolveParams(ctypes.Structure):
                 ("tune_ev_threshold", _i32), ("tune_blocks_per_cu", _i32), ("tune_wave_batch", _i32),
                 ("graph", _i32), ("contrib", _i32), ("image_npix", _i32),
                 ("g_sampling", _i32), ("cloud_phase", _i32),
-                ("surface_albedo", ctypes.c_double)]
+                ("surface_albedo", ctypes.c_double), ("ms_transmission", _i32), ("ld_law", _i32),
+                ("a_orbit", ctypes.c_double), ("ld_c1", ctypes.c_double), ("ld_c2", ctypes.c_double),
+                ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double)]
 
 
 class BatchItem(ctypes.Structure):
