@@ -160,6 +160,54 @@ double orc_sample_hg(double zeta, double g)
     return mu;
 }
 
+/* Draine's hybrid HG-Rayleigh function (Sect. 3, aerosol scattering):
+ * P = (1 - G^2)/(1 + alpha (1 + 2 G^2)/3) (1 + alpha mu^2)/(1 + G^2 - 2 G mu)^{3/2},
+ * i.e. P_HG(G) (1 + alpha mu^2) over its normalisation, whose mean cosine
+ * is G (1 + alpha (3 + 2 G^2)/5)/(1 + alpha (1 + 2 G^2)/3).               */
+double orc_draine_mean_cosine(double G, double alpha)
+{
+    return G * (1.0 + alpha * (3.0 + 2.0 * G * G) / 5.0) / (1.0 + alpha * (1.0 + 2.0 * G * G) / 3.0);
+}
+
+/* G of a cloud whose asymmetry factor is g: the root of mean cosine = g on
+ * [-1, 1] by bisection (the mean cosine rises from -1 to 1); alpha = 0 is
+ * HG itself (G = g). */
+double orc_draine_G(double g, double alpha)
+{
+    if (alpha == 0.0) return g;
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (orc_draine_mean_cosine(mid, alpha) < g) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+double orc_phase_draine(double mu, double G, double alpha)
+{
+    return orc_phase_hg(mu, G) * (1.0 + alpha * mu * mu) / (1.0 + alpha * (1.0 + 2.0 * G * G) / 3.0);
+}
+
+/* Exact sampling by rejection from HG(G): candidate k has cos(theta) from
+ * HG(G) with za[k] and is accepted when zacc[k] (1 + alpha) < 1 + alpha mu^2
+ * (the acceptance probability (1 + alpha mu^2)/(1 + alpha) <= 1 for
+ * alpha >= 0); the n-th candidate is taken if none before is accepted.     */
+double orc_sample_draine(const double *za, const double *zacc, int n, double G, double alpha)
+{
+    double mu = 0.0;
+    for (int k = 0; k < n; ++k) {
+        mu = orc_sample_hg(za[k], G);
+        if (zacc[k] * (1.0 + alpha) < 1.0 + alpha * mu * mu) break;
+    }
+    return mu;
+}
+
+/* Candidates drawn for one Draine scattering (the last is taken if none of
+ * the others is accepted: probability below (alpha/(1+alpha))^31). */
+#define ORC_DRAINE_MAXC 32
+
 /* Rotate unit d by polar cos(theta)=mu about it and azimuth psi. */
 void orc_rotate(double d[3], double mu, double psi)
 {
@@ -650,7 +698,7 @@ typedef struct {
     double rr_survive;
     double tau_peel_max;
     double mu0;           /* slab incidence cosine; <= 0: uniform over disk */
-    int64_t cloud_phase;  /* 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein */
+    int64_t cloud_phase;  /* 0 Henyey-Greenstein, 1 two-term HG, 2 Draine */
     double surface_albedo; /* 0: absorbing lower boundary; > 0: Lambert surface */
     /* transmission with multiple scattering (mode 2) */
     double omega_star;    /* solid angle pi (R_star / a)^2 of the stellar beam at the planet */
@@ -658,6 +706,7 @@ typedef struct {
     double ld_c1, ld_c2;
     double transit_y, transit_z; /* planet centre on the stellar disk (sky plane), cm */
     double r_star;
+    double draine_alpha;  /* alpha of Draine's function (cloud_phase 2) */
 } orc_params;
 
 typedef struct {
@@ -943,10 +992,13 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         /* interaction in cell c */
         int64_t c = cell_index(g, ry.i, ry.j, ry.k);
         double om = op->omega[c], pg = op->p_gas[c], gc = op->g_cld[c];
+        double Gd = pr->cloud_phase == 2 ? orc_draine_G(gc, pr->draine_alpha) : 0.0;
         for (int o = 0; o < nout; ++o) {
             const double *ov = slab_back ? oback : obs + 3 * o;
             double mu = d[0] * ov[0] + d[1] * ov[1] + d[2] * ov[2];
-            double pc = pr->cloud_phase == 1 ? orc_phase_tthg(mu, gc) : orc_phase_hg(mu, gc);
+            double pc = pr->cloud_phase == 1 ? orc_phase_tthg(mu, gc)
+                        : pr->cloud_phase == 2 ? orc_phase_draine(mu, Gd, pr->draine_alpha)
+                                               : orc_phase_hg(mu, gc);
             double theta = (pg * orc_phase_rayleigh(mu) + (1.0 - pg) * pc) / (4.0 * ORC_PI);
             double t = peel_tau(g, op, &ry, ov, pr->tau_peel_max, pr->max_cross, &ncross);
             double f = cont ? W * theta * exp(-t) : W * om * theta * exp(-t);
@@ -968,6 +1020,14 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
             double u2a, u2b;  /* the lobe: block 2, slot b */
             orc_draw(pr->seed, tag, pid, e, 2, &u2a, &u2b);
             mu = orc_sample_tthg(u2b, u1a, gc);
+        } else if (pr->cloud_phase == 2) {
+            /* Draine: candidate 0 from block 1 slot a, accepted by block 2
+             * slot b; candidate k >= 1 from block 2 + k (slots a, b) */
+            double za[ORC_DRAINE_MAXC], zc[ORC_DRAINE_MAXC], u2a;
+            za[0] = u1a;
+            orc_draw(pr->seed, tag, pid, e, 2, &u2a, &zc[0]);
+            for (int k = 1; k < ORC_DRAINE_MAXC; ++k) orc_draw(pr->seed, tag, pid, e, (uint32_t)(2 + k), &za[k], &zc[k]);
+            mu = orc_sample_draine(za, zc, ORC_DRAINE_MAXC, Gd, pr->draine_alpha);
         } else {
             mu = orc_sample_hg(u1a, gc);
         }

@@ -58,7 +58,7 @@ class _Params(ctypes.Structure):
                 ("cloud_phase", ctypes.c_int64), ("surface_albedo", ctypes.c_double),
                 ("omega_star", ctypes.c_double), ("ld_law", ctypes.c_int64), ("ld_c1", ctypes.c_double),
                 ("ld_c2", ctypes.c_double), ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double),
-                ("r_star", ctypes.c_double)]
+                ("r_star", ctypes.c_double), ("draine_alpha", ctypes.c_double)]
 
 
 class _Optics(ctypes.Structure):
@@ -118,6 +118,14 @@ def lib():
         L.orc_transport_gsampled.restype = i64
         L.orc_transmission.argtypes = [ctypes.POINTER(_Grid), vp, i64, i64, i64, u64, i64, dbl, dbl,
                                        ctypes.POINTER(_Params), vp, vp, i64]
+        L.orc_draine_mean_cosine.argtypes = [dbl, dbl]
+        L.orc_draine_mean_cosine.restype = dbl
+        L.orc_draine_G.argtypes = [dbl, dbl]
+        L.orc_draine_G.restype = dbl
+        L.orc_phase_draine.argtypes = [dbl, dbl, dbl]
+        L.orc_phase_draine.restype = dbl
+        L.orc_sample_draine.argtypes = [vp, vp, ctypes.c_int, dbl, dbl]
+        L.orc_sample_draine.restype = dbl
         L.orc_limb_darkening.argtypes = [i64, dbl, dbl, dbl]
         L.orc_limb_darkening.restype = dbl
         L.orc_chord_limb_weight.argtypes = [i64, dbl, dbl, dbl, dbl, dbl, dbl, dbl]
@@ -180,6 +188,23 @@ def phase_tthg(mu, g):
 
 def sample_tthg(z_lobe, z, g):
     return lib().orc_sample_tthg(float(z_lobe), float(z), float(g))
+
+
+def draine_G(g, alpha):
+    return lib().orc_draine_G(float(g), float(alpha))
+
+
+def draine_mean_cosine(G, alpha):
+    return lib().orc_draine_mean_cosine(float(G), float(alpha))
+
+
+def phase_draine(mu, G, alpha):
+    return lib().orc_phase_draine(float(mu), float(G), float(alpha))
+
+
+def sample_draine(za, zacc, G, alpha):
+    a, b = _f64(za), _f64(zacc)
+    return lib().orc_sample_draine(a.ctypes.data, b.ctypes.data, len(a), float(G), float(alpha))
 
 
 def rotate(d, mu, psi):
@@ -308,7 +333,8 @@ class Params:
     n_alpha: int = 360
     r_star: float = 6.957e10
     g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
-    cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
+    cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein, 2 Draine
+    draine_alpha: float = 0.5  # alpha of Draine's function
     surface_albedo: float = 0.0  # 0 absorbing lower boundary; > 0 Lambert surface
     a_orbit: float = 0.0  # star-planet distance [cm] (transmission with scattering)
     ld_law: int = 0  # stellar limb darkening: 0 none, 1 linear, 2 quadratic, 3 sqrt, 4 log, 5 exp, 6 power-2
@@ -362,7 +388,7 @@ def _params(params: Params, mode: int, tag: int, max_cross: int, nobs: int) -> _
                    params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
                    int(params.cloud_phase), float(params.surface_albedo), omega_star(params),
                    int(params.ld_law), float(params.ld_c1), float(params.ld_c2), float(params.transit_y),
-                   float(params.transit_z), float(params.r_star))
+                   float(params.transit_z), float(params.r_star), float(params.draine_alpha))
 
 
 def limb_darkening(law: int, c1: float, c2: float, mu: float) -> float:
