@@ -230,7 +230,15 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   aerosol scattering): forward lobe g1 = g with weight a = 1 - g2^2 and
  *   backward lobe g2 = -g/2, the lobe of a cloud scattering chosen by Philox
  *   block 2, slot b of the event (zeta < a: forward); the peel-off uses the
- *   mixture a P_HG(g1) + (1 - a) P_HG(g2).
+ *   mixture a P_HG(g1) + (1 - a) P_HG(g2).  2 = Draine's hybrid HG-Rayleigh
+ *   function (same section) P_HG(G) (1 + alpha mu^2)/(1 + alpha (1 + 2 G^2)
+ *   /3), alpha = draine_alpha, G found from the cloud's asymmetry factor g by
+ *   bisection on the mean cosine; sampled exactly by rejection from HG(G):
+ *   candidate 0 from block 1, slot a, accepted when block 2, slot b times
+ *   (1 + alpha) < 1 + alpha mu^2, candidate k >= 1 from block 2 + k (slots a,
+ *   b), the 32nd taken if none before is accepted.  Other values: EINVAL.
+ * draine_alpha: in [0, 1] (default 0.5; 1 = Cornette-Shanks); EINVAL
+ *   outside.
  * surface_albedo: 0 = the lower boundary absorbs every packet that reaches
  *   it; A_s in (0, 1] = a Lambert floor (Sect. 3, surface scattering): a
  *   packet reaching it peels off W A_s max(n.o, 0)/pi e^{-tau} toward each
@@ -281,6 +289,7 @@ typedef struct {
     double ld_c2;
     double transit_y;
     double transit_z;
+    double draine_alpha;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -411,7 +411,9 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
     if (!(p->tau_vert_max >= 0.0)) return fail(MCRT_EINVAL, "tau_vert_max must be >= 0");
     if (p->max_events < 1) return fail(MCRT_EINVAL, "max_events must be >= 1");
     if (p->absorption != MCRT_SURVIVAL && p->absorption != MCRT_CONTINUOUS) return fail(MCRT_EINVAL, "bad absorption");
-    if (p->cloud_phase != 0 && p->cloud_phase != 1) return fail(MCRT_EINVAL, "cloud_phase must be 0 (HG) or 1 (TTHG)");
+    if (p->cloud_phase < 0 || p->cloud_phase > 2)
+        return fail(MCRT_EINVAL, "cloud_phase must be 0 (HG), 1 (TTHG) or 2 (Draine)");
+    if (!(p->draine_alpha >= 0.0 && p->draine_alpha <= 1.0)) return fail(MCRT_EINVAL, "draine_alpha must be in [0, 1]");
     if (!(p->surface_albedo >= 0.0 && p->surface_albedo <= 1.0))
         return fail(MCRT_EINVAL, "surface_albedo must be in [0, 1]");
     if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
@@ -704,6 +706,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.batch = p->tune_wave_batch > 0 ? p->tune_wave_batch : 64;
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     A.cloud_phase = p->cloud_phase;
+    A.draine_alpha = p->draine_alpha;
     A.surface_albedo = p->surface_albedo;
     A.trans_ms = mode == MCRT_MODE_TRANSMISSION ? 1 : 0;
     if (A.trans_ms) {
@@ -738,9 +741,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         auto add = [&gkey](const void* v, size_t n) { gkey.append((const char*)v, n); };
         const int32_t ids[3] = {mode, gid, oid};
         add(ids, sizeof ids);
-        const double dpar[14] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
+        const double dpar[15] = {p->rr_threshold, p->rr_survive, p->emis_bias, p->tau_vert_max, p->tau_peel_max,
                                  p->mu0, (double)p->max_events, p->surface_albedo, p->r_star, p->a_orbit,
-                                 p->ld_c1, p->ld_c2, p->transit_y, p->transit_z};
+                                 p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->draine_alpha};
         add(dpar, sizeof dpar);
         const int64_t ipar[14] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
                                   p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling,
@@ -857,7 +860,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             HIPTRY(hipMemcpyAsync(v_slots, hps, sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
             HIPTRY(hipMemcpyAsync(v_solves, hsv, sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
             launch_prep_optics(g->dev, ncell, (const PrepSlot*)v_slots, nb, op->kind == MCRT_OPAC_HIRES ? 1 : 0, op->nT,
-                               op->nP, op->T_grid, op->lnP_grid, op->lnk, op->nspec, (const double*)v_shift, st);
+                               op->nP, op->T_grid, op->lnP_grid, op->lnk, op->nspec, (const double*)v_shift,
+                               p->cloud_phase == 2 ? 1 : 0, p->draine_alpha, st);
             if (mode == MCRT_MODE_EMISSION)
                 launch_prep_sources(g->dev, ncell, (const PrepSlot*)v_slots, nb, p->tau_vert_max, p->emis_bias,
                                     (double*)v_ps, st);
@@ -1220,6 +1224,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     A.batch = common->tune_wave_batch > 0 ? common->tune_wave_batch : 64;
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
     A.cloud_phase = common->cloud_phase;
+    A.draine_alpha = common->draine_alpha;
     A.surface_albedo = common->surface_albedo;
     A.peel_w = 1.0;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
@@ -1292,7 +1297,8 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
             OpacRes* op = I.ls.op;
             const PrepSlot* ps = (const PrepSlot*)v_slots + (a - s0);
             launch_prep_optics(I.ls.g->dev, I.ls.g->ncell, ps, e - a, 0, op->nT, op->nP, op->T_grid, op->lnP_grid,
-                               op->lnk, op->nspec, nullptr, st);
+                               op->lnk, op->nspec, nullptr, common->cloud_phase == 2 ? 1 : 0,
+                               common->draine_alpha, st);
             if (I.mode == MCRT_MODE_EMISSION)
                 launch_prep_sources(I.ls.g->dev, I.ls.g->ncell, ps, e - a, I.p.tau_vert_max, I.p.emis_bias,
                                     (double*)v_ps, st);
@@ -1702,6 +1708,7 @@ void mcrt_default_params(mcrt_solve_params* p)
     p->n_b = 256;
     p->n_alpha = 360;
     p->r_star = 6.957e10;
+    p->draine_alpha = 0.5;
 }
 
 int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, int32_t* grid_id)

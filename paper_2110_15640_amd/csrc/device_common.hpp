@@ -105,6 +105,27 @@ __device__ __forceinline__ void rotate_dir(double& dx, double& dy, double& dz, d
     dz = nz / n;
 }
 
+// ------------------------------------------------------ Draine phase function
+// Draine's hybrid HG-Rayleigh function (Sect. 3, aerosol scattering) is
+// P_HG(G) (1 + alpha mu^2) / (1 + alpha (1 + 2 G^2)/3); its mean cosine
+// G (1 + alpha (3 + 2 G^2)/5) / (1 + alpha (1 + 2 G^2)/3) rises from -1 to 1
+// on [-1, 1], so the G of a cloud with asymmetry factor g is found by
+// bisection to the last bit (alpha = 0: HG, G = g).
+__host__ __device__ inline double draine_G(double g, double alpha)
+{
+    if (alpha == 0.0) return g;
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        const double m = mid * (1.0 + alpha * (3.0 + 2.0 * mid * mid) / 5.0) /
+                         (1.0 + alpha * (1.0 + 2.0 * mid * mid) / 3.0);
+        if (m < g) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 // ------------------------------------------------- stellar limb darkening
 // I(mu)/I(1) of the stellar disk at zenith cosine mu (Sect. 5.1.1): laws
 // 0 none, 1 linear, 2 quadratic, 3 square-root, 4 logarithmic,

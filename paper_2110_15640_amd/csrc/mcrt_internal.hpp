@@ -114,7 +114,8 @@ struct BatchArgs {
     double obs[2][3 * kMaxObs];  // observer directions for albedo [0] and emission [1] solves
     int batch;         // packets a wave takes from the dispenser at once
     int ev_threshold;  // waiting lanes that trigger event handling
-    int cloud_phase;   // 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein
+    int cloud_phase;   // 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein, 2 Draine (g_cld holds G)
+    double draine_alpha;
     double surface_albedo;  // 0: the lower boundary absorbs; > 0: Lambert albedo of the floor
     // transmission with multiple scattering: births on the annulus, the birth
     // peel-off is the direct light (no 1/4pi), later peel-offs are scaled by
@@ -145,7 +146,7 @@ struct PrepSlot {
 
 void launch_prep_optics(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, int hires, int nT,
                         int nP, const double* T_grid, const double* lnP_grid, const double* lnk_tpl, int nlam,
-                        const double* shift, hipStream_t stream);
+                        const double* shift, int draine, double alpha, hipStream_t stream);
 void launch_prep_sources(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, double tau_vert,
                          double xi, double* scratch, hipStream_t stream);
 size_t prep_scratch_doubles(int ncell, int nslots);

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_prep_optics(GridDev g, int ncell, const
                                                      int hires, int nT, int nP, const double* __restrict__ T_grid,
                                                      const double* __restrict__ lnP_grid,
                                                      const double* __restrict__ lnk_tpl, int nlam,
-                                                     const double* __restrict__ shift)
+                                                     const double* __restrict__ shift, int draine, double alpha)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -72,6 +72,7 @@ __global__ void __launch_bounds__(256) k_prep_optics(GridDev g, int ncell, const
         om = kext > 0.0 ? ksc / kext : 0.0;
         pg = ksc > 0.0 ? S.k_ray / ksc : 1.0;
         gc = g.cld_g ? (double)g.cld_g[c] : 0.0;
+        if (draine) gc = draine_G(gc, alpha);  // Draine clouds carry G in place of g
     } else {
         double kl = hires_kappa_at(lnk_tpl, nlam, nP, bt, bp, S.n, shift ? shift[c] : 0.0);
         double kext = kl + S.k_ray;
@@ -281,10 +282,10 @@ size_t prep_scratch_doubles(int ncell, int nslots)
 
 void launch_prep_optics(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, int hires, int nT, int nP,
                         const double* T_grid, const double* lnP_grid, const double* lnk_tpl, int nlam,
-                        const double* shift, hipStream_t stream)
+                        const double* shift, int draine, double alpha, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_prep_optics, dim3(nb(ncell, 256), nslots), dim3(256), 0, stream, g, ncell, slots, hires, nT,
-                       nP, T_grid, lnP_grid, lnk_tpl, nlam, shift);
+                       nP, T_grid, lnP_grid, lnk_tpl, nlam, shift, draine, alpha);
 }
 
 void launch_prep_sources(const GridDev& g, int ncell, const PrepSlot* slots, int nslots, double tau_vert, double xi,

@@ -309,21 +309,36 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
         globe = draw(A.seed, S.tag, q, L.e(), 2).b < a ? gc : g2;
     }
+    // Draine clouds (g_cld holds G): rejection from HG(G), candidate 0 from
+    // block 1, slot a with acceptance block 2, slot b; candidate k >= 1 from
+    // block 2 + k; at most 32 candidates
+    const bool draine = A.cloud_phase == 2 && !sf && !(usel < pg);
     if (MIXED) {
         float z = fminf((float)u1.a, 0.99999994f);
         float mu;
         float g32 = (float)globe;
+        auto hgs = [g32](float zz) {
+            if (fabsf(g32) < 1e-6f) return 2.0f * zz - 1.0f;
+            const float t = (1.0f - g32 * g32) / (1.0f - g32 + 2.0f * g32 * zz);
+            return (1.0f + g32 * g32 - t * t) / (2.0f * g32);
+        };
         if (sf) {
             mu = sqrtf(z);
         } else if ((float)usel < (float)pg) {
             float qq = 4.0f * z - 2.0f;
             float u = cbrtf(qq + sqrtf(qq * qq + 1.0f));
             mu = u - 1.0f / u;
-        } else if (fabsf(g32) < 1e-6f) {
-            mu = 2.0f * z - 1.0f;
         } else {
-            float t = (1.0f - g32 * g32) / (1.0f - g32 + 2.0f * g32 * z);
-            mu = (1.0f + g32 * g32 - t * t) / (2.0f * g32);
+            mu = hgs(z);
+        }
+        if (draine) {
+            const float al = (float)A.draine_alpha;
+            float zc = (float)draw(A.seed, S.tag, q, L.e(), 2).b;
+            for (int k = 1; k < 32 && !(zc * (1.0f + al) < 1.0f + al * mu * mu); ++k) {
+                const U2 cd = draw(A.seed, S.tag, q, L.e(), 2 + k);
+                mu = hgs(fminf((float)cd.a, 0.99999994f));
+                zc = (float)cd.b;
+            }
         }
         mu = fminf(fmaxf(mu, -1.0f), 1.0f);
         float st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
@@ -350,6 +365,15 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
         L.sdz() = ddz / n;
     } else {
         double mu = sf ? sqrt(u1.a) : ((usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, globe));
+        if (draine) {
+            const double al = A.draine_alpha;
+            double zc = draw(A.seed, S.tag, q, L.e(), 2).b;
+            for (int k = 1; k < 32 && !(zc * (1.0 + al) < 1.0 + al * mu * mu); ++k) {
+                const U2 cd = draw(A.seed, S.tag, q, L.e(), 2 + k);
+                mu = sample_hg(cd.a, globe);
+                zc = cd.b;
+            }
+        }
         rotate_dir(L.sdx(), L.sdy(), L.sdz(), mu, 2.0 * kPi * u1.b);
     }
     if (L.W < A.rr_threshold * L.W0()) {
@@ -412,6 +436,9 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 if (A.cloud_phase == 1) {
                     const float g2 = -0.5f * gcf, af = 1.0f - g2 * g2;
                     ph = af * hgf(gcf) + (1.0f - af) * hgf(g2);
+                } else if (A.cloud_phase == 2) {  // Draine (gcf is G)
+                    const float al = (float)A.draine_alpha;
+                    ph = hgf(gcf) * (1.0f + al * mu * mu) / (1.0f + al * (1.0f + 2.0f * gcf * gcf) / 3.0f);
                 } else {
                     ph = hgf(gcf);
                 }
@@ -425,6 +452,9 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 if (A.cloud_phase == 1) {
                     const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
                     pc = a * p_hg(mu, gc) + (1.0 - a) * p_hg(mu, g2);
+                } else if (A.cloud_phase == 2) {  // Draine (gc is G)
+                    const double al = A.draine_alpha;
+                    pc = p_hg(mu, gc) * (1.0 + al * mu * mu) / (1.0 + al * (1.0 + 2.0 * gc * gc) / 3.0);
                 } else {
                     pc = p_hg(mu, gc);
                 }

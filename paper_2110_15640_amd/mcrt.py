@@ -64,7 +64,8 @@ class SolveParams(ctypes.Structure):
                 ("g_sampling", _i32), ("cloud_phase", _i32),
                 ("surface_albedo", ctypes.c_double), ("ms_transmission", _i32), ("ld_law", _i32),
                 ("a_orbit", ctypes.c_double), ("ld_c1", ctypes.c_double), ("ld_c2", ctypes.c_double),
-                ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double)]
+                ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double),
+                ("draine_alpha", ctypes.c_double)]
 
 
 class BatchItem(ctypes.Structure):

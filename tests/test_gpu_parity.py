@@ -619,3 +619,45 @@ def test_ms_transmission_and_limb_darkening_parity(ctx, torch_dev):
     check_solve(got, ref)
     ctx.free_grid(hid)
     ctx.free_opacity(hoid)
+
+
+def test_draine_clouds_parity(ctx, torch_dev):
+    """Draine clouds (G from the asymmetry factor in the optics preparation,
+    exact rejection sampler): every packet against the oracle (emission with
+    clouds, FP64, alpha = 0.5), the albedo spectrum (alpha = 1), a batch equal
+    to its single solves, and the mixed form within 1e-3 / 3 sigma."""
+    _log("Draine clouds: emission 16x8x10 with clouds, albedo sphere, batch, mixed vs fp64")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2, config_no=90)
+    rng = np.random.default_rng(23)
+    grid.cld_ksca = rng.uniform(0, 6e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 5e-3, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.3, 0.95, grid.ncell).astype(np.float32)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 1500
+    dump = dump_buffer(torch_dev, 4, n, 4)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=141, obs_phase=phases, packet_dump=dump,
+                             cloud_phase=2)
+    ref = O.solve_emission(grid, table, O.Params(n_packets=n, seed=141, obs_phase=tuple(phases), cloud_phase=2),
+                           keep_packets=True)
+    check_packets(dump, ref, (2, 2, n, 4))
+    check_solve(got, ref)
+    kw = dict(n_packets=4000, seed=143, obs_phase=[0.0, 1.1], cloud_phase=2, draine_alpha=1.0)
+    alb = ctx.solve_albedo(gid, oid, table, **kw)
+    aref = O.solve_albedo(grid, table, O.Params(**dict(kw, obs_phase=(0.0, 1.1))))
+    check_solve(alb, aref)
+    mix = ctx.solve_albedo(gid, oid, table, precision=M.MCRT_MIXED, **kw)
+    assert np.all(np.abs(mix["value"] - alb["value"]) <= np.maximum(3.0 * alb["stderr"], 1e-3 * np.abs(alb["value"])))
+    items = [dict(mode="emission", gid=gid, oid=oid, table=table, spec_idx=[1], n_packets=900),
+             dict(mode="albedo", gid=gid, oid=oid, table=table, spec_idx=[0], n_packets=700)]
+    common = dict(obs_phase=[0.25, 0.5], seed=145, decorrelate=1, cloud_phase=2)
+    outs = ctx.solve_batch(items, **common)
+    for it, b in zip(items, outs):
+        fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
+        one = fn(it["gid"], it["oid"], it["table"], spec_idx=it["spec_idx"], n_packets=it["n_packets"], **common)
+        assert np.array_equal(b["sums"], one["sums"]) and np.array_equal(b["counters"], one["counters"])
+    with pytest.raises(M.McrtError) as e:
+        ctx.solve_albedo(gid, oid, table, n_packets=10, obs_phase=[0.0], cloud_phase=2, draine_alpha=1.5)
+    assert e.value.name == "EINVAL"
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
