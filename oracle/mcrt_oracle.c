@@ -204,6 +204,34 @@ double orc_sample_draine(const double *za, const double *zacc, int n, double G, 
     return mu;
 }
 
+/* Forced interaction of a flight whose path to the edge of the grid has
+ * optical depth tp (0 < tp < inf) (Sect. 4, forced interaction): tau is
+ * drawn with zeta (the flight's block 0, slot a) from a density q on
+ * [0, tp] and the packet's weight is multiplied by e^{-tau}/q(tau), while
+ * the fraction e^{-tp} that would have left unscattered is booked as
+ * escaped.  1: forced scattering, q = e^{-tau}/(1 - e^{-tp}) (the factor is
+ * 1 - e^{-tp}); 2: path-length stretching, q = l e^{-l tau}/(1 - e^{-l tp})
+ * with l = 1/(1 + tp); 3: hybrid, q the equal mixture of 1 and 2, the
+ * component chosen by zc < 1/2.                                            */
+double orc_forced_tau(int64_t kind, double tp, double zeta, double zc, double *wfac)
+{
+    double pf = -expm1(-tp);
+    double l = 1.0 / (1.0 + tp);
+    double pl = -expm1(-l * tp);
+    double tau;
+    if (kind == 1 || (kind == 3 && zc < 0.5)) tau = -log1p(-zeta * pf);
+    else tau = -log1p(-zeta * pl) / l;
+    if (kind == 1) {
+        *wfac = pf;
+    } else if (kind == 2) {
+        *wfac = exp(-tau) * pl / (l * exp(-l * tau));
+    } else {
+        double q = 0.5 * exp(-tau) / pf + 0.5 * l * exp(-l * tau) / pl;
+        *wfac = exp(-tau) / q;
+    }
+    return tau;
+}
+
 /* Candidates drawn for one Draine scattering (the last is taken if none of
  * the others is accepted: probability below (alpha/(1+alpha))^31). */
 #define ORC_DRAINE_MAXC 32
@@ -707,6 +735,9 @@ typedef struct {
     double transit_y, transit_z; /* planet centre on the stellar disk (sky plane), cm */
     double r_star;
     double draine_alpha;  /* alpha of Draine's function (cloud_phase 2) */
+    int64_t forced;       /* forced interaction: 0 off, 1 forced scattering, 2 path-length
+                           * stretching, 3 hybrid (equal mixture of 1 and 2) */
+    int64_t forced_first; /* 1: only the packet's first flight is forced */
 } orc_params;
 
 typedef struct {
@@ -780,6 +811,32 @@ static double peel_tau(const orc_grid *g, const orc_optics *op, const orc_ray *s
         if (tau > tau_cut) { *ncross += nc; return INFINITY; }
         if (ry.k >= g->nlay) { *ncross += nc; return tau; }
         if (ry.k < 0) { *ncross += nc; return INFINITY; }
+        if (nc >= max_cross) { *ncross += nc; return INFINITY; }
+    }
+}
+
+/* Optical depth along d from the event point to the edge of the grid (the
+ * extra ray trace of a forced interaction): *to_surface tells whether the
+ * path ends on the planet (or the slab's floor) rather than at the top;
+ * infinite when the walk fails or meets the crossing cap.                  */
+static double path_tau(const orc_grid *g, const orc_optics *op, const orc_ray *start, const double d[3],
+                       int64_t max_cross, int64_t *ncross, int *to_surface)
+{
+    orc_ray ry = *start;
+    ry.ef = F_NONE;
+    double tau = 0.0;
+    int64_t nc = 0;
+    for (;;) {
+        double s;
+        int f = exit_distance(g, &ry, d, &s);
+        if (f == F_NONE) { *ncross += nc; return INFINITY; }
+        int64_t c = cell_index(g, ry.i, ry.j, ry.k);
+        tau = tau + op->a_ext[c] * s;
+        advance(g, &ry, d, s);
+        cross_face(g, &ry, f);
+        nc++;
+        if (ry.k >= g->nlay) { *ncross += nc; *to_surface = 0; return tau; }
+        if (ry.k < 0) { *ncross += nc; *to_surface = 1; return tau; }
         if (nc >= max_cross) { *ncross += nc; return INFINITY; }
     }
 }
@@ -950,6 +1007,20 @@ static void run_packet(const orc_grid *g, const orc_optics *op, const orc_params
         double tau, usel;
         orc_draw(pr->seed, tag, pid, e, 0, &ua, &usel);
         tau = -log(ua);
+        if (pr->forced != 0 && (pr->forced_first == 0 || e == 1)) {
+            /* the extra ray trace: optical depth to the edge of the grid
+             * along d; the unscattered fraction is booked where the path ends */
+            int to_surf = 0;
+            double tp = path_tau(g, op, &ry, d, pr->max_cross, &ncross, &to_surf);
+            if (tp > 0.0 && tp < INFINITY) {
+                double zc, zd, wf;
+                orc_draw(pr->seed, tag, pid, e, 34, &zc, &zd);  /* hybrid component: block 34, slot a */
+                tau = orc_forced_tau(pr->forced, tp, ua, zc, &wf);
+                if (to_surf) K[K_SURF] += W * exp(-tp);
+                else K[K_ESC] += W * exp(-tp);
+                W = W * wf;
+            }
+        }
         int term = walk_flight(g, op, &ry, d, tau, cont, &W, &K[K_ABS], pr->max_cross, &ncross);
         if (term == T_ESCAPE) { K[K_ESC] += W; break; }
         if (term == T_SURFACE && !(pr->surface_albedo > 0.0)) { K[K_SURF] += W; break; }

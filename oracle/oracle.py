@@ -58,7 +58,8 @@ class _Params(ctypes.Structure):
                 ("cloud_phase", ctypes.c_int64), ("surface_albedo", ctypes.c_double),
                 ("omega_star", ctypes.c_double), ("ld_law", ctypes.c_int64), ("ld_c1", ctypes.c_double),
                 ("ld_c2", ctypes.c_double), ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double),
-                ("r_star", ctypes.c_double), ("draine_alpha", ctypes.c_double)]
+                ("r_star", ctypes.c_double), ("draine_alpha", ctypes.c_double),
+                ("forced", ctypes.c_int64), ("forced_first", ctypes.c_int64)]
 
 
 class _Optics(ctypes.Structure):
@@ -126,6 +127,8 @@ def lib():
         L.orc_phase_draine.restype = dbl
         L.orc_sample_draine.argtypes = [vp, vp, ctypes.c_int, dbl, dbl]
         L.orc_sample_draine.restype = dbl
+        L.orc_forced_tau.argtypes = [i64, dbl, dbl, dbl, vp]
+        L.orc_forced_tau.restype = dbl
         L.orc_limb_darkening.argtypes = [i64, dbl, dbl, dbl]
         L.orc_limb_darkening.restype = dbl
         L.orc_chord_limb_weight.argtypes = [i64, dbl, dbl, dbl, dbl, dbl, dbl, dbl]
@@ -205,6 +208,13 @@ def phase_draine(mu, G, alpha):
 def sample_draine(za, zacc, G, alpha):
     a, b = _f64(za), _f64(zacc)
     return lib().orc_sample_draine(a.ctypes.data, b.ctypes.data, len(a), float(G), float(alpha))
+
+
+def forced_tau(kind, tp, zeta, zc):
+    """(tau, weight factor) of a forced flight over a path of depth tp."""
+    w = np.zeros(1)
+    t = lib().orc_forced_tau(int(kind), float(tp), float(zeta), float(zc), w.ctypes.data)
+    return t, float(w[0])
 
 
 def rotate(d, mu, psi):
@@ -335,6 +345,8 @@ class Params:
     g_sampling: int = 0  # 0 fixed-g solves; per-packet g: 1 unbiased, 2 uniform, 3 composite
     cloud_phase: int = 0  # 0 Henyey-Greenstein, 1 two-term Henyey-Greenstein, 2 Draine
     draine_alpha: float = 0.5  # alpha of Draine's function
+    forced: int = 0  # forced interaction: 0 off, 1 forced scattering, 2 path-length stretching, 3 hybrid
+    forced_first: int = 0  # 1: only the first flight of a packet is forced
     surface_albedo: float = 0.0  # 0 absorbing lower boundary; > 0 Lambert surface
     a_orbit: float = 0.0  # star-planet distance [cm] (transmission with scattering)
     ld_law: int = 0  # stellar limb darkening: 0 none, 1 linear, 2 quadratic, 3 sqrt, 4 log, 5 exp, 6 power-2
@@ -388,7 +400,8 @@ def _params(params: Params, mode: int, tag: int, max_cross: int, nobs: int) -> _
                    params.rr_threshold, params.rr_survive, params.tau_peel_max, params.mu0,
                    int(params.cloud_phase), float(params.surface_albedo), omega_star(params),
                    int(params.ld_law), float(params.ld_c1), float(params.ld_c2), float(params.transit_y),
-                   float(params.transit_z), float(params.r_star), float(params.draine_alpha))
+                   float(params.transit_z), float(params.r_star), float(params.draine_alpha),
+                   int(params.forced), int(params.forced_first))
 
 
 def limb_darkening(law: int, c1: float, c2: float, mu: float) -> float:
