@@ -239,6 +239,22 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   b), the 32nd taken if none before is accepted.  Other values: EINVAL.
  * draine_alpha: in [0, 1] (default 0.5; 1 = Cornette-Shanks); EINVAL
  *   outside.
+ * forced: forced interactions (Sect. 4, forced interaction), albedo,
+ *   emission and multiple-scattering transmission: before a flight, an extra
+ *   ray trace finds the optical depth tp to the edge of the grid along the
+ *   packet direction (the top, or the planet / the slab floor); with
+ *   0 < tp < inf the flight's tau is drawn with the flight's own zeta (block
+ *   0, slot a) from a density q on [0, tp], the weight is multiplied by
+ *   e^{-tau}/q(tau) and the fraction W e^{-tp} is booked as escaped (or to
+ *   SURF when the path ends on the floor).  0 off; 1 forced scattering,
+ *   q = e^{-tau}/(1 - e^{-tp}); 2 path-length stretching,
+ *   q = l e^{-l tau}/(1 - e^{-l tp}) with l = 1/(1 + tp); 3 hybrid, the
+ *   equal mixture, its component chosen by block 34, slot a < 1/2.  Needs
+ *   MCRT_SURVIVAL and surface_albedo = 0 (EINVAL otherwise); the probe's
+ *   crossings count in NCROSS.  A packet forced on every flight leaves only
+ *   through the roulette or the event cap.
+ * forced_first: 1 = only a packet's first flight is forced ("forced first
+ *   scattering"); 0 = every flight.
  * surface_albedo: 0 = the lower boundary absorbs every packet that reaches
  *   it; A_s in (0, 1] = a Lambert floor (Sect. 3, surface scattering): a
  *   packet reaching it peels off W A_s max(n.o, 0)/pi e^{-tau} toward each
@@ -290,6 +306,8 @@ typedef struct {
     double transit_y;
     double transit_z;
     double draine_alpha;
+    int32_t forced;
+    int32_t forced_first;
 } mcrt_solve_params;
 
 void mcrt_default_params(mcrt_solve_params* p);

@@ -414,6 +414,10 @@ int plan_common(hipStream_t def_stream, GridRes* g, OpacRes* op, const mcrt_solv
     if (p->cloud_phase < 0 || p->cloud_phase > 2)
         return fail(MCRT_EINVAL, "cloud_phase must be 0 (HG), 1 (TTHG) or 2 (Draine)");
     if (!(p->draine_alpha >= 0.0 && p->draine_alpha <= 1.0)) return fail(MCRT_EINVAL, "draine_alpha must be in [0, 1]");
+    if (p->forced < 0 || p->forced > 3 || (p->forced_first != 0 && p->forced_first != 1))
+        return fail(MCRT_EINVAL, "forced must be 0 to 3 and forced_first 0 or 1");
+    if (p->forced && (p->absorption != MCRT_SURVIVAL || p->surface_albedo > 0.0))
+        return fail(MCRT_EINVAL, "forced interactions need survival biasing and an absorbing lower boundary");
     if (!(p->surface_albedo >= 0.0 && p->surface_albedo <= 1.0))
         return fail(MCRT_EINVAL, "surface_albedo must be in [0, 1]");
     if (!(p->mu0 <= 1.0)) return fail(MCRT_EINVAL, "mu0 must be <= 1");
@@ -707,6 +711,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     A.ev_threshold = p->tune_ev_threshold > 0 ? p->tune_ev_threshold : 16;
     A.cloud_phase = p->cloud_phase;
     A.draine_alpha = p->draine_alpha;
+    A.forced = p->forced;
+    A.forced_first = p->forced_first;
     A.surface_albedo = p->surface_albedo;
     A.trans_ms = mode == MCRT_MODE_TRANSMISSION ? 1 : 0;
     if (A.trans_ms) {
@@ -745,9 +751,9 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
                                  p->mu0, (double)p->max_events, p->surface_albedo, p->r_star, p->a_orbit,
                                  p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->draine_alpha};
         add(dpar, sizeof dpar);
-        const int64_t ipar[14] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
+        const int64_t ipar[16] = {(int64_t)p->seed, (int64_t)N, p->precision, p->decorrelate, p->scattering,
                                   p->absorption, batch, A.ev_threshold, bpc, A.batch, npix, p->g_sampling,
-                                  p->cloud_phase, p->ld_law};
+                                  p->cloud_phase, p->ld_law, p->forced, p->forced_first};
         add(ipar, sizeof ipar);
         add(pl.obs.data(), sizeof(double) * pl.obs.size());
         add(pl.specs.data(), sizeof(int) * pl.specs.size());
@@ -1225,6 +1231,8 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     A.ev_threshold = common->tune_ev_threshold > 0 ? common->tune_ev_threshold : 16;
     A.cloud_phase = common->cloud_phase;
     A.draine_alpha = common->draine_alpha;
+    A.forced = common->forced;
+    A.forced_first = common->forced_first;
     A.surface_albedo = common->surface_albedo;
     A.peel_w = 1.0;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;

@@ -126,6 +126,30 @@ __host__ __device__ inline double draine_G(double g, double alpha)
     return 0.5 * (lo + hi);
 }
 
+// ------------------------------------------------------ forced interaction
+// Optical depth of a forced flight over a path of depth tp (0 < tp < inf)
+// from zeta, and the weight factor e^{-tau}/q(tau) of its density q on
+// [0, tp]: kind 1 forced scattering q = e^{-tau}/(1 - e^{-tp}); kind 2
+// path-length stretching q = l e^{-l tau}/(1 - e^{-l tp}), l = 1/(1 + tp);
+// kind 3 their equal mixture, the component picked by zc < 1/2.
+__host__ __device__ inline double forced_tau(int kind, double tp, double zeta, double zc, double& wf)
+{
+    const double pf = -expm1(-tp);
+    const double l = 1.0 / (1.0 + tp);
+    const double pl = -expm1(-l * tp);
+    const bool stretch = kind == 2 || (kind == 3 && !(zc < 0.5));
+    const double tau = stretch ? -log1p(-zeta * pl) / l : -log1p(-zeta * pf);
+    if (kind == 1) {
+        wf = pf;
+    } else if (kind == 2) {
+        wf = exp(-tau) * pl / (l * exp(-l * tau));
+    } else {
+        const double q = 0.5 * exp(-tau) / pf + 0.5 * l * exp(-l * tau) / pl;
+        wf = exp(-tau) / q;
+    }
+    return tau;
+}
+
 // ------------------------------------------------- stellar limb darkening
 // I(mu)/I(1) of the stellar disk at zenith cosine mu (Sect. 5.1.1): laws
 // 0 none, 1 linear, 2 quadratic, 3 square-root, 4 logarithmic,

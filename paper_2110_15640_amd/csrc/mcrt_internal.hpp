@@ -123,6 +123,8 @@ struct BatchArgs {
     // row holds W0 - F
     int trans_ms;
     double peel_w;
+    int forced;        // forced interaction: 0 off, 1 forced scattering, 2 path-length stretching, 3 hybrid
+    int forced_first;  // 1: only a packet's first flight
     LimbDark ld;
     // images: npix x npix pixels over [-img_half, img_half]^2 of each
     // observer's sky plane, horizontal / vertical unit vectors per observer

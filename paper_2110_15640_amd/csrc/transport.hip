@@ -34,13 +34,21 @@ namespace mcrt {
 namespace {
 using namespace dev;
 
-enum { M_FLIGHT = 0, M_PEEL = 1, M_EVENT = 2, M_DEAD = 3, M_BIRTH = 4, M_IDLE = 5 };
+// Lane modes; the walking ones come first: a flight, a peel-off ray, or the
+// probe of a forced interaction (the optical depth to the grid's edge along
+// the packet direction).
+enum { M_FLIGHT = 0, M_PEEL = 1, M_PROBE = 2, M_EVENT = 3, M_DEAD = 4, M_BIRTH = 5, M_IDLE = 6 };
+// Observer-field values outside the observer range: the walk that ended was a
+// probe, or the next flight's optical depth is already chosen.
+constexpr int kProbeDone = 15, kTauSet = 14;
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
 // Birth record of a packet, kept in the counter columns of its row until the
 // packet dies: position, direction, weight, cell * 8 + (entry face + 1)
 // (-1: nothing emits), then the index of the solve whose optics it uses;
-// with a Lambert floor, the weight the floor has absorbed so far.
-enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE, B_SURF };
+// with a Lambert floor, the weight the floor has absorbed so far; with
+// forced interactions, the unscattered fractions booked so far to the floor
+// (B_SURF) and to escape (B_FESC).
+enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE, B_SURF, B_FESC };
 
 // Per-lane state that the cell walk does not touch lives in LDS (one slot
 // per lane, structure of arrays) so the registers hold only the walking ray;
@@ -130,16 +138,26 @@ __device__ __forceinline__ double ld(const void* p, int c)
 }
 
 // Write the packet's row: its peel-off sums, then the counters; `kind` says
-// where its remaining weight went.
+// where its remaining weight went.  EXT (here and below): the kernel form
+// with the Lambert floor, Draine clouds, forced interactions and
+// multiple-scattering transmission; without it that code is compiled out.
+template <bool EXT>
 __device__ __forceinline__ void finish_packet(Lane& L, const BatchArgs& A, int kind)
 {
     double* row = A.rows + L.gid() * (unsigned long long)A.row_w;
-    for (int o = 0; o < A.n_out; ++o) row[o] = A.trans_ms ? L.W0() - L.Fo(o) : L.Fo(o);
+    for (int o = 0; o < A.n_out; ++o) row[o] = (EXT && A.trans_ms) ? L.W0() - L.Fo(o) : L.Fo(o);
     row += A.n_out;
-    // a Lambert floor never ends a packet; it has kept its absorbed share
-    const double wsurf = A.surface_albedo > 0.0 ? row[B_SURF] : 0.0;
-    row[K_ESC] = kind == K_ESC ? L.W : 0.0;
-    row[K_SURF] = kind == K_SURF ? L.W : wsurf;
+    if (EXT) {
+        // weight booked before the end: absorbed by a Lambert floor (which
+        // never ends a packet) or the unscattered fractions of forced flights
+        const double wsurf = (A.surface_albedo > 0.0 || A.forced) ? row[B_SURF] : 0.0;
+        const double wesc = A.forced ? row[B_FESC] : 0.0;
+        row[K_ESC] = kind == K_ESC ? wesc + L.W : wesc;
+        row[K_SURF] = kind == K_SURF ? wsurf + L.W : wsurf;
+    } else {
+        row[K_ESC] = kind == K_ESC ? L.W : 0.0;
+        row[K_SURF] = kind == K_SURF ? L.W : 0.0;
+    }
     row[K_ABS] = L.w_abs;
     row[K_RR] = L.w_rr();
     row[K_CAP] = kind == K_CAP ? L.W : 0.0;
@@ -169,38 +187,75 @@ __device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const doub
 }
 
 // Start the lane's next walk from its event point: a flight along the
-// packet direction (optical depth drawn from the event's block 0, slot a) or
-// a peel-off ray toward the current observer.  Both use one inlined walker
-// start, so a wave starting both kinds runs it once.
+// packet direction (optical depth drawn from the event's block 0, slot a,
+// unless a forced interaction chose it), a peel-off ray toward the current
+// observer, or, before a forced flight, the probe along the packet
+// direction.  All use one inlined walker start, so a wave starting several
+// kinds runs it once.
+template <bool EXT>
 __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs,
                                            bool flight)
 {
     double dx, dy, dz;
     int ef;
-    if (flight) {
-        const SolveDev& S = A.solves[L.solve()];
-        U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
-        L.tau = -log(u.a);
-        dx = L.sdx();
-        dy = L.sdy();
-        dz = L.sdz();
-        ef = L.sef();
+    if constexpr (!EXT) {
+        if (flight) {
+            const SolveDev& S = A.solves[L.solve()];
+            U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
+            L.tau = -log(u.a);
+            dx = L.sdx();
+            dy = L.sdy();
+            dz = L.sdz();
+            ef = L.sef();
+        } else {
+            observer(L, A, sobs, dx, dy, dz);
+            L.tau = 0.0;
+            ef = F_NONE;
+        }
+        wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
+        L.ncw = 0;
+        L.mode = flight ? M_FLIGHT : M_PEEL;
+        if (!flight && g.geom == 1 && !(dz > 0.0)) {  // a slab peel-off ray that never reaches the top
+            L.tau = INFINITY;
+            L.mode = M_EVENT;
+            L.ev = E_PEEL_DONE;
+        }
     } else {
-        observer(L, A, sobs, dx, dy, dz);
-        L.tau = 0.0;
-        ef = F_NONE;
-    }
-    wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
-    L.ncw = 0;
-    L.mode = flight ? M_FLIGHT : M_PEEL;
-    // a slab peel-off ray that never reaches the top, or a floor peel-off
-    // ray below the horizon (the floor's normal is the packet direction then)
-    const bool dark = !flight && ((g.geom == 1 && !(dz > 0.0)) ||
-                                  (L.surf() && !(L.sdx() * dx + L.sdy() * dy + L.sdz() * dz > 0.0)));
-    if (dark) {
-        L.tau = INFINITY;
-        L.mode = M_EVENT;
-        L.ev = E_PEEL_DONE;
+        int kind = flight ? M_FLIGHT : M_PEEL;
+        if (flight && A.forced != 0 && L.o() != kTauSet && (A.forced_first == 0 || L.e() == 1)) kind = M_PROBE;
+        if (kind == M_FLIGHT) {
+            if (A.forced != 0 && L.o() == kTauSet) {
+                L.o() = 0;
+            } else {
+                const SolveDev& S = A.solves[L.solve()];
+                U2 u = draw(A.seed, S.tag, L.gid() - S.pbase, L.e(), 0);
+                L.tau = -log(u.a);
+            }
+            ef = L.sef();
+        } else {
+            L.tau = 0.0;
+            ef = F_NONE;
+        }
+        if (kind == M_PEEL) {
+            observer(L, A, sobs, dx, dy, dz);
+        } else {
+            dx = L.sdx();
+            dy = L.sdy();
+            dz = L.sdz();
+        }
+        if (kind == M_PROBE) L.o() = kProbeDone;
+        wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
+        L.ncw = 0;
+        L.mode = kind;
+        // a slab peel-off ray that never reaches the top, or a floor peel-off
+        // ray below the horizon (the floor's normal is the packet direction then)
+        const bool dark = kind == M_PEEL && ((g.geom == 1 && !(dz > 0.0)) ||
+                                             (L.surf() && !(L.sdx() * dx + L.sdy() * dy + L.sdz() * dz > 0.0)));
+        if (dark) {
+            L.tau = INFINITY;
+            L.mode = M_EVENT;
+            L.ev = E_PEEL_DONE;
+        }
     }
 }
 
@@ -211,7 +266,7 @@ __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const Batc
 // the crossing: a lane whose walk ends in this cell (interaction, surface
 // hit, end of a peel-off) discards its walker afterwards, so the walker is
 // never kept in two versions.
-template <bool MIXED>
+template <bool MIXED, bool EXT>
 __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
                                           const BatchArgs& A)
 {
@@ -263,9 +318,12 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
         done = !inside || L.ncw >= g.max_cross;
         if (done) L.ev = !inside ? (L.w.k >= g.nlay ? E_ESCAPE : E_SURFACE) : E_LOST;
     } else {
+        // a probe runs to the edge of the grid, the floor included; a
+        // peel-off ray stops beyond tau_peel_max or on the planet
+        const bool probe = EXT && L.mode == M_PROBE;
         done = true;
-        if (L.tau > A.tau_peel_max) L.tau = INFINITY;
-        else if (!inside) { if (L.w.k < 0) L.tau = INFINITY; }
+        if (L.tau > (probe ? INFINITY : A.tau_peel_max)) L.tau = INFINITY;
+        else if (!inside) { if (L.w.k < 0 && !probe) L.tau = INFINITY; }
         else if (L.ncw >= g.max_cross) L.tau = INFINITY;
         else done = false;
         if (done) L.ev = E_PEEL_DONE;
@@ -284,11 +342,11 @@ enum { A_NONE = 0, A_PEEL = 1, A_FLIGHT = 2, A_SCATTER = 3, A_FINISH = 4 };
 // A reflection by the Lambert floor takes the same steps: its albedo is A_s,
 // its absorbed share goes to the floor, and its polar cosine about the
 // normal (held as the packet direction) is sqrt(zeta), block 1, slot a.
-template <bool MIXED>
+template <bool MIXED, bool EXT>
 __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArgs& A, const SolveDev& S)
 {
     const unsigned long long q = L.gid() - S.pbase;
-    const bool sf = L.surf();
+    const bool sf = EXT && L.surf();
     const int c = L.cell(g);
     const double om = sf ? A.surface_albedo : ld<MIXED>(S.omega, c);
     const double pg = sf ? 0.0 : ld<MIXED>(S.p_gas, c), gc = sf ? 0.0 : ld<MIXED>(S.g_cld, c);
@@ -312,7 +370,7 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
     // Draine clouds (g_cld holds G): rejection from HG(G), candidate 0 from
     // block 1, slot a with acceptance block 2, slot b; candidate k >= 1 from
     // block 2 + k; at most 32 candidates
-    const bool draine = A.cloud_phase == 2 && !sf && !(usel < pg);
+    const bool draine = EXT && A.cloud_phase == 2 && !sf && !(usel < pg);
     if (MIXED) {
         float z = fminf((float)u1.a, 0.99999994f);
         float mu;
@@ -407,15 +465,37 @@ __device__ __forceinline__ int pixel_of(double x, double half, int npix)
 
 // Bookkeeping of one event; returns the action that follows.  L.ev carries
 // the counter that receives the final weight when the action is A_FINISH.
-template <bool MIXED>
+template <bool MIXED, bool EXT>
 __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const BatchArgs& A)
 {
     const SolveDev& S = A.solves[L.solve()];
+    if (EXT && L.ev == E_PEEL_DONE && L.o() == kProbeDone) {
+        // forced interaction: with the path's optical depth tp known, the
+        // flight's tau comes from a density on [0, tp], the weight takes the
+        // factor e^{-tau}/q(tau) and the unscattered fraction W e^{-tp} is
+        // booked where the path ends (nothing is forced when tp is 0 or
+        // infinite: a walk failure or the crossing cap)
+        const double tp = L.tau;
+        const unsigned long long q = L.gid() - S.pbase;
+        const U2 u = draw(A.seed, S.tag, q, L.e(), 0);
+        double tau = -log(u.a);
+        if (tp > 0.0 && tp < INFINITY) {
+            double wf;
+            tau = forced_tau(A.forced, tp, u.a, draw(A.seed, S.tag, q, L.e(), 34).a, wf);
+            double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+            const int slot = L.w.k < 0 ? B_SURF : B_FESC;
+            b[slot] = b[slot] + L.W * exp(-tp);
+            L.W = L.W * wf;
+        }
+        L.tau = tau;
+        L.o() = kTauSet;
+        return A_FLIGHT;
+    }
     if (L.ev == E_PEEL_DONE) {
         double f;
         if (L.birth()) {  // emission point (isotropic), or a transmission chord's direct light
-            f = A.trans_ms ? L.W * exp(-L.tau) : L.W * exp(-L.tau) / (4.0 * kPi);
-        } else if (L.surf()) {  // Lambert floor: W A_s max(n.o, 0)/pi e^{-tau}, n held as the direction
+            f = (EXT && A.trans_ms) ? L.W * exp(-L.tau) : L.W * exp(-L.tau) / (4.0 * kPi);
+        } else if (EXT && L.surf()) {  // Lambert floor: W A_s max(n.o, 0)/pi e^{-tau}, n held as the direction
             const double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
             f = mu > 0.0 ? L.W * A.surface_albedo * (mu / kPi) * exp(-L.tau) : 0.0;
         } else {
@@ -436,7 +516,7 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 if (A.cloud_phase == 1) {
                     const float g2 = -0.5f * gcf, af = 1.0f - g2 * g2;
                     ph = af * hgf(gcf) + (1.0f - af) * hgf(g2);
-                } else if (A.cloud_phase == 2) {  // Draine (gcf is G)
+                } else if (EXT && A.cloud_phase == 2) {  // Draine (gcf is G)
                     const float al = (float)A.draine_alpha;
                     ph = hgf(gcf) * (1.0f + al * mu * mu) / (1.0f + al * (1.0f + 2.0f * gcf * gcf) / 3.0f);
                 } else {
@@ -452,7 +532,7 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                 if (A.cloud_phase == 1) {
                     const double g2 = -0.5 * gc, a = 1.0 - g2 * g2;
                     pc = a * p_hg(mu, gc) + (1.0 - a) * p_hg(mu, g2);
-                } else if (A.cloud_phase == 2) {  // Draine (gc is G)
+                } else if (EXT && A.cloud_phase == 2) {  // Draine (gc is G)
                     const double al = A.draine_alpha;
                     pc = p_hg(mu, gc) * (1.0 + al * mu * mu) / (1.0 + al * (1.0 + 2.0 * gc * gc) / 3.0);
                 } else {
@@ -465,7 +545,7 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         }
         // scattered light of a transmission packet: per steradian, over the
         // stellar beam's solid angle (peel_w = 1 otherwise)
-        if (!L.birth()) f = f * A.peel_w;
+        if (EXT && !L.birth()) f = f * A.peel_w;
         L.Fo(L.o()) += f;
         if ((S.cf || S.img) && f > 0.0) {
             const double sc = f * (S.cf_ltot ? S.cf_w * *S.cf_ltot : S.cf_w);
@@ -499,10 +579,10 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
         L.nint() += 1;
         L.o() = 0;
         L.birth() = 0;
-        L.surf() = 0;
+        if (EXT) L.surf() = 0;
         return A_PEEL;
     }
-    if (L.ev == E_SURFACE && A.surface_albedo > 0.0) {
+    if (EXT && L.ev == E_SURFACE && A.surface_albedo > 0.0) {
         // the floor reflects: an event on the surface of the lowest cell,
         // entered through its inner face; until the reflection the packet
         // direction holds the floor's outward normal (radial on a sphere, +z
@@ -690,10 +770,15 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 
 // New packet L.gid: load its birth record and return the first action (a
 // flight for albedo, the emission-point peel-off, or finish if none emits).
+template <bool EXT>
 __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs& A)
 {
-    double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
-    if (A.surface_albedo > 0.0) b[B_SURF] = 0.0;
+    const double* b = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+    if (EXT) {
+        double* bw = A.rows + L.gid() * (unsigned long long)A.row_w + A.n_out;
+        if (A.surface_albedo > 0.0 || A.forced) bw[B_SURF] = 0.0;
+        if (A.forced) bw[B_FESC] = 0.0;
+    }
     const int sv = (int)b[B_SOLVE];
     const SolveDev& S = A.solves[sv];
     L.C->st[L.t] = 0u;
@@ -727,7 +812,7 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
 // VGPRs per lane, 16 waves per CU, with some spills; 2: no spills, ~170 VGPRs,
 // so up to 3 waves per SIMD = 3 blocks per CU), chosen at launch from the
 // requested blocks per CU.
-template <bool MIXED, bool MULTI, int MINB>
+template <bool MIXED, bool MULTI, int MINB, bool EXT>
 __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1, BatchArgs A)
 {
     __shared__ double sobs[2 * 3 * kMaxObs];
@@ -750,16 +835,16 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
     const void* aabs = nullptr;
     for (;;) {
         const GridDev& g = MULTI ? A.grids[lgrid] : g1;
-        if (L.mode <= M_PEEL) walk_step<MIXED>(L, g, aext, aabs, A);
+        if (L.mode <= M_PROBE) walk_step<MIXED, EXT>(L, g, aext, aabs, A);
         unsigned long long evm = __ballot(L.mode == M_EVENT);
-        unsigned long long walking = __ballot(L.mode <= M_PEEL);
+        unsigned long long walking = __ballot(L.mode <= M_PROBE);
         if (__popcll(evm) < A.ev_threshold && walking != 0) continue;
         int act = A_NONE;
-        if (L.mode == M_EVENT) act = handle_event<MIXED>(L, g, A);
-        if (act == A_SCATTER) act = scatter<MIXED>(L, g, A, A.solves[L.solve()]);
+        if (L.mode == M_EVENT) act = handle_event<MIXED, EXT>(L, g, A);
+        if (act == A_SCATTER) act = scatter<MIXED, EXT>(L, g, A, A.solves[L.solve()]);
         for (int pass = 0; pass < 2; ++pass) {
             if (act == A_FINISH) {
-                finish_packet(L, A, L.ev);
+                finish_packet<EXT>(L, A, L.ev);
                 act = A_NONE;
             }
             if (pass == 1) break;
@@ -809,14 +894,14 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
             if (L.mode == M_BIRTH) {
                 if (MULTI) lgrid = A.solves[solve_of(A, L.gid())].grid;
                 const GridDev& gb = MULTI ? A.grids[lgrid] : g1;
-                act = birth(L, gb, A);
+                act = birth<EXT>(L, gb, A);
                 const SolveDev& S = A.solves[L.solve()];  // the solve the birth record chose
                 aext = S.a_ext;
                 aabs = S.a_abs;
             }
         }
         const GridDev& ga = MULTI ? A.grids[lgrid] : g1;
-        if (act == A_FLIGHT || act == A_PEEL) start_walk(L, ga, A, sobs, act == A_FLIGHT);
+        if (act == A_FLIGHT || act == A_PEEL) start_walk<EXT>(L, ga, A, sobs, act == A_FLIGHT);
         if (__ballot(L.mode != M_IDLE) == 0) break;
     }
 }
@@ -935,15 +1020,21 @@ void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixe
                                  int blocks_per_cu, hipStream_t stream)
 {
     const bool wide = blocks_per_cu <= 3;  // up to 256 VGPRs: at most 3 waves per SIMD
-#define MCRT_K4(MX, MU)                                                                                       \
-    if (wide)                                                                                                 \
-        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 2>), dim3(blocks), dim3(kTPB), 0, stream, g, a);  \
-    else                                                                                                      \
-        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 4>), dim3(blocks), dim3(kTPB), 0, stream, g, a);
-    if (mixed && multi) { MCRT_K4(true, true) }
-    else if (mixed) { MCRT_K4(true, false) }
-    else if (multi) { MCRT_K4(false, true) }
-    else { MCRT_K4(false, false) }
+    // the extended form only when a launch uses one of its features
+    const bool ext = a.surface_albedo > 0.0 || a.cloud_phase == 2 || a.forced != 0 || a.trans_ms != 0;
+#define MCRT_K4(MX, MU, EX)                                                                                      \
+    if (wide)                                                                                                    \
+        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 2, EX>), dim3(blocks), dim3(kTPB), 0, stream, g, a); \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_transport_persistent<MX, MU, 4, EX>), dim3(blocks), dim3(kTPB), 0, stream, g, a);
+#define MCRT_K4X(MX, MU)              \
+    if (ext) { MCRT_K4(MX, MU, true) } \
+    else { MCRT_K4(MX, MU, false) }
+    if (mixed && multi) { MCRT_K4X(true, true) }
+    else if (mixed) { MCRT_K4X(true, false) }
+    else if (multi) { MCRT_K4X(false, true) }
+    else { MCRT_K4X(false, false) }
+#undef MCRT_K4X
 #undef MCRT_K4
 }
 

@@ -65,7 +65,7 @@ class SolveParams(ctypes.Structure):
                 ("surface_albedo", ctypes.c_double), ("ms_transmission", _i32), ("ld_law", _i32),
                 ("a_orbit", ctypes.c_double), ("ld_c1", ctypes.c_double), ("ld_c2", ctypes.c_double),
                 ("transit_y", ctypes.c_double), ("transit_z", ctypes.c_double),
-                ("draine_alpha", ctypes.c_double)]
+                ("draine_alpha", ctypes.c_double), ("forced", _i32), ("forced_first", _i32)]
 
 
 class BatchItem(ctypes.Structure):

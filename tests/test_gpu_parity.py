@@ -661,3 +661,60 @@ def test_draine_clouds_parity(ctx, torch_dev):
     assert e.value.name == "EINVAL"
     ctx.free_grid(gid)
     ctx.free_opacity(oid)
+
+
+def test_forced_interactions_parity(ctx, torch_dev):
+    """Forced interactions (probe to the grid's edge, forced optical depth,
+    weight factor, unscattered fraction booked): every packet against the
+    oracle for each scheme on every flight and on the first only (emission
+    sphere with clouds, slab albedo, multiple-scattering transmission),
+    counters included; the mixed form within 1e-3 / 3 sigma; parameter
+    checks."""
+    _log("forced interactions: emission sphere 12x6x8 (kinds 1-3, every / first), slab albedo, ms transmission")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(12, 6, 8, nband=1, ng=2, config_no=100)
+    rng = np.random.default_rng(29)
+    grid.cld_ksca = rng.uniform(0, 2e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 2e-3, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(0.0, 0.8, grid.ncell).astype(np.float32)
+    table.k_ray = table.k_ray * 100.0
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 1200
+    for kind, first in ((1, 0), (2, 0), (3, 0), (1, 1), (3, 1)):
+        dump = dump_buffer(torch_dev, 2, n, 2)
+        kw = dict(n_packets=n, seed=161 + kind, forced=kind, forced_first=first)
+        got = ctx.solve_emission(gid, oid, table, obs_phase=list(phases[:2]), packet_dump=dump, **kw)
+        ref = O.solve_emission(grid, table, O.Params(obs_phase=tuple(phases[:2]), **kw), keep_packets=True)
+        check_packets(dump, ref, (1, 2, n, 2))
+        check_solve(got, ref)
+    R = I.R_SUN
+    kw = dict(n_packets=n, seed=171, forced=3, a_orbit=0.03 * 1.496e13, r_star=R)
+    dump = dump_buffer(torch_dev, 2, n, 1)
+    got = ctx.solve_transmission(gid, oid, table, ms_transmission=1, packet_dump=dump, **kw)
+    ref = O.solve_transmission_ms(grid, table, O.Params(**kw), keep_packets=True)
+    d = dump.cpu().numpy().reshape(2, n)
+    for gi in range(2):
+        v = ref.extra["packets"][(0, gi)][0]
+        assert np.all(np.abs(d[gi] - v) <= RTOL * np.abs(v) + 1e-12 * np.abs(v).max()), gi
+    check_solve(got, ref)
+    mix = ctx.solve_emission(gid, oid, table, obs_phase=list(phases[:2]), precision=M.MCRT_MIXED,
+                             n_packets=4000, seed=173, forced=1)
+    f64 = ctx.solve_emission(gid, oid, table, obs_phase=list(phases[:2]), n_packets=4000, seed=173, forced=1)
+    assert np.all(np.abs(mix["value"] - f64["value"]) <= np.maximum(3.0 * f64["stderr"], 1e-3 * f64["value"]))
+    for bad in (dict(forced=4), dict(forced=1, absorption=M.MCRT_CONTINUOUS), dict(forced=1, surface_albedo=0.3)):
+        with pytest.raises(M.McrtError) as e:
+            ctx.solve_emission(gid, oid, table, n_packets=10, obs_phase=[0.5], **bad)
+        assert e.value.name == "EINVAL"
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+    slab, st = I.make_albedo_slab(nlay=10, nlam=2)
+    sid, soid = ctx.upload_grid(slab), ctx.upload_opacity(st)
+    n = 2000
+    dump = dump_buffer(torch_dev, 2, n, 1)
+    kw = dict(n_packets=n, seed=175, forced=2, forced_first=1)
+    got = ctx.solve_albedo(sid, soid, st, packet_dump=dump, **kw)
+    ref = O.solve_albedo(slab, st, O.Params(**kw), keep_packets=True)
+    check_packets(dump, ref, (2, 1, n, 1))
+    check_solve(got, ref)
+    ctx.free_grid(sid)
+    ctx.free_opacity(soid)
