@@ -910,52 +910,53 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
 // sums rows [chunk*kChunk, (chunk+1)*kChunk) of solve s into
 // partials[s][chunk][2*n_out + kNCounters]; then one block per (s, column)
 // sums the chunks.  Optional copy of F to a packet dump.
+//
+// Thread t of a chunk block owns column t % w of the rows t / w, t / w + R,
+// ... (w the row width, R = 256 / w rows per pass), so each pass of the
+// block reads R whole rows as one contiguous, coalesced range; the R
+// per-thread sums of a column are then added in row-slot order.
 constexpr int kChunk = 4096;
 constexpr int kRT = 256;
 
 __global__ void __launch_bounds__(kRT) k_rows_partial(BatchArgs A, double* __restrict__ partials, int chunks,
                                                       double* __restrict__ dump)
 {
-    __shared__ double sh[kRT];
+    __shared__ double sh[2 * kRT];
     const int s = blockIdx.y;
     const SolveDev S = A.solves[s];
+    const int w = A.row_w;  // n_out peel-off sums + the counters
+    const int R = kRT / w;
+    const int t = threadIdx.x;
+    const int c = t % w, r0 = t / w;
     const unsigned long long q0 = (unsigned long long)blockIdx.x * kChunk;
-    const int pw = 2 * A.n_out + kNCounters;
-    double* out = partials + ((size_t)s * chunks + blockIdx.x) * pw;
-    for (int col = 0; col < A.n_out + kNCounters; ++col) {
-        double acc = 0.0, acc2 = 0.0;
-        for (int t = threadIdx.x; t < kChunk; t += kRT) {
-            unsigned long long q = q0 + (unsigned long long)t;
-            if (q < S.n) {
-                double v = A.rows[(S.begin + q) * (unsigned long long)A.row_w + col];
-                acc = acc + v;
-                acc2 = acc2 + v * v;
-                if (dump && col < A.n_out) dump[(S.begin + q) * (unsigned long long)A.n_out + col] = v;
-            }
+    const unsigned long long qe = q0 + kChunk < S.n ? q0 + kChunk : S.n;
+    const double* rows = A.rows + S.begin * (unsigned long long)w + c;
+    double acc = 0.0, acc2 = 0.0;
+    if (r0 < R) {
+#pragma unroll 4
+        for (unsigned long long q = q0 + r0; q < qe; q += R) {
+            const double v = rows[q * (unsigned long long)w];
+            acc = acc + v;
+            acc2 = acc2 + v * v;
+            if (dump && c < A.n_out) dump[(S.begin + q) * (unsigned long long)A.n_out + c] = v;
         }
-        sh[threadIdx.x] = acc;
-        __syncthreads();
-        for (int st = kRT / 2; st > 0; st >>= 1) {
-            if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
-            __syncthreads();
+    }
+    sh[t] = acc;
+    sh[kRT + t] = acc2;
+    __syncthreads();
+    if (t < w) {
+        double tot = 0.0, tot2 = 0.0;
+        for (int j = 0; j < R; ++j) {
+            tot = tot + sh[t + j * w];
+            tot2 = tot2 + sh[kRT + t + j * w];
         }
-        double tot = sh[0];
-        __syncthreads();
-        if (col < A.n_out) {
-            sh[threadIdx.x] = acc2;
-            __syncthreads();
-            for (int st = kRT / 2; st > 0; st >>= 1) {
-                if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
-                __syncthreads();
-            }
-            double tot2 = sh[0];
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                out[2 * col] = tot;
-                out[2 * col + 1] = tot2;
-            }
-        } else if (threadIdx.x == 0) {
-            out[2 * A.n_out + (col - A.n_out)] = tot;
+        const int pw = 2 * A.n_out + kNCounters;
+        double* out = partials + ((size_t)s * chunks + blockIdx.x) * pw;
+        if (t < A.n_out) {
+            out[2 * t] = tot;
+            out[2 * t + 1] = tot2;
+        } else {
+            out[2 * A.n_out + (t - A.n_out)] = tot;
         }
     }
 }
