@@ -27,8 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "packets/s at 1e-3 rel. spectral error, plain vs batched; p50/p99 solve latency"
 # FP64 operations the traversal performs per cell crossing on the spherical
-# grid (exit distances to 2 shells, 2 latitude cones, 2 longitude half-planes,
-# the move and the optical-depth update); see the design doc for the breakdown.
+# grid: r.r and p.d (10); outer shell C, D, sqrt, root (7); inner shell on
+# inward rays (3.5 on average); the entry-face tolerance (2); two latitude
+# cones, each a, b, c, discriminant, sqrt, two roots and the nappe checks
+# (2 x 33); two longitude half-planes when approached (15); the move (6);
+# the optical-depth update (2).
 FLOP_PER_CROSSING = 110.0
 PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X
 PEAK_HBM = 8000.0  # GB/s
@@ -36,11 +39,11 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "db914ba0580ae7ff284760697ed0294615094b5b07326239a2d210434e2d923a"
-TRAFFIC_BYTES_PER_SOLVE = (126606277 * (1048576 / 524305) + 24204059 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "b28b249277ddfb5ef792946711fa21dd6a4c187f1db0f989e1473dd7f8458371"
+TRAFFIC_BYTES_PER_SOLVE = (136656004 * (1048576 / 524308) + 24069922 * 1.0) * 1024 / 168
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
-VALU_BUSY = 0.914
+VALU_BUSY = 0.910
 
 
 def parse():
@@ -255,8 +258,8 @@ def summarize(res, wall, steps, pk_step, npk, ng):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path shards by whole "
-              "(band, g) solves, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path would shard by whole "
+              "(band, g) solves across GPUs, each GPU holding the grid and table", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2110_15640_amd import inputs as I
