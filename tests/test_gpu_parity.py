@@ -718,3 +718,31 @@ def test_forced_interactions_parity(ctx, torch_dev):
     check_solve(got, ref)
     ctx.free_grid(sid)
     ctx.free_opacity(soid)
+
+
+def test_maximum_index_grids(ctx, torch_dev):
+    """Grids at the index limits of the packed lane state: 2048 longitudes x
+    1024 latitudes (4.2e6 cells) and 2048 layers; every packet against the
+    oracle for emission and albedo; one longitude, latitude or layer more is
+    rejected."""
+    _log("maximum index grids: 2048x1024x2 and 1x1x2048, emission + albedo, every packet")
+    from paper_2110_15640_amd import mcrt as M
+    _, table, _ = I.make_emission_3d(8, 4, 2, nband=2, ng=1, config_no=110)
+    oid = ctx.upload_opacity(table)
+    n = 400
+    for grid, seed in ((I.make_sphere(2048, 1024, 2, seed=111), 181), (I.make_sphere(1, 1, 2048, seed=113), 185)):
+        gid = ctx.upload_grid(grid)
+        dump = dump_buffer(torch_dev, 2, n, 2)
+        got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=seed, obs_phase=[0.5, 0.0], packet_dump=dump)
+        ref = O.solve_emission(grid, table, O.Params(n_packets=n, seed=seed, obs_phase=(0.5, 0.0)), keep_packets=True)
+        check_packets(dump, ref, (2, 1, n, 2))
+        check_solve(got, ref)
+        alb = ctx.solve_albedo(gid, oid, table, n_packets=n, seed=seed + 1, obs_phase=[0.0, 1.0])
+        aref = O.solve_albedo(grid, table, O.Params(n_packets=n, seed=seed + 1, obs_phase=(0.0, 1.0)))
+        check_solve(alb, aref)
+        ctx.free_grid(gid)
+    for shape in ((2049, 4, 2), (8, 1025, 2), (1, 1, 2049)):
+        with pytest.raises(M.McrtError) as e:
+            ctx.upload_grid(I.make_sphere(*shape, seed=115))
+        assert e.value.name == "EINVAL", shape
+    ctx.free_opacity(oid)
