@@ -87,9 +87,17 @@ uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx);
  * optional winds u (east), v (north), w (up) [cm/s] float (NULL = 0) and
  * optional grey cloud opacities cld_ksca, cld_kabs [cm^2/g] and asymmetry
  * cld_g float (NULL = no cloud).  omega_rot: solid-body rotation [1/s].
+ * flags: MCRT_BORROW_DEVICE = the per-cell arrays (T, P, rho, winds,
+ * clouds) are DEVICE pointers on the context's device (e.g. torch tensors'
+ * data_ptr()) that the library reads in place: nothing is copied or counted
+ * against the budget, and the caller keeps them alive and unchanged until
+ * mcrt_grid_free; the edge arrays stay host memory.  Their values are checked
+ * on the device at upload.
  * Errors: EINVAL for non-monotone or incomplete edges, non-finite values,
- * T <= 0, P <= 0, rho < 0, |g| >= 1; EBUDGET if the copy would exceed the
- * budget (nothing is allocated then). */
+ * T <= 0, P <= 0, rho < 0, |g| >= 1, or a borrowed pointer that is not
+ * device memory of this device; EBUDGET if the copy would exceed the budget
+ * (nothing is allocated then). */
+#define MCRT_BORROW_DEVICE 1
 typedef struct {
     int32_t geometry;
     int32_t nlon, nlat, nlay;
@@ -106,6 +114,7 @@ typedef struct {
     const float* cld_kabs;
     const float* cld_g;
     double omega_rot;
+    int32_t flags;
 } mcrt_grid_desc;
 
 int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* desc, int32_t* grid_id);

@@ -21,6 +21,15 @@
 #include "../../include/mcrt.h"
 #include "mcrt_internal.hpp"
 
+namespace mcrt {
+// Checks of borrowed per-cell arrays on the device (kernels.hip): bit 0 T,
+// 1 P, 2 rho, 3 winds, 4 cloud opacities, 5 cloud g set in *bad where a cell
+// fails.
+void launch_check_cells(const float* T, const float* P, const double* rho, const float* u, const float* v,
+                        const float* w, const float* cs, const float* ca, const float* cg, size_t n, int* bad,
+                        hipStream_t stream);
+}  // namespace mcrt
+
 using namespace mcrt;
 
 namespace {
@@ -289,6 +298,12 @@ int validate_grid(const mcrt_grid_desc* d)
             std::fabs(d->lon_edges[0] + kPi) > 1e-12 || std::fabs(d->lon_edges[d->nlon] - kPi) > 1e-12)
             return fail(MCRT_EINVAL, "lon_edges must increase from -pi to pi");
     }
+    if (d->flags & ~MCRT_BORROW_DEVICE) return fail(MCRT_EINVAL, "unknown grid flags");
+    if (d->cld_ksca || d->cld_kabs || d->cld_g)
+        if (!(d->cld_ksca && d->cld_kabs && d->cld_g))
+            return fail(MCRT_EINVAL, "cloud needs cld_ksca, cld_kabs and cld_g together");
+    if (!std::isfinite(d->omega_rot)) return fail(MCRT_EINVAL, "omega_rot must be finite");
+    if (d->flags & MCRT_BORROW_DEVICE) return MCRT_OK;  // per-cell values are checked on the device
     size_t n = (size_t)d->nlon * d->nlat * d->nlay;
     for (size_t c = 0; c < n; ++c) {
         if (!(std::isfinite(d->T[c]) && d->T[c] > 0.0f)) return fail(MCRT_EINVAL, "T[%zu] must be finite and > 0", c);
@@ -298,9 +313,7 @@ int validate_grid(const mcrt_grid_desc* d)
     const float* wind[3] = {d->u, d->v, d->w};
     for (int q = 0; q < 3; ++q)
         if (wind[q] && !finite_all(wind[q], n)) return fail(MCRT_EINVAL, "winds must be finite");
-    if (d->cld_ksca || d->cld_kabs || d->cld_g) {
-        if (!(d->cld_ksca && d->cld_kabs && d->cld_g))
-            return fail(MCRT_EINVAL, "cloud needs cld_ksca, cld_kabs and cld_g together");
+    if (d->cld_ksca) {
         for (size_t c = 0; c < n; ++c) {
             if (!(std::isfinite(d->cld_ksca[c]) && d->cld_ksca[c] >= 0.0f && std::isfinite(d->cld_kabs[c]) &&
                   d->cld_kabs[c] >= 0.0f))
@@ -308,7 +321,40 @@ int validate_grid(const mcrt_grid_desc* d)
             if (!(std::fabs(d->cld_g[c]) < 1.0f)) return fail(MCRT_EINVAL, "cloud g must satisfy |g| < 1");
         }
     }
-    if (!std::isfinite(d->omega_rot)) return fail(MCRT_EINVAL, "omega_rot must be finite");
+    return MCRT_OK;
+}
+
+// Borrowed per-cell arrays: device memory of the context's device, whose
+// values pass the same checks as a host grid's (run on the device).
+int check_borrowed(mcrt_ctx* ctx, const mcrt_grid_desc* d, size_t n)
+{
+    const void* ptrs[9] = {d->T, d->P, d->rho, d->u, d->v, d->w, d->cld_ksca, d->cld_kabs, d->cld_g};
+    for (const void* p : ptrs) {
+        if (!p) continue;
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice ||
+            at.device != ctx->device) {
+            (void)hipGetLastError();
+            return fail(MCRT_EINVAL, "borrowed grid arrays must be device memory of device %d", ctx->device);
+        }
+    }
+    int* bad = nullptr;
+    HIPTRY(hipMalloc(&bad, sizeof(int)));
+    int h = 0;
+    hipError_t e = hipMemcpy(bad, &h, sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        launch_check_cells(d->T, d->P, d->rho, d->u, d->v, d->w, d->cld_ksca, d->cld_kabs, d->cld_g, n, bad, nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(&h, bad, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(bad);
+    HIPTRY(e);
+    if (h & 1) return fail(MCRT_EINVAL, "T must be finite and > 0");
+    if (h & 2) return fail(MCRT_EINVAL, "P must be finite and > 0");
+    if (h & 4) return fail(MCRT_EINVAL, "rho must be finite and >= 0");
+    if (h & 8) return fail(MCRT_EINVAL, "winds must be finite");
+    if (h & 16) return fail(MCRT_EINVAL, "cloud opacities must be finite and >= 0");
+    if (h & 32) return fail(MCRT_EINVAL, "cloud g must satisfy |g| < 1");
     return MCRT_OK;
 }
 
@@ -1730,6 +1776,8 @@ int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, int32_t* grid_id)
     const bool slab = d->geometry == MCRT_PLANE_PARALLEL;
     const int nlon = d->nlon, nlat = d->nlat, nlay = d->nlay;
     const size_t n = (size_t)nlon * nlat * nlay;
+    const bool borrow = (d->flags & MCRT_BORROW_DEVICE) != 0;
+    if (borrow && (rc = check_borrowed(ctx, d, n))) return rc;
     // host-side edge tables
     std::vector<double> lat(nlat + 1), lon(nlon + 1);
     if (slab) {
@@ -1782,16 +1830,28 @@ int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, int32_t* grid_id)
     UP(lon_s, los.data(), los.size(), dp);
     UP(lon_c, loc.data(), loc.size(), dp);
     UP(vol_r, volr.data(), volr.size(), dp);
-    UP(T, d->T, n, fp);
-    UP(P, d->P, n, fp);
-    UP(rho, d->rho, n, dp);
-    if (d->u) UP(u, d->u, n, fp);
-    if (d->v) UP(v, d->v, n, fp);
-    if (d->w) UP(w, d->w, n, fp);
-    if (d->cld_ksca) {
-        UP(cld_ksca, d->cld_ksca, n, fp);
-        UP(cld_kabs, d->cld_kabs, n, fp);
-        UP(cld_g, d->cld_g, n, fp);
+    if (borrow) {  // read in place; the caller owns them
+        gd.T = d->T;
+        gd.P = d->P;
+        gd.rho = d->rho;
+        gd.u = d->u;
+        gd.v = d->v;
+        gd.w = d->w;
+        gd.cld_ksca = d->cld_ksca;
+        gd.cld_kabs = d->cld_kabs;
+        gd.cld_g = d->cld_g;
+    } else {
+        UP(T, d->T, n, fp);
+        UP(P, d->P, n, fp);
+        UP(rho, d->rho, n, dp);
+        if (d->u) UP(u, d->u, n, fp);
+        if (d->v) UP(v, d->v, n, fp);
+        if (d->w) UP(w, d->w, n, fp);
+        if (d->cld_ksca) {
+            UP(cld_ksca, d->cld_ksca, n, fp);
+            UP(cld_kabs, d->cld_kabs, n, fp);
+            UP(cld_g, d->cld_g, n, fp);
+        }
     }
 #undef UP
     G->ncell = (int)n;

@@ -19,6 +19,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "mcrt_internal.hpp"
 
@@ -147,6 +149,27 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) out[col] = sh[0] + shc[0];
+}
+
+// ------------------------------------------------- borrowed grid checks
+// The validation of host grids, done where borrowed device arrays live:
+// every cell sets the bits of the checks it fails (atomic OR on one word).
+__global__ void __launch_bounds__(256) k_check_cells(const float* __restrict__ T, const float* __restrict__ P,
+                                                     const double* __restrict__ rho, const float* __restrict__ u,
+                                                     const float* __restrict__ v, const float* __restrict__ w,
+                                                     const float* __restrict__ cs, const float* __restrict__ ca,
+                                                     const float* __restrict__ cg, size_t n, int* __restrict__ bad)
+{
+    int f = 0;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (size_t)gridDim.x * 256) {
+        if (!(isfinite(T[c]) && T[c] > 0.0f)) f |= 1;
+        if (!(isfinite(P[c]) && P[c] > 0.0f)) f |= 2;
+        if (!(isfinite(rho[c]) && rho[c] >= 0.0)) f |= 4;
+        if ((u && !isfinite(u[c])) || (v && !isfinite(v[c])) || (w && !isfinite(w[c]))) f |= 8;
+        if (cs && !(isfinite(cs[c]) && cs[c] >= 0.0f && isfinite(ca[c]) && ca[c] >= 0.0f)) f |= 16;
+        if (cg && !(fabsf(cg[c]) < 1.0f)) f |= 32;
+    }
+    if (f) atomicOr(bad, f);
 }
 
 // ---------------------------------------------------------------- K5 chords
@@ -332,6 +355,14 @@ void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_reduce_rows, dim3(width), dim3(256), 0, stream, partials, nblocks, width, out);
+}
+
+void launch_check_cells(const float* T, const float* P, const double* rho, const float* u, const float* v,
+                        const float* w, const float* cs, const float* ca, const float* cg, size_t n, int* bad,
+                        hipStream_t stream)
+{
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_cells, dim3(blocks), dim3(256), 0, stream, T, P, rho, u, v, w, cs, ca, cg, n, bad);
 }
 
 void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag, int* counts,

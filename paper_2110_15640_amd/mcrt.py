@@ -42,7 +42,11 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("geometry", _i32), ("nlon", _i32), ("nlat", _i32), ("nlay", _i32),
                 ("r_edges", _vp), ("lat_edges", _vp), ("lon_edges", _vp),
                 ("T", _vp), ("P", _vp), ("rho", _vp), ("u", _vp), ("v", _vp), ("w", _vp),
-                ("cld_ksca", _vp), ("cld_kabs", _vp), ("cld_g", _vp), ("omega_rot", _dbl)]
+                ("cld_ksca", _vp), ("cld_kabs", _vp), ("cld_g", _vp), ("omega_rot", _dbl),
+                ("flags", _i32)]
+
+
+MCRT_BORROW_DEVICE = 1
 
 
 class OpacityDesc(ctypes.Structure):
@@ -147,13 +151,16 @@ class Context:
         h = _vp()
         _check(L.mcrt_create(device, hbm_budget_bytes, ctypes.byref(h)))
         self._h = h
+        self.device = device
         self._keep = []
         self._ncell = {}
+        self._borrowed = {}  # grid id -> device tensors the library reads in place
 
     def close(self):
         if getattr(self, "_h", None):
             load().mcrt_destroy(self._h)
             self._h = None
+        self._borrowed = {}
 
     def __del__(self):
         try:
@@ -172,21 +179,39 @@ class Context:
         return int(load().mcrt_memory_in_use(self._h))
 
     # ---------------------------------------------------------- uploads
-    def upload_grid(self, g) -> int:
-        """g: paper_2110_15640_amd.inputs.Grid (host numpy arrays)."""
+    def upload_grid(self, g, borrow: bool = False) -> int:
+        """g: paper_2110_15640_amd.inputs.Grid (host numpy arrays).  borrow:
+        the per-cell arrays are first placed in torch device tensors, which
+        the library reads in place (MCRT_BORROW_DEVICE); this context keeps
+        them alive until free_grid."""
         arrs = dict(r=_arr(g.r_edges, np.float64), lat=_arr(g.lat_edges, np.float64),
                     lon=_arr(g.lon_edges, np.float64), T=_arr(g.T, np.float32),
                     P=_arr(g.P, np.float32), rho=_arr(g.rho, np.float64),
                     u=_arr(g.u, np.float32), v=_arr(g.v, np.float32), w=_arr(g.w, np.float32),
                     cs=_arr(g.cld_ksca, np.float32), ca=_arr(g.cld_kabs, np.float32),
                     cg=_arr(g.cld_g, np.float32))
+        cell = dict(arrs)
+        held = None
+        if borrow:
+            import torch
+            dev = torch.device("cuda", self.device)
+            held = {k: torch.from_numpy(v).to(dev) for k, v in arrs.items()
+                    if v is not None and k not in ("r", "lat", "lon")}
+            torch.cuda.synchronize(dev)
+            cell.update(held)
+
+        def ptr(k):
+            v = cell[k]
+            return None if v is None else (v.data_ptr() if hasattr(v, "data_ptr") else _ptr(v))
+
         d = GridDesc(g.geometry, g.nlon, g.nlat, g.nlay, _ptr(arrs["r"]), _ptr(arrs["lat"]),
-                     _ptr(arrs["lon"]), _ptr(arrs["T"]), _ptr(arrs["P"]), _ptr(arrs["rho"]),
-                     _ptr(arrs["u"]), _ptr(arrs["v"]), _ptr(arrs["w"]), _ptr(arrs["cs"]),
-                     _ptr(arrs["ca"]), _ptr(arrs["cg"]), float(g.omega_rot))
+                     _ptr(arrs["lon"]), ptr("T"), ptr("P"), ptr("rho"), ptr("u"), ptr("v"), ptr("w"),
+                     ptr("cs"), ptr("ca"), ptr("cg"), float(g.omega_rot), MCRT_BORROW_DEVICE if borrow else 0)
         gid = _i32()
         _check(load().mcrt_grid_upload(self._h, ctypes.byref(d), ctypes.byref(gid)))
         self._ncell[gid.value] = g.nlon * g.nlat * g.nlay
+        if held is not None:
+            self._borrowed[gid.value] = held
         return gid.value
 
     def upload_opacity(self, t) -> int:
@@ -207,6 +232,7 @@ class Context:
 
     def free_grid(self, gid: int):
         _check(load().mcrt_grid_free(self._h, gid))
+        self._borrowed.pop(gid, None)
 
     def free_opacity(self, oid: int):
         _check(load().mcrt_opacity_free(self._h, oid))

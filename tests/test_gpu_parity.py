@@ -746,3 +746,50 @@ def test_maximum_index_grids(ctx, torch_dev):
             ctx.upload_grid(I.make_sphere(*shape, seed=115))
         assert e.value.name == "EINVAL", shape
     ctx.free_opacity(oid)
+
+
+def test_borrowed_device_grid(ctx, torch_dev):
+    """A grid whose per-cell arrays are borrowed device tensors (read in
+    place, not counted in the library's memory): bit-identical results to the
+    copied grid for emission with clouds and raytrace transmission; borrowed
+    host pointers and bad device values are rejected."""
+    _log("borrowed device grid: emission + transmission vs copied grid; error checks")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2, config_no=120)
+    rng = np.random.default_rng(31)
+    grid.cld_ksca = rng.uniform(0, 3e-2, grid.ncell).astype(np.float32)
+    grid.cld_kabs = rng.uniform(0, 3e-3, grid.ncell).astype(np.float32)
+    grid.cld_g = rng.uniform(-0.2, 0.8, grid.ncell).astype(np.float32)
+    oid = ctx.upload_opacity(table)
+    gid = ctx.upload_grid(grid)
+    used = ctx.memory_in_use
+    bid = ctx.upload_grid(grid, borrow=True)
+    per_cell = grid.ncell * (4 + 4 + 8 + 3 * 4)
+    assert ctx.memory_in_use - used < per_cell  # only the edge tables were allocated
+    kw = dict(n_packets=3000, seed=191, obs_phase=list(phases[:2]))
+    a = ctx.solve_emission(gid, oid, table, **kw)
+    b = ctx.solve_emission(bid, oid, table, **kw)
+    assert np.array_equal(a["sums"], b["sums"]) and np.array_equal(a["counters"], b["counters"])
+    kt = dict(n_b=16, n_alpha=24, seed=193, r_star=I.R_SUN)
+    assert np.array_equal(ctx.solve_transmission(gid, oid, table, **kt)["sums"],
+                          ctx.solve_transmission(bid, oid, table, **kt)["sums"])
+    ctx.free_grid(bid)
+    ctx.free_grid(gid)
+    # a host pointer passed as borrowed
+    T = np.ascontiguousarray(grid.T, dtype=np.float32)
+    rho = np.ascontiguousarray(grid.rho, dtype=np.float64)
+    r, lat, lon = (np.ascontiguousarray(x, dtype=np.float64) for x in (grid.r_edges, grid.lat_edges, grid.lon_edges))
+    d = M.GridDesc(0, grid.nlon, grid.nlat, grid.nlay, r.ctypes.data, lat.ctypes.data, lon.ctypes.data,
+                   T.ctypes.data, T.ctypes.data, rho.ctypes.data, None, None, None, None, None, None, 0.0,
+                   M.MCRT_BORROW_DEVICE)
+    import ctypes
+    out = ctypes.c_int32()
+    assert M.load().mcrt_grid_upload(ctx._h, ctypes.byref(d), ctypes.byref(out)) == -1
+    # bad values in borrowed device memory: found by the device check
+    bad = I.make_sphere(8, 4, 3, seed=5)
+    bad.rho = bad.rho.copy()
+    bad.rho[7] = np.nan
+    with pytest.raises(M.McrtError) as e:
+        ctx.upload_grid(bad, borrow=True)
+    assert e.value.name == "EINVAL"
+    ctx.free_opacity(oid)
