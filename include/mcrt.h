@@ -126,8 +126,10 @@ int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id);
  * g_weights[ng] (sum 1).  kind = MCRT_OPAC_HIRES: kappa[nspec][nT][nP] on
  * the log-uniform grid lam_n = lam_min_um exp(n dlnlam), ng = 1.  k_ray
  * [nspec]: Rayleigh opacity [cm^2/g] at each spectral point.  Host arrays,
- * copied.  Errors: EINVAL for kappa < 0 or non-finite, a non-increasing
- * T/P grid, P_grid <= 0, weights not summing to 1 within 1e-9. */
+ * copied.  Errors: EINVAL for kappa < 0 or non-finite, a ck kappa that
+ * decreases from one g-ordinate to the next at some (band, T, P) (a
+ * k-distribution is sorted), a non-increasing T/P grid, P_grid <= 0,
+ * weights not summing to 1 within 1e-9. */
 typedef struct {
     int32_t kind;
     int32_t nspec;

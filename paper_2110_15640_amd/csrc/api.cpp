@@ -383,6 +383,15 @@ int validate_opacity(const mcrt_opacity_desc* d)
             ws += d->g_weights[g];
         }
         if (std::fabs(ws - 1.0) > 1e-9) return fail(MCRT_EINVAL, "g_weights must sum to 1 (got %.12g)", ws);
+        // a k-distribution is sorted: kappa non-decreasing in g at every (band, T, P)
+        const size_t tp = (size_t)d->nT * d->nP;
+        for (int s = 0; s < d->nspec; ++s)
+            for (int g = 0; g + 1 < d->ng; ++g) {
+                const float* a = d->kappa + ((size_t)s * d->ng + g) * tp;
+                for (size_t q = 0; q < tp; ++q)
+                    if (!(a[q] <= a[q + tp]))
+                        return fail(MCRT_EINVAL, "ck kappa must be non-decreasing in g (band %d, g %d)", s, g);
+            }
         for (int s = 0; s < d->nspec; ++s)
             if (!(d->lam_um[s] > 0.0 && std::isfinite(d->lam_um[s]))) return fail(MCRT_EINVAL, "lam_um must be > 0");
     } else {

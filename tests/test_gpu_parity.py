@@ -242,6 +242,12 @@ def test_edge_cases(ctx, torch_dev):
     with pytest.raises(M.McrtError) as e:
         ctx.upload_opacity(bad_t)
     assert e.value.name == "EINVAL"
+    _, t2, _ = I.make_emission_3d(4, 2, 2, nband=2, ng=4, config_no=5)
+    unsorted = t2.kappa.copy()
+    unsorted[1, 2, 3, 4] = unsorted[1, 3, 3, 4] * 1.5  # g = 2 above g = 3 at one (T, P)
+    with pytest.raises(M.McrtError) as e:
+        ctx.upload_opacity(I.CKTable(t2.lam_um, t2.g_weights, t2.T_grid, t2.P_grid, unsorted, t2.k_ray))
+    assert e.value.name == "EINVAL"
     with pytest.raises(M.McrtError) as e:
         M.Context(0, hbm_budget_bytes=1024).upload_grid(grid)
     assert e.value.name == "EBUDGET"
