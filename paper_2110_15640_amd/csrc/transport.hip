@@ -282,14 +282,14 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     const bool lost = flight && f == F_NONE && !(a > 0.0);
     const bool hit = flight && !lost && a > 0.0 && L.tau < a * s;
     const bool pend = !flight && f == F_NONE;
-    const double ds = hit ? L.tau / a : s;
-    // the interaction point, from the walker before it moves
-    const double ti = L.w.t + ds;
-    const double ex = L.w.px + ti * L.w.dx, ey = L.w.py + ti * L.w.dy, ez = L.w.pz + ti * L.w.dz;
+    // the walk's parameter and cell before the crossing (the walker keeps its
+    // origin and direction, so the interaction point follows from them)
+    const double t0 = L.w.t;
     const int ei = L.w.i, ej = L.w.j, ek = L.w.k;
     if (flight) {
         if (!lost && !hit) L.tau = L.tau - a * s;
         if (cont && !lost) {
+            const double ds = hit ? L.tau / a : s;
             double wn = L.W * exp(-aa * ds);
             L.w_abs = L.w_abs + (L.W - wn);
             L.W = wn;
@@ -301,10 +301,11 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     if (lost || hit || pend) {
         L.ncross += L.ncw;
         L.mode = M_EVENT;
-        if (hit) {
-            L.sx() = ex;
-            L.sy() = ey;
-            L.sz() = ez;
+        if (hit) {  // at t0 + tau / a (tau is still the depth left on entering the cell)
+            const double ti = t0 + L.tau / a;
+            L.sx() = L.w.px + ti * L.w.dx;
+            L.sy() = L.w.py + ti * L.w.dy;
+            L.sz() = L.w.pz + ti * L.w.dz;
             L.set_cell(ei, ej, ek);
             L.set_sef(F_NONE);
         }
