@@ -678,9 +678,12 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
     const double sq = sqrt(fmax(D, 0.0));
     const bool neg = cone ? B >= 0.0 : B > 0.0;  // the sign rule of each kind at B = 0
     const double q = neg ? -(B + sq) : (-B + sq);
-    const double x0q = q / (quad ? A : 1.0);
+    // one division gives the near root q / A of a quadric (a shell has A = 1)
+    // or the root -C / B2 of a linear face, whichever the lane has
+    const double rd = (quad ? q : -C) / (quad ? A : B2);
+    const double x0q = rd;
     const double x1q = (quad && q != 0.0) ? C / q : INFINITY;
-    const double xl = (!quad && B2 != 0.0) ? -C / B2 : INFINITY;
+    const double xl = (!quad && B2 != 0.0) ? rd : INFINITY;
     if (shell) {
         if (slab) {
             const double x = fmax(-C / B2, w.t);  // (R - pz) / dz
@@ -714,7 +717,7 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
             } else {
                 double x0 = INFINITY, x1 = INFINITY;
                 if (!quad) {
-                    x0 = B != 0.0 ? -C / B2 : INFINITY;
+                    x0 = B != 0.0 ? rd : INFINITY;
                 } else if (D >= 0.0) {
                     x0 = x0q;
                     x1 = x1q;
