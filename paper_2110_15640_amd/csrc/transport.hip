@@ -633,14 +633,11 @@ __device__ __forceinline__ int solve_of(const BatchArgs& A, unsigned long long g
 // the slab's incidence; emission: cell from the biased CDF, uniform position in
 // its volume, isotropic direction, weight (L_i/L_tot)/q_i), one thread each.
 template <bool MULTI>
-__global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
+__device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs& A, unsigned long long gid, double* b)
 {
-    const unsigned long long gid = (unsigned long long)blockIdx.x * 256 + threadIdx.x;
-    if (gid >= A.total) return;
     int sv = solve_of(A, gid);
     const GridDev& g = MULTI ? A.grids[A.solves[sv].grid] : g1;
     const double r_toa = g.r[g.nlay];
-    double* b = A.rows + gid * (unsigned long long)A.row_w + A.n_out;
     const unsigned long long q = gid - A.solves[sv].pbase;
     const uint32_t tag = A.solves[sv].tag;
     double wmul = 1.0;
@@ -767,6 +764,28 @@ __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
     b[B_DZ] = mu;
     b[B_W] = S.wbirth[c] * wmul;
     b[B_CELL] = (double)c * 8.0 + (double)(F_NONE + 1);
+}
+
+// The records of a block's packets are built in LDS and its rows written
+// as one contiguous range (peel-off columns as zeros): coalesced stores of
+// whole lines instead of 72 B pieces of 120 B rows.
+constexpr int kMaxRowW = kMaxObs + kNCounters;
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
+{
+    __shared__ double sh[256 * kMaxRowW];
+    const int w = A.row_w;
+    const unsigned long long r0 = (unsigned long long)blockIdx.x * 256;
+    double* mine = sh + threadIdx.x * w;
+    for (int c = 0; c < w; ++c) mine[c] = 0.0;
+    const unsigned long long gid = r0 + threadIdx.x;
+    if (gid < A.total) birth_record<MULTI>(g1, A, gid, mine + A.n_out);
+    __syncthreads();
+    const unsigned long long left = A.total - r0;
+    const int n = (int)(left < 256 ? left : 256) * w;
+    double* dst = A.rows + r0 * (unsigned long long)w;
+    for (int x = threadIdx.x; x < n; x += 256) dst[x] = sh[x];
 }
 
 // New packet L.gid: load its birth record and return the first action (a
