@@ -39,11 +39,11 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "b28b249277ddfb5ef792946711fa21dd6a4c187f1db0f989e1473dd7f8458371"
-TRAFFIC_BYTES_PER_SOLVE = (136656004 * (1048576 / 524308) + 24069922 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "b8440a84d058e57873845ec5a646b28c2472ac308ab6d452696cc2623ba279bc"
+TRAFFIC_BYTES_PER_SOLVE = (149342580 * (1048576 / 524305) + 24011093 * 1.0) * 1024 / 168
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
-VALU_BUSY = 0.910
+VALU_BUSY = 0.894
 
 
 def parse():
