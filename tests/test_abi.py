@@ -58,3 +58,43 @@ def test_default_params_and_error_string_need_no_device():
     assert p.rr_threshold == 1e-3 and p.rr_survive == 0.1 and p.emis_bias == 0.5
     assert p.tau_vert_max == 30.0 and p.max_events == 1000000 and p.n_b == 256 and p.n_alpha == 360
     assert isinstance(M.load().mcrt_last_error(), bytes)
+
+
+def _c_layout(structs):
+    """sizeof and offsetof of every field, from the header compiled by gcc."""
+    import shutil
+    import subprocess
+    import tempfile
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcrt.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.check_call([gcc, "-I", os.path.dirname(HEADER), "-o", exe, src])
+        out = subprocess.check_output([exe]).decode()
+    res = {}
+    for ln in out.splitlines():
+        a, b, c = ln.split()
+        res[(a, b)] = int(c)
+    return res
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcrt.so not built")
+def test_binding_struct_offsets_and_sizes_match_the_c_compiler():
+    """Beyond the field names: every ctypes offset and struct size equals what
+    a C compiler makes of the header, so no field has a mismatched type."""
+    from paper_2110_15640_amd import mcrt as M
+    pairs = [("mcrt_grid_desc", M.GridDesc), ("mcrt_opacity_desc", M.OpacityDesc),
+             ("mcrt_solve_params", M.SolveParams), ("mcrt_result", M.Result), ("mcrt_batch_item", M.BatchItem)]
+    lay = _c_layout([(c, [f[0] for f in py._fields_]) for c, py in pairs])
+    for cname, py in pairs:
+        assert lay[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert lay[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
