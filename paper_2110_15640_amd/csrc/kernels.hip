@@ -296,9 +296,24 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
             if (ch >= nch) break;
             long long o0 = offsets[ch], o1 = offsets[ch + 1];
             double tau = 0.0;
-            if (s < nslot) {
-                for (long long o = o0; o < o1; ++o)
-                    tau = tau + alpha[(size_t)seg_cell[o] * nslot + s] * seg_len[o];
+            // the chord's segments in chunks of 64: each lane loads one (cell,
+            // length) pair (coalesced), then the wave walks the chunk in
+            // segment order taking them from the lanes, so the row gathers of
+            // consecutive segments do not wait on one another's index loads
+            for (long long c0 = o0; c0 < o1; c0 += 64) {
+                const int nseg = (int)(o1 - c0 < 64 ? o1 - c0 : 64);
+                uint32_t mc = 0;
+                double ml = 0.0;
+                if (lane < nseg) {
+                    mc = seg_cell[c0 + lane];
+                    ml = seg_len[c0 + lane];
+                }
+#pragma unroll 8
+                for (int k = 0; k < nseg; ++k) {
+                    const uint32_t cell = (uint32_t)__shfl((int)mc, k);
+                    const double len = __shfl(ml, k);
+                    if (s < nslot) tau = tau + alpha[(size_t)cell * nslot + s] * len;
+                }
             }
             if (!chord_ok[ch]) tau = INFINITY;
             double v = (1.0 - exp(-tau)) * chord_b[ch];
