@@ -1077,9 +1077,11 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     int tblocks = chord_tau_blocks(nch);
     if ((rc = scratch(ctx, sl, st, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
     if ((rc = scratch(ctx, sl, st, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
+    void* v_tp = nullptr;
     if (op->kind == MCRT_OPAC_HIRES) {
         if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
         if ((rc = scratch(ctx, sl, st, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
+        if ((rc = scratch(ctx, sl, st, "cell_tp", sizeof(CellTP) * (size_t)ncell, &v_tp))) return rc;
     }
     const uint32_t tag = 0;  // chords are common to all spectral points
     const bool prof = p->profile != 0;
@@ -1102,6 +1104,7 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
                       (double*)v_b, (int*)v_ok, ld, st);
     if (op->kind == MCRT_OPAC_HIRES) {
         launch_doppler_shift(g->dev, -1.0, 0.0, 0.0, op->dlnlam, (double*)v_shift, st);
+        launch_cell_tp(g->dev, ncell, op->nT, op->nP, op->T_grid, op->lnP_grid, (CellTP*)v_tp, st);
         HIPTRY(hipMemcpyAsync(v_nl, pl.specs.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
     }
     double* alpha = (double*)v_alpha;
@@ -1116,8 +1119,8 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
                                  st);
             }
         } else {
-            launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nT, op->nP, op->T_grid, op->lnP_grid,
-                                     op->k_ray_dev, (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
+            launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nP, (const CellTP*)v_tp, op->k_ray_dev,
+                                     (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
         if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st));
         launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok, alpha,
@@ -1469,7 +1472,7 @@ uint64_t estimate_bytes(mcrt_ctx* ctx, const Request& r, GridRes* g, OpacRes* op
         const uint64_t tblocks = (uint64_t)chord_tau_blocks((int)nch);
         const uint64_t segs = nch * (2ULL * g->dev.nlay + 2ULL * g->dev.nlat + g->dev.nlon + 8ULL);
         return nch * (4 + 8 + 8 + 4) + 8 + ncell * nslot * 8 + tblocks * 2 * nslot * 8 + nrow * 16 + ncell * 8 +
-               nrow * 4 + segs * 12 + (1ULL << 20);
+               ncell * sizeof(CellTP) + nrow * 4 + segs * 12 + (1ULL << 20);
     }
     const bool mixed = r.p.precision == MCRT_MIXED;
     const uint64_t N = r.p.n_packets;

@@ -97,10 +97,19 @@ __device__ __forceinline__ double hires_kappa(const double* __restrict__ lnk_tpl
 // alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
 // Threads run slot-fastest so a wave reads consecutive wavelengths of the
 // [T][P][lambda] table and writes a contiguous row.
+__global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, int nP,
+                                                 const double* __restrict__ T_grid,
+                                                 const double* __restrict__ lnP_grid, CellTP* __restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
+    const Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
+    out[c] = CellTP{bt.i0, bt.i1, bp.i0, bp.i1, bt.t, bp.t};
+}
+
 __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
-                                                           int nlam, int nT, int nP,
-                                                           const double* __restrict__ T_grid,
-                                                           const double* __restrict__ lnP_grid,
+                                                           int nlam, int nP, const CellTP* __restrict__ tp,
                                                            const double* __restrict__ k_ray,
                                                            const double* __restrict__ shift,
                                                            const int* __restrict__ nlist, int nslot,
@@ -110,8 +119,10 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
     if (t >= (long long)ncell * nslot) return;
     int c = (int)(t / nslot), s = (int)(t % nslot);
     int n = nlist[s];
-    Bracket bt = bracket(T_grid, nT, (double)g.T[c]);
-    Bracket bp = bracket(lnP_grid, nP, log((double)g.P[c]));
+    const CellTP q = tp[c];
+    Bracket bt, bp;
+    bt.i0 = q.ti0; bt.i1 = q.ti1; bt.t = q.tt;
+    bp.i0 = q.pi0; bp.i1 = q.pi1; bp.t = q.pt;
     double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
     double kext = kl + k_ray[n];
     alpha[(size_t)c * slot_stride + s] = g.rho[c] * kext;
@@ -357,14 +368,20 @@ void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, dou
     hipLaunchKernelGGL(k_doppler_shift, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ox, oy, oz, dlnlam, shift);
 }
 
-void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT, int nP,
-                              const double* T_grid, const double* lnP_grid, const double* k_ray,
-                              const double* shift, const int* nlist, int nslot, int slot_stride, double* alpha,
-                              hipStream_t stream)
+void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T_grid, const double* lnP_grid,
+                    CellTP* out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_cell_tp, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, nT, nP, T_grid, lnP_grid,
+                       out);
+}
+
+void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
+                              const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
+                              int nslot, int slot_stride, double* alpha, hipStream_t stream)
 {
     long long n = (long long)ncell * nslot;
-    hipLaunchKernelGGL(k_hires_alpha_block, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nT,
-                       nP, T_grid, lnP_grid, k_ray, shift, nlist, nslot, slot_stride, alpha);
+    hipLaunchKernelGGL(k_hires_alpha_block, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nP,
+                       tp, k_ray, shift, nlist, nslot, slot_stride, alpha);
 }
 
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out, hipStream_t stream)

@@ -170,10 +170,17 @@ void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT
                       OpticsDev<double> out, int ext_stride, hipStream_t stream);
 void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, double dlnlam,
                           double* shift, hipStream_t stream);
-void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nT,
-                              int nP, const double* T_grid, const double* lnP_grid,
-                              const double* k_ray, const double* shift, const int* nlist, int nslot,
-                              int slot_stride, double* alpha, hipStream_t stream);
+// A cell's place in the opacity table's (T, ln P) grid: bracketing nodes
+// and fractions, the same for every wavelength of a transmission solve.
+struct CellTP {
+    int ti0, ti1, pi0, pi1;
+    double tt, pt;
+};
+void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T_grid, const double* lnP_grid,
+                    CellTP* out, hipStream_t stream);
+void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
+                              const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
+                              int nslot, int slot_stride, double* alpha, hipStream_t stream);
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,
                             hipStream_t stream);
 void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
