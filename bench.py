@@ -39,11 +39,11 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "b8440a84d058e57873845ec5a646b28c2472ac308ab6d452696cc2623ba279bc"
-TRAFFIC_BYTES_PER_SOLVE = (149342580 * (1048576 / 524305) + 24011093 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "a84443d09128666b888822c16e4681e40d460d3d25e9784324edaa11916d86a2"
+TRAFFIC_BYTES_PER_SOLVE = (149612886 * (1048576 / 524305) + 24011793 * 1.0) * 1024 / 168
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
-VALU_BUSY = 0.894
+VALU_BUSY = 0.893
 
 
 def parse():
