@@ -219,9 +219,11 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   replays it on later calls with identical arguments (same ids, parameters,
  *   packet_dump and stream, and the same library scratch buffers).  Results are
  *   identical to the eager path; profile is ignored (kernel_ms then holds the
- *   whole replay).  The library keeps at most 16 graphs and drops those of a
- *   grid or table when it is freed.  Ignored by transmission and served
- *   requests.
+ *   whole replay).  mcrt_solve_batch records likewise (the whole multi-grid
+ *   chain: grid table, per-launch solve tables, preparation, transport and
+ *   reduction of every launch).  The library keeps at most 16 graphs and
+ *   drops those of a grid or table when it is freed.  Ignored by
+ *   transmission and served requests.
  * contrib: mcrt_solve_albedo / mcrt_solve_emission only (EINVAL elsewhere):
  *   non-zero also fills mcrt_result.cf with the contribution functions.
  * image_npix: the same solves on a spherical grid: > 0 also fills

@@ -96,6 +96,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     void* pinned = nullptr;
     int32_t gid = 0, oid = 0;
+    std::vector<int32_t> gids, oids;  // every grid and table of a recorded batch
     uint64_t used = 0;
     ~GraphEntry()
     {
@@ -596,8 +597,10 @@ void drop_graphs(mcrt_ctx* ctx, int32_t gid, int32_t oid)
 {
     std::lock_guard<std::mutex> gk(ctx->graph_mu);
     for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
-        const bool hit = (gid == 0 && oid == 0) || (gid != 0 && it->second->gid == gid) ||
-                         (oid != 0 && it->second->oid == oid);
+        const GraphEntry& e = *it->second;
+        const bool hit = (gid == 0 && oid == 0) || (gid != 0 && e.gid == gid) || (oid != 0 && e.oid == oid) ||
+                         (gid != 0 && std::find(e.gids.begin(), e.gids.end(), gid) != e.gids.end()) ||
+                         (oid != 0 && std::find(e.oids.begin(), e.oids.end(), oid) != e.oids.end());
         it = hit ? ctx->graphs.erase(it) : std::next(it);
     }
 }
@@ -1295,94 +1298,198 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     A.peel_w = 1.0;
     const int bpc = common->tune_blocks_per_cu > 0 ? common->tune_blocks_per_cu : 4;
     const int pblocks = ctx->n_cu * bpc;
-    const bool prof = common->profile != 0;
+    // Replayable form (params.graph): the chain below is recorded once per set
+    // of arguments (items, parameters, launch partition, stream and scratch
+    // addresses) with its host tables in pinned memory, and replayed after.
+    const bool use_graph = common->graph != 0 && !sl.stream_ordered;
+    const bool prof = common->profile != 0 && !use_graph;
     if (prof && (rc = prof_events(ctx, sl, launches.size()))) return rc;
-    std::vector<std::vector<SolveDev>> hsv(launches.size());
-    std::vector<std::vector<PrepSlot>> hps(launches.size());
-    HIPTRY(hipEventRecord(sl.ev0, st));
-    HIPTRY(hipMemcpyAsync(v_grids, hgrids.data(), sizeof(GridDev) * hgrids.size(), hipMemcpyHostToDevice, st));
-    launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
-    for (size_t li = 0; li < launches.size(); ++li) {
-        const int s0 = launches[li].first, s1 = launches[li].second, nb = s1 - s0;
-        hsv[li].resize(nb);
-        hps[li].resize(nb);
-        char* arena = (char*)v_arena;
-        uint64_t begin = 0;
-        for (int sg = s0; sg < s1; ++sg) {
-            const Flat& F = fl[sg];
-            Item& I = *it[F.item];
-            const int ncell = I.ls.g->ncell;
-            const int b = I.pl.specs[F.spec];
-            OpacRes* op = I.ls.op;
-            PrepSlot& P = hps[li][sg - s0];
-            P.lnk = op->lnk + ((size_t)b * op->ng + F.g) * op->nT * op->nP;
-            P.k_ray = op->k_ray[b];
-            P.n = b;
-            P.lam_cm = op->lam_um[b] * 1e-4;
-            auto take = [&](size_t bytes) {
-                char* r = arena;
-                arena += (bytes + 255) & ~(size_t)255;
-                return r;
-            };
-            P.opt = (double*)take(sizeof(double) * 5 * (size_t)ncell);
-            P.optf = mixed ? (float*)take(sizeof(float) * 5 * (size_t)ncell) : nullptr;
-            P.cdf = P.wbirth = nullptr;
-            if (I.mode == MCRT_MODE_EMISSION) {
-                P.cdf = (double*)take(sizeof(double) * 2 * (size_t)ncell);
-                P.wbirth = P.cdf + ncell;
+    GraphEntry* ge = nullptr;
+    bool capture = false;
+    std::string gkey;
+    size_t n_tab = 0;  // solve slots over all launches
+    for (auto& L : launches) n_tab += (size_t)(L.second - L.first);
+    if (use_graph) {
+        auto add = [&gkey](const void* v, size_t n) { gkey.append((const char*)v, n); };
+        add("batch", 5);
+        for (int q = 0; q < n_items; ++q) {
+            const Item& I = *it[q];
+            const int64_t ip[5] = {I.mode, items[q].grid_id, items[q].opac_id, (int64_t)I.p.n_packets,
+                                   (int64_t)I.pl.specs.size()};
+            add(ip, sizeof ip);
+            add(I.pl.specs.data(), sizeof(int) * I.pl.specs.size());
+            add(I.pl.obs.data(), sizeof(double) * I.pl.obs.size());
+        }
+        const double dpar[10] = {common->rr_threshold, common->rr_survive, common->emis_bias, common->tau_vert_max,
+                                 common->tau_peel_max, common->mu0, (double)common->max_events,
+                                 common->surface_albedo, common->draine_alpha, 0.0};
+        add(dpar, sizeof dpar);
+        const int64_t ipar[13] = {(int64_t)common->seed, common->precision, common->decorrelate, common->scattering,
+                                  common->absorption, A.ev_threshold, bpc, A.batch, common->cloud_phase,
+                                  common->forced, common->forced_first, (int64_t)launches.size(), n_items};
+        add(ipar, sizeof ipar);
+        add(launches.data(), sizeof(launches[0]) * launches.size());
+        const void* ptrs[10] = {st, v_arena, v_sums, v_part, v_solves, v_slots, v_ctr, v_grids, v_ps, nullptr};
+        add(ptrs, sizeof ptrs);
+        std::lock_guard<std::mutex> gk(ctx->graph_mu);
+        auto gi = ctx->graphs.find(gkey);
+        if (gi != ctx->graphs.end()) {
+            ge = gi->second.get();
+        } else {
+            if (ctx->graphs.size() >= kMaxGraphs) {  // drop the least recently used
+                auto lru = ctx->graphs.begin();
+                for (auto q = ctx->graphs.begin(); q != ctx->graphs.end(); ++q)
+                    if (q->second->used < lru->second->used) lru = q;
+                ctx->graphs.erase(lru);
             }
-            P.stats = sums + (size_t)sg * row_w + pw;
-            SolveDev& S = hsv[li][sg - s0];
-            S.begin = begin;
-            S.pbase = begin;
-            S.n = I.p.n_packets;
-            begin += S.n;
-            S.tag = common->decorrelate ? (uint32_t)(1 + b * I.pl.ng + F.g) : 0u;
-            S.mode = I.mode == MCRT_MODE_EMISSION ? 1 : 0;
-            S.grid = I.gslot;
-            S.cdf = P.cdf;
-            S.wbirth = P.wbirth;
-            if (mixed) {
-                const float* f = P.optf;
-                S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
-                S.g_cld = f + 4 * (size_t)ncell;
-            } else {
-                const double* d = P.opt;
-                S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
-                S.g_cld = d + 4 * (size_t)ncell;
+            std::unique_ptr<GraphEntry> e(new GraphEntry());
+            for (int q = 0; q < n_items; ++q) {
+                e->gids.push_back(items[q].grid_id);
+                e->oids.push_back(items[q].opac_id);
+            }
+            HIPTRY(hipHostMalloc(&e->pinned, sizeof(GridDev) * grids.size() + (sizeof(SolveDev) + sizeof(PrepSlot)) * n_tab));
+            ge = e.get();
+            ctx->graphs[gkey] = std::move(e);
+            capture = true;
+        }
+        ge->used = ++ctx->graph_clock;
+    }
+    // host tables: pinned (graph) or pageable (eager; kept until the end)
+    std::vector<GridDev> e_grids;
+    std::vector<SolveDev> e_solves;
+    std::vector<PrepSlot> e_slots;
+    GridDev* t_grids;
+    SolveDev* t_solves;
+    PrepSlot* t_slots;
+    if (use_graph) {
+        t_grids = (GridDev*)ge->pinned;
+        t_solves = (SolveDev*)(t_grids + grids.size());
+        t_slots = (PrepSlot*)(t_solves + n_tab);
+    } else {
+        e_grids.resize(grids.size());
+        e_solves.resize(n_tab);
+        e_slots.resize(n_tab);
+        t_grids = e_grids.data();
+        t_solves = e_solves.data();
+        t_slots = e_slots.data();
+    }
+    for (size_t q = 0; q < grids.size(); ++q) t_grids[q] = hgrids[q];
+
+    auto enqueue = [&]() -> int {
+        HIPTRY(hipMemcpyAsync(v_grids, t_grids, sizeof(GridDev) * grids.size(), hipMemcpyHostToDevice, st));
+        launch_fill_f64(sums, (size_t)nsolve * row_w, 0.0, st);
+        size_t tab0 = 0;
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const int s0 = launches[li].first, s1 = launches[li].second, nb = s1 - s0;
+            SolveDev* hsv = t_solves + tab0;
+            PrepSlot* hps = t_slots + tab0;
+            tab0 += (size_t)nb;
+            char* arena = (char*)v_arena;
+            uint64_t begin = 0;
+            for (int sg = s0; sg < s1; ++sg) {
+                const Flat& F = fl[sg];
+                Item& I = *it[F.item];
+                const int ncell = I.ls.g->ncell;
+                const int b = I.pl.specs[F.spec];
+                OpacRes* op = I.ls.op;
+                PrepSlot& P = hps[sg - s0];
+                P = PrepSlot{};
+                P.lnk = op->lnk + ((size_t)b * op->ng + F.g) * op->nT * op->nP;
+                P.k_ray = op->k_ray[b];
+                P.n = b;
+                P.lam_cm = op->lam_um[b] * 1e-4;
+                auto take = [&](size_t bytes) {
+                    char* r = arena;
+                    arena += (bytes + 255) & ~(size_t)255;
+                    return r;
+                };
+                P.opt = (double*)take(sizeof(double) * 5 * (size_t)ncell);
+                P.optf = mixed ? (float*)take(sizeof(float) * 5 * (size_t)ncell) : nullptr;
+                P.cdf = P.wbirth = nullptr;
+                if (I.mode == MCRT_MODE_EMISSION) {
+                    P.cdf = (double*)take(sizeof(double) * 2 * (size_t)ncell);
+                    P.wbirth = P.cdf + ncell;
+                }
+                P.stats = sums + (size_t)sg * row_w + pw;
+                SolveDev& S = hsv[sg - s0];
+                S = SolveDev{};
+                S.begin = begin;
+                S.pbase = begin;
+                S.n = I.p.n_packets;
+                begin += S.n;
+                S.tag = common->decorrelate ? (uint32_t)(1 + b * I.pl.ng + F.g) : 0u;
+                S.mode = I.mode == MCRT_MODE_EMISSION ? 1 : 0;
+                S.grid = I.gslot;
+                S.cdf = P.cdf;
+                S.wbirth = P.wbirth;
+                if (mixed) {
+                    const float* f = P.optf;
+                    S.a_ext = f; S.a_abs = f + ncell; S.omega = f + 2 * (size_t)ncell; S.p_gas = f + 3 * (size_t)ncell;
+                    S.g_cld = f + 4 * (size_t)ncell;
+                } else {
+                    const double* d = P.opt;
+                    S.a_ext = d; S.a_abs = d + ncell; S.omega = d + 2 * (size_t)ncell; S.p_gas = d + 3 * (size_t)ncell;
+                    S.g_cld = d + 4 * (size_t)ncell;
+                }
+            }
+            double* rows = (double*)arena;  // rows after the optics of the launch
+            HIPTRY(hipMemcpyAsync(v_slots, hps, sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
+            HIPTRY(hipMemcpyAsync(v_solves, hsv, sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
+            // preparation per run of consecutive solves of one item (one grid, one table)
+            for (int a = s0; a < s1;) {
+                int e = a;
+                while (e < s1 && fl[e].item == fl[a].item) ++e;
+                Item& I = *it[fl[a].item];
+                OpacRes* op = I.ls.op;
+                const PrepSlot* ps = (const PrepSlot*)v_slots + (a - s0);
+                launch_prep_optics(I.ls.g->dev, I.ls.g->ncell, ps, e - a, 0, op->nT, op->nP, op->T_grid, op->lnP_grid,
+                                   op->lnk, op->nspec, nullptr, common->cloud_phase == 2 ? 1 : 0,
+                                   common->draine_alpha, st);
+                if (I.mode == MCRT_MODE_EMISSION)
+                    launch_prep_sources(I.ls.g->dev, I.ls.g->ncell, ps, e - a, I.p.tau_vert_max, I.p.emis_bias,
+                                        (double*)v_ps, st);
+                a = e;
+            }
+            A.rows = rows;
+            A.solves = (const SolveDev*)v_solves;
+            A.n_solves = nb;
+            A.total = begin;
+            launch_init_dispensers(A.counter, A.total, st);
+            launch_births(hgrids[0], A, true, st);
+            if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li], st));
+            launch_transport_persistent(hgrids[0], A, mixed, true, pblocks, bpc, st);
+            if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li + 1], st));
+            int chunks_l = 1;
+            for (int sg = s0; sg < s1; ++sg)
+                chunks_l = std::max(chunks_l, reduce_rows_chunks(it[fl[sg].item]->p.n_packets));
+            launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks_l, sums + (size_t)s0 * row_w, row_w, nullptr,
+                               st);
+            // in eager form the next launch's pageable tables are copied only after
+            // this launch ran; stream order alone protects the reused device buffers
+            if (!use_graph && li + 1 < launches.size()) HIPTRY(hipStreamSynchronize(st));
+        }
+        return MCRT_OK;
+    };
+    if (use_graph) {
+        if (capture) {
+            HIPTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int crc = enqueue();
+            hipGraph_t gr = nullptr;
+            hipError_t ee = hipStreamEndCapture(st, &gr);
+            if (crc == MCRT_OK && ee == hipSuccess) ee = hipGraphInstantiate(&ge->exec, gr, nullptr, nullptr, 0);
+            ge->graph = gr;
+            if (crc != MCRT_OK || ee != hipSuccess) {
+                std::lock_guard<std::mutex> gk(ctx->graph_mu);
+                ctx->graphs.erase(gkey);
+                if (crc != MCRT_OK) return crc;
+                HIPTRY(ee);
             }
         }
-        double* rows = (double*)arena;  // rows after the optics of the launch
-        HIPTRY(hipMemcpyAsync(v_slots, hps[li].data(), sizeof(PrepSlot) * nb, hipMemcpyHostToDevice, st));
-        HIPTRY(hipMemcpyAsync(v_solves, hsv[li].data(), sizeof(SolveDev) * nb, hipMemcpyHostToDevice, st));
-        // preparation per run of consecutive solves of one item (one grid, one table)
-        for (int a = s0; a < s1;) {
-            int e = a;
-            while (e < s1 && fl[e].item == fl[a].item) ++e;
-            Item& I = *it[fl[a].item];
-            OpacRes* op = I.ls.op;
-            const PrepSlot* ps = (const PrepSlot*)v_slots + (a - s0);
-            launch_prep_optics(I.ls.g->dev, I.ls.g->ncell, ps, e - a, 0, op->nT, op->nP, op->T_grid, op->lnP_grid,
-                               op->lnk, op->nspec, nullptr, common->cloud_phase == 2 ? 1 : 0,
-                               common->draine_alpha, st);
-            if (I.mode == MCRT_MODE_EMISSION)
-                launch_prep_sources(I.ls.g->dev, I.ls.g->ncell, ps, e - a, I.p.tau_vert_max, I.p.emis_bias,
-                                    (double*)v_ps, st);
-            a = e;
-        }
-        A.rows = rows;
-        A.solves = (const SolveDev*)v_solves;
-        A.n_solves = nb;
-        A.total = begin;
-        launch_init_dispensers(A.counter, A.total, st);
-        launch_births(hgrids[0], A, true, st);
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li], st));
-        launch_transport_persistent(hgrids[0], A, mixed, true, pblocks, bpc, st);
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * li + 1], st));
-        int chunks_l = 1;
-        for (int sg = s0; sg < s1; ++sg) chunks_l = std::max(chunks_l, reduce_rows_chunks(it[fl[sg].item]->p.n_packets));
-        launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks_l, sums + (size_t)s0 * row_w, row_w, nullptr, st);
-        if (li + 1 < launches.size()) HIPTRY(hipStreamSynchronize(st));  // the arena is reused
+        HIPTRY(hipEventRecord(sl.ev0, st));
+        HIPTRY(hipGraphLaunch(ge->exec, st));
+    } else {
+        HIPTRY(hipEventRecord(sl.ev0, st));
+        if ((rc = enqueue())) return rc;
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nsolve * row_w);
@@ -1390,6 +1497,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     mcrt_result tr{};
     if ((rc = finish_timing(ctx, sl, st, &tr))) return rc;
     if (prof && (rc = prof_collect(ctx, sl, launches.size(), &tr))) return rc;
+    if (use_graph) tr.kernel_ms = tr.elapsed_ms;  // the whole replay
     // per item post-processing, as for the single-request solves
     for (int q = 0; q < n_items; ++q) {
         Item& I = *it[q];

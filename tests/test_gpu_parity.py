@@ -799,3 +799,35 @@ def test_borrowed_device_grid(ctx, torch_dev):
         ctx.upload_grid(bad, borrow=True)
     assert e.value.name == "EINVAL"
     ctx.free_opacity(oid)
+
+
+def test_multi_grid_batch_graph_replays(ctx, torch_dev):
+    """A multi-grid batch recorded as a hipGraph (params.graph): the first call
+    records the whole chain (two launches of solves on three uneven grids),
+    later identical calls replay it; with eager work and synchronisations in
+    between, every replay equals the eager batch bit for bit."""
+    _log("multi-grid batch graph: record + 3 replays (2 launches) vs eager, eager work in between")
+    specs = [(16, 8, 10), (24, 12, 6), (8, 4, 12)]
+    gids, tabs = [], []
+    for q, (a, b, c) in enumerate(specs):
+        grid, table, _ = I.make_emission_3d(a, b, c, nband=3, ng=2, config_no=130 + q)
+        table.k_ray = table.k_ray * 30.0
+        gids.append(ctx.upload_grid(grid))
+        tabs.append((ctx.upload_opacity(table), table))
+    items = [dict(mode="emission", gid=gids[0], oid=tabs[0][0], table=tabs[0][1], spec_idx=[0, 2], n_packets=1500),
+             dict(mode="albedo", gid=gids[1], oid=tabs[1][0], table=tabs[1][1], spec_idx=[1], n_packets=800),
+             dict(mode="emission", gid=gids[2], oid=tabs[2][0], table=tabs[2][1], spec_idx=[2, 0], n_packets=1100)]
+    common = dict(obs_phase=[0.0, 0.5], seed=197, decorrelate=1, max_batch=5)
+    eager = ctx.solve_batch(items, **common)
+    for rep in range(4):
+        got = ctx.solve_batch(items, graph=1, **common)
+        for e, g in zip(eager, got):
+            assert np.array_equal(e["sums"], g["sums"]) and np.array_equal(e["counters"], g["counters"]), rep
+            assert np.array_equal(e["value"], g["value"]), rep
+        # eager work and a synchronisation between replays
+        ctx.solve_emission(gids[0], tabs[0][0], tabs[0][1], n_packets=300, seed=rep, obs_phase=[0.25], spec_idx=[1])
+        torch_dev.cuda.synchronize()
+    for g in gids:
+        ctx.free_grid(g)
+    for o, _ in tabs:
+        ctx.free_opacity(o)
