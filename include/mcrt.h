@@ -41,7 +41,7 @@ extern "C" {
 #define MCRT_EDEVICE (-3)    /* HIP runtime error; context unusable   */
 #define MCRT_ENOTFOUND (-4)  /* unknown grid / opacity / ticket id    */
 #define MCRT_EBUDGET (-5)    /* would exceed the context's HBM budget */
-#define MCRT_EBUSY (-6)      /* object in use by queued work          */
+#define MCRT_EBUSY (-6)      /* object in use by a running solve      */
 #define MCRT_ECANCELLED (-7) /* request was cancelled                 */
 
 #define MCRT_SPHERICAL 0
@@ -419,7 +419,10 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
  * arrival order whenever the context's HBM budget covers the request's
  * device scratch (estimated at submit), so requests run concurrently on the
  * device while grids and tables stay resident.  A request whose scratch
- * alone exceeds the budget is rejected at submit with MCRT_EBUDGET.
+ * alone exceeds the budget is rejected at submit with MCRT_EBUDGET; one
+ * that no longer fits when no other request is running (the memory went to
+ * uploads or blocking solves after it was submitted) fails with MCRT_EBUDGET
+ * instead of holding up the queue.
  * mcrt_poll sets *done to 1 once the request finished, failed or was
  * cancelled.  mcrt_wait blocks until then, copies the results into the
  * caller's arrays (shaped as for the blocking solve), forgets the ticket and

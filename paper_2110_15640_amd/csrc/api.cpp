@@ -114,7 +114,7 @@ struct mcrt_ctx {
     int n_cu = 256;
     uint64_t budget = 0;
     uint64_t in_use = 0;
-    std::mutex mem_mu;  // in_use
+    mutable std::mutex mem_mu;  // in_use, reserved, served
     std::mutex mu;      // grids, opacs, refs
     std::mutex main_mu; // blocking solves on the main slot
     Slot main;
@@ -133,7 +133,8 @@ struct mcrt_ctx {
     std::map<uint64_t, std::unique_ptr<Request>> requests;
     std::vector<std::thread> workers;
     std::vector<std::unique_ptr<Slot>> wslots;
-    uint64_t reserved = 0;  // bytes admitted to running requests
+    uint64_t reserved = 0;  // bytes admitted to running requests (their estimates)
+    uint64_t served = 0;    // bytes of in_use the running requests allocated
     uint64_t next_ticket = 1;
     int n_workers = 3;
     bool stopping = false;
@@ -146,6 +147,14 @@ int hip_check(mcrt_ctx* ctx, hipError_t e, const char* what)
     if (e == hipSuccess) return MCRT_OK;
     if (ctx) ctx->poisoned = true;
     return fail(MCRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device memory held or promised, in bytes (caller holds mem_mu): what is
+// allocated, plus what admitted requests may still allocate (an admitted
+// request's allocations are charged to its reservation, not twice).
+uint64_t held_locked(const mcrt_ctx* ctx)
+{
+    return ctx->in_use + (ctx->reserved > ctx->served ? ctx->reserved - ctx->served : 0);
 }
 
 #define HIPTRY(expr)                                          \
@@ -161,11 +170,12 @@ int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out, hipStream_t ordered = nu
     if (bytes == 0) bytes = 8;
     {
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
-        if (!ordered && ctx->in_use + ctx->reserved + bytes > ctx->budget)
+        if (!ordered && held_locked(ctx) + bytes > ctx->budget)
             return fail(MCRT_EBUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu in use, %llu reserved, "
                         "budget %llu)", bytes, (unsigned long long)ctx->in_use, (unsigned long long)ctx->reserved,
                         (unsigned long long)ctx->budget);
         ctx->in_use += bytes;
+        if (ordered) ctx->served += bytes;
     }
     void* p = nullptr;
     hipError_t e = ordered ? hipMallocAsync(&p, bytes, ordered) : hipMalloc(&p, bytes);
@@ -173,6 +183,7 @@ int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out, hipStream_t ordered = nu
         (void)hipGetLastError();
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
         ctx->in_use -= bytes;
+        if (ordered) ctx->served -= bytes;
         return fail(MCRT_ENOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
     }
     out.p = p;
@@ -187,6 +198,7 @@ void dev_free(mcrt_ctx* ctx, DevBuf& b, hipStream_t ordered = nullptr)
         else (void)hipFree(b.p);
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
         ctx->in_use -= b.bytes;
+        if (ordered) ctx->served -= b.bytes;
     }
     b.p = nullptr;
     b.bytes = 0;
@@ -713,7 +725,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         uint64_t room;
         {
             std::lock_guard<std::mutex> mk(ctx->mem_mu);
-            room = ctx->budget > ctx->in_use + ctx->reserved ? ctx->budget - ctx->in_use - ctx->reserved : 0;
+            room = ctx->budget - std::min(ctx->budget, held_locked(ctx));
         }
         uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
         int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
@@ -1225,7 +1237,7 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     uint64_t room;
     {
         std::lock_guard<std::mutex> mk(ctx->mem_mu);
-        room = ctx->budget > ctx->in_use + ctx->reserved ? ctx->budget - ctx->in_use - ctx->reserved : 0;
+        room = ctx->budget - std::min(ctx->budget, held_locked(ctx));
     }
     const uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
     // launches: consecutive solves while the footprint fits (and <= max_batch)
@@ -1603,18 +1615,37 @@ void worker_main(mcrt_ctx* ctx, Slot* sl)
     (void)hipSetDevice(ctx->device);
     std::unique_lock<std::mutex> lk(ctx->q_mu);
     for (;;) {
+        // With no admitted request left, memory held now (grids, tables, the
+        // blocking solves' scratch) only shrinks if the caller frees it, so
+        // the head of the queue is taken then and fails if it does not fit,
+        // rather than blocking every request behind it.
         ctx->q_cv.wait(lk, [&] {
             if (ctx->stopping) return true;
             if (ctx->queue.empty()) return false;
             std::lock_guard<std::mutex> mk(ctx->mem_mu);
-            return ctx->in_use + ctx->reserved + ctx->queue.front()->est <= ctx->budget;
+            return ctx->reserved == 0 || held_locked(ctx) + ctx->queue.front()->est <= ctx->budget;
         });
         if (ctx->stopping) return;
         Request* r = ctx->queue.front();
         ctx->queue.pop_front();
+        bool fits;
+        uint64_t held;
         {
             std::lock_guard<std::mutex> mk(ctx->mem_mu);
-            ctx->reserved += r->est;
+            held = held_locked(ctx);
+            fits = held + r->est <= ctx->budget;
+            if (fits) ctx->reserved += r->est;
+        }
+        if (!fits) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "request needs %llu bytes of scratch; %llu of the budget of %llu are held",
+                          (unsigned long long)r->est, (unsigned long long)held, (unsigned long long)ctx->budget);
+            r->rc = MCRT_EBUDGET;
+            r->err = msg;
+            r->t_start = r->t_done = Clock::now();
+            r->status = R_FAILED;
+            ctx->q_cv.notify_all();
+            continue;
         }
         r->status = R_RUNNING;
         r->t_start = Clock::now();
@@ -1708,9 +1739,10 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
     r->est = estimate_bytes(ctx, *r, ls.g, ls.op);
     {
         std::lock_guard<std::mutex> mk(ctx->mem_mu);
-        if (r->est + ctx->in_use > ctx->budget)
+        const uint64_t resident = ctx->in_use - ctx->served;  // not freed when running requests end
+        if (r->est + resident > ctx->budget)
             return fail(MCRT_EBUDGET, "request needs %llu bytes of scratch; the budget leaves %llu",
-                        (unsigned long long)r->est, (unsigned long long)(ctx->budget - std::min(ctx->budget, ctx->in_use)));
+                        (unsigned long long)r->est, (unsigned long long)(ctx->budget - std::min(ctx->budget, resident)));
     }
     std::lock_guard<std::mutex> lk(ctx->q_mu);
     if (ctx->stopping) return fail(MCRT_EINVAL, "context is shutting down");
@@ -1805,7 +1837,12 @@ void mcrt_destroy(mcrt_ctx* ctx)
     delete ctx;
 }
 
-uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+uint64_t mcrt_memory_in_use(const mcrt_ctx* ctx)
+{
+    if (!ctx) return 0;
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    return ctx->in_use;
+}
 
 int mcrt_serve_config(mcrt_ctx* ctx, int32_t n_workers)
 {
@@ -1989,7 +2026,7 @@ int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->grids.find(grid_id);
     if (it == ctx->grids.end()) return fail(MCRT_ENOTFOUND, "grid %d not found", grid_id);
-    if (it->second->refs > 0) return fail(MCRT_EBUSY, "grid %d is used by queued work", grid_id);
+    if (it->second->refs > 0) return fail(MCRT_EBUSY, "grid %d is in use by a running solve", grid_id);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->main.stream);
     drop_graphs(ctx, grid_id, 0);
@@ -2059,7 +2096,7 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->opacs.find(opac_id);
     if (it == ctx->opacs.end()) return fail(MCRT_ENOTFOUND, "opacity %d not found", opac_id);
-    if (it->second->refs > 0) return fail(MCRT_EBUSY, "opacity %d is used by queued work", opac_id);
+    if (it->second->refs > 0) return fail(MCRT_EBUSY, "opacity %d is in use by a running solve", opac_id);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->main.stream);
     drop_graphs(ctx, 0, opac_id);

@@ -83,3 +83,47 @@ def test_cancel_poll_and_budget(torch_dev):
         with pytest.raises(M.McrtError) as e:
             ctx.poll(t3)
         assert e.value.name == "ENOTFOUND"
+
+
+def test_queued_request_that_no_longer_fits_fails_without_blocking(torch_dev):
+    """Admission charges a running request's allocations to its reservation
+    once; a queued request whose scratch no longer fits after the memory went
+    to a blocking solve fails with EBUDGET once nothing runs, and the queue
+    keeps serving the requests behind it."""
+    print("serving: queued request outgrown by a blocking solve", flush=True)
+    from paper_2110_15640_amd import mcrt as M
+    grid, ck, phases = I.make_emission_3d(16, 8, 10, nband=1, ng=1)
+    MB = 1 << 20
+    per_mpkt = 96 * 10**6  # rows of 12 doubles per packet with one observer
+    probe = M.Context(0)
+    probe.upload_grid(grid)
+    probe.upload_opacity(ck)
+    resident = probe.memory_in_use
+    probe.close()
+    # A = 4e6 packets (~384 MB), R = 12e6 (~1152 MB), S = 8e6 (~768 MB):
+    # R fits alone at submit, S fits beside A, R does not fit beside S
+    budget = resident + 1400 * MB
+    with M.Context(0, hbm_budget_bytes=budget) as ctx:
+        ctx.serve_config(1)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(ck)
+        assert ctx.memory_in_use == resident
+        ta = ctx.submit("emission", gid, oid, ck, n_packets=4 * 10**6, obs_phase=[0.5], seed=1)
+        tr = ctx.submit("emission", gid, oid, ck, n_packets=12 * 10**6, obs_phase=[0.5], seed=2)
+        try:
+            s = ctx.solve_emission(gid, oid, ck, n_packets=8 * 10**6, obs_phase=[0.5], seed=3)
+        except M.McrtError as e:
+            assert e.name == "EBUDGET"
+            ctx.wait(ta)
+            try:
+                ctx.wait(tr)
+            except M.McrtError:
+                pass
+            pytest.skip("request A ended before the blocking solve allocated; R was admitted first")
+        assert np.all(s["value"] > 0)
+        assert ctx.memory_in_use >= resident + 8 * per_mpkt
+        assert np.all(ctx.wait(ta)["value"] > 0)
+        with pytest.raises(M.McrtError) as e:
+            ctx.wait(tr)
+        assert e.value.name == "EBUDGET"
+        tt = ctx.submit("emission", gid, oid, ck, n_packets=10**5, obs_phase=[0.5], seed=4)
+        assert np.all(ctx.wait(tt)["value"] > 0)
