@@ -41,6 +41,11 @@ PEAK_HBM = 8000.0  # GB/s
 # measured on (hash below), else reported as null.
 TRAFFIC_KERNEL_SHA = "a84443d09128666b888822c16e4681e40d460d3d25e9784324edaa11916d86a2"
 TRAFFIC_BYTES_PER_SOLVE = (149612886 * (1048576 / 524305) + 24011793 * 1.0) * 1024 / 168
+# The same for the chord optical-depth kernel of the transmission solve: bytes
+# per (chord segment, wavelength) over its launches, valid for the sources of
+# that kernel hashed below.
+TRAFFIC_K5_SHA = "e5cfb9b0efe980757e8be275c005d6eb1bd26bfe02aecf7eea079a54939e8ea3"
+TRAFFIC_K5_BYTES_PER_SEG_WL = ((469041505.25 * (1048576 / 524311.25) + 902880.0) * 1024) / (7861278 * 20064)
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
 VALU_BUSY = 0.893
@@ -75,12 +80,12 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sha() -> str:
-    """sha256 of the transport kernel's sources, concatenated in this order."""
+def kernel_sha(main: str = "transport.hip") -> str:
+    """sha256 of a kernel's sources (its file, then the shared headers)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2110_15640_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("transport.hip", "device_common.hpp", "mcrt_internal.hpp"):
+    for f in (main, "device_common.hpp", "mcrt_internal.hpp"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
 
@@ -120,13 +125,16 @@ def transmission_leg(M, I):
         nseg, nl, nblk = r["n_segments"], table.nlam, r["kernel_launches"]
         k5_bytes = nseg * nl * 8.0 + nseg * nblk * 12.0 + nch * nblk * 12.0
         k5_gbps = k5_bytes / (r["kernel_ms"] * 1e-3) / 1e9
+        k5_traffic = (TRAFFIC_K5_BYTES_PER_SEG_WL * nseg * nl / max(nblk, 1)
+                      if kernel_sha("kernels.hip") == TRAFFIC_K5_SHA else None)
         return {"workload": f"3D hi-res transmission: {grid.nlon}x{grid.nlat}x{grid.nlay} grid, {table.nlam} wavelengths "
                             "1.0-1.1 um, 256 x 360 chords, winds + rotation Doppler",
                 "ms": wall * 1e3, "chord_wavelengths_per_s": nch * table.nlam / wall,
                 "chord_tau_kernel_ms": r["kernel_ms"], "chord_tau_launches": r["kernel_launches"],
                 "segments": nseg,
                 "roofline": {"bound": "hbm", "kernel": "k_chord_tau", "achieved": k5_gbps, "peak": PEAK_HBM,
-                             "unit": "GB/s", "frac": k5_gbps / PEAK_HBM, "traffic": None,
+                             "unit": "GB/s", "frac": k5_gbps / PEAK_HBM, "traffic": k5_traffic,
+                             "traffic_unit": "bytes per launch (mean)",
                              "bytes_per_segment_wavelength": 8.0},
                 "depth_min": float(depth.min()), "depth_max": float(depth.max()),
                 "rel_se_median": float(np.median(r["stderr"][:, 0] / depth))}
