@@ -406,7 +406,8 @@ int mcrt_solve_batch(mcrt_ctx* ctx, int32_t n_items, const mcrt_batch_item* item
  * solves of this request (up to 4 of its spectral points with its packet
  * count, at most 1e6 each) over event thresholds {16, 24, 32}, blocks per
  * compute unit {3, 4} and wave batches {32, 128}, and writes the fastest into
- * params->tune_* (best_packets_per_s, if not NULL, receives its trial rate).
+ * params->tune_* (best_packets_per_s, if not NULL, receives its trial rate:
+ * packets of all the trial's (spectral point, g) solves per second).
  * Results of a solve do not depend on these settings.  mode: MCRT_MODE_ALBEDO
  * or MCRT_MODE_EMISSION.  Errors as for the blocking solves. */
 int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,

@@ -2115,13 +2115,15 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     // request's packet count (at most 1e6) each, all in one batch, so that
     // the end-of-launch tail weighs about as much as in the real launches
     std::vector<int32_t> all;
-    if (params->spec_idx && params->n_spec > 0) {
-        all.assign(params->spec_idx, params->spec_idx + params->n_spec);
-    } else {
+    int ng = 1;  // solves per spectral point (the g-ordinates, unless sampled per packet)
+    {
         Lease ls;
         int rc = lease(ctx, grid_id, opac_id, ls);
         if (rc) return rc;
-        for (int q = 0; q < ls.op->nspec; ++q) all.push_back(q);
+        if (params->spec_idx && params->n_spec > 0) all.assign(params->spec_idx, params->spec_idx + params->n_spec);
+        else
+            for (int q = 0; q < ls.op->nspec; ++q) all.push_back(q);
+        if (ls.op->kind == MCRT_OPAC_CK && !params->g_sampling) ng = ls.op->ng;
     }
     std::vector<int32_t> spec;
     const int nt = std::min<int>(4, (int)all.size());
@@ -2138,7 +2140,7 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     t.image_npix = 0;
     const int evs[3] = {16, 24, 32}, bpcs[2] = {3, 4}, wbs[2] = {32, 128};
     double best = -1.0;
-    int be = 16, bb = 4, bw = 64;
+    int be = evs[0], bb = bpcs[0], bw = wbs[0];
     std::vector<double> v(64 * 8), e(64 * 8);
     mcrt_result r{};
     r.value = v.data();
@@ -2157,7 +2159,7 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
                 }
                 int rc = blocking_solve(ctx, mode, grid_id, opac_id, &t, &r);
                 if (rc) return rc;
-                double rate = (double)t.n_packets * t.n_spec / std::max(r.elapsed_ms, 1e-3) * 1e3;
+                double rate = (double)t.n_packets * t.n_spec * ng / std::max(r.elapsed_ms, 1e-3) * 1e3;
                 if (rate > best) {
                     best = rate;
                     be = evs[a];

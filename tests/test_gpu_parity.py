@@ -274,6 +274,34 @@ def test_batched_and_launch_shapes_are_bit_identical(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("mode", ["albedo", "emission"])
+def test_autotuner_picks_a_candidate_shape_that_keeps_results(ctx, torch_dev, mode):
+    """The autotuner returns one of its candidate launch shapes and a trial
+    rate, and the solve run with that shape equals the default-shape solve
+    bit for bit; it refuses the chord (transmission) path."""
+    _log(f"autotuner: {mode}")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=3, ng=2)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    fn = ctx.solve_albedo if mode == "albedo" else ctx.solve_emission
+    kw = dict(n_packets=20000, seed=67, obs_phase=[0.0, 0.5], precision=M.MCRT_MIXED)
+    tuned = ctx.autotune(mode, gid, oid, **kw)
+    assert tuned["tune_ev_threshold"] in (16, 24, 32)
+    assert tuned["tune_blocks_per_cu"] in (3, 4)
+    assert tuned["tune_wave_batch"] in (32, 128)
+    assert np.isfinite(tuned["trial_packets_per_s"]) and tuned["trial_packets_per_s"] > 0.0
+    tuned.pop("trial_packets_per_s")
+    ref = fn(gid, oid, table, **kw)
+    got = fn(gid, oid, table, **kw, **tuned)
+    assert np.array_equal(got["sums"], ref["sums"])
+    assert np.array_equal(got["counters"], ref["counters"])
+    with pytest.raises(M.McrtError) as e:
+        ctx.autotune("transmission", gid, oid, n_b=16, n_alpha=16)
+    assert e.value.name == "EINVAL"
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
+@pytest.mark.parametrize("mode", ["albedo", "emission"])
 def test_mixed_precision_agrees_with_fp64(ctx, torch_dev, mode):
     """FP32 opacity / phase-function / direction math on the same random
     stream: spectra within 1e-3 relative and 3 sigma of the FP64 ones."""
