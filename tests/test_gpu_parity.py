@@ -352,6 +352,45 @@ def test_multi_grid_batch_equals_single_solves(ctx, torch_dev):
         ctx.free_opacity(o)
 
 
+@pytest.mark.parametrize("feature", [dict(surface_albedo=0.3), dict(cloud_phase=1), dict(cloud_phase=2, draine_alpha=0.7),
+                                     dict(forced=2, forced_first=1)],
+                         ids=["lambert", "tthg", "draine", "forced"])
+def test_multi_grid_batch_with_extended_features(ctx, torch_dev, feature):
+    """The multi-grid kernel forms with the Lambert floor, two-term HG or
+    Draine clouds and forced interactions: every item of a batch on grids of
+    uneven size (with clouds) equals its own single solve, in FP64 and in the
+    mixed form."""
+    _log(f"multi-grid batch with {feature}")
+    from paper_2110_15640_amd import mcrt as M
+    specs = [(12, 6, 8), (16, 8, 5)]
+    gids, tabs = [], []
+    rng = np.random.default_rng(41)
+    for q, (a, b, c) in enumerate(specs):
+        grid, table, _ = I.make_emission_3d(a, b, c, nband=3, ng=2, config_no=20 + q)
+        grid.cld_ksca = rng.uniform(0, 2e-2, grid.ncell).astype(np.float32)
+        grid.cld_kabs = rng.uniform(0, 2e-3, grid.ncell).astype(np.float32)
+        grid.cld_g = rng.uniform(0.0, 0.8, grid.ncell).astype(np.float32)
+        table.k_ray = table.k_ray * 50.0
+        gids.append(ctx.upload_grid(grid))
+        tabs.append((ctx.upload_opacity(table), table))
+    items = [dict(mode="emission", gid=gids[0], oid=tabs[0][0], table=tabs[0][1], spec_idx=[0, 2], n_packets=900),
+             dict(mode="albedo", gid=gids[1], oid=tabs[1][0], table=tabs[1][1], spec_idx=[1], n_packets=700),
+             dict(mode="emission", gid=gids[1], oid=tabs[1][0], table=tabs[1][1], spec_idx=[2], n_packets=1100)]
+    for prec in (M.MCRT_FP64, M.MCRT_MIXED):
+        common = dict(obs_phase=[0.0, 0.5], seed=79, decorrelate=1, precision=prec, max_events=200, **feature)
+        outs = ctx.solve_batch(items, max_batch=0, **common)
+        for it, got in zip(items, outs):
+            fn = ctx.solve_albedo if it["mode"] == "albedo" else ctx.solve_emission
+            ref = fn(it["gid"], it["oid"], it["table"], spec_idx=it["spec_idx"], n_packets=it["n_packets"], **common)
+            assert np.array_equal(got["sums"], ref["sums"]), (prec, it["mode"])
+            assert np.array_equal(got["counters"], ref["counters"]), (prec, it["mode"])
+            assert np.all(np.isfinite(got["value"]))
+    for g in gids:
+        ctx.free_grid(g)
+    for o, _ in tabs:
+        ctx.free_opacity(o)
+
+
 def test_graph_replays_equal_eager(ctx, torch_dev):
     """Recorded solves (params.graph): the first call records the device chain,
     later identical calls replay it; with other eager work and synchronisations
