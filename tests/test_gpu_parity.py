@@ -139,6 +139,31 @@ def test_emission_parity_with_clouds(ctx, torch_dev):
     ctx.free_opacity(oid)
 
 
+def test_peel_off_cut_parity(ctx, torch_dev):
+    """A low peel-off cut (tau_peel_max = 1.5) drops many peel-offs mid-walk:
+    every packet against the oracle, albedo and emission, FP64."""
+    _log("peel-off cut parity: tau_peel_max = 1.5, albedo and emission on 12x6x8")
+    grid, table, phases = I.make_emission_3d(12, 6, 8, nband=2, ng=1, config_no=30)
+    table.k_ray = table.k_ray * 100.0
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    n = 1500
+    kw = dict(n_packets=n, seed=47, tau_peel_max=1.5)
+    dump = dump_buffer(torch_dev, 2, n, 2)
+    got = ctx.solve_emission(gid, oid, table, obs_phase=[0.0, 0.5], packet_dump=dump, **kw)
+    ref = O.solve_emission(grid, table, O.Params(obs_phase=(0.0, 0.5), **kw), keep_packets=True)
+    check_packets(dump, ref, (2, 1, n, 2))
+    check_solve(got, ref)
+    dump = dump_buffer(torch_dev, 2, n, 2)
+    got = ctx.solve_albedo(gid, oid, table, obs_phase=[0.0, 0.5], packet_dump=dump, **kw)
+    ref = O.solve_albedo(grid, table, O.Params(obs_phase=(0.0, 0.5), **kw), keep_packets=True)
+    check_packets(dump, ref, (2, 1, n, 2))
+    check_solve(got, ref)
+    full = ctx.solve_albedo(gid, oid, table, obs_phase=[0.0, 0.5], n_packets=n, seed=47)
+    assert np.all(got["value"] <= full["value"]) and np.any(got["value"] < full["value"])
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
 def test_emission_no_scattering_and_tau_cut(ctx, torch_dev):
     _log("emission parity: scattering off, tau_vert = 3, bias xi = 0.8")
     grid, table, phases = I.make_emission_3d(12, 6, 8, nband=3, ng=1)

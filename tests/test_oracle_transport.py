@@ -205,3 +205,25 @@ def test_emission_bias_is_unbiased():
     for o in range(2):
         for r in res[1:]:
             within(r.value[0, o] - res[0].value[0, o], 0.0, math.hypot(r.stderr[0, o], res[0].stderr[0, o]))
+
+
+def test_peel_off_cut_keeps_or_drops_whole_contributions():
+    """A peel-off whose optical depth to the observer passes tau_peel_max is
+    dropped, the others are kept whole, and no random number depends on the
+    cut: so every packet's walk (its counters, crossings aside) is the same
+    for every cut, its tally can only grow with the cut, a cut at 0 keeps
+    nothing (every path has tau > 0), and cuts at 50 and beyond every path's
+    depth agree to e^-50."""
+    g = I.make_sphere(8, 4, 5, seed=16)
+    _, tab, _ = I.make_emission_3d(8, 4, 5, nband=2, ng=2)
+    op = O.ck_optics(g, tab, 1, 0)
+    obs = O.albedo_obs_dirs([0.0, 0.7])
+    walk = [c for c in range(O.NK) if O.K_NAMES[c] != "n_crossings"]
+    runs = [O.transport(g, op, O.Params(n_packets=400, seed=19, tau_peel_max=cut), 0, obs)
+            for cut in (0.0, 0.5, 2.0, 50.0, math.inf)]
+    assert np.all(runs[0][0] == 0.0)
+    for (fa, ka), (fb, kb) in zip(runs, runs[1:]):
+        assert np.array_equal(ka[:, walk], kb[:, walk])
+        assert np.all(fb >= fa)
+    assert np.any(runs[2][0] > runs[1][0]) and np.any(runs[1][0] > 0.0)
+    np.testing.assert_allclose(runs[3][0], runs[4][0], rtol=0.0, atol=1e-20 * runs[4][0].max())
