@@ -501,8 +501,10 @@ def transport_gsampled(grid, optics_list, params: Params, mode: int, obs, q, wfa
     return F[:, :nout], K, G
 
 
-def _tag(params, spec_slot_idx, g, ng):
-    return (1 + spec_slot_idx * ng + g) if params.decorrelate else 0
+def _tag(params, spec, g, ng):
+    """Key tag of the (spectral point, g) solve: 1 + spec * ng + g with
+    decorrelate (spec is the band or table wavelength index), else 0."""
+    return (1 + spec * ng + g) if params.decorrelate else 0
 
 
 @dataclass

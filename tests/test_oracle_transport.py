@@ -227,3 +227,25 @@ def test_peel_off_cut_keeps_or_drops_whole_contributions():
         assert np.all(fb >= fa)
     assert np.any(runs[2][0] > runs[1][0]) and np.any(runs[1][0] > 0.0)
     np.testing.assert_allclose(runs[3][0], runs[4][0], rtol=0.0, atol=1e-20 * runs[4][0].max())
+
+
+def test_decorrelated_keys_follow_band_and_g():
+    """With decorrelate the (band, g) solve draws under the key whose high
+    word is seed_hi ^ (1 + band * ng + g): each packet equals the
+    undecorrelated run with that seed, wherever the band sits in the
+    request."""
+    g = I.make_sphere(8, 4, 5, seed=16)
+    _, tab, _ = I.make_emission_3d(8, 4, 5, nband=3, ng=2)
+    seed = 0x1234_5678_9ABC_DEF0
+    p = O.Params(n_packets=200, seed=seed, decorrelate=True, obs_phase=(0.0, 0.7))
+    r1 = O.solve_albedo(g, tab, p, spec_idx=[2, 0], keep_packets=True)
+    r2 = O.solve_albedo(g, tab, p, spec_idx=[0], keep_packets=True)
+    obs = O.albedo_obs_dirs([0.0, 0.7])
+    for si, b in enumerate([2, 0]):
+        for gi in range(2):
+            tag = 1 + b * 2 + gi
+            p0 = O.Params(n_packets=200, seed=seed ^ (tag << 32), obs_phase=(0.0, 0.7))
+            F0, _ = O.transport(g, O.ck_optics(g, tab, b, gi), p0, 0, obs)
+            assert np.array_equal(r1.extra["packets"][(si, gi)][0], F0), (b, gi)
+    assert np.array_equal(r1.extra["packets"][(1, 0)][0], r2.extra["packets"][(0, 0)][0])
+    assert not np.array_equal(r1.extra["packets"][(1, 0)][0], r1.extra["packets"][(1, 1)][0])
