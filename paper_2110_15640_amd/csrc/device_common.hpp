@@ -599,6 +599,33 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
     return face;
 }
 
+// Arithmetic of a crossing.  The exact form rounds every product and sum on
+// its own and divides correctly rounded, operation for operation as the FP64
+// oracle; the fast form, taken by the FP32-mixed transport, contracts a
+// product and a sum into one multiply-add and divides through the hardware
+// reciprocal refined by two Newton steps and a residual correction (within a
+// few ulp of the rounded quotient).
+template <bool FAST>
+__host__ __device__ __forceinline__ double wk_mad(double a, double b, double c)
+{
+    if constexpr (FAST) return fma(a, b, c);
+    else return a * b + c;
+}
+
+template <bool FAST>
+__host__ __device__ __forceinline__ double wk_div(double a, double b)
+{
+    if constexpr (FAST) {
+        double r = __builtin_amdgcn_rcp(b);
+        r = fma(r, fma(-b, r, 1.0), r);
+        r = fma(r, fma(-b, r, 1.0), r);
+        const double qt = a * r;
+        return fma(fma(-b, qt, a), r, qt);
+    } else {
+        return a / b;
+    }
+}
+
 // Move to parameter tf on face f, enter the neighbour cell and compute the
 // faces that are new to it.  Returns false when the walk left the grid
 // (k == nlay: top; k < 0: surface).
@@ -610,7 +637,9 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
 // and the equator: the linear B2 t + C = 0), so one branch-free body solves
 // that equation for every lane of a wave, whatever face kind it crosses, and
 // per-kind selects pick the roots.  The arithmetic of each kind is the same,
-// operation for operation, as in wk_shells, wk_cone and wk_plane.
+// operation for operation, as in wk_shells, wk_cone and wk_plane (in the
+// exact form; FAST: see wk_mad and wk_div).
+template <bool FAST = false>
 __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
 {
     w.t = tf;
@@ -644,7 +673,7 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
         } else {
             A = 1.0;
             B = w.B0;
-            C = w.C0 - R * R;
+            C = wk_mad<FAST>(-R, R, w.C0);
         }
     } else if (cone) {
         const int e = down ? w.j : w.j + 1;
@@ -657,9 +686,9 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
             B2 = w.dz;
             C = w.pz;
         } else {
-            A = w.dz * w.dz * c2 - (w.dx * w.dx + w.dy * w.dy) * s2;
-            B = w.pz * w.dz * c2 - (w.px * w.dx + w.py * w.dy) * s2;
-            C = w.pz * w.pz * c2 - (w.px * w.px + w.py * w.py) * s2;
+            A = wk_mad<FAST>(w.dz * w.dz, c2, -(wk_mad<FAST>(w.dx, w.dx, w.dy * w.dy) * s2));
+            B = wk_mad<FAST>(w.pz * w.dz, c2, -(wk_mad<FAST>(w.px, w.dx, w.py * w.dy) * s2));
+            C = wk_mad<FAST>(w.pz * w.pz, c2, -(wk_mad<FAST>(w.px, w.px, w.py * w.py) * s2));
             B2 = 2.0 * B;
         }
     } else {
@@ -667,26 +696,26 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
         sb = g.lon_s[e];
         cb = g.lon_c[e];
         const double nx = -sb, ny = cb;
-        const double dn = w.dx * nx + w.dy * ny;
+        const double dn = wk_mad<FAST>(w.dx, nx, w.dy * ny);
         has = west ? dn < 0.0 : dn > 0.0;
         B2 = dn;
-        C = w.px * nx + w.py * ny;
+        C = wk_mad<FAST>(w.px, nx, w.py * ny);
     }
     // one solve for every lane
     const bool quad = A != 0.0;
-    const double D = B * B - A * C;
+    const double D = wk_mad<FAST>(B, B, -(A * C));
     const double sq = sqrt(fmax(D, 0.0));
     const bool neg = cone ? B >= 0.0 : B > 0.0;  // the sign rule of each kind at B = 0
     const double q = neg ? -(B + sq) : (-B + sq);
     // one division gives the near root q / A of a quadric (a shell has A = 1)
     // or the root -C / B2 of a linear face, whichever the lane has
-    const double rd = (quad ? q : -C) / (quad ? A : B2);
+    const double rd = wk_div<FAST>(quad ? q : -C, quad ? A : B2);
     const double x0q = rd;
-    const double x1q = (quad && q != 0.0) ? C / q : INFINITY;
+    const double x1q = (quad && q != 0.0) ? wk_div<FAST>(C, q) : INFINITY;
     const double xl = (!quad && B2 != 0.0) ? rd : INFINITY;
     if (shell) {
         if (slab) {
-            const double x = fmax(-C / B2, w.t);  // (R - pz) / dz
+            const double x = fmax(wk_div<FAST>(-C, B2), w.t);  // (R - pz) / dz
             if (outward) {
                 w.tout = w.dz > 0.0 ? x : INFINITY;
                 w.tin = INFINITY;
@@ -722,8 +751,10 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
                     x0 = x0q;
                     x1 = x1q;
                 }
-                const bool ok0 = x0 < INFINITY && (tb > 0.0 ? (w.pz + x0 * w.dz > 0.0) : (w.pz + x0 * w.dz < 0.0));
-                const bool ok1 = x1 < INFINITY && (tb > 0.0 ? (w.pz + x1 * w.dz > 0.0) : (w.pz + x1 * w.dz < 0.0));
+                const bool ok0 = x0 < INFINITY && (tb > 0.0 ? (wk_mad<FAST>(x0, w.dz, w.pz) > 0.0)
+                                                            : (wk_mad<FAST>(x0, w.dz, w.pz) < 0.0));
+                const bool ok1 = x1 < INFINITY && (tb > 0.0 ? (wk_mad<FAST>(x1, w.dz, w.pz) > 0.0)
+                                                            : (wk_mad<FAST>(x1, w.dz, w.pz) < 0.0));
                 if (!ok0) x0 = INFINITY;
                 if (!ok1) x1 = INFINITY;
                 r1 = fmin(x0, x1);
@@ -746,8 +777,8 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
     double th = INFINITY;
     if (has) {
         th = fmax(xl, w.t);
-        const double hx = w.px + th * w.dx, hy = w.py + th * w.dy;
-        if (!(cb * hx + sb * hy > 0.0)) th = INFINITY;
+        const double hx = wk_mad<FAST>(th, w.dx, w.px), hy = wk_mad<FAST>(th, w.dy, w.py);
+        if (!(wk_mad<FAST>(cb, hx, sb * hy) > 0.0)) th = INFINITY;
     }
     w.tlo = west ? th : INFINITY;
     w.thi = west ? INFINITY : th;

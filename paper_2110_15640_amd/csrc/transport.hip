@@ -287,25 +287,25 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     const double t0 = L.w.t;
     const int ei = L.w.i, ej = L.w.j, ek = L.w.k;
     if (flight) {
-        if (!lost && !hit) L.tau = L.tau - a * s;
+        if (!lost && !hit) L.tau = wk_mad<MIXED>(-a, s, L.tau);
         if (cont && !lost) {
-            const double ds = hit ? L.tau / a : s;
+            const double ds = hit ? wk_div<MIXED>(L.tau, a) : s;
             double wn = L.W * exp(-aa * ds);
             L.w_abs = L.w_abs + (L.W - wn);
             L.W = wn;
         }
     } else if (!pend) {
-        L.tau = L.tau + ae * s;
+        L.tau = wk_mad<MIXED>(ae, s, L.tau);
     }
-    const bool inside = wk_cross(g, L.w, f, tf);
+    const bool inside = wk_cross<MIXED>(g, L.w, f, tf);
     if (lost || hit || pend) {
         L.ncross += L.ncw;
         L.mode = M_EVENT;
         if (hit) {  // at t0 + tau / a (tau is still the depth left on entering the cell)
-            const double ti = t0 + L.tau / a;
-            L.sx() = L.w.px + ti * L.w.dx;
-            L.sy() = L.w.py + ti * L.w.dy;
-            L.sz() = L.w.pz + ti * L.w.dz;
+            const double ti = t0 + wk_div<MIXED>(L.tau, a);
+            L.sx() = wk_mad<MIXED>(ti, L.w.dx, L.w.px);
+            L.sy() = wk_mad<MIXED>(ti, L.w.dy, L.w.py);
+            L.sz() = wk_mad<MIXED>(ti, L.w.dz, L.w.pz);
             L.set_cell(ei, ej, ek);
             L.set_sef(F_NONE);
         }
