@@ -39,16 +39,16 @@ PEAK_HBM = 8000.0  # GB/s
 # (FETCH_SIZE, WRITE_SIZE, scaled by what they read for a 1 GiB copy), per
 # (band, g) solve of this workload; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC_KERNEL_SHA = "a84443d09128666b888822c16e4681e40d460d3d25e9784324edaa11916d86a2"
-TRAFFIC_BYTES_PER_SOLVE = (149612886 * (1048576 / 524305) + 24011793 * 1.0) * 1024 / 168
+TRAFFIC_KERNEL_SHA = "12da1ef9c9a243d44c1034556529feae500e5df2d29f296c616772af915e7ff2"
+TRAFFIC_BYTES_PER_SOLVE = (150046959.375 * (1048576 / 524305.3125) + 24003375.59375 * 1.0) * 1024 / 168
 # The same for the chord optical-depth kernel of the transmission solve: bytes
 # per (chord segment, wavelength) over its launches, valid for the sources of
 # that kernel hashed below.
-TRAFFIC_K5_SHA = "e5cfb9b0efe980757e8be275c005d6eb1bd26bfe02aecf7eea079a54939e8ea3"
-TRAFFIC_K5_BYTES_PER_SEG_WL = ((469041505.25 * (1048576 / 524311.25) + 902880.0) * 1024) / (7861278 * 20064)
+TRAFFIC_K5_SHA = "6ea9567c02174f389aa9d0c01488085c5f997a63030f58e9348fee2de27d2417"
+TRAFFIC_K5_BYTES_PER_SEG_WL = ((468570912.9375 * (1048576 / 524311.3125) + 902880.0) * 1024) / (7861278 * 20064)
 # SIMD VALU busy fraction from the same counter runs (SQ_ACTIVE_INST_VALU /
 # SQ_WAVE_CYCLES x 4 waves per SIMD): the transport is bound by VALU issue
-VALU_BUSY = 0.893
+VALU_BUSY = 0.882
 
 
 def parse():
