@@ -435,7 +435,10 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
  * returns the request's own status (MCRT_ECANCELLED if cancelled).
  * mcrt_cancel removes a queued request (MCRT_EBUSY once it runs).
  * mcrt_serve_config sets the number of workers (1..16, default 3) before the
- * first submit.  Requests on one context are independent: a result is the
+ * first submit.  The workers allocate their scratch stream-ordered from the
+ * device's default memory pool, which keeps up to the budget's worth of
+ * freed memory while workers run (process-wide for that pool) and is trimmed
+ * when the context is destroyed.  Requests on one context are independent: a result is the
  * same alone and in a mix (the RNG is keyed per request and tallies are
  * reduced in a fixed order). */
 int mcrt_serve_config(mcrt_ctx* ctx, int32_t n_workers);

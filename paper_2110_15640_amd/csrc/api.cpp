@@ -1690,10 +1690,19 @@ void stop_workers(mcrt_ctx* ctx)
         ctx->queue.clear();
         ctx->q_cv.notify_all();
     }
+    const bool had_workers = !ctx->workers.empty();
     for (auto& t : ctx->workers) t.join();
     ctx->workers.clear();
     for (auto& sl : ctx->wslots) slot_destroy(ctx, *sl);
     ctx->wslots.clear();
+    // hand the memory the default pool kept for the workers back to the device
+    hipMemPool_t pool = nullptr;
+    if (had_workers && hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool) {
+        uint64_t zero = 0;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &zero);
+        (void)hipMemPoolTrimTo(pool, 0);
+    }
+    (void)hipGetLastError();
 }
 
 int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_params* p, uint64_t* ticket)
@@ -1747,6 +1756,16 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
     std::lock_guard<std::mutex> lk(ctx->q_mu);
     if (ctx->stopping) return fail(MCRT_EINVAL, "context is shutting down");
     if (ctx->workers.empty()) {
+        // The workers' stream-ordered scratch comes from the device's default
+        // pool.  Let the pool keep up to the budget's worth of freed memory,
+        // so that a request reuses what earlier ones freed instead of having
+        // it returned to the device and mapped again at every synchronisation.
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool) {
+            uint64_t keep = ctx->budget;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
         for (int w = 0; w < ctx->n_workers; ++w) {
             std::unique_ptr<Slot> sl(new Slot());
             if ((rc = slot_init(*sl))) return rc;
