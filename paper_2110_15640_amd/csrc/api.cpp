@@ -727,7 +727,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             std::lock_guard<std::mutex> mk(ctx->mem_mu);
             room = ctx->budget - std::min(ctx->budget, held_locked(ctx));
         }
-        uint64_t cap = std::min<uint64_t>(room / 2, 24ULL << 30);
+        uint64_t cap = room / 2;  // half of what the budget leaves: fewer launches, fewer drain tails
         int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
         batch = std::max(1, std::min(std::min(batch, fit), nsolve));
     }
