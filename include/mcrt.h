@@ -212,7 +212,8 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   albedo/emission, chord optical depth for transmission) with HIP events on
  *   the solve's stream; see mcrt_result.kernel_ms.
  * max_batch: (spectral point, g) solves per persistent transport launch;
- *   1 = one launch per solve, 0 = as many as the HBM budget allows.
+ *   1 = one launch per solve, 0 = as many as fit in half of what the HBM
+ *   budget leaves (a blocking solve keeps its scratch for the next one).
  * tune_ev_threshold, tune_blocks_per_cu, tune_wave_batch: launch shape of the
  *   persistent transport (lanes waiting before events are handled, 256-lane
  *   blocks per compute unit -- 1 to 3 select the spill-free register form, 4
