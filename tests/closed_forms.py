@@ -205,3 +205,107 @@ def isothermal_disk_integral(r_edges, alpha):
     v0, _ = integrate.quad(lambda b: (1.0 - math.exp(-surface_ray_tau(b, r, alpha))) * b,
                            0.0, r[0], epsabs=0.0, epsrel=1e-12, limit=200)
     return 2.0 * math.pi * (v0 + transit_integral(r, alpha))
+
+
+# ------------------------------------------ invariance (separable kernels)
+def _invariance_X(vfun, M, omega, n, X0=None):
+    """Solve the Fourier-mode invariance equation of a semi-infinite
+    atmosphere whose mode kernel is separable, p^m(mu, mu') = v(mu)^T M v(mu').
+
+    Ambartsumian's principle gives, for each mode m (azimuth convention
+    S = sum_m (2 - delta_m0) S^m cos m dphi),
+        (1/mu + 1/mu0) S^m = omega [p^m(mu, -mu0) + (1/2) int p^m S^m dmu''/mu''
+                                     + (1/2) int S^m p^m dmu'/mu' + (1/4) int int S^m p^m S^m]
+    which factors as S^m = eps omega mu mu0 / (mu + mu0) X(mu)^T M X(mu0),
+    eps = +-1 the parity of v, with the vector function
+        X(mu) = v(mu) + (omega/2) mu int_0^1 [X(mu)^T M X(mu')] v(mu') / (mu + mu') dmu'.
+    Solved on n Gauss nodes: damped fixed point, then Newton (hybr).
+    Returns (nodes, weights, X at the nodes)."""
+    mu, w = gauss01(n)
+    V = vfun(mu)
+    r = V.shape[1]
+    Wm = w[None, :] / (mu[:, None] + mu[None, :])
+
+    def kmat(X):  # K_i with X_i = v_i + K_i X_i
+        return 0.5 * omega * mu[:, None, None] * np.einsum("ij,ja,jb->iab", Wm, V, X @ M.T)
+
+    X = V.copy() if X0 is None else X0.copy()
+    for _ in range(300):
+        K = kmat(X)
+        X = 0.5 * X + 0.5 * np.stack([np.linalg.solve(np.eye(r) - K[i], V[i]) for i in range(n)])
+
+    def resid(x):
+        Xx = x.reshape(n, r)
+        return (Xx - V - np.einsum("iab,ib->ia", kmat(Xx), Xx)).ravel()
+
+    sol = optimize.root(resid, X.ravel(), method="hybr", tol=1e-14)
+    X = sol.x.reshape(n, r)
+    assert np.abs(resid(sol.x)).max() < 1e-10
+    return mu, w, X
+
+
+class InvarianceMode:
+    """S^m(mu, mu0) of one Fourier mode with a separable kernel, solved from
+    the invariance equation (see _invariance_X); omega = 1 is reached by
+    continuation from omega = 0.9 so that the physical root is followed."""
+
+    def __init__(self, vfun, M, eps, omega, n=96):
+        self.vfun, self.M, self.eps, self.omega = vfun, np.asarray(M, dtype=np.float64), eps, omega
+        X = None
+        path = [o for o in (0.9, 0.99, 0.999, 0.9999) if o < omega] + [omega]
+        for o in path:
+            self.mu, self.w, X = _invariance_X(vfun, self.M, o, n, X)
+        self.X = X
+
+    def X_at(self, m):
+        """Nystrom extension of X to arbitrary mu in (0, 1]."""
+        m = np.atleast_1d(np.asarray(m, dtype=np.float64))
+        V = self.vfun(m)
+        Wm = self.w[None, :] / (m[:, None] + self.mu[None, :])
+        K = 0.5 * self.omega * m[:, None, None] * np.einsum("ij,ja,jb->iab", Wm, self.vfun(self.mu),
+                                                           self.X @ self.M.T)
+        r = V.shape[1]
+        return np.stack([np.linalg.solve(np.eye(r) - K[i], V[i]) for i in range(len(m))])
+
+    def S(self, m, m0):
+        m = np.atleast_1d(np.asarray(m, dtype=np.float64))
+        m0 = np.atleast_1d(np.asarray(m0, dtype=np.float64))
+        Xa, Xb = self.X_at(m), self.X_at(m0)
+        return self.eps * self.omega * (m[:, None] * m0[None, :]) / (m[:, None] + m0[None, :]) * \
+            np.einsum("ia,ab,jb->ij", Xa, self.M, Xb)
+
+
+class RayleighSemiInfinite:
+    """Reflection of a semi-infinite atmosphere scattering with the scalar
+    Rayleigh phase function (3/4)(1 + cos^2 Theta), from the invariance
+    equation of its three Fourier modes:
+        p^0 = (3/8)(3 - mu^2 - mu'^2 + 3 mu^2 mu'^2)   (rank 2, even),
+        p^1 = (3/4) mu mu' sqrt(1-mu^2) sqrt(1-mu'^2)   (rank 1, odd),
+        p^2 = (3/16)(1-mu^2)(1-mu'^2)                    (rank 1, even).
+    S(mu, mu0, dphi) = S^0 + 2 S^1 cos dphi + 2 S^2 cos 2 dphi (dphi = pi is
+    backscatter); E = S / (4 pi mu0) per incident packet."""
+
+    def __init__(self, omega=1.0, n=96):
+        self.modes = [
+            InvarianceMode(lambda m: np.stack([np.ones_like(m), m * m], axis=1),
+                           0.375 * np.array([[3.0, -1.0], [-1.0, 3.0]]), 1.0, omega, n),
+            InvarianceMode(lambda m: (m * np.sqrt(np.maximum(1.0 - m * m, 0.0)))[:, None],
+                           np.array([[0.75]]), -1.0, omega, n),
+            InvarianceMode(lambda m: (1.0 - m * m)[:, None], np.array([[3.0 / 16.0]]), 1.0, omega, n),
+        ]
+
+    def S(self, m, m0, dphi):
+        out = self.modes[0].S(m, m0)
+        for k in (1, 2):
+            out = out + 2.0 * self.modes[k].S(m, m0) * math.cos(k * dphi)
+        return out
+
+    def geometric_albedo(self, n=200):
+        mu, w = gauss01(n)
+        back = np.diag(self.S(mu, mu, math.pi))
+        return 0.5 * float((w * back).sum())
+
+    def plane_albedo(self, mu0, n=200):
+        """Reflected over incident flux: (1/(2 mu0)) int_0^1 S^0(mu, mu0) dmu."""
+        mu, w = gauss01(n)
+        return float((w * self.modes[0].S(mu, np.array([mu0]))[:, 0]).sum()) / (2.0 * mu0)

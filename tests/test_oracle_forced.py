@@ -21,7 +21,7 @@ from oracle import oracle as O
 from paper_2110_15640_amd import inputs as I
 
 
-def within(x, ref, se, k=4.0, floor=1e-13):
+def within(x, ref, se, k=3.0, floor=1e-13):
     assert abs(x - ref) <= k * se + floor * abs(ref), (x, ref, se, (x - ref) / max(se, 1e-300))
 
 

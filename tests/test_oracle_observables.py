@@ -11,7 +11,7 @@ from oracle import oracle as O
 from paper_2110_15640_amd import inputs as I
 
 
-def within(x, ref, se, k=4.0, floor=0.0):
+def within(x, ref, se, k=3.0, floor=0.0):
     assert abs(x - ref) <= k * se + floor, (x, ref, se)
 
 

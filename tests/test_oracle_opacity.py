@@ -172,3 +172,75 @@ def test_vertical_tau_cut():
     tau_above = 3.3 * (g.nlay - 1 - k)
     assert np.array_equal(src.L > 0, tau_above <= 10.0 + 1e-9)
     assert src.n_emit == 4 * g.nlon * g.nlat
+
+
+def _linear_hires_table(nlam=16, a=0.5, b=0.125, p_pow=0.0):
+    """kappa(n, T, P) = (a + b n) (P / 1 bar)^p_pow: linear in the wavelength
+    index (exact in float32), so the Doppler interpolation is checked alone."""
+    Tg = np.array([800.0, 1600.0, 2400.0])
+    Pg = np.array([1e-2, 1.0, 100.0])
+    kap = ((a + b * np.arange(nlam))[:, None, None] * np.ones(3)[None, :, None] *
+           (Pg[None, None, :] ** p_pow)).astype(np.float32)
+    return I.HiresTable(1.0, 1e-5, Tg, Pg, kap, np.zeros(nlam))
+
+
+def test_doppler_interpolation_is_linear_in_kappa_at_fractional_shifts():
+    """At lambda_eff between two table wavelengths the oracle interpolates
+    kappa linearly in the (fractional) log-uniform index.  With kappa_n =
+    a + b n the result must be a + b (n + shift) exactly (to rounding);
+    interpolating ln kappa instead would give a geometric mean, off by up to
+    ~1e-2 here.  Cells sit on (T, P) nodes, also with a power law in P."""
+    g = I.make_sphere(8, 4, 3, seed=11)
+    rng = np.random.default_rng(4)
+    Tn, Pn = np.array([800.0, 1600.0, 2400.0]), np.array([1e-2, 1.0, 100.0])
+    g.T = Tn[rng.integers(0, 3, g.ncell)].astype(np.float32)
+    g.P = Pn[rng.integers(0, 3, g.ncell)].astype(np.float32)
+    nlam, a, b = 16, 0.5, 0.125
+    for p_pow in (0.0, 0.5):
+        tab = _linear_hires_table(nlam, a, b, p_pow)
+        pfac = g.P.astype(np.float64) ** p_pow
+        for frac in (-2.5, -0.3, 0.75, 3.125):
+            sh = np.full(g.ncell, frac) + rng.uniform(-0.49, 0.49, g.ncell)
+            for n in (4, 7, 11):
+                x = n + sh  # stays inside [0, nlam - 1] for these n and shifts
+                assert x.min() > 0.0 and x.max() < nlam - 1
+                got = O.hires_optics(g, tab, n, sh).a_abs
+                # exact to rounding; with the power law the float32 table
+                # entries carry ~6e-8 (a ln-kappa interpolation is off by >= 5e-4)
+                np.testing.assert_allclose(got, g.rho * (a + b * x) * pfac, rtol=1e-12 if p_pow == 0.0 else 2e-7)
+    # a uniform recession of 2.5 table steps gives the fractional shift the
+    # same way (observer at -x, speed V along +x)
+    dln = _linear_hires_table().dlnlam
+    V = 2.99792458e10 * (1.0 - math.exp(-2.5 * dln))
+    latc = 0.5 * (g.lat_edges[:-1] + g.lat_edges[1:])
+    lonc = 0.5 * (g.lon_edges[:-1] + g.lon_edges[1:])
+    kk, jj, ii = np.meshgrid(np.arange(g.nlay), np.arange(g.nlat), np.arange(g.nlon), indexing="ij")
+    th, ph = latc[jj.ravel()], lonc[ii.ravel()]
+    g.u, g.v, g.w = -V * np.sin(ph), -V * np.sin(th) * np.cos(ph), V * np.cos(th) * np.cos(ph)
+    sh = O.doppler_shift(g, np.array([-1.0, 0.0, 0.0]), dln)
+    np.testing.assert_allclose(sh, -2.5, atol=1e-6)
+    tab = _linear_hires_table()
+    np.testing.assert_allclose(O.hires_optics(g, tab, 9, sh).a_abs, g.rho * (a + b * (9 + sh)), rtol=1e-12)
+
+
+def test_doppler_interpolation_clamps_at_the_table_ends():
+    """lambda_eff outside the table takes the end value: kappa_0 below the
+    first wavelength, kappa_{nlam-1} above the last."""
+    g = I.make_sphere(8, 4, 3, seed=12)
+    g.T = np.full(g.ncell, 1600.0, np.float32)
+    g.P = np.full(g.ncell, 1.0, np.float32)
+    nlam, a, b = 16, 0.5, 0.125
+    tab = _linear_hires_table(nlam, a, b)
+    rng = np.random.default_rng(5)
+    lo = -rng.uniform(0.0, 40.0, g.ncell)
+    for n in (0, 1, 2):
+        sh = lo - n  # n + shift <= 0
+        np.testing.assert_allclose(O.hires_optics(g, tab, n, sh).a_abs, g.rho * a, rtol=1e-12)
+    hi = rng.uniform(0.0, 40.0, g.ncell)
+    for n in (nlam - 1, nlam - 2, nlam - 5):
+        sh = hi + (nlam - 1 - n)  # n + shift >= nlam - 1
+        np.testing.assert_allclose(O.hires_optics(g, tab, n, sh).a_abs, g.rho * (a + b * (nlam - 1)), rtol=1e-12)
+    # exactly on an end and one step inside: no clamping artefact
+    sh = np.zeros(g.ncell)
+    np.testing.assert_allclose(O.hires_optics(g, tab, nlam - 1, sh).a_abs, g.rho * (a + b * (nlam - 1)), rtol=1e-12)
+    np.testing.assert_allclose(O.hires_optics(g, tab, 0, sh + 0.5).a_abs, g.rho * (a + 0.5 * b), rtol=1e-12)

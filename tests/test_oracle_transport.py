@@ -12,7 +12,7 @@ from oracle import oracle as O
 from paper_2110_15640_amd import inputs as I
 
 
-def within(x, ref, se, k=4.0, floor=0.0):
+def within(x, ref, se, k=3.0, floor=0.0):
     assert abs(x - ref) <= k * se + floor, (x, ref, se, (x - ref) / max(se, 1e-300))
 
 
@@ -249,3 +249,54 @@ def test_decorrelated_keys_follow_band_and_g():
             assert np.array_equal(r1.extra["packets"][(si, gi)][0], F0), (b, gi)
     assert np.array_equal(r1.extra["packets"][(1, 0)][0], r2.extra["packets"][(0, 0)][0])
     assert not np.array_equal(r1.extra["packets"][(1, 0)][0], r1.extra["packets"][(1, 1)][0])
+
+
+@pytest.fixture(scope="module")
+def ray_inv():
+    return CF.RayleighSemiInfinite(1.0)
+
+
+def test_invariance_solver_against_doubling_and_h_function(dbl_ray, ray_inv):
+    """The invariance-equation solver used for the conservative Rayleigh pins
+    is itself pinned: at omega = 0.99 every Fourier mode equals adding-doubling
+    (an independent algorithm); with the isotropic kernel at omega = 1 it
+    reproduces Chandrasekhar's H-function form; at omega = 1 the plane albedo
+    is 1 (no absorption)."""
+    D = dbl_ray
+    R99 = CF.RayleighSemiInfinite(0.99)
+    for m in range(3):
+        S_inv = R99.modes[m].S(D.mu, D.mu)
+        S_dbl = 4.0 * D.mu[:, None] * D.mu[None, :] * D.rho[m]
+        assert np.abs(S_inv - S_dbl).max() <= 1e-5 * np.abs(S_dbl).max()
+    assert R99.geometric_albedo() == pytest.approx(D.geometric_albedo(), rel=1e-5)
+    iso = CF.InvarianceMode(lambda m: np.ones((len(m), 1)), np.array([[1.0]]), 1.0, 1.0)
+    S_h, _ = CF.isotropic_semi_infinite(1.0)
+    m = np.array([0.05, 0.3, 0.7, 1.0])
+    np.testing.assert_allclose(iso.S(m, m), S_h(m[:, None], m[None, :]), rtol=1e-7)
+    for mu0 in (1.0, 0.6, 0.15):
+        assert ray_inv.plane_albedo(mu0) == pytest.approx(1.0, abs=1e-6)
+
+
+def test_semi_infinite_conservative_rayleigh_normal_incidence(ray_inv):
+    """omega = 1 scalar Rayleigh, tau = 8192, mu0 = 1: only the azimuth-mean
+    mode survives and E(mu) = S^0(mu, 1)/(4 pi).  The values at mu = 1, 0.8,
+    0.49, 0.2 (4.4067, 3.3541, 1.8604, 0.6555) are the reference."""
+    g, t = I.make_homogeneous_slab(8192.0, 1.0, rayleigh=True)
+    mus = [1.0, 0.8, 0.49, 0.2]
+    S0 = ray_inv.modes[0].S(np.array(mus), np.array([1.0]))[:, 0]
+    np.testing.assert_allclose(S0, [4.4067, 3.3541, 1.8604, 0.6555], atol=2e-4)
+    obs = [slab_obs(m, 0.3 * q) for q, m in enumerate(mus)]
+    r = run(g, t, dict(n_packets=12000, mu0=1.0, seed=14), obs)
+    for o, m in enumerate(mus):
+        E = float(S0[o]) / (4.0 * math.pi)
+        within(r.value[0, o] / math.pi, E, r.stderr[0, o] / math.pi, floor=2e-4 * E)
+
+
+def test_semi_infinite_conservative_rayleigh_geometric_albedo(ray_inv):
+    """omega = 1 scalar Rayleigh: A_g = (1/2) int S(mu, mu; pi) dmu = 0.75176
+    (the unpolarised value; the polarised problem's 0.80 does not apply)."""
+    Ag = ray_inv.geometric_albedo()
+    assert Ag == pytest.approx(0.75176, abs=2e-5)
+    g, t = I.make_homogeneous_slab(8192.0, 1.0, rayleigh=True)
+    r = run(g, t, dict(n_packets=30000, seed=15))
+    within(r.value[0, 0], Ag, r.stderr[0, 0], floor=2e-4)

@@ -66,7 +66,7 @@ def test_single_scattering_tthg_slab():
         P = a * hg(c, gc) + (1 - a) * hg(c, -gc / 2)
         E = om_e * P / (4 * math.pi) * mu * (1 - math.exp(-tau_e * (1 / mu0 + 1 / mu))) / (mu + mu0)
         got, se = r.value[0, o] / math.pi, r.stderr[0, o] / math.pi
-        assert abs(got - E) <= 4.0 * se, (o, got, E, se)
+        assert abs(got - E) <= 3.0 * se, (o, got, E, se)
 
 
 def test_zero_asymmetry_reduces_to_isotropic_hg():
