@@ -387,6 +387,32 @@ int mcrt_solve_emission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
 int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id,
                             const mcrt_solve_params* params, mcrt_result* result);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  mode = MCRT_MODE_ALBEDO or MCRT_MODE_EMISSION; otherwise the
+ * same arguments, results and errors as mcrt_solve_albedo /
+ * mcrt_solve_emission, and the same values bit for bit (the batch size does
+ * not change a result).  The solve's scratch (optics, emission sources,
+ * packet rows, tallies) is carved from one fixed device array of
+ * MCRT_NOALLOC_SCRATCH_BYTES (256 MiB) that the library holds on every GPU
+ * it runs on until the process ends (its address is looked up when a
+ * context is created), so the call itself allocates no device or pinned
+ * memory; as many (spectral point, g) solves share a transport launch as fit
+ * in it (params.max_batch caps that).  The caller still provides resident
+ * grids and tables and the host result arrays.  The array is shared by all
+ * contexts on a GPU and keeps the last call's contents (each call clears
+ * what must start at zero).  Calls that overlapped on one GPU would race on
+ * it, so the library serialises them within a process: a call waits for the
+ * previous one, which returns only when its results are copied out (each
+ * process holds its own copy of the array).  Errors: EINVAL for
+ * another mode, params.graph != 0, or when one launch of a single solve
+ * (one band with g-ordinate sampling) needs more than the fixed scratch
+ * (e.g. n_packets too large: each packet's row takes (n_obs + 11) * 8 B);
+ * otherwise as for the blocking solves. */
+#define MCRT_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int mcrt_solve_noalloc(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
+                       const mcrt_solve_params* params, mcrt_result* result);
+
 /* Batched solves on grids of uneven size: n_items albedo / emission requests,
  * each with its own (spherical) grid, correlated-k table, spectral points and
  * packet count, share the common params (observers, scattering, absorption,

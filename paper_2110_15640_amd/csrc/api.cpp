@@ -85,6 +85,10 @@ struct Slot {
     std::vector<hipEvent_t> prof_ev;  // pairs around timed launches
     std::map<std::string, DevBuf> scratch;  // grow-only, by role
     bool stream_ordered = false;  // serving slots allocate with hipMallocAsync
+    // Fixed arena (the allocation-free solve): scratch is carved from it in
+    // order, from offset 0 at every call, instead of allocated.
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
 };
 
 struct Request;
@@ -109,6 +113,22 @@ constexpr size_t kMaxGraphs = 16;
 
 }  // namespace
 
+namespace {
+
+// Scratch of the allocation-free solve (mcrt_solve_noalloc): one fixed array
+// per GPU the library runs on, held until the process ends and shared by
+// every context on that GPU.  Host code never passes the array's name to the
+// device: its address on each GPU comes from hipGetSymbolAddress (taken once
+// per device when a context is created) and only that address is used.
+constexpr size_t kNoallocBytes = MCRT_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoallocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+std::mutex g_noalloc_mu;                     // guards g_noalloc_ptr
+void* g_noalloc_ptr[kNoallocDevices] = {};   // device address of `scratch` per GPU
+std::mutex g_noalloc_run[kNoallocDevices];   // one allocation-free solve per GPU at a time
+
+}  // namespace
+
 struct mcrt_ctx {
     int device = 0;
     int n_cu = 256;
@@ -118,6 +138,7 @@ struct mcrt_ctx {
     std::mutex mu;      // grids, opacs, refs
     std::mutex main_mu; // blocking solves on the main slot
     Slot main;
+    Slot na;            // allocation-free solves: the device's fixed scratch array
     std::map<int32_t, std::unique_ptr<GridRes>> grids;
     std::map<int32_t, std::unique_ptr<OpacRes>> opacs;
     int32_t next_grid = 1, next_opac = 1;
@@ -205,8 +226,17 @@ void dev_free(mcrt_ctx* ctx, DevBuf& b, hipStream_t ordered = nullptr)
 }
 
 // Scratch buffer of at least `bytes` under `name` in slot `sl` (grow-only).
-int scratch(mcrt_ctx* ctx, Slot& sl, hipStream_t st, const char* name, size_t bytes, void** out)
+int slot_scratch(mcrt_ctx* ctx, Slot& sl, hipStream_t st, const char* name, size_t bytes, void** out)
 {
+    if (sl.arena) {
+        const size_t at = (sl.arena_off + 255) & ~(size_t)255;
+        if (at > sl.arena_cap || bytes > sl.arena_cap - at)
+            return fail(MCRT_EINVAL, "scratch '%s' (%zu bytes) does not fit in the fixed scratch of %zu bytes", name,
+                        bytes, sl.arena_cap);
+        *out = sl.arena + at;
+        sl.arena_off = at + bytes;
+        return MCRT_OK;
+    }
     DevBuf& b = sl.scratch[name];
     if (b.bytes < bytes) {
         if (b.p) {
@@ -717,8 +747,46 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     const size_t row_b = (size_t)N * prow * sizeof(double);
     // with g-ordinate sampling a band's packets (one range) serve its ng solves
     const size_t per_solve = opt_b + src_b + (gs ? row_b / ng : row_b);
+    const int chunks = reduce_rows_chunks(N);
+    const size_t cf_n = p->contrib ? (size_t)ns * no * 2 * ncell : 0;  // [spec][observer][2][cell]
+    const int npix = p->image_npix;
+    const size_t img_n = (size_t)ns * no * npix * npix;  // [spec][observer][row][column]
     int batch;
-    if (sl.stream_ordered) {
+    if (sl.arena) {
+        // the largest batch whose scratch, carved below in this order, fits the arena
+        auto carved = [&](int b) {
+            size_t t = 0;
+            auto add = [&t](size_t x) { t = ((t + 255) & ~(size_t)255) + x; };
+            add(sizeof(double) * 5 * (size_t)ncell * b);
+            if (mixed) add(sizeof(float) * 5 * (size_t)ncell * b);
+            add(row_b * (size_t)(gs ? b / ng : b));
+            add(sizeof(double) * (size_t)nsolve * row_w);
+            add(sizeof(double) * (size_t)b * chunks * pw);
+            add(sizeof(SolveDev) * (size_t)b);
+            add(sizeof(PrepSlot) * (size_t)b);
+            add(sizeof(unsigned long long) * kXcds);
+            if (mode == MCRT_MODE_EMISSION) {
+                add(src_b * b);
+                add(sizeof(double) * prep_scratch_doubles(ncell, b));
+            }
+            if (op->kind == MCRT_OPAC_HIRES) add(sizeof(double) * (size_t)ncell);
+            if (cf_n) add(sizeof(double) * cf_n);
+            if (img_n) add(sizeof(double) * img_n);
+            return t;
+        };
+        const int step = gs ? ng : 1;  // whole bands per launch with g-ordinate sampling
+        int lo = step, hi = std::max(step, std::min(p->max_batch > 0 ? p->max_batch : nsolve, nsolve) / step * step);
+        hi = std::min(hi, kMaxSolvesPerLaunch / step * step);
+        if (carved(lo) > sl.arena_cap)
+            return fail(MCRT_EINVAL, "one launch of this solve needs %zu bytes of scratch, more than the fixed %zu",
+                        carved(lo), sl.arena_cap);
+        while (lo < hi) {
+            const int mid = (lo / step + (hi / step - lo / step + 1) / 2) * step;
+            if (carved(mid) <= sl.arena_cap) lo = mid;
+            else hi = mid - step;
+        }
+        batch = lo;
+    } else if (sl.stream_ordered) {
         batch = serving_batch(ctx, p->max_batch, nsolve, per_solve);  // as admitted
     } else {
         batch = p->max_batch > 0 ? p->max_batch : nsolve;
@@ -733,32 +801,28 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
     }
     batch = std::min(batch, kMaxSolvesPerLaunch);
     if (gs) batch = std::max(ng, batch / ng * ng);  // whole bands per launch
-    const int chunks = reduce_rows_chunks(N);
     void *v_opt, *v_optf = nullptr, *v_src = nullptr, *v_rows, *v_sums, *v_part, *v_ps = nullptr,
                  *v_shift = nullptr, *v_solves, *v_slots, *v_ctr;
-    if ((rc = scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * batch, &v_opt))) return rc;
-    if (mixed && (rc = scratch(ctx, sl, st, "optics_f32", sizeof(float) * 5 * (size_t)ncell * batch, &v_optf)))
+    if ((rc = slot_scratch(ctx, sl, st, "optics", sizeof(double) * 5 * (size_t)ncell * batch, &v_opt))) return rc;
+    if (mixed && (rc = slot_scratch(ctx, sl, st, "optics_f32", sizeof(float) * 5 * (size_t)ncell * batch, &v_optf)))
         return rc;
-    if ((rc = scratch(ctx, sl, st, "rows", row_b * (gs ? batch / ng : batch), &v_rows))) return rc;
-    if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
-    if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
-    if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
-    if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * (size_t)batch, &v_slots))) return rc;
-    if ((rc = scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "rows", row_b * (gs ? batch / ng : batch), &v_rows))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "row_part", sizeof(double) * (size_t)batch * chunks * pw, &v_part))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "solves", sizeof(SolveDev) * (size_t)batch, &v_solves))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * (size_t)batch, &v_slots))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
     if (mode == MCRT_MODE_EMISSION) {
-        if ((rc = scratch(ctx, sl, st, "sources", src_b * batch, &v_src))) return rc;
-        if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * prep_scratch_doubles(ncell, batch), &v_ps)))
+        if ((rc = slot_scratch(ctx, sl, st, "sources", src_b * batch, &v_src))) return rc;
+        if ((rc = slot_scratch(ctx, sl, st, "prep_scratch", sizeof(double) * prep_scratch_doubles(ncell, batch), &v_ps)))
             return rc;
     }
     if (op->kind == MCRT_OPAC_HIRES)
-        if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
-    void* v_cf = nullptr;  // contribution functions [spec][observer][2][cell]
-    const size_t cf_n = p->contrib ? (size_t)ns * no * 2 * ncell : 0;
-    if (p->contrib && (rc = scratch(ctx, sl, st, "contrib", sizeof(double) * cf_n, &v_cf))) return rc;
-    void* v_img = nullptr;  // images [spec][observer][row][column]
-    const int npix = p->image_npix;
-    const size_t img_n = (size_t)ns * no * npix * npix;
-    if (npix && (rc = scratch(ctx, sl, st, "image", sizeof(double) * img_n, &v_img))) return rc;
+        if ((rc = slot_scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+    void* v_cf = nullptr;  // contribution functions
+    if (p->contrib && (rc = slot_scratch(ctx, sl, st, "contrib", sizeof(double) * cf_n, &v_cf))) return rc;
+    void* v_img = nullptr;  // images
+    if (npix && (rc = slot_scratch(ctx, sl, st, "image", sizeof(double) * img_n, &v_img))) return rc;
     double* sums = (double*)v_sums;
 
     BatchArgs A{};
@@ -1084,19 +1148,19 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     const int kSlot = 64;
     const int nslot_max = std::min(kSlot, nrow);
     void *v_cnt, *v_off, *v_b, *v_ok, *v_alpha, *v_part, *v_sums, *v_shift = nullptr, *v_nl = nullptr;
-    if ((rc = scratch(ctx, sl, st, "chord_cnt", sizeof(int) * (size_t)nch, &v_cnt))) return rc;
-    if ((rc = scratch(ctx, sl, st, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
-    if ((rc = scratch(ctx, sl, st, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
-    if ((rc = scratch(ctx, sl, st, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
-    if ((rc = scratch(ctx, sl, st, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_cnt", sizeof(int) * (size_t)nch, &v_cnt))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
     int tblocks = chord_tau_blocks(nch);
-    if ((rc = scratch(ctx, sl, st, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
-    if ((rc = scratch(ctx, sl, st, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
     void* v_tp = nullptr;
     if (op->kind == MCRT_OPAC_HIRES) {
-        if ((rc = scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
-        if ((rc = scratch(ctx, sl, st, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
-        if ((rc = scratch(ctx, sl, st, "cell_tp", sizeof(CellTP) * (size_t)ncell, &v_tp))) return rc;
+        if ((rc = slot_scratch(ctx, sl, st, "shift", sizeof(double) * (size_t)ncell, &v_shift))) return rc;
+        if ((rc = slot_scratch(ctx, sl, st, "nlist", sizeof(int) * (size_t)ns, &v_nl))) return rc;
+        if ((rc = slot_scratch(ctx, sl, st, "cell_tp", sizeof(CellTP) * (size_t)ncell, &v_tp))) return rc;
     }
     const uint32_t tag = 0;  // chords are common to all spectral points
     const bool prof = p->profile != 0;
@@ -1112,8 +1176,8 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     HIPTRY(hipStreamSynchronize(st));
     res->n_segments = nseg;
     void *v_sc, *v_sl;
-    if ((rc = scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
-    if ((rc = scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
     const LimbDark ld{p->ld_law, p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->r_star};
     launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
                       (double*)v_b, (int*)v_ok, ld, st);
@@ -1269,14 +1333,14 @@ int solve_batch(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int n_items, co
     for (auto& L : launches) max_prep = std::max<uint64_t>(max_prep, prep_scratch_doubles(max_ncell, L.second - L.first));
     const int chunks = reduce_rows_chunks(max_n);
     void *v_arena, *v_sums, *v_part, *v_solves, *v_slots, *v_ctr, *v_grids, *v_ps;
-    if ((rc = scratch(ctx, sl, st, "batch_arena", max_bytes, &v_arena))) return rc;
-    if ((rc = scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
-    if ((rc = scratch(ctx, sl, st, "row_part", sizeof(double) * max_slots * chunks * pw, &v_part))) return rc;
-    if ((rc = scratch(ctx, sl, st, "solves", sizeof(SolveDev) * max_slots, &v_solves))) return rc;
-    if ((rc = scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * max_slots, &v_slots))) return rc;
-    if ((rc = scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
-    if ((rc = scratch(ctx, sl, st, "grid_table", sizeof(GridDev) * grids.size(), &v_grids))) return rc;
-    if ((rc = scratch(ctx, sl, st, "prep_scratch", sizeof(double) * max_prep, &v_ps))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "batch_arena", max_bytes, &v_arena))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "sums", sizeof(double) * (size_t)nsolve * row_w, &v_sums))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "row_part", sizeof(double) * max_slots * chunks * pw, &v_part))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "solves", sizeof(SolveDev) * max_slots, &v_solves))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "prep_slots", sizeof(PrepSlot) * max_slots, &v_slots))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "dispenser", sizeof(unsigned long long) * kXcds, &v_ctr))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "grid_table", sizeof(GridDev) * grids.size(), &v_grids))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "prep_scratch", sizeof(double) * max_prep, &v_ps))) return rc;
     double* sums = (double*)v_sums;
     std::vector<GridDev> hgrids;
     for (GridRes* g : grids) hgrids.push_back(g->dev);
@@ -1838,6 +1902,19 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
         ctx->n_cu = prop.multiProcessorCount;
     int rc = slot_init(ctx->main);
     if (rc) return rc;
+    if ((rc = slot_init(ctx->na))) return rc;
+    if (device < kNoallocDevices) {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_ptr[device]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(MCRT_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            g_noalloc_ptr[device] = ptr;
+        }
+        ctx->na.arena = (char*)g_noalloc_ptr[device];
+        ctx->na.arena_cap = kNoallocBytes;
+    }
     *out = ctx.release();
     return MCRT_OK;
 }
@@ -1849,6 +1926,7 @@ void mcrt_destroy(mcrt_ctx* ctx)
     stop_workers(ctx);
     drop_graphs(ctx, 0, 0);
     slot_destroy(ctx, ctx->main);
+    slot_destroy(ctx, ctx->na);
     for (auto& kv : ctx->grids)
         for (auto& b : kv.second->bufs) dev_free(ctx, b);
     for (auto& kv : ctx->opacs)
@@ -2222,6 +2300,23 @@ int mcrt_solve_transmission(mcrt_ctx* ctx, int32_t grid_id, int32_t opac_id, con
 {
     if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
     return blocking_solve(ctx, MCRT_MODE_TRANSMISSION, grid_id, opac_id, params, result);
+}
+
+int mcrt_solve_noalloc(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
+                       const mcrt_solve_params* params, mcrt_result* result)
+{
+    if (!ctx) return fail(MCRT_EINVAL, "ctx is NULL");
+    if (mode != MCRT_MODE_ALBEDO && mode != MCRT_MODE_EMISSION)
+        return fail(MCRT_EINVAL, "the allocation-free solve takes MCRT_MODE_ALBEDO or MCRT_MODE_EMISSION");
+    if (!params) return fail(MCRT_EINVAL, "params is NULL");
+    if (params->graph) return fail(MCRT_EINVAL, "graph (recorded solves keep pinned host tables) is not available "
+                                                "to the allocation-free solve");
+    if (!ctx->na.arena) return fail(MCRT_EINVAL, "device %d has no fixed scratch", ctx->device);
+    std::lock_guard<std::mutex> lk(g_noalloc_run[ctx->device]);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    ctx->na.arena_off = 0;
+    return solve_packets(ctx, ctx->na, ctx->na.stream, grid_id, opac_id, params, result, mode);
 }
 
 }  // extern "C"

@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
     L.mcrt_default_params.restype = None
     for nm in ("mcrt_solve_albedo", "mcrt_solve_emission", "mcrt_solve_transmission"):
         getattr(L, nm).argtypes = [_vp, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
+    L.mcrt_solve_noalloc.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(Result)]
     L.mcrt_solve_batch.argtypes = [_vp, _i32, ctypes.POINTER(BatchItem), ctypes.POINTER(SolveParams),
                                    ctypes.POINTER(Result)]
     L.mcrt_autotune.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(SolveParams), ctypes.POINTER(_dbl)]
@@ -385,6 +386,18 @@ class Context:
         ns = table.nband if hasattr(table, "g_weights") else table.nlam
         ng = table.ng if hasattr(table, "g_weights") else 1
         return self._solve(load().mcrt_solve_emission, gid, oid, ns, lambda p: p.n_obs, ng, kw)
+
+    def solve_noalloc(self, mode: str, gid, oid, table, **kw):
+        """mcrt_solve_noalloc: an albedo or emission solve whose scratch is the
+        library's fixed per-device array (no device allocation in the call)."""
+        m = MODES[mode]
+        if mode == "albedo":
+            return self._solve(lambda h, g, o, p, r: load().mcrt_solve_noalloc(h, m, g, o, p, r), gid, oid,
+                               table.nband, lambda p: max(p.n_obs, 1), table.ng, kw)
+        ns = table.nband if hasattr(table, "g_weights") else table.nlam
+        ng = table.ng if hasattr(table, "g_weights") else 1
+        return self._solve(lambda h, g, o, p, r: load().mcrt_solve_noalloc(h, m, g, o, p, r), gid, oid, ns,
+                           lambda p: p.n_obs, ng, kw)
 
     def solve_transmission(self, gid, oid, table, **kw):
         ns = table.nband if hasattr(table, "g_weights") else table.nlam
