@@ -117,7 +117,12 @@ typedef struct {
     int32_t flags;
 } mcrt_grid_desc;
 
-int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* desc, int32_t* grid_id);
+/* stream: hipStream_t (NULL = the null stream) on which the copies and the
+ * device check of borrowed arrays run, after the caller's earlier work on
+ * it; the call returns when they are done.  When the budget is short and no
+ * blocking solve is running, the scratch the blocking solves keep (see
+ * params.max_batch) is released first. */
+int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* desc, void* stream, int32_t* grid_id);
 int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id);
 
 /* Opacity table (Sect. 7).  kind = MCRT_OPAC_CK: pre-mixed k-table
@@ -145,7 +150,9 @@ typedef struct {
     const double* k_ray;
 } mcrt_opacity_desc;
 
-int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* desc, int32_t* opac_id);
+/* stream: as for mcrt_grid_upload (the re-laid-out table is copied on it and
+ * the call returns when the copy is done). */
+int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* desc, void* stream, int32_t* opac_id);
 int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
 
 /* Solve parameters.  Fill with mcrt_default_params() first.
@@ -213,7 +220,9 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   the solve's stream; see mcrt_result.kernel_ms.
  * max_batch: (spectral point, g) solves per persistent transport launch;
  *   1 = one launch per solve, 0 = as many as fit in half of what the HBM
- *   budget leaves (a blocking solve keeps its scratch for the next one).
+ *   budget leaves (a blocking solve keeps its scratch for the next one,
+ *   until an upload or a served request needs the room while no blocking
+ *   solve runs).
  * tune_ev_threshold, tune_blocks_per_cu, tune_wave_batch: launch shape of the
  *   persistent transport (lanes waiting before events are handled, 256-lane
  *   blocks per compute unit -- 1 to 3 select the spill-free register form, 4
@@ -451,21 +460,27 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
  * Worker threads, each with its own HIP stream, admit queued requests in
  * arrival order whenever the context's HBM budget covers the request's
  * device scratch (estimated at submit), so requests run concurrently on the
- * device while grids and tables stay resident.  A request whose scratch
+ * device while grids and tables stay resident.  A served request reaches
+ * the device as persistent launches of at most 2^22 packets, each taking the
+ * device's blocks shared among the requests running when it starts, so the
+ * launches of concurrent requests are resident together.  Scratch that
+ * blocking solves keep for their next call is released when it stands in
+ * the way of a request and no blocking solve runs.  A request whose scratch
  * alone exceeds the budget is rejected at submit with MCRT_EBUDGET; one
  * that no longer fits when no other request is running (the memory went to
- * uploads or blocking solves after it was submitted) fails with MCRT_EBUDGET
- * instead of holding up the queue.
+ * uploads, or to a blocking solve still running, after it was submitted)
+ * fails with MCRT_EBUDGET instead of holding up the queue.
  * mcrt_poll sets *done to 1 once the request finished, failed or was
  * cancelled.  mcrt_wait blocks until then, copies the results into the
  * caller's arrays (shaped as for the blocking solve), forgets the ticket and
  * returns the request's own status (MCRT_ECANCELLED if cancelled).
  * mcrt_cancel removes a queued request (MCRT_EBUSY once it runs).
  * mcrt_serve_config sets the number of workers (1..16, default 3) before the
- * first submit.  The workers allocate their scratch stream-ordered from the
- * device's default memory pool, which keeps up to the budget's worth of
- * freed memory while workers run (process-wide for that pool) and is trimmed
- * when the context is destroyed.  Requests on one context are independent: a result is the
+ * first submit.  The workers allocate their scratch stream-ordered from a
+ * memory pool of the context, which keeps up to the budget's worth of freed
+ * memory while workers run (trimmed first when a blocking allocation would
+ * otherwise take the process past the budget) and is destroyed with the
+ * context.  Requests on one context are independent: a result is the
  * same alone and in a mix (the RNG is keyed per request and tallies are
  * reduced in a fixed order). */
 int mcrt_serve_config(mcrt_ctx* ctx, int32_t n_workers);

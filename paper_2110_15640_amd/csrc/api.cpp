@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -159,6 +160,8 @@ struct mcrt_ctx {
     uint64_t next_ticket = 1;
     int n_workers = 3;
     bool stopping = false;
+    std::atomic<int> n_running{0};   // served requests on the device now
+    hipMemPool_t pool = nullptr;     // the workers' stream-ordered scratch (private to the context)
 };
 
 namespace {
@@ -189,6 +192,7 @@ uint64_t held_locked(const mcrt_ctx* ctx)
 int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out, hipStream_t ordered = nullptr)
 {
     if (bytes == 0) bytes = 8;
+    bool trim = false;
     {
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
         if (!ordered && held_locked(ctx) + bytes > ctx->budget)
@@ -197,9 +201,20 @@ int dev_alloc(mcrt_ctx* ctx, size_t bytes, DevBuf& out, hipStream_t ordered = nu
                         (unsigned long long)ctx->budget);
         ctx->in_use += bytes;
         if (ordered) ctx->served += bytes;
+        // memory the workers' pool keeps after frees is not in in_use: hand it
+        // back to the device before a blocking allocation would go past the budget
+        if (!ordered && ctx->pool) {
+            uint64_t reserved = 0, used = 0;
+            if (hipMemPoolGetAttribute(ctx->pool, hipMemPoolAttrReservedMemCurrent, &reserved) == hipSuccess &&
+                hipMemPoolGetAttribute(ctx->pool, hipMemPoolAttrUsedMemCurrent, &used) == hipSuccess)
+                trim = ctx->in_use + (reserved > used ? reserved - used : 0) > ctx->budget;
+        }
     }
+    if (trim) (void)hipMemPoolTrimTo(ctx->pool, 0);
     void* p = nullptr;
-    hipError_t e = ordered ? hipMallocAsync(&p, bytes, ordered) : hipMalloc(&p, bytes);
+    hipError_t e = ordered ? (ctx->pool ? hipMallocFromPoolAsync(&p, bytes, ctx->pool, ordered)
+                                        : hipMallocAsync(&p, bytes, ordered))
+                           : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
@@ -284,14 +299,15 @@ void slot_destroy(mcrt_ctx* ctx, Slot& sl)
 }
 
 template <typename T>
-int upload(mcrt_ctx* ctx, std::vector<DevBuf>& bufs, size_t& total, const T* host, size_t n, T** dev)
+int upload(mcrt_ctx* ctx, std::vector<DevBuf>& bufs, size_t& total, const T* host, size_t n, T** dev,
+           hipStream_t st)
 {
     DevBuf b;
     int rc = dev_alloc(ctx, n * sizeof(T), b);
     if (rc) return rc;
     bufs.push_back(b);
     total += b.bytes;
-    HIPTRY(hipMemcpy(b.p, host, n * sizeof(T), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpyAsync(b.p, host, n * sizeof(T), hipMemcpyHostToDevice, st));
     *dev = (T*)b.p;
     return MCRT_OK;
 }
@@ -369,7 +385,7 @@ int validate_grid(const mcrt_grid_desc* d)
 
 // Borrowed per-cell arrays: device memory of the context's device, whose
 // values pass the same checks as a host grid's (run on the device).
-int check_borrowed(mcrt_ctx* ctx, const mcrt_grid_desc* d, size_t n)
+int check_borrowed(mcrt_ctx* ctx, const mcrt_grid_desc* d, size_t n, hipStream_t st)
 {
     const void* ptrs[9] = {d->T, d->P, d->rho, d->u, d->v, d->w, d->cld_ksca, d->cld_kabs, d->cld_g};
     for (const void* p : ptrs) {
@@ -381,15 +397,18 @@ int check_borrowed(mcrt_ctx* ctx, const mcrt_grid_desc* d, size_t n)
             return fail(MCRT_EINVAL, "borrowed grid arrays must be device memory of device %d", ctx->device);
         }
     }
+    // on the caller's stream: the check reads the arrays after the caller's
+    // earlier work on that stream (e.g. the kernels that wrote them)
     int* bad = nullptr;
     HIPTRY(hipMalloc(&bad, sizeof(int)));
     int h = 0;
-    hipError_t e = hipMemcpy(bad, &h, sizeof(int), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyAsync(bad, &h, sizeof(int), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        launch_check_cells(d->T, d->P, d->rho, d->u, d->v, d->w, d->cld_ksca, d->cld_kabs, d->cld_g, n, bad, nullptr);
+        launch_check_cells(d->T, d->P, d->rho, d->u, d->v, d->w, d->cld_ksca, d->cld_kabs, d->cld_g, n, bad, st);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemcpy(&h, bad, sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(bad);
     HIPTRY(e);
     if (h & 1) return fail(MCRT_EINVAL, "T must be finite and > 0");
@@ -647,6 +666,22 @@ void drop_graphs(mcrt_ctx* ctx, int32_t gid, int32_t oid)
     }
 }
 
+// Blocking solves keep their scratch in the main slot for the next one.
+// When it stands in the way of an upload or a served request, and no blocking
+// solve is running, it is released (with the recorded solves, which bake its
+// addresses in).  Returns whether anything was released.  Never called with
+// main_mu held.
+bool reclaim_main(mcrt_ctx* ctx)
+{
+    std::unique_lock<std::mutex> lk(ctx->main_mu, std::try_to_lock);
+    if (!lk.owns_lock() || ctx->main.scratch.empty()) return false;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->main.stream);
+    drop_graphs(ctx, 0, 0);
+    release_scratch(ctx, ctx->main);
+    return true;
+}
+
 int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -664,13 +699,27 @@ int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
 }
 
 // Solves per persistent launch for a serving request: a fixed share of the
-// budget, so that the admission estimate and the allocation agree.
-int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve)
+// budget, so that the admission estimate and the allocation agree, and at
+// most kServeLaunchPackets packets, so that a long request reaches the device
+// as a sequence of short launches between which other requests' launches
+// are dispatched (and each launch's share of the device is chosen anew).
+constexpr uint64_t kServeLaunchPackets = 1ull << 22;
+int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve, uint64_t packets_per_solve)
 {
     uint64_t cap = std::min<uint64_t>(ctx->budget / 8, 24ULL << 30);
     int batch = max_batch > 0 ? max_batch : nsolve;
     int fit = (int)std::max<uint64_t>(1, cap / std::max<uint64_t>(per_solve, 1));
-    return std::max(1, std::min(std::min(batch, fit), nsolve));
+    int short_launch = (int)std::max<uint64_t>(1, kServeLaunchPackets / std::max<uint64_t>(packets_per_solve, 1));
+    return std::max(1, std::min(std::min(std::min(batch, fit), short_launch), nsolve));
+}
+
+// Persistent blocks of a served launch: the device's blocks shared among the
+// requests running now, so that the launches of concurrent requests are
+// resident together instead of queueing behind one whole-device grid.
+int serving_blocks(mcrt_ctx* ctx, int bpc)
+{
+    const int k = std::max(1, ctx->n_running.load());
+    return std::max(ctx->n_cu, ctx->n_cu * bpc / k);
 }
 
 // Sky-plane axes of observer o for images: vertical e_v = z projected on the
@@ -787,7 +836,7 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         }
         batch = lo;
     } else if (sl.stream_ordered) {
-        batch = serving_batch(ctx, p->max_batch, nsolve, per_solve);  // as admitted
+        batch = serving_batch(ctx, p->max_batch, nsolve, per_solve, gs ? N / ng + 1 : N);  // as admitted
     } else {
         batch = p->max_batch > 0 ? p->max_batch : nsolve;
         uint64_t room;
@@ -1011,7 +1060,8 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
             launch_init_dispensers(A.counter, A.total, st);
             launch_births(g->dev, A, false, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt], st));
-            launch_transport_persistent(g->dev, A, mixed, false, pblocks, bpc, st);
+            launch_transport_persistent(g->dev, A, mixed, false, sl.stream_ordered ? serving_blocks(ctx, bpc) : pblocks,
+                                        bpc, st);
             if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * bt + 1], st));
             double* dump = p->packet_dump ? p->packet_dump + (size_t)(gs ? s0 / ng : s0) * N * no : nullptr;
             launch_reduce_rows(A, nullptr, nb, (double*)v_part, chunks, sums + (size_t)s0 * row_w, row_w, dump, st);
@@ -1665,7 +1715,9 @@ uint64_t estimate_bytes(mcrt_ctx* ctx, const Request& r, GridRes* g, OpacRes* op
     const uint64_t opt_b = ncell * 5 * (8 + (mixed ? 4 : 0));
     const uint64_t src_b = r.mode == MCRT_MODE_EMISSION ? ncell * 16 : 0;
     const uint64_t row_b = N * prow * 8;
-    const uint64_t batch = (uint64_t)serving_batch(ctx, r.p.max_batch, (int)nsolve, opt_b + src_b + row_b);
+    const uint64_t gsn = r.p.g_sampling ? N / (uint64_t)r.ng + 1 : N;
+    uint64_t batch = (uint64_t)serving_batch(ctx, r.p.max_batch, (int)nsolve, opt_b + src_b + row_b, gsn);
+    if (r.p.g_sampling) batch = std::max<uint64_t>(r.ng, batch / r.ng * r.ng);  // whole bands, as the solve rounds
     const uint64_t chunks = (uint64_t)reduce_rows_chunks(N);
     uint64_t b = opt_b * batch + row_b * batch + nsolve * row_w * 8 + batch * chunks * pw * 8 +
                  batch * (sizeof(SolveDev) + sizeof(PrepSlot)) + 64;
@@ -1694,11 +1746,18 @@ void worker_main(mcrt_ctx* ctx, Slot* sl)
         ctx->queue.pop_front();
         bool fits;
         uint64_t held;
-        {
-            std::lock_guard<std::mutex> mk(ctx->mem_mu);
-            held = held_locked(ctx);
-            fits = held + r->est <= ctx->budget;
-            if (fits) ctx->reserved += r->est;
+        for (int attempt = 0;; ++attempt) {
+            {
+                std::lock_guard<std::mutex> mk(ctx->mem_mu);
+                held = held_locked(ctx);
+                fits = held + r->est <= ctx->budget;
+                if (fits) ctx->reserved += r->est;
+            }
+            if (fits || attempt > 0) break;
+            lk.unlock();  // the blocking solves' kept scratch gives way, if no blocking solve runs
+            const bool freed = reclaim_main(ctx);
+            lk.lock();
+            if (!freed) break;
         }
         if (!fits) {
             char msg[160];
@@ -1713,6 +1772,7 @@ void worker_main(mcrt_ctx* ctx, Slot* sl)
         }
         r->status = R_RUNNING;
         r->t_start = Clock::now();
+        ctx->n_running++;
         lk.unlock();
         mcrt_result res{};
         res.value = r->value.data();
@@ -1723,6 +1783,7 @@ void worker_main(mcrt_ctx* ctx, Slot* sl)
         res.l_tot = r->l_tot.data();
         int rc = run_solve(ctx, *sl, sl->stream, r->mode, r->gid, r->oid, &r->p, &res);
         std::string err = rc ? std::string(mcrt_last_error()) : std::string();
+        ctx->n_running--;
         release_scratch(ctx, *sl);
         (void)hipStreamSynchronize(sl->stream);
         lk.lock();
@@ -1759,12 +1820,11 @@ void stop_workers(mcrt_ctx* ctx)
     ctx->workers.clear();
     for (auto& sl : ctx->wslots) slot_destroy(ctx, *sl);
     ctx->wslots.clear();
-    // hand the memory the default pool kept for the workers back to the device
-    hipMemPool_t pool = nullptr;
-    if (had_workers && hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool) {
-        uint64_t zero = 0;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &zero);
-        (void)hipMemPoolTrimTo(pool, 0);
+    // hand the memory the workers' pool kept back to the device
+    if (had_workers && ctx->pool) {
+        (void)hipMemPoolTrimTo(ctx->pool, 0);
+        (void)hipMemPoolDestroy(ctx->pool);
+        ctx->pool = nullptr;
     }
     (void)hipGetLastError();
 }
@@ -1810,6 +1870,12 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
     r->counters.assign(ng * kNCounters, 0.0);
     r->l_tot.assign(ng, 0.0);
     r->est = estimate_bytes(ctx, *r, ls.g, ls.op);
+    bool crowded;
+    {
+        std::lock_guard<std::mutex> mk(ctx->mem_mu);
+        crowded = held_locked(ctx) + r->est > ctx->budget;
+    }
+    if (crowded) reclaim_main(ctx);  // the blocking solves' kept scratch gives way to served requests
     {
         std::lock_guard<std::mutex> mk(ctx->mem_mu);
         const uint64_t resident = ctx->in_use - ctx->served;  // not freed when running requests end
@@ -1820,16 +1886,28 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
     std::lock_guard<std::mutex> lk(ctx->q_mu);
     if (ctx->stopping) return fail(MCRT_EINVAL, "context is shutting down");
     if (ctx->workers.empty()) {
-        // The workers' stream-ordered scratch comes from the device's default
-        // pool.  Let the pool keep up to the budget's worth of freed memory,
-        // so that a request reuses what earlier ones freed instead of having
-        // it returned to the device and mapped again at every synchronisation.
+        // The workers' stream-ordered scratch comes from a memory pool of this
+        // context.  It keeps up to the budget's worth of freed memory, so that
+        // a request reuses what earlier ones freed instead of having it
+        // returned to the device and mapped again at every synchronisation;
+        // blocking allocations trim it when in_use plus what it keeps would
+        // pass the budget.
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = ctx->device;
         hipMemPool_t pool = nullptr;
-        if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool) {
-            uint64_t keep = ctx->budget;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (hipMemPoolCreate(&pool, &props) != hipSuccess || !pool) {
+            (void)hipGetLastError();
+            return fail(MCRT_EDEVICE, "hipMemPoolCreate failed");
         }
-        (void)hipGetLastError();
+        uint64_t keep = ctx->budget;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        {
+            std::lock_guard<std::mutex> mk(ctx->mem_mu);
+            ctx->pool = pool;
+        }
         for (int w = 0; w < ctx->n_workers; ++w) {
             std::unique_ptr<Slot> sl(new Slot());
             if ((rc = slot_init(*sl))) return rc;
@@ -1873,6 +1951,164 @@ int wait_request(mcrt_ctx* ctx, uint64_t ticket, mcrt_result* out)
     ctx->requests.erase(it);
     if (rc) g_err = err;
     return rc;
+}
+
+int grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, hipStream_t st, int32_t* grid_id)
+{
+    int rc = validate_grid(d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    HIPTRY(hipSetDevice(ctx->device));
+    const bool slab = d->geometry == MCRT_PLANE_PARALLEL;
+    const int nlon = d->nlon, nlat = d->nlat, nlay = d->nlay;
+    const size_t n = (size_t)nlon * nlat * nlay;
+    const bool borrow = (d->flags & MCRT_BORROW_DEVICE) != 0;
+    if (borrow && (rc = check_borrowed(ctx, d, n, st))) return rc;
+    // host-side edge tables
+    std::vector<double> lat(nlat + 1), lon(nlon + 1);
+    if (slab) {
+        lat = {-kPi / 2, kPi / 2};
+        lon = {-kPi, kPi};
+    } else {
+        std::copy(d->lat_edges, d->lat_edges + nlat + 1, lat.begin());
+        std::copy(d->lon_edges, d->lon_edges + nlon + 1, lon.begin());
+    }
+    std::vector<double> lc2(nlat + 1), ls2(nlat + 1), lsn(nlat + 1), los(nlon), loc(nlon), volr(nlay);
+    for (int e = 0; e <= nlat; ++e) {
+        double c = std::cos(lat[e]), s = std::sin(lat[e]);
+        lc2[e] = c * c;
+        ls2[e] = s * s;
+        lsn[e] = s;
+    }
+    for (int e = 0; e < nlon; ++e) {
+        los[e] = std::sin(lon[e]);
+        loc[e] = std::cos(lon[e]);
+    }
+    for (int k = 0; k < nlay; ++k)
+        volr[k] = (std::pow(d->r_edges[k + 1], 3.0) - std::pow(d->r_edges[k], 3.0)) / 3.0;
+
+    std::unique_ptr<GridRes> G(new GridRes());
+    GridDev& gd = G->dev;
+    gd.geom = slab ? 1 : 0;
+    gd.nlon = nlon;
+    gd.nlat = nlat;
+    gd.nlay = nlay;
+    gd.max_cross = 4 * (nlay + nlat + nlon) + 16;
+    gd.omega_rot = d->omega_rot;
+    auto cleanup = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        for (auto& b : G->bufs) dev_free(ctx, b);
+        return code;
+    };
+    double* dp;
+    float* fp;
+#define UP(field, host, cnt, ptr)                                            \
+    do {                                                                     \
+        int _r = upload(ctx, G->bufs, G->bytes, host, cnt, &ptr, st);            \
+        if (_r) return cleanup(_r);                                          \
+        gd.field = ptr;                                                      \
+    } while (0)
+    UP(r, d->r_edges, (size_t)nlay + 1, dp);
+    UP(lat, lat.data(), lat.size(), dp);
+    UP(lat_c2, lc2.data(), lc2.size(), dp);
+    UP(lat_s2, ls2.data(), ls2.size(), dp);
+    UP(lat_sin, lsn.data(), lsn.size(), dp);
+    UP(lon, lon.data(), lon.size(), dp);
+    UP(lon_s, los.data(), los.size(), dp);
+    UP(lon_c, loc.data(), loc.size(), dp);
+    UP(vol_r, volr.data(), volr.size(), dp);
+    if (borrow) {  // read in place; the caller owns them
+        gd.T = d->T;
+        gd.P = d->P;
+        gd.rho = d->rho;
+        gd.u = d->u;
+        gd.v = d->v;
+        gd.w = d->w;
+        gd.cld_ksca = d->cld_ksca;
+        gd.cld_kabs = d->cld_kabs;
+        gd.cld_g = d->cld_g;
+    } else {
+        UP(T, d->T, n, fp);
+        UP(P, d->P, n, fp);
+        UP(rho, d->rho, n, dp);
+        if (d->u) UP(u, d->u, n, fp);
+        if (d->v) UP(v, d->v, n, fp);
+        if (d->w) UP(w, d->w, n, fp);
+        if (d->cld_ksca) {
+            UP(cld_ksca, d->cld_ksca, n, fp);
+            UP(cld_kabs, d->cld_kabs, n, fp);
+            UP(cld_g, d->cld_g, n, fp);
+        }
+    }
+#undef UP
+    // the host arrays (and the edge tables above) are read before return
+    if (hipError_t e = hipStreamSynchronize(st)) return cleanup(hip_check(ctx, e, "hipStreamSynchronize"));
+    G->ncell = (int)n;
+    G->r0 = d->r_edges[0];
+    G->r_toa = d->r_edges[nlay];
+    int32_t id = ctx->next_grid++;
+    ctx->grids[id] = std::move(G);
+    *grid_id = id;
+    return MCRT_OK;
+}
+
+
+int opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, hipStream_t st, int32_t* opac_id)
+{
+    int rc = validate_opacity(d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
+    HIPTRY(hipSetDevice(ctx->device));
+    std::unique_ptr<OpacRes> O(new OpacRes());
+    O->kind = d->kind;
+    O->nspec = d->nspec;
+    O->ng = d->ng;
+    O->nT = d->nT;
+    O->nP = d->nP;
+    O->lam_min = d->lam_min_um;
+    O->dlnlam = d->dlnlam;
+    O->k_ray.assign(d->k_ray, d->k_ray + d->nspec);
+    if (d->kind == MCRT_OPAC_CK) {
+        O->lam_um.assign(d->lam_um, d->lam_um + d->nspec);
+        O->g_weights.assign(d->g_weights, d->g_weights + d->ng);
+    } else {
+        O->g_weights = {1.0};
+    }
+    const size_t nTP = (size_t)d->nT * d->nP;
+    const size_t ntab = (size_t)d->nspec * d->ng * nTP;
+    std::vector<double> lnk(ntab);
+    if (d->kind == MCRT_OPAC_CK) {
+        for (size_t i = 0; i < ntab; ++i) lnk[i] = d->kappa[i] > 0.0f ? std::log((double)d->kappa[i]) : -INFINITY;
+    } else {
+        // [lam][T][P] -> [T][P][lam]: consecutive wavelengths are contiguous
+        const size_t nl = (size_t)d->nspec;
+        for (size_t l = 0; l < nl; ++l)
+            for (size_t tp = 0; tp < nTP; ++tp) {
+                float kv = d->kappa[l * nTP + tp];
+                lnk[tp * nl + l] = kv > 0.0f ? std::log((double)kv) : -INFINITY;
+            }
+    }
+    std::vector<double> lnP(d->nP);
+    for (int q = 0; q < d->nP; ++q) lnP[q] = std::log(d->P_grid[q]);
+    auto cleanup = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        for (auto& b : O->bufs) dev_free(ctx, b);
+        return code;
+    };
+    if ((rc = upload(ctx, O->bufs, O->bytes, lnk.data(), lnk.size(), &O->lnk, st))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, d->T_grid, (size_t)d->nT, &O->T_grid, st))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, lnP.data(), lnP.size(), &O->lnP_grid, st))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, d->k_ray, (size_t)d->nspec, &O->k_ray_dev, st))) return cleanup(rc);
+    if ((rc = upload(ctx, O->bufs, O->bytes, O->g_weights.data(), O->g_weights.size(), &O->gw_dev, st)))
+        return cleanup(rc);
+    // the staged host tables are read before return
+    if (hipError_t e = hipStreamSynchronize(st)) return cleanup(hip_check(ctx, e, "hipStreamSynchronize"));
+    int32_t id = ctx->next_opac++;
+    ctx->opacs[id] = std::move(O);
+    *opac_id = id;
+    return MCRT_OK;
 }
 
 }  // namespace
@@ -2019,102 +2255,12 @@ void mcrt_default_params(mcrt_solve_params* p)
     p->draine_alpha = 0.5;
 }
 
-int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, int32_t* grid_id)
+int mcrt_grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, void* stream, int32_t* grid_id)
 {
     if (!ctx || !grid_id) return fail(MCRT_EINVAL, "ctx and grid_id are required");
-    int rc = validate_grid(d);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
-    HIPTRY(hipSetDevice(ctx->device));
-    const bool slab = d->geometry == MCRT_PLANE_PARALLEL;
-    const int nlon = d->nlon, nlat = d->nlat, nlay = d->nlay;
-    const size_t n = (size_t)nlon * nlat * nlay;
-    const bool borrow = (d->flags & MCRT_BORROW_DEVICE) != 0;
-    if (borrow && (rc = check_borrowed(ctx, d, n))) return rc;
-    // host-side edge tables
-    std::vector<double> lat(nlat + 1), lon(nlon + 1);
-    if (slab) {
-        lat = {-kPi / 2, kPi / 2};
-        lon = {-kPi, kPi};
-    } else {
-        std::copy(d->lat_edges, d->lat_edges + nlat + 1, lat.begin());
-        std::copy(d->lon_edges, d->lon_edges + nlon + 1, lon.begin());
-    }
-    std::vector<double> lc2(nlat + 1), ls2(nlat + 1), lsn(nlat + 1), los(nlon), loc(nlon), volr(nlay);
-    for (int e = 0; e <= nlat; ++e) {
-        double c = std::cos(lat[e]), s = std::sin(lat[e]);
-        lc2[e] = c * c;
-        ls2[e] = s * s;
-        lsn[e] = s;
-    }
-    for (int e = 0; e < nlon; ++e) {
-        los[e] = std::sin(lon[e]);
-        loc[e] = std::cos(lon[e]);
-    }
-    for (int k = 0; k < nlay; ++k)
-        volr[k] = (std::pow(d->r_edges[k + 1], 3.0) - std::pow(d->r_edges[k], 3.0)) / 3.0;
-
-    std::unique_ptr<GridRes> G(new GridRes());
-    GridDev& gd = G->dev;
-    gd.geom = slab ? 1 : 0;
-    gd.nlon = nlon;
-    gd.nlat = nlat;
-    gd.nlay = nlay;
-    gd.max_cross = 4 * (nlay + nlat + nlon) + 16;
-    gd.omega_rot = d->omega_rot;
-    auto cleanup = [&](int code) {
-        for (auto& b : G->bufs) dev_free(ctx, b);
-        return code;
-    };
-    double* dp;
-    float* fp;
-#define UP(field, host, cnt, ptr)                                            \
-    do {                                                                     \
-        int _r = upload(ctx, G->bufs, G->bytes, host, cnt, &ptr);            \
-        if (_r) return cleanup(_r);                                          \
-        gd.field = ptr;                                                      \
-    } while (0)
-    UP(r, d->r_edges, (size_t)nlay + 1, dp);
-    UP(lat, lat.data(), lat.size(), dp);
-    UP(lat_c2, lc2.data(), lc2.size(), dp);
-    UP(lat_s2, ls2.data(), ls2.size(), dp);
-    UP(lat_sin, lsn.data(), lsn.size(), dp);
-    UP(lon, lon.data(), lon.size(), dp);
-    UP(lon_s, los.data(), los.size(), dp);
-    UP(lon_c, loc.data(), loc.size(), dp);
-    UP(vol_r, volr.data(), volr.size(), dp);
-    if (borrow) {  // read in place; the caller owns them
-        gd.T = d->T;
-        gd.P = d->P;
-        gd.rho = d->rho;
-        gd.u = d->u;
-        gd.v = d->v;
-        gd.w = d->w;
-        gd.cld_ksca = d->cld_ksca;
-        gd.cld_kabs = d->cld_kabs;
-        gd.cld_g = d->cld_g;
-    } else {
-        UP(T, d->T, n, fp);
-        UP(P, d->P, n, fp);
-        UP(rho, d->rho, n, dp);
-        if (d->u) UP(u, d->u, n, fp);
-        if (d->v) UP(v, d->v, n, fp);
-        if (d->w) UP(w, d->w, n, fp);
-        if (d->cld_ksca) {
-            UP(cld_ksca, d->cld_ksca, n, fp);
-            UP(cld_kabs, d->cld_kabs, n, fp);
-            UP(cld_g, d->cld_g, n, fp);
-        }
-    }
-#undef UP
-    G->ncell = (int)n;
-    G->r0 = d->r_edges[0];
-    G->r_toa = d->r_edges[nlay];
-    int32_t id = ctx->next_grid++;
-    ctx->grids[id] = std::move(G);
-    *grid_id = id;
-    return MCRT_OK;
+    int rc = grid_upload(ctx, d, (hipStream_t)stream, grid_id);
+    if (rc == MCRT_EBUDGET && reclaim_main(ctx)) rc = grid_upload(ctx, d, (hipStream_t)stream, grid_id);
+    return rc;
 }
 
 int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
@@ -2132,59 +2278,12 @@ int mcrt_grid_free(mcrt_ctx* ctx, int32_t grid_id)
     return MCRT_OK;
 }
 
-int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, int32_t* opac_id)
+int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, void* stream, int32_t* opac_id)
 {
     if (!ctx || !opac_id) return fail(MCRT_EINVAL, "ctx and opac_id are required");
-    int rc = validate_opacity(d);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->poisoned) return fail(MCRT_EDEVICE, "context is unusable after an earlier device error");
-    HIPTRY(hipSetDevice(ctx->device));
-    std::unique_ptr<OpacRes> O(new OpacRes());
-    O->kind = d->kind;
-    O->nspec = d->nspec;
-    O->ng = d->ng;
-    O->nT = d->nT;
-    O->nP = d->nP;
-    O->lam_min = d->lam_min_um;
-    O->dlnlam = d->dlnlam;
-    O->k_ray.assign(d->k_ray, d->k_ray + d->nspec);
-    if (d->kind == MCRT_OPAC_CK) {
-        O->lam_um.assign(d->lam_um, d->lam_um + d->nspec);
-        O->g_weights.assign(d->g_weights, d->g_weights + d->ng);
-    } else {
-        O->g_weights = {1.0};
-    }
-    const size_t nTP = (size_t)d->nT * d->nP;
-    const size_t ntab = (size_t)d->nspec * d->ng * nTP;
-    std::vector<double> lnk(ntab);
-    if (d->kind == MCRT_OPAC_CK) {
-        for (size_t i = 0; i < ntab; ++i) lnk[i] = d->kappa[i] > 0.0f ? std::log((double)d->kappa[i]) : -INFINITY;
-    } else {
-        // [lam][T][P] -> [T][P][lam]: consecutive wavelengths are contiguous
-        const size_t nl = (size_t)d->nspec;
-        for (size_t l = 0; l < nl; ++l)
-            for (size_t tp = 0; tp < nTP; ++tp) {
-                float kv = d->kappa[l * nTP + tp];
-                lnk[tp * nl + l] = kv > 0.0f ? std::log((double)kv) : -INFINITY;
-            }
-    }
-    std::vector<double> lnP(d->nP);
-    for (int q = 0; q < d->nP; ++q) lnP[q] = std::log(d->P_grid[q]);
-    auto cleanup = [&](int code) {
-        for (auto& b : O->bufs) dev_free(ctx, b);
-        return code;
-    };
-    if ((rc = upload(ctx, O->bufs, O->bytes, lnk.data(), lnk.size(), &O->lnk))) return cleanup(rc);
-    if ((rc = upload(ctx, O->bufs, O->bytes, d->T_grid, (size_t)d->nT, &O->T_grid))) return cleanup(rc);
-    if ((rc = upload(ctx, O->bufs, O->bytes, lnP.data(), lnP.size(), &O->lnP_grid))) return cleanup(rc);
-    if ((rc = upload(ctx, O->bufs, O->bytes, d->k_ray, (size_t)d->nspec, &O->k_ray_dev))) return cleanup(rc);
-    if ((rc = upload(ctx, O->bufs, O->bytes, O->g_weights.data(), O->g_weights.size(), &O->gw_dev)))
-        return cleanup(rc);
-    int32_t id = ctx->next_opac++;
-    ctx->opacs[id] = std::move(O);
-    *opac_id = id;
-    return MCRT_OK;
+    int rc = opacity_upload(ctx, d, (hipStream_t)stream, opac_id);
+    if (rc == MCRT_EBUDGET && reclaim_main(ctx)) rc = opacity_upload(ctx, d, (hipStream_t)stream, opac_id);
+    return rc;
 }
 
 int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id)

@@ -102,9 +102,9 @@ def load() -> ctypes.CDLL:
     L.mcrt_last_error.restype = ctypes.c_char_p
     L.mcrt_memory_in_use.argtypes = [_vp]
     L.mcrt_memory_in_use.restype = _u64
-    L.mcrt_grid_upload.argtypes = [_vp, ctypes.POINTER(GridDesc), ctypes.POINTER(_i32)]
+    L.mcrt_grid_upload.argtypes = [_vp, ctypes.POINTER(GridDesc), _vp, ctypes.POINTER(_i32)]
     L.mcrt_grid_free.argtypes = [_vp, _i32]
-    L.mcrt_opacity_upload.argtypes = [_vp, ctypes.POINTER(OpacityDesc), ctypes.POINTER(_i32)]
+    L.mcrt_opacity_upload.argtypes = [_vp, ctypes.POINTER(OpacityDesc), _vp, ctypes.POINTER(_i32)]
     L.mcrt_opacity_free.argtypes = [_vp, _i32]
     L.mcrt_default_params.argtypes = [ctypes.POINTER(SolveParams)]
     L.mcrt_default_params.restype = None
@@ -180,11 +180,14 @@ class Context:
         return int(load().mcrt_memory_in_use(self._h))
 
     # ---------------------------------------------------------- uploads
-    def upload_grid(self, g, borrow: bool = False) -> int:
+    def upload_grid(self, g, borrow: bool = False, stream=None) -> int:
         """g: paper_2110_15640_amd.inputs.Grid (host numpy arrays).  borrow:
         the per-cell arrays are first placed in torch device tensors, which
         the library reads in place (MCRT_BORROW_DEVICE); this context keeps
-        them alive until free_grid."""
+        them alive until free_grid.  stream: a torch stream (or a raw
+        hipStream_t) to upload on; with borrow it defaults to torch's current
+        stream, so the library checks the tensors after the copies that
+        filled them."""
         arrs = dict(r=_arr(g.r_edges, np.float64), lat=_arr(g.lat_edges, np.float64),
                     lon=_arr(g.lon_edges, np.float64), T=_arr(g.T, np.float32),
                     P=_arr(g.P, np.float32), rho=_arr(g.rho, np.float64),
@@ -196,9 +199,10 @@ class Context:
         if borrow:
             import torch
             dev = torch.device("cuda", self.device)
-            held = {k: torch.from_numpy(v).to(dev) for k, v in arrs.items()
+            held = {k: torch.from_numpy(v).to(dev, non_blocking=False) for k, v in arrs.items()
                     if v is not None and k not in ("r", "lat", "lon")}
-            torch.cuda.synchronize(dev)
+            if stream is None:
+                stream = torch.cuda.current_stream(dev)
             cell.update(held)
 
         def ptr(k):
@@ -209,14 +213,15 @@ class Context:
                      _ptr(arrs["lon"]), ptr("T"), ptr("P"), ptr("rho"), ptr("u"), ptr("v"), ptr("w"),
                      ptr("cs"), ptr("ca"), ptr("cg"), float(g.omega_rot), MCRT_BORROW_DEVICE if borrow else 0)
         gid = _i32()
-        _check(load().mcrt_grid_upload(self._h, ctypes.byref(d), ctypes.byref(gid)))
+        st = None if stream is None else getattr(stream, "cuda_stream", stream)
+        _check(load().mcrt_grid_upload(self._h, ctypes.byref(d), st, ctypes.byref(gid)))
         self._ncell[gid.value] = g.nlon * g.nlat * g.nlay
         if held is not None:
             self._borrowed[gid.value] = held
         return gid.value
 
-    def upload_opacity(self, t) -> int:
-        """t: inputs.CKTable or inputs.HiresTable."""
+    def upload_opacity(self, t, stream=None) -> int:
+        """t: inputs.CKTable or inputs.HiresTable; stream as for upload_grid."""
         hires = not hasattr(t, "g_weights")
         kap = _arr(t.kappa, np.float32)
         Tg, Pg, kr = _arr(t.T_grid, np.float64), _arr(t.P_grid, np.float64), _arr(t.k_ray, np.float64)
@@ -228,7 +233,8 @@ class Context:
             d = OpacityDesc(MCRT_OPAC_CK, t.nband, t.ng, len(Tg), len(Pg), _ptr(lam), 0.0, 0.0, _ptr(gw),
                             _ptr(Tg), _ptr(Pg), _ptr(kap), _ptr(kr))
         oid = _i32()
-        _check(load().mcrt_opacity_upload(self._h, ctypes.byref(d), ctypes.byref(oid)))
+        st = None if stream is None else getattr(stream, "cuda_stream", stream)
+        _check(load().mcrt_opacity_upload(self._h, ctypes.byref(d), st, ctypes.byref(oid)))
         return oid.value
 
     def free_grid(self, gid: int):

@@ -98,3 +98,34 @@ def test_binding_struct_offsets_and_sizes_match_the_c_compiler():
         assert lay[(cname, "size")] == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert lay[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def _prototypes():
+    """name -> list of parameter declarations, from the header's prototypes."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(?:int|void|uint64_t|const char\*)\s+(mcrt_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", txt):
+        args = [a.strip() for a in m.group(2).split(",") if a.strip() and a.strip() != "void"]
+        out[m.group(1)] = args
+    return out
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcrt.so not built")
+def test_binding_argtypes_match_header_prototypes():
+    """Every function the binding declares takes as many arguments as its C
+    prototype; the uploads take the caller's stream before the id."""
+    from paper_2110_15640_amd import mcrt as M
+    L = M.load()
+    protos = _prototypes()
+    assert set(protos) == set(declared_functions())
+    checked = 0
+    for name, args in protos.items():
+        at = getattr(L, name).argtypes
+        if at is None:
+            continue
+        assert len(at) == len(args), (name, args)
+        checked += 1
+    assert checked >= 15
+    for name in ("mcrt_grid_upload", "mcrt_opacity_upload"):
+        assert protos[name][2].replace(" ", "") == "void*stream", protos[name]
+    assert protos["mcrt_solve_noalloc"][1].replace(" ", "") == "int32_tmode"

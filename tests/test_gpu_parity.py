@@ -846,6 +846,30 @@ def test_maximum_index_grids(ctx, torch_dev):
     ctx.free_opacity(oid)
 
 
+def test_uploads_on_a_caller_stream(ctx, torch_dev):
+    """Uploads ordered on a caller's stream: a copied grid and table uploaded
+    on a side stream, and a borrowed grid whose tensors are filled on that
+    stream and checked there without a device-wide synchronisation, give the
+    same results bit for bit as uploads on the null stream."""
+    _log("uploads on a caller stream (copied and borrowed) vs null-stream uploads")
+    torch = torch_dev
+    grid, table, phases = I.make_emission_3d(16, 8, 10, nband=2, ng=2, config_no=121)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    s = torch.cuda.Stream()
+    sid, soid = ctx.upload_grid(grid, stream=s), ctx.upload_opacity(table, stream=s)
+    with torch.cuda.stream(s):
+        bid = ctx.upload_grid(grid, borrow=True)  # tensors filled and checked on s
+    kw = dict(n_packets=2000, seed=195, obs_phase=list(phases[:2]))
+    a = ctx.solve_emission(gid, oid, table, **kw)
+    for g2, o2 in ((sid, soid), (bid, oid), (bid, soid)):
+        b = ctx.solve_emission(g2, o2, table, **kw)
+        assert np.array_equal(a["sums"], b["sums"]) and np.array_equal(a["counters"], b["counters"])
+    for g2 in (bid, sid, gid):
+        ctx.free_grid(g2)
+    ctx.free_opacity(soid)
+    ctx.free_opacity(oid)
+
+
 def test_borrowed_device_grid(ctx, torch_dev):
     """A grid whose per-cell arrays are borrowed device tensors (read in
     place, not counted in the library's memory): bit-identical results to the
@@ -882,7 +906,7 @@ def test_borrowed_device_grid(ctx, torch_dev):
                    M.MCRT_BORROW_DEVICE)
     import ctypes
     out = ctypes.c_int32()
-    assert M.load().mcrt_grid_upload(ctx._h, ctypes.byref(d), ctypes.byref(out)) == -1
+    assert M.load().mcrt_grid_upload(ctx._h, ctypes.byref(d), None, ctypes.byref(out)) == -1
     # bad values in borrowed device memory: found by the device check
     bad = I.make_sphere(8, 4, 3, seed=5)
     bad.rho = bad.rho.copy()

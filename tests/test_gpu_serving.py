@@ -85,45 +85,86 @@ def test_cancel_poll_and_budget(torch_dev):
         assert e.value.name == "ENOTFOUND"
 
 
+def _big_table(nband, ng=8, nT=20, nP=20):
+    """A correlated-k table of nband x ng x nT x nP entries (constant in g,
+    so sorted): nband * ng * nT * nP * 8 bytes on the device."""
+    ck = I.make_ck_table(np.random.Generator(np.random.PCG64(7)), nband=1, ng=ng, nT=nT, nP=nP)
+    return I.CKTable(np.linspace(1.0, 2.0, nband), ck.g_weights, ck.T_grid, ck.P_grid,
+                     np.full((nband, ng, nT, nP), 1e-2, dtype=np.float32), np.full(nband, 1e-6))
+
+
 def test_queued_request_that_no_longer_fits_fails_without_blocking(torch_dev):
     """Admission charges a running request's allocations to its reservation
     once; a queued request whose scratch no longer fits after the memory went
-    to a blocking solve fails with EBUDGET once nothing runs, and the queue
-    keeps serving the requests behind it."""
-    print("serving: queued request outgrown by a blocking solve", flush=True)
+    to an upload fails with EBUDGET once nothing runs, and the queue keeps
+    serving the requests behind it."""
+    print("serving: queued request outgrown by an upload", flush=True)
     from paper_2110_15640_amd import mcrt as M
     grid, ck, phases = I.make_emission_3d(16, 8, 10, nband=1, ng=1)
+    _, ck_a, _ = I.make_emission_3d(16, 8, 10, nband=100, ng=8)
     MB = 1 << 20
-    per_mpkt = 96 * 10**6  # rows of 12 doubles per packet with one observer
     probe = M.Context(0)
     probe.upload_grid(grid)
     probe.upload_opacity(ck)
+    probe.upload_opacity(ck_a)
     resident = probe.memory_in_use
     probe.close()
-    # A = 4e6 packets (~384 MB), R = 12e6 (~1152 MB), S = 8e6 (~768 MB):
-    # R fits alone at submit, S fits beside A, R does not fit beside S
-    budget = resident + 1400 * MB
+    big = _big_table(11000)  # 281.6 MB on the device
+    # A: 800 solves of 2e6 packets (two per launch, ~384 MB of scratch; long
+    # enough to outlast the upload's host preparation); R: 12e6 packets
+    # (~1152 MB).  R fits alone at submit, the table fits beside A, R does not
+    # fit beside the table.
+    budget = resident + 1300 * MB
     with M.Context(0, hbm_budget_bytes=budget) as ctx:
         ctx.serve_config(1)
-        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(ck)
+        gid, oid, oid_a = ctx.upload_grid(grid), ctx.upload_opacity(ck), ctx.upload_opacity(ck_a)
         assert ctx.memory_in_use == resident
-        ta = ctx.submit("emission", gid, oid, ck, n_packets=4 * 10**6, obs_phase=[0.5], seed=1)
+        ta = ctx.submit("emission", gid, oid_a, ck_a, n_packets=2 * 10**6, obs_phase=[0.5], seed=1)
         tr = ctx.submit("emission", gid, oid, ck, n_packets=12 * 10**6, obs_phase=[0.5], seed=2)
         try:
-            s = ctx.solve_emission(gid, oid, ck, n_packets=8 * 10**6, obs_phase=[0.5], seed=3)
+            ctx.upload_opacity(big)
+            a_was_running = not ctx.poll(ta)
         except M.McrtError as e:
             assert e.name == "EBUDGET"
+            a_was_running = False
+        if not a_was_running:
             ctx.wait(ta)
             try:
                 ctx.wait(tr)
             except M.McrtError:
                 pass
-            pytest.skip("request A ended before the blocking solve allocated; R was admitted first")
-        assert np.all(s["value"] > 0)
-        assert ctx.memory_in_use >= resident + 8 * per_mpkt
+            pytest.skip("request A ended before the upload; R may have been admitted first")
+        assert ctx.memory_in_use >= resident + 281 * 10**6
         assert np.all(ctx.wait(ta)["value"] > 0)
         with pytest.raises(M.McrtError) as e:
             ctx.wait(tr)
         assert e.value.name == "EBUDGET"
         tt = ctx.submit("emission", gid, oid, ck, n_packets=10**5, obs_phase=[0.5], seed=4)
         assert np.all(ctx.wait(tt)["value"] > 0)
+
+
+def test_blocking_solve_scratch_gives_way_to_served_requests(torch_dev):
+    """The scratch a blocking solve keeps for the next one does not shrink
+    what serving admits: a request that fits the context's budget beside its
+    grids and tables is admitted after a blocking solve that kept half the
+    budget, and gives the blocking solve's result bit for bit."""
+    print("serving: blocking-solve scratch released for a served request", flush=True)
+    from paper_2110_15640_amd import mcrt as M
+    grid, ck, phases = I.make_emission_3d(32, 16, 20, nband=4, ng=4)
+    MB = 1 << 20
+    kt = dict(n_b=600, n_alpha=700, seed=21, spec_idx=[2], r_star=I.R_SUN)  # ~0.6 GB of chord segments
+    with M.Context(0, hbm_budget_bytes=1024 * MB) as ctx:
+        ctx.serve_config(2)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(ck)
+        resident = ctx.memory_in_use
+        ref = ctx.solve_transmission(gid, oid, ck, **kt)
+        em = ctx.solve_emission(gid, oid, ck, n_packets=10**6, obs_phase=[0.5], seed=22)
+        assert np.all(em["value"] > 0)
+        kept = ctx.memory_in_use - resident
+        assert kept > 400 * MB, kept  # half of what the budget left, and the chords' scratch
+        got = ctx.wait(ctx.submit("transmission", gid, oid, ck, **kt))
+        assert np.array_equal(got["sums"], ref["sums"]) and np.array_equal(got["value"], ref["value"])
+        assert ctx.memory_in_use < resident + 64 * MB
+        # blocking solves still work afterwards, and give the same result
+        em2 = ctx.solve_emission(gid, oid, ck, n_packets=10**6, obs_phase=[0.5], seed=22)
+        assert np.array_equal(em2["sums"], em["sums"])
