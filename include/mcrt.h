@@ -210,7 +210,10 @@ int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
  *   results agree with an independent FP64 evaluation to ~1e-12; the mixed
  *   form keeps optical properties, phase functions and directions in FP32 and
  *   computes crossings in FP64 with multiply-adds and a refined-reciprocal
- *   division (spectra within 1e-3 and 3 sigma of the FP64 ones).
+ *   division (spectra within 1e-3 and 3 sigma of the FP64 ones).  Raytrace
+ *   transmission in the mixed form stores each cell's extinction per
+ *   spectral row in FP32 (evaluated in FP64, rounded once) and accumulates
+ *   the chords' optical depths in FP64.
  * stream: hipStream_t to run on (NULL = the context's own stream).
  * packet_dump: optional DEVICE buffer of doubles receiving each packet's
  *   peel-off sum per observer, [solve][packet][observer] with solves ordered

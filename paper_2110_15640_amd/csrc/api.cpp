@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <deque>
 #include <thread>
+#include <type_traits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -841,8 +842,14 @@ int solve_packets(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, 
         batch = p->max_batch > 0 ? p->max_batch : nsolve;
         uint64_t room;
         {
+            // the slot's own scratch is regrown in place (each buffer freed
+            // before its larger successor is allocated), so it counts as room:
+            // repeated calls then plan the same launches as the first
+            uint64_t own = 0;
+            for (const auto& kv : sl.scratch) own += kv.second.bytes;
             std::lock_guard<std::mutex> mk(ctx->mem_mu);
-            room = ctx->budget - std::min(ctx->budget, held_locked(ctx));
+            const uint64_t held = held_locked(ctx);
+            room = ctx->budget - std::min(ctx->budget, held - std::min(held, own));
         }
         uint64_t cap = room / 2;  // half of what the budget leaves: fewer launches, fewer drain tails
         int fit = (int)std::max<uint64_t>(1, cap / std::max<size_t>(per_solve, 1));
@@ -1236,14 +1243,16 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
         launch_cell_tp(g->dev, ncell, op->nT, op->nP, op->T_grid, op->lnP_grid, (CellTP*)v_tp, st);
         HIPTRY(hipMemcpyAsync(v_nl, pl.specs.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
     }
-    double* alpha = (double*)v_alpha;
-    for (int r0 = 0; r0 < nrow; r0 += kSlot) {
-        int nslot = std::min(kSlot, nrow - r0);
+    // Per block of up to 64 spectral rows: extinction of every cell (FP64, or
+    // FP32 in the mixed form: half the bytes the chords gather), then the
+    // chords' optical depths, accumulated in FP64 either way.
+    auto rows_block = [&](auto* alpha, int r0, int nslot) {
+        using R = std::remove_pointer_t<decltype(alpha)>;
         if (op->kind == MCRT_OPAC_CK) {
             for (int q = 0; q < nslot; ++q) {
                 int rr = r0 + q, b = pl.specs[rr / ng], gi = rr % ng;
                 const double* tab = op->lnk + ((size_t)b * op->ng + gi) * op->nT * op->nP;
-                OpticsDev<double> od{alpha + q, nullptr, nullptr, nullptr, nullptr};
+                OpticsDev<R> od{alpha + q, nullptr, nullptr, nullptr, nullptr};
                 launch_ck_optics(g->dev, ncell, tab, op->nT, op->nP, op->T_grid, op->lnP_grid, op->k_ray[b], od, nslot,
                                  st);
             }
@@ -1251,10 +1260,16 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
             launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nP, (const CellTP*)v_tp, op->k_ray_dev,
                                      (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st));
-        launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok, alpha,
-                         nslot, (double*)v_part, tblocks, st);
-        if (prof) HIPTRY(hipEventRecord(sl.prof_ev[2 * (r0 / kSlot) + 1], st));
+        if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st);
+        launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok,
+                         (const R*)alpha, nslot, (double*)v_part, tblocks, st);
+        if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot) + 1], st);
+    };
+    const bool mixed = p->precision == MCRT_MIXED;
+    for (int r0 = 0; r0 < nrow; r0 += kSlot) {
+        int nslot = std::min(kSlot, nrow - r0);
+        if (mixed) rows_block((float*)v_alpha, r0, nslot);
+        else rows_block((double*)v_alpha, r0, nslot);
         launch_reduce_partials((double*)v_part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
     }
     HIPTRY(hipGetLastError());

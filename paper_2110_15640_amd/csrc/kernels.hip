@@ -29,10 +29,13 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------- K1
+// R: type of the stored properties (double, or float for the mixed form; the
+// arithmetic is FP64 either way and the result is rounded once on store).
+template <typename R>
 __global__ void __launch_bounds__(256) k_ck_optics(GridDev g, int ncell, const double* __restrict__ lnk_tab,
                                                    int nT, int nP, const double* __restrict__ T_grid,
                                                    const double* __restrict__ lnP_grid, double k_ray,
-                                                   OpticsDev<double> out, int ext_stride)
+                                                   OpticsDev<R> out, int ext_stride)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -45,12 +48,12 @@ __global__ void __launch_bounds__(256) k_ck_optics(GridDev g, int ncell, const d
     double ksc = k_ray + ks;
     double kext = kab + ksc;
     double rho = g.rho[c];
-    out.a_ext[(size_t)c * ext_stride] = rho * kext;
+    out.a_ext[(size_t)c * ext_stride] = (R)(rho * kext);
     if (out.a_abs) {
-        out.a_abs[c] = rho * kab;
-        out.omega[c] = kext > 0.0 ? ksc / kext : 0.0;
-        out.p_gas[c] = ksc > 0.0 ? k_ray / ksc : 1.0;
-        out.g_cld[c] = g.cld_g ? (double)g.cld_g[c] : 0.0;
+        out.a_abs[c] = (R)(rho * kab);
+        out.omega[c] = (R)(kext > 0.0 ? ksc / kext : 0.0);
+        out.p_gas[c] = (R)(ksc > 0.0 ? k_ray / ksc : 1.0);
+        out.g_cld[c] = (R)(g.cld_g ? (double)g.cld_g[c] : 0.0);
     }
 }
 
@@ -108,12 +111,13 @@ __global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, i
     out[c] = CellTP{bt.i0, bt.i1, bp.i0, bp.i1, bt.t, bp.t};
 }
 
+template <typename R>
 __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
                                                            int nlam, int nP, const CellTP* __restrict__ tp,
                                                            const double* __restrict__ k_ray,
                                                            const double* __restrict__ shift,
                                                            const int* __restrict__ nlist, int nslot,
-                                                           int slot_stride, double* __restrict__ alpha)
+                                                           int slot_stride, R* __restrict__ alpha)
 {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)ncell * nslot) return;
@@ -125,7 +129,7 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
     bp.i0 = q.pi0; bp.i1 = q.pi1; bp.t = q.pt;
     double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
     double kext = kl + k_ray[n];
-    alpha[(size_t)c * slot_stride + s] = g.rho[c] * kext;
+    alpha[(size_t)c * slot_stride + s] = (R)(g.rho[c] * kext);
 }
 
 // (emission sources for the transport live in prep.hip)
@@ -288,12 +292,15 @@ __global__ void __launch_bounds__(256) k_scan_int(const int* __restrict__ in, lo
 constexpr int kChordWaves = 4;
 constexpr int kChordsPerWave = 8;
 
+// R: the stored extinction (double, or float in the mixed form: half the
+// gathered bytes); tau accumulates in FP64 either way.
+template <typename R>
 __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __restrict__ offsets,
                                                    const uint32_t* __restrict__ seg_cell,
                                                    const double* __restrict__ seg_len,
                                                    const double* __restrict__ chord_b,
                                                    const int* __restrict__ chord_ok,
-                                                   const double* __restrict__ alpha, int nslot,
+                                                   const R* __restrict__ alpha, int nslot,
                                                    double* __restrict__ partials)
 {
     __shared__ double sh1[kChordWaves][64];
@@ -323,7 +330,7 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
                 for (int k = 0; k < nseg; ++k) {
                     const uint32_t cell = (uint32_t)__shfl((int)mc, k);
                     const double len = __shfl(ml, k);
-                    if (s < nslot) tau = tau + alpha[(size_t)cell * nslot + s] * len;
+                    if (s < nslot) tau = tau + (double)alpha[(size_t)cell * nslot + s] * len;
                 }
             }
             if (!chord_ok[ch]) tau = INFINITY;
@@ -353,13 +360,18 @@ inline int nblk(long long n, int b) { return (int)((n + b - 1) / b); }
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+template <typename R>
 void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP, const double* T_grid,
-                      const double* lnP_grid, double k_ray, OpticsDev<double> out, int ext_stride,
+                      const double* lnP_grid, double k_ray, OpticsDev<R> out, int ext_stride,
                       hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_ck_optics, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, lnk_tab, nT, nP, T_grid,
-                       lnP_grid, k_ray, out, ext_stride);
+    hipLaunchKernelGGL(k_ck_optics<R>, dim3(nblk(ncell, 256)), dim3(256), 0, stream, g, ncell, lnk_tab, nT, nP,
+                       T_grid, lnP_grid, k_ray, out, ext_stride);
 }
+template void launch_ck_optics<double>(const GridDev&, int, const double*, int, int, const double*, const double*,
+                                       double, OpticsDev<double>, int, hipStream_t);
+template void launch_ck_optics<float>(const GridDev&, int, const double*, int, int, const double*, const double*,
+                                      double, OpticsDev<float>, int, hipStream_t);
 
 void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, double dlnlam, double* shift,
                           hipStream_t stream)
@@ -375,14 +387,21 @@ void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T
                        out);
 }
 
+template <typename R>
 void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
                               const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
-                              int nslot, int slot_stride, double* alpha, hipStream_t stream)
+                              int nslot, int slot_stride, R* alpha, hipStream_t stream)
 {
     long long n = (long long)ncell * nslot;
-    hipLaunchKernelGGL(k_hires_alpha_block, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam, nP,
-                       tp, k_ray, shift, nlist, nslot, slot_stride, alpha);
+    hipLaunchKernelGGL(k_hires_alpha_block<R>, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam,
+                       nP, tp, k_ray, shift, nlist, nslot, slot_stride, alpha);
 }
+template void launch_hires_alpha_block<double>(const GridDev&, int, const double*, int, int, const CellTP*,
+                                               const double*, const double*, const int*, int, int, double*,
+                                               hipStream_t);
+template void launch_hires_alpha_block<float>(const GridDev&, int, const double*, int, int, const CellTP*,
+                                              const double*, const double*, const int*, int, int, float*,
+                                              hipStream_t);
 
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out, hipStream_t stream)
 {
@@ -420,12 +439,17 @@ void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, ui
 
 int chord_tau_blocks(int nch) { return nblk(nch, kChordWaves * kChordsPerWave); }
 
+template <typename R>
 void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell, const double* seg_len,
-                      const double* chord_b, const int* chord_ok, const double* alpha, int nslot, double* partials,
+                      const double* chord_b, const int* chord_ok, const R* alpha, int nslot, double* partials,
                       int nblocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_chord_tau, dim3(nblocks), dim3(256), 0, stream, nch, offsets, seg_cell, seg_len, chord_b,
-                       chord_ok, alpha, nslot, partials);
+    hipLaunchKernelGGL(k_chord_tau<R>, dim3(nblocks), dim3(256), 0, stream, nch, offsets, seg_cell, seg_len,
+                       chord_b, chord_ok, alpha, nslot, partials);
 }
+template void launch_chord_tau<double>(int, const long long*, const uint32_t*, const double*, const double*,
+                                       const int*, const double*, int, double*, int, hipStream_t);
+template void launch_chord_tau<float>(int, const long long*, const uint32_t*, const double*, const double*,
+                                      const int*, const float*, int, double*, int, hipStream_t);
 
 }  // namespace mcrt

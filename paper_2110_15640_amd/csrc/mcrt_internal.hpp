@@ -165,9 +165,11 @@ void launch_fill_f64(double* p, size_t n, double v, hipStream_t stream);
 void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream);
 
 // Launchers (kernels.hip).  All run on `stream`; none synchronises.
+// R = double, or float for the mixed transmission form (stored once rounded).
+template <typename R>
 void launch_ck_optics(const GridDev& g, int ncell, const double* lnk_tab, int nT, int nP,
                       const double* T_grid, const double* lnP_grid, double k_ray,
-                      OpticsDev<double> out, int ext_stride, hipStream_t stream);
+                      OpticsDev<R> out, int ext_stride, hipStream_t stream);
 void launch_doppler_shift(const GridDev& g, double ox, double oy, double oz, double dlnlam,
                           double* shift, hipStream_t stream);
 // A cell's place in the opacity table's (T, ln P) grid: bracketing nodes
@@ -178,9 +180,10 @@ struct CellTP {
 };
 void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T_grid, const double* lnP_grid,
                     CellTP* out, hipStream_t stream);
+template <typename R>
 void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
                               const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
-                              int nslot, int slot_stride, double* alpha, hipStream_t stream);
+                              int nslot, int slot_stride, R* alpha, hipStream_t stream);
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,
                             hipStream_t stream);
 void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
@@ -190,9 +193,10 @@ void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* 
 void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
                        const long long* offsets, uint32_t* seg_cell, double* seg_len,
                        double* chord_b, int* chord_ok, const LimbDark& ld, hipStream_t stream);
+template <typename R>
 void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell,
                       const double* seg_len, const double* chord_b, const int* chord_ok,
-                      const double* alpha, int nslot, double* partials, int nblocks,
+                      const R* alpha, int nslot, double* partials, int nblocks,
                       hipStream_t stream);
 int chord_tau_blocks(int nch);
 

@@ -41,9 +41,31 @@ class ServeReport:
     scale: float
     latencies_ms: List[float] = field(default_factory=list)
     kinds: List[str] = field(default_factory=list)
-    packets: int = 0
+    packets: int = 0           # Monte Carlo packets (albedo and emission requests)
+    chord_wavelengths: int = 0  # chords x wavelengths (transmission requests)
     wall: float = 0.0
     service_ms: Dict[str, float] = field(default_factory=dict)
+    # per finished request: (start, end) on the device side of admission, in s
+    # from the first submit (submit time + queued_ms, submit time + latency_ms)
+    spans: List[tuple] = field(default_factory=list)
+    alone: dict = field(default_factory=dict)
+
+    def overlap(self) -> dict:
+        """Fractions of the busy time (some request running) during which at
+        least 2 (and 3) requests were running together."""
+        ev = sorted([(a, 1) for a, _ in self.spans] + [(b, -1) for _, b in self.spans])
+        busy = two = three = 0.0
+        n, last = 0, None
+        for t, d in ev:
+            if last is not None and n > 0:
+                dt = t - last
+                busy += dt
+                two += dt if n >= 2 else 0.0
+                three += dt if n >= 3 else 0.0
+            n += d
+            last = t
+        return {"busy_s": busy, "frac_ge2_running": two / busy if busy > 0 else 0.0,
+                "frac_ge3_running": three / busy if busy > 0 else 0.0}
 
     def summary(self) -> dict:
         lat = np.array(self.latencies_ms)
@@ -51,12 +73,15 @@ class ServeReport:
                "offered_load": self.load_target, "packet_scale": self.scale,
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "mean_ms": float(lat.mean()), "packets_per_s": self.packets / self.wall,
-               "service_ms_alone": self.service_ms}
+               "chord_wavelengths_per_s": self.chord_wavelengths / self.wall,
+               "service_ms_alone": self.service_ms, "concurrency": self.overlap()}
         for k in ("albedo", "emission", "transmission"):
             sel = [l for l, kk in zip(self.latencies_ms, self.kinds) if kk == k]
             if sel:
                 out[f"p50_ms_{k}"] = float(np.percentile(sel, 50))
                 out[f"p99_ms_{k}"] = float(np.percentile(sel, 99))
+        if self.alone:
+            out["alone_vs_mix"] = self.alone
         return out
 
 
@@ -121,7 +146,11 @@ def calibrate(ctx: M.Context, rate: float, load: float, precision: int = M.MCRT_
 
 
 def run_poisson(ctx: M.Context, rate: float = 20.0, duration: float = 60.0, load: float = 0.7, seed: int = 211015645,
-                precision: int = M.MCRT_MIXED, workers: int = 3, log=print) -> ServeReport:
+                precision: int = M.MCRT_MIXED, workers: int = 3, log=print, rerun_alone: int = 8) -> ServeReport:
+    """Poisson arrivals of the mix for `duration` seconds; each request has its
+    own transport seed.  Afterwards `rerun_alone` requests of each kind
+    (seeded choice) are run again with nothing else on the device and their
+    sums compared with the ones they got in the mix."""
     ctx.serve_config(workers)
     wl, st, scale = calibrate(ctx, rate, load, precision)
     by_kind = {w.kind: w for w in wl}
@@ -136,6 +165,7 @@ def run_poisson(ctx: M.Context, rate: float = 20.0, duration: float = 60.0, load
     kinds = rng.choice([k for k, _ in MIX], size=len(t_arr), p=[p for _, p in MIX])
     rep = ServeReport(rate, duration, len(t_arr), load, scale, service_ms=st)
     pending = {}
+    sums = {}
     t0 = time.perf_counter()
     nxt = 0
     last_log = t0
@@ -143,16 +173,21 @@ def run_poisson(ctx: M.Context, rate: float = 20.0, duration: float = 60.0, load
         now = time.perf_counter() - t0
         while nxt < len(t_arr) and t_arr[nxt] <= now:
             w = by_kind[kinds[nxt]]
-            tk = ctx.submit(w.mode, w.gid, w.oid, w.table, **w.kw)
-            pending[tk] = w
+            tk = ctx.submit(w.mode, w.gid, w.oid, w.table, **{**w.kw, "seed": seed + 1 + nxt})
+            pending[tk] = (w, nxt, time.perf_counter() - t0)
             nxt += 1
         done = [tk for tk in pending if ctx.poll(tk)]
         for tk in done:
-            w = pending.pop(tk)
+            w, q, t_sub = pending.pop(tk)
             r = ctx.wait(tk)
             rep.latencies_ms.append(r["latency_ms"])
             rep.kinds.append(w.kind)
-            rep.packets += w.packets
+            rep.spans.append((t_sub + r["queued_ms"] * 1e-3, t_sub + r["latency_ms"] * 1e-3))
+            sums[q] = r["sums"]
+            if w.kind == "transmission":
+                rep.chord_wavelengths += w.packets
+            else:
+                rep.packets += w.packets
         if time.perf_counter() - last_log > 10.0:
             last_log = time.perf_counter()
             log(f"[serve] t={now:.0f}s submitted {nxt}/{len(t_arr)} in flight {len(pending)}")
@@ -160,4 +195,17 @@ def run_poisson(ctx: M.Context, rate: float = 20.0, duration: float = 60.0, load
             wait_for = (t_arr[nxt] - (time.perf_counter() - t0)) if nxt < len(t_arr) else 0.002
             time.sleep(min(max(wait_for, 0.0), 0.002))
     rep.wall = time.perf_counter() - t0
+    if rerun_alone > 0:
+        pick = np.random.Generator(np.random.PCG64(seed + 7))
+        same, worst, n = 0, 0.0, 0
+        for k, _ in MIX:
+            idx = [q for q in range(len(t_arr)) if kinds[q] == k and q in sums]
+            for q in pick.choice(idx, size=min(rerun_alone, len(idx)), replace=False):
+                w = by_kind[k]
+                a = ctx.wait(ctx.submit(w.mode, w.gid, w.oid, w.table, **{**w.kw, "seed": seed + 1 + int(q)}))
+                d = np.abs(a["sums"] - sums[q]) / np.maximum(np.abs(sums[q]), 1e-300)
+                worst = max(worst, float(d.max()))
+                same += int(np.array_equal(a["sums"], sums[q]))
+                n += 1
+        rep.alone = {"requests": n, "identical": same, "max_rel_diff": worst}
     return rep

@@ -25,5 +25,5 @@ def _profile_sha(name):
 def test_traffic_constants_match_the_profile_summaries():
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.TRAFFIC_KERNEL_SHA in _profile_sha("k_transport_persistent_emission_3d.md")
-    assert bench.TRAFFIC_K5_SHA in _profile_sha("k_chord_tau_transmission_hires.md")
+    assert bench.K4_PROFILE["sha"] in _profile_sha("k_transport_persistent_emission_3d.md")
+    assert bench.K5_PROFILE["sha"] in _profile_sha("k_chord_tau_transmission_hires.md")

@@ -116,5 +116,15 @@ def test_transmission_hires_full_size_sampled(ctx, torch_dev):
     np.testing.assert_allclose(got["sums"][picks], ref.sums, rtol=RTOL)
     np.testing.assert_allclose(got["value"][picks], ref.value, rtol=1e-12)
     assert np.all(np.isfinite(got["value"])) and np.all(got["value"] > 0.0)
+    # the mixed form (FP32 extinction rows, FP64 optical depths) in the same
+    # launch configuration: every wavelength within 1e-3 of the FP64 sums and
+    # 3 sigma of its depths, the sampled ones within 1e-3 of the oracle
+    from paper_2110_15640_amd import mcrt as M
+    mix = ctx.solve_transmission(gid, oid, table, precision=M.MCRT_MIXED, **kw)
+    rel = np.abs(mix["sums"][..., 0] - got["sums"][..., 0]) / np.abs(got["sums"][..., 0])
+    _log(f"  mixed vs FP64 sums: max rel {rel.max():.3e}")
+    assert rel.max() < 1e-3
+    assert np.all(np.abs(mix["value"] - got["value"]) <= 3.0 * got["stderr"])
+    np.testing.assert_allclose(mix["sums"][picks][..., 0], ref.sums[..., 0], rtol=1e-3)
     ctx.free_grid(gid)
     ctx.free_opacity(oid)

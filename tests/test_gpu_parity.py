@@ -215,6 +215,12 @@ def test_transmission_ck_parity(ctx, torch_dev):
     np.testing.assert_allclose(got["value"], ref.value, rtol=1e-12)
     np.testing.assert_allclose(got["per_g"], ref.per_g, rtol=1e-12)
     np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL)
+    # mixed form: FP32 extinction rows, FP64 optical depths -- within 1e-3
+    # (observed ~1e-7) of the FP64 sums and within 3 sigma of its values
+    from paper_2110_15640_amd import mcrt as M
+    mix = ctx.solve_transmission(gid, oid, table, precision=M.MCRT_MIXED, **kw)
+    np.testing.assert_allclose(mix["sums"][..., 0], got["sums"][..., 0], rtol=1e-3)
+    assert np.all(np.abs(mix["value"] - got["value"]) <= 3.0 * got["stderr"])
     ctx.free_grid(gid)
     ctx.free_opacity(oid)
 
@@ -229,6 +235,10 @@ def test_transmission_hires_parity_multi_block(ctx, torch_dev):
     ref = O.solve_transmission(grid, table, O.Params(**kw), spec_idx=spec)
     np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL)
     np.testing.assert_allclose(got["value"], ref.value, rtol=1e-12)
+    from paper_2110_15640_amd import mcrt as M
+    mix = ctx.solve_transmission(gid, oid, table, spec_idx=spec, precision=M.MCRT_MIXED, **kw)
+    np.testing.assert_allclose(mix["sums"][..., 0], ref.sums[..., 0], rtol=1e-3)
+    assert np.all(np.abs(mix["value"] - ref.value) <= 3.0 * got["stderr"])
     ctx.free_grid(gid)
     ctx.free_opacity(oid)
 
