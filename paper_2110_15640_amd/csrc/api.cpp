@@ -2033,6 +2033,14 @@ int grid_upload(mcrt_ctx* ctx, const mcrt_grid_desc* d, hipStream_t st, int32_t*
     UP(lon_s, los.data(), los.size(), dp);
     UP(lon_c, loc.data(), loc.size(), dp);
     UP(vol_r, volr.data(), volr.size(), dp);
+    std::vector<double> faces;
+    faces.reserve((size_t)nlay + 1 + 3 * ((size_t)nlat + 1) + 2 * (size_t)nlon);
+    faces.insert(faces.end(), d->r_edges, d->r_edges + nlay + 1);
+    gd.lat_base = (int)faces.size();
+    for (int e = 0; e <= nlat; ++e) faces.insert(faces.end(), {lat[e], ls2[e], lc2[e]});
+    gd.lon_base = (int)faces.size();
+    for (int e = 0; e < nlon; ++e) faces.insert(faces.end(), {los[e], loc[e]});
+    UP(faces, faces.data(), faces.size(), dp);
     if (borrow) {  // read in place; the caller owns them
         gd.T = d->T;
         gd.P = d->P;

@@ -457,6 +457,7 @@ struct Walker {
     double hi1, hi2;        // upper latitude cone roots
     double tlo, thi;        // lower / upper longitude half-plane hits
     int i, j, k;
+    int c;                  // cell index (k * nlat + j) * nlon + i, kept as the walk moves
     int ef;                 // face by which the current cell was entered
 };
 
@@ -494,8 +495,31 @@ __host__ __device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, 
     }
 }
 
+// Coefficients of the latitude cone z^2 cos^2(lat) = (x^2 + y^2) sin^2(lat)
+// along p0 + t d: a t^2 + 2 b t + c = 0.  The exact form evaluates them as
+// written; the fast form (FP32-mixed transport) uses cos^2 + sin^2 = 1 and
+// |d| = 1, i.e. a = dz^2 - sin^2, b = pz dz - (p0.d) sin^2,
+// c = pz^2 - |p0|^2 sin^2 (three multiply-adds instead of fifteen operations).
+template <bool FAST>
+__host__ __device__ __forceinline__ void wk_cone_coef(const GridDev& g, const Walker& w, int e, double& a, double& b,
+                                                      double& c)
+{
+    const double s2 = g.lat_s2[e];
+    if constexpr (FAST) {
+        a = fma(w.dz, w.dz, -s2);
+        b = fma(w.pz, w.dz, -(w.B0 * s2));
+        c = fma(w.pz, w.pz, -(w.C0 * s2));
+    } else {
+        const double c2 = g.lat_c2[e];
+        a = w.dz * w.dz * c2 - (w.dx * w.dx + w.dy * w.dy) * s2;
+        b = w.pz * w.dz * c2 - (w.px * w.dx + w.py * w.dy) * s2;
+        c = w.pz * w.pz * c2 - (w.px * w.px + w.py * w.py) * s2;
+    }
+}
+
 // Roots of the latitude cone of edge e on the nappe of its sign (or the
 // equatorial plane), ascending, INFINITY where absent.
+template <bool FAST = false>
 __host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker& w, int e, double& r1, double& r2)
 {
     r1 = INFINITY;
@@ -505,10 +529,8 @@ __host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker&
         if (w.dz != 0.0) r1 = -w.pz / w.dz;
         return;
     }
-    double c2 = g.lat_c2[e], s2 = g.lat_s2[e];
-    double a = w.dz * w.dz * c2 - (w.dx * w.dx + w.dy * w.dy) * s2;
-    double b = w.pz * w.dz * c2 - (w.px * w.dx + w.py * w.dy) * s2;
-    double c = w.pz * w.pz * c2 - (w.px * w.px + w.py * w.py) * s2;
+    double a, b, c;
+    wk_cone_coef<FAST>(g, w, e, a, b, c);
     double x0 = INFINITY, x1 = INFINITY;
     if (a == 0.0) {
         if (b != 0.0) x0 = -c / (2.0 * b);
@@ -542,6 +564,7 @@ __host__ __device__ __forceinline__ double wk_plane(const GridDev& g, const Walk
     return (cb * hx + sb * hy > 0.0) ? th : INFINITY;
 }
 
+template <bool FAST = false>
 __host__ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, double px, double py, double pz, double dx,
                                          double dy, double dz, int i, int j, int k, int ef)
 {
@@ -549,6 +572,7 @@ __host__ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, d
     w.dx = dx; w.dy = dy; w.dz = dz;
     w.t = 0.0;
     w.i = i; w.j = j; w.k = k;
+    w.c = (k * g.nlat + j) * g.nlon + i;
     w.ef = ef;
     w.B0 = px * dx + py * dy + pz * dz;
     w.C0 = px * px + py * py + pz * pz;
@@ -556,8 +580,8 @@ __host__ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, d
     w.lo1 = w.lo2 = w.hi1 = w.hi2 = INFINITY;
     w.tlo = w.thi = INFINITY;
     if (g.geom == 1) return;
-    if (j > 0) wk_cone(g, w, j, w.lo1, w.lo2);
-    if (j < g.nlat - 1) wk_cone(g, w, j + 1, w.hi1, w.hi2);
+    if (j > 0) wk_cone<FAST>(g, w, j, w.lo1, w.lo2);
+    if (j < g.nlat - 1) wk_cone<FAST>(g, w, j + 1, w.hi1, w.hi2);
     if (g.nlon > 1) {
         w.tlo = wk_plane(g, w, i, false);
         w.thi = wk_plane(g, w, i + 1 == g.nlon ? 0 : i + 1, true);
@@ -575,7 +599,8 @@ __host__ __device__ __forceinline__ double wk_next_root(double r1, double r2, do
 
 // Parameter and face of the next crossing (ties: outer, inner, lat-low,
 // lat-high, lon-low, lon-high).
-__host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double& tf)
+template <bool FAST = false>
+__host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& w, double& tf, double r_top = 0.0)
 {
     double best = w.tout;
     int face = w.tout < INFINITY ? F_OUT : F_NONE;
@@ -586,9 +611,10 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
     }
     // entry-face tolerance 1e-9 |p|, with |p| bounded by the cell's outer
     // radius (it only separates a re-found root of the cone just crossed,
-    // ~1e-16 |p| away, from genuine ones)
+    // ~1e-16 |p| away, from genuine ones); the fast form bounds |p| by the
+    // top of the grid, r_top (the caller's, no gather per step)
     double lo = w.t;
-    if (w.ef == F_LATLO || w.ef == F_LATHI) lo = w.t + 1e-9 * g.r[w.k + 1];
+    if (w.ef == F_LATLO || w.ef == F_LATHI) lo = w.t + 1e-9 * (FAST ? r_top : g.r[w.k + 1]);
     double a = wk_next_root(w.lo1, w.lo2, w.t, w.ef == F_LATLO ? lo : w.t);
     if (a < best) { best = a; face = F_LATLO; }
     double b = wk_next_root(w.hi1, w.hi2, w.t, w.ef == F_LATHI ? lo : w.t);
@@ -639,33 +665,67 @@ __host__ __device__ __forceinline__ double wk_div(double a, double b)
 // per-kind selects pick the roots.  The arithmetic of each kind is the same,
 // operation for operation, as in wk_shells, wk_cone and wk_plane (in the
 // exact form; FAST: see wk_mad and wk_div).
+// The grid-table values a crossing reads, loaded by wk_cross_begin so that a
+// caller can issue other loads (the extinction gather) before the crossing's
+// arithmetic in wk_cross_end waits for them: v1 = the new sphere's radius,
+// the cone's latitude or the plane's sin(lon); v2 = the cone's sin^2(lat) or
+// the plane's cos(lon); v3 = the cone's cos^2(lat) (exact form only).
+struct CrossIn {
+    double v1, v2, v3;
+    bool inside;
+};
+
+// Index update and table loads of a crossing, without branches: every lane
+// of a wave runs the same instructions whatever face it crosses (a lane with
+// no face, f < 0, keeps its indices and loads in-range entries it ignores).
 template <bool FAST = false>
-__host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
+__host__ __device__ __forceinline__ CrossIn wk_cross_begin(const GridDev& g, Walker& w, int f, double tf)
 {
+    CrossIn x;
     w.t = tf;
-    if (f < 0) return false;
+    const bool valid = f >= 0;
+    const bool shell = valid && f <= F_IN, cone = f == F_LATLO || f == F_LATHI, plane = f == F_LONLO || f == F_LONHI;
+    const bool outward = f == F_OUT, down = f == F_LATLO, west = f == F_LONLO;
+    const int dk = shell ? (outward ? 1 : -1) : 0;
+    const int dj = cone ? (down ? -1 : 1) : 0;
+    const bool wrap = west ? (w.i == 0) : (w.i + 1 == g.nlon);
+    const int ni = west ? (w.i == 0 ? g.nlon - 1 : w.i - 1) : (w.i + 1 == g.nlon ? 0 : w.i + 1);
+    const int di = plane ? (west ? (wrap ? g.nlon - 1 : -1) : (wrap ? 1 - g.nlon : 1)) : 0;
+    w.k += dk;
+    w.j += dj;
+    w.i = plane ? ni : w.i;
+    w.c += dk * (g.nlon * g.nlat) + dj * g.nlon + di;
+    w.ef = shell ? (outward ? F_IN : F_OUT)
+                 : (cone ? (down ? F_LATHI : F_LATLO) : (plane ? (west ? F_LONHI : F_LONLO) : w.ef));
+    x.inside = valid && w.k < g.nlay && w.k >= 0;
+    const int kr = outward ? w.k + 1 : w.k;
+    const int kk = kr < 0 ? 0 : (kr > g.nlay ? g.nlay : kr);
+    const int e = down ? w.j : w.j + 1;
+    const bool has = down ? w.j > 0 : w.j < g.nlat - 1;
+    const int ee = g.lat_base + 3 * ((cone && has) ? e : 0);
+    const int ep = g.lon_base + 2 * (west ? w.i : (w.i + 1 == g.nlon ? 0 : w.i + 1));
+    const int o1 = shell ? kk : (cone ? ee : ep);
+    const int o2 = (cone ? ee : ep) + 1;
+    x.v1 = g.faces[o1];
+    x.v2 = g.faces[o2];
+    x.v3 = FAST ? 0.0 : g.faces[ee + 2];
+    return x;
+}
+
+template <bool FAST = false>
+__host__ __device__ __forceinline__ bool wk_cross_end(const GridDev& g, Walker& w, int f, const CrossIn& x)
+{
+    if (!x.inside) return false;
     const bool shell = f <= F_IN, cone = f == F_LATLO || f == F_LATHI;
     const bool outward = f == F_OUT, down = f == F_LATLO, west = f == F_LONLO;
     const bool slab = g.geom == 1;
-    // indices of the new cell
-    if (shell) {
-        w.k += outward ? 1 : -1;
-        w.ef = outward ? F_IN : F_OUT;
-        if (w.k >= g.nlay || w.k < 0) return false;
-    } else if (cone) {
-        w.j += down ? -1 : 1;
-        w.ef = down ? F_LATHI : F_LATLO;
-    } else {
-        w.i = west ? (w.i == 0 ? g.nlon - 1 : w.i - 1) : (w.i + 1 == g.nlon ? 0 : w.i + 1);
-        w.ef = west ? F_LONHI : F_LONLO;
-    }
     // the new surface: coefficients of A t^2 + 2 B t + C (A = 0: B2 t + C)
     double A = 0.0, B = 0.0, C = 0.0, B2 = 0.0;
     bool has = true;     // a surface to intersect at all
     bool equator = false;
     double tb = 0.0, sb = 0.0, cb = 0.0;
     if (shell) {
-        const double R = g.r[outward ? w.k + 1 : w.k];
+        const double R = x.v1;
         has = outward || slab || w.B0 < 0.0;
         if (slab) {
             B2 = w.dz;
@@ -676,25 +736,29 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
             C = wk_mad<FAST>(-R, R, w.C0);
         }
     } else if (cone) {
-        const int e = down ? w.j : w.j + 1;
         has = down ? w.j > 0 : w.j < g.nlat - 1;
-        const int ee = has ? e : 0;
-        tb = g.lat[ee];
-        const double c2 = g.lat_c2[ee], s2 = g.lat_s2[ee];
+        tb = x.v1;
         equator = tb == 0.0;
         if (equator) {
             B2 = w.dz;
             C = w.pz;
         } else {
-            A = wk_mad<FAST>(w.dz * w.dz, c2, -(wk_mad<FAST>(w.dx, w.dx, w.dy * w.dy) * s2));
-            B = wk_mad<FAST>(w.pz * w.dz, c2, -(wk_mad<FAST>(w.px, w.dx, w.py * w.dy) * s2));
-            C = wk_mad<FAST>(w.pz * w.pz, c2, -(wk_mad<FAST>(w.px, w.px, w.py * w.py) * s2));
+            const double s2 = x.v2;
+            if constexpr (FAST) {  // as wk_cone_coef's fast form
+                A = fma(w.dz, w.dz, -s2);
+                B = fma(w.pz, w.dz, -(w.B0 * s2));
+                C = fma(w.pz, w.pz, -(w.C0 * s2));
+            } else {
+                const double c2 = x.v3;
+                A = wk_mad<FAST>(w.dz * w.dz, c2, -(wk_mad<FAST>(w.dx, w.dx, w.dy * w.dy) * s2));
+                B = wk_mad<FAST>(w.pz * w.dz, c2, -(wk_mad<FAST>(w.px, w.dx, w.py * w.dy) * s2));
+                C = wk_mad<FAST>(w.pz * w.pz, c2, -(wk_mad<FAST>(w.px, w.px, w.py * w.py) * s2));
+            }
             B2 = 2.0 * B;
         }
     } else {
-        const int e = west ? w.i : (w.i + 1 == g.nlon ? 0 : w.i + 1);
-        sb = g.lon_s[e];
-        cb = g.lon_c[e];
+        sb = x.v1;
+        cb = x.v2;
         const double nx = -sb, ny = cb;
         const double dn = wk_mad<FAST>(w.dx, nx, w.dy * ny);
         has = west ? dn < 0.0 : dn > 0.0;
@@ -785,10 +849,14 @@ __host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, i
     return true;
 }
 
-__host__ __device__ __forceinline__ int wk_cell(const GridDev& g, const Walker& w)
+template <bool FAST = false>
+__host__ __device__ __forceinline__ bool wk_cross(const GridDev& g, Walker& w, int f, double tf)
 {
-    return (w.k * g.nlat + w.j) * g.nlon + w.i;
+    const CrossIn x = wk_cross_begin<FAST>(g, w, f, tf);
+    return wk_cross_end<FAST>(g, w, f, x);
 }
+
+__host__ __device__ __forceinline__ int wk_cell(const GridDev& /*g*/, const Walker& w) { return w.c; }
 
 }  // namespace dev
 }  // namespace mcrt

@@ -27,6 +27,12 @@ struct GridDev {
     const double* lon_s;   // sin(lon edge) [nlon]
     const double* lon_c;   // cos(lon edge) [nlon]
     const double* vol_r;   // (r_{k+1}^3 - r_k^3)/3 [nlay]
+    // the edge values a crossing reads, in one array so that one base and a
+    // per-lane offset reach any of them: r[k] at k; (lat, sin^2, cos^2) of
+    // latitude edge e at lat_base + 3 e; (sin, cos) of longitude edge e at
+    // lon_base + 2 e
+    const double* faces;
+    int lat_base, lon_base;
     const float* T;
     const float* P;
     const double* rho;

@@ -43,12 +43,18 @@ enum { M_FLIGHT = 0, M_PEEL = 1, M_PROBE = 2, M_EVENT = 3, M_DEAD = 4, M_BIRTH =
 constexpr int kProbeDone = 15, kTauSet = 14;
 enum { E_INTERACT = 0, E_ESCAPE = 1, E_SURFACE = 2, E_LOST = 3, E_PEEL_DONE = 4 };
 // Birth record of a packet, kept in the counter columns of its row until the
-// packet dies: position, direction, weight, cell * 8 + (entry face + 1)
-// (-1: nothing emits), then the index of the solve whose optics it uses;
+// packet dies: position, direction, weight, packed cell (i | j << 11 | k << 21)
+// * 8 + (entry face + 1) (-1: nothing emits), then the index of the solve
+// whose optics it uses;
 // with a Lambert floor, the weight the floor has absorbed so far; with
 // forced interactions, the unscattered fractions booked so far to the floor
 // (B_SURF) and to escape (B_FESC).
 enum { B_X = 0, B_Y, B_Z, B_DX, B_DY, B_DZ, B_W, B_CELL, B_SOLVE, B_SURF, B_FESC };
+
+__host__ __device__ __forceinline__ unsigned long long pack_ijk(int i, int j, int k)
+{
+    return (unsigned long long)i | ((unsigned long long)j << 11) | ((unsigned long long)k << 21);
+}
 
 // Per-lane state that the cell walk does not touch lives in LDS (one slot
 // per lane, structure of arrays) so the registers hold only the walking ray;
@@ -137,6 +143,13 @@ __device__ __forceinline__ double ld(const void* p, int c)
     return ((gdouble*)p)[c];
 }
 
+// Address of cell c's value in a per-cell array of the precision's type.
+template <bool MIXED>
+__device__ __forceinline__ const void* cell_addr(const void* p, int c)
+{
+    return MIXED ? (const void*)((const float*)p + c) : (const void*)((const double*)p + c);
+}
+
 // Write the packet's row: its peel-off sums, then the counters; `kind` says
 // where its remaining weight went.  EXT (here and below): the kernel form
 // with the Lambert floor, Draine clouds, forced interactions and
@@ -192,7 +205,7 @@ __device__ __forceinline__ void observer(Lane& L, const BatchArgs& A, const doub
 // observer, or, before a forced flight, the probe along the packet
 // direction.  All use one inlined walker start, so a wave starting several
 // kinds runs it once.
-template <bool EXT>
+template <bool MIXED, bool EXT>
 __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const BatchArgs& A, const double* sobs,
                                            bool flight)
 {
@@ -212,7 +225,7 @@ __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const Batc
             L.tau = 0.0;
             ef = F_NONE;
         }
-        wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
+        wk_start<MIXED>(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
         L.ncw = 0;
         L.mode = flight ? M_FLIGHT : M_PEEL;
         if (!flight && g.geom == 1 && !(dz > 0.0)) {  // a slab peel-off ray that never reaches the top
@@ -244,7 +257,7 @@ __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const Batc
             dz = L.sdz();
         }
         if (kind == M_PROBE) L.o() = kProbeDone;
-        wk_start(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
+        wk_start<MIXED>(g, L.w, L.sx(), L.sy(), L.sz(), dx, dy, dz, L.si(), L.sj(), L.sk(), ef);
         L.ncw = 0;
         L.mode = kind;
         // a slab peel-off ray that never reaches the top, or a floor peel-off
@@ -268,24 +281,30 @@ __device__ __forceinline__ void start_walk(Lane& L, const GridDev& g, const Batc
 // never kept in two versions.
 template <bool MIXED, bool EXT>
 __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void* aext, const void* aabs,
-                                          const BatchArgs& A)
+                                          const BatchArgs& A, double r_top)
 {
     double tf;
-    const int f = wk_next(g, L.w, tf);
+    const int f = wk_next<MIXED>(g, L.w, tf, r_top);
     const double s = tf - L.w.t;
     const int c = wk_cell(g, L.w);
     const bool flight = L.mode == M_FLIGHT;
     const bool cont = flight && A.absorption == 1;
-    const double ae = ld<MIXED>(aext, c);
-    const double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
-    const double a = cont ? (ae - aa) : ae;
-    const bool lost = flight && f == F_NONE && !(a > 0.0);
-    const bool hit = flight && !lost && a > 0.0 && L.tau < a * s;
-    const bool pend = !flight && f == F_NONE;
     // the walk's parameter and cell before the crossing (the walker keeps its
     // origin and direction, so the interaction point follows from them)
     const double t0 = L.w.t;
     const int ei = L.w.i, ej = L.w.j, ek = L.w.k;
+    // the grid-table loads of the crossing, then the extinction gather (its
+    // address formed first); the crossing's arithmetic waits only for the
+    // former, so the gather's latency overlaps it
+    const void* pe = cell_addr<MIXED>(aext, c);
+    const CrossIn xin = wk_cross_begin<MIXED>(g, L.w, f, tf);
+    const double ae = ld<MIXED>(pe, 0);
+    const double aa = cont ? ld<MIXED>(aabs, c) : 0.0;
+    const bool inside = wk_cross_end<MIXED>(g, L.w, f, xin);
+    const double a = cont ? (ae - aa) : ae;
+    const bool lost = flight && f == F_NONE && !(a > 0.0);
+    const bool hit = flight && !lost && a > 0.0 && L.tau < a * s;
+    const bool pend = !flight && f == F_NONE;
     if (flight) {
         if (!lost && !hit) L.tau = wk_mad<MIXED>(-a, s, L.tau);
         if (cont && !lost) {
@@ -297,7 +316,6 @@ __device__ __forceinline__ void walk_step(Lane& L, const GridDev& g, const void*
     } else if (!pend) {
         L.tau = wk_mad<MIXED>(ae, s, L.tau);
     }
-    const bool inside = wk_cross<MIXED>(g, L.w, f, tf);
     if (lost || hit || pend) {
         L.ncross += L.ncw;
         L.mode = M_EVENT;
@@ -690,7 +708,7 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
             double mu0 = A.mu0 > 0.0 ? A.mu0 : sqrt(1.0 - u.a);
             b[B_X] = 0.0; b[B_Y] = 0.0; b[B_Z] = g.r[g.nlay];
             b[B_DX] = sqrt(fmax(1.0 - mu0 * mu0, 0.0)); b[B_DY] = 0.0; b[B_DZ] = -mu0;
-            b[B_CELL] = (double)((g.nlay - 1) * 8 + (F_OUT + 1));
+            b[B_CELL] = (double)(((unsigned long long)(g.nlay - 1) << 21) * 8 + (F_OUT + 1));
         } else {
             double rho = r_toa * sqrt(u.a);
             double a = 2.0 * kPi * u.b;
@@ -701,8 +719,7 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
             locate_column(g, rs);
             b[B_X] = x; b[B_Y] = y; b[B_Z] = z;
             b[B_DX] = -1.0; b[B_DY] = 0.0; b[B_DZ] = 0.0;
-            int c = ((g.nlay - 1) * g.nlat + rs.j) * g.nlon + rs.i;
-            b[B_CELL] = (double)c * 8.0 + (double)(F_OUT + 1);
+            b[B_CELL] = (double)(pack_ijk(rs.i, rs.j, g.nlay - 1) * 8 + (F_OUT + 1));
         }
         b[B_W] = wmul;
         return;
@@ -721,8 +738,7 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
         locate_column(g, rs);
         b[B_X] = rs.x; b[B_Y] = rs.y; b[B_Z] = rs.z;
         b[B_DX] = -1.0; b[B_DY] = 0.0; b[B_DZ] = 0.0;
-        const int c = ((g.nlay - 1) * g.nlat + rs.j) * g.nlon + rs.i;
-        b[B_CELL] = (double)c * 8.0 + (double)(F_OUT + 1);
+        b[B_CELL] = (double)(pack_ijk(rs.i, rs.j, g.nlay - 1) * 8 + (F_OUT + 1));
         b[B_W] = bi * limb_weight(A.ld, rs.y, rs.z) * wmul;
         return;
     }
@@ -763,7 +779,7 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
     b[B_DY] = sp * sin(psi);
     b[B_DZ] = mu;
     b[B_W] = S.wbirth[c] * wmul;
-    b[B_CELL] = (double)c * 8.0 + (double)(F_NONE + 1);
+    b[B_CELL] = (double)(pack_ijk(i, j, k) * 8 + (F_NONE + 1));
 }
 
 // The records of a block's packets are built in LDS and its rows written
@@ -817,10 +833,9 @@ __device__ __forceinline__ int birth(Lane& L, const GridDev& g, const BatchArgs&
         L.ev = -1;
         return A_FINISH;
     }
-    const long long cc = (long long)cw;
-    const int c = (int)(cc >> 3);
+    const unsigned long long cc = (unsigned long long)cw;
+    L.C->ijk[L.t] = (uint32_t)(cc >> 3);
     L.set_sef((int)(cc & 7) - 1);
-    L.set_cell(c % g.nlon, (c / g.nlon) % g.nlat, c / (g.nlon * g.nlat));
     L.sx() = b[B_X]; L.sy() = b[B_Y]; L.sz() = b[B_Z];
     L.sdx() = b[B_DX]; L.sdy() = b[B_DY]; L.sdz() = b[B_DZ];
     if (S.mode == 0) return A_FLIGHT;
@@ -853,9 +868,10 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
     cold.st[threadIdx.x] = 0u;
     const void* aext = nullptr;
     const void* aabs = nullptr;
+    const double r_top1 = MULTI ? 0.0 : g1.r[g1.nlay];  // top of the grid (the fast walk's tolerance scale)
     for (;;) {
         const GridDev& g = MULTI ? A.grids[lgrid] : g1;
-        if (L.mode <= M_PROBE) walk_step<MIXED, EXT>(L, g, aext, aabs, A);
+        if (L.mode <= M_PROBE) walk_step<MIXED, EXT>(L, g, aext, aabs, A, MULTI ? g.r[g.nlay] : r_top1);
         unsigned long long evm = __ballot(L.mode == M_EVENT);
         unsigned long long walking = __ballot(L.mode <= M_PROBE);
         if (__popcll(evm) < A.ev_threshold && walking != 0) continue;
@@ -921,7 +937,7 @@ __global__ void __launch_bounds__(kTPB, MINB) k_transport_persistent(GridDev g1,
             }
         }
         const GridDev& ga = MULTI ? A.grids[lgrid] : g1;
-        if (act == A_FLIGHT || act == A_PEEL) start_walk<EXT>(L, ga, A, sobs, act == A_FLIGHT);
+        if (act == A_FLIGHT || act == A_PEEL) start_walk<MIXED, EXT>(L, ga, A, sobs, act == A_FLIGHT);
         if (__ballot(L.mode != M_IDLE) == 0) break;
     }
 }
