@@ -437,6 +437,56 @@ __device__ __forceinline__ double interp_tp(F lnk, const Bracket& bt, const Brac
 }
 
 
+// Arithmetic of a crossing.  The exact form rounds every product and sum on
+// its own and divides correctly rounded, operation for operation as the FP64
+// oracle; the fast form, taken by the FP32-mixed transport, contracts a
+// product and a sum into one multiply-add and divides through the hardware
+// reciprocal refined by two Newton steps and a residual correction (within a
+// few ulp of the rounded quotient).
+template <bool FAST>
+__host__ __device__ __forceinline__ double wk_mad(double a, double b, double c)
+{
+    if constexpr (FAST) return fma(a, b, c);
+    else return a * b + c;
+}
+
+template <bool FAST>
+__host__ __device__ __forceinline__ double wk_div(double a, double b)
+{
+    if constexpr (FAST) {
+        double r = __builtin_amdgcn_rcp(b);
+        r = fma(r, fma(-b, r, 1.0), r);
+        r = fma(r, fma(-b, r, 1.0), r);
+        const double qt = a * r;
+        return fma(fma(-b, qt, a), r, qt);
+    } else {
+        return a / b;
+    }
+}
+
+// Square root of x >= 0 (finite).  The fast form refines the hardware
+// reciprocal square root y ~ 1/sqrt(x) by Goldschmidt's iteration (g = x y,
+// h = y/2, r = 1/2 - h g, g <- g + g r, h <- h + h r) and two corrections
+// g <- g + (x - g^2) h, which bring it within an ulp or so of the rounded
+// root; without the library's range scaling, which these operands (squared
+// lengths of ~1e9 cm and their differences) never need.
+template <bool FAST>
+__host__ __device__ __forceinline__ double wk_sqrt(double x)
+{
+    if constexpr (FAST) {
+        const double y = __builtin_amdgcn_rsq(x);
+        double g = x * y, h = 0.5 * y;
+        const double r = fma(-h, g, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        g = fma(fma(-g, g, x), h, g);
+        g = fma(fma(-g, g, x), h, g);
+        return x > 0.0 ? g : 0.0;
+    } else {
+        return sqrt(x);
+    }
+}
+
 // ---------------------------------------------------------------- walker
 // Straight-line walk through the cells from an origin p0 along unit d.  Along
 // a straight line every face surface is met at fixed ray parameters t (a
@@ -461,31 +511,34 @@ struct Walker {
     int ef;                 // face by which the current cell was entered
 };
 
+// The faces of a walk's first cell (wk_start); FAST: the fast arithmetic of
+// wk_mad, wk_div and wk_sqrt, otherwise every operation rounded on its own.
+template <bool FAST = false>
 __host__ __device__ __forceinline__ void wk_shells(const GridDev& g, Walker& w, bool need_out, bool need_in)
 {
     if (g.geom == 1) {
-        if (need_out) w.tout = w.dz > 0.0 ? fmax((g.r[w.k + 1] - w.pz) / w.dz, w.t) : INFINITY;
-        if (need_in) w.tin = w.dz < 0.0 ? fmax((g.r[w.k] - w.pz) / w.dz, w.t) : INFINITY;
+        if (need_out) w.tout = w.dz > 0.0 ? fmax(wk_div<FAST>(g.r[w.k + 1] - w.pz, w.dz), w.t) : INFINITY;
+        if (need_in) w.tin = w.dz < 0.0 ? fmax(wk_div<FAST>(g.r[w.k] - w.pz, w.dz), w.t) : INFINITY;
         return;
     }
     if (need_out) {
         double R = g.r[w.k + 1];
-        double C = w.C0 - R * R;
-        double D = w.B0 * w.B0 - C;
+        double C = wk_mad<FAST>(-R, R, w.C0);
+        double D = wk_mad<FAST>(w.B0, w.B0, -C);
         if (D < 0.0) D = 0.0;
-        double sq = sqrt(D);
-        double far = (w.B0 <= 0.0) ? (-w.B0 + sq) : (-C / (w.B0 + sq));
+        double sq = wk_sqrt<FAST>(D);
+        double far = (w.B0 <= 0.0) ? (-w.B0 + sq) : wk_div<FAST>(-C, w.B0 + sq);
         w.tout = fmax(far, w.t);
     }
     if (need_in) {
         w.tin = INFINITY;
         if (w.B0 < 0.0) {
             double R = g.r[w.k];
-            double C = w.C0 - R * R;
-            double D = w.B0 * w.B0 - C;
+            double C = wk_mad<FAST>(-R, R, w.C0);
+            double D = wk_mad<FAST>(w.B0, w.B0, -C);
             if (D >= 0.0) {
-                const double q = -w.B0 + sqrt(D);
-                double nr = C / q;
+                const double q = -w.B0 + wk_sqrt<FAST>(D);
+                double nr = wk_div<FAST>(C, q);
                 if (nr >= w.t || C < 0.0) {
                     w.tin = fmax(nr, w.t);
                     w.tin_far = q;
@@ -526,25 +579,26 @@ __host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker&
     r2 = INFINITY;
     double tb = g.lat[e];
     if (tb == 0.0) {
-        if (w.dz != 0.0) r1 = -w.pz / w.dz;
+        if (w.dz != 0.0) r1 = wk_div<FAST>(-w.pz, w.dz);
         return;
     }
     double a, b, c;
     wk_cone_coef<FAST>(g, w, e, a, b, c);
     double x0 = INFINITY, x1 = INFINITY;
     if (a == 0.0) {
-        if (b != 0.0) x0 = -c / (2.0 * b);
+        if (b != 0.0) x0 = wk_div<FAST>(-c, 2.0 * b);
     } else {
-        double disc = b * b - a * c;
+        double disc = wk_mad<FAST>(b, b, -(a * c));
         if (disc >= 0.0) {
-            double sq = sqrt(disc);
+            double sq = wk_sqrt<FAST>(disc);
             double q = -(b + (b >= 0.0 ? sq : -sq));
-            x0 = q / a;
-            if (q != 0.0) x1 = c / q;
+            x0 = wk_div<FAST>(q, a);
+            if (q != 0.0) x1 = wk_div<FAST>(c, q);
         }
     }
-    bool ok0 = x0 < INFINITY && (tb > 0.0 ? (w.pz + x0 * w.dz > 0.0) : (w.pz + x0 * w.dz < 0.0));
-    bool ok1 = x1 < INFINITY && (tb > 0.0 ? (w.pz + x1 * w.dz > 0.0) : (w.pz + x1 * w.dz < 0.0));
+    const double z0 = wk_mad<FAST>(x0, w.dz, w.pz), z1 = wk_mad<FAST>(x1, w.dz, w.pz);
+    bool ok0 = x0 < INFINITY && (tb > 0.0 ? (z0 > 0.0) : (z0 < 0.0));
+    bool ok1 = x1 < INFINITY && (tb > 0.0 ? (z1 > 0.0) : (z1 < 0.0));
     if (!ok0) x0 = INFINITY;
     if (!ok1) x1 = INFINITY;
     r1 = fmin(x0, x1);
@@ -553,15 +607,16 @@ __host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker&
 }
 
 // Hit of the longitude half-plane of edge e (upper = the cell's upper face).
+template <bool FAST = false>
 __host__ __device__ __forceinline__ double wk_plane(const GridDev& g, const Walker& w, int e, bool upper)
 {
     double sb = g.lon_s[e], cb = g.lon_c[e];
     double nx = -sb, ny = cb;
-    double dn = w.dx * nx + w.dy * ny;
+    double dn = wk_mad<FAST>(w.dx, nx, w.dy * ny);
     if (upper ? !(dn > 0.0) : !(dn < 0.0)) return INFINITY;
-    double th = fmax(-(w.px * nx + w.py * ny) / dn, w.t);
-    double hx = w.px + th * w.dx, hy = w.py + th * w.dy;
-    return (cb * hx + sb * hy > 0.0) ? th : INFINITY;
+    double th = fmax(wk_div<FAST>(-wk_mad<FAST>(w.px, nx, w.py * ny), dn), w.t);
+    double hx = wk_mad<FAST>(th, w.dx, w.px), hy = wk_mad<FAST>(th, w.dy, w.py);
+    return (wk_mad<FAST>(cb, hx, sb * hy) > 0.0) ? th : INFINITY;
 }
 
 template <bool FAST = false>
@@ -576,15 +631,15 @@ __host__ __device__ __forceinline__ void wk_start(const GridDev& g, Walker& w, d
     w.ef = ef;
     w.B0 = px * dx + py * dy + pz * dz;
     w.C0 = px * px + py * py + pz * pz;
-    wk_shells(g, w, true, true);
+    wk_shells<FAST>(g, w, true, true);
     w.lo1 = w.lo2 = w.hi1 = w.hi2 = INFINITY;
     w.tlo = w.thi = INFINITY;
     if (g.geom == 1) return;
     if (j > 0) wk_cone<FAST>(g, w, j, w.lo1, w.lo2);
     if (j < g.nlat - 1) wk_cone<FAST>(g, w, j + 1, w.hi1, w.hi2);
     if (g.nlon > 1) {
-        w.tlo = wk_plane(g, w, i, false);
-        w.thi = wk_plane(g, w, i + 1 == g.nlon ? 0 : i + 1, true);
+        w.tlo = wk_plane<FAST>(g, w, i, false);
+        w.thi = wk_plane<FAST>(g, w, i + 1 == g.nlon ? 0 : i + 1, true);
     }
 }
 
@@ -623,33 +678,6 @@ __host__ __device__ __forceinline__ int wk_next(const GridDev& g, const Walker& 
     if (w.thi < best) { best = w.thi; face = F_LONHI; }
     tf = best;
     return face;
-}
-
-// Arithmetic of a crossing.  The exact form rounds every product and sum on
-// its own and divides correctly rounded, operation for operation as the FP64
-// oracle; the fast form, taken by the FP32-mixed transport, contracts a
-// product and a sum into one multiply-add and divides through the hardware
-// reciprocal refined by two Newton steps and a residual correction (within a
-// few ulp of the rounded quotient).
-template <bool FAST>
-__host__ __device__ __forceinline__ double wk_mad(double a, double b, double c)
-{
-    if constexpr (FAST) return fma(a, b, c);
-    else return a * b + c;
-}
-
-template <bool FAST>
-__host__ __device__ __forceinline__ double wk_div(double a, double b)
-{
-    if constexpr (FAST) {
-        double r = __builtin_amdgcn_rcp(b);
-        r = fma(r, fma(-b, r, 1.0), r);
-        r = fma(r, fma(-b, r, 1.0), r);
-        const double qt = a * r;
-        return fma(fma(-b, qt, a), r, qt);
-    } else {
-        return a / b;
-    }
 }
 
 // Move to parameter tf on face f, enter the neighbour cell and compute the
@@ -768,7 +796,7 @@ __host__ __device__ __forceinline__ bool wk_cross_end(const GridDev& g, Walker& 
     // one solve for every lane
     const bool quad = A != 0.0;
     const double D = wk_mad<FAST>(B, B, -(A * C));
-    const double sq = sqrt(fmax(D, 0.0));
+    const double sq = wk_sqrt<FAST>(fmax(D, 0.0));
     const bool neg = cone ? B >= 0.0 : B > 0.0;  // the sign rule of each kind at B = 0
     const double q = neg ? -(B + sq) : (-B + sq);
     // one division gives the near root q / A of a quadric (a shell has A = 1)
