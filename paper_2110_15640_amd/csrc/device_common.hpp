@@ -592,8 +592,18 @@ __host__ __device__ __forceinline__ void wk_cone(const GridDev& g, const Walker&
         if (disc >= 0.0) {
             double sq = wk_sqrt<FAST>(disc);
             double q = -(b + (b >= 0.0 ? sq : -sq));
-            x0 = wk_div<FAST>(q, a);
-            if (q != 0.0) x1 = wk_div<FAST>(c, q);
+            if constexpr (FAST) {  // both roots from one reciprocal, as in wk_cross_end
+                if (q != 0.0) {
+                    const double inv = wk_div<true>(1.0, a * q);
+                    x0 = (q * q) * inv;
+                    x1 = (c * a) * inv;
+                } else {
+                    x0 = 0.0;
+                }
+            } else {
+                x0 = wk_div<FAST>(q, a);
+                if (q != 0.0) x1 = wk_div<FAST>(c, q);
+            }
         }
     }
     const double z0 = wk_mad<FAST>(x0, w.dz, w.pz), z1 = wk_mad<FAST>(x1, w.dz, w.pz);
@@ -801,9 +811,20 @@ __host__ __device__ __forceinline__ bool wk_cross_end(const GridDev& g, Walker& 
     const double q = neg ? -(B + sq) : (-B + sq);
     // one division gives the near root q / A of a quadric (a shell has A = 1)
     // or the root -C / B2 of a linear face, whichever the lane has
-    const double rd = wk_div<FAST>(quad ? q : -C, quad ? A : B2);
+    double rd, x1q;
+    if constexpr (FAST) {
+        // both roots of a quadric from one reciprocal, 1/(A q): q/A = q^2/(A q)
+        // and C/q = C A/(A q); a linear face's root -C/B2 from 1/B2
+        const bool qz = quad && q == 0.0;
+        const double den = quad ? (qz ? A : A * q) : B2;
+        const double inv = wk_div<true>(1.0, den);
+        rd = quad ? (qz ? 0.0 : (q * q) * inv) : -C * inv;
+        x1q = (quad && !qz) ? (C * A) * inv : INFINITY;
+    } else {
+        rd = wk_div<FAST>(quad ? q : -C, quad ? A : B2);
+        x1q = (quad && q != 0.0) ? wk_div<FAST>(C, q) : INFINITY;
+    }
     const double x0q = rd;
-    const double x1q = (quad && q != 0.0) ? wk_div<FAST>(C, q) : INFINITY;
     const double xl = (!quad && B2 != 0.0) ? rd : INFINITY;
     if (shell) {
         if (slab) {
