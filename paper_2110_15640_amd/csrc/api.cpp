@@ -1236,8 +1236,13 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     if ((rc = slot_scratch(ctx, sl, st, "seg_cell", sizeof(uint32_t) * (size_t)std::max(nseg, 1LL), &v_sc))) return rc;
     if ((rc = slot_scratch(ctx, sl, st, "seg_len", sizeof(double) * (size_t)std::max(nseg, 1LL), &v_sl))) return rc;
     const LimbDark ld{p->ld_law, p->ld_c1, p->ld_c2, p->transit_y, p->transit_z, p->r_star};
-    launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
-                      (double*)v_b, (int*)v_ok, ld, st);
+    const bool mixed = p->precision == MCRT_MIXED;
+    if (mixed)
+        launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (float*)v_sl,
+                          (double*)v_b, (int*)v_ok, ld, st);
+    else
+        launch_chord_fill(g->dev, p->n_b, p->n_alpha, p->seed, tag, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl,
+                          (double*)v_b, (int*)v_ok, ld, st);
     if (op->kind == MCRT_OPAC_HIRES) {
         launch_doppler_shift(g->dev, -1.0, 0.0, 0.0, op->dlnlam, (double*)v_shift, st);
         launch_cell_tp(g->dev, ncell, op->nT, op->nP, op->T_grid, op->lnP_grid, (CellTP*)v_tp, st);
@@ -1261,11 +1266,10 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
                                      (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
         if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st);
-        launch_chord_tau(nch, (long long*)v_off, (uint32_t*)v_sc, (double*)v_sl, (double*)v_b, (int*)v_ok,
+        launch_chord_tau(p->n_b, p->n_alpha, (long long*)v_off, (uint32_t*)v_sc, (const R*)v_sl, (double*)v_b, (int*)v_ok,
                          (const R*)alpha, nslot, (double*)v_part, tblocks, st);
         if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot) + 1], st);
     };
-    const bool mixed = p->precision == MCRT_MIXED;
     for (int r0 = 0; r0 < nrow; r0 += kSlot) {
         int nslot = std::min(kSlot, nrow - r0);
         if (mixed) rows_block((float*)v_alpha, r0, nslot);

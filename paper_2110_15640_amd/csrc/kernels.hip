@@ -81,6 +81,26 @@ __global__ void __launch_bounds__(256) k_doppler_shift(GridDev g, double ox, dou
     shift[c] = log1p(-vlos / kC) / dlnlam;
 }
 
+// ln-kappa bilinear in (T, ln P) in FP32 (the mixed form's stored extinction
+// is FP32): weights, the weighted sum and the exponential in single
+// precision, the zero-corner rule as in interp_tp.
+template <typename F>
+__device__ __forceinline__ float interp_tp_f32(F lnk, const Bracket& bt, const Bracket& bp)
+{
+    const float t = (float)bt.t, u = (float)bp.t;
+    const float w0 = (1.0f - t) * (1.0f - u), w1 = (1.0f - t) * u, w2 = t * (1.0f - u), w3 = t * u;
+    float acc = 0.0f;
+    if (w0 > 0.0f) { double l = lnk(bt.i0, bp.i0); if (isinf(l)) return 0.0f; acc = fmaf(w0, (float)l, acc); }
+    if (w1 > 0.0f) { double l = lnk(bt.i0, bp.i1); if (isinf(l)) return 0.0f; acc = fmaf(w1, (float)l, acc); }
+    if (w2 > 0.0f) { double l = lnk(bt.i1, bp.i0); if (isinf(l)) return 0.0f; acc = fmaf(w2, (float)l, acc); }
+    if (w3 > 0.0f) { double l = lnk(bt.i1, bp.i1); if (isinf(l)) return 0.0f; acc = fmaf(w3, (float)l, acc); }
+    return __expf(acc);
+}
+
+// kappa at table position n + shift, linear in kappa between the two
+// neighbouring table wavelengths, clamped at the table ends; R = float
+// evaluates it in single precision (the fractional index stays FP64).
+template <typename R>
 __device__ __forceinline__ double hires_kappa(const double* __restrict__ lnk_tpl, int nlam, int nP,
                                               const Bracket& bt, const Bracket& bp, int n, double shift)
 {
@@ -91,10 +111,19 @@ __device__ __forceinline__ double hires_kappa(const double* __restrict__ lnk_tpl
     else if (x <= 0.0) { n0 = 0; fr = 0.0; }
     else if (x >= (double)(nlam - 1)) { n0 = nlam - 2; fr = 1.0; }
     else { n0 = (int)floor(x); fr = x - (double)n0; }
-    double k0 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
-    if (nlam == 1) return k0;
-    double k1 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
-    return (1.0 - fr) * k0 + fr * k1;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        const float k0 = interp_tp_f32([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
+        if (nlam == 1) return (double)k0;
+        const float k1 =
+            interp_tp_f32([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
+        const float f = (float)fr;
+        return (double)fmaf(f, k1, (1.0f - f) * k0);
+    } else {
+        double k0 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
+        if (nlam == 1) return k0;
+        double k1 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
+        return (1.0 - fr) * k0 + fr * k1;
+    }
 }
 
 // alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
@@ -111,6 +140,8 @@ __global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, i
     out[c] = CellTP{bt.i0, bt.i1, bp.i0, bp.i1, bt.t, bp.t};
 }
 
+constexpr int kAlphaCells = 4;  // cells per thread of the hi-res extinction block
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
                                                            int nlam, int nP, const CellTP* __restrict__ tp,
@@ -119,17 +150,26 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
                                                            const int* __restrict__ nlist, int nslot,
                                                            int slot_stride, R* __restrict__ alpha)
 {
+    // thread (cell group, slot): kAlphaCells cells one after another, so each
+    // wave has several independent chains of cell -> table loads in flight
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)ncell * nslot) return;
-    int c = (int)(t / nslot), s = (int)(t % nslot);
-    int n = nlist[s];
-    const CellTP q = tp[c];
-    Bracket bt, bp;
-    bt.i0 = q.ti0; bt.i1 = q.ti1; bt.t = q.tt;
-    bp.i0 = q.pi0; bp.i1 = q.pi1; bp.t = q.pt;
-    double kl = hires_kappa(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
-    double kext = kl + k_ray[n];
-    alpha[(size_t)c * slot_stride + s] = (R)(g.rho[c] * kext);
+    const int ngroup = (ncell + kAlphaCells - 1) / kAlphaCells;
+    if (t >= (long long)ngroup * nslot) return;
+    const int c0 = (int)(t / nslot) * kAlphaCells, s = (int)(t % nslot);
+    const int n = nlist[s];
+    const double kr = k_ray[n];
+#pragma unroll
+    for (int u = 0; u < kAlphaCells; ++u) {
+        const int c = c0 + u;
+        if (c >= ncell) break;
+        const CellTP q = tp[c];
+        Bracket bt, bp;
+        bt.i0 = q.ti0; bt.i1 = q.ti1; bt.t = q.tt;
+        bp.i0 = q.pi0; bp.i1 = q.pi1; bp.t = q.pt;
+        double kl = hires_kappa<R>(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
+        double kext = kl + kr;
+        alpha[(size_t)c * slot_stride + s] = (R)(g.rho[c] * kext);
+    }
 }
 
 // (emission sources for the transport live in prep.hip)
@@ -226,9 +266,11 @@ __global__ void __launch_bounds__(256) k_chord_count(GridDev g, int n_b, int n_a
     counts[ch] = n;
 }
 
+// R: type of the stored segment lengths (FP64, or FP32 in the mixed form).
+template <typename R>
 __global__ void __launch_bounds__(256) k_chord_fill(GridDev g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
                                                     const long long* __restrict__ offsets,
-                                                    uint32_t* __restrict__ seg_cell, double* __restrict__ seg_len,
+                                                    uint32_t* __restrict__ seg_cell, R* __restrict__ seg_len,
                                                     double* __restrict__ chord_b, int* __restrict__ chord_ok,
                                                     LimbDark ld)
 {
@@ -247,7 +289,7 @@ __global__ void __launch_bounds__(256) k_chord_fill(GridDev g, int n_b, int n_al
         int f = exit_distance(g, p, -1.0, 0.0, 0.0, s);
         if (f == F_NONE) break;
         seg_cell[o] = (uint32_t)cell_of(g, p);
-        seg_len[o] = s;
+        seg_len[o] = (R)s;
         ++o;
         advance(g, p, -1.0, 0.0, 0.0, s);
         cross(g, p, f);
@@ -294,10 +336,13 @@ constexpr int kChordsPerWave = 8;
 
 // R: the stored extinction (double, or float in the mixed form: half the
 // gathered bytes); tau accumulates in FP64 either way.
+// Blocks run consecutive chords (one impact parameter, consecutive limb
+// angles), so the blocks resident at a time cross a thin shell of cells whose
+// extinction rows the caches hold; a wave walks its chords one after another.
 template <typename R>
 __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __restrict__ offsets,
                                                    const uint32_t* __restrict__ seg_cell,
-                                                   const double* __restrict__ seg_len,
+                                                   const R* __restrict__ seg_len,
                                                    const double* __restrict__ chord_b,
                                                    const int* __restrict__ chord_ok,
                                                    const R* __restrict__ alpha, int nslot,
@@ -305,12 +350,13 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
 {
     __shared__ double sh1[kChordWaves][64];
     __shared__ double sh2[kChordWaves][64];
+    const int blk = (int)blockIdx.x;
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int s0 = 0; s0 < nslot; s0 += 64) {
         int s = s0 + lane;
         double a1 = 0.0, a2 = 0.0;
         for (int m = 0; m < kChordsPerWave; ++m) {
-            int ch = (blockIdx.x * kChordWaves + wave) * kChordsPerWave + m;
+            const int ch = (blk * kChordWaves + wave) * kChordsPerWave + m;
             if (ch >= nch) break;
             long long o0 = offsets[ch], o1 = offsets[ch + 1];
             double tau = 0.0;
@@ -321,7 +367,7 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
             for (long long c0 = o0; c0 < o1; c0 += 64) {
                 const int nseg = (int)(o1 - c0 < 64 ? o1 - c0 : 64);
                 uint32_t mc = 0;
-                double ml = 0.0;
+                R ml = (R)0;
                 if (lane < nseg) {
                     mc = seg_cell[c0 + lane];
                     ml = seg_len[c0 + lane];
@@ -329,7 +375,7 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
 #pragma unroll 8
                 for (int k = 0; k < nseg; ++k) {
                     const uint32_t cell = (uint32_t)__shfl((int)mc, k);
-                    const double len = __shfl(ml, k);
+                    const double len = (double)__shfl(ml, k);
                     if (s < nslot) tau = tau + (double)alpha[(size_t)cell * nslot + s] * len;
                 }
             }
@@ -347,7 +393,7 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
                 t1 = t1 + sh1[w][lane];
                 t2 = t2 + sh2[w][lane];
             }
-            double* row = partials + (size_t)blockIdx.x * (2 * nslot);
+            double* row = partials + (size_t)blk * (2 * nslot);
             row[2 * s] = t1;
             row[2 * s + 1] = t2;
         }
@@ -392,7 +438,7 @@ void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl
                               const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
                               int nslot, int slot_stride, R* alpha, hipStream_t stream)
 {
-    long long n = (long long)ncell * nslot;
+    long long n = (long long)((ncell + kAlphaCells - 1) / kAlphaCells) * nslot;
     hipLaunchKernelGGL(k_hires_alpha_block<R>, dim3(nblk(n, 256)), dim3(256), 0, stream, g, ncell, lnk_tpl, nlam,
                        nP, tp, k_ray, shift, nlist, nslot, slot_stride, alpha);
 }
@@ -428,28 +474,34 @@ void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* 
     hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(256), 0, stream, in, out, n);
 }
 
+template <typename R>
 void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag, const long long* offsets,
-                       uint32_t* seg_cell, double* seg_len, double* chord_b, int* chord_ok, const LimbDark& ld,
+                       uint32_t* seg_cell, R* seg_len, double* chord_b, int* chord_ok, const LimbDark& ld,
                        hipStream_t stream)
 {
     int nch = n_b * n_alpha;
-    hipLaunchKernelGGL(k_chord_fill, dim3(nblk(nch, 256)), dim3(256), 0, stream, g, n_b, n_alpha, seed, tag, offsets,
-                       seg_cell, seg_len, chord_b, chord_ok, ld);
+    hipLaunchKernelGGL(k_chord_fill<R>, dim3(nblk(nch, 256)), dim3(256), 0, stream, g, n_b, n_alpha, seed, tag,
+                       offsets, seg_cell, seg_len, chord_b, chord_ok, ld);
 }
+template void launch_chord_fill<double>(const GridDev&, int, int, uint64_t, uint32_t, const long long*, uint32_t*,
+                                        double*, double*, int*, const LimbDark&, hipStream_t);
+template void launch_chord_fill<float>(const GridDev&, int, int, uint64_t, uint32_t, const long long*, uint32_t*,
+                                       float*, double*, int*, const LimbDark&, hipStream_t);
 
 int chord_tau_blocks(int nch) { return nblk(nch, kChordWaves * kChordsPerWave); }
 
 template <typename R>
-void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell, const double* seg_len,
+void launch_chord_tau(int n_b, int n_alpha, const long long* offsets, const uint32_t* seg_cell, const R* seg_len,
                       const double* chord_b, const int* chord_ok, const R* alpha, int nslot, double* partials,
                       int nblocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_chord_tau<R>, dim3(nblocks), dim3(256), 0, stream, nch, offsets, seg_cell, seg_len,
-                       chord_b, chord_ok, alpha, nslot, partials);
+    const int nch = n_b * n_alpha;
+    hipLaunchKernelGGL(k_chord_tau<R>, dim3(nblocks), dim3(256), 0, stream, nch, offsets, seg_cell, seg_len, chord_b,
+                       chord_ok, alpha, nslot, partials);
 }
-template void launch_chord_tau<double>(int, const long long*, const uint32_t*, const double*, const double*,
+template void launch_chord_tau<double>(int, int, const long long*, const uint32_t*, const double*, const double*,
                                        const int*, const double*, int, double*, int, hipStream_t);
-template void launch_chord_tau<float>(int, const long long*, const uint32_t*, const double*, const double*,
+template void launch_chord_tau<float>(int, int, const long long*, const uint32_t*, const float*, const double*,
                                       const int*, const float*, int, double*, int, hipStream_t);
 
 }  // namespace mcrt

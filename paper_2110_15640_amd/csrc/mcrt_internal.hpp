@@ -196,12 +196,14 @@ void launch_chord_count(const GridDev& g, int n_b, int n_alpha, uint64_t seed, u
                         int* counts, hipStream_t stream);
 void launch_exclusive_scan_int(const int* in, long long* out, int n, long long* total_dev,
                                hipStream_t stream);
+// R = double, or float for the mixed form (segment lengths and extinction rows).
+template <typename R>
 void launch_chord_fill(const GridDev& g, int n_b, int n_alpha, uint64_t seed, uint32_t tag,
-                       const long long* offsets, uint32_t* seg_cell, double* seg_len,
+                       const long long* offsets, uint32_t* seg_cell, R* seg_len,
                        double* chord_b, int* chord_ok, const LimbDark& ld, hipStream_t stream);
 template <typename R>
-void launch_chord_tau(int nch, const long long* offsets, const uint32_t* seg_cell,
-                      const double* seg_len, const double* chord_b, const int* chord_ok,
+void launch_chord_tau(int n_b, int n_alpha, const long long* offsets, const uint32_t* seg_cell,
+                      const R* seg_len, const double* chord_b, const int* chord_ok,
                       const R* alpha, int nslot, double* partials, int nblocks,
                       hipStream_t stream);
 int chord_tau_blocks(int nch);
