@@ -372,11 +372,15 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
                     mc = seg_cell[c0 + lane];
                     ml = seg_len[c0 + lane];
                 }
-#pragma unroll 8
+                // every lane loads (a lane past the last slot reads slot 0 and
+                // drops it), so the loads of the unrolled segments issue
+                // together, unpredicated
+                const int sl = s < nslot ? s : 0;
+#pragma unroll 16
                 for (int k = 0; k < nseg; ++k) {
                     const uint32_t cell = (uint32_t)__shfl((int)mc, k);
                     const double len = (double)__shfl(ml, k);
-                    if (s < nslot) tau = tau + (double)alpha[(size_t)cell * nslot + s] * len;
+                    tau = tau + (double)alpha[(size_t)cell * nslot + sl] * len;
                 }
             }
             if (!chord_ok[ch]) tau = INFINITY;
