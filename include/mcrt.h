@@ -448,7 +448,7 @@ int mcrt_solve_batch(mcrt_ctx* ctx, int32_t n_items, const mcrt_batch_item* item
 
 /* Autotuner for the persistent transport launch shape: runs short trial
  * solves of this request (up to 4 of its spectral points with its packet
- * count, at most 1e6 each) over event thresholds {16, 24, 32}, blocks per
+ * count, at most 1e6 each) over event thresholds {20, 24, 28, 32}, blocks per
  * compute unit {3, 4} and wave batches {32, 128}, and writes the fastest into
  * params->tune_* (best_packets_per_s, if not NULL, receives its trial rate:
  * packets of all the trial's (spectral point, g) solves per second).

@@ -2361,14 +2361,14 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
     t.graph = 0;
     t.contrib = 0;
     t.image_npix = 0;
-    const int evs[3] = {16, 24, 32}, bpcs[2] = {3, 4}, wbs[2] = {32, 128};
+    const int evs[4] = {20, 24, 28, 32}, bpcs[2] = {3, 4}, wbs[2] = {32, 128};
     double best = -1.0;
     int be = evs[0], bb = bpcs[0], bw = wbs[0];
     std::vector<double> v(64 * 8), e(64 * 8);
     mcrt_result r{};
     r.value = v.data();
     r.stderr_ = e.data();
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 2; ++c) {
                 t.tune_ev_threshold = evs[a];

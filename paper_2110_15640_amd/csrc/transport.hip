@@ -435,11 +435,16 @@ __device__ __forceinline__ int scatter(Lane& L, const GridDev& g, const BatchArg
             ny = st * sp;
             nz = sgn * mu;
         }
+        // renormalised in FP64 (the traversal takes |d| = 1): one refined
+        // reciprocal square root and three products
         double ddx = nx, ddy = ny, ddz = nz;
-        double n = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-        L.sdx() = ddx / n;
-        L.sdy() = ddy / n;
-        L.sdz() = ddz / n;
+        const double nn = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
+        double y = __builtin_amdgcn_rsq(nn);
+        y = y * fma(-0.5 * nn, y * y, 1.5);
+        y = y * fma(-0.5 * nn, y * y, 1.5);
+        L.sdx() = ddx * y;
+        L.sdy() = ddy * y;
+        L.sdz() = ddz * y;
     } else {
         double mu = sf ? sqrt(u1.a) : ((usel < pg) ? sample_rayleigh(u1.a) : sample_hg(u1.a, globe));
         if (draine) {

@@ -320,7 +320,7 @@ def test_autotuner_picks_a_candidate_shape_that_keeps_results(ctx, torch_dev, mo
     fn = ctx.solve_albedo if mode == "albedo" else ctx.solve_emission
     kw = dict(n_packets=20000, seed=67, obs_phase=[0.0, 0.5], precision=M.MCRT_MIXED)
     tuned = ctx.autotune(mode, gid, oid, **kw)
-    assert tuned["tune_ev_threshold"] in (16, 24, 32)
+    assert tuned["tune_ev_threshold"] in (20, 24, 28, 32)
     assert tuned["tune_blocks_per_cu"] in (3, 4)
     assert tuned["tune_wave_batch"] in (32, 128)
     assert np.isfinite(tuned["trial_packets_per_s"]) and tuned["trial_packets_per_s"] > 0.0
