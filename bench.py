@@ -49,20 +49,39 @@ PEAK_HBM = 8000.0  # GB/s
 # workload.  Reported only while the kernel sources hash to `sha` and the run
 # matches that configuration (grid, packets per solve, observers, launch
 # shape, solves per launch); otherwise null.
+def _traffic(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib):
+    """HBM bytes from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled
+    by what it reads for a 1 GiB device copy (1,048,576 KiB each way)."""
+    return (fetch_kib * 1048576.0 / copy_fetch_kib + write_kib * 1048576.0 / copy_write_kib) * 1024.0
+
+
+def _busy(active_valu, wave_cycles, waves_per_simd=4):
+    return active_valu / wave_cycles * waves_per_simd
+
+
 K4_PROFILE = {
-    "sha": "12da1ef9c9a243d44c1034556529feae500e5df2d29f296c616772af915e7ff2",
-    "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4,
-    "launch": {"tune_ev_threshold": 32, "tune_blocks_per_cu": 4, "tune_wave_batch": 32},
-    "solves_per_launch": 168,
-    "bytes_per_launch": (150046959.375 * (1048576 / 524305.3125) + 24003375.59375 * 1.0) * 1024,
-    "valu_busy": 0.882,
+    "sha": "784c68d493abc66500e777463f1bc33c76c2d587440da6ca4d1d3bfbad43e49b",
+    "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
+    # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
+    "shapes": {
+        20: {"bytes_per_launch": _traffic(6.53936e8, 1.14488e8, 524342, 1.04859e6),
+             "valu_busy": _busy(1.64768e12, 6.96708e12)},
+        24: {"bytes_per_launch": _traffic(6.35264e8, 1.14179e8, 524316, 1.04858e6),
+             "valu_busy": _busy(1.62636e12, 6.79784e12)},
+        28: {"bytes_per_launch": _traffic(6.11883e8, 1.13914e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.63305e12, 6.75925e12)},
+        32: {"bytes_per_launch": _traffic(5.9057e8, 1.1368e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.66108e12, 6.82072e12)},
+    },
 }
 # The same for the chord optical-depth kernel of the transmission solve: bytes
 # per (chord segment, wavelength) over its launches.
 K5_PROFILE = {
-    "sha": "6ea9567c02174f389aa9d0c01488085c5f997a63030f58e9348fee2de27d2417",
-    "precision": 0, "n_segments": 7861278, "n_lambda": 20000,
-    "bytes_per_seg_wl": ((468570912.9375 * (1048576 / 524311.3125) + 902880.0) * 1024) / (7861278 * 20064),
+    "sha": "b13fe6912f0997fc95c872336ce4ff475c14565dedf6e73a91e480a0cc790d8c",
+    "n_segments": 7861278, "n_lambda": 20000,
+    # per precision (1 mixed: FP32 rows; 0 FP64), over 314 launches of 64 wavelengths (20,064)
+    "bytes_per_seg_wl": {1: _traffic(1.88577e8, 902880, 524726, 1.04923e6) / (7861278 * 20064),
+                         0: _traffic(4.6485e8, 902880, 524726, 1.04923e6) / (7861278 * 20064)},
 }
 
 
@@ -186,14 +205,14 @@ def transmission_leg(M, I):
             k5_bytes = nseg * nl * ab + nseg * nblk * 12.0 + nch * nblk * 12.0
             k5_gbps = k5_bytes / (r["kernel_ms"] * 1e-3) / 1e9
             P = K5_PROFILE
-            same = (kernel_sha("kernels.hip") == P["sha"] and prec == P["precision"] and nseg == P["n_segments"]
-                    and nl == P["n_lambda"])
+            same = kernel_sha("kernels.hip") == P["sha"] and nseg == P["n_segments"] and nl == P["n_lambda"]
             out[name] = {"ms": wall * 1e3, "chord_wavelengths_per_s": nch * nl / wall,
                          "chord_tau_kernel_ms": r["kernel_ms"], "chord_tau_launches": nblk, "segments": nseg,
                          "roofline": {"bound": "hbm", "kernel": f"k_chord_tau<{'float' if ab == 4 else 'double'}>",
                                       "achieved": k5_gbps, "peak": PEAK_HBM, "unit": "GB/s",
                                       "frac": k5_gbps / PEAK_HBM,
-                                      "traffic": P["bytes_per_seg_wl"] * nseg * nl / max(nblk, 1) if same else None,
+                                      "traffic": (P["bytes_per_seg_wl"][prec] * nseg * nl / max(nblk, 1)
+                                                  if same else None),
                                       "traffic_unit": "bytes per launch (mean)",
                                       "bytes_per_segment_wavelength": ab}}
         depth = res["mixed"]["value"][:, 0]
@@ -403,10 +422,12 @@ def main():
     k4_bytes = cross * ALPHA_BYTES_MIXED + nint * OMEGA_PGAS_BYTES + pk_step * a.steps * probes * CDF_PROBE_BYTES
     k4_gbps = k4_bytes / ksec / 1e9
     P = K4_PROFILE
-    same_run = (kernel_sha() == P["sha"] and [grid.nlon, grid.nlat, grid.nlay] == P["grid"]
-                and npk == P["packets_per_solve"] and len(phases) == P["n_obs"] and tune == P["launch"]
+    shape = P["shapes"].get(tune.get("tune_ev_threshold")) if (
+        tune.get("tune_blocks_per_cu") == 4 and tune.get("tune_wave_batch") == 32) else None
+    same_run = (shape is not None and kernel_sha() == P["sha"] and [grid.nlon, grid.nlat, grid.nlay] == P["grid"]
+                and npk == P["packets_per_solve"] and len(phases) == P["n_obs"]
                 and abs(solves_per_launch - P["solves_per_launch"]) < 1e-9)
-    traffic = P["bytes_per_launch"] if same_run else None
+    traffic = shape["bytes_per_launch"] if same_run else None
     avg_s = ksec / max(launches, 1)
     out = {
         "metric": METRIC, "value": value, "unit": "packets/s", "n_gpus": 1, "steps": a.steps,
@@ -433,7 +454,7 @@ def main():
                      "hbm_algorithmic_GBps": k4_gbps, "hbm_frac": k4_gbps / PEAK_HBM,
                      "hbm_algorithmic_bytes": k4_bytes,
                      "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9,
-                     "valu_busy": P["valu_busy"] if same_run else None},
+                     "valu_busy": shape["valu_busy"] if same_run else None},
     }
     if a.gsample:
         print("[bench] per-packet g sampling (composite), same packets per band", flush=True)
