@@ -208,6 +208,10 @@ def transmission_leg(M, I):
             same = kernel_sha("kernels.hip") == P["sha"] and nseg == P["n_segments"] and nl == P["n_lambda"]
             out[name] = {"ms": wall * 1e3, "chord_wavelengths_per_s": nch * nl / wall,
                          "chord_tau_kernel_ms": r["kernel_ms"], "chord_tau_launches": nblk, "segments": nseg,
+                         # the extinction blocks of one launch are formed while the previous launch's
+                         # chords are summed (two streams), so launches overlap: the same bytes over
+                         # the whole leg's wall time
+                         "chord_tau_bytes_over_leg_GBps": k5_bytes / wall / 1e9,
                          "roofline": {"bound": "hbm", "kernel": f"k_chord_tau<{'float' if ab == 4 else 'double'}>",
                                       "achieved": k5_gbps, "peak": PEAK_HBM, "unit": "GB/s",
                                       "frac": k5_gbps / PEAK_HBM,

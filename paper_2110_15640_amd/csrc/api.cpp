@@ -83,7 +83,9 @@ struct OpacRes {
 // Blocking solves use the context's main slot; each serving worker owns one.
 struct Slot {
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;  // second stream of a blocking transmission solve
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;  // ordering between the two streams
     std::vector<hipEvent_t> prof_ev;  // pairs around timed launches
     std::map<std::string, DevBuf> scratch;  // grow-only, by role
     bool stream_ordered = false;  // serving slots allocate with hipMallocAsync
@@ -280,7 +282,11 @@ int slot_init(Slot& sl)
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
         return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
-    if ((e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess)
+    if ((e = hipStreamCreateWithFlags(&sl.stream2, hipStreamNonBlocking)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    if ((e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.join, hipEventDisableTiming)) != hipSuccess)
         return fail(MCRT_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     return MCRT_OK;
 }
@@ -294,9 +300,15 @@ void slot_destroy(mcrt_ctx* ctx, Slot& sl)
     sl.prof_ev.clear();
     if (sl.ev0) (void)hipEventDestroy(sl.ev0);
     if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+    if (sl.fork) (void)hipEventDestroy(sl.fork);
+    if (sl.join) (void)hipEventDestroy(sl.join);
+    if (sl.stream2) {
+        (void)hipStreamSynchronize(sl.stream2);
+        (void)hipStreamDestroy(sl.stream2);
+    }
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    sl.stream = nullptr;
-    sl.ev0 = sl.ev1 = nullptr;
+    sl.stream = sl.stream2 = nullptr;
+    sl.ev0 = sl.ev1 = sl.fork = sl.join = nullptr;
 }
 
 template <typename T>
@@ -1209,9 +1221,16 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     if ((rc = slot_scratch(ctx, sl, st, "chord_off", sizeof(long long) * ((size_t)nch + 1), &v_off))) return rc;
     if ((rc = slot_scratch(ctx, sl, st, "chord_b", sizeof(double) * (size_t)nch, &v_b))) return rc;
     if ((rc = slot_scratch(ctx, sl, st, "chord_ok", sizeof(int) * (size_t)nch, &v_ok))) return rc;
-    if ((rc = slot_scratch(ctx, sl, st, "alpha_blk", sizeof(double) * (size_t)ncell * nslot_max, &v_alpha))) return rc;
+    // Blocking solves with more than one block of rows alternate the blocks
+    // between two streams with their own extinction and partial-sum buffers,
+    // so that one block's extinction rows are formed while the previous
+    // block's chords are summed; served requests use their one stream.
+    const int nbuf = (!sl.stream_ordered && nrow > kSlot) ? 2 : 1;
+    const size_t alpha_n = (size_t)ncell * nslot_max;
     int tblocks = chord_tau_blocks(nch);
-    if ((rc = slot_scratch(ctx, sl, st, "chord_part", sizeof(double) * (size_t)tblocks * 2 * nslot_max, &v_part))) return rc;
+    const size_t part_n = (size_t)tblocks * 2 * nslot_max;
+    if ((rc = slot_scratch(ctx, sl, st, "alpha_blk", sizeof(double) * alpha_n * nbuf, &v_alpha))) return rc;
+    if ((rc = slot_scratch(ctx, sl, st, "chord_part", sizeof(double) * part_n * nbuf, &v_part))) return rc;
     if ((rc = slot_scratch(ctx, sl, st, "chord_sums", sizeof(double) * (size_t)nrow * 2, &v_sums))) return rc;
     void* v_tp = nullptr;
     if (op->kind == MCRT_OPAC_HIRES) {
@@ -1251,7 +1270,7 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     // Per block of up to 64 spectral rows: extinction of every cell (FP64, or
     // FP32 in the mixed form: half the bytes the chords gather), then the
     // chords' optical depths, accumulated in FP64 either way.
-    auto rows_block = [&](auto* alpha, int r0, int nslot) {
+    auto rows_block = [&](auto* alpha, int r0, int nslot, hipStream_t st, double* part) {
         using R = std::remove_pointer_t<decltype(alpha)>;
         if (op->kind == MCRT_OPAC_CK) {
             for (int q = 0; q < nslot; ++q) {
@@ -1267,14 +1286,25 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
         }
         if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st);
         launch_chord_tau(p->n_b, p->n_alpha, (long long*)v_off, (uint32_t*)v_sc, (const R*)v_sl, (double*)v_b, (int*)v_ok,
-                         (const R*)alpha, nslot, (double*)v_part, tblocks, st);
+                         (const R*)alpha, nslot, part, tblocks, st);
         if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot) + 1], st);
+        launch_reduce_partials(part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
     };
+    hipStream_t st2 = nbuf == 2 ? sl.stream2 : st;
+    if (nbuf == 2) {  // the second stream starts after the common work above
+        HIPTRY(hipEventRecord(sl.fork, st));
+        HIPTRY(hipStreamWaitEvent(st2, sl.fork, 0));
+    }
     for (int r0 = 0; r0 < nrow; r0 += kSlot) {
-        int nslot = std::min(kSlot, nrow - r0);
-        if (mixed) rows_block((float*)v_alpha, r0, nslot);
-        else rows_block((double*)v_alpha, r0, nslot);
-        launch_reduce_partials((double*)v_part, tblocks, 2 * nslot, (double*)v_sums + 2 * (size_t)r0, st);
+        const int nslot = std::min(kSlot, nrow - r0), b = (r0 / kSlot) % nbuf;
+        hipStream_t sb = b ? st2 : st;
+        double* part = (double*)v_part + part_n * b;
+        if (mixed) rows_block((float*)v_alpha + alpha_n * b, r0, nslot, sb, part);
+        else rows_block((double*)v_alpha + alpha_n * b, r0, nslot, sb, part);
+    }
+    if (nbuf == 2) {  // the first stream waits for the second's last block
+        HIPTRY(hipEventRecord(sl.join, st2));
+        HIPTRY(hipStreamWaitEvent(st, sl.join, 0));
     }
     HIPTRY(hipGetLastError());
     std::vector<double> hs((size_t)nrow * 2);
