@@ -109,6 +109,9 @@ def parse():
                     help="time N randomly chosen requests of that batch in the plain FP64 form too (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the Poisson serving leg (0 = skip)")
+    ap.add_argument("--serve-workers", type=int, default=3, help="serving worker threads (requests on the device at once)")
+    ap.add_argument("--serve-scale", type=float, default=0.0,
+                    help="packet scale of the served requests (0 = calibrate to the offered load)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="run one 1 GiB device copy first (reference kernel for HBM counter scaling)")
     return ap.parse_args()
@@ -502,7 +505,8 @@ def main():
               "re-run alone", flush=True)
         from paper_2110_15640_amd import serve as SV
         with M.Context(0) as sctx:
-            rep = SV.run_poisson(sctx, rate=20.0, duration=a.serve_seconds, load=0.7,
+            rep = SV.run_poisson(sctx, rate=20.0, duration=a.serve_seconds, load=0.7, workers=a.serve_workers,
+                                 scale=a.serve_scale,
                                  log=lambda m: print(m, flush=True))
         out["serving"] = rep.summary()
     if a.cpu_baseline:

@@ -277,13 +277,21 @@ void release_scratch(mcrt_ctx* ctx, Slot& sl)
     sl.scratch.clear();
 }
 
-int slot_init(Slot& sl)
+// A slot's stream.  With own_queue (the serving workers) the stream is made
+// with a CU mask that covers every CU: the runtime then gives it a hardware
+// queue of its own instead of sharing one of its few default queues with
+// another stream, where two workers' launches would run one after the other.
+int slot_init(Slot& sl, bool own_queue = false, int n_cu = 0)
 {
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
+    if (own_queue && n_cu > 0) {
+        std::vector<uint32_t> mask((size_t)(n_cu + 31) / 32, 0xffffffffu);
+        if (n_cu % 32) mask.back() = (1u << (n_cu % 32)) - 1u;
+        if ((e = hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)mask.size(), mask.data())) != hipSuccess)
+            return fail(MCRT_EDEVICE, "hipExtStreamCreateWithCUMask: %s", hipGetErrorString(e));
+    } else if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess) {
         return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
-    if ((e = hipStreamCreateWithFlags(&sl.stream2, hipStreamNonBlocking)) != hipSuccess)
-        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
     if ((e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&sl.join, hipEventDisableTiming)) != hipSuccess)
@@ -713,10 +721,11 @@ int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
 
 // Solves per persistent launch for a serving request: a fixed share of the
 // budget, so that the admission estimate and the allocation agree, and at
-// most kServeLaunchPackets packets, so that a long request reaches the device
-// as a sequence of short launches between which other requests' launches
-// are dispatched (and each launch's share of the device is chosen anew).
-constexpr uint64_t kServeLaunchPackets = 1ull << 22;
+// most kServeLaunchPackets packets (about a quarter second of the whole
+// device), so that a very long request reaches the device as a sequence of
+// launches whose share of the device is chosen anew.  Splitting the
+// requests of an ordinary mix more finely only adds drain tails.
+constexpr uint64_t kServeLaunchPackets = 1ull << 26;
 int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve, uint64_t packets_per_solve)
 {
     uint64_t cap = std::min<uint64_t>(ctx->budget / 8, 24ULL << 30);
@@ -1226,6 +1235,10 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     // so that one block's extinction rows are formed while the previous
     // block's chords are summed; served requests use their one stream.
     const int nbuf = (!sl.stream_ordered && nrow > kSlot) ? 2 : 1;
+    if (nbuf == 2 && !sl.stream2) {  // made on first use: idle streams would still take a hardware queue share
+        hipError_t e = hipStreamCreateWithFlags(&sl.stream2, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
     const size_t alpha_n = (size_t)ncell * nslot_max;
     int tblocks = chord_tau_blocks(nch);
     const size_t part_n = (size_t)tblocks * 2 * nslot_max;
@@ -1959,7 +1972,7 @@ int submit(mcrt_ctx* ctx, int mode, int32_t gid, int32_t oid, const mcrt_solve_p
         }
         for (int w = 0; w < ctx->n_workers; ++w) {
             std::unique_ptr<Slot> sl(new Slot());
-            if ((rc = slot_init(*sl))) return rc;
+            if ((rc = slot_init(*sl, true, ctx->n_cu))) return rc;
             sl->stream_ordered = true;
             ctx->wslots.push_back(std::move(sl));
         }
@@ -2196,6 +2209,10 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
     int rc = slot_init(ctx->main);
     if (rc) return rc;
     if ((rc = slot_init(ctx->na))) return rc;
+    // The allocation-free entry point creates nothing on its calls: its second
+    // transmission stream is made here.
+    if ((e = hipStreamCreateWithFlags(&ctx->na.stream2, hipStreamNonBlocking)) != hipSuccess)
+        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     if (device < kNoallocDevices) {
         std::lock_guard<std::mutex> lk(g_noalloc_mu);
         if (!g_noalloc_ptr[device]) {

@@ -128,9 +128,13 @@ def service_times(ctx: M.Context, wl: List[Workload], reps: int = 2) -> Dict[str
 MIX = (("albedo", 0.50), ("emission", 0.35), ("transmission", 0.15))
 
 
-def calibrate(ctx: M.Context, rate: float, load: float, precision: int = M.MCRT_MIXED):
-    """Scale packets so that rate * E[service time alone] = load."""
+def calibrate(ctx: M.Context, rate: float, load: float, precision: int = M.MCRT_MIXED, scale: float = 0.0):
+    """Scale packets so that rate * E[service time alone] = load (scale > 0:
+    use that packet scale and only measure the service times)."""
     res = upload_inputs(ctx)
+    if scale > 0.0:
+        wl = build_workloads(res, scale, precision)
+        return wl, service_times(ctx, wl), scale
     scale = 1.0
     for _ in range(3):
         wl = build_workloads(res, scale, precision)
@@ -146,13 +150,14 @@ def calibrate(ctx: M.Context, rate: float, load: float, precision: int = M.MCRT_
 
 
 def run_poisson(ctx: M.Context, rate: float = 20.0, duration: float = 60.0, load: float = 0.7, seed: int = 211015645,
-                precision: int = M.MCRT_MIXED, workers: int = 3, log=print, rerun_alone: int = 8) -> ServeReport:
+                precision: int = M.MCRT_MIXED, workers: int = 3, log=print, rerun_alone: int = 8,
+                scale: float = 0.0) -> ServeReport:
     """Poisson arrivals of the mix for `duration` seconds; each request has its
     own transport seed.  Afterwards `rerun_alone` requests of each kind
     (seeded choice) are run again with nothing else on the device and their
     sums compared with the ones they got in the mix."""
     ctx.serve_config(workers)
-    wl, st, scale = calibrate(ctx, rate, load, precision)
+    wl, st, scale = calibrate(ctx, rate, load, precision, scale)
     by_kind = {w.kind: w for w in wl}
     rng = np.random.Generator(np.random.PCG64(seed))
     t_arr = []
