@@ -277,18 +277,25 @@ void release_scratch(mcrt_ctx* ctx, Slot& sl)
     sl.scratch.clear();
 }
 
-// A slot's stream.  With own_queue (the serving workers) the stream is made
-// with a CU mask that covers every CU: the runtime then gives it a hardware
-// queue of its own instead of sharing one of its few default queues with
-// another stream, where two workers' launches would run one after the other.
+// A stream on a hardware queue of its own: made with a CU mask that covers
+// every CU, which the runtime serves with a new queue instead of a share of
+// its few default ones.  Kernels of two streams that share a queue run one
+// after the other, so streams meant to overlap (the serving workers, the
+// two halves of a transmission solve) are made this way.
+int own_queue_stream(hipStream_t* st, int n_cu)
+{
+    std::vector<uint32_t> mask((size_t)(std::max(n_cu, 1) + 31) / 32, 0xffffffffu);
+    if (n_cu % 32) mask.back() = (1u << (n_cu % 32)) - 1u;
+    hipError_t e = hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipExtStreamCreateWithCUMask: %s", hipGetErrorString(e));
+    return MCRT_OK;
+}
+
 int slot_init(Slot& sl, bool own_queue = false, int n_cu = 0)
 {
     hipError_t e;
-    if (own_queue && n_cu > 0) {
-        std::vector<uint32_t> mask((size_t)(n_cu + 31) / 32, 0xffffffffu);
-        if (n_cu % 32) mask.back() = (1u << (n_cu % 32)) - 1u;
-        if ((e = hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)mask.size(), mask.data())) != hipSuccess)
-            return fail(MCRT_EDEVICE, "hipExtStreamCreateWithCUMask: %s", hipGetErrorString(e));
+    if (own_queue) {
+        if (int rc = own_queue_stream(&sl.stream, n_cu)) return rc;
     } else if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess) {
         return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     }
@@ -1235,10 +1242,8 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
     // so that one block's extinction rows are formed while the previous
     // block's chords are summed; served requests use their one stream.
     const int nbuf = (!sl.stream_ordered && nrow > kSlot) ? 2 : 1;
-    if (nbuf == 2 && !sl.stream2) {  // made on first use: idle streams would still take a hardware queue share
-        hipError_t e = hipStreamCreateWithFlags(&sl.stream2, hipStreamNonBlocking);
-        if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
-    }
+    if (nbuf == 2 && !sl.stream2)  // made on first use, so that slots that never need it hold no queue
+        if ((rc = own_queue_stream(&sl.stream2, ctx->n_cu))) return rc;
     const size_t alpha_n = (size_t)ncell * nslot_max;
     int tblocks = chord_tau_blocks(nch);
     const size_t part_n = (size_t)tblocks * 2 * nslot_max;
@@ -2211,8 +2216,7 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
     if ((rc = slot_init(ctx->na))) return rc;
     // The allocation-free entry point creates nothing on its calls: its second
     // transmission stream is made here.
-    if ((e = hipStreamCreateWithFlags(&ctx->na.stream2, hipStreamNonBlocking)) != hipSuccess)
-        return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    if ((rc = own_queue_stream(&ctx->na.stream2, ctx->n_cu))) return rc;
     if (device < kNoallocDevices) {
         std::lock_guard<std::mutex> lk(g_noalloc_mu);
         if (!g_noalloc_ptr[device]) {

@@ -333,6 +333,20 @@ __global__ void __launch_bounds__(256) k_scan_int(const int* __restrict__ in, lo
 // order into partials[block][slot][2].
 constexpr int kChordWaves = 4;
 constexpr int kChordsPerWave = 8;
+constexpr int kChordUnroll = 16;  // row gathers in flight per wave
+
+// Lane k's value of x, for every lane (k uniform across the wave).
+__device__ inline float lane_bcast(float x, int k)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), k));
+}
+__device__ inline double lane_bcast(double x, int k)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
 // R: the stored extinction (double, or float in the mixed form: half the
 // gathered bytes); tau accumulates in FP64 either way.
@@ -351,9 +365,14 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
     __shared__ double sh1[kChordWaves][64];
     __shared__ double sh2[kChordWaves][64];
     const int blk = (int)blockIdx.x;
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: chord bounds and segment counts then live
+    // in scalar registers and the per-segment tests are scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     for (int s0 = 0; s0 < nslot; s0 += 64) {
         int s = s0 + lane;
+        // every lane gathers (a lane past the last slot reads slot 0 and drops
+        // it), so the gathers issue unpredicated
+        const R* arow = alpha + (s < nslot ? s : 0);
         double a1 = 0.0, a2 = 0.0;
         for (int m = 0; m < kChordsPerWave; ++m) {
             const int ch = (blk * kChordWaves + wave) * kChordsPerWave + m;
@@ -362,8 +381,11 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
             double tau = 0.0;
             // the chord's segments in chunks of 64: each lane loads one (cell,
             // length) pair (coalesced), then the wave walks the chunk in
-            // segment order taking them from the lanes, so the row gathers of
-            // consecutive segments do not wait on one another's index loads
+            // segment order, sixteen segments at a time: their cell indices
+            // are broadcast to scalar registers, all sixteen row gathers are
+            // issued, and only then added in segment order.  (A loop over the
+            // chunk with a cross-lane shuffle in its body is not unrolled by
+            // the compiler, which then keeps one gather in flight per wave.)
             for (long long c0 = o0; c0 < o1; c0 += 64) {
                 const int nseg = (int)(o1 - c0 < 64 ? o1 - c0 : 64);
                 uint32_t mc = 0;
@@ -372,15 +394,18 @@ __global__ void __launch_bounds__(256) k_chord_tau(int nch, const long long* __r
                     mc = seg_cell[c0 + lane];
                     ml = seg_len[c0 + lane];
                 }
-                // every lane loads (a lane past the last slot reads slot 0 and
-                // drops it), so the loads of the unrolled segments issue
-                // together, unpredicated
-                const int sl = s < nslot ? s : 0;
-#pragma unroll 16
-                for (int k = 0; k < nseg; ++k) {
-                    const uint32_t cell = (uint32_t)__shfl((int)mc, k);
-                    const double len = (double)__shfl(ml, k);
-                    tau = tau + (double)alpha[(size_t)cell * nslot + sl] * len;
+                for (int k0 = 0; k0 < nseg; k0 += kChordUnroll) {
+                    R av[kChordUnroll];
+#pragma unroll
+                    for (int u = 0; u < kChordUnroll; ++u) {
+                        // k0 + u <= 63; lanes past the chunk hold cell 0, whose
+                        // row is read and dropped below
+                        const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane((int)mc, k0 + u);
+                        av[u] = arow[(size_t)cell * nslot];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChordUnroll; ++u)
+                        if (k0 + u < nseg) tau = tau + (double)av[u] * (double)lane_bcast(ml, k0 + u);
                 }
             }
             if (!chord_ok[ch]) tau = INFINITY;
