@@ -81,54 +81,74 @@ __global__ void __launch_bounds__(256) k_doppler_shift(GridDev g, double ox, dou
     shift[c] = log1p(-vlos / kC) / dlnlam;
 }
 
-// ln-kappa bilinear in (T, ln P) in FP32 (the mixed form's stored extinction
-// is FP32): weights, the weighted sum and the exponential in single
-// precision, the zero-corner rule as in interp_tp.
-template <typename F>
-__device__ __forceinline__ float interp_tp_f32(F lnk, const Bracket& bt, const Bracket& bp)
+// Bilinear ln-kappa in (T, ln P) from the four corner values l[] (order
+// (i0,i0), (i0,i1), (i1,i0), (i1,i1)), already loaded: the same terms in the
+// same order as interp_tp, a -inf corner with positive weight giving zero.
+// FP64, and FP32 for the mixed form (whose stored extinction is FP32):
+// weights, weighted sum and exponential in single precision.
+__device__ __forceinline__ double tp_vals_f64(const double* l, const Bracket& bt, const Bracket& bp)
+{
+    const double t = bt.t, u = bp.t;
+    const double w[4] = {(1.0 - t) * (1.0 - u), (1.0 - t) * u, t * (1.0 - u), t * u};
+    double acc = 0.0;
+    bool zero = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (w[q] > 0.0) {
+            zero = zero || isinf(l[q]);
+            acc = acc + w[q] * l[q];
+        }
+    return zero ? 0.0 : exp(acc);
+}
+__device__ __forceinline__ float tp_vals_f32(const double* l, const Bracket& bt, const Bracket& bp)
 {
     const float t = (float)bt.t, u = (float)bp.t;
-    const float w0 = (1.0f - t) * (1.0f - u), w1 = (1.0f - t) * u, w2 = t * (1.0f - u), w3 = t * u;
+    const float w[4] = {(1.0f - t) * (1.0f - u), (1.0f - t) * u, t * (1.0f - u), t * u};
     float acc = 0.0f;
-    if (w0 > 0.0f) { double l = lnk(bt.i0, bp.i0); if (isinf(l)) return 0.0f; acc = fmaf(w0, (float)l, acc); }
-    if (w1 > 0.0f) { double l = lnk(bt.i0, bp.i1); if (isinf(l)) return 0.0f; acc = fmaf(w1, (float)l, acc); }
-    if (w2 > 0.0f) { double l = lnk(bt.i1, bp.i0); if (isinf(l)) return 0.0f; acc = fmaf(w2, (float)l, acc); }
-    if (w3 > 0.0f) { double l = lnk(bt.i1, bp.i1); if (isinf(l)) return 0.0f; acc = fmaf(w3, (float)l, acc); }
-    return __expf(acc);
+    bool zero = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (w[q] > 0.0f) {
+            zero = zero || isinf(l[q]);
+            acc = fmaf(w[q], (float)l[q], acc);
+        }
+    return zero ? 0.0f : __expf(acc);
 }
 
-// kappa at table position n + shift, linear in kappa between the two
-// neighbouring table wavelengths, clamped at the table ends; R = float
-// evaluates it in single precision (the fractional index stays FP64).
-template <typename R>
-__device__ __forceinline__ double hires_kappa(const double* __restrict__ lnk_tpl, int nlam, int nP,
-                                              const Bracket& bt, const Bracket& bp, int n, double shift)
+// Table position n + shift split into the lower neighbour n0 and the
+// fraction fr, clamped at the table ends.
+__device__ __forceinline__ void hires_pos(int nlam, int n, double shift, int& n0, double& fr)
 {
-    double x = (double)n + shift;
-    int n0;
-    double fr;
+    const double x = (double)n + shift;
     if (nlam == 1) { n0 = 0; fr = 0.0; }
     else if (x <= 0.0) { n0 = 0; fr = 0.0; }
     else if (x >= (double)(nlam - 1)) { n0 = nlam - 2; fr = 1.0; }
     else { n0 = (int)floor(x); fr = x - (double)n0; }
+}
+
+// kappa at table position n0 + fr from the eight table values l[] (four
+// corners at n0, then the same four at n0 + 1), linear in kappa between the
+// two wavelengths; R = float evaluates it in single precision (the fraction
+// comes in FP64).
+template <typename R>
+__device__ __forceinline__ double hires_combine(const double* l, const Bracket& bt, const Bracket& bp, double fr,
+                                                int nlam)
+{
     if constexpr (sizeof(R) == sizeof(float)) {
-        const float k0 = interp_tp_f32([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
+        const float k0 = tp_vals_f32(l, bt, bp);
         if (nlam == 1) return (double)k0;
-        const float k1 =
-            interp_tp_f32([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
+        const float k1 = tp_vals_f32(l + 4, bt, bp);
         const float f = (float)fr;
         return (double)fmaf(f, k1, (1.0f - f) * k0);
     } else {
-        double k0 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0]; }, bt, bp);
+        const double k0 = tp_vals_f64(l, bt, bp);
         if (nlam == 1) return k0;
-        double k1 = interp_tp([&](int a, int b) { return lnk_tpl[((size_t)a * nP + b) * nlam + n0 + 1]; }, bt, bp);
+        const double k1 = tp_vals_f64(l + 4, bt, bp);
         return (1.0 - fr) * k0 + fr * k1;
     }
 }
 
-// alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
-// Threads run slot-fastest so a wave reads consecutive wavelengths of the
-// [T][P][lambda] table and writes a contiguous row.
+// Each cell's (T, ln P) brackets in the opacity table, once per solve.
 __global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, int nP,
                                                  const double* __restrict__ T_grid,
                                                  const double* __restrict__ lnP_grid, CellTP* __restrict__ out)
@@ -142,6 +162,9 @@ __global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, i
 
 constexpr int kAlphaCells = 4;  // cells per thread of the hi-res extinction block
 
+// alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
+// Threads run slot-fastest so a wave reads consecutive wavelengths of the
+// [T][P][lambda] table and writes a contiguous row.
 template <typename R>
 __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
                                                            int nlam, int nP, const CellTP* __restrict__ tp,
@@ -150,25 +173,50 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
                                                            const int* __restrict__ nlist, int nslot,
                                                            int slot_stride, R* __restrict__ alpha)
 {
-    // thread (cell group, slot): kAlphaCells cells one after another, so each
-    // wave has several independent chains of cell -> table loads in flight
+    // thread (cell group, slot), kAlphaCells cells each, in three passes so
+    // that the loads of one pass are all in flight together: the cells'
+    // brackets, shifts and densities; then the eight table values of every
+    // cell (a cell past the grid's end reads the last cell and is dropped);
+    // then kappa and the stores
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int ngroup = (ncell + kAlphaCells - 1) / kAlphaCells;
     if (t >= (long long)ngroup * nslot) return;
     const int c0 = (int)(t / nslot) * kAlphaCells, s = (int)(t % nslot);
     const int n = nlist[s];
     const double kr = k_ray[n];
+    CellTP q[kAlphaCells];
+    double sh[kAlphaCells], rho[kAlphaCells];
+#pragma unroll
+    for (int u = 0; u < kAlphaCells; ++u) {
+        const int c = c0 + u < ncell ? c0 + u : ncell - 1;
+        q[u] = tp[c];
+        sh[u] = shift ? shift[c] : 0.0;
+        rho[u] = g.rho[c];
+    }
+    const int d = nlam == 1 ? 0 : 1;
+    double lv[kAlphaCells][8];
+    double fr[kAlphaCells];
+#pragma unroll
+    for (int u = 0; u < kAlphaCells; ++u) {
+        int n0;
+        hires_pos(nlam, n, sh[u], n0, fr[u]);
+        const double* r00 = lnk_tpl + ((size_t)q[u].ti0 * nP + q[u].pi0) * nlam + n0;
+        const double* r01 = lnk_tpl + ((size_t)q[u].ti0 * nP + q[u].pi1) * nlam + n0;
+        const double* r10 = lnk_tpl + ((size_t)q[u].ti1 * nP + q[u].pi0) * nlam + n0;
+        const double* r11 = lnk_tpl + ((size_t)q[u].ti1 * nP + q[u].pi1) * nlam + n0;
+        lv[u][0] = r00[0]; lv[u][1] = r01[0]; lv[u][2] = r10[0]; lv[u][3] = r11[0];
+        lv[u][4] = r00[d]; lv[u][5] = r01[d]; lv[u][6] = r10[d]; lv[u][7] = r11[d];
+    }
 #pragma unroll
     for (int u = 0; u < kAlphaCells; ++u) {
         const int c = c0 + u;
         if (c >= ncell) break;
-        const CellTP q = tp[c];
         Bracket bt, bp;
-        bt.i0 = q.ti0; bt.i1 = q.ti1; bt.t = q.tt;
-        bp.i0 = q.pi0; bp.i1 = q.pi1; bp.t = q.pt;
-        double kl = hires_kappa<R>(lnk_tpl, nlam, nP, bt, bp, n, shift ? shift[c] : 0.0);
-        double kext = kl + kr;
-        alpha[(size_t)c * slot_stride + s] = (R)(g.rho[c] * kext);
+        bt.i0 = q[u].ti0; bt.i1 = q[u].ti1; bt.t = q[u].tt;
+        bp.i0 = q[u].pi0; bp.i1 = q[u].pi1; bp.t = q[u].pt;
+        const double kl = hires_combine<R>(lv[u], bt, bp, fr[u], nlam);
+        const double kext = kl + kr;
+        alpha[(size_t)c * slot_stride + s] = (R)(rho[u] * kext);
     }
 }
 
