@@ -77,11 +77,11 @@ K4_PROFILE = {
 # The same for the chord optical-depth kernel of the transmission solve: bytes
 # per (chord segment, wavelength) over its launches.
 K5_PROFILE = {
-    "sha": "b13fe6912f0997fc95c872336ce4ff475c14565dedf6e73a91e480a0cc790d8c",
+    "sha": "938f3ced1b4e4fd4f9b210b9db7cad9df42f8fe93c53128fcfba8f20ca915336",
     "n_segments": 7861278, "n_lambda": 20000,
     # per precision (1 mixed: FP32 rows; 0 FP64), over 314 launches of 64 wavelengths (20,064)
-    "bytes_per_seg_wl": {1: _traffic(1.88577e8, 902880, 524726, 1.04923e6) / (7861278 * 20064),
-                         0: _traffic(4.6485e8, 902880, 524726, 1.04923e6) / (7861278 * 20064)},
+    "bytes_per_seg_wl": {1: _traffic(1.88387e8, 902880, 524559, 1.04923e6) / (7861278 * 20064),
+                         0: _traffic(4.7141e8, 902880, 524559, 1.04923e6) / (7861278 * 20064)},
 }
 
 
@@ -202,10 +202,12 @@ def transmission_leg(M, I):
             wall = time.perf_counter() - t0
             res[name] = r
             # K5: per (segment, wavelength) one alpha gather (4 B mixed, 8 B FP64),
-            # plus the 12 B segment record and chord record once per 64-wavelength block
+            # plus once per 64-wavelength launch the segment record (cell and length:
+            # 8 B mixed, 12 B FP64) and the chord record (offset, impact weight, flag: 20 B)
             nseg, nl, nblk = r["n_segments"], table.nlam, r["kernel_launches"]
             ab = 4.0 if prec == M.MCRT_MIXED else 8.0
-            k5_bytes = nseg * nl * ab + nseg * nblk * 12.0 + nch * nblk * 12.0
+            k5_bytes = nseg * nl * ab + nseg * nblk * (ab + 4.0) + nch * nblk * 20.0
+            ncell_tr = grid.nlon * grid.nlat * grid.nlay
             k5_gbps = k5_bytes / (r["kernel_ms"] * 1e-3) / 1e9
             P = K5_PROFILE
             same = kernel_sha("kernels.hip") == P["sha"] and nseg == P["n_segments"] and nl == P["n_lambda"]
@@ -221,7 +223,12 @@ def transmission_leg(M, I):
                                       "traffic": (P["bytes_per_seg_wl"][prec] * nseg * nl / max(nblk, 1)
                                                   if same else None),
                                       "traffic_unit": "bytes per launch (mean)",
-                                      "bytes_per_segment_wavelength": ab}}
+                                      "bytes_per_segment_wavelength": ab,
+                                      # one launch's extinction block (cells x 64 wavelengths) is 126 MB in
+                                      # FP32, 252 MB in FP64: it stays in the 256 MB Infinity Cache, so the
+                                      # gathers can pass the HBM rate (frac > 1); the bytes that do leave
+                                      # L2 are the traffic above
+                                      "block_MB": ncell_tr * 64 * ab / 1e6}}
         depth = res["mixed"]["value"][:, 0]
         d64 = res["fp64"]["value"][:, 0]
         excess = np.abs(res["mixed"]["sums"][..., 0] - res["fp64"]["sums"][..., 0]) / \

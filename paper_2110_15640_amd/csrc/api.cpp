@@ -70,6 +70,7 @@ struct OpacRes {
     double lam_min = 0.0, dlnlam = 0.0;
     std::vector<double> lam_um, g_weights, k_ray;
     double* lnk = nullptr;     // CK: [nspec][ng][nT][nP]; HIRES: [nT][nP][nlam]
+    float* lnk_f32 = nullptr;  // HIRES: the same table rounded to FP32 (read by the mixed form)
     double* T_grid = nullptr;  // [nT]
     double* lnP_grid = nullptr;
     double* k_ray_dev = nullptr;
@@ -1299,7 +1300,10 @@ int solve_chords(mcrt_ctx* ctx, Slot& sl, hipStream_t def_stream, int32_t gid, i
                                  st);
             }
         } else {
-            launch_hires_alpha_block(g->dev, ncell, op->lnk, op->nspec, op->nP, (const CellTP*)v_tp, op->k_ray_dev,
+            const R* tab;
+            if constexpr (sizeof(R) == sizeof(float)) tab = op->lnk_f32;
+            else tab = op->lnk;
+            launch_hires_alpha_block(g->dev, ncell, tab, op->nspec, op->nP, (const CellTP*)v_tp, op->k_ray_dev,
                                      (double*)v_shift, (int*)v_nl + r0, nslot, nslot, alpha, st);
         }
         if (prof) (void)hipEventRecord(sl.prof_ev[2 * (r0 / kSlot)], st);
@@ -2173,6 +2177,15 @@ int opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* d, hipStream_t st, in
         return code;
     };
     if ((rc = upload(ctx, O->bufs, O->bytes, lnk.data(), lnk.size(), &O->lnk, st))) return cleanup(rc);
+    std::vector<float> lnk32;
+    if (d->kind == MCRT_OPAC_HIRES) {
+        // the mixed form rounds every table value to FP32 before use; ln of
+        // an FP32 kappa is finite (|ln| < 104) or -inf, so the copy keeps the
+        // zero-kappa corners
+        lnk32.resize(ntab);
+        for (size_t i = 0; i < ntab; ++i) lnk32[i] = (float)lnk[i];
+        if ((rc = upload(ctx, O->bufs, O->bytes, lnk32.data(), lnk32.size(), &O->lnk_f32, st))) return cleanup(rc);
+    }
     if ((rc = upload(ctx, O->bufs, O->bytes, d->T_grid, (size_t)d->nT, &O->T_grid, st))) return cleanup(rc);
     if ((rc = upload(ctx, O->bufs, O->bytes, lnP.data(), lnP.size(), &O->lnP_grid, st))) return cleanup(rc);
     if ((rc = upload(ctx, O->bufs, O->bytes, d->k_ray, (size_t)d->nspec, &O->k_ray_dev, st))) return cleanup(rc);

@@ -85,8 +85,8 @@ __global__ void __launch_bounds__(256) k_doppler_shift(GridDev g, double ox, dou
 // (i0,i0), (i0,i1), (i1,i0), (i1,i1)), already loaded: the same terms in the
 // same order as interp_tp, a -inf corner with positive weight giving zero.
 // FP64, and FP32 for the mixed form (whose stored extinction is FP32):
-// weights, weighted sum and exponential in single precision.
-__device__ __forceinline__ double tp_vals_f64(const double* l, const Bracket& bt, const Bracket& bp)
+// table values, weights, weighted sum and exponential in single precision.
+__device__ __forceinline__ double tp_vals(const double* l, const Bracket& bt, const Bracket& bp)
 {
     const double t = bt.t, u = bp.t;
     const double w[4] = {(1.0 - t) * (1.0 - u), (1.0 - t) * u, t * (1.0 - u), t * u};
@@ -100,7 +100,7 @@ __device__ __forceinline__ double tp_vals_f64(const double* l, const Bracket& bt
         }
     return zero ? 0.0 : exp(acc);
 }
-__device__ __forceinline__ float tp_vals_f32(const double* l, const Bracket& bt, const Bracket& bp)
+__device__ __forceinline__ float tp_vals(const float* l, const Bracket& bt, const Bracket& bp)
 {
     const float t = (float)bt.t, u = (float)bp.t;
     const float w[4] = {(1.0f - t) * (1.0f - u), (1.0f - t) * u, t * (1.0f - u), t * u};
@@ -110,7 +110,7 @@ __device__ __forceinline__ float tp_vals_f32(const double* l, const Bracket& bt,
     for (int q = 0; q < 4; ++q)
         if (w[q] > 0.0f) {
             zero = zero || isinf(l[q]);
-            acc = fmaf(w[q], (float)l[q], acc);
+            acc = fmaf(w[q], l[q], acc);
         }
     return zero ? 0.0f : __expf(acc);
 }
@@ -126,24 +126,20 @@ __device__ __forceinline__ void hires_pos(int nlam, int n, double shift, int& n0
     else { n0 = (int)floor(x); fr = x - (double)n0; }
 }
 
-// kappa at table position n0 + fr from the eight table values l[] (four
-// corners at n0, then the same four at n0 + 1), linear in kappa between the
-// two wavelengths; R = float evaluates it in single precision (the fraction
-// comes in FP64).
+// kappa at table position n0 + fr from the corner values a[] at n0 and b[]
+// at n0 + 1, linear in kappa between the two wavelengths; R = float evaluates
+// it in single precision (the fraction comes in FP64).
 template <typename R>
-__device__ __forceinline__ double hires_combine(const double* l, const Bracket& bt, const Bracket& bp, double fr,
-                                                int nlam)
+__device__ __forceinline__ double hires_combine(const R* a, const R* b, const Bracket& bt, const Bracket& bp,
+                                                double fr, int nlam)
 {
+    const R k0 = tp_vals(a, bt, bp);
+    if (nlam == 1) return (double)k0;
+    const R k1 = tp_vals(b, bt, bp);
     if constexpr (sizeof(R) == sizeof(float)) {
-        const float k0 = tp_vals_f32(l, bt, bp);
-        if (nlam == 1) return (double)k0;
-        const float k1 = tp_vals_f32(l + 4, bt, bp);
         const float f = (float)fr;
         return (double)fmaf(f, k1, (1.0f - f) * k0);
     } else {
-        const double k0 = tp_vals_f64(l, bt, bp);
-        if (nlam == 1) return k0;
-        const double k1 = tp_vals_f64(l + 4, bt, bp);
         return (1.0 - fr) * k0 + fr * k1;
     }
 }
@@ -164,24 +160,32 @@ constexpr int kAlphaCells = 4;  // cells per thread of the hi-res extinction blo
 
 // alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
 // Threads run slot-fastest so a wave reads consecutive wavelengths of the
-// [T][P][lambda] table and writes a contiguous row.
+// [T][P][lambda] table (lnk_tpl, in the extinction's type) and writes a
+// contiguous row.
 template <typename R>
-__global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const double* __restrict__ lnk_tpl,
+__global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell, const R* __restrict__ lnk_tpl,
                                                            int nlam, int nP, const CellTP* __restrict__ tp,
                                                            const double* __restrict__ k_ray,
                                                            const double* __restrict__ shift,
                                                            const int* __restrict__ nlist, int nslot,
                                                            int slot_stride, R* __restrict__ alpha)
 {
-    // thread (cell group, slot), kAlphaCells cells each, in three passes so
-    // that the loads of one pass are all in flight together: the cells'
-    // brackets, shifts and densities; then the eight table values of every
-    // cell (a cell past the grid's end reads the last cell and is dropped);
-    // then kappa and the stores
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ngroup = (ncell + kAlphaCells - 1) / kAlphaCells;
-    if (t >= (long long)ngroup * nslot) return;
-    const int c0 = (int)(t / nslot) * kAlphaCells, s = (int)(t % nslot);
+    // thread (cell group, slot), kAlphaCells cells each, in passes whose
+    // loads are in flight together: the cells' brackets, shifts and
+    // densities; the four table corners at n0 of every cell; then the corners
+    // at n0 + 1, which in the FP32 form are the next lane's values at its n0
+    // whenever that lane has the same cells and the next table wavelength
+    // (consecutive slots of one cell group), and loaded only where it has not
+    // (the FP64 form loads them all).  A thread
+    // past the end mirrors the last one (so every lane takes part in the
+    // exchange) and stores nothing; a cell past the grid's end reads the last
+    // cell and is dropped.
+    const long long total = (long long)((ncell + kAlphaCells - 1) / kAlphaCells) * nslot;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t < total;
+    const long long tc = live ? t : total - 1;
+    const int grp = (int)(tc / nslot), s = (int)(tc % nslot);
+    const int c0 = grp * kAlphaCells;
     const int n = nlist[s];
     const double kr = k_ray[n];
     CellTP q[kAlphaCells];
@@ -194,19 +198,41 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
         rho[u] = g.rho[c];
     }
     const int d = nlam == 1 ? 0 : 1;
-    double lv[kAlphaCells][8];
+    R a[kAlphaCells][4], b[kAlphaCells][4];
+    int n0[kAlphaCells];
     double fr[kAlphaCells];
+    size_t row[kAlphaCells][4];
 #pragma unroll
     for (int u = 0; u < kAlphaCells; ++u) {
-        int n0;
-        hires_pos(nlam, n, sh[u], n0, fr[u]);
-        const double* r00 = lnk_tpl + ((size_t)q[u].ti0 * nP + q[u].pi0) * nlam + n0;
-        const double* r01 = lnk_tpl + ((size_t)q[u].ti0 * nP + q[u].pi1) * nlam + n0;
-        const double* r10 = lnk_tpl + ((size_t)q[u].ti1 * nP + q[u].pi0) * nlam + n0;
-        const double* r11 = lnk_tpl + ((size_t)q[u].ti1 * nP + q[u].pi1) * nlam + n0;
-        lv[u][0] = r00[0]; lv[u][1] = r01[0]; lv[u][2] = r10[0]; lv[u][3] = r11[0];
-        lv[u][4] = r00[d]; lv[u][5] = r01[d]; lv[u][6] = r10[d]; lv[u][7] = r11[d];
+        hires_pos(nlam, n, sh[u], n0[u], fr[u]);
+        row[u][0] = ((size_t)q[u].ti0 * nP + q[u].pi0) * nlam + n0[u];
+        row[u][1] = ((size_t)q[u].ti0 * nP + q[u].pi1) * nlam + n0[u];
+        row[u][2] = ((size_t)q[u].ti1 * nP + q[u].pi0) * nlam + n0[u];
+        row[u][3] = ((size_t)q[u].ti1 * nP + q[u].pi1) * nlam + n0[u];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[u][k] = lnk_tpl[row[u][k]];
     }
+    if constexpr (sizeof(R) == sizeof(float)) {
+        const bool last_lane = (threadIdx.x & 63) == 63;
+        const int grp_next = __shfl_down(grp, 1);
+#pragma unroll
+        for (int u = 0; u < kAlphaCells; ++u) {
+            const int n0_next = __shfl_down(n0[u], 1);
+            const bool take = !last_lane && grp_next == grp && n0_next == n0[u] + d;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[u][k] = __shfl_down(a[u][k], 1);
+            if (!take) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) b[u][k] = lnk_tpl[row[u][k] + d];
+            }
+        }
+    } else {  // FP64: exchanging the doubles costs more registers than the loads save
+#pragma unroll
+        for (int u = 0; u < kAlphaCells; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[u][k] = lnk_tpl[row[u][k] + d];
+    }
+    if (!live) return;
 #pragma unroll
     for (int u = 0; u < kAlphaCells; ++u) {
         const int c = c0 + u;
@@ -214,7 +240,7 @@ __global__ void __launch_bounds__(256) k_hires_alpha_block(GridDev g, int ncell,
         Bracket bt, bp;
         bt.i0 = q[u].ti0; bt.i1 = q[u].ti1; bt.t = q[u].tt;
         bp.i0 = q[u].pi0; bp.i1 = q[u].pi1; bp.t = q[u].pt;
-        const double kl = hires_combine<R>(lv[u], bt, bp, fr[u], nlam);
+        const double kl = hires_combine<R>(a[u], b[u], bt, bp, fr[u], nlam);
         const double kext = kl + kr;
         alpha[(size_t)c * slot_stride + s] = (R)(rho[u] * kext);
     }
@@ -511,7 +537,7 @@ void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T
 }
 
 template <typename R>
-void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
+void launch_hires_alpha_block(const GridDev& g, int ncell, const R* lnk_tpl, int nlam, int nP,
                               const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
                               int nslot, int slot_stride, R* alpha, hipStream_t stream)
 {
@@ -522,7 +548,7 @@ void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl
 template void launch_hires_alpha_block<double>(const GridDev&, int, const double*, int, int, const CellTP*,
                                                const double*, const double*, const int*, int, int, double*,
                                                hipStream_t);
-template void launch_hires_alpha_block<float>(const GridDev&, int, const double*, int, int, const CellTP*,
+template void launch_hires_alpha_block<float>(const GridDev&, int, const float*, int, int, const CellTP*,
                                               const double*, const double*, const int*, int, int, float*,
                                               hipStream_t);
 

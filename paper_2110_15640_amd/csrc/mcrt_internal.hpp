@@ -186,8 +186,10 @@ struct CellTP {
 };
 void launch_cell_tp(const GridDev& g, int ncell, int nT, int nP, const double* T_grid, const double* lnP_grid,
                     CellTP* out, hipStream_t stream);
+// lnk_tpl: the [T][P][lambda] ln-kappa table in the extinction's own type
+// (FP64, or its FP32 copy for the mixed form).
 template <typename R>
-void launch_hires_alpha_block(const GridDev& g, int ncell, const double* lnk_tpl, int nlam, int nP,
+void launch_hires_alpha_block(const GridDev& g, int ncell, const R* lnk_tpl, int nlam, int nP,
                               const CellTP* tp, const double* k_ray, const double* shift, const int* nlist,
                               int nslot, int slot_stride, R* alpha, hipStream_t stream);
 void launch_reduce_partials(const double* partials, int nblocks, int width, double* out,

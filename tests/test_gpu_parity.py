@@ -243,6 +243,36 @@ def test_transmission_hires_parity_multi_block(ctx, torch_dev):
     ctx.free_opacity(oid)
 
 
+def test_transmission_hires_slot_order_invariance(ctx, torch_dev):
+    """A wavelength's extinction row does not depend on which slot holds it:
+    consecutive wavelengths share table values between neighbouring lanes,
+    shuffled, repeated or sparse ones load their own.  Both precisions,
+    bit-identical per wavelength; 150 wavelengths give a ragged last block."""
+    _log("transmission hi-res: slot order invariance (consecutive vs shuffled vs sparse wavelengths)")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table = I.make_transmission_hires(16, 8, 10, nlam=400, nT=5, nP=6)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    kw = dict(n_b=32, n_alpha=20, seed=49, r_star=I.R_SUN)
+    base = list(range(100, 250))
+    rng = np.random.default_rng(7)
+    shuffled = [int(x) for x in rng.permutation(base)]
+    # every other wavelength, each twice in a row, then the table's two ends
+    sparse = [w for w in base[::2] for _ in range(2)] + [0, 1, table.nlam - 2, table.nlam - 1]
+    for prec in (M.MCRT_FP64, M.MCRT_MIXED):
+        ref = ctx.solve_transmission(gid, oid, table, spec_idx=base, precision=prec, **kw)
+        for other in (shuffled, sparse):
+            got = ctx.solve_transmission(gid, oid, table, spec_idx=other, precision=prec, **kw)
+            for row, w in enumerate(other):
+                if w in base:
+                    assert np.array_equal(got["sums"][row], ref["sums"][base.index(w)]), (prec, w)
+        ends = ctx.solve_transmission(gid, oid, table, spec_idx=[0, 1, table.nlam - 2, table.nlam - 1],
+                                      precision=prec, **kw)
+        got = ctx.solve_transmission(gid, oid, table, spec_idx=sparse, precision=prec, **kw)
+        assert np.array_equal(got["sums"][-4:], ends["sums"]), prec
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
 def test_edge_cases(ctx, torch_dev):
     _log("edge cases: one packet, no emitting cells, error codes")
     from paper_2110_15640_amd import mcrt as M
