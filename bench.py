@@ -77,11 +77,11 @@ K4_PROFILE = {
 # The same for the chord optical-depth kernel of the transmission solve: bytes
 # per (chord segment, wavelength) over its launches.
 K5_PROFILE = {
-    "sha": "938f3ced1b4e4fd4f9b210b9db7cad9df42f8fe93c53128fcfba8f20ca915336",
+    "sha": "e03ea1bbd427660f811dd065b4be7b50aa4f8cd1a25fba23ddee0d8dde9d7d3e",
     "n_segments": 7861278, "n_lambda": 20000,
     # per precision (1 mixed: FP32 rows; 0 FP64), over 314 launches of 64 wavelengths (20,064)
-    "bytes_per_seg_wl": {1: _traffic(1.88387e8, 902880, 524559, 1.04923e6) / (7861278 * 20064),
-                         0: _traffic(4.7141e8, 902880, 524559, 1.04923e6) / (7861278 * 20064)},
+    "bytes_per_seg_wl": {1: _traffic(1.88522e8, 902880, 524559, 1.04892e6) / (7861278 * 20064),
+                         0: _traffic(4.71908e8, 902880, 524559, 1.04892e6) / (7861278 * 20064)},
 }
 
 

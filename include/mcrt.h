@@ -151,7 +151,10 @@ typedef struct {
 } mcrt_opacity_desc;
 
 /* stream: as for mcrt_grid_upload (the re-laid-out table is copied on it and
- * the call returns when the copy is done). */
+ * the call returns when the copy is done).  The device holds ln kappa in
+ * FP64 ([T][P][lambda] for MCRT_OPAC_HIRES, 8 B per entry) and, for
+ * MCRT_OPAC_HIRES, the same values rounded to FP32 (4 B per entry more),
+ * which the mixed-precision transmission reads. */
 int mcrt_opacity_upload(mcrt_ctx* ctx, const mcrt_opacity_desc* desc, void* stream, int32_t* opac_id);
 int mcrt_opacity_free(mcrt_ctx* ctx, int32_t opac_id);
 

@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_cell_tp(GridDev g, int ncell, int nT, i
     out[c] = CellTP{bt.i0, bt.i1, bp.i0, bp.i1, bt.t, bp.t};
 }
 
-constexpr int kAlphaCells = 4;  // cells per thread of the hi-res extinction block
+constexpr int kAlphaCells = 2;  // cells per thread of the hi-res extinction block
 
 // alpha[c * slot_stride + s] = rho (kappa_shifted(n_s) + k_ray(n_s)), n_s = nlist[s], s < nslot.
 // Threads run slot-fastest so a wave reads consecutive wavelengths of the
