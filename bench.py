@@ -60,7 +60,7 @@ def _busy(active_valu, wave_cycles, waves_per_simd=4):
 
 
 K4_PROFILE = {
-    "sha": "784c68d493abc66500e777463f1bc33c76c2d587440da6ca4d1d3bfbad43e49b",
+    "sha": "db7a316a18c16298844134fb1ed48e151e8a0a10e306d69a3ce7ca537b84fc44",
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
     # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
     "shapes": {
