@@ -468,7 +468,7 @@ int mcrt_autotune(mcrt_ctx* ctx, int32_t mode, int32_t grid_id, int32_t opac_id,
  * arrival order whenever the context's HBM budget covers the request's
  * device scratch (estimated at submit), so requests run concurrently on the
  * device while grids and tables stay resident.  A served request reaches
- * the device as persistent launches of at most 2^26 packets, each taking the
+ * the device as persistent launches of at most 2^23 packets, each taking the
  * device's blocks shared among the requests running when it starts, so the
  * launches of concurrent requests are resident together.  Scratch that
  * blocking solves keep for their next call is released when it stands in

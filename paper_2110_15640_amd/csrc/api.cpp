@@ -729,11 +729,12 @@ int lease(mcrt_ctx* ctx, int32_t gid, int32_t oid, Lease& L)
 
 // Solves per persistent launch for a serving request: a fixed share of the
 // budget, so that the admission estimate and the allocation agree, and at
-// most kServeLaunchPackets packets (about a quarter second of the whole
-// device), so that a very long request reaches the device as a sequence of
-// launches whose share of the device is chosen anew.  Splitting the
-// requests of an ordinary mix more finely only adds drain tails.
-constexpr uint64_t kServeLaunchPackets = 1ull << 26;
+// most kServeLaunchPackets packets (about 30 ms of the whole device), so that
+// a long request reaches the device as a sequence of launches whose share of
+// the device is chosen anew: a launch sized to a third of the device while
+// three requests ran keeps only that third after the other two finish, until
+// it ends.
+constexpr uint64_t kServeLaunchPackets = 1ull << 23;
 int serving_batch(mcrt_ctx* ctx, int max_batch, int nsolve, uint64_t per_solve, uint64_t packets_per_solve)
 {
     uint64_t cap = std::min<uint64_t>(ctx->budget / 8, 24ULL << 30);
