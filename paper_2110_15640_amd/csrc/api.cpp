@@ -2228,9 +2228,6 @@ int mcrt_create(int device, uint64_t hbm_budget_bytes, mcrt_ctx** out)
     int rc = slot_init(ctx->main);
     if (rc) return rc;
     if ((rc = slot_init(ctx->na))) return rc;
-    // The allocation-free entry point creates nothing on its calls: its second
-    // transmission stream is made here.
-    if ((rc = own_queue_stream(&ctx->na.stream2, ctx->n_cu))) return rc;
     if (device < kNoallocDevices) {
         std::lock_guard<std::mutex> lk(g_noalloc_mu);
         if (!g_noalloc_ptr[device]) {
