@@ -54,6 +54,29 @@ def test_mixed_requests_equal_their_blocking_solves(torch_dev):
             assert g["latency_ms"] >= g["queued_ms"] >= 0.0
 
 
+def test_served_request_split_into_launches_equals_blocking_solve(torch_dev):
+    """A served request longer than one serving launch (2^23 packets) runs as
+    several persistent launches, each with the device's share chosen when it
+    starts; its results are those of the blocking solve, bit for bit."""
+    print("serving: one emission request of 9.6e6 packets in several launches vs the blocking solve", flush=True)
+    from paper_2110_15640_amd import mcrt as M
+    grid, ck, _ = I.make_emission_3d(16, 8, 10, nband=2, ng=8)
+    with M.Context(0) as ctx:
+        ctx.serve_config(2)
+        gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(ck)
+        kw = dict(n_packets=600_000, seed=5, obs_phase=[0.3], precision=M.MCRT_MIXED, profile=1)
+        # a short request alongside, so the long one's launches see a changing share
+        t_short = ctx.submit("emission", gid, oid, ck, **dict(kw, n_packets=20_000, seed=6))
+        t_long = ctx.submit("emission", gid, oid, ck, **kw)
+        short, got = ctx.wait(t_short), ctx.wait(t_long)
+        ref = ctx.solve_emission(gid, oid, ck, **kw)
+        assert got["kernel_launches"] >= 2, got["kernel_launches"]
+        assert np.array_equal(got["sums"], ref["sums"])
+        assert np.array_equal(got["value"], ref["value"])
+        ref_short = ctx.solve_emission(gid, oid, ck, **dict(kw, n_packets=20_000, seed=6))
+        assert np.array_equal(short["sums"], ref_short["sums"])
+
+
 def test_cancel_poll_and_budget(torch_dev):
     print("serving: cancel, poll and budget rejection", flush=True)
     from paper_2110_15640_amd import mcrt as M
