@@ -273,6 +273,24 @@ def test_transmission_hires_slot_order_invariance(ctx, torch_dev):
     ctx.free_opacity(oid)
 
 
+def test_transmission_hires_single_wavelength_table(ctx, torch_dev):
+    """A one-wavelength hi-res table: every Doppler shift clamps to the one
+    entry (no neighbour wavelength to interpolate to), in both precisions."""
+    _log("transmission hi-res: one-wavelength table, winds + rotation")
+    from paper_2110_15640_amd import mcrt as M
+    grid, table = I.make_transmission_hires(16, 8, 10, nlam=1, nT=5, nP=6)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    kw = dict(n_b=32, n_alpha=20, seed=51, r_star=I.R_SUN)
+    got = ctx.solve_transmission(gid, oid, table, **kw)
+    ref = O.solve_transmission(grid, table, O.Params(**kw))
+    np.testing.assert_allclose(got["sums"], ref.sums, rtol=RTOL)
+    np.testing.assert_allclose(got["value"], ref.value, rtol=1e-12)
+    mix = ctx.solve_transmission(gid, oid, table, precision=M.MCRT_MIXED, **kw)
+    np.testing.assert_allclose(mix["sums"][..., 0], ref.sums[..., 0], rtol=1e-3)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
 def test_edge_cases(ctx, torch_dev):
     _log("edge cases: one packet, no emitting cells, error codes")
     from paper_2110_15640_amd import mcrt as M
