@@ -60,18 +60,18 @@ def _busy(active_valu, wave_cycles, waves_per_simd=4):
 
 
 K4_PROFILE = {
-    "sha": "db7a316a18c16298844134fb1ed48e151e8a0a10e306d69a3ce7ca537b84fc44",
+    "sha": "0f6bb0332af098936b28ff877f251c80b3678d05c98506e73a683016398c2cd3",
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
     # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
     "shapes": {
-        20: {"bytes_per_launch": _traffic(6.53936e8, 1.14488e8, 524342, 1.04859e6),
-             "valu_busy": _busy(1.64768e12, 6.96708e12)},
-        24: {"bytes_per_launch": _traffic(6.35264e8, 1.14179e8, 524316, 1.04858e6),
-             "valu_busy": _busy(1.62636e12, 6.79784e12)},
-        28: {"bytes_per_launch": _traffic(6.11883e8, 1.13914e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.63305e12, 6.75925e12)},
-        32: {"bytes_per_launch": _traffic(5.9057e8, 1.1368e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.66108e12, 6.82072e12)},
+        20: {"bytes_per_launch": _traffic(6.56307e8, 1.1448e8, 524344, 1.04859e6),
+             "valu_busy": _busy(1.62781e12, 6.89632e12)},
+        24: {"bytes_per_launch": _traffic(1.27313e9 / 2, 2.28355e8 / 2, 524343, 1.04859e6),
+             "valu_busy": _busy(3.21407e12, 1.34547e13)},
+        28: {"bytes_per_launch": _traffic(6.14575e8, 1.13914e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.61377e12, 6.68904e12)},
+        32: {"bytes_per_launch": _traffic(5.91873e8, 1.13672e8, 524342, 1.04859e6),
+             "valu_busy": _busy(1.64148e12, 6.74595e12)},
     },
 }
 # The same for the chord optical-depth kernel of the transmission solve: bytes
