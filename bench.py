@@ -77,7 +77,7 @@ K4_PROFILE = {
 # The same for the chord optical-depth kernel of the transmission solve: bytes
 # per (chord segment, wavelength) over its launches.
 K5_PROFILE = {
-    "sha": "e03ea1bbd427660f811dd065b4be7b50aa4f8cd1a25fba23ddee0d8dde9d7d3e",
+    "sha": "0eb2314978dcf52aae2f8960283e4800abb4b033705255706a7519cf7c401028",
     "n_segments": 7861278, "n_lambda": 20000,
     # per precision (1 mixed: FP32 rows; 0 FP64), over 314 launches of 64 wavelengths (20,064)
     "bytes_per_seg_wl": {1: _traffic(1.88522e8, 902880, 524559, 1.04892e6) / (7861278 * 20064),
