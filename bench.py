@@ -60,7 +60,7 @@ def _busy(active_valu, wave_cycles, waves_per_simd=4):
 
 
 K4_PROFILE = {
-    "sha": "0f6bb0332af098936b28ff877f251c80b3678d05c98506e73a683016398c2cd3",
+    "sha": "6bddf311c9251907a4d852d3214a46939a08aa1de3b719c9ee3a4997e65a7360",
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
     # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
     "shapes": {

@@ -655,10 +655,17 @@ __device__ __forceinline__ int solve_of(const BatchArgs& A, unsigned long long g
 // K4a: births of every packet of a batch (albedo: uniform on the top disk or
 // the slab's incidence; emission: cell from the biased CDF, uniform position in
 // its volume, isotropic direction, weight (L_i/L_tot)/q_i), one thread each.
+//
+// blk_sv >= 0: the solve every packet of the calling block belongs to (found
+// once per block); tab: when that solve is an emission solve with a fixed g,
+// 256 samples of its CDF, tab[m] = cdf[(m ncell) >> 8], which narrow the
+// search for the birth cell to the range between two samples (same cell as
+// the search over the whole CDF: see below).
 template <bool MULTI>
-__device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs& A, unsigned long long gid, double* b)
+__device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs& A, unsigned long long gid, double* b,
+                                             int blk_sv, const double* tab)
 {
-    int sv = solve_of(A, gid);
+    int sv = blk_sv >= 0 ? blk_sv : solve_of(A, gid);
     const GridDev& g = MULTI ? A.grids[A.solves[sv].grid] : g1;
     const double r_toa = g.r[g.nlay];
     const unsigned long long q = gid - A.solves[sv].pbase;
@@ -758,13 +765,26 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
     U2 u1 = draw(A.seed, tag, q, 0, 1);
     U2 u2 = draw(A.seed, tag, q, 0, 2);
     double target = u0.a * tot;
-    int lo = 0, hi = ncell - 1;  // smallest c with cdf[c] > target
+    int lo = 0, hi = ncell - 1;  // smallest c with cdf[c] > target (else ncell - 1)
+    if (tab != nullptr && sv == blk_sv) {
+        // m = the first sample above target; the cell lies after sample m - 1
+        // (every cdf value up to it is <= target) and at or before sample m
+        // (its value is > target); past the last sample, up to ncell - 1
+        int a = 0, z = 256;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            if (tab[mid] > target) z = mid;
+            else a = mid + 1;
+        }
+        lo = a == 0 ? 0 : (int)(((unsigned long long)(a - 1) * (unsigned)ncell) >> 8) + 1;
+        hi = a == 256 ? ncell - 1 : (int)(((unsigned long long)a * (unsigned)ncell) >> 8);
+    }
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
         if (S.cdf[mid] > target) hi = mid;
         else lo = mid + 1;
     }
-    int c = lo;
+    int c = lo < ncell ? lo : ncell - 1;
     int i = c % g.nlon, j = (c / g.nlon) % g.nlat, k = c / (g.nlon * g.nlat);
     double rk = g.r[k], rk1 = g.r[k + 1];
     double rk3 = rk * rk * rk;
@@ -789,21 +809,42 @@ __device__ __forceinline__ void birth_record(const GridDev& g1, const BatchArgs&
 
 // The records of a block's packets are built in LDS and its rows written
 // as one contiguous range (peel-off columns as zeros): coalesced stores of
-// whole lines instead of 72 B pieces of 120 B rows.
-constexpr int kMaxRowW = kMaxObs + kNCounters;
-
+// whole lines instead of 72 B pieces of 120 B rows.  Dynamic LDS: 256 CDF
+// samples, then 256 rows of row_w doubles (row_w = n_obs + kNCounters <= 19,
+// sized at launch, so a narrow row leaves room for more resident blocks).
 template <bool MULTI>
 __global__ void __launch_bounds__(256) k_births(GridDev g1, BatchArgs A)
 {
-    __shared__ double sh[256 * kMaxRowW];
+    extern __shared__ double births_lds[];
+    double* tab = births_lds;
+    double* sh = births_lds + 256;
+    __shared__ int blk[2];  // the block's solve (-1: several), and whether tab holds its CDF samples
     const int w = A.row_w;
     const unsigned long long r0 = (unsigned long long)blockIdx.x * 256;
+    const unsigned long long left = A.total - r0;
+    if (threadIdx.x == 0) {
+        const int sv = solve_of(A, r0);
+        const SolveDev& S = A.solves[sv];
+        const unsigned long long last = r0 + (left < 256 ? left : 256) - 1;
+        const bool one = r0 >= S.begin && last < S.begin + S.n;
+        blk[0] = one ? sv : -1;
+        blk[1] = one && S.mode == 1 && S.gs_n == 0;
+    }
+    __syncthreads();
+    const int blk_sv = blk[0];
+    const bool use_tab = blk[1] != 0;
+    if (use_tab) {
+        const SolveDev& S = A.solves[blk_sv];
+        const GridDev& g = MULTI ? A.grids[S.grid] : g1;
+        const unsigned ncell = (unsigned)(g.nlon * g.nlat * g.nlay);
+        tab[threadIdx.x] = S.cdf[((unsigned long long)threadIdx.x * ncell) >> 8];
+    }
     double* mine = sh + threadIdx.x * w;
     for (int c = 0; c < w; ++c) mine[c] = 0.0;
-    const unsigned long long gid = r0 + threadIdx.x;
-    if (gid < A.total) birth_record<MULTI>(g1, A, gid, mine + A.n_out);
     __syncthreads();
-    const unsigned long long left = A.total - r0;
+    const unsigned long long gid = r0 + threadIdx.x;
+    if (gid < A.total) birth_record<MULTI>(g1, A, gid, mine + A.n_out, blk_sv, use_tab ? tab : nullptr);
+    __syncthreads();
     const int n = (int)(left < 256 ? left : 256) * w;
     double* dst = A.rows + r0 * (unsigned long long)w;
     for (int x = threadIdx.x; x < n; x += 256) dst[x] = sh[x];
@@ -1054,8 +1095,9 @@ __global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, size_t
 void launch_births(const GridDev& g, const BatchArgs& a, bool multi, hipStream_t stream)
 {
     dim3 grid((unsigned)((a.total + 255) / 256));
-    if (multi) hipLaunchKernelGGL(k_births<true>, grid, dim3(256), 0, stream, g, a);
-    else hipLaunchKernelGGL(k_births<false>, grid, dim3(256), 0, stream, g, a);
+    const size_t lds = (size_t)(256 + 256 * a.row_w) * sizeof(double);  // <= 40 KB
+    if (multi) hipLaunchKernelGGL(k_births<true>, grid, dim3(256), lds, stream, g, a);
+    else hipLaunchKernelGGL(k_births<false>, grid, dim3(256), lds, stream, g, a);
 }
 
 void launch_transport_persistent(const GridDev& g, const BatchArgs& a, bool mixed, bool multi, int blocks,
