@@ -139,6 +139,26 @@ def test_emission_parity_with_clouds(ctx, torch_dev):
     ctx.free_opacity(oid)
 
 
+@pytest.mark.parametrize("shape", [(8, 4, 8), (4, 2, 3), (16, 8, 10)])
+def test_emission_birth_cells_every_packet(ctx, torch_dev, shape):
+    """Birth cells found through the per-block table of CDF samples: grids of
+    exactly 256 cells (the last sample is the last cell), fewer (repeated
+    samples) and more, with flat CDF stretches where the tau cut silences
+    cells; every packet's row against the oracle."""
+    nlon, nlat, nlay = shape
+    _log(f"emission birth cells: {nlon}x{nlat}x{nlay} grid, every packet")
+    grid, table, phases = I.make_emission_3d(nlon, nlat, nlay, nband=2, ng=1, config_no=31)
+    n = 1100  # several blocks of 256 packets, a ragged last one
+    dump = dump_buffer(torch_dev, 2, n, 1)
+    gid, oid = ctx.upload_grid(grid), ctx.upload_opacity(table)
+    got = ctx.solve_emission(gid, oid, table, n_packets=n, seed=53, obs_phase=[0.25], packet_dump=dump)
+    ref = O.solve_emission(grid, table, O.Params(n_packets=n, seed=53, obs_phase=(0.25,)), keep_packets=True)
+    check_packets(dump, ref, (2, 1, n, 1))
+    check_solve(got, ref)
+    ctx.free_grid(gid)
+    ctx.free_opacity(oid)
+
+
 def test_peel_off_cut_parity(ctx, torch_dev):
     """A low peel-off cut (tau_peel_max = 1.5) drops many peel-offs mid-walk:
     every packet against the oracle, albedo and emission, FP64."""
