@@ -282,13 +282,17 @@ void release_scratch(mcrt_ctx* ctx, Slot& sl)
 // every CU, which the runtime serves with a new queue instead of a share of
 // its few default ones.  Kernels of two streams that share a queue run one
 // after the other, so streams meant to overlap (the serving workers, the
-// two halves of a transmission solve) are made this way.
+// two halves of a transmission solve) are made this way.  Where the runtime
+// refuses CU-masked streams, an ordinary stream does the same work (the
+// results do not depend on it; only the overlap may be lost).
 int own_queue_stream(hipStream_t* st, int n_cu)
 {
     std::vector<uint32_t> mask((size_t)(std::max(n_cu, 1) + 31) / 32, 0xffffffffu);
     if (n_cu % 32) mask.back() = (1u << (n_cu % 32)) - 1u;
-    hipError_t e = hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
-    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipExtStreamCreateWithCUMask: %s", hipGetErrorString(e));
+    if (hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) == hipSuccess) return MCRT_OK;
+    (void)hipGetLastError();
+    hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     return MCRT_OK;
 }
 
