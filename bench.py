@@ -64,14 +64,14 @@ K4_PROFILE = {
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
     # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
     "shapes": {
-        20: {"bytes_per_launch": _traffic(6.56307e8, 1.1448e8, 524344, 1.04859e6),
-             "valu_busy": _busy(1.62781e12, 6.89632e12)},
-        24: {"bytes_per_launch": _traffic(1.27313e9 / 2, 2.28355e8 / 2, 524343, 1.04859e6),
-             "valu_busy": _busy(3.21407e12, 1.34547e13)},
-        28: {"bytes_per_launch": _traffic(6.14575e8, 1.13914e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.61377e12, 6.68904e12)},
-        32: {"bytes_per_launch": _traffic(5.91873e8, 1.13672e8, 524342, 1.04859e6),
-             "valu_busy": _busy(1.64148e12, 6.74595e12)},
+        20: {"bytes_per_launch": _traffic(6.56173e8, 1.14478e8, 524342, 1.04859e6),
+             "valu_busy": _busy(1.62781e12, 6.89747e12)},
+        24: {"bytes_per_launch": _traffic(1.2712e9 / 2, 2.28354e8 / 2, 524342, 1.04859e6),
+             "valu_busy": _busy(3.21407e12, 1.34585e13)},
+        28: {"bytes_per_launch": _traffic(6.14826e8, 1.13913e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.61377e12, 6.68946e12)},
+        32: {"bytes_per_launch": _traffic(5.92012e8, 1.13671e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.64148e12, 6.74611e12)},
     },
 }
 # The same for the chord optical-depth kernel of the transmission solve: bytes
@@ -80,8 +80,8 @@ K5_PROFILE = {
     "sha": "0eb2314978dcf52aae2f8960283e4800abb4b033705255706a7519cf7c401028",
     "n_segments": 7861278, "n_lambda": 20000,
     # per precision (1 mixed: FP32 rows; 0 FP64), over 314 launches of 64 wavelengths (20,064)
-    "bytes_per_seg_wl": {1: _traffic(1.88522e8, 902880, 524559, 1.04892e6) / (7861278 * 20064),
-                         0: _traffic(4.71908e8, 902880, 524559, 1.04892e6) / (7861278 * 20064)},
+    "bytes_per_seg_wl": {1: _traffic(1.88063e8, 902880, 524722, 1.04923e6) / (7861278 * 20064),
+                         0: _traffic(4.72339e8, 902880, 524722, 1.04923e6) / (7861278 * 20064)},
 }
 
 
