@@ -517,11 +517,13 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
     }
     if (L.ev == E_PEEL_DONE) {
         double f;
+        // attenuation e^{-tau} in FP32 in the mixed form, as for the scattered peel-offs below
+        const double att = MIXED ? (double)(L.tau < INFINITY ? __expf(-(float)L.tau) : 0.0f) : exp(-L.tau);
         if (L.birth()) {  // emission point (isotropic), or a transmission chord's direct light
-            f = (EXT && A.trans_ms) ? L.W * exp(-L.tau) : L.W * exp(-L.tau) / (4.0 * kPi);
+            f = (EXT && A.trans_ms) ? L.W * att : L.W * att / (4.0 * kPi);
         } else if (EXT && L.surf()) {  // Lambert floor: W A_s max(n.o, 0)/pi e^{-tau}, n held as the direction
             const double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
-            f = mu > 0.0 ? L.W * A.surface_albedo * (mu / kPi) * exp(-L.tau) : 0.0;
+            f = mu > 0.0 ? L.W * A.surface_albedo * (mu / kPi) * att : 0.0;
         } else {
             // normalised mixture of the Rayleigh and cloud phase functions
             // toward the observer, weighted by the gas scattering probability
@@ -547,9 +549,8 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                     ph = hgf(gcf);
                 }
                 float theta = (pgf * pr + (1.0f - pgf) * ph) * (float)(0.25 / kPi);
-                float att = L.tau < INFINITY ? __expf(-(float)L.tau) : 0.0f;
                 float w = A.absorption == 1 ? (float)L.W : (float)(L.W * om);
-                f = (double)(w * theta * att);
+                f = (double)(w * theta * (float)att);
             } else {
                 double mu = L.sdx() * L.w.dx + L.sdy() * L.w.dy + L.sdz() * L.w.dz;
                 double pc;
@@ -563,7 +564,6 @@ __device__ __forceinline__ int handle_event(Lane& L, const GridDev& g, const Bat
                     pc = p_hg(mu, gc);
                 }
                 double theta = (pg * p_rayleigh(mu) + (1.0 - pg) * pc) / (4.0 * kPi);
-                double att = exp(-L.tau);
                 f = A.absorption == 1 ? L.W * theta * att : L.W * om * theta * att;
             }
         }
