@@ -56,22 +56,26 @@ def _traffic(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib):
 
 
 def _busy(active_valu, wave_cycles, waves_per_simd=4):
+    """SQ_ACTIVE_INST_VALU per wave cycle times the waves sharing a SIMD: the
+    share of SIMD cycles with a VALU instruction in flight (about 1 when the
+    SIMDs issue VALU work every cycle; FP64 instructions that occupy a SIMD
+    for more than one cycle can take it slightly past 1)."""
     return active_valu / wave_cycles * waves_per_simd
 
 
 K4_PROFILE = {
-    "sha": "6bddf311c9251907a4d852d3214a46939a08aa1de3b719c9ee3a4997e65a7360",
+    "sha": "672340fea5202d167d0d2aa733b7075f8f01962dfdbd22a013706e8becd4c134",
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
     # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
     "shapes": {
-        20: {"bytes_per_launch": _traffic(6.56173e8, 1.14478e8, 524342, 1.04859e6),
-             "valu_busy": _busy(1.62781e12, 6.89747e12)},
-        24: {"bytes_per_launch": _traffic(1.2712e9 / 2, 2.28354e8 / 2, 524342, 1.04859e6),
-             "valu_busy": _busy(3.21407e12, 1.34585e13)},
-        28: {"bytes_per_launch": _traffic(6.14826e8, 1.13913e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.61377e12, 6.68946e12)},
-        32: {"bytes_per_launch": _traffic(5.92012e8, 1.13671e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.64148e12, 6.74611e12)},
+        20: {"bytes_per_launch": _traffic(1.31076e8, 1.18905e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.61723e12, 6.51007e12)},
+        24: {"bytes_per_launch": _traffic(2.61871e8 / 2, 2.3786e8 / 2, 524343, 1.04859e6),
+             "valu_busy": _busy(3.19614e12, 1.28055e13)},
+        28: {"bytes_per_launch": _traffic(1.30884e8, 1.18958e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.60599e12, 6.41207e12)},
+        32: {"bytes_per_launch": _traffic(1.31367e8, 1.18989e8, 524343, 1.04859e6),
+             "valu_busy": _busy(1.6346e12, 6.50642e12)},
     },
 }
 # The same for the chord optical-depth kernel of the transmission solve: bytes
