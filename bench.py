@@ -42,6 +42,9 @@ OMEGA_PGAS_BYTES = 8.0    # per interaction (omega and P_gas, FP32)
 CDF_PROBE_BYTES = 8.0     # per probe of the emission CDF (FP64), ceil(log2(ncell)) probes per birth
 PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X
 PEAK_HBM = 8000.0  # GB/s
+# VALU issue peak: a wave64 instruction occupies a 16-lane SIMD for 4 cycles,
+# 256 CUs x 4 SIMDs at 2.4 GHz (the same unit counts give 78.6 FP64 TFLOP/s)
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4.0  # wave-level VALU instructions per second
 
 # HBM traffic of the transport kernel from two rocprofv3 counter passes
 # (FETCH_SIZE, WRITE_SIZE, each scaled by what it reads for a 1 GiB copy) and
@@ -66,16 +69,17 @@ def _busy(active_valu, wave_cycles, waves_per_simd=4):
 K4_PROFILE = {
     "sha": "672340fea5202d167d0d2aa733b7075f8f01962dfdbd22a013706e8becd4c134",
     "grid": [128, 64, 50], "packets_per_solve": 1000000, "n_obs": 4, "solves_per_launch": 800,
-    # per event threshold (4 blocks per compute unit, wave batch 32): bytes and VALU busy per launch
+    # per event threshold (4 blocks per compute unit, wave batch 32): bytes, VALU busy and
+    # wave-level VALU instructions (SQ_INSTS_VALU) per launch
     "shapes": {
         20: {"bytes_per_launch": _traffic(1.31076e8, 1.18905e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.61723e12, 6.51007e12)},
+             "valu_busy": _busy(1.61723e12, 6.51007e12), "valu_insts": 1.57343e12},
         24: {"bytes_per_launch": _traffic(2.61871e8 / 2, 2.3786e8 / 2, 524343, 1.04859e6),
-             "valu_busy": _busy(3.19614e12, 1.28055e13)},
+             "valu_busy": _busy(3.19614e12, 1.28055e13), "valu_insts": 3.1132e12 / 2},
         28: {"bytes_per_launch": _traffic(1.30884e8, 1.18958e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.60599e12, 6.41207e12)},
+             "valu_busy": _busy(1.60599e12, 6.41207e12), "valu_insts": 1.5658e12},
         32: {"bytes_per_launch": _traffic(1.31367e8, 1.18989e8, 524343, 1.04859e6),
-             "valu_busy": _busy(1.6346e12, 6.50642e12)},
+             "valu_busy": _busy(1.6346e12, 6.50642e12), "valu_insts": 1.59495e12},
     },
 }
 # The same for the chord optical-depth kernel of the transmission solve: bytes
@@ -472,7 +476,11 @@ def main():
                      "hbm_algorithmic_GBps": k4_gbps, "hbm_frac": k4_gbps / PEAK_HBM,
                      "hbm_algorithmic_bytes": k4_bytes,
                      "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9,
-                     "valu_busy": shape["valu_busy"] if same_run else None},
+                     "valu_busy": shape["valu_busy"] if same_run else None,
+                     # the issue roofline: wave-level VALU instructions per second (profiled
+                     # count per launch over this run's launch time) against the VALU peak
+                     "valu_insts_per_s": shape["valu_insts"] / avg_s if same_run else None,
+                     "valu_issue_frac": shape["valu_insts"] / avg_s / PEAK_VALU_WAVE_INSTS if same_run else None},
     }
     if a.gsample:
         print("[bench] per-packet g sampling (composite), same packets per band", flush=True)
